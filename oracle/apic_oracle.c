@@ -1,0 +1,330 @@
+/*
+ * Serial FP64 reference ("oracle") for the electrostatic particle-in-cell
+ * coupling loop: linear (cloud-in-cell) charge deposition, field gather,
+ * Boris velocity advance and the position update with periodic wrap.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU baseline
+ * leg of the benchmark do. It shares no source, header, table or constant with
+ * the HIP path.
+ *
+ * Built with gcc -O2 -ffp-contract=off, no fast-math: every floating-point
+ * operation below is a plain IEEE-754 double operation in the order written.
+ *
+ * The paper (AlgoPlasma, "Core functionality") names these operations as the
+ * particle-space and particle-grid coupling modules (A_Pusher with the Boris
+ * pusher, B_Scatter, C_Gather) and cites the textbook schemes of Birdsall &
+ * Langdon and Hockney & Eastwood for them without restating formulas. The
+ * formulas below are those textbook schemes:
+ *   grid: periodic, node-centred, X_j = j*dx, j = 0..nx-1;
+ *   shape: linear hat (CIC); in 2D the tensor product of 1D hats;
+ *   deposit: rho_j += (Q/dV) * sum_p W_j(x_p);
+ *   gather:  E_p = sum_j W_j(x_p) E_j (same weights as the deposit);
+ *   Boris (1970): half electric kick, magnetic rotation, half electric kick.
+ * The quantised deposit (integer CIC weights summed in int64) is not in the
+ * paper; it is the fixed-point reading of the same deposit, documented at
+ * or_deposit_q_1d / or_deposit_q_2d.
+ *
+ * Layout: 2D grid arrays are row-major [ny][nx], node index j = iy*nx + ix.
+ */
+#include <math.h>
+#include <stdint.h>
+
+/* ---- cloud-in-cell weights --------------------------------------------- */
+
+/* Cell index and fractional position of coordinate x on a periodic grid of n
+ * nodes spaced d apart: i = floor(x/d), f = x/d - i. A coordinate that rounds
+ * onto the right edge (i == n) belongs to node 0 with f = 0. */
+static void cic_cell(double x, int n, double d, int64_t *i_out, double *f_out)
+{
+    double g = x / d;
+    double fl = floor(g);
+    int64_t i = (int64_t)fl;
+    double f = g - fl;
+    if (i >= n) { i -= n; }
+    if (i < 0) { i += n; }
+    if (i >= n || i < 0) { i = 0; f = 0.0; }
+    *i_out = i;
+    *f_out = f;
+}
+
+/* Periodic wrap of a coordinate into [0, L). */
+static double wrap(double x, double L)
+{
+    x = fmod(x, L);
+    if (x < 0.0) x += L;
+    if (x >= L) x -= L;
+    return x;
+}
+
+/* Weights of one particle on its two 1D nodes (i, i+1 mod n). */
+void or_cic_weights_1d(double x, int n, double d, int64_t *i, int64_t *ip, double *w0, double *w1)
+{
+    double f;
+    cic_cell(x, n, d, i, &f);
+    *ip = (*i + 1) % n;
+    *w0 = 1.0 - f;
+    *w1 = f;
+}
+
+/* ---- deposit (B_Scatter) ----------------------------------------------- */
+
+void or_deposit_1d(int64_t n, const double *x, int nx, double dx, double q_over_dv, double *rho)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t i; double f;
+        cic_cell(x[p], nx, dx, &i, &f);
+        int64_t ip = (i + 1) % nx;
+        rho[i] += q_over_dv * (1.0 - f);
+        rho[ip] += q_over_dv * f;
+    }
+}
+
+void or_deposit_2d(int64_t n, const double *x, const double *y, int nx, int ny,
+                   double dx, double dy, double q_over_dv, double *rho)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t i, j; double fx, fy;
+        cic_cell(x[p], nx, dx, &i, &fx);
+        cic_cell(y[p], ny, dy, &j, &fy);
+        int64_t ip = (i + 1) % nx, jp = (j + 1) % ny;
+        rho[j * nx + i]   += q_over_dv * ((1.0 - fx) * (1.0 - fy));
+        rho[j * nx + ip]  += q_over_dv * (fx * (1.0 - fy));
+        rho[jp * nx + i]  += q_over_dv * ((1.0 - fx) * fy);
+        rho[jp * nx + ip] += q_over_dv * (fx * fy);
+    }
+}
+
+/* ---- quantised deposit (fixed-point reading of the same deposit) --------
+ * A particle sits in cell (ix[, iy]) at in-cell offset o in [0,1) held in
+ * binary32. Its 1D weights are the integers w1 = round-half-even(o * 2^S) and
+ * w0 = 2^S - w1; o * 2^S is exact (a power-of-two scale), so the rounding is
+ * the only approximation and the two weights sum to exactly 2^S. In 2D the
+ * node weights are the integer products of the per-axis weights and sum to
+ * exactly 2^(2S). The node sums are exact int64 additions, hence independent
+ * of summation order. */
+static int64_t qweight(float o, int S)
+{
+    double s = ldexp((double)o, S);
+    return (int64_t)nearbyint(s);
+}
+
+void or_deposit_q_1d(int64_t n, const int32_t *ix, const float *ox, int nx, int S, int64_t *I)
+{
+    const int64_t one = (int64_t)1 << S;
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t w1 = qweight(ox[p], S);
+        int64_t w0 = one - w1;
+        int64_t i = ix[p];
+        int64_t ip = (i + 1) % nx;
+        I[i] += w0;
+        I[ip] += w1;
+    }
+}
+
+void or_deposit_q_2d(int64_t n, const int32_t *ix, const int32_t *iy, const float *ox, const float *oy,
+                     int nx, int ny, int S, int64_t *I)
+{
+    const int64_t one = (int64_t)1 << S;
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t w1x = qweight(ox[p], S), w0x = one - w1x;
+        int64_t w1y = qweight(oy[p], S), w0y = one - w1y;
+        int64_t i = ix[p], j = iy[p];
+        int64_t ip = (i + 1) % nx, jp = (j + 1) % ny;
+        I[j * nx + i]   += w0x * w0y;
+        I[j * nx + ip]  += w1x * w0y;
+        I[jp * nx + i]  += w0x * w1y;
+        I[jp * nx + ip] += w1x * w1y;
+    }
+}
+
+/* ---- gather (C_Gather) ------------------------------------------------- */
+
+void or_gather_1d(int64_t n, const double *x, int nx, double dx, const double *E, double *Ep)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t i; double f;
+        cic_cell(x[p], nx, dx, &i, &f);
+        int64_t ip = (i + 1) % nx;
+        Ep[p] = (1.0 - f) * E[i] + f * E[ip];
+    }
+}
+
+void or_gather_2d(int64_t n, const double *x, const double *y, int nx, int ny, double dx, double dy,
+                  const double *Ex, const double *Ey, double *Epx, double *Epy)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t i, j; double fx, fy;
+        cic_cell(x[p], nx, dx, &i, &fx);
+        cic_cell(y[p], ny, dy, &j, &fy);
+        int64_t ip = (i + 1) % nx, jp = (j + 1) % ny;
+        double w00 = (1.0 - fx) * (1.0 - fy), w10 = fx * (1.0 - fy);
+        double w01 = (1.0 - fx) * fy, w11 = fx * fy;
+        Epx[p] = w00 * Ex[j * nx + i] + w10 * Ex[j * nx + ip] + w01 * Ex[jp * nx + i] + w11 * Ex[jp * nx + ip];
+        Epy[p] = w00 * Ey[j * nx + i] + w10 * Ey[j * nx + ip] + w01 * Ey[jp * nx + i] + w11 * Ey[jp * nx + ip];
+    }
+}
+
+/* ---- Boris velocity advance (A_Pusher, Boris 1970) ----------------------
+ * Uniform magnetic field along z (bz), electric field in the plane (Ez = 0).
+ *   a   = (q/m) dt / 2
+ *   v-  = v + a E
+ *   t   = a bz z^ ,  s = 2 t / (1 + |t|^2)
+ *   v'  = v- + v- x t
+ *   v+  = v- + v' x s
+ *   v   = v+ + a E
+ * vdim = 1: only vx (no magnetic term); vdim = 2: (vx, vy), bz must be 0;
+ * vdim = 3: (vx, vy, vz), vz is unchanged since Ez = 0 and B is along z.
+ * Epy may be NULL when vdim = 1 (1D electric field). */
+void or_boris(int64_t n, int vdim, double *vx, double *vy, double *vz,
+              const double *Epx, const double *Epy, double qm, double dt, double bz)
+{
+    const double a = qm * dt * 0.5;
+    const double t = a * bz;
+    const double s = 2.0 * t / (1.0 + t * t);
+    (void)vz;
+    for (int64_t p = 0; p < n; ++p) {
+        if (vdim == 1) {
+            double m1 = vx[p] + a * Epx[p];
+            vx[p] = m1 + a * Epx[p];
+            continue;
+        }
+        double ex = Epx[p], ey = Epy ? Epy[p] : 0.0;
+        double mx = vx[p] + a * ex;
+        double my = vy[p] + a * ey;
+        double px = mx + my * t;
+        double py = my - mx * t;
+        double qx = mx + py * s;
+        double qy = my - px * s;
+        vx[p] = qx + a * ex;
+        vy[p] = qy + a * ey;
+    }
+}
+
+/* ---- position update with periodic boundaries ---------------------------
+ * The paper leaves this to the application code ("move_particles" in the
+ * two-stream driver): x <- x + v dt, then wrap into [0, L). */
+void or_move_1d(int64_t n, double *x, const double *vx, double dt, double L)
+{
+    for (int64_t p = 0; p < n; ++p) x[p] = wrap(x[p] + vx[p] * dt, L);
+}
+
+void or_move_2d(int64_t n, double *x, double *y, const double *vx, const double *vy,
+                double dt, double Lx, double Ly)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        x[p] = wrap(x[p] + vx[p] * dt, Lx);
+        y[p] = wrap(y[p] + vy[p] * dt, Ly);
+    }
+}
+
+/* ---- adjoint (transpose-Jacobian) operators -----------------------------
+ * Discrete adjoints of the operators above, used to build the reference
+ * gradient of a scalar loss through the time loop. "lam" arrays are the
+ * adjoint variables; every routine ACCUMULATES (+=) into its outputs.
+ *
+ * Deposit  rho_j = rho0 + c * sum_p W_j(x_p):
+ *   lam_x_p += c * sum_j lam_rho_j * dW_j/dx (x_p)        (a gradient gather)
+ * Gather   E_p = sum_j W_j(x_p) E_j:
+ *   lam_E_j += sum_p W_j(x_p) lam_Ep_p                    (a scatter)
+ *   lam_x_p += sum_j dW_j/dx (x_p) E_j * lam_Ep_p
+ * The CIC hat is piecewise linear; dW/dx is its one-sided slope inside the
+ * cell that holds the particle (the derivative almost everywhere). */
+
+void or_adj_deposit_1d(int64_t n, const double *x, int nx, double dx, double c,
+                       const double *lrho, double *lx)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t i; double f;
+        cic_cell(x[p], nx, dx, &i, &f);
+        int64_t ip = (i + 1) % nx;
+        lx[p] += c * ((lrho[ip] - lrho[i]) / dx);
+    }
+}
+
+void or_adj_deposit_2d(int64_t n, const double *x, const double *y, int nx, int ny, double dx, double dy,
+                       double c, const double *lrho, double *lx, double *ly)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t i, j; double fx, fy;
+        cic_cell(x[p], nx, dx, &i, &fx);
+        cic_cell(y[p], ny, dy, &j, &fy);
+        int64_t ip = (i + 1) % nx, jp = (j + 1) % ny;
+        double l00 = lrho[j * nx + i], l10 = lrho[j * nx + ip];
+        double l01 = lrho[jp * nx + i], l11 = lrho[jp * nx + ip];
+        /* d/dx of (1-fx)(1-fy), fx(1-fy), (1-fx)fy, fx fy  = (-(1-fy), (1-fy), -fy, fy)/dx */
+        double gx = ((1.0 - fy) * (l10 - l00) + fy * (l11 - l01)) / dx;
+        double gy = ((1.0 - fx) * (l01 - l00) + fx * (l11 - l10)) / dy;
+        lx[p] += c * gx;
+        ly[p] += c * gy;
+    }
+}
+
+void or_adj_gather_1d(int64_t n, const double *x, int nx, double dx, const double *E,
+                      const double *lEp, double *lE, double *lx)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t i; double f;
+        cic_cell(x[p], nx, dx, &i, &f);
+        int64_t ip = (i + 1) % nx;
+        lE[i] += (1.0 - f) * lEp[p];
+        lE[ip] += f * lEp[p];
+        lx[p] += ((E[ip] - E[i]) / dx) * lEp[p];
+    }
+}
+
+void or_adj_gather_2d(int64_t n, const double *x, const double *y, int nx, int ny, double dx, double dy,
+                      const double *Ex, const double *Ey, const double *lEpx, const double *lEpy,
+                      double *lEx, double *lEy, double *lx, double *ly)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t i, j; double fx, fy;
+        cic_cell(x[p], nx, dx, &i, &fx);
+        cic_cell(y[p], ny, dy, &j, &fy);
+        int64_t ip = (i + 1) % nx, jp = (j + 1) % ny;
+        int64_t a00 = j * nx + i, a10 = j * nx + ip, a01 = jp * nx + i, a11 = jp * nx + ip;
+        double w00 = (1.0 - fx) * (1.0 - fy), w10 = fx * (1.0 - fy);
+        double w01 = (1.0 - fx) * fy, w11 = fx * fy;
+        double ax = lEpx[p], ay = lEpy[p];
+        lEx[a00] += w00 * ax; lEx[a10] += w10 * ax; lEx[a01] += w01 * ax; lEx[a11] += w11 * ax;
+        lEy[a00] += w00 * ay; lEy[a10] += w10 * ay; lEy[a01] += w01 * ay; lEy[a11] += w11 * ay;
+        /* gradient of the interpolated field along x and y, dotted with lam_Ep */
+        double dExdx = ((1.0 - fy) * (Ex[a10] - Ex[a00]) + fy * (Ex[a11] - Ex[a01])) / dx;
+        double dEydx = ((1.0 - fy) * (Ey[a10] - Ey[a00]) + fy * (Ey[a11] - Ey[a01])) / dx;
+        double dExdy = ((1.0 - fx) * (Ex[a01] - Ex[a00]) + fx * (Ex[a11] - Ex[a10])) / dy;
+        double dEydy = ((1.0 - fx) * (Ey[a01] - Ey[a00]) + fx * (Ey[a11] - Ey[a10])) / dy;
+        lx[p] += dExdx * ax + dEydx * ay;
+        ly[p] += dExdy * ax + dEydy * ay;
+    }
+}
+
+/* Adjoint of the Boris map. For a fixed uniform bz the map is linear in
+ * (v, E_p): v_new = R v + a (R + I) E_p, with R the rotation
+ *   R = [[1 - s t, s], [-s, 1 - s t]]   acting on (vx, vy),
+ * obtained by composing v' = v- + v- x t and v+ = v- + v' x s. Its adjoint is
+ *   lam_v_old = R^T lam_v_new,   lam_Ep = a (R + I)^T lam_v_new.
+ * On entry lv* hold lam for v_new; on return they hold lam for v_old. lEp*
+ * are OVERWRITTEN with lam_Ep. vdim as in or_boris. */
+void or_adj_boris(int64_t n, int vdim, double *lvx, double *lvy, double *lEpx, double *lEpy,
+                  double qm, double dt, double bz)
+{
+    const double a = qm * dt * 0.5;
+    const double t = a * bz;
+    const double s = 2.0 * t / (1.0 + t * t);
+    const double r = 1.0 - s * t;
+    for (int64_t p = 0; p < n; ++p) {
+        if (vdim == 1) {
+            lEpx[p] = 2.0 * a * lvx[p];
+            continue;
+        }
+        double gx = lvx[p], gy = lvy[p];
+        /* R^T = [[r, -s], [s, r]] */
+        double ox = r * gx - s * gy;
+        double oy = s * gx + r * gy;
+        /* (R + I)^T g = R^T g + g */
+        lEpx[p] = a * (ox + gx);
+        lEpy[p] = a * (oy + gy);
+        lvx[p] = ox;
+        lvy[p] = oy;
+    }
+}
