@@ -1,0 +1,191 @@
+/*
+ * apic -- MI355X (gfx950) particle-in-cell coupling loop, C ABI.
+ *
+ * The loop is the electrostatic PIC cycle of the AlgoPlasma paper: its
+ * "Core functionality" section names the modules (B_Scatter deposits particle
+ * charge onto the grid, D_Poisson solves for the potential and evaluates E,
+ * C_Gather interpolates E to the particles, A_Pusher advances velocities with
+ * the Boris pusher), and the two-stream example's application driver fixes the
+ * order (field of the initial charge, initial half push, then per step: full
+ * push, position update with periodic boundaries, deposit, field). The paper
+ * leaves data structures and execution order to the caller; so does this ABI:
+ * every particle, grid and workspace array is allocated and owned by the
+ * caller, and the library owns only its context (FFT plans, graph cache,
+ * a few device words for error flags).
+ *
+ * Conventions shared by all entry points
+ *   - Pointers marked [dev] are device (HBM) pointers on the current HIP
+ *     device; [host] are host pointers. No entry point allocates device memory
+ *     after apic_create.
+ *   - All work is enqueued asynchronously on the given hipStream_t (pass the
+ *     stream as void*; NULL = default stream). Argument errors are detected on
+ *     the host and returned synchronously, before anything is enqueued.
+ *     Errors found by kernels (a NaN/out-of-range particle, fixed-point
+ *     headroom exceeded, an inconsistent bucket table) set a device flag that
+ *     apic_sync_status() reads.
+ *   - Units are the caller's (the reference workloads use omega_pe = 1,
+ *     eps0 = 1, q/m = -1 for electrons).
+ *   - Grids are periodic and node-centred: node j sits at X_j = j*dx.
+ *     2D grid arrays are row-major [ny][nx]; a vector field is [dim][ny][nx].
+ *   - Return value: APIC_OK or a negative apic_status. No C++ exception
+ *     crosses the ABI. apic_last_error() gives a message for the last failure.
+ */
+#ifndef APIC_H
+#define APIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    APIC_OK = 0,
+    APIC_EINVAL = -1,        /* bad argument (host-side check)                 */
+    APIC_EHIP = -2,          /* a HIP / hipFFT call failed                     */
+    APIC_ENOMEM = -3,        /* context allocation failed (apic_create only)   */
+    APIC_EOVERFLOW = -4,     /* fixed-point deposit headroom exceeded          */
+    APIC_EDOMAIN = -5,       /* NaN/Inf or out-of-range particle, or particles
+                                not ordered as the bucket table says           */
+    APIC_EUNSUPPORTED = -6   /* valid but not implemented combination          */
+} apic_status;
+
+typedef enum {
+    APIC_FP64 = 0,  /* positions x,y in [0,L) and velocities as double          */
+    APIC_MIXED = 1  /* cell index + binary32 in-cell offset, binary32 velocity,
+                       int64 fixed-point deposit, FP64 field solve             */
+} apic_precision;
+
+/* One periodic plasma (one replica). */
+typedef struct {
+    int dim;              /* 1 or 2 spatial dimensions                          */
+    int vdim;             /* velocity components: 1 (dim 1), 2 or 3 (dim 2)     */
+    int nx, ny;           /* grid nodes per axis (ny = 1 when dim = 1); 2D
+                             grids need nx, ny <= 32768                         */
+    double lx, ly;        /* box lengths (ly ignored when dim = 1)              */
+    double dt;            /* time step                                          */
+    double qm;            /* charge-to-mass ratio of the particles              */
+    double q_macro;       /* charge of one macro-particle                       */
+    double rho_ion;       /* uniform immobile background charge density         */
+    double bz;            /* uniform magnetic field along z (needs vdim >= 2)   */
+    apic_precision prec;
+    int frac_bits;        /* mixed path: S, fixed-point weight bits per axis;
+                             0 selects 32 (dim 1) or 20 (dim 2)                 */
+    int tile_x, tile_y;   /* sort bucket = tile of tile_x * tile_y cells, powers
+                             of two; 0 selects the default for the grid        */
+} apic_grid_desc;
+
+/* Particle arrays (structure of arrays), all [dev], caller-owned, length n.
+ * FP64 path : x (and y when dim = 2) are double positions in [0, L);
+ *             vx, vy, vz are double.
+ * MIXED path: cell is the packed cell word (iy << 16) | ix in 2D, ix in 1D;
+ *             ox (and oy) are binary32 offsets in [0,1) in cell units;
+ *             vx, vy, vz are float.
+ * Unused components (y/oy in 1D, vy when vdim = 1, vz when vdim < 3) are NULL.
+ * bucket_start [dev, int32, apic_num_buckets()+1] describes the current order:
+ *             particles of bucket b occupy [bucket_start[b], bucket_start[b+1]).
+ *             Written by apic_sort_by_cell and apic_step; read by apic_deposit,
+ *             apic_gather_push and apic_step. NULL in apic_deposit /
+ *             apic_gather_push selects the unsorted (untiled) kernels.
+ * perm        [dev, int32, n] optional output of apic_sort_by_cell:
+ *             sorted[i] = unsorted[perm[i]]. NULL = not written. */
+typedef struct {
+    int64_t n;
+    double *x, *y;
+    int32_t *cell;
+    float *ox, *oy;
+    void *vx, *vy, *vz;
+    int32_t *bucket_start;
+    int32_t *perm;
+} apic_particles;
+
+typedef struct apic_ctx apic_ctx;
+
+/* Create a context for one plasma of n_particles particles: validates the
+ * descriptor, builds the FFT plans for 2D grids and allocates the context's
+ * own small device words. Returns APIC_EINVAL for an invalid descriptor. */
+apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ctx **out);
+void apic_destroy(apic_ctx *ctx);
+
+/* Bytes of caller-provided device workspace that apic_sort_by_cell and
+ * apic_step need (second particle buffer, bucket counters, deposit and FFT
+ * buffers). The workspace must stay untouched between calls that share it
+ * only in that the library does not rely on its contents across calls. */
+apic_status apic_workspace_size(const apic_ctx *ctx, size_t *bytes);
+
+/* Number of sort buckets (tiles) of the context's grid. */
+int64_t apic_num_buckets(const apic_ctx *ctx);
+
+/* Fixed-point bits S the context uses (mixed path). */
+int apic_frac_bits(const apic_ctx *ctx);
+
+/* Counting sort of the particles by bucket (a1): key = tile-major bucket of
+ * each particle's cell; histogram, exclusive scan, scatter. Particles end up
+ * ordered by ascending bucket, in place; bucket_start is written; perm is
+ * written when non-NULL. The order inside a bucket is unspecified. */
+apic_status apic_sort_by_cell(apic_ctx *ctx, apic_particles *p, void *ws, void *stream);
+
+/* CIC charge deposit (a2) of the particles' current positions.
+ * FP64 : rho [dev, double, G] is overwritten with
+ *        rho_ion + (q_macro/dV) * sum_p W_j(x_p).
+ * MIXED: rho [dev, int64, G] is overwritten with the fixed-point node sums
+ *        I_j = sum_p w_pj, w = products of round-half-even(o * 2^S) weights;
+ *        each particle contributes exactly 2^(S*dim) (exact, order-free).
+ * G = nx*ny. With p->bucket_start set the particles must be bucket-ordered
+ * (LDS-tiled kernel); with NULL any order is accepted. */
+apic_status apic_deposit(apic_ctx *ctx, const apic_particles *p, void *rho, void *stream);
+
+/* Periodic Poisson solve and field (a3): -lap_h phi = rho with the 3-point
+ * (1D) / 5-point (2D) finite-difference Laplacian, mean-free phi, and
+ * E = -(centred difference of phi).
+ * rho  [dev]: double [G] (FP64) or int64 fixed-point sums [G] (MIXED; converted
+ *             with rho_ion + q_macro * I * 2^(-S*dim) / dV).
+ * E    [dev, double, dim*G] output.
+ * E32  [dev, float, dim*G] output copy for the mixed gather; may be NULL.
+ * we   [dev, double, 1] output field energy 1/2 sum |E|^2 dV; may be NULL. */
+apic_status apic_field_solve(apic_ctx *ctx, const void *rho, double *E, float *E32, double *we,
+                             void *ws, void *stream);
+
+/* Gather (a4) + Boris velocity advance (a5) [+ position update (a6)].
+ * E [dev]: double [dim*G] (FP64) or float [dim*G] (MIXED).
+ * The velocity advances by dt * dt_scale (dt_scale = -0.5 gives the initial
+ * backward half push, a7). move != 0 then advances positions by dt (not
+ * scaled) with periodic wrap. With p->bucket_start set, particles must be
+ * bucket-ordered (E tile staged in LDS). */
+apic_status apic_gather_push(apic_ctx *ctx, apic_particles *p, const void *E, double dt_scale,
+                             int move, void *stream);
+
+/* nsteps full PIC cycles (a1-a8) from the leapfrog state (x^n, v^{n-1/2}),
+ * bucket-ordered with a valid bucket_start, and the field E^n:
+ *   gather E^n -> Boris -> move -> deposit rho^{n+1} -> counting sort ->
+ *   Poisson -> E^{n+1}.
+ * rho  [dev] optional output (NULL = none): the last step's deposit, in the
+ *        format of apic_deposit (FP64 rho, or the int64 fixed-point sums).
+ * E    [dev]: double [dim*G] in/out (FP64 E^n in, E^{n+nsteps} out).
+ * E32  [dev]: float [dim*G] in/out for MIXED (must hold E^n as float); NULL for FP64.
+ * diag [dev, double, nsteps*4] per step k (time level n+k -> n+k+1):
+ *        [0] total deposited charge at n+k+1, sum_j (rho_j - rho_ion) dV
+ *        [1] field energy W_E at n+k+1
+ *        [2] kinetic energy at n+k: M/2 * sum_p (|v^{-}|^2 + |v^{+}|^2)/2
+ *            with M = q_macro/qm
+ *        [3] x-momentum M * sum_p vx^{n+k+1/2}
+ *      may be NULL.
+ * p->perm [dev, int32, n] optional: the last step's reordering,
+ *        after[i] = before_last_step[perm[i]].
+ * On return the particles are again bucket-ordered (bucket_start updated). */
+apic_status apic_step(apic_ctx *ctx, apic_particles *p, void *rho, double *E, float *E32, int nsteps,
+                      double *diag, void *ws, void *stream);
+
+/* Waits for the stream, then returns and clears the device error flags
+ * (APIC_OK, APIC_EDOMAIN or APIC_EOVERFLOW). */
+apic_status apic_sync_status(apic_ctx *ctx, void *stream);
+
+/* Message for the last error on this context (never NULL). */
+const char *apic_last_error(const apic_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APIC_H */

@@ -1,0 +1,216 @@
+"""Thin Python binding of libapic (ctypes). Argument marshalling only.
+
+torch provides device memory and the current HIP stream; every step of the
+PIC loop runs in the HIP kernels of libapic.so. There is no CPU fallback: if
+the library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libapic.so")
+
+APIC_FP64 = 0
+APIC_MIXED = 1
+
+_STATUS = {0: "APIC_OK", -1: "APIC_EINVAL", -2: "APIC_EHIP", -3: "APIC_ENOMEM", -4: "APIC_EOVERFLOW",
+           -5: "APIC_EDOMAIN", -6: "APIC_EUNSUPPORTED"}
+
+
+class ApicError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s (%d): %s" % (_STATUS.get(status, "?"), status, msg))
+        self.status = status
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("vdim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("dt", ctypes.c_double),
+                ("qm", ctypes.c_double), ("q_macro", ctypes.c_double), ("rho_ion", ctypes.c_double),
+                ("bz", ctypes.c_double), ("prec", ctypes.c_int), ("frac_bits", ctypes.c_int),
+                ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int)]
+
+
+class ParticlesC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("cell", ctypes.c_void_p), ("ox", ctypes.c_void_p), ("oy", ctypes.c_void_p),
+                ("vx", ctypes.c_void_p), ("vy", ctypes.c_void_p), ("vz", ctypes.c_void_p),
+                ("bucket_start", ctypes.c_void_p), ("perm", ctypes.c_void_p)]
+
+
+EXPORTS = ["apic_create", "apic_destroy", "apic_workspace_size", "apic_num_buckets", "apic_frac_bits",
+           "apic_sort_by_cell", "apic_deposit", "apic_field_solve", "apic_gather_push", "apic_step",
+           "apic_sync_status", "apic_last_error"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libapic.so and declare the C signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libapic.so is not built (%s); run __graft_entry__.build()" % path)
+    L = ctypes.CDLL(path)
+    vp, i64, dbl, cint = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    P = ctypes.POINTER
+    sigs = {
+        "apic_create": ([P(GridDesc), i64, P(vp)], cint),
+        "apic_destroy": ([vp], None),
+        "apic_workspace_size": ([vp, P(ctypes.c_size_t)], cint),
+        "apic_num_buckets": ([vp], i64),
+        "apic_frac_bits": ([vp], cint),
+        "apic_sort_by_cell": ([vp, P(ParticlesC), vp, vp], cint),
+        "apic_deposit": ([vp, P(ParticlesC), vp, vp], cint),
+        "apic_field_solve": ([vp, vp, vp, vp, vp, vp, vp], cint),
+        "apic_gather_push": ([vp, P(ParticlesC), vp, dbl, cint, vp], cint),
+        "apic_step": ([vp, P(ParticlesC), vp, vp, vp, cint, vp, vp, vp], cint),
+        "apic_sync_status": ([vp, vp], cint),
+        "apic_last_error": ([vp], ctypes.c_char_p),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    if path == LIB_PATH:
+        _lib = L
+    return L
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """One plasma on the GPU: owns the libapic context and its workspace."""
+
+    def __init__(self, *, dim, vdim, nx, ny, lx, ly, dt, n, qm=-1.0, q_macro=None, rho_ion=1.0, bz=0.0,
+                 precision="mixed", frac_bits=0, tile=(0, 0), device="cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libapic needs a HIP GPU; none is visible")
+        self.L = load_library()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.mixed = precision == "mixed"
+        if q_macro is None:
+            vol = lx * (ly if dim == 2 else 1.0)
+            q_macro = -rho_ion * vol / n
+        self.desc = GridDesc(dim, vdim, nx, ny if dim == 2 else 1, lx, ly if dim == 2 else 1.0, dt, qm, q_macro,
+                             rho_ion, bz, APIC_MIXED if self.mixed else APIC_FP64, frac_bits, tile[0], tile[1])
+        self.n = int(n)
+        h = ctypes.c_void_p()
+        st = self.L.apic_create(ctypes.byref(self.desc), self.n, ctypes.byref(h))
+        if st != 0:
+            raise ApicError(st, "apic_create rejected the descriptor")
+        self.h = h
+        sz = ctypes.c_size_t()
+        self._check(self.L.apic_workspace_size(self.h, ctypes.byref(sz)))
+        self.ws = torch.empty(max(int(sz.value), 256), dtype=torch.uint8, device=self.device)
+        self.nbuckets = int(self.L.apic_num_buckets(self.h))
+        self.frac_bits = int(self.L.apic_frac_bits(self.h))
+        self.dim, self.vdim, self.nx = dim, vdim, nx
+        self.ny = ny if dim == 2 else 1
+        self.G = self.nx * self.ny
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.L.apic_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            msg = self.L.apic_last_error(self.h)
+            raise ApicError(st, msg.decode() if msg else "")
+
+    def sync(self):
+        self._check(self.L.apic_sync_status(self.h, _stream()))
+
+    # -- entry points -------------------------------------------------------
+    def sort_by_cell(self, parts: "Particles", perm=None):
+        s = parts.struct(perm=perm)
+        self._check(self.L.apic_sort_by_cell(self.h, ctypes.byref(s), ctypes.c_void_p(self.ws.data_ptr()), _stream()))
+
+    def deposit(self, parts: "Particles", rho, tiled=True):
+        s = parts.struct(tiled=tiled)
+        self._check(self.L.apic_deposit(self.h, ctypes.byref(s), ctypes.c_void_p(rho.data_ptr()), _stream()))
+
+    def field_solve(self, rho, E, E32=None, we=None):
+        self._check(self.L.apic_field_solve(self.h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(E.data_ptr()),
+                                            ctypes.c_void_p(_ptr(E32)), ctypes.c_void_p(_ptr(we)),
+                                            ctypes.c_void_p(self.ws.data_ptr()), _stream()))
+
+    def gather_push(self, parts: "Particles", E, dt_scale=1.0, move=True, tiled=True):
+        s = parts.struct(tiled=tiled)
+        self._check(self.L.apic_gather_push(self.h, ctypes.byref(s), ctypes.c_void_p(E.data_ptr()),
+                                            float(dt_scale), 1 if move else 0, _stream()))
+
+    def step(self, parts: "Particles", E, E32, nsteps, diag=None, rho=None, perm=None):
+        s = parts.struct(perm=perm)
+        self._check(self.L.apic_step(self.h, ctypes.byref(s), ctypes.c_void_p(_ptr(rho)), ctypes.c_void_p(E.data_ptr()),
+                                     ctypes.c_void_p(_ptr(E32)), int(nsteps), ctypes.c_void_p(_ptr(diag)),
+                                     ctypes.c_void_p(self.ws.data_ptr()), _stream()))
+
+
+class Particles:
+    """Device SoA particle arrays for one Context (torch tensors)."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        t = ctx.torch
+        n, dev = ctx.n, ctx.device
+        r = t.float32 if ctx.mixed else t.float64
+        self.x = self.y = self.cell = self.ox = self.oy = None
+        if ctx.mixed:
+            self.cell = t.zeros(n, dtype=t.int32, device=dev)
+            self.ox = t.zeros(n, dtype=t.float32, device=dev)
+            if ctx.dim == 2:
+                self.oy = t.zeros(n, dtype=t.float32, device=dev)
+        else:
+            self.x = t.zeros(n, dtype=t.float64, device=dev)
+            if ctx.dim == 2:
+                self.y = t.zeros(n, dtype=t.float64, device=dev)
+        self.vx = t.zeros(n, dtype=r, device=dev)
+        self.vy = t.zeros(n, dtype=r, device=dev) if ctx.vdim >= 2 else None
+        self.vz = t.zeros(n, dtype=r, device=dev) if ctx.vdim >= 3 else None
+        self.bucket_start = t.zeros(ctx.nbuckets + 1, dtype=t.int32, device=dev)
+
+    def struct(self, perm=None, tiled=True) -> ParticlesC:
+        return ParticlesC(self.ctx.n, _ptr(self.x), _ptr(self.y), _ptr(self.cell), _ptr(self.ox), _ptr(self.oy),
+                          _ptr(self.vx), _ptr(self.vy), _ptr(self.vz),
+                          _ptr(self.bucket_start) if tiled else None, _ptr(perm))
+
+    def upload(self, x=None, y=None, vx=None, vy=None, vz=None, cell=None, ox=None, oy=None):
+        t = self.ctx.torch
+        dev = self.ctx.device
+
+        def put(dst, src):
+            if src is not None and dst is not None:
+                dst.copy_(t.from_numpy(np.ascontiguousarray(src)).to(dev, dst.dtype))
+
+        put(self.x, x)
+        put(self.y, y)
+        put(self.cell, cell)
+        put(self.ox, ox)
+        put(self.oy, oy)
+        put(self.vx, vx)
+        put(self.vy, vy)
+        put(self.vz, vz)
+
+    def download(self):
+        g = lambda a: None if a is None else a.cpu().numpy()
+        return {k: g(getattr(self, k)) for k in ("x", "y", "cell", "ox", "oy", "vx", "vy", "vz", "bucket_start")}

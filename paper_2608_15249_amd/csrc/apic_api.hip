@@ -1,0 +1,503 @@
+// Host side of libapic: context, workspace layout, argument checks and the
+// C-ABI entry points declared in include/apic.h.
+#include "apic.h"
+#include "apic_internal.h"
+
+#include <hipfft/hipfft.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace apic;
+
+struct apic_ctx {
+    apic_grid_desc d;
+    int64_t n;
+    Geo g;
+    bool mixed;
+    CtxDev dev;
+    void *dev_block = nullptr;
+    hipfftHandle fwd = 0, inv = 0;
+    bool have_fft = false;
+    std::string err;
+    // workspace layout (byte offsets)
+    size_t o_x, o_y, o_cell, o_ox, o_oy, o_vx, o_vy, o_vz;
+    size_t o_keys, o_count, o_cursor, o_bstart, o_acc, o_rho, o_rhat, o_ehat;
+    size_t ws_bytes;
+    double dV, mass;
+};
+
+namespace {
+
+apic_status fail(apic_ctx *c, apic_status st, const char *msg) {
+    if (c) c->err = msg;
+    return st;
+}
+
+apic_status hip_fail(apic_ctx *c, hipError_t e, const char *where) {
+    if (c) c->err = std::string(where) + ": " + hipGetErrorString(e);
+    return APIC_EHIP;
+}
+
+#define HIPCHK(ctx, expr)                                   \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+#define FFTCHK(ctx, expr)                                                    \
+    do {                                                                     \
+        hipfftResult r_ = (expr);                                            \
+        if (r_ != HIPFFT_SUCCESS) {                                          \
+            (ctx)->err = std::string(#expr) + " failed (" + std::to_string((int)r_) + ")"; \
+            return APIC_EHIP;                                                \
+        }                                                                    \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int ilog2_floor(int64_t v) {
+    int r = 0;
+    while ((int64_t(1) << (r + 1)) <= v) ++r;
+    return r;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Default bucket tile: about 4096 particles per bucket (the workgroup's work
+// item), tile side a power of two.
+void default_tiles(const apic_grid_desc &d, int64_t n, int &tsx, int &tsy) {
+    const double cells = (double)d.nx * (d.dim == 2 ? d.ny : 1);
+    const double ppc = n > 0 ? (double)n / cells : 1.0;
+    double target = 4096.0 / (ppc > 0 ? ppc : 1.0);
+    if (target < 1.0) target = 1.0;
+    if (d.dim == 1) {
+        tsx = ilog2_floor((int64_t)target);
+        if (tsx > 12) tsx = 12;
+        tsy = 0;
+    } else {
+        int t = ilog2_floor((int64_t)target);
+        tsx = (t + 1) / 2;
+        tsy = t / 2;
+        if (tsx > 5) tsx = 5;
+        if (tsy > 5) tsy = 5;
+        if (tsx < 1) tsx = 1;
+        if (tsy < 1) tsy = 1;
+    }
+}
+
+void layout(apic_ctx *c) {
+    const int64_t n = c->n;
+    const size_t r = c->mixed ? 4 : 8;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    const int dim = c->d.dim, vdim = c->d.vdim;
+    c->o_x = c->o_y = c->o_cell = c->o_ox = c->o_oy = c->o_vx = c->o_vy = c->o_vz = (size_t)-1;
+    if (c->mixed) {
+        c->o_cell = take(4 * n);
+        c->o_ox = take(4 * n);
+        if (dim == 2) c->o_oy = take(4 * n);
+    } else {
+        c->o_x = take(8 * n);
+        if (dim == 2) c->o_y = take(8 * n);
+    }
+    c->o_vx = take(r * n);
+    if (vdim >= 2) c->o_vy = take(r * n);
+    if (vdim >= 3) c->o_vz = take(r * n);
+    const int64_t nb = c->g.nbuckets;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    c->o_keys = take(4 * n);
+    c->o_count = take(4 * nb);
+    c->o_cursor = take(4 * nb);
+    c->o_bstart = take(4 * (nb + 1));
+    c->o_acc = take(8 * G);
+    c->o_rho = take(8 * G);
+    if (dim == 2) {
+        const int64_t H = (int64_t)(c->d.nx / 2 + 1) * c->d.ny;
+        c->o_rhat = take(16 * H);
+        c->o_ehat = take(32 * H);
+    } else {
+        c->o_rhat = c->o_ehat = (size_t)-1;
+    }
+    c->ws_bytes = off;
+}
+
+template <typename T>
+T *wsp(void *ws, size_t off) {
+    return off == (size_t)-1 ? nullptr : (T *)((char *)ws + off);
+}
+
+Parts parts_of(const apic_particles *p) {
+    Parts q;
+    q.x = p->x;
+    q.y = p->y;
+    q.cell = p->cell;
+    q.ox = p->ox;
+    q.oy = p->oy;
+    q.vx = p->vx;
+    q.vy = p->vy;
+    q.vz = p->vz;
+    return q;
+}
+
+Parts parts_ws(const apic_ctx *c, void *ws) {
+    Parts q;
+    q.x = wsp<double>(ws, c->o_x);
+    q.y = wsp<double>(ws, c->o_y);
+    q.cell = wsp<int32_t>(ws, c->o_cell);
+    q.ox = wsp<float>(ws, c->o_ox);
+    q.oy = wsp<float>(ws, c->o_oy);
+    q.vx = wsp<void>(ws, c->o_vx);
+    q.vy = wsp<void>(ws, c->o_vy);
+    q.vz = wsp<void>(ws, c->o_vz);
+    return q;
+}
+
+apic_status check_parts(apic_ctx *c, const apic_particles *p, bool need_bstart) {
+    if (!p) return fail(c, APIC_EINVAL, "particles is NULL");
+    if (p->n != c->n) return fail(c, APIC_EINVAL, "particles.n differs from the context's particle count");
+    const int dim = c->d.dim, vdim = c->d.vdim;
+    if (c->mixed) {
+        if (!p->cell || !p->ox || (dim == 2 && !p->oy))
+            return fail(c, APIC_EINVAL, "mixed path needs cell, ox (and oy in 2D)");
+    } else {
+        if (!p->x || (dim == 2 && !p->y)) return fail(c, APIC_EINVAL, "FP64 path needs x (and y in 2D)");
+    }
+    if (!p->vx || (vdim >= 2 && !p->vy) || (vdim >= 3 && !p->vz))
+        return fail(c, APIC_EINVAL, "missing velocity component");
+    if (need_bstart && !p->bucket_start) return fail(c, APIC_EINVAL, "bucket_start is NULL");
+    return APIC_OK;
+}
+
+PushC push_coeffs(const apic_ctx *c, double dt_scale, int move) {
+    PushC pc;
+    const double dte = c->d.dt * dt_scale;
+    pc.a = c->d.qm * dte * 0.5;
+    pc.t = pc.a * c->d.bz;
+    pc.s = 2.0 * pc.t / (1.0 + pc.t * pc.t);
+    pc.af = (float)pc.a;
+    pc.tf = (float)pc.t;
+    pc.sf = (float)pc.s;
+    pc.dt = c->d.dt;
+    const double dx = c->d.lx / c->d.nx;
+    const double dy = c->d.dim == 2 ? c->d.ly / c->d.ny : 1.0;
+    pc.dtdx = (float)(c->d.dt / dx);
+    pc.dtdy = (float)(c->d.dt / dy);
+    pc.move = move;
+    return pc;
+}
+
+// Scale of the accumulation buffer to charge density.
+double acc_scale(const apic_ctx *c) {
+    double s = c->d.q_macro / c->dV;
+    if (c->mixed) s = std::ldexp(s, -c->g.S * c->d.dim);
+    return s;
+}
+
+int64_t max_per_bucket(const apic_ctx *c) {
+    if (!c->mixed) return INT32_MAX;
+    const int bits = 63 - c->g.S * c->d.dim - c->d.dim;
+    if (bits >= 31) return INT32_MAX;
+    return (int64_t(1) << bits) - 1;
+}
+
+apic_status field_from_acc(apic_ctx *c, void *acc, bool acc_is_rho, double *E, float *E32, double *we_out,
+                           double *charge_out, int step_mode, int clear, void *ws, hipStream_t s) {
+    const double scale = acc_is_rho ? 1.0 : acc_scale(c);
+    const double add = acc_is_rho ? 0.0 : c->d.rho_ion;
+    const bool mixed_acc = c->mixed && !acc_is_rho;
+    if (c->d.dim == 1) {
+        HIPCHK(c, launch_field1d(c->g, mixed_acc, acc, scale, add, c->d.rho_ion, c->d.lx / c->d.nx, clear, E, E32,
+                                 we_out, charge_out, step_mode, c->dev, s));
+        return APIC_OK;
+    }
+    double *rho = wsp<double>(ws, c->o_rho);
+    void *rhat = wsp<void>(ws, c->o_rhat);
+    char *ehat = wsp<char>(ws, c->o_ehat);
+    const size_t H = (size_t)(c->d.nx / 2 + 1) * c->d.ny;
+    HIPCHK(c, launch_rho(c->g, mixed_acc, acc, rho, scale, add, c->d.rho_ion, c->dV, clear, charge_out, step_mode,
+                         c->dev, s));
+    FFTCHK(c, hipfftSetStream(c->fwd, s));
+    FFTCHK(c, hipfftExecD2Z(c->fwd, (hipfftDoubleReal *)rho, (hipfftDoubleComplex *)rhat));
+    HIPCHK(c, launch_spectral(c->g, rhat, ehat, ehat + 16 * H, c->dev, s));
+    FFTCHK(c, hipfftSetStream(c->inv, s));
+    FFTCHK(c, hipfftExecZ2D(c->inv, (hipfftDoubleComplex *)ehat, (hipfftDoubleReal *)E));
+    HIPCHK(c, launch_efinish(c->g, E, E32, c->dV, we_out, step_mode, c->dev, s));
+    return APIC_OK;
+}
+
+apic_status copy_parts(apic_ctx *c, const Parts &dst, const Parts &src, hipStream_t s) {
+    const int64_t n = c->n;
+    const size_t r = c->mixed ? 4 : 8;
+    if (c->mixed) {
+        HIPCHK(c, launch_copy_bytes(dst.cell, src.cell, 4 * n, s));
+        HIPCHK(c, launch_copy_bytes(dst.ox, src.ox, 4 * n, s));
+        if (c->d.dim == 2) HIPCHK(c, launch_copy_bytes(dst.oy, src.oy, 4 * n, s));
+    } else {
+        HIPCHK(c, launch_copy_bytes(dst.x, src.x, 8 * n, s));
+        if (c->d.dim == 2) HIPCHK(c, launch_copy_bytes(dst.y, src.y, 8 * n, s));
+    }
+    HIPCHK(c, launch_copy_bytes(dst.vx, src.vx, r * n, s));
+    if (c->d.vdim >= 2) HIPCHK(c, launch_copy_bytes(dst.vy, src.vy, r * n, s));
+    if (c->d.vdim >= 3) HIPCHK(c, launch_copy_bytes(dst.vz, src.vz, r * n, s));
+    return APIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ctx **out) {
+    if (!desc || !out) return APIC_EINVAL;
+    *out = nullptr;
+    const apic_grid_desc &d = *desc;
+    if (d.dim != 1 && d.dim != 2) return APIC_EINVAL;
+    if (d.dim == 1 && (d.vdim != 1 || d.ny != 1)) return APIC_EINVAL;
+    if (d.dim == 2 && (d.vdim != 2 && d.vdim != 3)) return APIC_EINVAL;
+    if (d.nx < 2 || d.ny < 1 || (d.dim == 2 && (d.ny < 2 || d.nx > 32768 || d.ny > 32768))) return APIC_EINVAL;
+    if (d.dim == 1 && d.nx > 8192) return APIC_EUNSUPPORTED;
+    if (!(d.lx > 0) || (d.dim == 2 && !(d.ly > 0)) || !(d.dt > 0) || !std::isfinite(d.qm) || d.qm == 0.0)
+        return APIC_EINVAL;
+    if (d.bz != 0.0 && d.vdim < 2) return APIC_EINVAL;
+    if (n_particles < 0 || n_particles > (int64_t)INT32_MAX - 1) return APIC_EINVAL;
+    if (d.prec != APIC_FP64 && d.prec != APIC_MIXED) return APIC_EINVAL;
+    if ((d.tile_x && !is_pow2(d.tile_x)) || (d.tile_y && !is_pow2(d.tile_y))) return APIC_EINVAL;
+
+    apic_ctx *c = new (std::nothrow) apic_ctx();
+    if (!c) return APIC_ENOMEM;
+    c->d = d;
+    c->n = n_particles;
+    c->mixed = d.prec == APIC_MIXED;
+    Geo &g = c->g;
+    g.dim = d.dim;
+    g.vdim = d.vdim;
+    g.nx = d.nx;
+    g.ny = d.dim == 2 ? d.ny : 1;
+    c->d.ny = g.ny;
+    int tsx, tsy;
+    default_tiles(d, n_particles, tsx, tsy);
+    if (d.tile_x) tsx = ilog2_floor(d.tile_x);
+    if (d.dim == 2 && d.tile_y) tsy = ilog2_floor(d.tile_y);
+    if (d.dim == 1) tsy = 0;
+    if (tsx > 10 || tsy > 10) { delete c; return APIC_EINVAL; }
+    g.tsx = tsx;
+    g.tsy = tsy;
+    g.nbx = (g.nx + (1 << tsx) - 1) >> tsx;
+    g.nby = d.dim == 2 ? (g.ny + (1 << tsy) - 1) >> tsy : 1;
+    g.nbuckets = g.nbx * g.nby;
+    g.halo = 1;
+    g.np = (int)n_particles;
+    g.S = d.frac_bits ? d.frac_bits : (d.dim == 1 ? 32 : 20);
+    if (c->mixed && (g.S < 1 || g.S > 32 || g.S * d.dim > 48)) { delete c; return APIC_EINVAL; }
+    g.lx = d.lx;
+    g.ly = d.dim == 2 ? d.ly : 1.0;
+    const double dx = d.lx / d.nx, dy = d.dim == 2 ? d.ly / d.ny : 1.0;
+    g.inv_dx = 1.0 / dx;
+    g.inv_dy = 1.0 / dy;
+    c->dV = dx * dy;
+    c->mass = d.q_macro / d.qm;
+    layout(c);
+
+    // context device words + wavenumber tables
+    const int hx = g.nx / 2 + 1;
+    size_t bytes = align256(sizeof(int)) * 3 + align256(sizeof(double) * kMaxPartials) +
+                   align256(sizeof(double) * hx) * 2 + align256(sizeof(double) * g.ny) * 2;
+    if (hipMalloc(&c->dev_block, bytes) != hipSuccess) { delete c; return APIC_ENOMEM; }
+    if (hipMemset(c->dev_block, 0, bytes) != hipSuccess) { (void)hipFree(c->dev_block); delete c; return APIC_EHIP; }
+    char *b = (char *)c->dev_block;
+    size_t off = 0;
+    auto take = [&](size_t sz) { char *p = b + off; off += align256(sz); return p; };
+    c->dev.err = (int *)take(sizeof(int));
+    c->dev.counter = (unsigned *)take(sizeof(int));
+    c->dev.step = (int *)take(sizeof(int));
+    c->dev.partials = (double *)take(sizeof(double) * kMaxPartials);
+    c->dev.kx2 = (double *)take(sizeof(double) * hx);
+    c->dev.kapx = (double *)take(sizeof(double) * hx);
+    c->dev.ky2 = (double *)take(sizeof(double) * g.ny);
+    c->dev.kapy = (double *)take(sizeof(double) * g.ny);
+    // modified wavenumbers of the periodic FD operators:
+    //   K^2_d = (2/d sin(k d / 2))^2 (3-point second difference),
+    //   kappa_d = sin(k d)/d (centred first difference), k = 2 pi m / L.
+    std::vector<double> kx2(hx), kapx(hx), ky2(g.ny), kapy(g.ny);
+    for (int m = 0; m < hx; ++m) {
+        double h = M_PI * m / g.nx;  // k dx / 2
+        kx2[m] = std::pow(2.0 / dx * std::sin(h), 2);
+        kapx[m] = std::sin(2.0 * h) / dx;
+    }
+    for (int m = 0; m < g.ny; ++m) {
+        int mm = (m <= g.ny / 2) ? m : m - g.ny;
+        double h = M_PI * mm / g.ny;
+        ky2[m] = std::pow(2.0 / dy * std::sin(h), 2);
+        kapy[m] = std::sin(2.0 * h) / dy;
+    }
+    if (d.dim == 1) { ky2[0] = 0.0; kapy[0] = 0.0; }
+    bool copied = hipMemcpy(c->dev.kx2, kx2.data(), sizeof(double) * hx, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(c->dev.kapx, kapx.data(), sizeof(double) * hx, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(c->dev.ky2, ky2.data(), sizeof(double) * g.ny, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(c->dev.kapy, kapy.data(), sizeof(double) * g.ny, hipMemcpyHostToDevice) == hipSuccess;
+    if (!copied) {
+        (void)hipFree(c->dev_block);
+        delete c;
+        return APIC_EHIP;
+    }
+    if (d.dim == 2) {
+        int n2[2] = {g.ny, g.nx};
+        if (hipfftPlan2d(&c->fwd, g.ny, g.nx, HIPFFT_D2Z) != HIPFFT_SUCCESS ||
+            hipfftPlanMany(&c->inv, 2, n2, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_Z2D, 2) != HIPFFT_SUCCESS) {
+            (void)hipFree(c->dev_block);
+            delete c;
+            return APIC_EHIP;
+        }
+        c->have_fft = true;
+    }
+    *out = c;
+    return APIC_OK;
+}
+
+void apic_destroy(apic_ctx *c) {
+    if (!c) return;
+    if (c->have_fft) {
+        hipfftDestroy(c->fwd);
+        hipfftDestroy(c->inv);
+    }
+    if (c->dev_block) (void)hipFree(c->dev_block);
+    delete c;
+}
+
+apic_status apic_workspace_size(const apic_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return APIC_EINVAL;
+    *bytes = c->ws_bytes;
+    return APIC_OK;
+}
+
+int64_t apic_num_buckets(const apic_ctx *c) { return c ? c->g.nbuckets : -1; }
+
+int apic_frac_bits(const apic_ctx *c) { return c ? c->g.S : -1; }
+
+const char *apic_last_error(const apic_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+apic_status apic_sort_by_cell(apic_ctx *c, apic_particles *p, void *ws, void *stream) {
+    if (!c) return APIC_EINVAL;
+    apic_status st = check_parts(c, p, true);
+    if (st != APIC_OK) return st;
+    if (!ws) return fail(c, APIC_EINVAL, "workspace is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = c->g.nbuckets;
+    int32_t *keys = wsp<int32_t>(ws, c->o_keys);
+    int32_t *count = wsp<int32_t>(ws, c->o_count);
+    int32_t *cursor = wsp<int32_t>(ws, c->o_cursor);
+    Parts src = parts_of(p), tmp = parts_ws(c, ws);
+    HIPCHK(c, launch_fill_i32(count, nb, 0, s));
+    HIPCHK(c, launch_keys_hist(c->g, c->mixed, src, c->n, keys, count, c->dev, s));
+    HIPCHK(c, launch_scan(count, p->bucket_start, cursor, count, nb, c->n, max_per_bucket(c), nullptr, c->dev, s));
+    HIPCHK(c, launch_scatter(c->g, c->mixed, src, tmp, c->n, keys, cursor, p->bucket_start, p->perm, c->dev, s));
+    return copy_parts(c, src, tmp, s);
+}
+
+apic_status apic_deposit(apic_ctx *c, const apic_particles *p, void *rho, void *stream) {
+    if (!c) return APIC_EINVAL;
+    apic_status st = check_parts(c, p, false);
+    if (st != APIC_OK) return st;
+    if (!rho) return fail(c, APIC_EINVAL, "rho is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    HIPCHK(c, launch_fill_u64((uint64_t *)rho, G, 0, s));
+    HIPCHK(c, launch_deposit(c->g, c->mixed, parts_of(p), c->n, p->bucket_start, rho, c->dev, s));
+    if (!c->mixed)
+        HIPCHK(c, launch_rho(c->g, false, rho, (double *)rho, acc_scale(c), c->d.rho_ion, c->d.rho_ion, c->dV, 0,
+                             nullptr, 0, c->dev, s));
+    return APIC_OK;
+}
+
+apic_status apic_field_solve(apic_ctx *c, const void *rho, double *E, float *E32, double *we, void *ws,
+                             void *stream) {
+    if (!c) return APIC_EINVAL;
+    if (!rho || !E || !ws) return fail(c, APIC_EINVAL, "rho, E and workspace are required");
+    hipStream_t s = (hipStream_t)stream;
+    // FP64 input already is rho; mixed input is the fixed-point node sums.
+    return field_from_acc(c, const_cast<void *>(rho), !c->mixed, E, E32, we, nullptr, 0, 0, ws, s);
+}
+
+apic_status apic_gather_push(apic_ctx *c, apic_particles *p, const void *E, double dt_scale, int move,
+                             void *stream) {
+    if (!c) return APIC_EINVAL;
+    apic_status st = check_parts(c, p, false);
+    if (st != APIC_OK) return st;
+    if (!E) return fail(c, APIC_EINVAL, "E is NULL");
+    if (!std::isfinite(dt_scale)) return fail(c, APIC_EINVAL, "dt_scale is not finite");
+    hipStream_t s = (hipStream_t)stream;
+    PushC pc = push_coeffs(c, dt_scale, move);
+    HIPCHK(c, launch_gather_push(c->g, c->mixed, parts_of(p), c->n, p->bucket_start, E, pc, c->dev, s));
+    return APIC_OK;
+}
+
+apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, float *E32, int nsteps, double *diag,
+                      void *ws, void *stream) {
+    if (!c) return APIC_EINVAL;
+    apic_status st = check_parts(c, p, true);
+    if (st != APIC_OK) return st;
+    if (!E || !ws || nsteps < 0) return fail(c, APIC_EINVAL, "E, workspace and nsteps >= 0 are required");
+    if (c->mixed && !E32) return fail(c, APIC_EINVAL, "mixed path needs E32 (E^n as float)");
+    if (nsteps == 0) return APIC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = c->g.nbuckets;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    int32_t *count = wsp<int32_t>(ws, c->o_count);
+    int32_t *cursor = wsp<int32_t>(ws, c->o_cursor);
+    void *acc = wsp<void>(ws, c->o_acc);
+    Parts A = parts_of(p), B = parts_ws(c, ws);
+    int32_t *bsA = p->bucket_start, *bsB = wsp<int32_t>(ws, c->o_bstart);
+    const PushC pc = push_coeffs(c, 1.0, 1);
+    const void *Ecur = c->mixed ? (const void *)E32 : (const void *)E;
+    HIPCHK(c, launch_fill_i32(count, nb, 0, s));
+    HIPCHK(c, launch_fill_u64((uint64_t *)acc, G, 0, s));
+    HIPCHK(c, launch_set_step(c->dev.step, -1, s));
+    for (int k = 0; k < nsteps; ++k) {
+        const bool even = (k & 1) == 0;
+        const Parts &src = even ? A : B;
+        const Parts &dst = even ? B : A;
+        int32_t *bs_src = even ? bsA : bsB;
+        int32_t *bs_dst = even ? bsB : bsA;
+        HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, Ecur, pc, count, c->dev, s));
+        HIPCHK(c, launch_scan(count, bs_dst, cursor, count, nb, c->n, max_per_bucket(c), diag, c->dev, s));
+        HIPCHK(c, launch_step_push(c->g, c->mixed, src, dst, bs_src, bs_dst, cursor, Ecur, pc, acc, p->perm, diag,
+                                   c->mass, c->dev, s));
+        if (rho && k == nsteps - 1) {
+            if (c->mixed)
+                HIPCHK(c, launch_copy_bytes(rho, acc, 8 * G, s));
+            else
+                HIPCHK(c, launch_rho(c->g, false, acc, (double *)rho, acc_scale(c), c->d.rho_ion, c->d.rho_ion, c->dV,
+                                     0, nullptr, 0, c->dev, s));
+        }
+        st = field_from_acc(c, acc, false, E, E32, diag ? diag + 1 : nullptr, diag ? diag + 0 : nullptr, 1, 1, ws,
+                            s);
+        if (st != APIC_OK) return st;
+    }
+    if (nsteps & 1) {
+        st = copy_parts(c, A, B, s);
+        if (st != APIC_OK) return st;
+        HIPCHK(c, launch_copy_bytes(bsA, bsB, 4 * (int64_t)(nb + 1), s));
+    }
+    return APIC_OK;
+}
+
+apic_status apic_sync_status(apic_ctx *c, void *stream) {
+    if (!c) return APIC_EINVAL;
+    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    int bits = 0;
+    HIPCHK(c, hipMemcpy(&bits, c->dev.err, sizeof(int), hipMemcpyDeviceToHost));
+    if (bits == 0) return APIC_OK;
+    int zero = 0;
+    HIPCHK(c, hipMemcpy(c->dev.err, &zero, sizeof(int), hipMemcpyHostToDevice));
+    if (bits & ERR_OVERFLOW)
+        return fail(c, APIC_EOVERFLOW, "fixed-point deposit headroom exceeded (too many particles per bucket)");
+    if (bits & ERR_COUNT) return fail(c, APIC_EDOMAIN, "bucket histogram total differs from particle count");
+    if (bits & ERR_ORDER)
+        return fail(c, APIC_EDOMAIN, "particles not ordered as bucket_start says, or a slot overflowed");
+    return fail(c, APIC_EDOMAIN, "non-finite or out-of-range particle coordinate");
+}
+
+}  // extern "C"

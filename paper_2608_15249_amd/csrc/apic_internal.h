@@ -1,0 +1,109 @@
+// Internal declarations shared by the kernel and host translation units of
+// libapic (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace apic {
+
+// Error bits raised by kernels (OR-ed into a device word of the context).
+enum : int {
+    ERR_DOMAIN = 1,    // NaN/Inf or out-of-range particle coordinate
+    ERR_ORDER = 2,     // particle outside the tile its bucket says / slot overflow
+    ERR_OVERFLOW = 4,  // fixed-point node sums may exceed int64
+    ERR_COUNT = 8,     // histogram total differs from the particle count
+};
+
+// Grid geometry and bucket (tile) layout, passed to kernels by value.
+struct Geo {
+    int dim, vdim;
+    int nx, ny;           // nodes per axis (ny = 1 in 1D)
+    int tsx, tsy;         // log2 of the tile size in cells
+    int nbx, nby;         // tiles per axis
+    int nbuckets;
+    int halo;             // deposit halo (cells) around a tile held in LDS
+    int S;                // fixed-point weight bits per axis (mixed path)
+    int np;               // number of particles (bounds for bucket tables)
+    double lx, ly;
+    double inv_dx, inv_dy;
+};
+
+// Boris / move coefficients for one call (dt_eff = dt * dt_scale).
+struct PushC {
+    double a, t, s;       // a = (q/m) dt_eff / 2, t = a bz, s = 2t/(1+t^2)
+    float af, tf, sf;
+    double dt;            // position step (unscaled dt)
+    float dtdx, dtdy;     // dt/dx, dt/dy in binary32 (mixed path)
+    int move;
+};
+
+// One particle buffer set (structure of arrays).
+struct Parts {
+    double *x, *y;
+    int32_t *cell;
+    float *ox, *oy;
+    void *vx, *vy, *vz;
+};
+
+// Device scratch owned by the context.
+struct CtxDev {
+    int *err;             // error bits
+    unsigned *counter;    // arrival counter of the last-block reductions
+    int *step;            // step index inside apic_step (device side)
+    double *partials;     // per-block partial sums [kMaxPartials]
+    double *kx2, *kapx;   // modified wavenumber tables, x: [nx/2+1]
+    double *ky2, *kapy;   // y: [ny]
+};
+
+constexpr int kMaxPartials = 65536;
+
+// ---- launchers (apic_kernels.hip) -----------------------------------------
+// All return hipSuccess or the launch error.
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_set_step(int *step, int v, hipStream_t s);
+hipError_t launch_copy_bytes(void *dst, const void *src, int64_t bytes, hipStream_t s);
+
+// general counting sort (arbitrary input order)
+hipError_t launch_keys_hist(const Geo &g, bool mixed, const Parts &p, int64_t n, int32_t *keys,
+                            int32_t *count, const CtxDev &c, hipStream_t s);
+hipError_t launch_scan(const int32_t *count, int32_t *start, int32_t *cursor, int32_t *count_zero,
+                       int nb, int64_t n, int64_t max_per_bucket, double *diag, const CtxDev &c,
+                       hipStream_t s);
+hipError_t launch_scatter(const Geo &g, bool mixed, const Parts &src, const Parts &dst, int64_t n,
+                          const int32_t *keys, int32_t *cursor, const int32_t *start, int32_t *perm,
+                          const CtxDev &c, hipStream_t s);
+
+// deposit of current positions into acc (double weights or int64 sums)
+hipError_t launch_deposit(const Geo &g, bool mixed, const Parts &p, int64_t n, const int32_t *bstart,
+                          void *acc, const CtxDev &c, hipStream_t s);
+
+// gather + Boris (+ move), in place
+hipError_t launch_gather_push(const Geo &g, bool mixed, const Parts &p, int64_t n,
+                              const int32_t *bstart, const void *E, const PushC &pc, const CtxDev &c,
+                              hipStream_t s);
+
+// fused step kernels
+hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int32_t *bstart,
+                             const void *E, const PushC &pc, int32_t *count, const CtxDev &c,
+                             hipStream_t s);
+hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Parts &dst,
+                            const int32_t *bstart, const int32_t *bstart_new, int32_t *cursor,
+                            const void *E, const PushC &pc, void *acc, int32_t *perm, double *diag,
+                            double mass, const CtxDev &c, hipStream_t s);
+
+// field: accumulation buffer -> rho (FP64): rho = add + scale * acc;
+// charge = dV * sum (rho - ion); outputs are step-indexed when step_mode != 0.
+hipError_t launch_rho(const Geo &g, bool mixed, void *acc, double *rho, double scale, double add, double ion,
+                      double dV, int clear, double *charge_out, int step_mode, const CtxDev &c, hipStream_t s);
+hipError_t launch_spectral(const Geo &g, const void *rho_hat, void *ex_hat, void *ey_hat,
+                           const CtxDev &c, hipStream_t s);
+hipError_t launch_efinish(const Geo &g, const double *E, float *E32, double dV, double *we_out,
+                          int step_mode, const CtxDev &c, hipStream_t s);
+hipError_t launch_field1d(const Geo &g, bool mixed, void *acc, double scale, double add, double ion,
+                          double dx, int clear, double *E, float *E32, double *we_out,
+                          double *charge_out, int step_mode, const CtxDev &c, hipStream_t s);
+
+}  // namespace apic
