@@ -71,7 +71,8 @@ typedef struct {
     double bz;            /* uniform magnetic field along z (needs vdim >= 2)   */
     apic_precision prec;
     int frac_bits;        /* mixed path: S, fixed-point weight bits per axis;
-                             0 selects 32 (dim 1) or 20 (dim 2)                 */
+                             1..32 in 1D, 1..23 in 2D; 0 selects 32 (dim 1) or
+                             20 (dim 2)                                         */
     int tile_x, tile_y;   /* sort bucket = tile of tile_x * tile_y cells, powers
                              of two; 0 selects the default for the grid        */
 } apic_grid_desc;
@@ -162,8 +163,10 @@ apic_status apic_gather_push(apic_ctx *ctx, apic_particles *p, const void *E, do
  *   Poisson -> E^{n+1}.
  * rho  [dev] optional output (NULL = none): the last step's deposit, in the
  *        format of apic_deposit (FP64 rho, or the int64 fixed-point sums).
- * E    [dev]: double [dim*G] in/out (FP64 E^n in, E^{n+nsteps} out).
- * E32  [dev]: float [dim*G] in/out for MIXED (must hold E^n as float); NULL for FP64.
+ * E    [dev]: double [dim*G] in/out (E^n in, E^{n+nsteps} out). The mixed path
+ *        rounds E to binary32 as it stages each tile for the gather.
+ * E32  [dev]: optional float [dim*G] output (NULL = none): E^{n+nsteps} rounded
+ *        to binary32.
  * diag [dev, double, nsteps*4] per step k (time level n+k -> n+k+1):
  *        [0] total deposited charge at n+k+1, sum_j (rho_j - rho_ion) dV
  *        [1] field energy W_E at n+k+1
@@ -173,9 +176,23 @@ apic_status apic_gather_push(apic_ctx *ctx, apic_particles *p, const void *E, do
  *      may be NULL.
  * p->perm [dev, int32, n] optional: the last step's reordering,
  *        after[i] = before_last_step[perm[i]].
- * On return the particles are again bucket-ordered (bucket_start updated). */
+ * On return the particles are again bucket-ordered (bucket_start updated).
+ * The order inside each bucket is a function of the previous order only
+ * (slots come from per-bucket tallies, not from atomics), so repeated runs
+ * give identical bits; the one exception is a particle that jumps more than
+ * one tile in a step, which takes a slot at the end of its bucket in arrival
+ * order. Workspace contents are not relied on across calls. */
 apic_status apic_step(apic_ctx *ctx, apic_particles *p, void *rho, double *E, float *E32, int nsteps,
                       double *diag, void *ws, void *stream);
+
+/* Per-phase timing of apic_step with HIP events recorded on the caller's
+ * stream around each phase of each step (count pass, scan, push pass, field
+ * solve). apic_profile_enable(ctx, max_steps) creates the events (host call,
+ * not for capture; max_steps = 0 disables); apic_profile_read waits for the
+ * last event and returns the summed milliseconds per phase in ms[4] and the
+ * number of profiled steps, then rearms. Steps beyond max_steps are not timed. */
+apic_status apic_profile_enable(apic_ctx *ctx, int max_steps);
+apic_status apic_profile_read(apic_ctx *ctx, double ms[4], int *steps);
 
 /* Waits for the stream, then returns and clears the device error flags
  * (APIC_OK, APIC_EDOMAIN or APIC_EOVERFLOW). */

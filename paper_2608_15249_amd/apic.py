@@ -45,7 +45,7 @@ class ParticlesC(ctypes.Structure):
 
 EXPORTS = ["apic_create", "apic_destroy", "apic_workspace_size", "apic_num_buckets", "apic_frac_bits",
            "apic_sort_by_cell", "apic_deposit", "apic_field_solve", "apic_gather_push", "apic_step",
-           "apic_sync_status", "apic_last_error"]
+           "apic_sync_status", "apic_last_error", "apic_profile_enable", "apic_profile_read"]
 
 _lib = None
 
@@ -73,6 +73,8 @@ def load_library(path: str = LIB_PATH):
         "apic_step": ([vp, P(ParticlesC), vp, vp, vp, cint, vp, vp, vp], cint),
         "apic_sync_status": ([vp, vp], cint),
         "apic_last_error": ([vp], ctypes.c_char_p),
+        "apic_profile_enable": ([vp, cint], cint),
+        "apic_profile_read": ([vp, P(ctypes.c_double), P(cint)], cint),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -139,6 +141,16 @@ class Context:
 
     def sync(self):
         self._check(self.L.apic_sync_status(self.h, _stream()))
+
+    def profile_enable(self, max_steps: int):
+        self._check(self.L.apic_profile_enable(self.h, int(max_steps)))
+
+    def profile_read(self):
+        """Summed milliseconds per phase (count, scan, push, field) and steps."""
+        ms = (ctypes.c_double * 4)()
+        nst = ctypes.c_int()
+        self._check(self.L.apic_profile_read(self.h, ms, ctypes.byref(nst)))
+        return list(ms), int(nst.value)
 
     # -- entry points -------------------------------------------------------
     def sort_by_cell(self, parts: "Particles", perm=None):

@@ -26,8 +26,13 @@ struct apic_ctx {
     // workspace layout (byte offsets)
     size_t o_x, o_y, o_cell, o_ox, o_oy, o_vx, o_vy, o_vz;
     size_t o_keys, o_count, o_cursor, o_bstart, o_acc, o_rho, o_rhat, o_ehat;
+    size_t o_cnt, o_offs, o_farcnt, o_farcur, o_tot;
+    size_t o_keys2, o_idx, o_idx2, o_rcnt, o_roff;
     size_t ws_bytes;
     double dV, mass;
+    // per-phase timing (apic_profile_enable)
+    std::vector<hipEvent_t> ev;   // 5 events per profiled step
+    int prof_max = 0, prof_used = 0;
 };
 
 namespace {
@@ -110,9 +115,19 @@ void layout(apic_ctx *c) {
     const int64_t nb = c->g.nbuckets;
     const int64_t G = (int64_t)c->d.nx * c->d.ny;
     c->o_keys = take(4 * n);
+    c->o_keys2 = take(4 * n);
+    c->o_idx = take(4 * n);
+    c->o_idx2 = take(4 * n);
+    c->o_rcnt = take(4 * (int64_t)sort_chunks(n) * sort_table_entries());
+    c->o_roff = take(4 * (int64_t)sort_chunks(n) * sort_table_entries());
     c->o_count = take(4 * nb);
     c->o_cursor = take(4 * nb);
     c->o_bstart = take(4 * (nb + 1));
+    c->o_cnt = take(4 * nb * kStepTab);
+    c->o_offs = take(4 * nb * kStepTab);
+    c->o_farcnt = take(4 * nb);
+    c->o_farcur = take(4 * nb);
+    c->o_tot = take(4 * nb);
     c->o_acc = take(8 * G);
     c->o_rho = take(8 * G);
     if (dim == 2) {
@@ -204,28 +219,37 @@ int64_t max_per_bucket(const apic_ctx *c) {
     return (int64_t(1) << bits) - 1;
 }
 
-apic_status field_from_acc(apic_ctx *c, void *acc, bool acc_is_rho, double *E, float *E32, double *we_out,
-                           double *charge_out, int step_mode, int clear, void *ws, hipStream_t s) {
+// Field of an accumulation buffer (or of a given FP64 rho): rho -> E (and
+// E32 when non-NULL). step_mode: diagnostics go to diag[step] together with
+// the push-pass partials (npush buckets); otherwise we/charge are written
+// directly when non-NULL.
+apic_status field_from_acc(apic_ctx *c, void *acc, bool acc_is_rho, double *E, float *E32, double *diag,
+                           double *we, double *charge, int npush, int clear, void *ws, hipStream_t s) {
     const double scale = acc_is_rho ? 1.0 : acc_scale(c);
     const double add = acc_is_rho ? 0.0 : c->d.rho_ion;
     const bool mixed_acc = c->mixed && !acc_is_rho;
+    const double G = (double)c->d.nx * c->d.ny;
     if (c->d.dim == 1) {
+        const int step_mode = diag ? 1 : 0;
         HIPCHK(c, launch_field1d(c->g, mixed_acc, acc, scale, add, c->d.rho_ion, c->d.lx / c->d.nx, clear, E, E32,
-                                 we_out, charge_out, step_mode, c->dev, s));
+                                 diag ? diag + 1 : we, diag ? diag + 0 : charge, step_mode, c->dev, s));
+        if (diag && npush)
+            HIPCHK(c, launch_finalize(npush, 0, c->mass, c->dV, G, c->d.rho_ion, diag, nullptr, nullptr, c->dev, s));
         return APIC_OK;
     }
     double *rho = wsp<double>(ws, c->o_rho);
     void *rhat = wsp<void>(ws, c->o_rhat);
     char *ehat = wsp<char>(ws, c->o_ehat);
     const size_t H = (size_t)(c->d.nx / 2 + 1) * c->d.ny;
-    HIPCHK(c, launch_rho(c->g, mixed_acc, acc, rho, scale, add, c->d.rho_ion, c->dV, clear, charge_out, step_mode,
-                         c->dev, s));
+    HIPCHK(c, launch_rho(c->g, mixed_acc, acc, rho, scale, add, clear, s));
     FFTCHK(c, hipfftSetStream(c->fwd, s));
     FFTCHK(c, hipfftExecD2Z(c->fwd, (hipfftDoubleReal *)rho, (hipfftDoubleComplex *)rhat));
     HIPCHK(c, launch_spectral(c->g, rhat, ehat, ehat + 16 * H, c->dev, s));
+    HIPCHK(c, launch_finalize(diag ? npush : 0, spectral_blocks(c->g), c->mass, c->dV, G, c->d.rho_ion, diag, we,
+                              charge, c->dev, s));
     FFTCHK(c, hipfftSetStream(c->inv, s));
     FFTCHK(c, hipfftExecZ2D(c->inv, (hipfftDoubleComplex *)ehat, (hipfftDoubleReal *)E));
-    HIPCHK(c, launch_efinish(c->g, E, E32, c->dV, we_out, step_mode, c->dev, s));
+    if (E32) HIPCHK(c, launch_to_f32(E, E32, 2 * (int64_t)G, s));
     return APIC_OK;
 }
 
@@ -291,7 +315,7 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     g.halo = 1;
     g.np = (int)n_particles;
     g.S = d.frac_bits ? d.frac_bits : (d.dim == 1 ? 32 : 20);
-    if (c->mixed && (g.S < 1 || g.S > 32 || g.S * d.dim > 48)) { delete c; return APIC_EINVAL; }
+    if (c->mixed && (g.S < 1 || g.S > 32 || (d.dim == 2 && g.S > 23))) { delete c; return APIC_EINVAL; }
     g.lx = d.lx;
     g.ly = d.dim == 2 ? d.ly : 1.0;
     const double dx = d.lx / d.nx, dy = d.dim == 2 ? d.ly / d.ny : 1.0;
@@ -303,7 +327,8 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
 
     // context device words + wavenumber tables
     const int hx = g.nx / 2 + 1;
-    size_t bytes = align256(sizeof(int)) * 3 + align256(sizeof(double) * kMaxPartials) +
+    size_t bytes = align256(sizeof(int)) * 2 + align256(sizeof(double) * 2 * g.nbuckets) +
+                   align256(sizeof(double) * kMaxSpecBlocks) + align256(sizeof(double)) +
                    align256(sizeof(double) * hx) * 2 + align256(sizeof(double) * g.ny) * 2;
     if (hipMalloc(&c->dev_block, bytes) != hipSuccess) { delete c; return APIC_ENOMEM; }
     if (hipMemset(c->dev_block, 0, bytes) != hipSuccess) { (void)hipFree(c->dev_block); delete c; return APIC_EHIP; }
@@ -311,9 +336,10 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     size_t off = 0;
     auto take = [&](size_t sz) { char *p = b + off; off += align256(sz); return p; };
     c->dev.err = (int *)take(sizeof(int));
-    c->dev.counter = (unsigned *)take(sizeof(int));
     c->dev.step = (int *)take(sizeof(int));
-    c->dev.partials = (double *)take(sizeof(double) * kMaxPartials);
+    c->dev.part_push = (double *)take(sizeof(double) * 2 * g.nbuckets);
+    c->dev.part_spec = (double *)take(sizeof(double) * kMaxSpecBlocks);
+    c->dev.rho0 = (double *)take(sizeof(double));
     c->dev.kx2 = (double *)take(sizeof(double) * hx);
     c->dev.kapx = (double *)take(sizeof(double) * hx);
     c->dev.ky2 = (double *)take(sizeof(double) * g.ny);
@@ -359,6 +385,7 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
 
 void apic_destroy(apic_ctx *c) {
     if (!c) return;
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->have_fft) {
         hipfftDestroy(c->fwd);
         hipfftDestroy(c->inv);
@@ -386,14 +413,26 @@ apic_status apic_sort_by_cell(apic_ctx *c, apic_particles *p, void *ws, void *st
     if (!ws) return fail(c, APIC_EINVAL, "workspace is NULL");
     hipStream_t s = (hipStream_t)stream;
     const int nb = c->g.nbuckets;
-    int32_t *keys = wsp<int32_t>(ws, c->o_keys);
+    int32_t *k0 = wsp<int32_t>(ws, c->o_keys), *k1 = wsp<int32_t>(ws, c->o_keys2);
+    int32_t *i0 = wsp<int32_t>(ws, c->o_idx), *i1 = wsp<int32_t>(ws, c->o_idx2);
     int32_t *count = wsp<int32_t>(ws, c->o_count);
     int32_t *cursor = wsp<int32_t>(ws, c->o_cursor);
     Parts src = parts_of(p), tmp = parts_ws(c, ws);
+    // bucket table from the histogram of keys
     HIPCHK(c, launch_fill_i32(count, nb, 0, s));
-    HIPCHK(c, launch_keys_hist(c->g, c->mixed, src, c->n, keys, count, c->dev, s));
-    HIPCHK(c, launch_scan(count, p->bucket_start, cursor, count, nb, c->n, max_per_bucket(c), nullptr, c->dev, s));
-    HIPCHK(c, launch_scatter(c->g, c->mixed, src, tmp, c->n, keys, cursor, p->bucket_start, p->perm, c->dev, s));
+    HIPCHK(c, launch_keys_hist(c->g, c->mixed, src, c->n, k0, count, c->dev, s));
+    HIPCHK(c, launch_scan(count, p->bucket_start, cursor, nb, c->n, max_per_bucket(c), c->dev, s));
+    // stable order by key
+    HIPCHK(c, launch_keys_init(c->g, c->mixed, src, c->n, k0, i0, c->dev, s));
+    int bits = 1;
+    while ((1ll << bits) < (int64_t)nb) ++bits;
+    for (int shift = 0; shift < bits; shift += 8) {
+        HIPCHK(c, launch_radix_pass(k0, i0, k1, i1, c->n, shift, wsp<int32_t>(ws, c->o_rcnt),
+                                    wsp<int32_t>(ws, c->o_roff), c->dev, s));
+        std::swap(k0, k1);
+        std::swap(i0, i1);
+    }
+    HIPCHK(c, launch_gather_parts(c->g, c->mixed, src, tmp, c->n, i0, p->perm, c->dev, s));
     return copy_parts(c, src, tmp, s);
 }
 
@@ -406,9 +445,7 @@ apic_status apic_deposit(apic_ctx *c, const apic_particles *p, void *rho, void *
     const int64_t G = (int64_t)c->d.nx * c->d.ny;
     HIPCHK(c, launch_fill_u64((uint64_t *)rho, G, 0, s));
     HIPCHK(c, launch_deposit(c->g, c->mixed, parts_of(p), c->n, p->bucket_start, rho, c->dev, s));
-    if (!c->mixed)
-        HIPCHK(c, launch_rho(c->g, false, rho, (double *)rho, acc_scale(c), c->d.rho_ion, c->d.rho_ion, c->dV, 0,
-                             nullptr, 0, c->dev, s));
+    if (!c->mixed) HIPCHK(c, launch_rho(c->g, false, rho, (double *)rho, acc_scale(c), c->d.rho_ion, 0, s));
     return APIC_OK;
 }
 
@@ -418,7 +455,7 @@ apic_status apic_field_solve(apic_ctx *c, const void *rho, double *E, float *E32
     if (!rho || !E || !ws) return fail(c, APIC_EINVAL, "rho, E and workspace are required");
     hipStream_t s = (hipStream_t)stream;
     // FP64 input already is rho; mixed input is the fixed-point node sums.
-    return field_from_acc(c, const_cast<void *>(rho), !c->mixed, E, E32, we, nullptr, 0, 0, ws, s);
+    return field_from_acc(c, const_cast<void *>(rho), !c->mixed, E, E32, nullptr, we, nullptr, 0, 0, ws, s);
 }
 
 apic_status apic_gather_push(apic_ctx *c, apic_particles *p, const void *E, double dt_scale, int move,
@@ -440,19 +477,21 @@ apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, floa
     apic_status st = check_parts(c, p, true);
     if (st != APIC_OK) return st;
     if (!E || !ws || nsteps < 0) return fail(c, APIC_EINVAL, "E, workspace and nsteps >= 0 are required");
-    if (c->mixed && !E32) return fail(c, APIC_EINVAL, "mixed path needs E32 (E^n as float)");
     if (nsteps == 0) return APIC_OK;
     hipStream_t s = (hipStream_t)stream;
     const int nb = c->g.nbuckets;
     const int64_t G = (int64_t)c->d.nx * c->d.ny;
-    int32_t *count = wsp<int32_t>(ws, c->o_count);
-    int32_t *cursor = wsp<int32_t>(ws, c->o_cursor);
+    int32_t *cnt = wsp<int32_t>(ws, c->o_cnt);
+    int32_t *offs = wsp<int32_t>(ws, c->o_offs);
+    int32_t *farcnt = wsp<int32_t>(ws, c->o_farcnt);
+    int32_t *farcur = wsp<int32_t>(ws, c->o_farcur);
+    int32_t *tot = wsp<int32_t>(ws, c->o_tot);
     void *acc = wsp<void>(ws, c->o_acc);
     Parts A = parts_of(p), B = parts_ws(c, ws);
     int32_t *bsA = p->bucket_start, *bsB = wsp<int32_t>(ws, c->o_bstart);
     const PushC pc = push_coeffs(c, 1.0, 1);
-    const void *Ecur = c->mixed ? (const void *)E32 : (const void *)E;
-    HIPCHK(c, launch_fill_i32(count, nb, 0, s));
+    HIPCHK(c, launch_fill_i32(farcnt, nb, 0, s));
+    HIPCHK(c, launch_fill_i32(tot, nb, 0, s));
     HIPCHK(c, launch_fill_u64((uint64_t *)acc, G, 0, s));
     HIPCHK(c, launch_set_step(c->dev.step, -1, s));
     for (int k = 0; k < nsteps; ++k) {
@@ -461,26 +500,62 @@ apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, floa
         const Parts &dst = even ? B : A;
         int32_t *bs_src = even ? bsA : bsB;
         int32_t *bs_dst = even ? bsB : bsA;
-        HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, Ecur, pc, count, c->dev, s));
-        HIPCHK(c, launch_scan(count, bs_dst, cursor, count, nb, c->n, max_per_bucket(c), diag, c->dev, s));
-        HIPCHK(c, launch_step_push(c->g, c->mixed, src, dst, bs_src, bs_dst, cursor, Ecur, pc, acc, p->perm, diag,
-                                   c->mass, c->dev, s));
-        if (rho && k == nsteps - 1) {
+        const bool last = k == nsteps - 1;
+        hipEvent_t *ev = nullptr;
+        if (c->prof_used < c->prof_max) ev = &c->ev[5 * (size_t)c->prof_used++];
+        if (ev) HIPCHK(c, hipEventRecord(ev[0], s));
+        HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, E, pc, cnt, tot, farcnt, c->dev, s));
+        if (ev) HIPCHK(c, hipEventRecord(ev[1], s));
+        HIPCHK(c, launch_scan_dir(c->g, cnt, farcnt, tot, bs_dst, offs, farcur, c->n, max_per_bucket(c), 1, c->dev,
+                                  s));
+        if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
+        HIPCHK(c, launch_step_push(c->g, c->mixed, src, dst, bs_src, bs_dst, offs, farcur, E, pc, acc, p->perm,
+                                   diag ? c->dev.part_push : nullptr, c->dev, s));
+        if (ev) HIPCHK(c, hipEventRecord(ev[3], s));
+        if (rho && last) {
             if (c->mixed)
                 HIPCHK(c, launch_copy_bytes(rho, acc, 8 * G, s));
             else
-                HIPCHK(c, launch_rho(c->g, false, acc, (double *)rho, acc_scale(c), c->d.rho_ion, c->d.rho_ion, c->dV,
-                                     0, nullptr, 0, c->dev, s));
+                HIPCHK(c, launch_rho(c->g, false, acc, (double *)rho, acc_scale(c), c->d.rho_ion, 0, s));
         }
-        st = field_from_acc(c, acc, false, E, E32, diag ? diag + 1 : nullptr, diag ? diag + 0 : nullptr, 1, 1, ws,
-                            s);
+        st = field_from_acc(c, acc, false, E, last ? E32 : nullptr, diag, nullptr, nullptr, diag ? nb : 0, 1, ws, s);
         if (st != APIC_OK) return st;
+        if (ev) HIPCHK(c, hipEventRecord(ev[4], s));
     }
     if (nsteps & 1) {
         st = copy_parts(c, A, B, s);
         if (st != APIC_OK) return st;
         HIPCHK(c, launch_copy_bytes(bsA, bsB, 4 * (int64_t)(nb + 1), s));
     }
+    return APIC_OK;
+}
+
+apic_status apic_profile_enable(apic_ctx *c, int max_steps) {
+    if (!c || max_steps < 0) return APIC_EINVAL;
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    c->ev.clear();
+    c->prof_max = c->prof_used = 0;
+    if (max_steps == 0) return APIC_OK;
+    c->ev.resize(5 * (size_t)max_steps);
+    for (auto &e : c->ev) HIPCHK(c, hipEventCreate(&e));
+    c->prof_max = max_steps;
+    return APIC_OK;
+}
+
+apic_status apic_profile_read(apic_ctx *c, double ms[4], int *steps) {
+    if (!c || !ms || !steps) return APIC_EINVAL;
+    for (int k = 0; k < 4; ++k) ms[k] = 0.0;
+    *steps = c->prof_used;
+    if (c->prof_used == 0) return APIC_OK;
+    HIPCHK(c, hipEventSynchronize(c->ev[5 * (size_t)(c->prof_used - 1) + 4]));
+    for (int st = 0; st < c->prof_used; ++st) {
+        for (int k = 0; k < 4; ++k) {
+            float t = 0.0f;
+            HIPCHK(c, hipEventElapsedTime(&t, c->ev[5 * (size_t)st + k], c->ev[5 * (size_t)st + k + 1]));
+            ms[k] += t;
+        }
+    }
+    c->prof_used = 0;
     return APIC_OK;
 }
 

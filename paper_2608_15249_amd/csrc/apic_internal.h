@@ -49,14 +49,16 @@ struct Parts {
 // Device scratch owned by the context.
 struct CtxDev {
     int *err;             // error bits
-    unsigned *counter;    // arrival counter of the last-block reductions
     int *step;            // step index inside apic_step (device side)
-    double *partials;     // per-block partial sums [kMaxPartials]
+    double *part_push;    // per-bucket (kinetic, momentum) partials [2 * nbuckets]
+    double *part_spec;    // per-block field-energy partials [kMaxSpecBlocks]
+    double *rho0;         // rho_hat(0) = sum_j rho_j of the last spectral solve
     double *kx2, *kapx;   // modified wavenumber tables, x: [nx/2+1]
     double *ky2, *kapy;   // y: [ny]
 };
 
-constexpr int kMaxPartials = 65536;
+constexpr int kMaxSpecBlocks = 1024;
+constexpr int kStepTab = 40;  // per-bucket direction table entries (4 waves x 10 directions)
 
 // ---- launchers (apic_kernels.hip) -----------------------------------------
 // All return hipSuccess or the launch error.
@@ -65,43 +67,53 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_set_step(int *step, int v, hipStream_t s);
 hipError_t launch_copy_bytes(void *dst, const void *src, int64_t bytes, hipStream_t s);
+hipError_t launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 
 // general counting sort (arbitrary input order)
 hipError_t launch_keys_hist(const Geo &g, bool mixed, const Parts &p, int64_t n, int32_t *keys,
                             int32_t *count, const CtxDev &c, hipStream_t s);
-hipError_t launch_scan(const int32_t *count, int32_t *start, int32_t *cursor, int32_t *count_zero,
-                       int nb, int64_t n, int64_t max_per_bucket, double *diag, const CtxDev &c,
-                       hipStream_t s);
-hipError_t launch_scatter(const Geo &g, bool mixed, const Parts &src, const Parts &dst, int64_t n,
-                          const int32_t *keys, int32_t *cursor, const int32_t *start, int32_t *perm,
-                          const CtxDev &c, hipStream_t s);
+hipError_t launch_scan(int32_t *count, int32_t *start, int32_t *cursor, int nb, int64_t n,
+                       int64_t max_per_bucket, const CtxDev &c, hipStream_t s);
+// stable LSD radix sort of (bucket key, index), then a gather of the arrays
+hipError_t launch_keys_init(const Geo &g, bool mixed, const Parts &p, int64_t n, int32_t *keys,
+                            int32_t *idx, const CtxDev &c, hipStream_t s);
+int sort_chunks(int64_t n);
+int sort_table_entries();
+hipError_t launch_radix_pass(const int32_t *kin, const int32_t *iin, int32_t *kout, int32_t *iout,
+                             int64_t n, int shift, int32_t *cnt, int32_t *off, const CtxDev &c,
+                             hipStream_t s);
+hipError_t launch_gather_parts(const Geo &g, bool mixed, const Parts &src, const Parts &dst, int64_t n,
+                               const int32_t *idx, int32_t *perm, const CtxDev &c, hipStream_t s);
 
 // deposit of current positions into acc (double weights or int64 sums)
 hipError_t launch_deposit(const Geo &g, bool mixed, const Parts &p, int64_t n, const int32_t *bstart,
                           void *acc, const CtxDev &c, hipStream_t s);
 
-// gather + Boris (+ move), in place
+// gather + Boris (+ move), in place; E is double (FP64) or float (mixed)
 hipError_t launch_gather_push(const Geo &g, bool mixed, const Parts &p, int64_t n,
                               const int32_t *bstart, const void *E, const PushC &pc, const CtxDev &c,
                               hipStream_t s);
 
-// fused step kernels
+// fused step: direction tallies, scan into offsets, push + deposit + scatter
 hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int32_t *bstart,
-                             const void *E, const PushC &pc, int32_t *count, const CtxDev &c,
-                             hipStream_t s);
+                             const double *E, const PushC &pc, int32_t *cnt, int32_t *tot,
+                             int32_t *farcnt, const CtxDev &c, hipStream_t s);
+hipError_t launch_scan_dir(const Geo &g, const int32_t *cnt, int32_t *farcnt, int32_t *tot,
+                           int32_t *start, int32_t *offs, int32_t *farcur, int64_t n,
+                           int64_t max_per_bucket, int step_mode, const CtxDev &c, hipStream_t s);
 hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Parts &dst,
-                            const int32_t *bstart, const int32_t *bstart_new, int32_t *cursor,
-                            const void *E, const PushC &pc, void *acc, int32_t *perm, double *diag,
-                            double mass, const CtxDev &c, hipStream_t s);
+                            const int32_t *bstart, const int32_t *bstart_new, const int32_t *offs,
+                            int32_t *farcur, const double *E, const PushC &pc, void *acc, int32_t *perm,
+                            double *part, const CtxDev &c, hipStream_t s);
 
-// field: accumulation buffer -> rho (FP64): rho = add + scale * acc;
-// charge = dV * sum (rho - ion); outputs are step-indexed when step_mode != 0.
-hipError_t launch_rho(const Geo &g, bool mixed, void *acc, double *rho, double scale, double add, double ion,
-                      double dV, int clear, double *charge_out, int step_mode, const CtxDev &c, hipStream_t s);
+// field: accumulation buffer -> rho (FP64): rho = add + scale * acc
+hipError_t launch_rho(const Geo &g, bool mixed, void *acc, double *rho, double scale, double add,
+                      int clear, hipStream_t s);
+int spectral_blocks(const Geo &g);
 hipError_t launch_spectral(const Geo &g, const void *rho_hat, void *ex_hat, void *ey_hat,
                            const CtxDev &c, hipStream_t s);
-hipError_t launch_efinish(const Geo &g, const double *E, float *E32, double dV, double *we_out,
-                          int step_mode, const CtxDev &c, hipStream_t s);
+hipError_t launch_finalize(int npush, int nspec, double mass, double dV, double G, double rho_ion,
+                           double *diag, double *we, double *charge, const CtxDev &c, hipStream_t s);
 hipError_t launch_field1d(const Geo &g, bool mixed, void *acc, double scale, double add, double ion,
                           double dx, int clear, double *E, float *E32, double *we_out,
                           double *charge_out, int step_mode, const CtxDev &c, hipStream_t s);

@@ -17,12 +17,14 @@
 //    (neighbouring tiles, which share halo nodes and E tiles) run on the same
 //    XCD, so their traffic stays in that XCD's L2.
 //  * Per step the fused path runs two particle passes: a count pass (gather,
-//    push and move computed, only the new bucket histogram kept) and a push
+//    push and move computed, only the tallies of new buckets kept) and a push
 //    pass that recomputes the same update bit for bit, deposits rho^{n+1} and
 //    writes each particle straight to its slot of the next bucket order
 //    (counting sort: histogram -> exclusive scan -> scatter). State traffic is
 //    read + read + write per particle-step instead of read/write for the push
-//    plus read/write for a separate sort.
+//    plus read/write for a separate sort. Slots come from a per-(bucket,
+//    wave, direction) offset table, so the order, the deposit sums and all
+//    reductions are reproducible run to run.
 //  * The mixed path holds positions as an integer cell plus a binary32
 //    in-cell offset and deposits with int64 fixed-point weights, so the charge
 //    density is exact and independent of summation order.
@@ -57,6 +59,17 @@ __device__ __forceinline__ int bucket_of_block(int nbuckets) {
 
 inline int grid_for_buckets(int nbuckets) { return ((nbuckets + 7) >> 3) << 3; }
 
+// Persistent launches: gridDim.x (a multiple of 8) blocks walk the buckets.
+// Block i runs on XCD i % 8 and takes every (gridDim.x/8)-th bucket of that
+// XCD's contiguous bucket range, so neighbouring tiles share an L2.
+__device__ __forceinline__ void bucket_walk(int nbuckets, int &first, int &end, int &stride) {
+    const int per = (nbuckets + 7) >> 3;
+    const int x = (int)(blockIdx.x & 7);
+    first = x * per + (int)(blockIdx.x >> 3);
+    end = min((x + 1) * per, nbuckets);
+    stride = (int)(gridDim.x >> 3);
+}
+
 // ---------------------------------------------------------------- reductions
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -65,7 +78,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Block-wide sum, deterministic (fixed tree); result valid in every thread.
-__device__ double block_sum(double v, double *sh /* [kWaves] */) {
+__device__ double block_sum(double v, double *sh /* [waves] */) {
     v = wave_sum(v);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) sh[w] = v;
@@ -74,31 +87,6 @@ __device__ double block_sum(double v, double *sh /* [kWaves] */) {
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
     __syncthreads();
     return t;
-}
-
-// Deterministic grid-wide sum: each block stores its partial, the last block
-// to arrive adds the partials in block order and writes out = scale * sum.
-__device__ void grid_sum_store(double v, double *out, double scale, const CtxDev &c, double *sh) {
-    double b = block_sum(v, sh);
-    __shared__ int is_last;
-    if (threadIdx.x == 0) {
-        c.partials[blockIdx.x] = b;
-        __threadfence();
-        unsigned prev = atomicAdd(c.counter, 1u);
-        is_last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (is_last) {
-        __threadfence();
-        double t = 0.0;
-        for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x)
-            t += ((volatile double *)c.partials)[i];
-        t = block_sum(t, sh);
-        if (threadIdx.x == 0) {
-            if (out) *out = t * scale;
-            *c.counter = 0u;
-        }
-    }
 }
 
 __device__ __forceinline__ double *step_slot(double *base, const CtxDev &c) {
@@ -196,6 +184,8 @@ __device__ __forceinline__ int bucket_of(const Geo &g, int ix, int iy) {
 }
 
 // Boris advance: half kick, rotation about z, half kick (Boris 1970).
+// With t = 0 (no magnetic field) the rotation terms are exact zeros, so the
+// uniform branch that skips them gives the same bits as the full formula.
 template <typename R, int VDIM>
 __device__ __forceinline__ void boris(R &vx, R &vy, R ex, R ey, R a, R t, R s) {
     if constexpr (VDIM == 1) {
@@ -204,12 +194,16 @@ __device__ __forceinline__ void boris(R &vx, R &vy, R ex, R ey, R a, R t, R s) {
     } else {
         R mx = vx + a * ex;
         R my = vy + a * ey;
-        R px = mx + my * t;
-        R py = my - mx * t;
-        R qx = mx + py * s;
-        R qy = my - px * s;
-        vx = qx + a * ex;
-        vy = qy + a * ey;
+        if (t != R(0)) {
+            R px = mx + my * t;
+            R py = my - mx * t;
+            R qx = mx + py * s;
+            R qy = my - px * s;
+            mx = qx;
+            my = qy;
+        }
+        vx = mx + a * ex;
+        vy = my + a * ey;
     }
 }
 
@@ -292,9 +286,10 @@ __device__ __forceinline__ int64_t qw1(float o, float scale) {
 
 // ------------------------------------------------------- LDS tile helpers
 
-// E tile: nodes [x0, x0+TX] x [y0, y0+TY] (periodic), comps [DIM].
-template <typename R, int DIM>
-__device__ void load_e_tile(R *sE, const R *E, const Geo &g, int x0, int y0, int wx, int wy) {
+// E tile: nodes [x0, x0+TX] x [y0, y0+TY] (periodic), comps [DIM], converted
+// to the push precision R on the way into LDS.
+template <typename R, typename ET, int DIM>
+__device__ void load_e_tile(R *sE, const ET *E, const Geo &g, int x0, int y0, int wx, int wy) {
     const int G = g.nx * g.ny;
     const int tot = wx * wy;
     for (int t = threadIdx.x; t < tot; t += blockDim.x) {
@@ -304,8 +299,8 @@ __device__ void load_e_tile(R *sE, const R *E, const Geo &g, int x0, int y0, int
         int gy = y0 + ly;
         if (gy >= g.ny) gy -= g.ny;
         int gi = gy * g.nx + gx;
-        sE[t] = E[gi];
-        if constexpr (DIM == 2) sE[tot + t] = E[G + gi];
+        sE[t] = (R)E[gi];
+        if constexpr (DIM == 2) sE[tot + t] = (R)E[G + gi];
     }
 }
 
@@ -325,13 +320,15 @@ __device__ __forceinline__ void gather_lds(const R *sE, int wx, int tot, int lx,
     }
 }
 
-template <typename R, int DIM>
-__device__ __forceinline__ void gather_global(const R *E, const Geo &g, int ix, int iy, R fx, R fy,
+// Same interpolation from the global field (node values converted to R first,
+// exactly as the LDS tile holds them).
+template <typename R, typename ET, int DIM>
+__device__ __forceinline__ void gather_global(const ET *E, const Geo &g, int ix, int iy, R fx, R fy,
                                               R &ex, R &ey) {
     int ip = ix + 1;
     if (ip >= g.nx) ip = 0;
     if constexpr (DIM == 1) {
-        ex = (R(1) - fx) * E[ix] + fx * E[ip];
+        ex = (R(1) - fx) * (R)E[ix] + fx * (R)E[ip];
         ey = R(0);
     } else {
         const int G = g.nx * g.ny;
@@ -340,8 +337,8 @@ __device__ __forceinline__ void gather_global(const R *E, const Geo &g, int ix, 
         R w00 = (R(1) - fx) * (R(1) - fy), w10 = fx * (R(1) - fy);
         R w01 = (R(1) - fx) * fy, w11 = fx * fy;
         int a00 = iy * g.nx + ix, a10 = iy * g.nx + ip, a01 = jp * g.nx + ix, a11 = jp * g.nx + ip;
-        ex = w00 * E[a00] + w10 * E[a10] + w01 * E[a01] + w11 * E[a11];
-        ey = w00 * E[G + a00] + w10 * E[G + a10] + w01 * E[G + a01] + w11 * E[G + a11];
+        ex = w00 * (R)E[a00] + w10 * (R)E[a10] + w01 * (R)E[a01] + w11 * (R)E[a11];
+        ey = w00 * (R)E[G + a00] + w10 * (R)E[G + a10] + w01 * (R)E[G + a01] + w11 * (R)E[G + a11];
     }
 }
 
@@ -354,23 +351,29 @@ __device__ __forceinline__ void acc_add(typename AccOf<MIX>::T *a, typename AccO
     atomicAdd(a, v);
 }
 
-// CIC weights of a particle at (fx, fy) as accumulator values.
+// CIC weights of a particle at (fx, fy) as accumulator values. Fixed point:
+// w1 = round-half-even(o 2^S) (o 2^S is exact in binary32), w0 = 2^S - w1;
+// in 2D (S <= 23) both fit 24 bits and the node weight is their exact 48-bit
+// product (24-bit multiplies).
 template <bool MIX, int DIM>
 __device__ __forceinline__ void dep_weights(const Pt<MIX> &p, const Geo &g,
                                             typename AccOf<MIX>::T w[4]) {
     if constexpr (MIX) {
         const float scale = (float)(1ull << g.S);
-        const int64_t one = (int64_t)1 << g.S;
-        int64_t w1x = qw1(p.fx, scale), w0x = one - w1x;
         if constexpr (DIM == 1) {
-            w[0] = (unsigned long long)w0x;
-            w[1] = (unsigned long long)w1x;
+            const unsigned long long w1 = (uint32_t)rintf(p.fx * scale);
+            w[0] = (1ull << g.S) - w1;
+            w[1] = w1;
         } else {
-            int64_t w1y = qw1(p.fy, scale), w0y = one - w1y;
-            w[0] = (unsigned long long)(w0x * w0y);
-            w[1] = (unsigned long long)(w1x * w0y);
-            w[2] = (unsigned long long)(w0x * w1y);
-            w[3] = (unsigned long long)(w1x * w1y);
+            const uint32_t one = 1u << g.S;
+            const uint32_t w1x = (uint32_t)rintf(p.fx * scale) & 0xFFFFFFu;
+            const uint32_t w0x = (one - w1x) & 0xFFFFFFu;
+            const uint32_t w1y = (uint32_t)rintf(p.fy * scale) & 0xFFFFFFu;
+            const uint32_t w0y = (one - w1y) & 0xFFFFFFu;
+            w[0] = (unsigned long long)w0x * w0y;
+            w[1] = (unsigned long long)w1x * w0y;
+            w[2] = (unsigned long long)w0x * w1y;
+            w[3] = (unsigned long long)w1x * w1y;
         }
     } else {
         double fx = p.fx, fy = p.fy;
@@ -408,42 +411,23 @@ __device__ __forceinline__ void deposit_global(typename AccOf<MIX>::T *acc, cons
 // global memory with one atomic per non-zero node.
 template <bool MIX, int DIM>
 __device__ void flush_region(typename AccOf<MIX>::T *acc, const typename AccOf<MIX>::T *sA, const Geo &g,
-                             int x0, int y0, int wx, int wy) {
+                             int x0, int y0, int wx, int wy, int halo) {
     const int tot = wx * wy;
     for (int t = threadIdx.x; t < tot; t += blockDim.x) {
         typename AccOf<MIX>::T v = sA[t];
         if (v == (typename AccOf<MIX>::T)0) continue;
         int lx = t % wx, ly = t / wx;
-        int gx = x0 - g.halo + lx;
+        int gx = x0 - halo + lx;
         gx %= g.nx;
         if (gx < 0) gx += g.nx;
         int gy = 0;
         if constexpr (DIM == 2) {
-            gy = y0 - g.halo + ly;
+            gy = y0 - halo + ly;
             gy %= g.ny;
             if (gy < 0) gy += g.ny;
         }
         acc_add<MIX>(&acc[gy * g.nx + gx], v);
     }
-}
-
-// Wave-aggregated reservation of slots in per-key counters: lanes with equal
-// key get consecutive slots (in lane order) from one atomicAdd per key.
-__device__ __forceinline__ int reserve_slot(int32_t *cursor, int key, bool active) {
-    uint64_t rem = __ballot(active);
-    int slot = -1;
-    const uint64_t lt = lanemask_lt();
-    while (rem) {
-        const int leader = __ffsll((unsigned long long)rem) - 1;
-        const int k = __shfl(key, leader);
-        const uint64_t grp = __ballot(active && key == k);
-        int base = 0;
-        if ((int)__lane_id() == leader) base = atomicAdd(&cursor[k], (int)__popcll(grp));
-        base = __shfl(base, leader);
-        if (active && key == k) slot = base + (int)__popcll(grp & lt);
-        rem &= ~grp;
-    }
-    return slot;
 }
 
 // Wave-aggregated increment of per-key counters.
@@ -456,6 +440,138 @@ __device__ __forceinline__ void count_keys(int32_t *count, int key, bool active)
         if ((int)__lane_id() == leader) atomicAdd(&count[k], (int)__popcll(grp));
         rem &= ~grp;
     }
+}
+
+// ------------------------------------------------- step: bucket directions
+//
+// A particle of bucket (bx, by) lands after the move in bucket (bx+dbx,
+// by+dby) (periodic). Moves with |dbx|, |dby| <= 1 get the direction code
+// d = (dby+1)*3 + (dbx+1) in 0..8; larger jumps get kFar. The count pass
+// tallies particles per (source bucket, wave, d); the scan turns the tallies
+// into start offsets inside the destination buckets (ordered by d, then wave);
+// the push pass hands out consecutive slots per (wave, d) in the order the
+// wave meets its particles. The order is therefore fixed by the previous
+// order alone: no atomics decide where a near particle goes. Far movers
+// (rare) take slots from an atomic cursor at the end of their bucket.
+constexpr int kDirs = 10;
+constexpr int kFar = 9;
+constexpr int kTab = kWaves * kDirs;  // per-bucket table entries
+
+__device__ __forceinline__ int dir_code(const Geo &g, int bx, int by, int nbx_new, int nby_new) {
+    int dbx = nbx_new - bx, dby = nby_new - by;
+    if (dbx > g.nbx / 2) dbx -= g.nbx;
+    if (dbx < -(g.nbx / 2)) dbx += g.nbx;
+    if (dby > g.nby / 2) dby -= g.nby;
+    if (dby < -(g.nby / 2)) dby += g.nby;
+    return (dbx >= -1 && dbx <= 1 && dby >= -1 && dby <= 1) ? (dby + 1) * 3 + (dbx + 1) : kFar;
+}
+
+// Source bucket that reaches bucket nbk with direction d.
+__device__ __forceinline__ int dir_source(const Geo &g, int nbk, int d) {
+    const int dbx = d % 3 - 1, dby = d / 3 - 1;
+    int sx = ((g.dim == 2) ? nbk % g.nbx : nbk) - dbx;
+    int sy = ((g.dim == 2) ? nbk / g.nbx : 0) - dby;
+    if (sx < 0) sx += g.nbx;
+    if (sx >= g.nbx) sx -= g.nbx;
+    if (sy < 0) sy += g.nby;
+    if (sy >= g.nby) sy -= g.nby;
+    return (g.dim == 2) ? sy * g.nbx + sx : sx;
+}
+
+// |v|^2 of a particle for the kinetic-energy diagnostic (binary32 squares on
+// the mixed path, FP64 on the FP64 path).
+template <bool MIX, int VDIM>
+__device__ __forceinline__ double vsq(const Pt<MIX> &q) {
+    auto v2 = q.vx * q.vx;
+    if constexpr (VDIM >= 2) v2 = v2 + q.vy * q.vy;
+    if constexpr (VDIM >= 3) v2 = v2 + q.vz * q.vz;
+    return (double)v2;
+}
+
+// Gather + Boris + move of one loaded particle of the block's tile; shared by
+// the count and the push pass so that both compute identical bits. A particle
+// outside the tile (the bucket table does not match the order) is flagged
+// and clamped into the tile so that every access stays in bounds.
+template <bool MIX, int DIM, int VDIM>
+__device__ __forceinline__ bool advance(Pt<MIX> &q, const Geo &g, const PushC &pc,
+                                        const typename Pt<MIX>::R *sE, int ex_w, int ey_w, int x0, int y0,
+                                        int &lx, int &ly, int &sx, int &sy) {
+    using R = typename Pt<MIX>::R;
+    const R a = MIX ? (R)pc.af : (R)pc.a, t = MIX ? (R)pc.tf : (R)pc.t, s = MIX ? (R)pc.sf : (R)pc.s;
+    lx = q.ix - x0;
+    ly = (DIM == 2) ? q.iy - y0 : 0;
+    const bool in = (unsigned)lx < (unsigned)(ex_w - 1) && (DIM == 1 || (unsigned)ly < (unsigned)(ey_w - 1));
+    if (!in) {
+        lx = min(max(lx, 0), ex_w - 2);
+        ly = (DIM == 2) ? min(max(ly, 0), ey_w - 2) : 0;
+        q.ix = x0 + lx;
+        q.iy = y0 + ly;
+    }
+    R ex, ey;
+    gather_lds<R, DIM>(sE, ex_w, ex_w * ey_w, lx, ly, q.fx, q.fy, ex, ey);
+    boris<R, VDIM>(q.vx, q.vy, ex, ey, a, t, s);
+    return move_pt<MIX, DIM>(q, g, pc, sx, sy) && in;
+}
+
+// Raw stored words of one particle: loaded unconditionally (the caller clamps
+// the index) so that a wave issues all its loads before it needs any data.
+template <bool MIX> struct Raw {
+    int32_t c;
+    float ox, oy, vx, vy, vz;
+};
+template <> struct Raw<false> {
+    double x, y, vx, vy, vz;
+};
+
+template <bool MIX, int DIM, int VDIM>
+__device__ __forceinline__ void load_raw(const Parts &s, int i, Raw<MIX> &r) {
+    if constexpr (MIX) {
+        r.c = s.cell[i];
+        r.ox = s.ox[i];
+        r.oy = (DIM == 2) ? s.oy[i] : 0.0f;
+        r.vx = ((const float *)s.vx)[i];
+        r.vy = (VDIM >= 2) ? ((const float *)s.vy)[i] : 0.0f;
+        r.vz = (VDIM >= 3) ? ((const float *)s.vz)[i] : 0.0f;
+    } else {
+        r.x = s.x[i];
+        r.y = (DIM == 2) ? s.y[i] : 0.0;
+        r.vx = ((const double *)s.vx)[i];
+        r.vy = (VDIM >= 2) ? ((const double *)s.vy)[i] : 0.0;
+        r.vz = (VDIM >= 3) ? ((const double *)s.vz)[i] : 0.0;
+    }
+}
+
+// Decode raw words into the working form (same checks as load_pt).
+template <bool MIX, int DIM, int VDIM>
+__device__ __forceinline__ bool decode(const Raw<MIX> &r, const Geo &g, Pt<MIX> &p) {
+    bool ok;
+    if constexpr (MIX) {
+        p.ix = (DIM == 2) ? (r.c & 0xFFFF) : r.c;
+        p.iy = (DIM == 2) ? (r.c >> 16) : 0;
+        p.fx = r.ox;
+        p.fy = (DIM == 2) ? r.oy : 0.0f;
+        ok = (unsigned)p.ix < (unsigned)g.nx && (p.fx >= 0.0f) && (p.fx < 1.0f);
+        if constexpr (DIM == 2) ok = ok && (unsigned)p.iy < (unsigned)g.ny && (p.fy >= 0.0f) && (p.fy < 1.0f);
+        if (!ok) { p.ix = 0; p.iy = 0; p.fx = 0.0f; p.fy = 0.0f; }
+    } else {
+        p.x = r.x;
+        double f;
+        ok = cell_f64(p.x, g.inv_dx, g.nx, p.ix, f);
+        p.fx = f;
+        if constexpr (DIM == 2) {
+            p.y = r.y;
+            ok = cell_f64(p.y, g.inv_dy, g.ny, p.iy, f) && ok;
+            p.fy = f;
+        } else {
+            p.y = 0.0;
+            p.iy = 0;
+            p.fy = 0.0;
+        }
+    }
+    p.vx = r.vx;
+    p.vy = r.vy;
+    p.vz = r.vz;
+    return ok;
 }
 
 // ================================================================= kernels
@@ -479,6 +595,11 @@ __global__ void k_copy_bytes(uint4 *dst, const uint4 *src, int64_t n16, char *dt
     if (blockIdx.x == 0 && (int)threadIdx.x < tail) dtail[threadIdx.x] = stail[threadIdx.x];
 }
 
+__global__ void k_to_f32(const double *src, float *dst, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
 // ---- general counting sort: keys + histogram --------------------------------
 template <bool MIX, int DIM, int VDIM>
 __global__ void __launch_bounds__(kBlock) k_keys_hist(Geo g, Parts p, int64_t n, int32_t *keys,
@@ -499,106 +620,264 @@ __global__ void __launch_bounds__(kBlock) k_keys_hist(Geo g, Parts p, int64_t n,
     }
 }
 
-// ---- exclusive scan over buckets (one workgroup) ------------------------------
-// start[b] = sum_{b'<b} count[b'], start[nb] = total; cursor = start;
-// count_zero (if non-null) is cleared for the next histogram. Also clears the
-// per-step diag accumulators and advances the device step index.
-__global__ void __launch_bounds__(1024) k_scan(const int32_t *count, int32_t *start, int32_t *cursor,
-                                               int32_t *count_zero, int nb, int64_t n, int64_t max_per,
-                                               double *diag, CtxDev c) {
-    __shared__ int64_t sh[1024];
+// ---- block-wide exclusive scan helper (1024 threads) ------------------------
+// Scans vals[0..nb) into out[0..nb] (out[nb] = total) in chunks of
+// 1024*kPer elements; returns the total in every thread.
+constexpr int kScanPer = 16;
+
+__device__ int64_t block_exclusive_scan(const int32_t *vals, int32_t *out, int nb, int64_t max_per, int &bad,
+                                        int64_t *sh /* [32] */) {
     __shared__ int64_t carry;
-    __shared__ int step_now;
-    if (threadIdx.x == 0) {
-        carry = 0;
-        if (diag) {
-            int st = *c.step + 1;
-            *c.step = st;
-            step_now = st;
-        }
-    }
+    if (threadIdx.x == 0) carry = 0;
     __syncthreads();
-    const int T = blockDim.x;
-    const int per = 16;
-    int bad = 0;
-    for (int base = 0; base < nb; base += T * per) {
-        int64_t loc[per];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int base = 0; base < nb; base += blockDim.x * kScanPer) {
+        int64_t loc[kScanPer];
         int64_t s = 0;
-        for (int k = 0; k < per; ++k) {
-            int b = base + threadIdx.x * per + k;
-            int64_t v = (b < nb) ? count[b] : 0;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            int b = base + threadIdx.x * kScanPer + k;
+            int64_t v = (b < nb) ? vals[b] : 0;
             if (v > max_per) bad = 1;
             loc[k] = v;
             s += v;
         }
-        sh[threadIdx.x] = s;
-        __syncthreads();
-        // Hillis-Steele inclusive scan over thread sums
-        for (int off = 1; off < T; off <<= 1) {
-            int64_t add = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
-            __syncthreads();
-            sh[threadIdx.x] += add;
-            __syncthreads();
+        // inclusive wave scan of thread sums
+        int64_t inc = s;
+        for (int off = 1; off < 64; off <<= 1) {
+            int64_t y = __shfl_up(inc, off);
+            if (lane >= off) inc += y;
         }
-        int64_t run = carry + sh[threadIdx.x] - s;
-        for (int k = 0; k < per; ++k) {
-            int b = base + threadIdx.x * per + k;
-            if (b < nb) {
-                start[b] = (int32_t)run;
-                cursor[b] = (int32_t)run;
-                if (count_zero) count_zero[b] = 0;
+        if (lane == 63) sh[w] = inc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t r = 0;
+            for (int i = 0; i < nw; ++i) {
+                int64_t t = sh[i];
+                sh[i] = r;
+                r += t;
             }
+            sh[nw] = r;
+        }
+        __syncthreads();
+        int64_t run = carry + sh[w] + inc - s;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            int b = base + threadIdx.x * kScanPer + k;
+            if (b < nb) out[b] = (int32_t)run;
             run += loc[k];
         }
         __syncthreads();
-        if (threadIdx.x == T - 1) carry += sh[T - 1];
+        if (threadIdx.x == 0) carry += sh[nw];
         __syncthreads();
     }
+    if (threadIdx.x == 0) out[nb] = (int32_t)carry;
+    __syncthreads();
+    return carry;
+}
+
+// ---- exclusive scan over buckets for the general sort (one workgroup) --------
+__global__ void __launch_bounds__(1024) k_scan(int32_t *count, int32_t *start, int32_t *cursor, int nb,
+                                               int64_t n, int64_t max_per, CtxDev c) {
+    __shared__ int64_t sh[32];
+    int bad = 0;
+    int64_t total = block_exclusive_scan(count, start, nb, max_per, bad, sh);
     if (bad) raise_err(c.err, ERR_OVERFLOW);
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        cursor[b] = start[b];
+        count[b] = 0;
+    }
+    if (threadIdx.x == 0 && total != n) raise_err(c.err, ERR_COUNT);
+}
+
+// ---- step: destination totals -> scan -> per-source offsets -------------------
+// tot [nb] (summed by the count pass) is scanned into start (the next bucket
+// table) and cleared; the device step index advances when step_mode.
+__global__ void __launch_bounds__(1024) k_scan_tot(int32_t *tot, int32_t *start, int nb, int64_t n,
+                                                   int64_t max_per, int step_mode, CtxDev c) {
+    __shared__ int64_t sh[32];
+    int bad = 0;
+    int64_t total = block_exclusive_scan(tot, start, nb, max_per, bad, sh);
+    if (bad) raise_err(c.err, ERR_OVERFLOW);
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) tot[b] = 0;
     if (threadIdx.x == 0) {
-        start[nb] = (int32_t)carry;
-        if (carry != n) raise_err(c.err, ERR_COUNT);
-        if (diag) {
-            double *d = diag + 4 * step_now;
-            d[2] = 0.0;
-            d[3] = 0.0;
+        if (total != n) raise_err(c.err, ERR_COUNT);
+        if (step_mode) *c.step = *c.step + 1;
+    }
+}
+
+// For each destination bucket: its sources' tallies, in direction-then-wave
+// order, occupy consecutive ranges from start[nb]; far arrivals follow.
+__global__ void __launch_bounds__(kBlock) k_dir_offsets(Geo g, const int32_t *cnt, const int32_t *start,
+                                                        int32_t *offs, int32_t *farcur, int32_t *farcnt) {
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < g.nbuckets; b += gridDim.x * blockDim.x) {
+        int32_t run = start[b];
+        for (int d = 0; d < kFar; ++d) {
+            const int s = dir_source(g, b, d);
+            for (int w = 0; w < kWaves; ++w) {
+                offs[s * kTab + w * kDirs + d] = run;
+                run += cnt[s * kTab + w * kDirs + d];
+            }
+        }
+        farcur[b] = run;
+        farcnt[b] = 0;
+    }
+}
+
+// ---- general sort: stable LSD radix sort of (bucket key, index) ----------------
+// Keys are bucket indices; each pass orders by 8 more key bits, keeping the
+// previous order among equal digits (stable), so the result is the stable
+// counting sort of the input by bucket. Per pass: tallies per (chunk, wave,
+// digit), one exclusive scan in (digit, chunk, wave) order, and a scatter that
+// hands out slots per (wave, digit) in the order the wave meets its elements
+// (lanes with equal digits are ranked with ballots). Each wave owns a
+// contiguous range of its chunk, so (chunk, wave, element) order is input
+// order and every pass is stable; no atomic decides an element's slot.
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSortPer = 16;                    // elements per thread and chunk
+constexpr int kSortChunk = kBlock * kSortPer;   // elements per chunk (block)
+constexpr int kSortTab = kWaves * kRadix;       // tallies per chunk
+
+template <bool MIX, int DIM, int VDIM>
+__global__ void __launch_bounds__(kBlock) k_keys_init(Geo g, Parts p, int64_t n, int32_t *keys, int32_t *idx,
+                                                      CtxDev c) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        Pt<MIX> q;
+        if (!load_pt<MIX, DIM, VDIM>(p, i, g, q)) raise_err(c.err, ERR_DOMAIN);
+        keys[i] = bucket_of<MIX, DIM>(g, q.ix, q.iy);
+        idx[i] = (int32_t)i;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_radix_count(const int32_t *keys, int64_t n, int shift, int32_t *cnt) {
+    __shared__ int32_t s[kSortTab];
+    for (int t = threadIdx.x; t < kSortTab; t += blockDim.x) s[t] = 0;
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    // wave w owns the contiguous range [w*64*kSortPer, (w+1)*64*kSortPer) of the chunk
+    const int64_t base = (int64_t)blockIdx.x * kSortChunk + (int64_t)w * 64 * kSortPer + __lane_id();
+    for (int j = 0; j < kSortPer; ++j) {
+        const int64_t i = base + j * 64;
+        if (i < n) atomicAdd(&s[w * kRadix + ((keys[i] >> shift) & (kRadix - 1))], 1);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kSortTab; t += blockDim.x) cnt[(int64_t)blockIdx.x * kSortTab + t] = s[t];
+}
+
+// Exclusive scan of the tallies in (digit, chunk, wave) order (one workgroup).
+__global__ void __launch_bounds__(1024) k_radix_scan(const int32_t *cnt, int32_t *off, int nchunks) {
+    __shared__ int64_t sh[32];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int64_t L = (int64_t)kSortTab * nchunks;
+    auto addr = [&](int64_t v) {  // virtual (digit, chunk, wave) index -> table address
+        const int64_t d = v / ((int64_t)nchunks * kWaves);
+        const int64_t r = v - d * (int64_t)nchunks * kWaves;
+        const int64_t ch = r / kWaves, wv = r - ch * kWaves;
+        return ch * kSortTab + wv * kRadix + d;
+    };
+    for (int64_t base = 0; base < L; base += (int64_t)blockDim.x * kScanPer) {
+        int64_t loc[kScanPer];
+        int64_t s = 0;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            const int64_t v = base + (int64_t)threadIdx.x * kScanPer + k;
+            loc[k] = (v < L) ? cnt[addr(v)] : 0;
+            s += loc[k];
+        }
+        int64_t inc = s;
+        for (int o = 1; o < 64; o <<= 1) {
+            int64_t y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
+        }
+        if (lane == 63) sh[w] = inc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t r = 0;
+            for (int i = 0; i < nw; ++i) {
+                int64_t t = sh[i];
+                sh[i] = r;
+                r += t;
+            }
+            sh[nw] = r;
+        }
+        __syncthreads();
+        int64_t run = carry + sh[w] + inc - s;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            const int64_t v = base + (int64_t)threadIdx.x * kScanPer + k;
+            if (v < L) off[addr(v)] = (int32_t)run;
+            run += loc[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) carry += sh[nw];
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_radix_scatter(const int32_t *kin, const int32_t *iin, int32_t *kout,
+                                                          int32_t *iout, int64_t n, int shift, const int32_t *off,
+                                                          CtxDev c) {
+    __shared__ int32_t sRun[kSortTab];
+    for (int t = threadIdx.x; t < kSortTab; t += blockDim.x) sRun[t] = off[(int64_t)blockIdx.x * kSortTab + t];
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    const uint64_t lt = lanemask_lt();
+    // same element -> wave mapping as k_radix_count; wave-major order is input order (stable)
+    const int64_t base = (int64_t)blockIdx.x * kSortChunk + (int64_t)w * 64 * kSortPer + __lane_id();
+    for (int j = 0; j < kSortPer; ++j) {
+        const int64_t i = base + j * 64;
+        const bool act = i < n;
+        const int key = act ? kin[i] : 0;
+        const int d = (key >> shift) & (kRadix - 1);
+        // lanes holding the same digit
+        uint64_t peers = __ballot(act);
+#pragma unroll
+        for (int bit = 0; bit < kRadixBits; ++bit) {
+            const uint64_t bb = __ballot(act && ((d >> bit) & 1));
+            peers &= ((d >> bit) & 1) ? bb : ~bb;
+        }
+        if (act) {
+            const int basek = sRun[w * kRadix + d];
+            const int slot = basek + (int)__popcll(peers & lt);
+            if ((int)__lane_id() == __ffsll((unsigned long long)peers) - 1)
+                sRun[w * kRadix + d] = basek + (int)__popcll(peers);
+            if (slot >= 0 && slot < n) {
+                kout[slot] = key;
+                iout[slot] = iin[i];
+            } else {
+                raise_err(c.err, ERR_ORDER);
+            }
         }
     }
 }
 
-// ---- general counting sort: scatter -----------------------------------------
+// dst[j] = src[idx[j]] for every particle array; perm (optional) = idx.
 template <bool MIX, int DIM, int VDIM>
-__global__ void __launch_bounds__(kBlock) k_scatter(Geo g, Parts src, Parts dst, int64_t n, const int32_t *keys,
-                                                    int32_t *cursor, const int32_t *start, int32_t *perm,
-                                                    CtxDev c) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t n_up = ((n + 63) / 64) * 64;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_up; i += stride) {
-        bool act = i < n;
-        int key = act ? keys[i] : 0;
-        int slot = reserve_slot(cursor, key, act);
-        if (act) {
-            if (slot >= start[key + 1]) {
-                raise_err(c.err, ERR_ORDER);
-                continue;
-            }
-            Pt<MIX> q;
-            load_pt<MIX, DIM, VDIM>(src, i, g, q);
-            // copy the raw stored values (no re-normalisation)
-            if constexpr (MIX) {
-                dst.cell[slot] = src.cell[i];
-                dst.ox[slot] = src.ox[i];
-                if constexpr (DIM == 2) dst.oy[slot] = src.oy[i];
-            } else {
-                dst.x[slot] = src.x[i];
-                if constexpr (DIM == 2) dst.y[slot] = src.y[i];
-            }
-            using R = typename Pt<MIX>::R;
-            ((R *)dst.vx)[slot] = q.vx;
-            if constexpr (VDIM >= 2) ((R *)dst.vy)[slot] = q.vy;
-            if constexpr (VDIM >= 3) ((R *)dst.vz)[slot] = q.vz;
-            if (perm) perm[slot] = (int32_t)i;
+__global__ void __launch_bounds__(kBlock) k_gather_parts(Parts src, Parts dst, int64_t n, const int32_t *idx,
+                                                         int32_t *perm, CtxDev c) {
+    using R = typename Pt<MIX>::R;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx[j];
+        if (i < 0 || i >= n) {
+            raise_err(c.err, ERR_ORDER);
+            continue;
         }
+        if constexpr (MIX) {
+            dst.cell[j] = src.cell[i];
+            dst.ox[j] = src.ox[i];
+            if constexpr (DIM == 2) dst.oy[j] = src.oy[i];
+        } else {
+            dst.x[j] = src.x[i];
+            if constexpr (DIM == 2) dst.y[j] = src.y[i];
+        }
+        ((R *)dst.vx)[j] = ((const R *)src.vx)[i];
+        if constexpr (VDIM >= 2) ((R *)dst.vy)[j] = ((const R *)src.vy)[i];
+        if constexpr (VDIM >= 3) ((R *)dst.vz)[j] = ((const R *)src.vz)[i];
+        if (perm) perm[j] = (int32_t)i;
     }
 }
 
@@ -630,8 +909,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(Geo g, Parts p, const 
     const int bx = (DIM == 2) ? (b % g.nbx) : b;
     const int by = (DIM == 2) ? (b / g.nbx) : 0;
     const int x0 = bx << g.tsx, y0 = (DIM == 2) ? (by << g.tsy) : 0;
-    const int wx = (1 << g.tsx) + 1 + 2 * g.halo;
-    const int wy = (DIM == 2) ? (1 << g.tsy) + 1 + 2 * g.halo : 1;
+    const int wx = (1 << g.tsx) + 1;
+    const int wy = (DIM == 2) ? (1 << g.tsy) + 1 : 1;
     for (int t = threadIdx.x; t < wx * wy; t += blockDim.x) sA[t] = (A)0;
     __syncthreads();
     const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
@@ -643,8 +922,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(Geo g, Parts p, const 
         }
         A w[4];
         dep_weights<MIX, DIM>(q, g, w);
-        int lx = q.ix - x0 + g.halo;
-        int ly = (DIM == 2) ? q.iy - y0 + g.halo : 0;
+        int lx = q.ix - x0;
+        int ly = (DIM == 2) ? q.iy - y0 : 0;
         bool inl = (lx >= 0) && (lx <= wx - 2) && ((DIM == 1) || (ly >= 0 && ly <= wy - 2));
         if (inl) {
             int a = ly * wx + lx;
@@ -660,7 +939,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(Geo g, Parts p, const 
         }
     }
     __syncthreads();
-    flush_region<MIX, DIM>(acc, sA, g, x0, y0, wx, wy);
+    flush_region<MIX, DIM>(acc, sA, g, x0, y0, wx, wy, 0);
 }
 
 // ---- gather + push (+ move), in place -------------------------------------------
@@ -678,7 +957,7 @@ __global__ void __launch_bounds__(kBlock) k_gather_push_direct(Geo g, Parts p, i
             continue;
         }
         R ex, ey;
-        gather_global<R, DIM>(E, g, q.ix, q.iy, q.fx, q.fy, ex, ey);
+        gather_global<R, R, DIM>(E, g, q.ix, q.iy, q.fx, q.fy, ex, ey);
         boris<R, VDIM>(q.vx, q.vy, ex, ey, a, t, s);
         if (pc.move) {
             int sx, sy;
@@ -701,7 +980,7 @@ __global__ void __launch_bounds__(kBlock) k_gather_push_tiled(Geo g, Parts p, co
     const int by = (DIM == 2) ? (b / g.nbx) : 0;
     const int x0 = bx << g.tsx, y0 = (DIM == 2) ? (by << g.tsy) : 0;
     const int ex_w = (1 << g.tsx) + 1, ey_w = (DIM == 2) ? (1 << g.tsy) + 1 : 1;
-    load_e_tile<R, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
+    load_e_tile<R, R, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
     __syncthreads();
     const R a = MIX ? (R)pc.af : (R)pc.a, t = MIX ? (R)pc.tf : (R)pc.t, s = MIX ? (R)pc.sf : (R)pc.s;
     const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
@@ -717,7 +996,7 @@ __global__ void __launch_bounds__(kBlock) k_gather_push_tiled(Geo g, Parts p, co
             gather_lds<R, DIM>(sE, ex_w, ex_w * ey_w, lx, ly, q.fx, q.fy, ex, ey);
         } else {
             raise_err(c.err, ERR_ORDER);
-            gather_global<R, DIM>(E, g, q.ix, q.iy, q.fx, q.fy, ex, ey);
+            gather_global<R, R, DIM>(E, g, q.ix, q.iy, q.fx, q.fy, ex, ey);
         }
         boris<R, VDIM>(q.vx, q.vy, ex, ey, a, t, s);
         if (pc.move) {
@@ -728,238 +1007,328 @@ __global__ void __launch_bounds__(kBlock) k_gather_push_tiled(Geo g, Parts p, co
     }
 }
 
-// ---- fused step, pass 1: new-bucket histogram ---------------------------------
-// Same arithmetic as k_step_push up to the new cell; keeps only the counts.
-template <bool MIX, int DIM, int VDIM>
-__global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int32_t *bstart,
-                                                       const typename Pt<MIX>::R *E, PushC pc,
-                                                       int32_t *count, CtxDev c) {
+// ---- fused step, pass 1: direction tallies ------------------------------------
+// Same arithmetic as k_step_push up to the new cell; keeps only the tallies
+// per (bucket, wave, direction) and counts far movers at their destination.
+// U particles per thread are loaded before any is processed (more loads in
+// flight per wave).
+template <bool MIX, int DIM, int VDIM, int U>
+__global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int32_t *bstart, const double *E,
+                                                       PushC pc, int32_t *cnt, int32_t *tot, int32_t *farcnt,
+                                                       CtxDev c) {
     using R = typename Pt<MIX>::R;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int32_t sCnt[9];
+    __shared__ int sErr;
+    __shared__ int32_t sCnt[kTab];
     R *sE = (R *)smem;
-    const int b = bucket_of_block(g.nbuckets);
-    if (b >= g.nbuckets) return;
-    const int bx = (DIM == 2) ? (b % g.nbx) : b;
-    const int by = (DIM == 2) ? (b / g.nbx) : 0;
-    const int x0 = bx << g.tsx, y0 = (DIM == 2) ? (by << g.tsy) : 0;
+    const int w = threadIdx.x >> 6;
     const int ex_w = (1 << g.tsx) + 1, ey_w = (DIM == 2) ? (1 << g.tsy) + 1 : 1;
-    if (threadIdx.x < 9) sCnt[threadIdx.x] = 0;
-    load_e_tile<R, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
-    __syncthreads();
-    const R a = MIX ? (R)pc.af : (R)pc.a, t = MIX ? (R)pc.tf : (R)pc.t, s = MIX ? (R)pc.sf : (R)pc.s;
-    const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
-    // whole waves iterate together so the wave-aggregated counters see all lanes
-    const int span = i1 - i0;
-    const int span_up = ((span + 63) / 64) * 64;
-    for (int k = threadIdx.x; k < span_up; k += blockDim.x) {
-        const bool act = k < span;
-        int slot_code = 0;   // neighbour index 0..8, or 9 = far
-        int nbk = 0;
-        if (act) {
-            Pt<MIX> q;
-            bool ok = load_pt<MIX, DIM, VDIM>(p, i0 + k, g, q);
-            int lx = q.ix - x0, ly = (DIM == 2) ? q.iy - y0 : 0;
-            R ex, ey;
-            if (lx >= 0 && lx < ex_w - 1 && ly >= 0 && (DIM == 1 || ly < ey_w - 1)) {
-                gather_lds<R, DIM>(sE, ex_w, ex_w * ey_w, lx, ly, q.fx, q.fy, ex, ey);
-            } else {
-                ok = false;
-                gather_global<R, DIM>(E, g, q.ix, q.iy, q.fx, q.fy, ex, ey);
+    if (threadIdx.x == 0) sErr = 0;
+    int first, end, stride;
+    bucket_walk(g.nbuckets, first, end, stride);
+    for (int b = first; b < end; b += stride) {
+        const int bx = (DIM == 2) ? (b % g.nbx) : b;
+        const int by = (DIM == 2) ? (b / g.nbx) : 0;
+        const int x0 = bx << g.tsx, y0 = (DIM == 2) ? (by << g.tsy) : 0;
+        if (threadIdx.x < kTab) sCnt[threadIdx.x] = 0;
+        load_e_tile<R, double, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
+        __syncthreads();
+        const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
+        const int span = i1 - i0;
+        // two register sets, each chunk's loads issued one chunk ahead of its use
+        constexpr int CH = kBlock * U;
+        Raw<MIX> ra[U], rb[U];
+        auto fetch = [&](Raw<MIX> *r, int base) {
+#pragma unroll
+            for (int j = 0; j < U; ++j)
+                load_raw<MIX, DIM, VDIM>(p, i0 + min(base + j * kBlock + (int)threadIdx.x, span - 1), r[j]);
+            // keep these loads where they are: issued one chunk ahead of their use
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        auto process = [&](Raw<MIX> *r, int base) {
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int k = base + j * kBlock + threadIdx.x;
+                const bool act = k < span;
+                int code = -1, nbk = 0;
+                if (act) {
+                    Pt<MIX> q;
+                    bool good = decode<MIX, DIM, VDIM>(r[j], g, q);
+                    int lx, ly, sx, sy;
+                    good = advance<MIX, DIM, VDIM>(q, g, pc, sE, ex_w, ey_w, x0, y0, lx, ly, sx, sy) && good;
+                    if (!good) atomicOr(&sErr, ERR_DOMAIN);
+                    const int nbx_new = q.ix >> g.tsx, nby_new = (DIM == 2) ? (q.iy >> g.tsy) : 0;
+                    nbk = nby_new * g.nbx + nbx_new;
+                    code = dir_code(g, bx, by, nbx_new, nby_new);
+                }
+                uint64_t rem = __ballot(code >= 0 && code < kFar);
+                while (rem) {
+                    const int leader = __ffsll((unsigned long long)rem) - 1;
+                    const int kc = __builtin_amdgcn_readlane(code, leader);
+                    const uint64_t grp = __ballot(code == kc);
+                    if ((int)__lane_id() == leader) sCnt[w * kDirs + kc] += (int)__popcll(grp);
+                    rem &= ~grp;
+                }
+                if (code == kFar) {
+                    atomicAdd(&farcnt[nbk], 1);
+                    atomicAdd(&tot[nbk], 1);
+                }
             }
-            boris<R, VDIM>(q.vx, q.vy, ex, ey, a, t, s);
-            int sx, sy;
-            ok = move_pt<MIX, DIM>(q, g, pc, sx, sy) && ok;
-            if (!ok) raise_err(c.err, ERR_DOMAIN);
-            nbk = bucket_of<MIX, DIM>(g, q.ix, q.iy);
-            int nbx_ = (DIM == 2) ? nbk % g.nbx : nbk;
-            int nby_ = (DIM == 2) ? nbk / g.nbx : 0;
-            int dbx = nbx_ - bx, dby = nby_ - by;
-            if (dbx > g.nbx / 2) dbx -= g.nbx;
-            if (dbx < -(g.nbx / 2)) dbx += g.nbx;
-            if (dby > g.nby / 2) dby -= g.nby;
-            if (dby < -(g.nby / 2)) dby += g.nby;
-            slot_code = (dbx >= -1 && dbx <= 1 && dby >= -1 && dby <= 1) ? (dby + 1) * 3 + (dbx + 1) : 9;
+        };
+        if (span > 0) fetch(ra, 0);
+        for (int base = 0; base < span; base += 2 * CH) {
+            if (base + CH < span) fetch(rb, base + CH);
+            process(ra, base);
+            if (base + 2 * CH < span) fetch(ra, base + 2 * CH);
+            if (base + CH < span) process(rb, base + CH);
         }
-        // near buckets: wave-aggregated LDS counters; far buckets: global atomics
-        uint64_t rem = __ballot(act && slot_code < 9);
-        while (rem) {
-            const int leader = __ffsll((unsigned long long)rem) - 1;
-            const int kc = __shfl(slot_code, leader);
-            const uint64_t grp = __ballot(act && slot_code == kc);
-            if ((int)__lane_id() == leader) atomicAdd(&sCnt[kc], (int)__popcll(grp));
-            rem &= ~grp;
+        __syncthreads();
+        if (threadIdx.x < kTab) cnt[b * kTab + threadIdx.x] = sCnt[threadIdx.x];
+        if (threadIdx.x < kFar) {
+            int v = 0;
+            for (int w2 = 0; w2 < kWaves; ++w2) v += sCnt[w2 * kDirs + threadIdx.x];
+            if (v) {
+                const int d = threadIdx.x;
+                int nx_ = bx + d % 3 - 1, ny_ = by + d / 3 - 1;
+                if (nx_ < 0) nx_ += g.nbx;
+                if (nx_ >= g.nbx) nx_ -= g.nbx;
+                if (ny_ < 0) ny_ += g.nby;
+                if (ny_ >= g.nby) ny_ -= g.nby;
+                atomicAdd(&tot[(DIM == 2) ? ny_ * g.nbx + nx_ : nx_], v);
+            }
         }
-        if (act && slot_code == 9) atomicAdd(&count[nbk], 1);
+        __syncthreads();
     }
     __syncthreads();
-    if (threadIdx.x < 9) {
-        int v = sCnt[threadIdx.x];
-        if (v) {
-            int dbx = (int)(threadIdx.x % 3) - 1, dby = (int)(threadIdx.x / 3) - 1;
-            int nbx_ = bx + dbx, nby_ = by + dby;
-            if (nbx_ < 0) nbx_ += g.nbx;
-            if (nbx_ >= g.nbx) nbx_ -= g.nbx;
-            if (nby_ < 0) nby_ += g.nby;
-            if (nby_ >= g.nby) nby_ -= g.nby;
-            int nb = (DIM == 2) ? nby_ * g.nbx + nbx_ : nbx_;
-            atomicAdd(&count[nb], v);
-        }
-    }
+    if (threadIdx.x == 0 && sErr) raise_err(c.err, sErr);
 }
 
 // ---- fused step, pass 2: push, deposit, scatter into the next bucket order -----
-template <bool MIX, int DIM, int VDIM>
+template <bool MIX, int DIM, int VDIM, int U>
 __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts dst, const int32_t *bstart,
-                                                      const int32_t *bstart_new, int32_t *cursor,
-                                                      const typename Pt<MIX>::R *E, PushC pc,
-                                                      typename AccOf<MIX>::T *acc, int32_t *perm,
-                                                      double *diag, double mass, CtxDev c) {
+                                                      const int32_t *bstart_new, const int32_t *offs,
+                                                      int32_t *farcur, const double *E, PushC pc,
+                                                      typename AccOf<MIX>::T *acc, int32_t *perm, double *part,
+                                                      CtxDev c) {
     using R = typename Pt<MIX>::R;
     using A = typename AccOf<MIX>::T;
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int sErr;
     __shared__ double sRed[kWaves];
-    const int b = bucket_of_block(g.nbuckets);
-    if (b >= g.nbuckets) return;
-    const int bx = (DIM == 2) ? (b % g.nbx) : b;
-    const int by = (DIM == 2) ? (b / g.nbx) : 0;
-    const int x0 = bx << g.tsx, y0 = (DIM == 2) ? (by << g.tsy) : 0;
+    __shared__ int32_t sRun[kTab];
+    __shared__ int32_t sEnd[kFar];   // end of each neighbour destination bucket
     const int ex_w = (1 << g.tsx) + 1, ey_w = (DIM == 2) ? (1 << g.tsy) + 1 : 1;
     const int wx = (1 << g.tsx) + 1 + 2 * g.halo;
     const int wy = (DIM == 2) ? (1 << g.tsy) + 1 + 2 * g.halo : 1;
     A *sA = (A *)smem;
     R *sE = (R *)(smem + (((size_t)wx * wy * sizeof(A) + 15) & ~(size_t)15));
-    for (int t2 = threadIdx.x; t2 < wx * wy; t2 += blockDim.x) sA[t2] = (A)0;
-    load_e_tile<R, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
-    __syncthreads();
-    const R a = MIX ? (R)pc.af : (R)pc.a, t = MIX ? (R)pc.tf : (R)pc.t, s = MIX ? (R)pc.sf : (R)pc.s;
-    const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
-    const int span = i1 - i0;
-    const int span_up = ((span + 63) / 64) * 64;
-    double ke = 0.0, px = 0.0;
-    for (int k = threadIdx.x; k < span_up; k += blockDim.x) {
-        const bool act = k < span;
-        Pt<MIX> q;
-        int nbk = 0;
-        if (act) {
-            bool ok = load_pt<MIX, DIM, VDIM>(src, i0 + k, g, q);
-            const double v2o = (double)q.vx * (double)q.vx + (double)q.vy * (double)q.vy +
-                               (double)q.vz * (double)q.vz;
-            int lx = q.ix - x0, ly = (DIM == 2) ? q.iy - y0 : 0;
-            R ex, ey;
-            if (lx >= 0 && lx < ex_w - 1 && ly >= 0 && (DIM == 1 || ly < ey_w - 1)) {
-                gather_lds<R, DIM>(sE, ex_w, ex_w * ey_w, lx, ly, q.fx, q.fy, ex, ey);
-            } else {
-                ok = false;
-                gather_global<R, DIM>(E, g, q.ix, q.iy, q.fx, q.fy, ex, ey);
-            }
-            boris<R, VDIM>(q.vx, q.vy, ex, ey, a, t, s);
-            const double v2n = (double)q.vx * (double)q.vx + (double)q.vy * (double)q.vy +
-                               (double)q.vz * (double)q.vz;
-            ke += 0.5 * (v2o + v2n);
-            px += (double)q.vx;
-            int sx, sy;
-            ok = move_pt<MIX, DIM>(q, g, pc, sx, sy) && ok;
-            if (!ok) raise_err(c.err, ERR_DOMAIN);
-            nbk = bucket_of<MIX, DIM>(g, q.ix, q.iy);
-            // deposit rho^{n+1}
-            A w[4];
-            dep_weights<MIX, DIM>(q, g, w);
-            int dlx = lx + sx + g.halo;
-            int dly = (DIM == 2) ? ly + sy + g.halo : 0;
-            bool inl = (dlx >= 0) && (dlx <= wx - 2) && ((DIM == 1) || (dly >= 0 && dly <= wy - 2));
-            if (inl) {
-                int a0 = dly * wx + dlx;
-                acc_add<MIX>(&sA[a0], w[0]);
-                acc_add<MIX>(&sA[a0 + 1], w[1]);
-                if constexpr (DIM == 2) {
-                    acc_add<MIX>(&sA[a0 + wx], w[2]);
-                    acc_add<MIX>(&sA[a0 + wx + 1], w[3]);
+    const int w = threadIdx.x >> 6;
+    const uint64_t lt = lanemask_lt();
+    if (threadIdx.x == 0) sErr = 0;
+    int first, end, stride;
+    bucket_walk(g.nbuckets, first, end, stride);
+    for (int b = first; b < end; b += stride) {
+        const int bx = (DIM == 2) ? (b % g.nbx) : b;
+        const int by = (DIM == 2) ? (b / g.nbx) : 0;
+        const int x0 = bx << g.tsx, y0 = (DIM == 2) ? (by << g.tsy) : 0;
+        for (int t2 = threadIdx.x; t2 < wx * wy; t2 += blockDim.x) sA[t2] = (A)0;
+        if (threadIdx.x < kTab) sRun[threadIdx.x] = offs[b * kTab + threadIdx.x];
+        if (threadIdx.x < kFar) {
+            const int d = threadIdx.x;
+            int nx_ = bx + d % 3 - 1, ny_ = by + d / 3 - 1;
+            if (nx_ < 0) nx_ += g.nbx;
+            if (nx_ >= g.nbx) nx_ -= g.nbx;
+            if (ny_ < 0) ny_ += g.nby;
+            if (ny_ >= g.nby) ny_ -= g.nby;
+            sEnd[d] = bstart_new[((DIM == 2) ? ny_ * g.nbx + nx_ : nx_) + 1];
+        }
+        load_e_tile<R, double, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
+        __syncthreads();
+        const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
+        const int span = i1 - i0;
+        double ke = 0.0, px = 0.0;
+        constexpr int CH = kBlock * U;
+        Raw<MIX> ra[U], rb[U];
+        auto fetch = [&](Raw<MIX> *r, int base) {
+#pragma unroll
+            for (int j = 0; j < U; ++j)
+                load_raw<MIX, DIM, VDIM>(src, i0 + min(base + j * kBlock + (int)threadIdx.x, span - 1), r[j]);
+            // keep these loads where they are: issued one chunk ahead of their use
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        auto process = [&](Raw<MIX> *r, int base) {
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int k = base + j * kBlock + threadIdx.x;
+                const bool act = k < span;
+                int code = -1, nbk = 0;
+                Pt<MIX> q;
+                if (act) {
+                    bool good = decode<MIX, DIM, VDIM>(r[j], g, q);
+                    const double v2o = vsq<MIX, VDIM>(q);
+                    int lx, ly, sx, sy;
+                    good = advance<MIX, DIM, VDIM>(q, g, pc, sE, ex_w, ey_w, x0, y0, lx, ly, sx, sy) && good;
+                    if (!good) atomicOr(&sErr, ERR_DOMAIN);
+                    const double v2n = vsq<MIX, VDIM>(q);
+                    ke += 0.5 * (v2o + v2n);
+                    px += (double)q.vx;
+                    const int nbx_new = q.ix >> g.tsx, nby_new = (DIM == 2) ? (q.iy >> g.tsy) : 0;
+                    nbk = nby_new * g.nbx + nbx_new;
+                    code = dir_code(g, bx, by, nbx_new, nby_new);
+                    // deposit rho^{n+1}: LDS tile + halo, global beyond it
+                    A wgt[4];
+                    dep_weights<MIX, DIM>(q, g, wgt);
+                    const int dlx = lx + sx + g.halo;
+                    const int dly = (DIM == 2) ? ly + sy + g.halo : 0;
+                    const bool inl = (unsigned)dlx <= (unsigned)(wx - 2) && ((DIM == 1) || (unsigned)dly <= (unsigned)(wy - 2));
+                    if (inl) {
+                        const int a0 = dly * wx + dlx;
+                        acc_add<MIX>(&sA[a0], wgt[0]);
+                        acc_add<MIX>(&sA[a0 + 1], wgt[1]);
+                        if constexpr (DIM == 2) {
+                            acc_add<MIX>(&sA[a0 + wx], wgt[2]);
+                            acc_add<MIX>(&sA[a0 + wx + 1], wgt[3]);
+                        }
+                    } else {
+                        deposit_global<MIX, DIM>(acc, g, q.ix, q.iy, wgt);
+                    }
                 }
-            } else {
-                deposit_global<MIX, DIM>(acc, g, q.ix, q.iy, w);
+                // slot: consecutive per (wave, direction) in the order the wave meets
+                // them; each group's range is checked once against its bucket's end
+                // (the start is its offset-table entry, computed from the same scan).
+                int slot = -1;
+                uint64_t rem = __ballot(code >= 0 && code < kFar);
+                while (rem) {
+                    const int leader = __ffsll((unsigned long long)rem) - 1;
+                    const int kc = __builtin_amdgcn_readlane(code, leader);
+                    const uint64_t grp = __ballot(code == kc);
+                    const int basek = sRun[w * kDirs + kc];
+                    const int cntk = (int)__popcll(grp);
+                    const bool fits = basek + cntk <= sEnd[kc];
+                    if (code == kc) slot = fits ? basek + (int)__popcll(grp & lt) : -1;
+                    if ((int)__lane_id() == leader) sRun[w * kDirs + kc] = basek + cntk;
+                    rem &= ~grp;
+                }
+                if (code == kFar) {
+                    slot = atomicAdd(&farcur[nbk], 1);
+                    if (slot >= bstart_new[nbk + 1]) slot = -1;
+                }
+                if (act) {
+                    if (slot >= 0) {
+                        store_pt<MIX, DIM, VDIM>(dst, slot, q);
+                        if (perm) perm[slot] = i0 + k;
+                    } else {
+                        atomicOr(&sErr, ERR_ORDER);
+                    }
+                }
+            }
+        };
+        if (span > 0) fetch(ra, 0);
+        for (int base = 0; base < span; base += 2 * CH) {
+            if (base + CH < span) fetch(rb, base + CH);
+            process(ra, base);
+            if (base + 2 * CH < span) fetch(ra, base + 2 * CH);
+            if (base + CH < span) process(rb, base + CH);
+        }
+        __syncthreads();
+        flush_region<MIX, DIM>(acc, sA, g, x0, y0, wx, wy, g.halo);
+        if (part) {
+            double kt = block_sum(ke, sRed);
+            double pt = block_sum(px, sRed);
+            if (threadIdx.x == 0) {
+                part[2 * b] = kt;
+                part[2 * b + 1] = pt;
             }
         }
-        const int slot = reserve_slot(cursor, nbk, act);
-        if (act) {
-            if (slot >= 0 && slot < bstart_new[nbk + 1]) {
-                store_pt<MIX, DIM, VDIM>(dst, slot, q);
-                if (perm) perm[slot] = i0 + k;
-            } else {
-                raise_err(c.err, ERR_ORDER);
-            }
-        }
+        __syncthreads();
     }
     __syncthreads();
-    flush_region<MIX, DIM>(acc, sA, g, x0, y0, wx, wy);
-    if (diag) {
-        double kt = block_sum(ke, sRed);
-        double pt = block_sum(px, sRed);
-        if (threadIdx.x == 0) {
-            double *d = step_slot(diag, c);
-            atomicAdd(&d[2], 0.5 * mass * kt);
-            atomicAdd(&d[3], mass * pt);
-        }
-    }
+    if (threadIdx.x == 0 && sErr) raise_err(c.err, sErr);
 }
 
 // ---- field: accumulation -> rho --------------------------------------------------
 // rho_j = add + scale * acc_j (acc: double weights or int64 fixed-point sums);
-// charge = dV * sum_j (rho_j - ion); acc is cleared when clear != 0.
+// acc is cleared when clear != 0.
 template <bool MIX>
 __global__ void __launch_bounds__(kBlock) k_rho(int64_t G, typename AccOf<MIX>::T *acc, double *rho,
-                                                double scale, double add, double ion, double dV, int clear,
-                                                double *charge, int step_mode, CtxDev c) {
-    __shared__ double sRed[kWaves];
-    double part = 0.0;
+                                                double scale, double add, int clear) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G; i += (int64_t)gridDim.x * blockDim.x) {
         typename AccOf<MIX>::T v = acc[i];
         double w;
         if constexpr (MIX) w = (double)(int64_t)v;
         else w = v;
-        double r = add + scale * w;
-        rho[i] = r;
-        part += r - ion;
+        rho[i] = add + scale * w;
         if (clear) acc[i] = (typename AccOf<MIX>::T)0;
     }
-    double *out = charge ? (step_mode ? step_slot(charge, c) : charge) : nullptr;
-    grid_sum_store(part, out, dV, c, sRed);
 }
 
 // Spectral Poisson + centred gradient on the half-spectrum [ny][nx/2+1]:
 //   phi_hat = rho_hat / K^2 (K^2 = modified wavenumber of the FD Laplacian,
 //   phi_hat(0) = 0), E_hat_d = -i kappa_d phi_hat with kappa = sin(k d)/d,
 //   scaled by 1/(nx ny) for the unnormalised inverse transform.
+// Per-block partial of sum_k w_k |E_hat_k|^2 (Parseval over the half
+// spectrum, w = 1 on the kx = 0 and Nyquist columns, else 2) goes to
+// c.part_spec; rho_hat(0) (= sum_j rho_j) to c.rho0.
 __global__ void __launch_bounds__(kBlock) k_spectral(Geo g, const double2 *rh, double2 *exh, double2 *eyh,
                                                      CtxDev c) {
+    __shared__ double sRed[kWaves];
     const int hx = g.nx / 2 + 1;
     const int64_t tot = (int64_t)hx * g.ny;
     const double norm = 1.0 / ((double)g.nx * (double)g.ny);
+    double part = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
         int kx = (int)(i % hx), ky = (int)(i / hx);
         double K2 = c.kx2[kx] + c.ky2[ky];
         double2 r = rh[i];
-        double inv = (kx == 0 && ky == 0) ? 0.0 : norm / K2;
+        if (i == 0) *c.rho0 = r.x;
+        double inv = (kx == 0 && ky == 0) ? 0.0 : 1.0 / K2;
         double pr = r.x * inv, pi = r.y * inv;
         // -i * kappa * (pr + i pi) = kappa * pi - i kappa * pr
         double kax = c.kapx[kx], kay = c.kapy[ky];
-        exh[i] = make_double2(kax * pi, -kax * pr);
-        eyh[i] = make_double2(kay * pi, -kay * pr);
+        double wgt = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
+        part += wgt * (kax * kax + kay * kay) * (pr * pr + pi * pi);
+        exh[i] = make_double2(kax * pi * norm, -kax * pr * norm);
+        eyh[i] = make_double2(kay * pi * norm, -kay * pr * norm);
     }
+    double bs = block_sum(part, sRed);
+    if (threadIdx.x == 0) c.part_spec[blockIdx.x] = bs;
 }
 
-__global__ void __launch_bounds__(kBlock) k_efinish(int64_t G, int dim, const double *E, float *E32, double dV,
-                                                    double *we, int step_mode, CtxDev c) {
-    __shared__ double sRed[kWaves];
-    double part = 0.0;
-    const int64_t n = G * dim;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        double e = E[i];
-        part += e * e;
-        if (E32) E32[i] = (float)e;
+// Sums the per-block partials in a fixed order (deterministic) and writes the
+// step diagnostics, or the field energy / charge of a standalone solve.
+//   kinetic  = 0.5 * mass * sum(part_push[2b]),   momentum = mass * sum(part_push[2b+1])
+//   W_E      = 0.5 * dV / G * sum(part_spec)      (Parseval)
+//   charge   = dV * (rho0 - G * rho_ion)
+__global__ void __launch_bounds__(1024) k_finalize(int npush, int nspec, double mass, double dV, double G,
+                                                   double rho_ion, double *diag, double *we, double *charge,
+                                                   CtxDev c) {
+    __shared__ double sRed[16];
+    double k = 0.0, p = 0.0, e = 0.0;
+    for (int i = threadIdx.x; i < npush; i += blockDim.x) {
+        k += c.part_push[2 * i];
+        p += c.part_push[2 * i + 1];
     }
-    double *out = we ? (step_mode ? step_slot(we, c) : we) : nullptr;
-    grid_sum_store(part, out, 0.5 * dV, c, sRed);
+    for (int i = threadIdx.x; i < nspec; i += blockDim.x) e += c.part_spec[i];
+    k = block_sum(k, sRed);
+    p = block_sum(p, sRed);
+    e = block_sum(e, sRed);
+    if (threadIdx.x == 0) {
+        double *d = diag ? step_slot(diag, c) : nullptr;
+        if (npush && d) {
+            d[2] = 0.5 * mass * k;
+            d[3] = mass * p;
+        }
+        if (nspec) {
+            double wE = 0.5 * dV / G * e;
+            double q = dV * (*c.rho0 - G * rho_ion);
+            if (d) {
+                d[0] = q;
+                d[1] = wE;
+            }
+            if (we) *we = wE;
+            if (charge) *charge = q;
+        }
+    }
 }
 
 // 1D periodic field by Gauss's law on the half nodes (identical to the FFT
@@ -989,7 +1358,6 @@ __global__ void __launch_bounds__(1024) k_field1d(int nx, typename AccOf<MIX>::T
         if (clear) acc[i] = (typename AccOf<MIX>::T)0;
     }
     double qsum = block_sum(part, sRed);
-    // mean of rho, computed from the stored values in a fixed order
     double ps = 0.0;
     for (int i = threadIdx.x; i < nx; i += T) ps += sr[i];
     double mean = block_sum(ps, sRed) / (double)nx;
@@ -1001,9 +1369,9 @@ __global__ void __launch_bounds__(1024) k_field1d(int nx, typename AccOf<MIX>::T
     sScan[threadIdx.x] = loc;
     __syncthreads();
     for (int off = 1; off < T; off <<= 1) {
-        double add = (threadIdx.x >= (unsigned)off) ? sScan[threadIdx.x - off] : 0.0;
+        double addv = (threadIdx.x >= (unsigned)off) ? sScan[threadIdx.x - off] : 0.0;
         __syncthreads();
-        sScan[threadIdx.x] += add;
+        sScan[threadIdx.x] += addv;
         __syncthreads();
     }
     double run = sScan[threadIdx.x] - loc;
@@ -1042,9 +1410,9 @@ inline size_t tile_e_bytes(const Geo &g, bool mixed) {
     return (size_t)ex_w * ey_w * g.dim * (mixed ? 4 : 8);
 }
 
-inline size_t tile_acc_bytes(const Geo &g) {
-    const int wx = (1 << g.tsx) + 1 + 2 * g.halo;
-    const int wy = (g.dim == 2) ? (1 << g.tsy) + 1 + 2 * g.halo : 1;
+inline size_t tile_acc_bytes(const Geo &g, int halo) {
+    const int wx = (1 << g.tsx) + 1 + 2 * halo;
+    const int wy = (g.dim == 2) ? (1 << g.tsy) + 1 + 2 * halo : 1;
     return (((size_t)wx * wy * 8) + 15) & ~(size_t)15;
 }
 
@@ -1052,19 +1420,21 @@ inline size_t tile_acc_bytes(const Geo &g) {
 
 // ================================================================ launchers
 
-#define APIC_DISPATCH(g, mixed, KERNEL_CALL)                                             \
-    do {                                                                                 \
-        if (mixed) {                                                                     \
-            constexpr bool MIX = true;                                                   \
-            if ((g).dim == 1) { constexpr int DIM = 1, VDIM = 1; KERNEL_CALL; }          \
-            else if ((g).vdim == 2) { constexpr int DIM = 2, VDIM = 2; KERNEL_CALL; }    \
-            else { constexpr int DIM = 2, VDIM = 3; KERNEL_CALL; }                       \
-        } else {                                                                         \
-            constexpr bool MIX = false;                                                  \
-            if ((g).dim == 1) { constexpr int DIM = 1, VDIM = 1; KERNEL_CALL; }          \
-            else if ((g).vdim == 2) { constexpr int DIM = 2, VDIM = 2; KERNEL_CALL; }    \
-            else { constexpr int DIM = 2, VDIM = 3; KERNEL_CALL; }                       \
-        }                                                                                \
+#define APIC_DISPATCH(g, mixed, ...)                                                    \
+    do {                                                                                \
+        if (mixed) {                                                                    \
+            constexpr bool MIX = true;                                                  \
+            [[maybe_unused]] constexpr int U = 2;                                       \
+            if ((g).dim == 1) { constexpr int DIM = 1, VDIM = 1; __VA_ARGS__; }         \
+            else if ((g).vdim == 2) { constexpr int DIM = 2, VDIM = 2; __VA_ARGS__; }   \
+            else { constexpr int DIM = 2, VDIM = 3; __VA_ARGS__; }                      \
+        } else {                                                                        \
+            constexpr bool MIX = false;                                                 \
+            [[maybe_unused]] constexpr int U = 2;                                       \
+            if ((g).dim == 1) { constexpr int DIM = 1, VDIM = 1; __VA_ARGS__; }         \
+            else if ((g).vdim == 2) { constexpr int DIM = 2, VDIM = 2; __VA_ARGS__; }   \
+            else { constexpr int DIM = 2, VDIM = 3; __VA_ARGS__; }                      \
+        }                                                                               \
     } while (0)
 
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
@@ -1093,6 +1463,12 @@ hipError_t launch_copy_bytes(void *dst, const void *src, int64_t bytes, hipStrea
     return hipGetLastError();
 }
 
+hipError_t launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(n)), dim3(kBlock), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_keys_hist(const Geo &g, bool mixed, const Parts &p, int64_t n, int32_t *keys, int32_t *count,
                             const CtxDev &c, hipStream_t s) {
     if (n <= 0) return hipSuccess;
@@ -1102,20 +1478,50 @@ hipError_t launch_keys_hist(const Geo &g, bool mixed, const Parts &p, int64_t n,
     return hipGetLastError();
 }
 
-hipError_t launch_scan(const int32_t *count, int32_t *start, int32_t *cursor, int32_t *count_zero, int nb,
-                       int64_t n, int64_t max_per_bucket, double *diag, const CtxDev &c, hipStream_t s) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, count, start, cursor, count_zero, nb, n, max_per_bucket,
-                       diag, c);
+hipError_t launch_scan(int32_t *count, int32_t *start, int32_t *cursor, int nb, int64_t n, int64_t max_per_bucket,
+                       const CtxDev &c, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, count, start, cursor, nb, n, max_per_bucket, c);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const Geo &g, bool mixed, const Parts &src, const Parts &dst, int64_t n,
-                          const int32_t *keys, int32_t *cursor, const int32_t *start, int32_t *perm,
-                          const CtxDev &c, hipStream_t s) {
+hipError_t launch_scan_dir(const Geo &g, const int32_t *cnt, int32_t *farcnt, int32_t *tot, int32_t *start,
+                           int32_t *offs, int32_t *farcur, int64_t n, int64_t max_per_bucket, int step_mode,
+                           const CtxDev &c, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_tot, dim3(1), dim3(1024), 0, s, tot, start, g.nbuckets, n, max_per_bucket, step_mode,
+                       c);
+    hipLaunchKernelGGL(k_dir_offsets, dim3(blocks_for(g.nbuckets, 1024)), dim3(kBlock), 0, s, g, cnt, start, offs,
+                       farcur, farcnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_keys_init(const Geo &g, bool mixed, const Parts &p, int64_t n, int32_t *keys, int32_t *idx,
+                            const CtxDev &c, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     APIC_DISPATCH(g, mixed,
-                  hipLaunchKernelGGL((k_scatter<MIX, DIM, VDIM>), dim3(blocks_for(n)), dim3(kBlock), 0, s, g, src,
-                                     dst, n, keys, cursor, start, perm, c));
+                  hipLaunchKernelGGL((k_keys_init<MIX, DIM, VDIM>), dim3(blocks_for(n)), dim3(kBlock), 0, s, g, p, n,
+                                     keys, idx, c));
+    return hipGetLastError();
+}
+
+int sort_chunks(int64_t n) { return (int)((n + kSortChunk - 1) / kSortChunk); }
+int sort_table_entries() { return kSortTab; }
+
+hipError_t launch_radix_pass(const int32_t *kin, const int32_t *iin, int32_t *kout, int32_t *iout, int64_t n,
+                             int shift, int32_t *cnt, int32_t *off, const CtxDev &c, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int C = sort_chunks(n);
+    hipLaunchKernelGGL(k_radix_count, dim3(C), dim3(kBlock), 0, s, kin, n, shift, cnt);
+    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, s, cnt, off, C);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(C), dim3(kBlock), 0, s, kin, iin, kout, iout, n, shift, off, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_parts(const Geo &g, bool mixed, const Parts &src, const Parts &dst, int64_t n,
+                               const int32_t *idx, int32_t *perm, const CtxDev &c, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    APIC_DISPATCH(g, mixed,
+                  hipLaunchKernelGGL((k_gather_parts<MIX, DIM, VDIM>), dim3(blocks_for(n)), dim3(kBlock), 0, s, src,
+                                     dst, n, idx, perm, c));
     return hipGetLastError();
 }
 
@@ -1123,12 +1529,10 @@ hipError_t launch_deposit(const Geo &g, bool mixed, const Parts &p, int64_t n, c
                           const CtxDev &c, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (bstart) {
-        Geo g0 = g;
-        g0.halo = 0;
-        size_t sh = tile_acc_bytes(g0);
+        size_t sh = tile_acc_bytes(g, 0);
         APIC_DISPATCH(g, mixed,
                       hipLaunchKernelGGL((k_deposit_tiled<MIX, DIM, VDIM>), dim3(grid_for_buckets(g.nbuckets)),
-                                         dim3(kBlock), sh, s, g0, p, bstart, (typename AccOf<MIX>::T *)acc, c));
+                                         dim3(kBlock), sh, s, g, p, bstart, (typename AccOf<MIX>::T *)acc, c));
     } else {
         APIC_DISPATCH(g, mixed,
                       hipLaunchKernelGGL((k_deposit_direct<MIX, DIM, VDIM>), dim3(blocks_for(n)), dim3(kBlock), 0, s,
@@ -1153,52 +1557,76 @@ hipError_t launch_gather_push(const Geo &g, bool mixed, const Parts &p, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int32_t *bstart, const void *E,
-                             const PushC &pc, int32_t *count, const CtxDev &c, hipStream_t s) {
+// Persistent grid: as many blocks as fit on the device at once (a multiple of
+// 8 for the XCD walk), never more than the bucket count needs.
+template <typename K>
+int persistent_grid(K kernel, size_t shmem, int nbuckets) {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, shmem) != hipSuccess || per_cu <= 0)
+        per_cu = 4;
+    int g = cus * per_cu;
+    const int need = grid_for_buckets(nbuckets);
+    if (g > need) g = need;
+    return ((g + 7) >> 3) << 3;
+}
+
+hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int32_t *bstart, const double *E,
+                             const PushC &pc, int32_t *cnt, int32_t *tot, int32_t *farcnt, const CtxDev &c,
+                             hipStream_t s) {
     size_t sh = tile_e_bytes(g, mixed);
-    APIC_DISPATCH(g, mixed,
-                  hipLaunchKernelGGL((k_step_count<MIX, DIM, VDIM>), dim3(grid_for_buckets(g.nbuckets)), dim3(kBlock),
-                                     sh, s, g, p, bstart, (const typename Pt<MIX>::R *)E, pc, count, c));
+    APIC_DISPATCH(g, mixed, {
+        auto kern = k_step_count<MIX, DIM, VDIM, U>;
+        hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, p, bstart, E,
+                           pc, cnt, tot, farcnt, c);
+    });
     return hipGetLastError();
 }
 
 hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Parts &dst, const int32_t *bstart,
-                            const int32_t *bstart_new, int32_t *cursor, const void *E, const PushC &pc, void *acc,
-                            int32_t *perm, double *diag, double mass, const CtxDev &c, hipStream_t s) {
-    size_t sh = tile_acc_bytes(g) + tile_e_bytes(g, mixed);
-    APIC_DISPATCH(g, mixed,
-                  hipLaunchKernelGGL((k_step_push<MIX, DIM, VDIM>), dim3(grid_for_buckets(g.nbuckets)), dim3(kBlock),
-                                     sh, s, g, src, dst, bstart, bstart_new, cursor, (const typename Pt<MIX>::R *)E,
-                                     pc, (typename AccOf<MIX>::T *)acc, perm, diag, mass, c));
+                            const int32_t *bstart_new, const int32_t *offs, int32_t *farcur, const double *E,
+                            const PushC &pc, void *acc, int32_t *perm, double *part, const CtxDev &c,
+                            hipStream_t s) {
+    size_t sh = tile_acc_bytes(g, g.halo) + tile_e_bytes(g, mixed);
+    APIC_DISPATCH(g, mixed, {
+        auto kern = k_step_push<MIX, DIM, VDIM, U>;
+        hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, src, dst,
+                           bstart, bstart_new, offs, farcur, E, pc, (typename AccOf<MIX>::T *)acc, perm, part, c);
+    });
     return hipGetLastError();
 }
 
-hipError_t launch_rho(const Geo &g, bool mixed, void *acc, double *rho, double scale, double add, double ion,
-                      double dV, int clear, double *charge_out, int step_mode, const CtxDev &c, hipStream_t s) {
+hipError_t launch_rho(const Geo &g, bool mixed, void *acc, double *rho, double scale, double add, int clear,
+                      hipStream_t s) {
     const int64_t G = (int64_t)g.nx * g.ny;
-    const int nb = blocks_for(G, 1024);
+    const int nb = blocks_for(G, 2048);
     if (mixed)
         hipLaunchKernelGGL(k_rho<true>, dim3(nb), dim3(kBlock), 0, s, G, (unsigned long long *)acc, rho, scale, add,
-                           ion, dV, clear, charge_out, step_mode, c);
+                           clear);
     else
-        hipLaunchKernelGGL(k_rho<false>, dim3(nb), dim3(kBlock), 0, s, G, (double *)acc, rho, scale, add, ion, dV,
-                           clear, charge_out, step_mode, c);
+        hipLaunchKernelGGL(k_rho<false>, dim3(nb), dim3(kBlock), 0, s, G, (double *)acc, rho, scale, add, clear);
     return hipGetLastError();
 }
+
+int spectral_blocks(const Geo &g) { return blocks_for((int64_t)(g.nx / 2 + 1) * g.ny, kMaxSpecBlocks); }
 
 hipError_t launch_spectral(const Geo &g, const void *rho_hat, void *ex_hat, void *ey_hat, const CtxDev &c,
                            hipStream_t s) {
-    const int64_t tot = (int64_t)(g.nx / 2 + 1) * g.ny;
-    hipLaunchKernelGGL(k_spectral, dim3(blocks_for(tot)), dim3(kBlock), 0, s, g, (const double2 *)rho_hat,
+    hipLaunchKernelGGL(k_spectral, dim3(spectral_blocks(g)), dim3(kBlock), 0, s, g, (const double2 *)rho_hat,
                        (double2 *)ex_hat, (double2 *)ey_hat, c);
     return hipGetLastError();
 }
 
-hipError_t launch_efinish(const Geo &g, const double *E, float *E32, double dV, double *we_out, int step_mode,
-                          const CtxDev &c, hipStream_t s) {
-    const int64_t G = (int64_t)g.nx * g.ny;
-    const int nb = blocks_for(G * g.dim, 1024);
-    hipLaunchKernelGGL(k_efinish, dim3(nb), dim3(kBlock), 0, s, G, g.dim, E, E32, dV, we_out, step_mode, c);
+hipError_t launch_finalize(int npush, int nspec, double mass, double dV, double G, double rho_ion, double *diag,
+                           double *we, double *charge, const CtxDev &c, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, npush, nspec, mass, dV, G, rho_ion, diag, we, charge,
+                       c);
     return hipGetLastError();
 }
 
