@@ -482,9 +482,7 @@ apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, floa
     const int nb = c->g.nbuckets;
     const int64_t G = (int64_t)c->d.nx * c->d.ny;
     int32_t *cnt = wsp<int32_t>(ws, c->o_cnt);
-    int32_t *offs = wsp<int32_t>(ws, c->o_offs);
     int32_t *farcnt = wsp<int32_t>(ws, c->o_farcnt);
-    int32_t *farcur = wsp<int32_t>(ws, c->o_farcur);
     int32_t *tot = wsp<int32_t>(ws, c->o_tot);
     void *acc = wsp<void>(ws, c->o_acc);
     Parts A = parts_of(p), B = parts_ws(c, ws);
@@ -506,10 +504,9 @@ apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, floa
         if (ev) HIPCHK(c, hipEventRecord(ev[0], s));
         HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, E, pc, cnt, tot, farcnt, c->dev, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[1], s));
-        HIPCHK(c, launch_scan_dir(c->g, cnt, farcnt, tot, bs_dst, offs, farcur, c->n, max_per_bucket(c), 1, c->dev,
-                                  s));
+        HIPCHK(c, launch_scan_dir(c->g, tot, bs_dst, c->n, max_per_bucket(c), 1, c->dev, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
-        HIPCHK(c, launch_step_push(c->g, c->mixed, src, dst, bs_src, bs_dst, offs, farcur, E, pc, acc, p->perm,
+        HIPCHK(c, launch_step_push(c->g, c->mixed, src, dst, bs_src, bs_dst, cnt, farcnt, E, pc, acc, p->perm,
                                    diag ? c->dev.part_push : nullptr, c->dev, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[3], s));
         if (rho && last) {

@@ -98,12 +98,11 @@ hipError_t launch_gather_push(const Geo &g, bool mixed, const Parts &p, int64_t 
 hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int32_t *bstart,
                              const double *E, const PushC &pc, int32_t *cnt, int32_t *tot,
                              int32_t *farcnt, const CtxDev &c, hipStream_t s);
-hipError_t launch_scan_dir(const Geo &g, const int32_t *cnt, int32_t *farcnt, int32_t *tot,
-                           int32_t *start, int32_t *offs, int32_t *farcur, int64_t n,
-                           int64_t max_per_bucket, int step_mode, const CtxDev &c, hipStream_t s);
+hipError_t launch_scan_dir(const Geo &g, int32_t *tot, int32_t *start, int64_t n, int64_t max_per_bucket,
+                           int step_mode, const CtxDev &c, hipStream_t s);
 hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Parts &dst,
-                            const int32_t *bstart, const int32_t *bstart_new, const int32_t *offs,
-                            int32_t *farcur, const double *E, const PushC &pc, void *acc, int32_t *perm,
+                            const int32_t *bstart, const int32_t *bstart_new, const int32_t *cnt,
+                            int32_t *farcnt, const double *E, const PushC &pc, void *acc, int32_t *perm,
                             double *part, const CtxDev &c, hipStream_t s);
 
 // field: accumulation buffer -> rho (FP64): rho = add + scale * acc

@@ -706,24 +706,6 @@ __global__ void __launch_bounds__(1024) k_scan_tot(int32_t *tot, int32_t *start,
     }
 }
 
-// For each destination bucket: its sources' tallies, in direction-then-wave
-// order, occupy consecutive ranges from start[nb]; far arrivals follow.
-__global__ void __launch_bounds__(kBlock) k_dir_offsets(Geo g, const int32_t *cnt, const int32_t *start,
-                                                        int32_t *offs, int32_t *farcur, int32_t *farcnt) {
-    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < g.nbuckets; b += gridDim.x * blockDim.x) {
-        int32_t run = start[b];
-        for (int d = 0; d < kFar; ++d) {
-            const int s = dir_source(g, b, d);
-            for (int w = 0; w < kWaves; ++w) {
-                offs[s * kTab + w * kDirs + d] = run;
-                run += cnt[s * kTab + w * kDirs + d];
-            }
-        }
-        farcur[b] = run;
-        farcnt[b] = 0;
-    }
-}
-
 // ---- general sort: stable LSD radix sort of (bucket key, index) ----------------
 // Keys are bucket indices; each pass orders by 8 more key bits, keeping the
 // previous order among equal digits (stable), so the result is the stable
@@ -1106,8 +1088,8 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
 // ---- fused step, pass 2: push, deposit, scatter into the next bucket order -----
 template <bool MIX, int DIM, int VDIM, int U>
 __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts dst, const int32_t *bstart,
-                                                      const int32_t *bstart_new, const int32_t *offs,
-                                                      int32_t *farcur, const double *E, PushC pc,
+                                                      const int32_t *bstart_new, const int32_t *cnt,
+                                                      int32_t *farcnt, const double *E, PushC pc,
                                                       typename AccOf<MIX>::T *acc, int32_t *perm, double *part,
                                                       CtxDev c) {
     using R = typename Pt<MIX>::R;
@@ -1116,7 +1098,7 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
     __shared__ int sErr;
     __shared__ double sRed[kWaves];
     __shared__ int32_t sRun[kTab];
-    __shared__ int32_t sEnd[kFar];   // end of each neighbour destination bucket
+    __shared__ int32_t sEnd[kFar];   // end of each neighbour destination bucket (slot bound)
     const int ex_w = (1 << g.tsx) + 1, ey_w = (DIM == 2) ? (1 << g.tsy) + 1 : 1;
     const int wx = (1 << g.tsx) + 1 + 2 * g.halo;
     const int wy = (DIM == 2) ? (1 << g.tsy) + 1 + 2 * g.halo : 1;
@@ -1132,15 +1114,29 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
         const int by = (DIM == 2) ? (b / g.nbx) : 0;
         const int x0 = bx << g.tsx, y0 = (DIM == 2) ? (by << g.tsy) : 0;
         for (int t2 = threadIdx.x; t2 < wx * wy; t2 += blockDim.x) sA[t2] = (A)0;
-        if (threadIdx.x < kTab) sRun[threadIdx.x] = offs[b * kTab + threadIdx.x];
-        if (threadIdx.x < kFar) {
-            const int d = threadIdx.x;
-            int nx_ = bx + d % 3 - 1, ny_ = by + d / 3 - 1;
-            if (nx_ < 0) nx_ += g.nbx;
-            if (nx_ >= g.nbx) nx_ -= g.nbx;
-            if (ny_ < 0) ny_ += g.nby;
-            if (ny_ >= g.nby) ny_ -= g.nby;
-            sEnd[d] = bstart_new[((DIM == 2) ? ny_ * g.nbx + nx_ : nx_) + 1];
+        // first slot of each (wave, direction) tally of this bucket: inside the
+        // destination bucket the tallies of its sources follow direction order,
+        // then wave order, so the offset is the destination's start plus the
+        // tallies that precede this one.
+        if (threadIdx.x < kTab) {
+            const int w2 = threadIdx.x / kDirs, d = threadIdx.x % kDirs;
+            int off = 0;
+            if (d < kFar) {
+                int nx_ = bx + d % 3 - 1, ny_ = by + d / 3 - 1;
+                if (nx_ < 0) nx_ += g.nbx;
+                if (nx_ >= g.nbx) nx_ -= g.nbx;
+                if (ny_ < 0) ny_ += g.nby;
+                if (ny_ >= g.nby) ny_ -= g.nby;
+                const int nb = (DIM == 2) ? ny_ * g.nbx + nx_ : nx_;
+                off = bstart_new[nb];
+                for (int d2 = 0; d2 < d; ++d2) {
+                    const int s2 = dir_source(g, nb, d2);
+                    for (int w3 = 0; w3 < kWaves; ++w3) off += cnt[s2 * kTab + w3 * kDirs + d2];
+                }
+                for (int w3 = 0; w3 < w2; ++w3) off += cnt[b * kTab + w3 * kDirs + d];
+                if (w2 == 0) sEnd[d] = bstart_new[nb + 1];
+            }
+            sRun[threadIdx.x] = off;
         }
         load_e_tile<R, double, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
         __syncthreads();
@@ -1210,8 +1206,10 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                     rem &= ~grp;
                 }
                 if (code == kFar) {
-                    slot = atomicAdd(&farcur[nbk], 1);
-                    if (slot >= bstart_new[nbk + 1]) slot = -1;
+                    // far arrivals fill the end of their bucket; the counter
+                    // returns to zero for the next step
+                    const int v = atomicSub(&farcnt[nbk], 1);
+                    slot = (v > 0) ? bstart_new[nbk + 1] - v : -1;
                 }
                 if (act) {
                     if (slot >= 0) {
@@ -1484,13 +1482,10 @@ hipError_t launch_scan(int32_t *count, int32_t *start, int32_t *cursor, int nb, 
     return hipGetLastError();
 }
 
-hipError_t launch_scan_dir(const Geo &g, const int32_t *cnt, int32_t *farcnt, int32_t *tot, int32_t *start,
-                           int32_t *offs, int32_t *farcur, int64_t n, int64_t max_per_bucket, int step_mode,
-                           const CtxDev &c, hipStream_t s) {
+hipError_t launch_scan_dir(const Geo &g, int32_t *tot, int32_t *start, int64_t n, int64_t max_per_bucket,
+                           int step_mode, const CtxDev &c, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_tot, dim3(1), dim3(1024), 0, s, tot, start, g.nbuckets, n, max_per_bucket, step_mode,
                        c);
-    hipLaunchKernelGGL(k_dir_offsets, dim3(blocks_for(g.nbuckets, 1024)), dim3(kBlock), 0, s, g, cnt, start, offs,
-                       farcur, farcnt);
     return hipGetLastError();
 }
 
@@ -1590,14 +1585,14 @@ hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int
 }
 
 hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Parts &dst, const int32_t *bstart,
-                            const int32_t *bstart_new, const int32_t *offs, int32_t *farcur, const double *E,
+                            const int32_t *bstart_new, const int32_t *cnt, int32_t *farcnt, const double *E,
                             const PushC &pc, void *acc, int32_t *perm, double *part, const CtxDev &c,
                             hipStream_t s) {
     size_t sh = tile_acc_bytes(g, g.halo) + tile_e_bytes(g, mixed);
     APIC_DISPATCH(g, mixed, {
         auto kern = k_step_push<MIX, DIM, VDIM, U>;
         hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, src, dst,
-                           bstart, bstart_new, offs, farcur, E, pc, (typename AccOf<MIX>::T *)acc, perm, part, c);
+                           bstart, bstart_new, cnt, farcnt, E, pc, (typename AccOf<MIX>::T *)acc, perm, part, c);
     });
     return hipGetLastError();
 }

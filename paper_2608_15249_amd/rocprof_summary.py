@@ -1,0 +1,95 @@
+"""Summaries of rocprofv3 result databases (kernel trace and PMC counters).
+
+Usage:
+  python -m paper_2608_15249_amd.rocprof_summary trace <results.db> [--cmd "..."]
+  python -m paper_2608_15249_amd.rocprof_summary traffic <fetch.db> <write.db> \
+        --kernel k_step_push --copy-bytes N [--cmd "..."]
+
+`trace` prints per-kernel call counts and average/total durations. `traffic`
+turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch, summed over the counter
+instances of a dispatch) into HBM bytes per dispatch of the named kernel,
+each scaled by the factor that makes the same counter read the known byte
+count of the plain copy kernel (k_copy_bytes) of the same run.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import json
+import re
+import sqlite3
+
+
+def _short(name: str) -> str:
+    n = name.replace("void ", "").replace("apic::(anonymous namespace)::", "")
+    m = re.match(r"([A-Za-z_0-9]+)(<[^>]*>)?", n)
+    return (m.group(1) + (m.group(2) or "")) if m else n[:60]
+
+
+def kernel_stats(db: str):
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, count(*), avg(end-start), sum(end-start) from kernels group by name").fetchall()
+    out = [(_short(n), c, a / 1e3, s / 1e6) for n, c, a, s in rows]
+    out.sort(key=lambda r: -r[3])
+    return out
+
+
+def pmc_per_dispatch(db: str, counter: str):
+    """{kernel short name: [value per dispatch]} summed over counter instances."""
+    con = sqlite3.connect(db)
+    per = collections.defaultdict(float)
+    names = {}
+    for name, did, cn, cv in con.execute("select name, dispatch_id, counter_name, counter_value from pmc_events"):
+        if cn != counter:
+            continue
+        per[did] += cv
+        names[did] = _short(name)
+    out = collections.defaultdict(list)
+    for did, v in per.items():
+        out[names[did]].append(v)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd_name", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("--cmd", default="")
+    f = sub.add_parser("traffic")
+    f.add_argument("fetch_db")
+    f.add_argument("write_db")
+    f.add_argument("--kernel", required=True)
+    f.add_argument("--copy-bytes", type=float, required=True)
+    f.add_argument("--cmd", default="")
+    f.add_argument("--tag", default="")
+    a = ap.parse_args()
+    if a.cmd_name == "trace":
+        if a.cmd:
+            print("command: %s" % a.cmd)
+        print("%-46s %7s %12s %12s" % ("kernel", "calls", "avg_us", "total_ms"))
+        for n, c, avg, tot in kernel_stats(a.db):
+            print("%-46s %7d %12.2f %12.3f" % (n[:46], c, avg, tot))
+        return
+    fe = pmc_per_dispatch(a.fetch_db, "FETCH_SIZE")
+    wr = pmc_per_dispatch(a.write_db, "WRITE_SIZE")
+    cf = [v for k, v in fe.items() if k.startswith("k_copy_bytes")]
+    cw = [v for k, v in wr.items() if k.startswith("k_copy_bytes")]
+    copy_f = max(x for vals in cf for x in vals) * 1024.0
+    copy_w = max(x for vals in cw for x in vals) * 1024.0
+    ff = a.copy_bytes / copy_f
+    fw = a.copy_bytes / copy_w
+    res = {"command": a.cmd, "tag": a.tag, "fetch_scale": ff, "write_scale": fw, "copy_bytes": a.copy_bytes,
+           "kernels": {}}
+    for k in sorted(set(fe) | set(wr)):
+        if not k.startswith(a.kernel):
+            continue
+        fk = sum(fe[k]) / len(fe[k]) * 1024.0 * ff
+        wk = sum(wr[k]) / len(wr[k]) * 1024.0 * fw
+        res["kernels"][k] = {"fetch_bytes": fk, "write_bytes": wk, "hbm_bytes_per_launch": fk + wk,
+                             "dispatches": len(fe[k])}
+    print(json.dumps(res, indent=1))
+
+
+if __name__ == "__main__":
+    main()
