@@ -396,11 +396,12 @@ def test_mixed_local_field_energy_error(torch):
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_step_deterministic(torch, precision):
-    """Two runs from the same input give identical bits: particle order and
-    values, fields and every diagnostic (the mixed path's int64 deposit is
-    order-free; the step's slot table and reductions have a fixed order). The
-    FP64 path's deposit uses FP64 atomics, so only its particle order table is
-    compared."""
+    """Mixed path: two runs from the same input give identical bits: particle
+    order and values, fields and every diagnostic. Slots come from the
+    per-bucket tallies, the int64 deposit is order-free and summed over tiles
+    in a fixed order, and every reduction has a fixed tree (no particle here
+    jumps more than a tile, the one case that takes a slot from an atomic
+    counter)."""
     from paper_2608_15249_amd.sim import Simulation
     w = W.thermal_2d(seed=7, nx=64, ppc=32)
     outs = []
@@ -411,13 +412,16 @@ def test_step_deterministic(torch, precision):
         sim.ctx.sync()
         outs.append((sim.E.cpu().numpy(), d.cpu().numpy(), sim.state()))
     (E1, d1, s1), (E2, d2, s2) = outs
-    if precision == "mixed":
-        assert np.array_equal(E1, E2)
-        assert np.array_equal(d1, d2)
-        for k in ("cell", "ox", "oy", "vx", "vy", "bucket_start"):
-            assert np.array_equal(s1[k], s2[k]), k
-    else:
+    if precision == "fp64":
+        # FP64 sums inside a tile use LDS atomics, whose order varies between
+        # runs: equal to rounding, and the bucket tables agree
+        assert np.allclose(E1, E2, rtol=0, atol=1e-12 * np.abs(E1).max())
         assert np.array_equal(s1["bucket_start"], s2["bucket_start"])
+        return
+    assert np.array_equal(E1, E2)
+    assert np.array_equal(d1, d2)
+    for k in ("cell", "ox", "oy", "vx", "vy", "bucket_start"):
+        assert np.array_equal(s1[k], s2[k]), k
 
 
 def test_nan_particle_reports_domain_error(torch):
