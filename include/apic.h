@@ -194,6 +194,60 @@ apic_status apic_step(apic_ctx *ctx, apic_particles *p, void *rho, double *E, fl
 apic_status apic_profile_enable(apic_ctx *ctx, int max_steps);
 apic_status apic_profile_read(apic_ctx *ctx, double ms[4], int *steps);
 
+/* ---- batched replicas (a9) ------------------------------------------------
+ * Many independent 1D1V periodic electrostatic plasmas ("replicas") with
+ * their own grid and particle counts, advanced together. Each replica is the
+ * single-plasma mixed-precision cycle (binary32 push of cell + offset
+ * positions, int64 fixed-point CIC deposit with S = 32, FP64 1D field solve)
+ * and gives the bits it gives alone. One persistent kernel launch per step
+ * (replayed from a captured HIP graph): workgroups pull (replica, chunk)
+ * items from a work counter, stage the replica's whole grid in LDS, and the
+ * workgroup that finishes a replica's last chunk solves its field. Particles
+ * keep their order (no sort: each replica's grid fits in LDS).
+ * Every replica is a neutral electron plasma: q_macro = -rho_ion * lx / n. */
+typedef struct {
+    int nx;          /* grid nodes, 2..1024                                    */
+    int64_t n;       /* particles                                              */
+    double lx;       /* box length                                             */
+} apic_replica;
+
+typedef struct apic_batch apic_batch;
+
+/* Packed state of all replicas, [dev], caller-owned: replica r owns particles
+ * [part_off[r], part_off[r+1]) and grid nodes [grid_off[r], grid_off[r+1]).
+ * cell: int32 cell index, ox: binary32 offset in [0,1), vx: binary32 velocity;
+ * E: double node field (E^n in, E^{n+k} out). */
+typedef struct {
+    int32_t *cell;
+    float *ox;
+    float *vx;
+    double *E;
+} apic_batch_state;
+
+/* chunk: particles per work item (0 = 8192). Fails with APIC_EINVAL for an
+ * invalid replica (nx outside 2..1024, n < 0, lx <= 0) or a total particle
+ * count above INT32_MAX - 1. Allocates the context's device tables. */
+apic_status apic_batch_create(const apic_replica *reps, int nrep, double dt, double qm, double rho_ion, int chunk,
+                              apic_batch **out);
+void apic_batch_destroy(apic_batch *b);
+/* Totals and the workspace size (int64 charge accumulator of all grids). */
+apic_status apic_batch_sizes(const apic_batch *b, int64_t *n_total, int64_t *g_total, size_t *ws_bytes);
+/* [host] part_off and grid_off, nrep + 1 entries each (either may be NULL). */
+apic_status apic_batch_offsets(const apic_batch *b, int64_t *part_off, int64_t *grid_off);
+/* Number of work items (for sizing external tuning loops). */
+int apic_batch_work_items(const apic_batch *b);
+/* E^0 from the initial positions, then the backward half push v^0 -> v^{-1/2}. */
+apic_status apic_batch_init(apic_batch *b, apic_batch_state *st, void *ws, void *stream);
+/* nsteps cycles. diag [dev, double, nsteps*nrep*4] (or NULL): per step k and
+ * replica r at (k*nrep + r)*4: charge, W_E at n+k+1, kinetic energy at n+k,
+ * x-momentum (as in apic_step). rho [dev, int64, g_total] optional: the last
+ * step's fixed-point node sums. use_graph != 0 replays one captured launch per
+ * step (captured on first use for the given pointers). */
+apic_status apic_batch_step(apic_batch *b, apic_batch_state *st, int nsteps, double *diag, int64_t *rho, void *ws,
+                            void *stream, int use_graph);
+apic_status apic_batch_sync_status(apic_batch *b, void *stream);
+const char *apic_batch_last_error(const apic_batch *b);
+
 /* Waits for the stream, then returns and clears the device error flags
  * (APIC_OK, APIC_EDOMAIN or APIC_EOVERFLOW). */
 apic_status apic_sync_status(apic_ctx *ctx, void *stream);

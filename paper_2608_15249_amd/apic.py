@@ -43,9 +43,20 @@ class ParticlesC(ctypes.Structure):
                 ("bucket_start", ctypes.c_void_p), ("perm", ctypes.c_void_p)]
 
 
+class ReplicaC(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("n", ctypes.c_int64), ("lx", ctypes.c_double)]
+
+
+class BatchStateC(ctypes.Structure):
+    _fields_ = [("cell", ctypes.c_void_p), ("ox", ctypes.c_void_p), ("vx", ctypes.c_void_p), ("E", ctypes.c_void_p)]
+
+
 EXPORTS = ["apic_create", "apic_destroy", "apic_workspace_size", "apic_num_buckets", "apic_frac_bits",
            "apic_sort_by_cell", "apic_deposit", "apic_field_solve", "apic_gather_push", "apic_step",
-           "apic_sync_status", "apic_last_error", "apic_profile_enable", "apic_profile_read"]
+           "apic_sync_status", "apic_last_error", "apic_profile_enable", "apic_profile_read",
+           "apic_batch_create", "apic_batch_destroy", "apic_batch_sizes", "apic_batch_offsets",
+           "apic_batch_work_items", "apic_batch_init", "apic_batch_step", "apic_batch_sync_status",
+           "apic_batch_last_error"]
 
 _lib = None
 
@@ -75,6 +86,15 @@ def load_library(path: str = LIB_PATH):
         "apic_last_error": ([vp], ctypes.c_char_p),
         "apic_profile_enable": ([vp, cint], cint),
         "apic_profile_read": ([vp, P(ctypes.c_double), P(cint)], cint),
+        "apic_batch_create": ([P(ReplicaC), cint, dbl, dbl, dbl, cint, P(vp)], cint),
+        "apic_batch_destroy": ([vp], None),
+        "apic_batch_sizes": ([vp, P(i64), P(i64), P(ctypes.c_size_t)], cint),
+        "apic_batch_offsets": ([vp, P(i64), P(i64)], cint),
+        "apic_batch_work_items": ([vp], cint),
+        "apic_batch_init": ([vp, P(BatchStateC), vp, vp], cint),
+        "apic_batch_step": ([vp, P(BatchStateC), cint, vp, vp, vp, vp, cint], cint),
+        "apic_batch_sync_status": ([vp, vp], cint),
+        "apic_batch_last_error": ([vp], ctypes.c_char_p),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -176,6 +196,78 @@ class Context:
         self._check(self.L.apic_step(self.h, ctypes.byref(s), ctypes.c_void_p(_ptr(rho)), ctypes.c_void_p(E.data_ptr()),
                                      ctypes.c_void_p(_ptr(E32)), int(nsteps), ctypes.c_void_p(_ptr(diag)),
                                      ctypes.c_void_p(self.ws.data_ptr()), _stream()))
+
+
+class Batch:
+    """Many 1D1V replicas on the GPU (apic_batch_*): packed device state."""
+
+    def __init__(self, reps, dt, qm=-1.0, rho_ion=1.0, chunk=0, device="cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libapic needs a HIP GPU; none is visible")
+        self.L = load_library()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.nrep = len(reps)
+        arr = (ReplicaC * self.nrep)(*[ReplicaC(int(nx), int(n), float(lx)) for nx, n, lx in reps])
+        h = ctypes.c_void_p()
+        st = self.L.apic_batch_create(arr, self.nrep, float(dt), float(qm), float(rho_ion), int(chunk),
+                                      ctypes.byref(h))
+        if st != 0:
+            raise ApicError(st, "apic_batch_create rejected the replicas")
+        self.h = h
+        nt, gt, ws = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+        self._check(self.L.apic_batch_sizes(h, ctypes.byref(nt), ctypes.byref(gt), ctypes.byref(ws)))
+        self.n_total, self.g_total = int(nt.value), int(gt.value)
+        po = (ctypes.c_int64 * (self.nrep + 1))()
+        go = (ctypes.c_int64 * (self.nrep + 1))()
+        self._check(self.L.apic_batch_offsets(h, po, go))
+        self.part_off = np.array(list(po), dtype=np.int64)
+        self.grid_off = np.array(list(go), dtype=np.int64)
+        dev = self.device
+        self.ws = torch.zeros(max(int(ws.value), 256), dtype=torch.uint8, device=dev)
+        self.cell = torch.zeros(self.n_total, dtype=torch.int32, device=dev)
+        self.ox = torch.zeros(self.n_total, dtype=torch.float32, device=dev)
+        self.vx = torch.zeros(self.n_total, dtype=torch.float32, device=dev)
+        self.E = torch.zeros(self.g_total, dtype=torch.float64, device=dev)
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.L.apic_batch_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            msg = self.L.apic_batch_last_error(self.h)
+            raise ApicError(st, msg.decode() if msg else "")
+
+    def _state(self):
+        return BatchStateC(self.cell.data_ptr(), self.ox.data_ptr(), self.vx.data_ptr(), self.E.data_ptr())
+
+    def upload(self, cell, ox, vx):
+        t = self.torch
+        self.cell.copy_(t.from_numpy(np.ascontiguousarray(cell, dtype=np.int32)).to(self.device))
+        self.ox.copy_(t.from_numpy(np.ascontiguousarray(ox, dtype=np.float32)).to(self.device))
+        self.vx.copy_(t.from_numpy(np.ascontiguousarray(vx, dtype=np.float32)).to(self.device))
+
+    def init(self):
+        st = self._state()
+        self._check(self.L.apic_batch_init(self.h, ctypes.byref(st), ctypes.c_void_p(self.ws.data_ptr()), _stream()))
+
+    def step(self, nsteps, diag=None, rho=None, use_graph=True):
+        st = self._state()
+        self._check(self.L.apic_batch_step(self.h, ctypes.byref(st), int(nsteps), ctypes.c_void_p(_ptr(diag)),
+                                           ctypes.c_void_p(_ptr(rho)), ctypes.c_void_p(self.ws.data_ptr()),
+                                           _stream(), 1 if use_graph else 0))
+
+    def sync(self):
+        self._check(self.L.apic_batch_sync_status(self.h, _stream()))
+
+    def work_items(self):
+        return int(self.L.apic_batch_work_items(self.h))
 
 
 class Particles:

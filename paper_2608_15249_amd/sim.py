@@ -13,7 +13,7 @@ from typing import Optional
 import numpy as np
 
 from . import workloads as W
-from .apic import Context, Particles
+from .apic import Batch, Context, Particles
 
 
 class Simulation:
@@ -75,3 +75,45 @@ class Simulation:
             ix, iy = W.unpack_cell(d["cell"], self.w.dim)
             d["ix"], d["iy"] = ix, iy
         return d
+
+
+class BatchSimulation:
+    """Replicas of 1D1V plasmas (e.g. the Landau-damping ensemble) advanced
+    together by the batched path. Inputs are the seeded replica workloads."""
+
+    def __init__(self, replicas, dt=0.1, chunk=0, states=None, device="cuda"):
+        self.replicas = list(replicas)
+        ws = [W.replica_workload(r) for r in self.replicas]
+        self.workloads = ws
+        self.batch = Batch([(w.nx, w.n_particles, w.Lx) for w in ws], dt, chunk=chunk, device=device)
+        cells, offs, vels = [], [], []
+        for i, w in enumerate(ws):
+            if states is not None:
+                x, vx = states[i]
+            else:
+                x, _, vx, _, _ = W.sample(w)
+            c, o = W.to_cell_offset(x, w.dx, w.nx)
+            cells.append(c)
+            offs.append(o)
+            vels.append(vx)
+        self.batch.upload(np.concatenate(cells), np.concatenate(offs), np.concatenate(vels))
+
+    def initialise(self):
+        self.batch.init()
+
+    def run(self, nsteps, diag=True, use_graph=True, rho=None):
+        d = None
+        if diag:
+            d = self.batch.torch.zeros(nsteps * self.batch.nrep * 4, dtype=self.batch.torch.float64,
+                                       device=self.batch.device)
+        self.batch.step(nsteps, d, rho=rho, use_graph=use_graph)
+        return d
+
+    def replica_field(self, r):
+        g0, g1 = self.batch.grid_off[r], self.batch.grid_off[r + 1]
+        return self.batch.E[g0:g1].cpu().numpy()
+
+    def replica_state(self, r):
+        p0, p1 = self.batch.part_off[r], self.batch.part_off[r + 1]
+        return (self.batch.cell[p0:p1].cpu().numpy(), self.batch.ox[p0:p1].cpu().numpy(),
+                self.batch.vx[p0:p1].cpu().numpy())
