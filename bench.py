@@ -1,23 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the PIC particle-grid coupling loop on one MI355X.
 
-Workload: 2D2V thermal plasma, 512 x 512 cells, dx = lambda_D = 1, 64
-electrons per cell (16,777,216), Maxwellian v_th = 1, uniform positions,
-immobile ion background, CIC, dt = 0.1 (seeded synthetic input).
+Default workload (thermal_2d): 2D2V thermal plasma, 512 x 512 cells,
+dx = lambda_D = 1, 64 electrons per cell (16,777,216), Maxwellian v_th = 1,
+uniform positions, immobile ion background, CIC, dt = 0.1 (seeded synthetic
+input). Other workloads (--workload): magnetized_2d3v (1024 x 1024, 32 per
+cell, 33,554,432 electrons, B_z with omega_c/omega_p = 2, dt = 0.05) and
+landau_batch (256 uneven 1D1V Landau-damping replicas advanced by the batched
+path, one graph-replayed persistent launch per step).
 
-One step = one full PIC cycle through apic_step: gather + Boris + move,
-deposit (CIC), counting sort by tile bucket, periodic Poisson solve and E.
-The headline value is the mixed-precision path (binary32 push, cell + binary32
-offset positions, int64 fixed-point deposit, FP64 field); the FP64 path is
-measured the same way and reported beside it.
+One step = one full PIC cycle: gather + Boris + move, deposit (CIC),
+counting sort by tile bucket, periodic Poisson solve and E. The headline value
+is the mixed-precision path (binary32 push, cell + binary32 offset positions,
+int64 fixed-point deposit, FP64 field); the FP64 path is measured the same
+way and reported beside it. The sort-bucket tile (single plasma) and the
+work-item size (batch) are picked by the library's autotuner unless given.
 
 Prints one JSON line. Roofline of the dominant kernel (the push pass:
-gather + Boris + move + deposit + scatter into the next bucket order) uses
-its average launch duration measured with HIP events on the stream the
-kernel runs on, inside the timed region.
+gather + Boris + move + deposit + scatter into the next bucket order; the
+whole persistent launch for the batch) uses its average launch duration
+measured with HIP events on the stream the kernel runs on, inside the timed
+region.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -28,38 +33,36 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic HBM bytes per particle and pass (particle state read/written
-# once per pass; grid terms are O(cells) and excluded):
-#   mixed 2D2V state: cell int32 + 2 offsets f32 + 2 velocities f32 = 20 B
-#   fp64  2D2V state: 2 positions f64 + 2 velocities f64          = 32 B
-# count pass reads the state; push pass reads it and writes it once.
-STATE_BYTES = {"mixed": 20, "fp64": 32}
+# Algorithmic HBM bytes per particle and pass: the particle state is read
+# once (count pass) or read and written once (push pass); grid terms are
+# O(cells) and excluded.
+#   mixed: cell int32 + dim binary32 offsets + vdim binary32 velocities
+#   fp64 : dim FP64 positions + vdim FP64 velocities
+def state_bytes(precision, dim, vdim):
+    return 4 + 4 * dim + 4 * vdim if precision == "mixed" else 8 * dim + 8 * vdim
 
 
-def kernel_source_sha():
-    p = os.path.join(ROOT, "paper_2608_15249_amd", "csrc", "apic_kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
-
-
-def load_traffic(precision):
+def load_traffic(precision, workload, tile):
     """HBM bytes per push-pass launch from committed rocprofv3 counter runs,
-    if they were taken on the current kernel source; else None."""
-    p = os.path.join(ROOT, "profiles", "step_push_thermal_2d_512_traffic.json")
+    if they were taken on the current kernel source, workload and tile;
+    else None."""
+    p = os.path.join(ROOT, "profiles", "step_push_%s_traffic.json" % workload)
     if not os.path.exists(p):
         return None
+    from paper_2608_15249_amd.rocprof_summary import kernel_source_sha
     try:
         d = json.load(open(p))
         e = d.get(precision)
-        if not e or d.get("kernel_src_sha") != kernel_source_sha():
+        if not e or d.get("kernel_src_sha") != kernel_source_sha() or list(d.get("tile", [])) != list(tile):
             return None
         return float(e["hbm_bytes_per_launch"])
     except Exception:
         return None
 
 
-def run_path(precision, w, state, steps, warmup, torch):
+def run_path(precision, w, state, steps, warmup, tile, torch):
     from paper_2608_15249_amd.sim import Simulation
-    sim = Simulation(w, precision, state=state, tile=(8, 8))
+    sim = Simulation(w, precision, state=state, tile=tile)
     sim.initialise()
     sim.ctx.sync()
     if warmup:
@@ -77,16 +80,18 @@ def run_path(precision, w, state, steps, warmup, torch):
     ms, nprof = sim.ctx.profile_read()
     sim.ctx.profile_enable(0)
     elapsed = t1 - t0
-    sb = STATE_BYTES[precision]
+    sb = state_bytes(precision, w.dim, w.vdim)
     push_ms = ms[2] / max(nprof, 1)
     push_bytes = 2 * sb * n
     achieved = push_bytes / (push_ms * 1e-3) / 1e9
-    traffic = load_traffic(precision)
+    traffic = load_traffic(precision, "%s_%d" % (w.name, w.nx), sim.tile)
     d = diag.cpu().numpy().reshape(steps, 4)
     out = {
         "value": n * steps / elapsed,
         "ms_per_step": 1e3 * elapsed / steps,
         "hbm_gbs_step": (3 * sb * n * steps) / elapsed / 1e9,
+        "tile": list(sim.tile),
+        "tune_ms_per_step": sim.tune_ms,
         "phase_ms_per_step": {"count": ms[0] / nprof, "scan": ms[1] / nprof, "push": push_ms,
                               "field": ms[3] / nprof},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -102,20 +107,105 @@ def run_path(precision, w, state, steps, warmup, torch):
     return out
 
 
+def run_batch(reps, steps, warmup, chunk, torch):
+    """The batched replicas: one graph-replayed persistent launch per step on
+    torch's current stream, timed with HIP events on that stream."""
+    from paper_2608_15249_amd.sim import BatchSimulation
+    bs = BatchSimulation(reps, chunk=chunk)
+    bs.initialise()
+    if warmup:
+        bs.run(warmup, diag=False)
+    bs.batch.sync()
+    n = bs.batch.n_total
+    diag = torch.zeros(steps * len(reps) * 4, dtype=torch.float64, device="cuda")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    bs.batch.step(steps, diag, use_graph=True)
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bs.batch.sync()
+    kern_ms = ev0.elapsed_time(ev1) / steps
+    elapsed = t1 - t0
+    sb = state_bytes("mixed", 1, 1)
+    launch_bytes = 2 * sb * n
+    achieved = launch_bytes / (kern_ms * 1e-3) / 1e9
+    out = {
+        "value": n * steps / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "hbm_gbs_step": launch_bytes * steps / elapsed / 1e9,
+        "chunk": bs.chunk,
+        "tune_ms_per_step": bs.tune_ms,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_batch<step> (gather+Boris+move+deposit+field, all replicas)",
+                     "bytes_per_launch": launch_bytes},
+        "particles": n,
+    }
+    del bs
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, state, nsteps):
     """Serial FP64 oracle on the same plasma (host, one core)."""
     import oracle as O
     x, y, vx, vy, vz = state
-    s = O.Setup(2, 2, w.nx, w.Lx, len(x), w.dt, ny=w.ny, Ly=w.Ly)
-    st = O.State.from_arrays(x, vx, y, vy)
+    s = O.Setup(w.dim, w.vdim, w.nx, w.Lx, len(x), w.dt, ny=w.ny, Ly=w.Ly, bz=w.bz)
+    st = O.State.from_arrays(x, vx, y, vy, vz)
     E, _ = O.initialise(s, st)
     t0 = time.perf_counter()
     for _ in range(nsteps):
         E, _, _ = O.step(s, st, E)
     t1 = time.perf_counter()
     return {"value": len(x) * nsteps / (t1 - t0), "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "full 512x512 / 16,777,216-particle plasma, %d oracle steps (serial C particle loops + "
-                      "numpy FFT, FP64), %.1f s" % (nsteps, t1 - t0)}
+            "sample": "full %dx%d / %d-particle plasma, %d oracle steps (serial C particle loops + numpy FFT, "
+                      "FP64), %.1f s" % (w.nx, w.ny, len(x), nsteps, t1 - t0)}
+
+
+def cpu_baseline_batch(reps, nsteps, target_particles=3_000_000):
+    """Serial FP64 oracle on the first replicas of the ensemble (about
+    target_particles particles in all), each advanced nsteps steps."""
+    import oracle as O
+    from paper_2608_15249_amd import workloads as W
+    done, tot, used = 0, 0.0, 0
+    for rep in reps:
+        if done >= target_particles:
+            break
+        w = W.replica_workload(rep)
+        x, _, vx, _, _ = W.sample(w)
+        s = O.Setup(1, 1, w.nx, w.Lx, len(x), w.dt)
+        st = O.State.from_arrays(x, vx)
+        E, _ = O.initialise(s, st)
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            E, _, _ = O.step(s, st, E)
+        tot += time.perf_counter() - t0
+        done += len(x)
+        used += 1
+    return {"value": done * nsteps / tot, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d replicas (%d particles), %d oracle steps each (serial C particle loops + numpy "
+                      "FFT, FP64), %.1f s" % (used, done, nsteps, tot)}
+
+
+def parse_tile(t):
+    if t == "auto":
+        return "auto"
+    a, b = t.lower().split("x")
+    return (int(a), int(b))
+
+
+WORKLOADS = {
+    "thermal_2d": "thermal_2d: 2D2V Maxwellian plasma, 512x512 cells, 64/cell, 16,777,216 electrons, dt=0.1, CIC, "
+                  "periodic FFT Poisson",
+    "magnetized_2d3v": "magnetized_2d3v: 2D3V Maxwellian plasma in uniform B_z (omega_c/omega_p=2), 1024x1024 cells, "
+                       "32/cell, 33,554,432 electrons, 1% density perturbation at k=(2pi/64,0), dt=0.05, CIC, "
+                       "periodic FFT Poisson",
+    "landau_batch": "landau_batch: 256 independent 1D1V Landau-damping replicas, Nx log-uniform in [32,512], "
+                    "particles log-uniform in [1e4,1e6], Maxwellian v_th=1, k=0.5 perturbation, dt=0.1, CIC",
+}
 
 
 def main():
@@ -126,6 +216,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", default="mixed,fp64")
+    ap.add_argument("--workload", default="thermal_2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--tile", default="auto", help="sort-bucket tile TXxTY, or auto (autotuner)")
+    ap.add_argument("--chunk", default="auto", help="batch work-item size, or auto (autotuner)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (N=%d requested)" % args.gpus,
@@ -134,39 +227,51 @@ def main():
     import torch
     from paper_2608_15249_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    w = W.thermal_2d()
+    common = {"metric": "particle-steps/s (sort+deposit+gather+push), HBM GB/s; mixed vs FP64 path",
+              "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
+    if args.workload == "landau_batch":
+        reps = W.landau_batch()
+        chunk = args.chunk if args.chunk == "auto" else int(args.chunk)
+        print("bench: landau_batch, %d replicas, %d warmup + %d timed steps" % (len(reps), args.warmup, args.steps),
+              file=sys.stderr, flush=True)
+        b = run_batch(reps, args.steps, args.warmup, chunk, torch)
+        line = dict(common)
+        line.update({"value": b["value"], "ms_per_step": b["ms_per_step"], "dtype": "f32+i64",
+                     "config": {"workload": WORKLOADS["landau_batch"], "replicas": len(reps),
+                                "particles": b["particles"], "chunk": b["chunk"], "precision": "mixed"},
+                     "hbm_gbs_step": b["hbm_gbs_step"], "roofline": b["roofline"],
+                     "tune_ms_per_step": b["tune_ms_per_step"]})
+        if not args.no_cpu_baseline:
+            print("bench: cpu baseline (%d oracle steps per replica)" % args.cpu_steps, file=sys.stderr, flush=True)
+            line["cpu_baseline"] = cpu_baseline_batch(reps, args.cpu_steps)
+        print(json.dumps(line), flush=True)
+        return
+    w = getattr(W, args.workload)()
     state = W.sample(w)
+    tile = parse_tile(args.tile)
     res = {}
     for path in args.paths.split(","):
-        print("bench: %s path, %d warmup + %d timed steps" % (path, args.warmup, args.steps), file=sys.stderr,
-              flush=True)
-        res[path] = run_path(path, w, state, args.steps, args.warmup, torch)
+        print("bench: %s, %s path, %d warmup + %d timed steps" % (args.workload, path, args.warmup, args.steps),
+              file=sys.stderr, flush=True)
+        res[path] = run_path(path, w, state, args.steps, args.warmup, tile, torch)
     head = res.get("mixed") or res[list(res)[0]]
-    line = {
-        "metric": "particle-steps/s (sort+deposit+gather+push), HBM GB/s; mixed vs FP64 path",
+    line = dict(common)
+    line.update({
         "value": head["value"],
-        "unit": "particle-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
         "ms_per_step": head["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
         "dtype": "f32+i64" if "mixed" in res else "f64",
-        "data": "synthetic",
-        "config": {"workload": "thermal_2d: 2D2V Maxwellian plasma, 512x512 cells, 64/cell, 16,777,216 electrons, "
-                               "dt=0.1, CIC, periodic FFT Poisson",
-                   "grid": [512, 512], "particles": w.n_particles, "tile": [8, 8],
-                   "precision": "mixed" if "mixed" in res else "fp64"},
+        "config": {"workload": WORKLOADS[args.workload], "grid": [w.nx, w.ny], "particles": w.n_particles,
+                   "tile": head["tile"], "precision": "mixed" if "mixed" in res else "fp64"},
         "hbm_gbs_step": head["hbm_gbs_step"],
         "roofline": head["roofline"],
         "phase_ms_per_step": head["phase_ms_per_step"],
-    }
+        "tune_ms_per_step": head["tune_ms_per_step"],
+    })
     if "fp64" in res and "mixed" in res:
         f = res["fp64"]
         line["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "hbm_gbs_step": f["hbm_gbs_step"],
-                        "roofline": f["roofline"], "phase_ms_per_step": f["phase_ms_per_step"]}
+                        "tile": f["tile"], "roofline": f["roofline"], "phase_ms_per_step": f["phase_ms_per_step"]}
         line["mixed_over_fp64"] = head["value"] / f["value"]
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (%d oracle steps)" % args.cpu_steps, file=sys.stderr, flush=True)

@@ -248,6 +248,29 @@ apic_status apic_batch_step(apic_batch *b, apic_batch_state *st, int nsteps, dou
 apic_status apic_batch_sync_status(apic_batch *b, void *stream);
 const char *apic_batch_last_error(const apic_batch *b);
 
+/* ---- autotuning -------------------------------------------------------------
+ * Setup calls (host, synchronous; they allocate scratch device memory and
+ * contexts of their own and must not run under graph capture). Each times
+ * nsteps steps per candidate on a private copy of the caller's particles
+ * (the caller's arrays are only read), returns the fastest candidate and
+ * its ms per step, and caches the pick for the process: a later call for the
+ * same shape returns the cached pick with *ms_per_step = -1 (may be NULL).
+ * Returns APIC_EINVAL for bad arguments, APIC_EHIP if no candidate ran.
+ *
+ * apic_autotune_tiles: sort-bucket tile (tile_x, tile_y) for apic_create, over
+ *   powers of two 4x4 .. 32x32 (2D) or 8 .. 1024 nodes (1D) plus the default
+ *   (0, 0). p: unsorted or sorted particles as for apic_sort_by_cell (n > 0);
+ *   bucket_start and perm are ignored. Cache key: dim, vdim, nx, ny,
+ *   precision and floor(log2(particles per cell)).
+ * apic_batch_autotune_chunk: work-item size (particles per item, 1024 ..
+ *   65536) for apic_batch_create. st: the packed initial state (cell, ox, vx;
+ *   E is ignored). Cache key: total particles and replica count. */
+apic_status apic_autotune_tiles(const apic_grid_desc *desc, const apic_particles *p, int nsteps, int *tile_x,
+                                int *tile_y, double *ms_per_step, void *stream);
+apic_status apic_batch_autotune_chunk(const apic_replica *reps, int nrep, double dt, double qm, double rho_ion,
+                                      const apic_batch_state *st, int nsteps, int *chunk, double *ms_per_step,
+                                      void *stream);
+
 /* Waits for the stream, then returns and clears the device error flags
  * (APIC_OK, APIC_EDOMAIN or APIC_EOVERFLOW). */
 apic_status apic_sync_status(apic_ctx *ctx, void *stream);

@@ -56,7 +56,7 @@ EXPORTS = ["apic_create", "apic_destroy", "apic_workspace_size", "apic_num_bucke
            "apic_sync_status", "apic_last_error", "apic_profile_enable", "apic_profile_read",
            "apic_batch_create", "apic_batch_destroy", "apic_batch_sizes", "apic_batch_offsets",
            "apic_batch_work_items", "apic_batch_init", "apic_batch_step", "apic_batch_sync_status",
-           "apic_batch_last_error"]
+           "apic_batch_last_error", "apic_autotune_tiles", "apic_batch_autotune_chunk"]
 
 _lib = None
 
@@ -95,6 +95,9 @@ def load_library(path: str = LIB_PATH):
         "apic_batch_step": ([vp, P(BatchStateC), cint, vp, vp, vp, vp, cint], cint),
         "apic_batch_sync_status": ([vp, vp], cint),
         "apic_batch_last_error": ([vp], ctypes.c_char_p),
+        "apic_autotune_tiles": ([P(GridDesc), P(ParticlesC), cint, P(cint), P(cint), P(dbl), vp], cint),
+        "apic_batch_autotune_chunk": ([P(ReplicaC), cint, dbl, dbl, dbl, P(BatchStateC), cint, P(cint), P(dbl), vp],
+                                      cint),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -191,6 +194,18 @@ class Context:
         self._check(self.L.apic_gather_push(self.h, ctypes.byref(s), ctypes.c_void_p(E.data_ptr()),
                                             float(dt_scale), 1 if move else 0, _stream()))
 
+    def autotune_tiles(self, parts: "Particles", nsteps: int = 5):
+        """Fastest sort-bucket tile for this plasma, timed on a copy of
+        `parts` (apic_autotune_tiles). Returns (tile_x, tile_y, ms_per_step);
+        ms_per_step is -1 when the pick came from the process cache."""
+        s = parts.struct()
+        tx, ty, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        st = self.L.apic_autotune_tiles(ctypes.byref(self.desc), ctypes.byref(s), int(nsteps), ctypes.byref(tx),
+                                        ctypes.byref(ty), ctypes.byref(ms), _stream())
+        if st != 0:
+            raise ApicError(st, "apic_autotune_tiles found no runnable tile")
+        return int(tx.value), int(ty.value), float(ms.value)
+
     def step(self, parts: "Particles", E, E32, nsteps, diag=None, rho=None, perm=None):
         s = parts.struct(perm=perm)
         self._check(self.L.apic_step(self.h, ctypes.byref(s), ctypes.c_void_p(_ptr(rho)), ctypes.c_void_p(E.data_ptr()),
@@ -209,7 +224,9 @@ class Batch:
         self.torch = torch
         self.device = torch.device(device)
         self.nrep = len(reps)
+        self.params = (float(dt), float(qm), float(rho_ion))
         arr = (ReplicaC * self.nrep)(*[ReplicaC(int(nx), int(n), float(lx)) for nx, n, lx in reps])
+        self.reps_c = arr
         h = ctypes.c_void_p()
         st = self.L.apic_batch_create(arr, self.nrep, float(dt), float(qm), float(rho_ion), int(chunk),
                                       ctypes.byref(h))
@@ -268,6 +285,19 @@ class Batch:
 
     def work_items(self):
         return int(self.L.apic_batch_work_items(self.h))
+
+    def autotune_chunk(self, nsteps: int = 5):
+        """Fastest work-item size for these replicas, timed on a copy of the
+        uploaded state (apic_batch_autotune_chunk). Returns (chunk, ms_per_step);
+        ms_per_step is -1 when the pick came from the process cache."""
+        st = self._state()
+        ch, ms = ctypes.c_int(), ctypes.c_double()
+        dt, qm, rho_ion = self.params
+        r = self.L.apic_batch_autotune_chunk(self.reps_c, self.nrep, dt, qm, rho_ion, ctypes.byref(st), int(nsteps),
+                                             ctypes.byref(ch), ctypes.byref(ms), _stream())
+        if r != 0:
+            raise ApicError(r, "apic_batch_autotune_chunk found no runnable chunk size")
+        return int(ch.value), float(ms.value)
 
 
 class Particles:

@@ -3,21 +3,39 @@
 Usage:
   python -m paper_2608_15249_amd.rocprof_summary trace <results.db> [--cmd "..."]
   python -m paper_2608_15249_amd.rocprof_summary traffic <fetch.db> <write.db> \
-        --kernel k_step_push --copy-bytes N [--cmd "..."]
+        --kernel k_step_push --copy-bytes N [--cmd "..."] [--tag mixed] \
+        [--merge-into profiles/step_push_<workload>_traffic.json --tile 8x8]
 
 `trace` prints per-kernel call counts and average/total durations. `traffic`
 turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch, summed over the counter
 instances of a dispatch) into HBM bytes per dispatch of the named kernel,
 each scaled by the factor that makes the same counter read the known byte
-count of the plain copy kernel (k_copy_bytes) of the same run.
+count of the plain copy kernel (k_copy_bytes) of the same run. With
+--merge-into the result is stored under its tag in a JSON file together with
+the hash of the step kernels' sources and the bucket tile, which is what the
+benchmark checks before it reports the counted traffic.
 """
 from __future__ import annotations
 
 import argparse
 import collections
+import hashlib
 import json
+import os
 import re
 import sqlite3
+
+_CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+KERNEL_SOURCES = ("apic_kernels.hip", "apic_device.h", "apic_internal.h")
+
+
+def kernel_source_sha() -> str:
+    """Hash of the step kernels' sources (a counter run is valid for these only)."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(_CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def _short(name: str) -> str:
@@ -63,6 +81,8 @@ def main():
     f.add_argument("--copy-bytes", type=float, required=True)
     f.add_argument("--cmd", default="")
     f.add_argument("--tag", default="")
+    f.add_argument("--merge-into", default="")
+    f.add_argument("--tile", default="")
     a = ap.parse_args()
     if a.cmd_name == "trace":
         if a.cmd:
@@ -89,6 +109,25 @@ def main():
         res["kernels"][k] = {"fetch_bytes": fk, "write_bytes": wk, "hbm_bytes_per_launch": fk + wk,
                              "dispatches": len(fe[k])}
     print(json.dumps(res, indent=1))
+    if a.merge_into:
+        sha = kernel_source_sha()
+        tile = [int(v) for v in a.tile.lower().split("x")] if a.tile else []
+        d = {}
+        if os.path.exists(a.merge_into):
+            with open(a.merge_into) as fh:
+                d = json.load(fh)
+            if d.get("kernel_src_sha") != sha or d.get("tile") != tile:
+                d = {}
+        d["kernel_src_sha"] = sha
+        d["tile"] = tile
+        d["note"] = ("HBM bytes per launch of the step kernels; FETCH_SIZE and WRITE_SIZE (KiB per dispatch, "
+                     "summed over counter instances) scaled so that the plain copy kernel k_copy_bytes of the "
+                     "same run reads/writes its known size")
+        main_k = [k for k in res["kernels"]]
+        d[a.tag] = {"hbm_bytes_per_launch": res["kernels"][main_k[0]]["hbm_bytes_per_launch"] if main_k else None,
+                    "detail": res}
+        with open(a.merge_into, "w") as fh:
+            json.dump(d, fh, indent=1)
 
 
 if __name__ == "__main__":

@@ -24,26 +24,41 @@ class Simulation:
         self.w = w
         if state is None:
             state = W.sample(w, n)
-        x, y, vx, vy, vz = state
-        self.n = len(x)
-        self.ctx = Context(dim=w.dim, vdim=w.vdim, nx=w.nx, ny=w.ny, lx=w.Lx, ly=w.Ly, dt=w.dt, n=self.n, bz=w.bz,
-                           precision=precision, frac_bits=frac_bits, tile=tile, device=device)
+        self.n = len(state[0])
+        mk = lambda t: Context(dim=w.dim, vdim=w.vdim, nx=w.nx, ny=w.ny, lx=w.Lx, ly=w.Ly, dt=w.dt, n=self.n,
+                               bz=w.bz, precision=precision, frac_bits=frac_bits, tile=t, device=device)
+        self.tune_ms = None
+        if tile == "auto":
+            # time the candidate tiles on this very state, then build the context with the pick
+            ctx = mk((0, 0))
+            p = Particles(ctx)
+            self._upload(p, ctx.mixed, state)
+            tx, ty, self.tune_ms = ctx.autotune_tiles(p)
+            tile = (tx, ty)
+            del p, ctx
+        self.tile = tuple(tile)
+        self.ctx = mk(self.tile)
         self.mixed = self.ctx.mixed
         self.p = Particles(self.ctx)
-        if self.mixed:
-            ix, ox = W.to_cell_offset(x, w.dx, w.nx)
-            iy = oy = None
-            if w.dim == 2:
-                iy, oy = W.to_cell_offset(y, w.dy, w.ny)
-            self.p.upload(cell=W.pack_cell(ix, iy), ox=ox, oy=oy, vx=vx, vy=vy, vz=vz)
-        else:
-            self.p.upload(x=x, y=y, vx=vx, vy=vy, vz=vz)
+        self._upload(self.p, self.mixed, state)
         dev = self.ctx.device
         G = self.ctx.G
         self.E = torch.zeros(w.dim * G, dtype=torch.float64, device=dev)
         self.E32 = torch.zeros(w.dim * G, dtype=torch.float32, device=dev) if self.mixed else None
         self.rho = torch.zeros(G, dtype=torch.int64 if self.mixed else torch.float64, device=dev)
         self.we0 = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    def _upload(self, p, mixed, state):
+        w = self.w
+        x, y, vx, vy, vz = state
+        if mixed:
+            ix, ox = W.to_cell_offset(x, w.dx, w.nx)
+            iy = oy = None
+            if w.dim == 2:
+                iy, oy = W.to_cell_offset(y, w.dy, w.ny)
+            p.upload(cell=W.pack_cell(ix, iy), ox=ox, oy=oy, vx=vx, vy=vy, vz=vz)
+        else:
+            p.upload(x=x, y=y, vx=vx, vy=vy, vz=vz)
 
     def initialise(self):
         c = self.ctx
@@ -85,7 +100,7 @@ class BatchSimulation:
         self.replicas = list(replicas)
         ws = [W.replica_workload(r) for r in self.replicas]
         self.workloads = ws
-        self.batch = Batch([(w.nx, w.n_particles, w.Lx) for w in ws], dt, chunk=chunk, device=device)
+        reps = [(w.nx, w.n_particles, w.Lx) for w in ws]
         cells, offs, vels = [], [], []
         for i, w in enumerate(ws):
             if states is not None:
@@ -96,7 +111,16 @@ class BatchSimulation:
             cells.append(c)
             offs.append(o)
             vels.append(vx)
-        self.batch.upload(np.concatenate(cells), np.concatenate(offs), np.concatenate(vels))
+        packed = (np.concatenate(cells), np.concatenate(offs), np.concatenate(vels))
+        self.tune_ms = None
+        if chunk == "auto":
+            b = Batch(reps, dt, chunk=0, device=device)
+            b.upload(*packed)
+            chunk, self.tune_ms = b.autotune_chunk()
+            del b
+        self.chunk = int(chunk)
+        self.batch = Batch(reps, dt, chunk=self.chunk, device=device)
+        self.batch.upload(*packed)
 
     def initialise(self):
         self.batch.init()

@@ -147,3 +147,21 @@ def test_batch_landau_damping(torch):
         om = np.pi / np.mean(np.diff(t[pk]))
         assert abs(gam / th.imag - 1) < 0.12, (r, gam, th)
         assert abs(om / th.real - 1) < 0.03, (r, om, th)
+
+
+def test_batch_autotune_chunk_picks_a_candidate_and_keeps_results(torch):
+    """The tuner returns one of its candidates, caches it, and the batch built
+    with the pick gives the same particle and field bits as any other chunk."""
+    from paper_2608_15249_amd.sim import BatchSimulation
+    a = BatchSimulation(REPS, chunk="auto")
+    assert a.chunk in (1024, 2048, 4096, 8192, 16384, 32768, 65536)
+    assert a.tune_ms is not None and a.tune_ms > 0
+    again = BatchSimulation(REPS, chunk="auto")
+    assert again.chunk == a.chunk and again.tune_ms == -1.0   # process cache
+    b = BatchSimulation(REPS, chunk=1024 if a.chunk != 1024 else 4096)
+    for s in (a, b):
+        s.initialise()
+        s.run(5)
+        s.batch.sync()
+    for f in ("E", "cell", "ox", "vx"):
+        assert torch.equal(getattr(a.batch, f), getattr(b.batch, f)), f

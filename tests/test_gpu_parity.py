@@ -438,3 +438,30 @@ def test_nan_particle_reports_domain_error(torch):
         c.sync()
     assert ei.value.status == -5
     c.sync()  # flag cleared
+
+
+def test_autotuned_tile_gives_the_same_plasma(torch):
+    """apic_autotune_tiles picks one of its candidate tiles (or the default),
+    caches the pick, and the mixed step with that tile advances the particle
+    set and the field to the same bits as a fixed 8x8 tile."""
+    from paper_2608_15249_amd.sim import Simulation
+    w = W.thermal_2d(nx=64, ppc=16)
+    state = W.sample(w)
+    a = Simulation(w, "mixed", state=state, tile="auto")
+    assert a.tile in [(4, 4), (8, 4), (8, 8), (16, 8), (16, 16), (32, 16), (32, 32), (0, 0)]
+    assert a.tune_ms > 0
+    again = Simulation(w, "mixed", state=state, tile="auto")
+    assert again.tile == a.tile and again.tune_ms == -1.0
+    b = Simulation(w, "mixed", state=state, tile=(8, 8))
+    for s in (a, b):
+        s.initialise()
+        s.run(4)
+        s.ctx.sync()
+    assert np.array_equal(a.field()[0], b.field()[0]) and np.array_equal(a.field()[1], b.field()[1])
+    sa, sb = a.state(), b.state()
+    ka = np.lexsort((sa["vy"].view(np.uint32), sa["vx"].view(np.uint32), sa["oy"].view(np.uint32),
+                     sa["ox"].view(np.uint32), sa["cell"]))
+    kb = np.lexsort((sb["vy"].view(np.uint32), sb["vx"].view(np.uint32), sb["oy"].view(np.uint32),
+                     sb["ox"].view(np.uint32), sb["cell"]))
+    for f in ("cell", "ox", "oy", "vx", "vy"):
+        assert np.array_equal(sa[f][ka], sb[f][kb]), f
