@@ -16,7 +16,8 @@
  * Conventions shared by all entry points
  *   - Pointers marked [dev] are device (HBM) pointers on the current HIP
  *     device; [host] are host pointers. No entry point allocates device memory
- *     after apic_create.
+ *     after apic_create / apic_batch_create, except the autotuning setup calls
+ *     (apic_autotune_tiles, apic_batch_autotune_chunk).
  *   - All work is enqueued asynchronously on the given hipStream_t (pass the
  *     stream as void*; NULL = default stream). Argument errors are detected on
  *     the host and returned synchronously, before anything is enqueued.
@@ -193,6 +194,60 @@ apic_status apic_step(apic_ctx *ctx, apic_particles *p, void *rho, double *E, fl
  * number of profiled steps, then rearms. Steps beyond max_steps are not timed. */
 apic_status apic_profile_enable(apic_ctx *ctx, int max_steps);
 apic_status apic_profile_read(apic_ctx *ctx, double ms[4], int *steps);
+
+/* Convert a physical FP64 state to the context's particle representation (any
+ * order): x, y [dev, double, n] positions (y NULL in 1D), vx, vy, vz [dev,
+ * double, n] velocities (NULL beyond vdim). FP64 path: copies into p->x, p->y,
+ * p->vx.. ; mixed path: p->cell = floor(x/dx) (mod nx; packed with iy in 2D),
+ * p->ox = binary32(x/dx - floor(x/dx)), an offset that rounds to 1 moving to
+ * the next cell with offset 0, velocities rounded to binary32. Positions must
+ * lie in [0, L] (L is node 0); a coordinate outside raises APIC_EDOMAIN at the
+ * next apic_sync_status. p->bucket_start and p->perm are not touched. */
+apic_status apic_import_state(apic_ctx *ctx, const double *x, const double *y, const double *vx, const double *vy,
+                              const double *vz, apic_particles *p, void *stream);
+
+/* ---- adjoint (a10) ----------------------------------------------------------
+ * Gradient of the final field energy W = 1/2 sum_j |E_j^T|^2 dV of an
+ * nsteps-step run with respect to every particle's initial position and
+ * velocity (reverse-mode derivative of the discrete cycle; the paper has no
+ * adjoint). The run is the cycle of the two-stream driver: sort, deposit,
+ * Poisson -> E^0, backward half push v^0 -> v^{-1/2}, then nsteps apic_step
+ * cycles. Reverse of each step: move (lam_v += dt lam_x), Boris (transpose of
+ * its linear map in (v, E_p)), gather (adjoint = scatter of lam_Ep into a grid
+ * lam_E, plus the field-slope term), Poisson (lam_rho = A^T lam_E, the same
+ * FFT solve with the conjugate symbol), deposit (adjoint = gather of the slope
+ * of lam_rho), sort (each step's permutation inverted). The derivative of the
+ * CIC hat is its slope inside the particle's cell.
+ *
+ * Step checkpointing: apic_adjoint_forward stores the state every `stride`
+ * steps in the caller's checkpoint buffer; apic_step_adjoint recomputes one
+ * segment of at most `stride` steps at a time from its checkpoint and walks it
+ * backwards. Memory: ckpt_bytes ~ (nsteps/stride + 1) states; ws_bytes holds
+ * the context workspace plus `stride` per-step snapshots (positions, sort
+ * permutation, E) and the lam arrays.
+ *
+ * Precision: the mixed path runs the per-particle adjoint in binary32, the
+ * FP64 path in FP64; grid adjoints are FP64 in both (accumulated with atomics,
+ * so FP64 gradients are reproducible to rounding, not bitwise). */
+
+/* Bytes of the checkpoint buffer and of the adjoint workspace. */
+apic_status apic_adjoint_sizes(const apic_ctx *ctx, int nsteps, int stride, size_t *ckpt_bytes, size_t *ws_bytes);
+
+/* Forward run with checkpoints. p0: the initial state (x^0, v^0) in the
+ * context's representation, any order, read only (bucket_start and perm
+ * ignored). ckpt [dev, ckpt_bytes], ws [dev, ws_bytes]: caller-owned.
+ * W [dev, double, 1]: W_E(T), may be NULL. E_out [dev, double, dim*G]: E^T,
+ * may be NULL. nsteps >= 0, stride >= 1. */
+apic_status apic_adjoint_forward(apic_ctx *ctx, const apic_particles *p0, int nsteps, int stride, void *ckpt,
+                                 double *W, double *E_out, void *ws, void *stream);
+
+/* Reverse sweep over the checkpoints of the last apic_adjoint_forward with the
+ * same nsteps and stride (ws contents between the two calls are not needed).
+ * Writes seed * dW/d(state at t = 0) in the input order of p0, as FP64:
+ * lam_x, lam_y [dev, n] (lam_y NULL in 1D) with respect to positions,
+ * lam_vx, lam_vy, lam_vz [dev, n] (NULL beyond vdim) with respect to v^0. */
+apic_status apic_step_adjoint(apic_ctx *ctx, const void *ckpt, int nsteps, int stride, double seed, double *lam_x,
+                              double *lam_y, double *lam_vx, double *lam_vy, double *lam_vz, void *ws, void *stream);
 
 /* ---- batched replicas (a9) ------------------------------------------------
  * Many independent 1D1V periodic electrostatic plasmas ("replicas") with

@@ -56,7 +56,8 @@ EXPORTS = ["apic_create", "apic_destroy", "apic_workspace_size", "apic_num_bucke
            "apic_sync_status", "apic_last_error", "apic_profile_enable", "apic_profile_read",
            "apic_batch_create", "apic_batch_destroy", "apic_batch_sizes", "apic_batch_offsets",
            "apic_batch_work_items", "apic_batch_init", "apic_batch_step", "apic_batch_sync_status",
-           "apic_batch_last_error", "apic_autotune_tiles", "apic_batch_autotune_chunk"]
+           "apic_batch_last_error", "apic_autotune_tiles", "apic_batch_autotune_chunk",
+           "apic_import_state", "apic_adjoint_sizes", "apic_adjoint_forward", "apic_step_adjoint"]
 
 _lib = None
 
@@ -95,6 +96,10 @@ def load_library(path: str = LIB_PATH):
         "apic_batch_step": ([vp, P(BatchStateC), cint, vp, vp, vp, vp, cint], cint),
         "apic_batch_sync_status": ([vp, vp], cint),
         "apic_batch_last_error": ([vp], ctypes.c_char_p),
+        "apic_import_state": ([vp, vp, vp, vp, vp, vp, P(ParticlesC), vp], cint),
+        "apic_adjoint_sizes": ([vp, cint, cint, P(ctypes.c_size_t), P(ctypes.c_size_t)], cint),
+        "apic_adjoint_forward": ([vp, P(ParticlesC), cint, cint, vp, vp, vp, vp, vp], cint),
+        "apic_step_adjoint": ([vp, vp, cint, cint, dbl, vp, vp, vp, vp, vp, vp, vp], cint),
         "apic_autotune_tiles": ([P(GridDesc), P(ParticlesC), cint, P(cint), P(cint), P(dbl), vp], cint),
         "apic_batch_autotune_chunk": ([P(ReplicaC), cint, dbl, dbl, dbl, P(BatchStateC), cint, P(cint), P(dbl), vp],
                                       cint),
@@ -205,6 +210,32 @@ class Context:
         if st != 0:
             raise ApicError(st, "apic_autotune_tiles found no runnable tile")
         return int(tx.value), int(ty.value), float(ms.value)
+
+    def import_state(self, parts: "Particles", x, y, vx, vy=None, vz=None):
+        """Physical FP64 device state -> this context's representation (apic_import_state)."""
+        s = parts.struct()
+        self._check(self.L.apic_import_state(self.h, ctypes.c_void_p(_ptr(x)), ctypes.c_void_p(_ptr(y)),
+                                             ctypes.c_void_p(_ptr(vx)), ctypes.c_void_p(_ptr(vy)),
+                                             ctypes.c_void_p(_ptr(vz)), ctypes.byref(s), _stream()))
+
+    def adjoint_sizes(self, nsteps: int, stride: int):
+        ck, ws = ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(self.L.apic_adjoint_sizes(self.h, int(nsteps), int(stride), ctypes.byref(ck), ctypes.byref(ws)))
+        return int(ck.value), int(ws.value)
+
+    def adjoint_forward(self, parts: "Particles", nsteps, stride, ckpt, ws, W=None, E_out=None):
+        s = parts.struct()
+        self._check(self.L.apic_adjoint_forward(self.h, ctypes.byref(s), int(nsteps), int(stride),
+                                                ctypes.c_void_p(ckpt.data_ptr()), ctypes.c_void_p(_ptr(W)),
+                                                ctypes.c_void_p(_ptr(E_out)), ctypes.c_void_p(ws.data_ptr()),
+                                                _stream()))
+
+    def step_adjoint(self, ckpt, nsteps, stride, ws, lam_x, lam_y, lam_vx, lam_vy=None, lam_vz=None, seed=1.0):
+        self._check(self.L.apic_step_adjoint(self.h, ctypes.c_void_p(ckpt.data_ptr()), int(nsteps), int(stride),
+                                             float(seed), ctypes.c_void_p(_ptr(lam_x)), ctypes.c_void_p(_ptr(lam_y)),
+                                             ctypes.c_void_p(_ptr(lam_vx)), ctypes.c_void_p(_ptr(lam_vy)),
+                                             ctypes.c_void_p(_ptr(lam_vz)), ctypes.c_void_p(ws.data_ptr()),
+                                             _stream()))
 
     def step(self, parts: "Particles", E, E32, nsteps, diag=None, rho=None, perm=None):
         s = parts.struct(perm=perm)

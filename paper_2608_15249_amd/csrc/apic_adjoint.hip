@@ -1,0 +1,838 @@
+// Reverse-mode derivative (adjoint) of the PIC cycle: the gradient of the
+// final field energy W = 1/2 sum_j |E_j^T|^2 dV with respect to every
+// particle's initial position and velocity, with step checkpointing.
+//
+// The forward map is the cycle the library runs: field of the initial charge,
+// backward half push, then per step gather -> Boris -> move -> deposit ->
+// sort -> Poisson. Adjoint of each module (lam_* = dW/d*):
+//   field    E = A rho with A circulant and odd (symbol -i kappa/K^2):
+//            lam_rho = A^T lam_E = -sum_d A_d lam_E_d (symbol +i kappa/K^2);
+//   deposit  lam_x += (Q/dV) sum_j lam_rho_j dW_j/dx  (a gradient gather);
+//   gather   lam_E += scatter of W_j lam_Ep, lam_x += sum_j dW_j/dx E_j.lam_Ep;
+//   Boris    linear for fixed B: lam_v_old = R^T lam_v, lam_Ep = a (R+I)^T lam_v;
+//   move     lam_v^{n+1/2} += dt lam_x^{n+1} (the wrap has slope one);
+//   sort     a permutation: each reverse step sends lam back to the order the
+//            particles had before that step (perm from the forward step).
+// dW/dx of the CIC hat is its slope inside the particle's cell.
+//
+// Checkpointing: the forward run stores the state every `stride` steps
+// (positions, v^{n-1/2}, bucket table, E^n, and each particle's index in the
+// caller's input order). The reverse sweep recomputes one segment at a time
+// from its checkpoint, keeping per-step positions, E^n and the sort
+// permutation of the segment, and walks it backwards. Particle order at a
+// segment's end may differ between the recomputation and the stored next
+// checkpoint (far movers take slots in arrival order; FP64 rounding), so the
+// step that crosses a checkpoint maps particles through their input indices.
+//
+// Arithmetic: the per-particle adjoint runs in the path's precision (binary32
+// for the mixed path, FP64 otherwise); grid adjoints accumulate in FP64 with
+// global atomics (their summation order is not fixed, so FP64 gradients
+// reproduce to rounding, not bitwise); the adjoint field solve is FP64.
+#include "apic.h"
+#include "apic_ctx.h"
+#include "apic_device.h"
+
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+#include <utility>
+
+using namespace apic;
+using namespace apic_host;
+
+namespace apic {
+namespace {
+
+inline int nblocks(int64_t n, int cap = 8192) {
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    return (int)(b > cap ? cap : b);
+}
+
+// Positions of one time level (structure of arrays of the path's layout).
+struct PosP {
+    const int32_t *cell;
+    const float *ox, *oy;
+    const double *x, *y;
+};
+
+template <typename R>
+struct AdjP {
+    Geo g;
+    int64_t n;
+    // level n: positions, field, lam_rho; lam arrays in the level-n order
+    PosP pos;
+    const double *E;        // [dim][G]
+    const double *lrho;     // [G]
+    const R *lxp_in;        // [dim][n]  lam_x carried from level n+1
+    const R *lep_in;        // [dim][n]  lam_Ep of the push at level n
+    const R *lv_in;         // [vdim][n] lam of v^{n-1/2}
+    int terminal;           // the three inputs above are zero
+    // reverse step n-1 (back != 0): lam in the level-(n-1) order
+    int back;
+    const int32_t *perm;    // level-n slot i came from level-(n-1) slot perm[i]
+    PosP prev;
+    double *lE_prev;        // [dim][G] accumulated with atomics
+    R *lxp_out, *lep_out, *lv_out;
+    int init;               // level n-1 is 0: add the backward half push
+    // final output (level 0): out[id0[i]] = lam of particle i
+    int final_out;
+    const int32_t *id0;
+    double *out_x, *out_y, *out_vx, *out_vy, *out_vz;
+    // coefficients
+    R dt, cq;               // dt; Q/dV
+    R a, t, s;              // Boris of a full step
+    R ah, th, sh;           // Boris of the backward half step
+    int *err;
+};
+
+template <bool MIX, int DIM>
+__device__ __forceinline__ bool load_pos(const PosP &p, int64_t i, const Geo &g, int &ix, int &iy,
+                                         typename RealOf<MIX>::T &fx, typename RealOf<MIX>::T &fy) {
+    using R = typename RealOf<MIX>::T;
+    bool ok = true;
+    if constexpr (MIX) {
+        const int32_t c = p.cell[i];
+        ix = (DIM == 2) ? (c & 0xFFFF) : c;
+        iy = (DIM == 2) ? (c >> 16) : 0;
+        fx = p.ox[i];
+        fy = (DIM == 2) ? p.oy[i] : 0.0f;
+        ok = ix >= 0 && ix < g.nx && iy >= 0 && iy < g.ny && fx >= 0.0f && fx < 1.0f && fy >= 0.0f && fy < 1.0f;
+    } else {
+        double f;
+        ok = cell_f64(p.x[i], g.inv_dx, g.nx, ix, f);
+        fx = (R)f;
+        iy = 0;
+        fy = R(0);
+        if constexpr (DIM == 2) {
+            ok = cell_f64(p.y[i], g.inv_dy, g.ny, iy, f) && ok;
+            fy = (R)f;
+        }
+    }
+    if (!ok) {
+        ix = iy = 0;
+        fx = fy = R(0);
+    }
+    return ok;
+}
+
+// lam^T (R + I)-type Boris adjoint for one velocity advance:
+// g (lam of v_new, x/y) -> lam of v_old; returns lam_Ep in ex, ey.
+template <typename R, int VDIM>
+__device__ __forceinline__ void boris_adj(R &gx, R &gy, R a, R t, R s, R &ex, R &ey) {
+    if constexpr (VDIM == 1) {
+        ex = R(2) * a * gx;
+        ey = R(0);
+    } else {
+        const R r = R(1) - s * t;
+        const R ox = r * gx - s * gy;   // R^T g, R = [[r, s], [-s, r]]
+        const R oy = s * gx + r * gy;
+        ex = a * (ox + gx);
+        ey = a * (oy + gy);
+        gx = ox;
+        gy = oy;
+    }
+}
+
+template <bool MIX, int DIM, int VDIM>
+__global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>::T> P) {
+    using R = typename RealOf<MIX>::T;
+    const Geo &g = P.g;
+    const int64_t n = P.n;
+    const int G = g.nx * g.ny;
+    const R idx = (R)g.inv_dx, idy = (R)g.inv_dy;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int ix, iy;
+        R fx, fy;
+        if (!load_pos<MIX, DIM>(P.pos, i, g, ix, iy, fx, fy)) raise_err(P.err, ERR_DOMAIN);
+        R lx = R(0), ly = R(0), lex = R(0), ley = R(0), lvx = R(0), lvy = R(0), lvz = R(0);
+        if (!P.terminal) {
+            lx = P.lxp_in[i];
+            lex = P.lep_in[i];
+            lvx = P.lv_in[i];
+            if constexpr (DIM == 2) {
+                ly = P.lxp_in[n + i];
+                ley = P.lep_in[n + i];
+            }
+            if constexpr (VDIM >= 2) lvy = P.lv_in[n + i];
+            if constexpr (VDIM >= 3) lvz = P.lv_in[2 * n + i];
+        }
+        // deposit and gather adjoints at level n: slope of the hat applied to
+        // g_j = E_j . lam_Ep + (Q/dV) lam_rho_j over the particle's cell
+        int ip = ix + 1;
+        if (ip >= g.nx) ip = 0;
+        if constexpr (DIM == 1) {
+            const R g0 = (R)P.E[ix] * lex + P.cq * (R)P.lrho[ix];
+            const R g1 = (R)P.E[ip] * lex + P.cq * (R)P.lrho[ip];
+            lx += (g1 - g0) * idx;
+        } else {
+            int jp = iy + 1;
+            if (jp >= g.ny) jp = 0;
+            const int a00 = iy * g.nx + ix, a10 = iy * g.nx + ip, a01 = jp * g.nx + ix, a11 = jp * g.nx + ip;
+            const R g00 = (R)P.E[a00] * lex + (R)P.E[G + a00] * ley + P.cq * (R)P.lrho[a00];
+            const R g10 = (R)P.E[a10] * lex + (R)P.E[G + a10] * ley + P.cq * (R)P.lrho[a10];
+            const R g01 = (R)P.E[a01] * lex + (R)P.E[G + a01] * ley + P.cq * (R)P.lrho[a01];
+            const R g11 = (R)P.E[a11] * lex + (R)P.E[G + a11] * ley + P.cq * (R)P.lrho[a11];
+            lx += ((R(1) - fy) * (g10 - g00) + fy * (g11 - g01)) * idx;
+            ly += ((R(1) - fx) * (g01 - g00) + fx * (g11 - g10)) * idy;
+        }
+        if (P.final_out) {
+            const int32_t o = P.id0[i];
+            if ((uint32_t)o >= (uint32_t)n) {
+                raise_err(P.err, ERR_ORDER);
+                continue;
+            }
+            P.out_x[o] = (double)lx;
+            if constexpr (DIM == 2) P.out_y[o] = (double)ly;
+            P.out_vx[o] = (double)lvx;
+            if constexpr (VDIM >= 2) P.out_vy[o] = (double)lvy;
+            if constexpr (VDIM >= 3) P.out_vz[o] = (double)lvz;
+            continue;
+        }
+        if (!P.back) continue;
+        // reverse of the step n-1 -> n: move, then Boris
+        R gx = lvx + P.dt * lx;
+        R gy = (DIM == 2) ? lvy + P.dt * ly : lvy;
+        R ex, ey;
+        boris_adj<R, VDIM>(gx, gy, P.a, P.t, P.s, ex, ey);
+        if (P.init) {
+            // v^{-1/2} = Boris(v^0, E_p^0, -dt/2) uses the same E_p^0
+            R hx, hy;
+            boris_adj<R, VDIM>(gx, gy, P.ah, P.th, P.sh, hx, hy);
+            ex += hx;
+            ey += hy;
+        }
+        const int32_t j = P.perm[i];
+        if ((uint32_t)j >= (uint32_t)n) {
+            raise_err(P.err, ERR_ORDER);
+            continue;
+        }
+        int jx, jy;
+        R qx, qy;
+        if (!load_pos<MIX, DIM>(P.prev, j, g, jx, jy, qx, qy)) raise_err(P.err, ERR_DOMAIN);
+        // gather adjoint at level n-1: scatter W_j(x^{n-1}) lam_Ep into lam_E
+        int jxp = jx + 1;
+        if (jxp >= g.nx) jxp = 0;
+        if constexpr (DIM == 1) {
+            unsafeAtomicAdd(&P.lE_prev[jx], (double)((R(1) - qx) * ex));
+            unsafeAtomicAdd(&P.lE_prev[jxp], (double)(qx * ex));
+        } else {
+            int jyp = jy + 1;
+            if (jyp >= g.ny) jyp = 0;
+            const R w00 = (R(1) - qx) * (R(1) - qy), w10 = qx * (R(1) - qy);
+            const R w01 = (R(1) - qx) * qy, w11 = qx * qy;
+            const int b00 = jy * g.nx + jx, b10 = jy * g.nx + jxp, b01 = jyp * g.nx + jx, b11 = jyp * g.nx + jxp;
+            unsafeAtomicAdd(&P.lE_prev[b00], (double)(w00 * ex));
+            unsafeAtomicAdd(&P.lE_prev[b10], (double)(w10 * ex));
+            unsafeAtomicAdd(&P.lE_prev[b01], (double)(w01 * ex));
+            unsafeAtomicAdd(&P.lE_prev[b11], (double)(w11 * ex));
+            unsafeAtomicAdd(&P.lE_prev[G + b00], (double)(w00 * ey));
+            unsafeAtomicAdd(&P.lE_prev[G + b10], (double)(w10 * ey));
+            unsafeAtomicAdd(&P.lE_prev[G + b01], (double)(w01 * ey));
+            unsafeAtomicAdd(&P.lE_prev[G + b11], (double)(w11 * ey));
+        }
+        P.lxp_out[j] = lx;
+        P.lep_out[j] = ex;
+        P.lv_out[j] = gx;
+        if constexpr (DIM == 2) {
+            P.lxp_out[n + j] = ly;
+            P.lep_out[n + j] = ey;
+        }
+        if constexpr (VDIM >= 2) P.lv_out[n + j] = gy;
+        if constexpr (VDIM >= 3) P.lv_out[2 * n + j] = lvz;   // no E_z and no z motion
+    }
+}
+
+// Physical FP64 state -> the path's representation (see apic_import_state).
+template <bool MIX, int DIM, int VDIM>
+__global__ void k_import(Geo g, int64_t n, double dx, double dy, const double *x, const double *y, const double *vx,
+                         const double *vy, const double *vz, Parts out, int *err) {
+    using R = typename RealOf<MIX>::T;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double xi = x[i];
+        const double yi = (DIM == 2) ? y[i] : 0.0;
+        // x = L (a wrap that rounded up) is the same node as x = 0
+        if (!(xi >= 0.0 && xi <= g.lx) || (DIM == 2 && !(yi >= 0.0 && yi <= g.ly))) raise_err(err, ERR_DOMAIN);
+        if constexpr (MIX) {
+            auto split = [](double v, double d, int nn, int &c, float &o) {
+                const double q = v / d;
+                double fl = floor(q);
+                o = (float)(q - fl);
+                if (o >= 1.0f) {
+                    o = 0.0f;
+                    fl += 1.0;
+                }
+                long long ci = (long long)fl % nn;
+                if (ci < 0) ci += nn;
+                c = (int)ci;
+            };
+            int cx, cy = 0;
+            float ox, oy = 0.0f;
+            split(isfinite(xi) ? xi : 0.0, dx, g.nx, cx, ox);
+            if constexpr (DIM == 2) split(isfinite(yi) ? yi : 0.0, dy, g.ny, cy, oy);
+            out.cell[i] = (DIM == 2) ? ((cy << 16) | cx) : cx;
+            out.ox[i] = ox;
+            if constexpr (DIM == 2) out.oy[i] = oy;
+        } else {
+            out.x[i] = xi;
+            if constexpr (DIM == 2) out.y[i] = yi;
+        }
+        ((R *)out.vx)[i] = (R)vx[i];
+        if constexpr (VDIM >= 2) ((R *)out.vy)[i] = (R)vy[i];
+        if constexpr (VDIM >= 3) ((R *)out.vz)[i] = (R)vz[i];
+    }
+}
+
+// out[i] = src[perm[i]] (input index carried through one forward step)
+__global__ void k_adj_compose_ids(int64_t n, const int32_t *src, const int32_t *perm, int32_t *out, int *err) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t p = perm[i];
+        if ((uint32_t)p >= (uint32_t)n) {
+            raise_err(err, ERR_ORDER);
+            out[i] = 0;
+            continue;
+        }
+        out[i] = src[p];
+    }
+}
+
+// inv[id[k]] = k
+__global__ void k_adj_invert(int64_t n, const int32_t *id, int32_t *inv, int *err) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t o = id[k];
+        if ((uint32_t)o >= (uint32_t)n) {
+            raise_err(err, ERR_ORDER);
+            continue;
+        }
+        inv[o] = (int32_t)k;
+    }
+}
+
+// out[i] = perm_last[inv[id_next[i]]]: the level-(e-1) slot of the particle
+// that sits in slot i of the stored level-e order
+__global__ void k_adj_cross_perm(int64_t n, const int32_t *id_next, const int32_t *inv, const int32_t *perm_last,
+                                 int32_t *out, int *err) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t o = id_next[i];
+        int32_t r = 0;
+        if ((uint32_t)o < (uint32_t)n) {
+            const int32_t k = inv[o];
+            if ((uint32_t)k < (uint32_t)n) r = perm_last[k];
+            else raise_err(err, ERR_ORDER);
+        } else {
+            raise_err(err, ERR_ORDER);
+        }
+        out[i] = r;
+    }
+}
+
+__global__ void k_adj_scale(int64_t m, const double *src, double *dst, double scale) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = scale * src[i];
+}
+
+__global__ void k_adj_fill(int64_t m, double *dst) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = 0.0;
+}
+
+// lam_rho_hat = norm * (i kappa_x lam_Ex_hat + i kappa_y lam_Ey_hat) / K^2, 0 at k = 0
+__global__ void k_adj_spectral(Geo g, const double2 *lxh, const double2 *lyh, double2 *lrh, CtxDev c) {
+    const int hx = g.nx / 2 + 1;
+    const int64_t tot = (int64_t)hx * g.ny;
+    const double norm = 1.0 / ((double)g.nx * (double)g.ny);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int kx = (int)(i % hx), ky = (int)(i / hx);
+        const double K2 = c.kx2[kx] + c.ky2[ky];
+        const double inv = (kx == 0 && ky == 0) ? 0.0 : norm / K2;
+        const double2 a = lxh[i], b = lyh[i];
+        const double kax = c.kapx[kx], kay = c.kapy[ky];
+        // i * kappa * (re + i im) = -kappa * im + i kappa * re
+        lrh[i] = make_double2(-(kax * a.y + kay * b.y) * inv, (kax * a.x + kay * b.x) * inv);
+    }
+}
+
+// 1D: lam_rho = -A lam_E with A the same Gauss-law solve as the forward field
+__global__ void __launch_bounds__(kBlock) k_adj_field1d(int nx, const double *lE, double dx, double *lrho) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *sr = (double *)smem;
+    __shared__ double sRed[kWaves];
+    __shared__ double sScan[kBlock];
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) sr[i] = lE[i];
+    __syncthreads();
+    (void)field1d_block(sr, nx, dx, lrho, nullptr, sRed, sScan);
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) lrho[i] = -lrho[i];
+}
+
+// W = 1/2 dV sum_i E_i^2 in a fixed order (one workgroup)
+__global__ void __launch_bounds__(1024) k_adj_energy(int64_t m, const double *E, double dV, double *W) {
+    __shared__ double sRed[16];
+    double p = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) p += E[i] * E[i];
+    p = block_sum(p, sRed);
+    if (threadIdx.x == 0) *W = 0.5 * dV * p;
+}
+
+}  // namespace
+}  // namespace apic
+
+namespace {
+
+// ---- layout of the checkpoint buffer and of the adjoint workspace ---------
+
+struct CkLayout {
+    size_t pos[3];      // mixed: cell, ox, oy; FP64: x, y (-1 = absent)
+    size_t vel[3];
+    size_t bstart, E, id;
+    size_t bytes;       // one checkpoint
+};
+
+CkLayout ck_layout(const apic_ctx *c) {
+    CkLayout L;
+    const int64_t n = c->n;
+    const size_t r = c->mixed ? 4 : 8;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    size_t off = 0;
+    auto take = [&](size_t b) { size_t o = off; off = align256(off + b); return o; };
+    for (auto &v : L.pos) v = (size_t)-1;
+    for (auto &v : L.vel) v = (size_t)-1;
+    if (c->mixed) {
+        L.pos[0] = take(4 * n);
+        L.pos[1] = take(4 * n);
+        if (c->d.dim == 2) L.pos[2] = take(4 * n);
+    } else {
+        L.pos[0] = take(8 * n);
+        if (c->d.dim == 2) L.pos[1] = take(8 * n);
+    }
+    for (int k = 0; k < c->d.vdim; ++k) L.vel[k] = take(r * n);
+    L.bstart = take(4 * (c->g.nbuckets + 1));
+    L.E = take(8 * (size_t)c->d.dim * G);
+    L.id = take(4 * n);
+    L.bytes = off;
+    return L;
+}
+
+struct AdjWs {
+    size_t ctx;                 // the context workspace (sort, step, field solve)
+    size_t pw_pos[3], pw_vel[3], bstart, E, E32, rho;
+    size_t id_a, id_b, inv, cross;
+    size_t snap_pos;            // stride entries of positions
+    size_t snap_pos_bytes;
+    size_t snap_perm, snap_E;   // stride entries
+    size_t lam[2][3];           // ping-pong: lam_x carried, lam_Ep, lam_v
+    size_t lE, lrho, W;
+    size_t bytes;
+};
+
+size_t pos_bytes(const apic_ctx *c) {
+    const int64_t n = c->n;
+    if (c->mixed) return align256(4 * n) * (c->d.dim == 2 ? 3 : 2);
+    return align256(8 * n) * c->d.dim;
+}
+
+AdjWs adj_layout(const apic_ctx *c, int stride) {
+    AdjWs L;
+    const int64_t n = c->n;
+    const size_t r = c->mixed ? 4 : 8;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    const int dim = c->d.dim, vdim = c->d.vdim;
+    size_t off = 0;
+    auto take = [&](size_t b) { size_t o = off; off = align256(off + b); return o; };
+    L.ctx = take(c->ws_bytes);
+    for (auto &v : L.pw_pos) v = (size_t)-1;
+    for (auto &v : L.pw_vel) v = (size_t)-1;
+    if (c->mixed) {
+        L.pw_pos[0] = take(4 * n);
+        L.pw_pos[1] = take(4 * n);
+        if (dim == 2) L.pw_pos[2] = take(4 * n);
+    } else {
+        L.pw_pos[0] = take(8 * n);
+        if (dim == 2) L.pw_pos[1] = take(8 * n);
+    }
+    for (int k = 0; k < vdim; ++k) L.pw_vel[k] = take(r * n);
+    L.bstart = take(4 * (c->g.nbuckets + 1));
+    L.E = take(8 * (size_t)dim * G);
+    L.E32 = take(4 * (size_t)dim * G);
+    L.rho = take(8 * (size_t)G);
+    L.id_a = take(4 * n);
+    L.id_b = take(4 * n);
+    L.inv = take(4 * n);
+    L.cross = take(4 * n);
+    L.snap_pos_bytes = pos_bytes(c);
+    L.snap_pos = take(L.snap_pos_bytes * (size_t)stride);
+    L.snap_perm = take(align256(4 * n) * (size_t)stride);
+    L.snap_E = take(align256(8 * (size_t)dim * G) * (size_t)stride);
+    for (int b = 0; b < 2; ++b) {
+        L.lam[b][0] = take(r * dim * n);
+        L.lam[b][1] = take(r * dim * n);
+        L.lam[b][2] = take(r * vdim * n);
+    }
+    L.lE = take(8 * (size_t)dim * G);
+    L.lrho = take(8 * (size_t)G);
+    L.W = take(8);
+    L.bytes = off;
+    return L;
+}
+
+// Position arrays of a position block laid out like pos_bytes() describes.
+PosP pos_block(const apic_ctx *c, char *base) {
+    PosP p{};
+    const int64_t n = c->n;
+    if (c->mixed) {
+        const size_t a = align256(4 * n);
+        p.cell = (const int32_t *)base;
+        p.ox = (const float *)(base + a);
+        p.oy = c->d.dim == 2 ? (const float *)(base + 2 * a) : nullptr;
+    } else {
+        const size_t a = align256(8 * n);
+        p.x = (const double *)base;
+        p.y = c->d.dim == 2 ? (const double *)(base + a) : nullptr;
+    }
+    return p;
+}
+
+PosP pos_ck(const apic_ctx *c, const CkLayout &L, char *ck) {
+    PosP p{};
+    if (c->mixed) {
+        p.cell = wsp<const int32_t>(ck, L.pos[0]);
+        p.ox = wsp<const float>(ck, L.pos[1]);
+        p.oy = wsp<const float>(ck, L.pos[2]);
+    } else {
+        p.x = wsp<const double>(ck, L.pos[0]);
+        p.y = wsp<const double>(ck, L.pos[1]);
+    }
+    return p;
+}
+
+apic_particles work_parts(const apic_ctx *c, const AdjWs &L, char *ws) {
+    apic_particles p{};
+    p.n = c->n;
+    if (c->mixed) {
+        p.cell = wsp<int32_t>(ws, L.pw_pos[0]);
+        p.ox = wsp<float>(ws, L.pw_pos[1]);
+        p.oy = wsp<float>(ws, L.pw_pos[2]);
+    } else {
+        p.x = wsp<double>(ws, L.pw_pos[0]);
+        p.y = wsp<double>(ws, L.pw_pos[1]);
+    }
+    p.vx = wsp<void>(ws, L.pw_vel[0]);
+    p.vy = wsp<void>(ws, L.pw_vel[1]);
+    p.vz = wsp<void>(ws, L.pw_vel[2]);
+    p.bucket_start = wsp<int32_t>(ws, L.bstart);
+    p.perm = nullptr;
+    return p;
+}
+
+// Copy the positions of p into a position block (pos_bytes layout).
+apic_status save_pos(apic_ctx *c, const apic_particles &p, char *dst, hipStream_t s) {
+    const int64_t n = c->n;
+    if (c->mixed) {
+        const size_t a = align256(4 * n);
+        HIPCHK(c, launch_copy_bytes(dst, p.cell, 4 * n, s));
+        HIPCHK(c, launch_copy_bytes(dst + a, p.ox, 4 * n, s));
+        if (c->d.dim == 2) HIPCHK(c, launch_copy_bytes(dst + 2 * a, p.oy, 4 * n, s));
+    } else {
+        const size_t a = align256(8 * n);
+        HIPCHK(c, launch_copy_bytes(dst, p.x, 8 * n, s));
+        if (c->d.dim == 2) HIPCHK(c, launch_copy_bytes(dst + a, p.y, 8 * n, s));
+    }
+    return APIC_OK;
+}
+
+// state <-> checkpoint (dir = +1: save, -1: load)
+apic_status ck_transfer(apic_ctx *c, const CkLayout &L, char *ck, apic_particles &p, double *E, int32_t *id,
+                        int dir, hipStream_t s) {
+    const int64_t n = c->n;
+    const size_t r = c->mixed ? 4 : 8;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    auto mv = [&](void *state, size_t off, size_t bytes) -> hipError_t {
+        if (!state || off == (size_t)-1) return hipSuccess;
+        return dir > 0 ? launch_copy_bytes(ck + off, state, (int64_t)bytes, s)
+                       : launch_copy_bytes(state, ck + off, (int64_t)bytes, s);
+    };
+    if (c->mixed) {
+        HIPCHK(c, mv(p.cell, L.pos[0], 4 * n));
+        HIPCHK(c, mv(p.ox, L.pos[1], 4 * n));
+        HIPCHK(c, mv(p.oy, L.pos[2], 4 * n));
+    } else {
+        HIPCHK(c, mv(p.x, L.pos[0], 8 * n));
+        HIPCHK(c, mv(p.y, L.pos[1], 8 * n));
+    }
+    HIPCHK(c, mv(p.vx, L.vel[0], r * n));
+    HIPCHK(c, mv(p.vy, L.vel[1], r * n));
+    HIPCHK(c, mv(p.vz, L.vel[2], r * n));
+    HIPCHK(c, mv(p.bucket_start, L.bstart, 4 * (size_t)(c->g.nbuckets + 1)));
+    HIPCHK(c, mv(E, L.E, 8 * (size_t)c->d.dim * G));
+    HIPCHK(c, mv(id, L.id, 4 * n));
+    return APIC_OK;
+}
+
+int n_checkpoints(int nsteps, int stride) { return (nsteps + stride - 1) / stride; }
+
+// lam_rho = A^T lam_E (FP64)
+apic_status adj_solve(apic_ctx *c, double *lE, double *lrho, char *ws_ctx, hipStream_t s) {
+    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    if (c->d.dim == 1) {
+        hipLaunchKernelGGL(k_adj_field1d, dim3(1), dim3(kBlock), (size_t)c->d.nx * sizeof(double), s, c->d.nx, lE,
+                           c->d.lx / c->d.nx, lrho);
+        HIPCHK(c, hipGetLastError());
+        return APIC_OK;
+    }
+    const size_t H = (size_t)(c->d.nx / 2 + 1) * c->d.ny;
+    char *rhat = wsp<char>(ws_ctx, c->o_rhat);
+    char *ehat = wsp<char>(ws_ctx, c->o_ehat);
+    FFTCHK(c, hipfftSetStream(c->fwd, s));
+    FFTCHK(c, hipfftExecD2Z(c->fwd, (hipfftDoubleReal *)lE, (hipfftDoubleComplex *)rhat));
+    FFTCHK(c, hipfftExecD2Z(c->fwd, (hipfftDoubleReal *)(lE + G), (hipfftDoubleComplex *)ehat));
+    hipLaunchKernelGGL(k_adj_spectral, dim3(nblocks((int64_t)H, 1024)), dim3(kBlock), 0, s, c->g,
+                       (const double2 *)rhat, (const double2 *)ehat, (double2 *)(ehat + 16 * H), c->dev);
+    HIPCHK(c, hipGetLastError());
+    FFTCHK(c, hipfftSetStream(c->inv, s));
+    FFTCHK(c, hipfftExecZ2D(c->inv, (hipfftDoubleComplex *)(ehat + 16 * H), (hipfftDoubleReal *)lrho));
+    return APIC_OK;
+}
+
+template <typename R>
+void boris_consts(const apic_ctx *c, double dt_scale, R &a, R &t, R &s) {
+    const PushC pc = push_coeffs(c, dt_scale, 1);
+    if (c->mixed) {
+        a = (R)pc.af;
+        t = (R)pc.tf;
+        s = (R)pc.sf;
+    } else {
+        a = (R)pc.a;
+        t = (R)pc.t;
+        s = (R)pc.s;
+    }
+}
+
+template <typename R>
+apic_status launch_level(apic_ctx *c, AdjP<R> &P, hipStream_t s) {
+    P.g = c->g;
+    P.n = c->n;
+    P.err = c->dev.err;
+    P.dt = (R)c->d.dt;
+    P.cq = (R)(c->d.q_macro / c->dV);
+    boris_consts<R>(c, 1.0, P.a, P.t, P.s);
+    boris_consts<R>(c, -0.5, P.ah, P.th, P.sh);
+    APIC_DISPATCH(c->g, c->mixed, {
+        if constexpr (std::is_same<R, typename RealOf<MIX>::T>::value)
+            hipLaunchKernelGGL((k_adj_level<MIX, DIM, VDIM>), dim3(nblocks(c->n)), dim3(kBlock), 0, s, P);
+    });
+    HIPCHK(c, hipGetLastError());
+    return APIC_OK;
+}
+
+apic_status check_adj_args(apic_ctx *c, int nsteps, int stride) {
+    if (nsteps < 0) return fail(c, APIC_EINVAL, "nsteps must be >= 0");
+    if (stride < 1) return fail(c, APIC_EINVAL, "checkpoint stride must be >= 1");
+    if (c->n < 1) return fail(c, APIC_EINVAL, "the adjoint needs at least one particle");
+    return APIC_OK;
+}
+
+template <typename R>
+apic_status step_adjoint_impl(apic_ctx *c, char *ck, int nsteps, int stride, double seed, double *out_x,
+                              double *out_y, double *out_vx, double *out_vy, double *out_vz, char *ws,
+                              hipStream_t s) {
+    const CkLayout CL = ck_layout(c);
+    const AdjWs L = adj_layout(c, stride);
+    const int64_t n = c->n;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    const int dim = c->d.dim;
+    char *ws_ctx = ws + L.ctx;
+    double *lE = wsp<double>(ws, L.lE);
+    double *lrho = wsp<double>(ws, L.lrho);
+    double *E_w = wsp<double>(ws, L.E);
+    int32_t *id_w = wsp<int32_t>(ws, L.id_a), *id_t = wsp<int32_t>(ws, L.id_b);
+    int32_t *inv = wsp<int32_t>(ws, L.inv), *cross = wsp<int32_t>(ws, L.cross);
+    const int C = n_checkpoints(nsteps, stride);
+    auto ckp = [&](int k) { return ck + (size_t)k * CL.bytes; };
+    auto snap_pos = [&](int k) { return ws + L.snap_pos + (size_t)k * L.snap_pos_bytes; };
+    auto snap_perm = [&](int k) { return (int32_t *)(ws + L.snap_perm + (size_t)k * align256(4 * n)); };
+    auto snap_E = [&](int k) { return (double *)(ws + L.snap_E + (size_t)k * align256(8 * (size_t)dim * G)); };
+    // level T: only the objective depends on E^T
+    hipLaunchKernelGGL(k_adj_scale, dim3(nblocks(dim * G)), dim3(kBlock), 0, s, (int64_t)dim * G,
+                       (const double *)(ckp(C) + CL.E), lE, seed * c->dV);
+    HIPCHK(c, hipGetLastError());
+    apic_status st = adj_solve(c, lE, lrho, ws_ctx, s);
+    if (st != APIC_OK) return st;
+    int cur = 0;
+    bool terminal = true;
+    apic_particles pw = work_parts(c, L, ws);
+    for (int seg = C - 1; seg >= 0; --seg) {
+        const int s0 = seg * stride, e = std::min(s0 + stride, nsteps), m = e - s0;
+        // recompute the segment from its checkpoint
+        st = ck_transfer(c, CL, ckp(seg), pw, E_w, id_w, -1, s);
+        if (st != APIC_OK) return st;
+        for (int k = 0; k < m; ++k) {
+            st = save_pos(c, pw, snap_pos(k), s);
+            if (st != APIC_OK) return st;
+            HIPCHK(c, launch_copy_bytes(snap_E(k), E_w, 8 * (int64_t)dim * G, s));
+            pw.perm = snap_perm(k);
+            st = apic_step(c, &pw, nullptr, E_w, nullptr, 1, nullptr, ws_ctx, s);
+            pw.perm = nullptr;
+            if (st != APIC_OK) return st;
+            hipLaunchKernelGGL(k_adj_compose_ids, dim3(nblocks(n)), dim3(kBlock), 0, s, n, id_w, snap_perm(k), id_t,
+                               c->dev.err);
+            HIPCHK(c, hipGetLastError());
+            std::swap(id_w, id_t);
+        }
+        // the step that ends at the stored checkpoint maps through input indices
+        hipLaunchKernelGGL(k_adj_invert, dim3(nblocks(n)), dim3(kBlock), 0, s, n, id_w, inv, c->dev.err);
+        HIPCHK(c, hipGetLastError());
+        hipLaunchKernelGGL(k_adj_cross_perm, dim3(nblocks(n)), dim3(kBlock), 0, s, n,
+                           (const int32_t *)(ckp(seg + 1) + CL.id), inv, snap_perm(m - 1), cross, c->dev.err);
+        HIPCHK(c, hipGetLastError());
+        for (int lvl = e; lvl > s0; --lvl) {
+            const int k = lvl - s0;
+            AdjP<R> P{};
+            P.pos = (lvl == e) ? pos_ck(c, CL, ckp(seg + 1)) : pos_block(c, snap_pos(k));
+            P.E = (lvl == e) ? (const double *)(ckp(seg + 1) + CL.E) : snap_E(k);
+            P.lrho = lrho;
+            P.lxp_in = wsp<R>(ws, L.lam[cur][0]);
+            P.lep_in = wsp<R>(ws, L.lam[cur][1]);
+            P.lv_in = wsp<R>(ws, L.lam[cur][2]);
+            P.terminal = terminal ? 1 : 0;
+            P.back = 1;
+            P.perm = (lvl == e) ? cross : snap_perm(k - 1);
+            P.prev = pos_block(c, snap_pos(k - 1));
+            P.lE_prev = lE;
+            P.lxp_out = wsp<R>(ws, L.lam[cur ^ 1][0]);
+            P.lep_out = wsp<R>(ws, L.lam[cur ^ 1][1]);
+            P.lv_out = wsp<R>(ws, L.lam[cur ^ 1][2]);
+            P.init = (lvl - 1 == 0) ? 1 : 0;
+            hipLaunchKernelGGL(k_adj_fill, dim3(nblocks(dim * G)), dim3(kBlock), 0, s, (int64_t)dim * G, lE);
+            HIPCHK(c, hipGetLastError());
+            st = launch_level<R>(c, P, s);
+            if (st != APIC_OK) return st;
+            cur ^= 1;
+            terminal = false;
+            st = adj_solve(c, lE, lrho, ws_ctx, s);
+            if (st != APIC_OK) return st;
+        }
+    }
+    // level 0: deposit and gather adjoints at x^0, then the outputs in input order
+    AdjP<R> P{};
+    P.pos = pos_ck(c, CL, ckp(0));
+    P.E = (const double *)(ckp(0) + CL.E);
+    P.lrho = lrho;
+    P.lxp_in = wsp<R>(ws, L.lam[cur][0]);
+    P.lep_in = wsp<R>(ws, L.lam[cur][1]);
+    P.lv_in = wsp<R>(ws, L.lam[cur][2]);
+    P.terminal = terminal ? 1 : 0;
+    P.final_out = 1;
+    P.id0 = (const int32_t *)(ckp(0) + CL.id);
+    P.out_x = out_x;
+    P.out_y = out_y;
+    P.out_vx = out_vx;
+    P.out_vy = out_vy;
+    P.out_vz = out_vz;
+    return launch_level<R>(c, P, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+apic_status apic_import_state(apic_ctx *c, const double *x, const double *y, const double *vx, const double *vy,
+                              const double *vz, apic_particles *p, void *stream) {
+    if (!c) return APIC_EINVAL;
+    apic_status st = check_parts(c, p, false);
+    if (st != APIC_OK) return st;
+    if (!x || (c->d.dim == 2 && !y) || !vx || (c->d.vdim >= 2 && !vy) || (c->d.vdim >= 3 && !vz))
+        return fail(c, APIC_EINVAL, "a state array is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const double dx = c->d.lx / c->d.nx, dy = c->d.dim == 2 ? c->d.ly / c->d.ny : 1.0;
+    const Parts out = parts_of(p);
+    APIC_DISPATCH(c->g, c->mixed,
+                  hipLaunchKernelGGL((k_import<MIX, DIM, VDIM>), dim3(nblocks(c->n)), dim3(kBlock), 0, s, c->g, c->n,
+                                     dx, dy, x, y, vx, vy, vz, out, c->dev.err));
+    HIPCHK(c, hipGetLastError());
+    return APIC_OK;
+}
+
+apic_status apic_adjoint_sizes(const apic_ctx *c, int nsteps, int stride, size_t *ckpt_bytes, size_t *ws_bytes) {
+    if (!c || nsteps < 0 || stride < 1) return APIC_EINVAL;
+    const CkLayout CL = ck_layout(c);
+    if (ckpt_bytes) *ckpt_bytes = CL.bytes * (size_t)(n_checkpoints(nsteps, stride) + 1);
+    if (ws_bytes) *ws_bytes = adj_layout(c, stride).bytes;
+    return APIC_OK;
+}
+
+apic_status apic_adjoint_forward(apic_ctx *c, const apic_particles *p0, int nsteps, int stride, void *ckpt,
+                                 double *W, double *E_out, void *ws, void *stream) {
+    if (!c) return APIC_EINVAL;
+    apic_status st = check_parts(c, p0, false);
+    if (st != APIC_OK) return st;
+    st = check_adj_args(c, nsteps, stride);
+    if (st != APIC_OK) return st;
+    if (!ckpt || !ws) return fail(c, APIC_EINVAL, "checkpoint buffer and workspace are required");
+    hipStream_t s = (hipStream_t)stream;
+    const CkLayout CL = ck_layout(c);
+    const AdjWs L = adj_layout(c, stride);
+    char *w = (char *)ws, *ck = (char *)ckpt;
+    char *ws_ctx = w + L.ctx;
+    const int64_t n = c->n;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    const int dim = c->d.dim;
+    double *E_w = wsp<double>(w, L.E);
+    float *E32_w = wsp<float>(w, L.E32);
+    int32_t *id_w = wsp<int32_t>(w, L.id_a), *id_t = wsp<int32_t>(w, L.id_b);
+    int32_t *perm = wsp<int32_t>(w, L.inv);
+    apic_particles pw = work_parts(c, L, w);
+    // x^0, v^0 in the caller's order -> sorted copy; id = input index
+    st = copy_parts(c, parts_of(&pw), parts_of(p0), s);
+    if (st != APIC_OK) return st;
+    pw.perm = id_w;
+    st = apic_sort_by_cell(c, &pw, ws_ctx, s);
+    pw.perm = nullptr;
+    if (st != APIC_OK) return st;
+    // E^0, then the backward half push
+    st = apic_deposit(c, &pw, wsp<void>(w, L.rho), s);
+    if (st != APIC_OK) return st;
+    st = apic_field_solve(c, wsp<void>(w, L.rho), E_w, c->mixed ? E32_w : nullptr, nullptr, ws_ctx, s);
+    if (st != APIC_OK) return st;
+    st = apic_gather_push(c, &pw, c->mixed ? (const void *)E32_w : (const void *)E_w, -0.5, 0, s);
+    if (st != APIC_OK) return st;
+    st = ck_transfer(c, CL, ck, pw, E_w, id_w, +1, s);
+    if (st != APIC_OK) return st;
+    for (int k = 0; k < nsteps; ++k) {
+        pw.perm = perm;
+        st = apic_step(c, &pw, nullptr, E_w, nullptr, 1, nullptr, ws_ctx, s);
+        pw.perm = nullptr;
+        if (st != APIC_OK) return st;
+        hipLaunchKernelGGL(k_adj_compose_ids, dim3(nblocks(n)), dim3(kBlock), 0, s, n, id_w, perm, id_t, c->dev.err);
+        HIPCHK(c, hipGetLastError());
+        std::swap(id_w, id_t);
+        if ((k + 1) % stride == 0 || k + 1 == nsteps) {
+            const int idx = (k + 1 + stride - 1) / stride;
+            st = ck_transfer(c, CL, ck + (size_t)idx * CL.bytes, pw, E_w, id_w, +1, s);
+            if (st != APIC_OK) return st;
+        }
+    }
+    if (W) {
+        hipLaunchKernelGGL(k_adj_energy, dim3(1), dim3(1024), 0, s, (int64_t)dim * G, E_w, c->dV, W);
+        HIPCHK(c, hipGetLastError());
+    }
+    if (E_out) HIPCHK(c, launch_copy_bytes(E_out, E_w, 8 * (int64_t)dim * G, s));
+    return APIC_OK;
+}
+
+apic_status apic_step_adjoint(apic_ctx *c, const void *ckpt, int nsteps, int stride, double seed, double *lam_x,
+                              double *lam_y, double *lam_vx, double *lam_vy, double *lam_vz, void *ws, void *stream) {
+    if (!c) return APIC_EINVAL;
+    apic_status st = check_adj_args(c, nsteps, stride);
+    if (st != APIC_OK) return st;
+    if (!ckpt || !ws) return fail(c, APIC_EINVAL, "checkpoint buffer and workspace are required");
+    if (!lam_x || (c->d.dim == 2 && !lam_y) || !lam_vx || (c->d.vdim >= 2 && !lam_vy) || (c->d.vdim >= 3 && !lam_vz))
+        return fail(c, APIC_EINVAL, "a gradient output array is NULL");
+    if (!std::isfinite(seed)) return fail(c, APIC_EINVAL, "seed is not finite");
+    hipStream_t s = (hipStream_t)stream;
+    if (c->mixed)
+        return step_adjoint_impl<float>(c, (char *)const_cast<void *>(ckpt), nsteps, stride, seed, lam_x, lam_y,
+                                        lam_vx, lam_vy, lam_vz, (char *)ws, s);
+    return step_adjoint_impl<double>(c, (char *)const_cast<void *>(ckpt), nsteps, stride, seed, lam_x, lam_y, lam_vx,
+                                     lam_vy, lam_vz, (char *)ws, s);
+}
+
+}  // extern "C"

@@ -1,7 +1,7 @@
 // Host side of libapic: context, workspace layout, argument checks and the
 // C-ABI entry points declared in include/apic.h.
 #include "apic.h"
-#include "apic_internal.h"
+#include "apic_ctx.h"
 
 #include <hipfft/hipfft.h>
 
@@ -12,30 +12,9 @@
 #include <vector>
 
 using namespace apic;
+using namespace apic_host;
 
-struct apic_ctx {
-    apic_grid_desc d;
-    int64_t n;
-    Geo g;
-    bool mixed;
-    CtxDev dev;
-    void *dev_block = nullptr;
-    hipfftHandle fwd = 0, inv = 0;
-    bool have_fft = false;
-    std::string err;
-    // workspace layout (byte offsets)
-    size_t o_x, o_y, o_cell, o_ox, o_oy, o_vx, o_vy, o_vz;
-    size_t o_keys, o_count, o_cursor, o_bstart, o_acc, o_rho, o_rhat, o_ehat;
-    size_t o_cnt, o_offs, o_farcnt, o_farcur, o_tot;
-    size_t o_keys2, o_idx, o_idx2, o_rcnt, o_roff;
-    size_t ws_bytes;
-    double dV, mass;
-    // per-phase timing (apic_profile_enable)
-    std::vector<hipEvent_t> ev;   // 5 events per profiled step
-    int prof_max = 0, prof_used = 0;
-};
-
-namespace {
+namespace apic_host {
 
 apic_status fail(apic_ctx *c, apic_status st, const char *msg) {
     if (c) c->err = msg;
@@ -46,23 +25,6 @@ apic_status hip_fail(apic_ctx *c, hipError_t e, const char *where) {
     if (c) c->err = std::string(where) + ": " + hipGetErrorString(e);
     return APIC_EHIP;
 }
-
-#define HIPCHK(ctx, expr)                                   \
-    do {                                                    \
-        hipError_t e_ = (expr);                             \
-        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
-    } while (0)
-
-#define FFTCHK(ctx, expr)                                                    \
-    do {                                                                     \
-        hipfftResult r_ = (expr);                                            \
-        if (r_ != HIPFFT_SUCCESS) {                                          \
-            (ctx)->err = std::string(#expr) + " failed (" + std::to_string((int)r_) + ")"; \
-            return APIC_EHIP;                                                \
-        }                                                                    \
-    } while (0)
-
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 int ilog2_floor(int64_t v) {
     int r = 0;
@@ -140,10 +102,6 @@ void layout(apic_ctx *c) {
     c->ws_bytes = off;
 }
 
-template <typename T>
-T *wsp(void *ws, size_t off) {
-    return off == (size_t)-1 ? nullptr : (T *)((char *)ws + off);
-}
 
 Parts parts_of(const apic_particles *p) {
     Parts q;
@@ -270,7 +228,7 @@ apic_status copy_parts(apic_ctx *c, const Parts &dst, const Parts &src, hipStrea
     return APIC_OK;
 }
 
-}  // namespace
+}  // namespace apic_host
 
 extern "C" {
 

@@ -973,22 +973,6 @@ inline size_t tile_acc_bytes(const Geo &g, int halo) {
 
 // ================================================================ launchers
 
-#define APIC_DISPATCH(g, mixed, ...)                                                    \
-    do {                                                                                \
-        if (mixed) {                                                                    \
-            constexpr bool MIX = true;                                                  \
-            [[maybe_unused]] constexpr int U = 2;                                       \
-            if ((g).dim == 1) { constexpr int DIM = 1, VDIM = 1; __VA_ARGS__; }         \
-            else if ((g).vdim == 2) { constexpr int DIM = 2, VDIM = 2; __VA_ARGS__; }   \
-            else { constexpr int DIM = 2, VDIM = 3; __VA_ARGS__; }                      \
-        } else {                                                                        \
-            constexpr bool MIX = false;                                                 \
-            [[maybe_unused]] constexpr int U = 2;                                       \
-            if ((g).dim == 1) { constexpr int DIM = 1, VDIM = 1; __VA_ARGS__; }         \
-            else if ((g).vdim == 2) { constexpr int DIM = 2, VDIM = 2; __VA_ARGS__; }   \
-            else { constexpr int DIM = 2, VDIM = 3; __VA_ARGS__; }                      \
-        }                                                                               \
-    } while (0)
 
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
     if (n <= 0) return hipSuccess;

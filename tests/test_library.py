@@ -18,7 +18,7 @@ def declared_functions():
 
 def test_header_declares_the_five_entry_points():
     names = declared_functions()
-    for n in ("apic_sort_by_cell", "apic_deposit", "apic_gather_push", "apic_step"):
+    for n in ("apic_sort_by_cell", "apic_deposit", "apic_gather_push", "apic_step", "apic_step_adjoint"):
         assert n in names, n
 
 
