@@ -90,6 +90,7 @@ void layout(apic_ctx *c) {
     c->o_farcnt = take(4 * nb);
     c->o_farcur = take(4 * nb);
     c->o_tot = take(4 * nb);
+    c->o_deep = take(4 * nb * kDeepTab);
     c->o_acc = take(8 * G);
     c->o_rho = take(8 * G);
     if (dim == 2) {
@@ -160,6 +161,8 @@ PushC push_coeffs(const apic_ctx *c, double dt_scale, int move) {
     pc.dtdx = (float)(c->d.dt / dx);
     pc.dtdy = (float)(c->d.dt / dy);
     pc.move = move;
+    pc.rot = c->d.bz != 0.0;
+    pc.deep = 0.25f;
     return pc;
 }
 
@@ -442,12 +445,15 @@ apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, floa
     int32_t *cnt = wsp<int32_t>(ws, c->o_cnt);
     int32_t *farcnt = wsp<int32_t>(ws, c->o_farcnt);
     int32_t *tot = wsp<int32_t>(ws, c->o_tot);
+    int32_t *deep = wsp<int32_t>(ws, c->o_deep);
     void *acc = wsp<void>(ws, c->o_acc);
     Parts A = parts_of(p), B = parts_ws(c, ws);
     int32_t *bsA = p->bucket_start, *bsB = wsp<int32_t>(ws, c->o_bstart);
     const PushC pc = push_coeffs(c, 1.0, 1);
     HIPCHK(c, launch_fill_i32(farcnt, nb, 0, s));
     HIPCHK(c, launch_fill_i32(tot, nb, 0, s));
+    // no deep ranges known for the incoming order: the first count reads all
+    HIPCHK(c, launch_fill_i32(deep, (int64_t)nb * kDeepTab, 0, s));
     HIPCHK(c, launch_fill_u64((uint64_t *)acc, G, 0, s));
     HIPCHK(c, launch_set_step(c->dev.step, -1, s));
     for (int k = 0; k < nsteps; ++k) {
@@ -460,12 +466,12 @@ apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, floa
         hipEvent_t *ev = nullptr;
         if (c->prof_used < c->prof_max) ev = &c->ev[5 * (size_t)c->prof_used++];
         if (ev) HIPCHK(c, hipEventRecord(ev[0], s));
-        HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, E, pc, cnt, tot, farcnt, c->dev, s));
+        HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, E, pc, cnt, tot, farcnt, deep, c->dev, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[1], s));
         HIPCHK(c, launch_scan_dir(c->g, tot, bs_dst, c->n, max_per_bucket(c), 1, c->dev, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
         HIPCHK(c, launch_step_push(c->g, c->mixed, src, dst, bs_src, bs_dst, cnt, farcnt, E, pc, acc, p->perm,
-                                   diag ? c->dev.part_push : nullptr, c->dev, s));
+                                   diag ? c->dev.part_push : nullptr, deep, c->dev, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[3], s));
         if (rho && last) {
             if (c->mixed)

@@ -470,21 +470,26 @@ __device__ double field1d_block(double *sr, int nx, double dx, double *E, float 
 }  // namespace
 }  // namespace apic
 
+// Particles per thread and pipeline stage in the fused step kernels.
+#ifndef APIC_STEP_U
+#define APIC_STEP_U 1
+#endif
+
 // Instantiates a statement for the precision / dimension combination of a
 // launch: MIX, DIM, VDIM (and the unroll factor U) are constexpr inside.
 #define APIC_DISPATCH(g, mixed, ...)                                                    \
     do {                                                                                \
         if (mixed) {                                                                    \
             constexpr bool MIX = true;                                                  \
-            [[maybe_unused]] constexpr int U = 2;                                       \
-            if ((g).dim == 1) { constexpr int DIM = 1, VDIM = 1; __VA_ARGS__; }         \
-            else if ((g).vdim == 2) { constexpr int DIM = 2, VDIM = 2; __VA_ARGS__; }   \
-            else { constexpr int DIM = 2, VDIM = 3; __VA_ARGS__; }                      \
+            [[maybe_unused]] constexpr int U = APIC_STEP_U;                                       \
+            if ((g).dim == 1) { [[maybe_unused]] constexpr int DIM = 1, VDIM = 1; __VA_ARGS__; }         \
+            else if ((g).vdim == 2) { [[maybe_unused]] constexpr int DIM = 2, VDIM = 2; __VA_ARGS__; }   \
+            else { [[maybe_unused]] constexpr int DIM = 2, VDIM = 3; __VA_ARGS__; }                      \
         } else {                                                                        \
             constexpr bool MIX = false;                                                 \
-            [[maybe_unused]] constexpr int U = 2;                                       \
-            if ((g).dim == 1) { constexpr int DIM = 1, VDIM = 1; __VA_ARGS__; }         \
-            else if ((g).vdim == 2) { constexpr int DIM = 2, VDIM = 2; __VA_ARGS__; }   \
-            else { constexpr int DIM = 2, VDIM = 3; __VA_ARGS__; }                      \
+            [[maybe_unused]] constexpr int U = APIC_STEP_U;                                       \
+            if ((g).dim == 1) { [[maybe_unused]] constexpr int DIM = 1, VDIM = 1; __VA_ARGS__; }         \
+            else if ((g).vdim == 2) { [[maybe_unused]] constexpr int DIM = 2, VDIM = 2; __VA_ARGS__; }   \
+            else { [[maybe_unused]] constexpr int DIM = 2, VDIM = 3; __VA_ARGS__; }                      \
         }                                                                               \
     } while (0)

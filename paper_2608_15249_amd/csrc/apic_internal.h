@@ -36,6 +36,8 @@ struct PushC {
     double dt;            // position step (unscaled dt)
     float dtdx, dtdy;     // dt/dx, dt/dy in binary32 (mixed path)
     int move;
+    int rot;              // bz != 0 (the push rotates v in the x-y plane)
+    float deep;           // slack (cells) that makes a staying particle "deep"
 };
 
 // One particle buffer set (structure of arrays).
@@ -59,6 +61,7 @@ struct CtxDev {
 
 constexpr int kMaxSpecBlocks = 1024;
 constexpr int kStepTab = 40;  // per-bucket direction table entries (4 waves x 10 directions)
+constexpr int kDeepTab = 8;   // per-bucket deep-range entries (4 waves x (start, count))
 
 // ---- launchers (apic_kernels.hip) -----------------------------------------
 // All return hipSuccess or the launch error.
@@ -95,15 +98,18 @@ hipError_t launch_gather_push(const Geo &g, bool mixed, const Parts &p, int64_t 
                               hipStream_t s);
 
 // fused step: direction tallies, scan into offsets, push + deposit + scatter
+// deep: per (bucket, wave) the [start, count) range, relative to the bucket,
+// of particles the previous push found deep inside their tile (written by
+// launch_step_push, all zero when unknown).
 hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int32_t *bstart,
                              const double *E, const PushC &pc, int32_t *cnt, int32_t *tot,
-                             int32_t *farcnt, const CtxDev &c, hipStream_t s);
+                             int32_t *farcnt, const int32_t *deep, const CtxDev &c, hipStream_t s);
 hipError_t launch_scan_dir(const Geo &g, int32_t *tot, int32_t *start, int64_t n, int64_t max_per_bucket,
                            int step_mode, const CtxDev &c, hipStream_t s);
 hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Parts &dst,
                             const int32_t *bstart, const int32_t *bstart_new, const int32_t *cnt,
                             int32_t *farcnt, const double *E, const PushC &pc, void *acc, int32_t *perm,
-                            double *part, const CtxDev &c, hipStream_t s);
+                            double *part, int32_t *deep, const CtxDev &c, hipStream_t s);
 
 // field: accumulation buffer -> rho (FP64): rho = add + scale * acc
 hipError_t launch_rho(const Geo &g, bool mixed, void *acc, double *rho, double scale, double add,

@@ -49,6 +49,8 @@ namespace {
 // (rare) take slots from an atomic cursor at the end of their bucket.
 constexpr int kDirs = 10;
 constexpr int kFar = 9;
+constexpr int kStay = 4;   // the direction of a particle that stays in its bucket
+static_assert(kDeepTab == 2 * kWaves, "deep table size");
 constexpr int kTab = kWaves * kDirs;  // per-bucket table entries
 
 __device__ __forceinline__ int dir_code(const Geo &g, int bx, int by, int nbx_new, int nby_new) {
@@ -588,14 +590,27 @@ __global__ void __launch_bounds__(kBlock) k_gather_push_tiled(Geo g, Parts p, co
 // per (bucket, wave, direction) and counts far movers at their destination.
 // U particles per thread are loaded before any is processed (more loads in
 // flight per wave).
+//
+// Deep ranges (see the push pass) are skipped when the tile's field cannot
+// move a deep particle out of the tile: 2|a| max|E| dt/dx, with slack for
+// rounding, below pc.deep. Their particles are credited as stays to the waves
+// that own their indices; the remaining particles run the full computation and
+// are tallied with LDS atomics into their owning waves' entries.
+
+// Number of indices k in [lo, hi) owned by wave w (k mod kBlock in [64w, 64w+64)).
+__device__ __forceinline__ int owned_by(int lo, int hi, int w) {
+    auto f = [w](int x) { return (x / kBlock) * 64 + min(max((x % kBlock) - 64 * w, 0), 64); };
+    return hi > lo ? f(hi) - f(lo) : 0;
+}
 template <bool MIX, int DIM, int VDIM, int U>
 __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int32_t *bstart, const double *E,
                                                        PushC pc, int32_t *cnt, int32_t *tot, int32_t *farcnt,
-                                                       CtxDev c) {
+                                                       const int32_t *deep, CtxDev c) {
     using R = typename Pt<MIX>::R;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sErr;
     __shared__ int32_t sCnt[kTab];
+    __shared__ float sMax[kWaves][2];
     R *sE = (R *)smem;
     const int w = threadIdx.x >> 6;
     const int ex_w = (1 << g.tsx) + 1, ey_w = (DIM == 2) ? (1 << g.tsy) + 1 : 1;
@@ -611,6 +626,83 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
         __syncthreads();
         const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
         const int span = i1 - i0;
+        // field bound of the tile: per axis, or |E| when the push rotates v
+        {
+            float e0 = 0.0f, e1 = 0.0f;
+            const int tn = ex_w * ey_w;
+            for (int t = threadIdx.x; t < tn; t += blockDim.x) {
+                const float ex = fabsf((float)sE[t]);
+                const float ey = (DIM == 2) ? fabsf((float)sE[tn + t]) : 0.0f;
+                if (pc.rot) {
+                    e0 = fmaxf(e0, sqrtf(ex * ex + ey * ey));
+                } else {
+                    e0 = fmaxf(e0, ex);
+                    e1 = fmaxf(e1, ey);
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                e0 = fmaxf(e0, __shfl_xor(e0, off));
+                e1 = fmaxf(e1, __shfl_xor(e1, off));
+            }
+            if ((threadIdx.x & 63) == 0) {
+                sMax[w][0] = e0;
+                sMax[w][1] = pc.rot ? e0 : e1;
+            }
+        }
+        __syncthreads();
+        float emx = 0.0f, emy = 0.0f;
+        for (int w2 = 0; w2 < kWaves; ++w2) {
+            emx = fmaxf(emx, sMax[w2][0]);
+            emy = fmaxf(emy, sMax[w2][1]);
+        }
+        const float kick = 2.0f * fabsf(MIX ? pc.af : (float)pc.a) * 1.0009765625f;
+        bool skip = kick * emx * pc.dtdx + 0.0009765625f <= pc.deep;
+        if constexpr (DIM == 2) skip = skip && kick * emy * pc.dtdy + 0.0009765625f <= pc.deep;
+        // deep ranges of this bucket: increasing, disjoint, inside [0, span)
+        int da[kWaves], dc[kWaves], ndeep = 0;
+        {
+            int lo = 0;
+#pragma unroll
+            for (int r = 0; r < kWaves; ++r) {
+                const int st = skip ? min(max(deep[b * kDeepTab + 2 * r], lo), span) : lo;
+                const int ct = skip ? min(max(deep[b * kDeepTab + 2 * r + 1], 0), span - st) : 0;
+                da[r] = st;
+                dc[r] = ct;
+                lo = st + ct;
+                ndeep += ct;
+            }
+        }
+        if (ndeep > 0) {
+            if ((threadIdx.x & 63) == 0) {
+                int st = 0;
+#pragma unroll
+                for (int r = 0; r < kWaves; ++r) st += owned_by(da[r], da[r] + dc[r], w);
+                atomicAdd(&sCnt[w * kDirs + kStay], st);
+            }
+            const int nsh = span - ndeep;
+            for (int t = threadIdx.x; t < nsh; t += blockDim.x) {
+                int k = t;
+#pragma unroll
+                for (int r = 0; r < kWaves; ++r)
+                    if (k >= da[r]) k += dc[r];
+                Raw<MIX> r1;
+                load_raw<MIX, DIM, VDIM>(p, i0 + k, r1);
+                Pt<MIX> q;
+                bool good = decode<MIX, DIM, VDIM>(r1, g, q);
+                int lx, ly, sx, sy;
+                good = advance<MIX, DIM, VDIM>(q, g, pc, sE, ex_w, ey_w, x0, y0, lx, ly, sx, sy) && good;
+                if (!good) atomicOr(&sErr, ERR_DOMAIN);
+                const int nbx_new = q.ix >> g.tsx, nby_new = (DIM == 2) ? (q.iy >> g.tsy) : 0;
+                const int code = dir_code(g, bx, by, nbx_new, nby_new);
+                if (code < kFar) {
+                    atomicAdd(&sCnt[((k % kBlock) >> 6) * kDirs + code], 1);
+                } else {
+                    const int nbk = nby_new * g.nbx + nbx_new;
+                    atomicAdd(&farcnt[nbk], 1);
+                    atomicAdd(&tot[nbk], 1);
+                }
+            }
+        } else {
         // two register sets, each chunk's loads issued one chunk ahead of its use
         constexpr int CH = kBlock * U;
         Raw<MIX> ra[U], rb[U];
@@ -658,6 +750,7 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
             if (base + 2 * CH < span) fetch(ra, base + 2 * CH);
             if (base + CH < span) process(rb, base + CH);
         }
+        }
         __syncthreads();
         if (threadIdx.x < kTab) cnt[b * kTab + threadIdx.x] = sCnt[threadIdx.x];
         if (threadIdx.x < kFar) {
@@ -680,12 +773,20 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
 }
 
 // ---- fused step, pass 2: push, deposit, scatter into the next bucket order -----
+// Staying particles are split by how far they sit from their tile's edges
+// after the move: a particle whose distance to every edge exceeds its own
+// displacement at the current velocity, |v| dt/dx, by at least pc.deep cells
+// is "deep" and takes its slot from the front of its wave's stay range; the
+// others fill that range from the back. The deep part of each range goes to
+// the deep table, so that the next count pass can credit those particles as
+// stays without reading them, as long as the field's share of the next move,
+// 2|a| max|E| dt/dx, stays below pc.deep.
 template <bool MIX, int DIM, int VDIM, int U>
 __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts dst, const int32_t *bstart,
                                                       const int32_t *bstart_new, const int32_t *cnt,
                                                       int32_t *farcnt, const double *E, PushC pc,
                                                       typename AccOf<MIX>::T *acc, int32_t *perm, double *part,
-                                                      CtxDev c) {
+                                                      int32_t *deep_out, CtxDev c) {
     using R = typename Pt<MIX>::R;
     using A = typename AccOf<MIX>::T;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -693,6 +794,8 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
     __shared__ double sRed[kWaves];
     __shared__ int32_t sRun[kTab];
     __shared__ int32_t sEnd[kFar];   // end of each neighbour destination bucket (slot bound)
+    __shared__ int32_t sBack[kWaves];    // next free slot, from the back, of each wave's stay range
+    __shared__ int32_t sFront0[kWaves];  // first slot of each wave's stay range
     const int ex_w = (1 << g.tsx) + 1, ey_w = (DIM == 2) ? (1 << g.tsy) + 1 : 1;
     const int wx = (1 << g.tsx) + 1 + 2 * g.halo;
     const int wy = (DIM == 2) ? (1 << g.tsy) + 1 + 2 * g.halo : 1;
@@ -729,6 +832,10 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                 }
                 for (int w3 = 0; w3 < w2; ++w3) off += cnt[b * kTab + w3 * kDirs + d];
                 if (w2 == 0) sEnd[d] = bstart_new[nb + 1];
+                if (d == kStay) {
+                    sFront0[w2] = off;
+                    sBack[w2] = off + cnt[b * kTab + w2 * kDirs + kStay];
+                }
             }
             sRun[threadIdx.x] = off;
         }
@@ -736,6 +843,9 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
         __syncthreads();
         const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
         const int span = i1 - i0;
+        // cells of this tile (the last tile of an axis may be cut by the grid edge)
+        const float txe = (float)min(1 << g.tsx, g.nx - x0);
+        const float tye = (DIM == 2) ? (float)min(1 << g.tsy, g.ny - y0) : 1.0f;
         double ke = 0.0, px = 0.0;
         constexpr int CH = kBlock * U;
         Raw<MIX> ra[U], rb[U];
@@ -752,6 +862,7 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                 const int k = base + j * kBlock + threadIdx.x;
                 const bool act = k < span;
                 int code = -1, nbk = 0;
+                bool deep = false;
                 Pt<MIX> q;
                 if (act) {
                     bool good = decode<MIX, DIM, VDIM>(r[j], g, q);
@@ -765,6 +876,25 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                     const int nbx_new = q.ix >> g.tsx, nby_new = (DIM == 2) ? (q.iy >> g.tsy) : 0;
                     nbk = nby_new * g.nbx + nbx_new;
                     code = dir_code(g, bx, by, nbx_new, nby_new);
+                    if (code == kStay) {
+                        const float ux = (float)(q.ix - x0) + (float)q.fx;
+                        const float mx = fminf(ux, txe - ux) - pc.deep;
+                        const float vx = fabsf((float)q.vx);
+                        if constexpr (DIM == 1) {
+                            deep = mx >= vx * pc.dtdx;
+                        } else {
+                            const float uy = (float)(q.iy - y0) + (float)q.fy;
+                            const float my = fminf(uy, tye - uy) - pc.deep;
+                            const float vy = fabsf((float)q.vy);
+                            if (!pc.rot) {
+                                deep = mx >= vx * pc.dtdx && my >= vy * pc.dtdy;
+                            } else {
+                                // the rotation can turn the in-plane speed along either axis
+                                const float vv = sqrtf(vx * vx + vy * vy);
+                                deep = mx >= vv * pc.dtdx && my >= vv * pc.dtdy;
+                            }
+                        }
+                    }
                     // deposit rho^{n+1}: LDS tile + halo, global beyond it
                     A wgt[4];
                     dep_weights<MIX, DIM>(q, g, wgt);
@@ -794,9 +924,24 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                     const uint64_t grp = __ballot(code == kc);
                     const int basek = sRun[w * kDirs + kc];
                     const int cntk = (int)__popcll(grp);
-                    const bool fits = basek + cntk <= sEnd[kc];
-                    if (code == kc) slot = fits ? basek + (int)__popcll(grp & lt) : -1;
-                    if ((int)__lane_id() == leader) sRun[w * kDirs + kc] = basek + cntk;
+                    if (kc == kStay) {
+                        // deep stays from the front of the wave's stay range, the rest from its back
+                        const uint64_t gd = __ballot(code == kStay && deep);
+                        const uint64_t gs = grp & ~gd;
+                        const int back = sBack[w];
+                        const int nd = (int)__popcll(gd), ns = (int)__popcll(gs);
+                        const bool fits = basek + nd <= back - ns;
+                        if (code == kStay)
+                            slot = !fits ? -1 : deep ? basek + (int)__popcll(gd & lt) : back - 1 - (int)__popcll(gs & lt);
+                        if ((int)__lane_id() == leader) {
+                            sRun[w * kDirs + kStay] = basek + nd;
+                            sBack[w] = back - ns;
+                        }
+                    } else {
+                        const bool fits = basek + cntk <= sEnd[kc];
+                        if (code == kc) slot = fits ? basek + (int)__popcll(grp & lt) : -1;
+                        if ((int)__lane_id() == leader) sRun[w * kDirs + kc] = basek + cntk;
+                    }
                     rem &= ~grp;
                 }
                 if (code == kFar) {
@@ -823,6 +968,12 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
             if (base + CH < span) process(rb, base + CH);
         }
         __syncthreads();
+        if (threadIdx.x < kWaves) {
+            // deep range of each wave's stays, relative to this bucket's new start
+            const int t = threadIdx.x;
+            deep_out[b * kDeepTab + 2 * t] = sFront0[t] - bstart_new[b];
+            deep_out[b * kDeepTab + 2 * t + 1] = sRun[t * kDirs + kStay] - sFront0[t];
+        }
         flush_region<MIX, DIM>(acc, sA, g, x0, y0, wx, wy, g.halo);
         if (part) {
             double kt = block_sum(ke, sRed);
@@ -1112,26 +1263,27 @@ int persistent_grid(K kernel, size_t shmem, int nbuckets) {
 }
 
 hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int32_t *bstart, const double *E,
-                             const PushC &pc, int32_t *cnt, int32_t *tot, int32_t *farcnt, const CtxDev &c,
-                             hipStream_t s) {
+                             const PushC &pc, int32_t *cnt, int32_t *tot, int32_t *farcnt, const int32_t *deep,
+                             const CtxDev &c, hipStream_t s) {
     size_t sh = tile_e_bytes(g, mixed);
     APIC_DISPATCH(g, mixed, {
         auto kern = k_step_count<MIX, DIM, VDIM, U>;
         hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, p, bstart, E,
-                           pc, cnt, tot, farcnt, c);
+                           pc, cnt, tot, farcnt, deep, c);
     });
     return hipGetLastError();
 }
 
 hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Parts &dst, const int32_t *bstart,
                             const int32_t *bstart_new, const int32_t *cnt, int32_t *farcnt, const double *E,
-                            const PushC &pc, void *acc, int32_t *perm, double *part, const CtxDev &c,
-                            hipStream_t s) {
+                            const PushC &pc, void *acc, int32_t *perm, double *part, int32_t *deep,
+                            const CtxDev &c, hipStream_t s) {
     size_t sh = tile_acc_bytes(g, g.halo) + tile_e_bytes(g, mixed);
     APIC_DISPATCH(g, mixed, {
         auto kern = k_step_push<MIX, DIM, VDIM, U>;
         hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, src, dst,
-                           bstart, bstart_new, cnt, farcnt, E, pc, (typename AccOf<MIX>::T *)acc, perm, part, c);
+                           bstart, bstart_new, cnt, farcnt, E, pc, (typename AccOf<MIX>::T *)acc, perm, part,
+                           deep, c);
     });
     return hipGetLastError();
 }
