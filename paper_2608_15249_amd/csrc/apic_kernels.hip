@@ -74,6 +74,50 @@ __device__ __forceinline__ int dir_source(const Geo &g, int nbk, int d) {
     return (g.dim == 2) ? sy * g.nbx + sx : sx;
 }
 
+// Direction code from a particle's tile-local cell after the move, (lxn,
+// lyn) = old tile-local cell + unwrapped cell shift: the widths of the tile
+// and of its neighbours (the last tile of an axis may be cut by the grid
+// edge; neighbours wrap periodically) decide whether it stayed, crossed into
+// a neighbour, or jumped farther (kFar). Same meaning as dir_code for every
+// move, without per-particle wrap arithmetic.
+struct TileNb {
+    int txe, lw, rw;   // widths (cells) of this tile and its left / right neighbour
+    int tye, dw, uw;   // same along y
+};
+
+__device__ __forceinline__ int tile_width(int i, int t, int n) { return min(t, n - i * t); }
+
+template <int DIM>
+__device__ __forceinline__ TileNb tile_nb(const Geo &g, int bx, int by) {
+    TileNb t;
+    const int T = 1 << g.tsx;
+    t.txe = tile_width(bx, T, g.nx);
+    t.lw = tile_width(bx == 0 ? g.nbx - 1 : bx - 1, T, g.nx);
+    t.rw = tile_width(bx == g.nbx - 1 ? 0 : bx + 1, T, g.nx);
+    if constexpr (DIM == 2) {
+        const int V = 1 << g.tsy;
+        t.tye = tile_width(by, V, g.ny);
+        t.dw = tile_width(by == 0 ? g.nby - 1 : by - 1, V, g.ny);
+        t.uw = tile_width(by == g.nby - 1 ? 0 : by + 1, V, g.ny);
+    } else {
+        t.tye = 1;
+        t.dw = t.uw = 1;
+    }
+    return t;
+}
+
+template <int DIM>
+__device__ __forceinline__ int dir_local(const TileNb &t, int lxn, int lyn) {
+    const int dbx = (lxn < 0) ? -1 : (lxn >= t.txe) ? 1 : 0;
+    bool far = lxn < -t.lw || lxn >= t.txe + t.rw;
+    int dby = 0;
+    if constexpr (DIM == 2) {
+        dby = (lyn < 0) ? -1 : (lyn >= t.tye) ? 1 : 0;
+        far = far || lyn < -t.dw || lyn >= t.tye + t.uw;
+    }
+    return far ? kFar : (dby + 1) * 3 + (dbx + 1);
+}
+
 // |v|^2 of a particle for the kinetic-energy diagnostic (binary32 squares on
 // the mixed path, FP64 on the FP64 path).
 template <bool MIX, int VDIM>
@@ -621,6 +665,7 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
         const int bx = (DIM == 2) ? (b % g.nbx) : b;
         const int by = (DIM == 2) ? (b / g.nbx) : 0;
         const int x0 = bx << g.tsx, y0 = (DIM == 2) ? (by << g.tsy) : 0;
+        const TileNb tn = tile_nb<DIM>(g, bx, by);
         if (threadIdx.x < kTab) sCnt[threadIdx.x] = 0;
         load_e_tile<R, double, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
         __syncthreads();
@@ -692,12 +737,11 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
                 int lx, ly, sx, sy;
                 good = advance<MIX, DIM, VDIM>(q, g, pc, sE, ex_w, ey_w, x0, y0, lx, ly, sx, sy) && good;
                 if (!good) atomicOr(&sErr, ERR_DOMAIN);
-                const int nbx_new = q.ix >> g.tsx, nby_new = (DIM == 2) ? (q.iy >> g.tsy) : 0;
-                const int code = dir_code(g, bx, by, nbx_new, nby_new);
+                const int code = dir_local<DIM>(tn, lx + sx, ly + sy);
                 if (code < kFar) {
                     atomicAdd(&sCnt[((k % kBlock) >> 6) * kDirs + code], 1);
                 } else {
-                    const int nbk = nby_new * g.nbx + nbx_new;
+                    const int nbk = ((DIM == 2) ? (q.iy >> g.tsy) * g.nbx : 0) + (q.ix >> g.tsx);
                     atomicAdd(&farcnt[nbk], 1);
                     atomicAdd(&tot[nbk], 1);
                 }
@@ -725,9 +769,8 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
                     int lx, ly, sx, sy;
                     good = advance<MIX, DIM, VDIM>(q, g, pc, sE, ex_w, ey_w, x0, y0, lx, ly, sx, sy) && good;
                     if (!good) atomicOr(&sErr, ERR_DOMAIN);
-                    const int nbx_new = q.ix >> g.tsx, nby_new = (DIM == 2) ? (q.iy >> g.tsy) : 0;
-                    nbk = nby_new * g.nbx + nbx_new;
-                    code = dir_code(g, bx, by, nbx_new, nby_new);
+                    code = dir_local<DIM>(tn, lx + sx, ly + sy);
+                    if (code == kFar) nbk = ((DIM == 2) ? (q.iy >> g.tsy) * g.nbx : 0) + (q.ix >> g.tsx);
                 }
                 uint64_t rem = __ballot(code >= 0 && code < kFar);
                 while (rem) {
@@ -810,6 +853,7 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
         const int bx = (DIM == 2) ? (b % g.nbx) : b;
         const int by = (DIM == 2) ? (b / g.nbx) : 0;
         const int x0 = bx << g.tsx, y0 = (DIM == 2) ? (by << g.tsy) : 0;
+        const TileNb tn = tile_nb<DIM>(g, bx, by);
         for (int t2 = threadIdx.x; t2 < wx * wy; t2 += blockDim.x) sA[t2] = (A)0;
         // first slot of each (wave, direction) tally of this bucket: inside the
         // destination bucket the tallies of its sources follow direction order,
@@ -844,8 +888,8 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
         const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
         const int span = i1 - i0;
         // cells of this tile (the last tile of an axis may be cut by the grid edge)
-        const float txe = (float)min(1 << g.tsx, g.nx - x0);
-        const float tye = (DIM == 2) ? (float)min(1 << g.tsy, g.ny - y0) : 1.0f;
+        const float txe = (float)tn.txe;
+        const float tye = (float)tn.tye;
         double ke = 0.0, px = 0.0;
         constexpr int CH = kBlock * U;
         Raw<MIX> ra[U], rb[U];
@@ -873,9 +917,8 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                     const double v2n = vsq<MIX, VDIM>(q);
                     ke += 0.5 * (v2o + v2n);
                     px += (double)q.vx;
-                    const int nbx_new = q.ix >> g.tsx, nby_new = (DIM == 2) ? (q.iy >> g.tsy) : 0;
-                    nbk = nby_new * g.nbx + nbx_new;
-                    code = dir_code(g, bx, by, nbx_new, nby_new);
+                    code = dir_local<DIM>(tn, lx + sx, ly + sy);
+                    if (code == kFar) nbk = ((DIM == 2) ? (q.iy >> g.tsy) * g.nbx : 0) + (q.ix >> g.tsx);
                     if (code == kStay) {
                         const float ux = (float)(q.ix - x0) + (float)q.fx;
                         const float mx = fminf(ux, txe - ux) - pc.deep;
