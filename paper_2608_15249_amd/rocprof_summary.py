@@ -3,8 +3,8 @@
 Usage:
   python -m paper_2608_15249_amd.rocprof_summary trace <results.db> [--cmd "..."]
   python -m paper_2608_15249_amd.rocprof_summary traffic <fetch.db> <write.db> \
-        --kernel k_step_push --copy-bytes N [--cmd "..."] [--tag mixed] \
-        [--merge-into profiles/step_push_<workload>_traffic.json --tile 8x8]
+        --kernel k_step --copy-bytes N [--cmd "..."] [--tag mixed] \
+        [--merge-into profiles/step_push_<workload>_traffic.json --tile 8x8 --main k_step_push]
 
 `trace` prints per-kernel call counts and average/total durations. `traffic`
 turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch, summed over the counter
@@ -83,6 +83,7 @@ def main():
     f.add_argument("--tag", default="")
     f.add_argument("--merge-into", default="")
     f.add_argument("--tile", default="")
+    f.add_argument("--main", default="", help="kernel (name prefix) whose bytes are the headline")
     a = ap.parse_args()
     if a.cmd_name == "trace":
         if a.cmd:
@@ -123,8 +124,9 @@ def main():
         d["note"] = ("HBM bytes per launch of the step kernels; FETCH_SIZE and WRITE_SIZE (KiB per dispatch, "
                      "summed over counter instances) scaled so that the plain copy kernel k_copy_bytes of the "
                      "same run reads/writes its known size")
-        main_k = [k for k in res["kernels"]]
-        d[a.tag] = {"hbm_bytes_per_launch": res["kernels"][main_k[0]]["hbm_bytes_per_launch"] if main_k else None,
+        main_k = [k for k in res["kernels"] if k.startswith(a.main or a.kernel)]
+        d[a.tag] = {"kernel": main_k[0] if main_k else None,
+                    "hbm_bytes_per_launch": res["kernels"][main_k[0]]["hbm_bytes_per_launch"] if main_k else None,
                     "detail": res}
         with open(a.merge_into, "w") as fh:
             json.dump(d, fh, indent=1)
