@@ -28,6 +28,10 @@ namespace apic {
 namespace {
 
 constexpr int kBatchMaxNx = 1024;
+#ifndef APIC_BATCH_U
+#define APIC_BATCH_U 8
+#endif
+constexpr int kBatchU = APIC_BATCH_U;   // particles per thread per pipeline stage
 
 struct RepP {
     int nx, nitems, item0, p0;   // grid nodes, work items, first item, first particle
@@ -53,6 +57,17 @@ struct BatchP {
 
 enum { MODE_DEPOSIT = 0, MODE_HALF = 1, MODE_STEP = 2 };
 
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform_f(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ int64_t uniform_l(int64_t v) {
+    const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ double uniform_d(double v) { return __longlong_as_double(uniform_l(__double_as_longlong(v))); }
+
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_batch(BatchP bp, int32_t *cell, float *ox, float *vx, double *E,
                                                   unsigned long long *acc, double *diag, int64_t *rho_out) {
@@ -73,10 +88,27 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchP bp, int32_t *cell, floa
     for (;;) {
         if (threadIdx.x == 0) sItem = atomicAdd(bp.head, 1);
         __syncthreads();
-        const int item = sItem;
+        // uniform across the block: the item and replica records become scalar
+        // loads, so per-item constants never wait behind the particle loads
+        const int item = __builtin_amdgcn_readfirstlane(sItem);
         if (item >= bp.n_items) break;
-        const Item it = bp.items[item];
-        const RepP rp = bp.reps[it.r];
+        // per-item constants moved to scalar registers once, before the particle
+        // loop (a value still pending from a vector load would make every wait
+        // inside the loop also wait for the prefetched particle loads)
+        Item it = bp.items[item];
+        it.r = uniform_i(it.r);
+        it.p0 = uniform_i(it.p0);
+        it.cnt = uniform_i(it.cnt);
+        RepP rp = bp.reps[it.r];
+        rp.nx = uniform_i(rp.nx);
+        rp.nitems = uniform_i(rp.nitems);
+        rp.item0 = uniform_i(rp.item0);
+        rp.n = uniform_i(rp.n);
+        rp.g0 = uniform_l(rp.g0);
+        rp.dtdx = uniform_f(rp.dtdx);
+        rp.dx = uniform_d(rp.dx);
+        rp.acc_scale = uniform_d(rp.acc_scale);
+        rp.mass = uniform_d(rp.mass);
         Geo g{};
         g.dim = 1;
         g.vdim = 1;
@@ -94,36 +126,78 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchP bp, int32_t *cell, floa
         }
         __syncthreads();
         double ke = 0.0, px = 0.0;
-        for (int k = threadIdx.x; k < it.cnt; k += blockDim.x) {
-            const int i = it.p0 + k;
-            Pt<true> q;
-            bool ok = load_pt<true, 1, 1>(ps, i, g, q);
-            if constexpr (MODE == MODE_DEPOSIT) {
-                unsigned long long w[4];
-                dep_weights<true, 1>(q, g, w);
-                atomicAdd(&sA[q.ix], w[0]);
-                atomicAdd(&sA[q.ix + 1 == rp.nx ? 0 : q.ix + 1], w[1]);
-            } else {
-                float ex, ey;
-                gather_lds<float, 1>(sE, rp.nx + 1, rp.nx + 1, q.ix, 0, q.fx, q.fy, ex, ey);
-                const double v2o = (double)(q.vx * q.vx);
-                boris<float, 1>(q.vx, q.vy, ex, ey, pc.af, pc.tf, pc.sf);
-                if constexpr (MODE == MODE_STEP) {
-                    const double v2n = (double)(q.vx * q.vx);
-                    ke += 0.5 * (v2o + v2n);
-                    px += (double)q.vx;
-                    int sx, sy;
-                    ok = move_pt<true, 1>(q, g, pc, sx, sy) && ok;
+        // kBatchU particles per thread per stage, each stage's words loaded one
+        // stage ahead of their use (indices clamped into the item, so every
+        // load is in bounds): enough loads in flight per wave to cover the
+        // memory latency with the few waves a replica chunk gives a CU
+        struct W3 {
+            int32_t c[kBatchU];
+            float o[kBatchU], v[kBatchU];
+        };
+        constexpr int CH = kBlock * kBatchU;
+        auto fetch = [&](int base, W3 &r) {
+#pragma unroll
+            for (int j = 0; j < kBatchU; ++j) {
+                const int i = it.p0 + min(base + j * kBlock + (int)threadIdx.x, it.cnt - 1);
+                r.c[j] = cell[i];
+                r.o[j] = ox[i];
+                r.v[j] = vx[i];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        auto process = [&](int base, const W3 &r) {
+#pragma unroll
+            for (int j = 0; j < kBatchU; ++j) {
+                const int k = base + j * kBlock + threadIdx.x;
+                if (k >= it.cnt) continue;
+                const int i = it.p0 + k;
+                Pt<true> q;
+                q.ix = r.c[j];
+                q.iy = 0;
+                q.fx = r.o[j];
+                q.fy = 0.0f;
+                q.vx = r.v[j];
+                q.vy = q.vz = 0.0f;
+                bool ok = (unsigned)q.ix < (unsigned)rp.nx && q.fx >= 0.0f && q.fx < 1.0f;
+                if (!ok) {
+                    q.ix = 0;
+                    q.fx = 0.0f;
+                }
+                if constexpr (MODE == MODE_DEPOSIT) {
                     unsigned long long w[4];
                     dep_weights<true, 1>(q, g, w);
                     atomicAdd(&sA[q.ix], w[0]);
                     atomicAdd(&sA[q.ix + 1 == rp.nx ? 0 : q.ix + 1], w[1]);
-                    cell[i] = q.ix;
-                    ox[i] = q.fx;
+                } else {
+                    float ex, ey;
+                    gather_lds<float, 1>(sE, rp.nx + 1, rp.nx + 1, q.ix, 0, q.fx, q.fy, ex, ey);
+                    const double v2o = (double)(q.vx * q.vx);
+                    boris<float, 1>(q.vx, q.vy, ex, ey, pc.af, pc.tf, pc.sf);
+                    if constexpr (MODE == MODE_STEP) {
+                        const double v2n = (double)(q.vx * q.vx);
+                        ke += 0.5 * (v2o + v2n);
+                        px += (double)q.vx;
+                        int sx, sy;
+                        ok = move_pt<true, 1>(q, g, pc, sx, sy) && ok;
+                        unsigned long long w[4];
+                        dep_weights<true, 1>(q, g, w);
+                        atomicAdd(&sA[q.ix], w[0]);
+                        atomicAdd(&sA[q.ix + 1 == rp.nx ? 0 : q.ix + 1], w[1]);
+                        cell[i] = q.ix;
+                        ox[i] = q.fx;
+                    }
+                    vx[i] = q.vx;
                 }
-                vx[i] = q.vx;
+                if (!ok) atomicOr(&sErr, ERR_DOMAIN);
             }
-            if (!ok) atomicOr(&sErr, ERR_DOMAIN);
+        };
+        W3 ra, rb;
+        if (it.cnt > 0) fetch(0, ra);
+        for (int base = 0; base < it.cnt; base += 2 * CH) {
+            if (base + CH < it.cnt) fetch(base + CH, rb);
+            process(base, ra);
+            if (base + 2 * CH < it.cnt) fetch(base + 2 * CH, ra);
+            if (base + CH < it.cnt) process(base + CH, rb);
         }
         __syncthreads();
         if constexpr (MODE == MODE_HALF) continue;
