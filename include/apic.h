@@ -279,7 +279,8 @@ typedef struct {
     double *E;
 } apic_batch_state;
 
-/* chunk: particles per work item (0 = 8192). Fails with APIC_EINVAL for an
+/* chunk: particles per work item (0 = 8192; at most 65535, larger values are
+ * clamped; at least 256). Fails with APIC_EINVAL for an
  * invalid replica (nx outside 2..1024, n < 0, lx <= 0) or a total particle
  * count above INT32_MAX - 1. Allocates the context's device tables. */
 apic_status apic_batch_create(const apic_replica *reps, int nrep, double dt, double qm, double rho_ion, int chunk,
@@ -318,7 +319,7 @@ const char *apic_batch_last_error(const apic_batch *b);
  *   bucket_start and perm are ignored. Cache key: dim, vdim, nx, ny,
  *   precision and floor(log2(particles per cell)).
  * apic_batch_autotune_chunk: work-item size (particles per item, 1024 ..
- *   65536) for apic_batch_create. st: the packed initial state (cell, ox, vx;
+ *   65535) for apic_batch_create. st: the packed initial state (cell, ox, vx;
  *   E is ignored). Cache key: total particles and replica count. */
 apic_status apic_autotune_tiles(const apic_grid_desc *desc, const apic_particles *p, int nsteps, int *tile_x,
                                 int *tile_y, double *ms_per_step, void *stream);

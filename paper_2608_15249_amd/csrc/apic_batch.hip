@@ -32,6 +32,13 @@ constexpr int kBatchMaxNx = 1024;
 #define APIC_BATCH_U 8
 #endif
 constexpr int kBatchU = APIC_BATCH_U;   // particles per thread per pipeline stage
+// LDS deposit word of cell j: the sum W_j of the right-node weights w1 < 2^32
+// of its particles in the low 48 bits, their count in the high 16 bits; a work
+// item holds at most kBatchMaxChunk particles, so neither field overflows.
+constexpr int kCountShift = 48;
+constexpr unsigned long long kCountUnit = 1ull << kCountShift;
+constexpr unsigned long long kSumMask = kCountUnit - 1;
+constexpr int kBatchMaxChunk = (1 << 16) - 1;
 
 struct RepP {
     int nx, nitems, item0, p0;   // grid nodes, work items, first item, first particle
@@ -166,8 +173,7 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchP bp, int32_t *cell, floa
                 if constexpr (MODE == MODE_DEPOSIT) {
                     unsigned long long w[4];
                     dep_weights<true, 1>(q, g, w);
-                    atomicAdd(&sA[q.ix], w[0]);
-                    atomicAdd(&sA[q.ix + 1 == rp.nx ? 0 : q.ix + 1], w[1]);
+                    atomicAdd(&sA[q.ix], w[1] + kCountUnit);
                 } else {
                     float ex, ey;
                     gather_lds<float, 1>(sE, rp.nx + 1, rp.nx + 1, q.ix, 0, q.fx, q.fy, ex, ey);
@@ -181,8 +187,7 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchP bp, int32_t *cell, floa
                         ok = move_pt<true, 1>(q, g, pc, sx, sy) && ok;
                         unsigned long long w[4];
                         dep_weights<true, 1>(q, g, w);
-                        atomicAdd(&sA[q.ix], w[0]);
-                        atomicAdd(&sA[q.ix + 1 == rp.nx ? 0 : q.ix + 1], w[1]);
+                        atomicAdd(&sA[q.ix], w[1] + kCountUnit);
                         cell[i] = q.ix;
                         ox[i] = q.fx;
                     }
@@ -201,8 +206,12 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchP bp, int32_t *cell, floa
         }
         __syncthreads();
         if constexpr (MODE == MODE_HALF) continue;
+        // node j receives w0 = 2^S - w1 from each particle of cell j and w1 from
+        // each particle of cell j-1: I_j = 2^S count_j - W_j + W_{j-1}
+        // (modulo 2^64, exact: the same integers as two atomics per particle)
         for (int i = threadIdx.x; i < rp.nx; i += blockDim.x) {
-            const unsigned long long v = sA[i];
+            const unsigned long long a = sA[i], b = sA[i == 0 ? rp.nx - 1 : i - 1];
+            const unsigned long long v = ((a >> kCountShift) << bp.S) - (a & kSumMask) + (b & kSumMask);
             if (v) atomicAdd(&acc[rp.g0 + i], v);
         }
         if constexpr (MODE == MODE_STEP) {
@@ -359,7 +368,8 @@ apic_status apic_batch_create(const apic_replica *reps, int nrep, double dt, dou
     if (!reps || !out || nrep <= 0 || !(dt > 0) || qm == 0.0 || !std::isfinite(qm)) return APIC_EINVAL;
     *out = nullptr;
     if (chunk <= 0) chunk = 8192;
-    if (chunk < kBlock || chunk > (1 << 24)) return APIC_EINVAL;
+    if (chunk < kBlock) return APIC_EINVAL;
+    chunk = std::min(chunk, kBatchMaxChunk);
     apic_batch *b = new (std::nothrow) apic_batch();
     if (!b) return APIC_ENOMEM;
     b->nrep = nrep;

@@ -234,7 +234,7 @@ apic_status apic_batch_autotune_chunk(const apic_replica *reps, int nrep, double
         }
     }
     hipStream_t s = (hipStream_t)stream;
-    const int cands[] = {1024, 2048, 4096, 8192, 16384, 32768, 65536};
+    const int cands[] = {1024, 2048, 4096, 8192, 16384, 32768, 65535};
     double best = INFINITY;
     int pick = 0;
     for (int ch : cands) {

@@ -154,7 +154,7 @@ def test_batch_autotune_chunk_picks_a_candidate_and_keeps_results(torch):
     with the pick gives the same particle and field bits as any other chunk."""
     from paper_2608_15249_amd.sim import BatchSimulation
     a = BatchSimulation(REPS, chunk="auto")
-    assert a.chunk in (1024, 2048, 4096, 8192, 16384, 32768, 65536)
+    assert a.chunk in (1024, 2048, 4096, 8192, 16384, 32768, 65535)
     assert a.tune_ms is not None and a.tune_ms > 0
     again = BatchSimulation(REPS, chunk="auto")
     assert again.chunk == a.chunk and again.tune_ms == -1.0   # process cache
