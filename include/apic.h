@@ -123,7 +123,8 @@ int64_t apic_num_buckets(const apic_ctx *ctx);
 int apic_frac_bits(const apic_ctx *ctx);
 
 /* Counting sort of the particles by bucket (a1): key = tile-major bucket of
- * each particle's cell; histogram, exclusive scan, scatter. Particles end up
+ * each particle's cell; stable radix passes (tallies, exclusive scan,
+ * scatter), the bucket table read off the sorted keys, a gather. Particles end up
  * ordered by ascending bucket, in place; bucket_start is written; perm is
  * written when non-NULL. The order inside a bucket is unspecified. */
 apic_status apic_sort_by_cell(apic_ctx *ctx, apic_particles *p, void *ws, void *stream);

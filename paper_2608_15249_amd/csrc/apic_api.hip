@@ -82,8 +82,7 @@ void layout(apic_ctx *c) {
     c->o_idx2 = take(4 * n);
     c->o_rcnt = take(4 * (int64_t)sort_chunks(n) * sort_table_entries());
     c->o_roff = take(4 * (int64_t)sort_chunks(n) * sort_table_entries());
-    c->o_count = take(4 * nb);
-    c->o_cursor = take(4 * nb);
+    c->o_rpart = take(4 * (int64_t)sort_part_entries());
     c->o_bstart = take(4 * (nb + 1));
     c->o_cnt = take(4 * nb * kStepTab);
     c->o_offs = take(4 * nb * kStepTab);
@@ -376,23 +375,19 @@ apic_status apic_sort_by_cell(apic_ctx *c, apic_particles *p, void *ws, void *st
     const int nb = c->g.nbuckets;
     int32_t *k0 = wsp<int32_t>(ws, c->o_keys), *k1 = wsp<int32_t>(ws, c->o_keys2);
     int32_t *i0 = wsp<int32_t>(ws, c->o_idx), *i1 = wsp<int32_t>(ws, c->o_idx2);
-    int32_t *count = wsp<int32_t>(ws, c->o_count);
-    int32_t *cursor = wsp<int32_t>(ws, c->o_cursor);
     Parts src = parts_of(p), tmp = parts_ws(c, ws);
-    // bucket table from the histogram of keys
-    HIPCHK(c, launch_fill_i32(count, nb, 0, s));
-    HIPCHK(c, launch_keys_hist(c->g, c->mixed, src, c->n, k0, count, c->dev, s));
-    HIPCHK(c, launch_scan(count, p->bucket_start, cursor, nb, c->n, max_per_bucket(c), c->dev, s));
     // stable order by key
     HIPCHK(c, launch_keys_init(c->g, c->mixed, src, c->n, k0, i0, c->dev, s));
     int bits = 1;
     while ((1ll << bits) < (int64_t)nb) ++bits;
     for (int shift = 0; shift < bits; shift += 8) {
         HIPCHK(c, launch_radix_pass(k0, i0, k1, i1, c->n, shift, wsp<int32_t>(ws, c->o_rcnt),
-                                    wsp<int32_t>(ws, c->o_roff), c->dev, s));
+                                    wsp<int32_t>(ws, c->o_roff), wsp<int32_t>(ws, c->o_rpart), c->dev, s));
         std::swap(k0, k1);
         std::swap(i0, i1);
     }
+    // bucket table from the sorted keys
+    HIPCHK(c, launch_bucket_table(k0, c->n, nb, p->bucket_start, max_per_bucket(c), c->dev, s));
     HIPCHK(c, launch_gather_parts(c->g, c->mixed, src, tmp, c->n, i0, p->perm, c->dev, s));
     return copy_parts(c, src, tmp, s);
 }
@@ -530,7 +525,7 @@ apic_status apic_sync_status(apic_ctx *c, void *stream) {
     HIPCHK(c, hipMemcpy(c->dev.err, &zero, sizeof(int), hipMemcpyHostToDevice));
     if (bits & ERR_OVERFLOW)
         return fail(c, APIC_EOVERFLOW, "fixed-point deposit headroom exceeded (too many particles per bucket)");
-    if (bits & ERR_COUNT) return fail(c, APIC_EDOMAIN, "bucket histogram total differs from particle count");
+    if (bits & ERR_COUNT) return fail(c, APIC_EDOMAIN, "bucket totals differ from particle count");
     if (bits & ERR_ORDER)
         return fail(c, APIC_EDOMAIN, "particles not ordered as bucket_start says, or a slot overflowed");
     return fail(c, APIC_EDOMAIN, "non-finite or out-of-range particle coordinate");

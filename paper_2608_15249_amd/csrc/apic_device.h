@@ -405,19 +405,6 @@ __device__ void flush_region(typename AccOf<MIX>::T *acc, const typename AccOf<M
     }
 }
 
-// Wave-aggregated increment of per-key counters.
-__device__ __forceinline__ void count_keys(int32_t *count, int key, bool active) {
-    uint64_t rem = __ballot(active);
-    while (rem) {
-        const int leader = __ffsll((unsigned long long)rem) - 1;
-        const int k = __shfl(key, leader);
-        const uint64_t grp = __ballot(active && key == k);
-        if ((int)__lane_id() == leader) atomicAdd(&count[k], (int)__popcll(grp));
-        rem &= ~grp;
-    }
-}
-
-
 // 1D periodic field by Gauss's law on the half nodes (identical to the FFT
 // solve of the 3-point Laplacian with centred gradient):
 //   E_{j+1/2} = E_{j-1/2} + (rho_j - <rho>) dx,  sum_j E_{j+1/2} = 0,

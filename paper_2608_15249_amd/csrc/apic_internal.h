@@ -12,7 +12,7 @@ enum : int {
     ERR_DOMAIN = 1,    // NaN/Inf or out-of-range particle coordinate
     ERR_ORDER = 2,     // particle outside the tile its bucket says / slot overflow
     ERR_OVERFLOW = 4,  // fixed-point node sums may exceed int64
-    ERR_COUNT = 8,     // histogram total differs from the particle count
+    ERR_COUNT = 8,     // bucket totals differ from the particle count
 };
 
 // Grid geometry and bucket (tile) layout, passed to kernels by value.
@@ -72,19 +72,19 @@ hipError_t launch_set_step(int *step, int v, hipStream_t s);
 hipError_t launch_copy_bytes(void *dst, const void *src, int64_t bytes, hipStream_t s);
 hipError_t launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 
-// general counting sort (arbitrary input order)
-hipError_t launch_keys_hist(const Geo &g, bool mixed, const Parts &p, int64_t n, int32_t *keys,
-                            int32_t *count, const CtxDev &c, hipStream_t s);
-hipError_t launch_scan(int32_t *count, int32_t *start, int32_t *cursor, int nb, int64_t n,
-                       int64_t max_per_bucket, const CtxDev &c, hipStream_t s);
-// stable LSD radix sort of (bucket key, index), then a gather of the arrays
+// general sort (arbitrary input order): stable LSD radix sort of
+// (bucket key, index), the bucket table of the sorted keys, then a gather of
+// the arrays
 hipError_t launch_keys_init(const Geo &g, bool mixed, const Parts &p, int64_t n, int32_t *keys,
                             int32_t *idx, const CtxDev &c, hipStream_t s);
 int sort_chunks(int64_t n);
 int sort_table_entries();
+int sort_part_entries();
 hipError_t launch_radix_pass(const int32_t *kin, const int32_t *iin, int32_t *kout, int32_t *iout,
-                             int64_t n, int shift, int32_t *cnt, int32_t *off, const CtxDev &c,
-                             hipStream_t s);
+                             int64_t n, int shift, int32_t *cnt, int32_t *off, int32_t *part,
+                             const CtxDev &c, hipStream_t s);
+hipError_t launch_bucket_table(const int32_t *sorted_keys, int64_t n, int nb, int32_t *start,
+                               int64_t max_per_bucket, const CtxDev &c, hipStream_t s);
 hipError_t launch_gather_parts(const Geo &g, bool mixed, const Parts &src, const Parts &dst, int64_t n,
                                const int32_t *idx, int32_t *perm, const CtxDev &c, hipStream_t s);
 

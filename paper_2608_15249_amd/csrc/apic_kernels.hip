@@ -240,26 +240,6 @@ __global__ void k_to_f32(const double *src, float *dst, int64_t n) {
         dst[i] = (float)src[i];
 }
 
-// ---- general counting sort: keys + histogram --------------------------------
-template <bool MIX, int DIM, int VDIM>
-__global__ void __launch_bounds__(kBlock) k_keys_hist(Geo g, Parts p, int64_t n, int32_t *keys,
-                                                      int32_t *count, CtxDev c) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t n_up = ((n + 63) / 64) * 64;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_up; i += stride) {
-        bool act = i < n;
-        int key = 0;
-        if (act) {
-            Pt<MIX> q;
-            bool ok = load_pt<MIX, DIM, VDIM>(p, i, g, q);
-            if (!ok) raise_err(c.err, ERR_DOMAIN);
-            key = bucket_of<MIX, DIM>(g, q.ix, q.iy);
-            keys[i] = key;
-        }
-        count_keys(count, key, act);
-    }
-}
-
 // ---- block-wide exclusive scan helper (1024 threads) ------------------------
 // Scans vals[0..nb) into out[0..nb] (out[nb] = total) in chunks of
 // 1024*kPer elements; returns the total in every thread.
@@ -314,20 +294,6 @@ __device__ int64_t block_exclusive_scan(const int32_t *vals, int32_t *out, int n
     if (threadIdx.x == 0) out[nb] = (int32_t)carry;
     __syncthreads();
     return carry;
-}
-
-// ---- exclusive scan over buckets for the general sort (one workgroup) --------
-__global__ void __launch_bounds__(1024) k_scan(int32_t *count, int32_t *start, int32_t *cursor, int nb,
-                                               int64_t n, int64_t max_per, CtxDev c) {
-    __shared__ int64_t sh[32];
-    int bad = 0;
-    int64_t total = block_exclusive_scan(count, start, nb, max_per, bad, sh);
-    if (bad) raise_err(c.err, ERR_OVERFLOW);
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        cursor[b] = start[b];
-        count[b] = 0;
-    }
-    if (threadIdx.x == 0 && total != n) raise_err(c.err, ERR_COUNT);
 }
 
 // ---- step: destination totals -> scan -> per-source offsets -------------------
@@ -387,57 +353,92 @@ __global__ void __launch_bounds__(kBlock) k_radix_count(const int32_t *keys, int
     for (int t = threadIdx.x; t < kSortTab; t += blockDim.x) cnt[(int64_t)blockIdx.x * kSortTab + t] = s[t];
 }
 
-// Exclusive scan of the tallies in (digit, chunk, wave) order (one workgroup).
-__global__ void __launch_bounds__(1024) k_radix_scan(const int32_t *cnt, int32_t *off, int nchunks) {
-    __shared__ int64_t sh[32];
-    __shared__ int64_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int64_t L = (int64_t)kSortTab * nchunks;
-    auto addr = [&](int64_t v) {  // virtual (digit, chunk, wave) index -> table address
-        const int64_t d = v / ((int64_t)nchunks * kWaves);
-        const int64_t r = v - d * (int64_t)nchunks * kWaves;
-        const int64_t ch = r / kWaves, wv = r - ch * kWaves;
-        return ch * kSortTab + wv * kRadix + d;
-    };
-    for (int64_t base = 0; base < L; base += (int64_t)blockDim.x * kScanPer) {
-        int64_t loc[kScanPer];
-        int64_t s = 0;
+// Exclusive scan of the tallies in (digit, chunk, wave) order, in three
+// launches that read the tally table row by row (thread d of a workgroup
+// handles digit d, so every load and store is coalesced): per range of R
+// chunks the digit totals, then (one workgroup) the first slot of every
+// digit in every range, then the offsets inside each range.
+static_assert(kRadix == kBlock, "one thread per digit");
+constexpr int kRadixParts = 256;  // chunk ranges at most
+
+__device__ __forceinline__ void chunk_range(int nchunks, int R, int &c0, int &c1) {
+    c0 = (int)blockIdx.x * R;
+    c1 = min(c0 + R, nchunks);
+}
+
+__global__ void __launch_bounds__(kBlock) k_radix_part(const int32_t *cnt, int nchunks, int R, int32_t *part) {
+    const int d = threadIdx.x;
+    int c0, c1;
+    chunk_range(nchunks, R, c0, c1);
+    int32_t s = 0;
+    for (int ch = c0; ch < c1; ++ch) {
+        const int32_t *row = cnt + (int64_t)ch * kSortTab + d;
 #pragma unroll
-        for (int k = 0; k < kScanPer; ++k) {
-            const int64_t v = base + (int64_t)threadIdx.x * kScanPer + k;
-            loc[k] = (v < L) ? cnt[addr(v)] : 0;
-            s += loc[k];
-        }
-        int64_t inc = s;
-        for (int o = 1; o < 64; o <<= 1) {
-            int64_t y = __shfl_up(inc, o);
-            if (lane >= o) inc += y;
-        }
-        if (lane == 63) sh[w] = inc;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int64_t r = 0;
-            for (int i = 0; i < nw; ++i) {
-                int64_t t = sh[i];
-                sh[i] = r;
-                r += t;
-            }
-            sh[nw] = r;
-        }
-        __syncthreads();
-        int64_t run = carry + sh[w] + inc - s;
-#pragma unroll
-        for (int k = 0; k < kScanPer; ++k) {
-            const int64_t v = base + (int64_t)threadIdx.x * kScanPer + k;
-            if (v < L) off[addr(v)] = (int32_t)run;
-            run += loc[k];
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) carry += sh[nw];
-        __syncthreads();
+        for (int w = 0; w < kWaves; ++w) s += row[w * kRadix];
     }
+    part[blockIdx.x * kRadix + d] = s;
+}
+
+// part[r][d] (digit d's tally in range r) becomes the slot where range r's
+// elements of digit d start: sum of all lower digits plus digit d in ranges
+// before r.
+__global__ void __launch_bounds__(kBlock) k_radix_base(int32_t *part, int P) {
+    __shared__ int32_t sw[kWaves];
+    const int d = threadIdx.x, lane = d & 63, w = d >> 6;
+    int32_t tot = 0;
+#pragma unroll 16
+    for (int r = 0; r < P; ++r) tot += part[r * kRadix + d];
+    int32_t inc = tot;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) sw[w] = inc;
+    __syncthreads();
+    int32_t run = inc - tot;
+    for (int i = 0; i < w; ++i) run += sw[i];
+#pragma unroll 16
+    for (int r = 0; r < P; ++r) {
+        const int32_t t = part[r * kRadix + d];
+        part[r * kRadix + d] = run;
+        run += t;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_radix_off(const int32_t *cnt, const int32_t *part, int nchunks, int R,
+                                                      int32_t *off) {
+    const int d = threadIdx.x;
+    int c0, c1;
+    chunk_range(nchunks, R, c0, c1);
+    int32_t run = part[blockIdx.x * kRadix + d];
+    for (int ch = c0; ch < c1; ++ch) {
+        const int64_t a = (int64_t)ch * kSortTab + d;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const int32_t t = cnt[a + w * kRadix];
+            off[a + w * kRadix] = run;
+            run += t;
+        }
+    }
+}
+
+// Bucket table of the sorted keys: start[b] is the first position whose key
+// is at least b (start[nb] = n). Position i (0 <= i <= n) writes the entries of
+// the buckets in (key[i-1], key[i]], with key[-1] = -1 and key[n] = nb, so each
+// entry has exactly one writer; the clamp keeps keys of out-of-domain
+// particles (already reported) inside the table.
+__global__ void k_bucket_bounds(const int32_t *key, int64_t n, int nb, int32_t *start) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int lo = max(i == 0 ? 0 : key[i - 1] + 1, 0);
+        const int hi = min(i == n ? nb : key[i], nb);
+        for (int b = lo; b <= hi; ++b) start[b] = (int32_t)i;
+    }
+}
+
+// Buckets holding more particles than the fixed-point node sums allow.
+__global__ void k_bucket_check(const int32_t *start, int nb, int64_t max_per, CtxDev c) {
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x)
+        if ((int64_t)start[b + 1] - start[b] > max_per) raise_err(c.err, ERR_OVERFLOW);
 }
 
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const int32_t *kin, const int32_t *iin, int32_t *kout,
@@ -1200,21 +1201,6 @@ hipError_t launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_keys_hist(const Geo &g, bool mixed, const Parts &p, int64_t n, int32_t *keys, int32_t *count,
-                            const CtxDev &c, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    APIC_DISPATCH(g, mixed,
-                  hipLaunchKernelGGL((k_keys_hist<MIX, DIM, VDIM>), dim3(blocks_for(n)), dim3(kBlock), 0, s, g, p, n,
-                                     keys, count, c));
-    return hipGetLastError();
-}
-
-hipError_t launch_scan(int32_t *count, int32_t *start, int32_t *cursor, int nb, int64_t n, int64_t max_per_bucket,
-                       const CtxDev &c, hipStream_t s) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, count, start, cursor, nb, n, max_per_bucket, c);
-    return hipGetLastError();
-}
-
 hipError_t launch_scan_dir(const Geo &g, int32_t *tot, int32_t *start, int64_t n, int64_t max_per_bucket,
                            int step_mode, const CtxDev &c, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_tot, dim3(1), dim3(1024), 0, s, tot, start, g.nbuckets, n, max_per_bucket, step_mode,
@@ -1233,13 +1219,24 @@ hipError_t launch_keys_init(const Geo &g, bool mixed, const Parts &p, int64_t n,
 
 int sort_chunks(int64_t n) { return (int)((n + kSortChunk - 1) / kSortChunk); }
 int sort_table_entries() { return kSortTab; }
+int sort_part_entries() { return kRadixParts * kRadix; }
+
+hipError_t launch_bucket_table(const int32_t *sorted_keys, int64_t n, int nb, int32_t *start, int64_t max_per_bucket,
+                               const CtxDev &c, hipStream_t s) {
+    hipLaunchKernelGGL(k_bucket_bounds, dim3(blocks_for(n + 1)), dim3(kBlock), 0, s, sorted_keys, n, nb, start);
+    hipLaunchKernelGGL(k_bucket_check, dim3(blocks_for(nb)), dim3(kBlock), 0, s, start, nb, max_per_bucket, c);
+    return hipGetLastError();
+}
 
 hipError_t launch_radix_pass(const int32_t *kin, const int32_t *iin, int32_t *kout, int32_t *iout, int64_t n,
-                             int shift, int32_t *cnt, int32_t *off, const CtxDev &c, hipStream_t s) {
+                             int shift, int32_t *cnt, int32_t *off, int32_t *part, const CtxDev &c, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int C = sort_chunks(n);
     hipLaunchKernelGGL(k_radix_count, dim3(C), dim3(kBlock), 0, s, kin, n, shift, cnt);
-    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, s, cnt, off, C);
+    const int R = (C + kRadixParts - 1) / kRadixParts, P = (C + R - 1) / R;
+    hipLaunchKernelGGL(k_radix_part, dim3(P), dim3(kBlock), 0, s, cnt, C, R, part);
+    hipLaunchKernelGGL(k_radix_base, dim3(1), dim3(kBlock), 0, s, part, P);
+    hipLaunchKernelGGL(k_radix_off, dim3(P), dim3(kBlock), 0, s, cnt, part, C, R, off);
     hipLaunchKernelGGL(k_radix_scatter, dim3(C), dim3(kBlock), 0, s, kin, iin, kout, iout, n, shift, off, c);
     return hipGetLastError();
 }
