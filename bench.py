@@ -60,6 +60,35 @@ def load_traffic(precision, workload, tile):
         return None
 
 
+def measure_copy_gbs(torch, nbytes=512 << 20, reps=20):
+    """Device-to-device copy rate (bytes read + bytes written per second) of
+    the runtime's plain copy on a buffer larger than the last-level cache:
+    the practical HBM ceiling the roofline is also compared against."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def with_copy(roof, copy_gbs):
+    roof = dict(roof)
+    roof["copy_gbs"] = copy_gbs
+    roof["frac_of_copy"] = roof["achieved"] / copy_gbs
+    return roof
+
+
 def run_path(precision, w, state, steps, warmup, tile, torch):
     from paper_2608_15249_amd.sim import Simulation
     sim = Simulation(w, precision, state=state, tile=tile)
@@ -94,6 +123,10 @@ def run_path(precision, w, state, steps, warmup, tile, torch):
         "tune_ms_per_step": sim.tune_ms,
         "phase_ms_per_step": {"count": ms[0] / nprof, "scan": ms[1] / nprof, "push": push_ms,
                               "field": ms[3] / nprof},
+        # particle-steps/s of the fused push kernel alone and of the whole
+        # particle part of the step (tallies + scan + push), field excluded
+        "particle_steps_s_by_phase": {"push": n / (push_ms * 1e-3),
+                                      "count+scan+push": n / ((ms[0] + ms[1] + ms[2]) / nprof * 1e-3)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None if traffic is None else traffic / (push_ms * 1e-3) / 1e9,
@@ -236,11 +269,12 @@ def main():
         print("bench: landau_batch, %d replicas, %d warmup + %d timed steps" % (len(reps), args.warmup, args.steps),
               file=sys.stderr, flush=True)
         b = run_batch(reps, args.steps, args.warmup, chunk, torch)
+        copy_gbs = measure_copy_gbs(torch)
         line = dict(common)
         line.update({"value": b["value"], "ms_per_step": b["ms_per_step"], "dtype": "f32+i64",
                      "config": {"workload": WORKLOADS["landau_batch"], "replicas": len(reps),
                                 "particles": b["particles"], "chunk": b["chunk"], "precision": "mixed"},
-                     "hbm_gbs_step": b["hbm_gbs_step"], "roofline": b["roofline"],
+                     "hbm_gbs_step": b["hbm_gbs_step"], "roofline": with_copy(b["roofline"], copy_gbs),
                      "tune_ms_per_step": b["tune_ms_per_step"]})
         if not args.no_cpu_baseline:
             print("bench: cpu baseline (%d oracle steps per replica)" % args.cpu_steps, file=sys.stderr, flush=True)
@@ -255,6 +289,7 @@ def main():
         print("bench: %s, %s path, %d warmup + %d timed steps" % (args.workload, path, args.warmup, args.steps),
               file=sys.stderr, flush=True)
         res[path] = run_path(path, w, state, args.steps, args.warmup, tile, torch)
+    copy_gbs = measure_copy_gbs(torch)
     head = res.get("mixed") or res[list(res)[0]]
     line = dict(common)
     line.update({
@@ -264,14 +299,17 @@ def main():
         "config": {"workload": WORKLOADS[args.workload], "grid": [w.nx, w.ny], "particles": w.n_particles,
                    "tile": head["tile"], "precision": "mixed" if "mixed" in res else "fp64"},
         "hbm_gbs_step": head["hbm_gbs_step"],
-        "roofline": head["roofline"],
+        "roofline": with_copy(head["roofline"], copy_gbs),
         "phase_ms_per_step": head["phase_ms_per_step"],
+        "particle_steps_s_by_phase": head["particle_steps_s_by_phase"],
         "tune_ms_per_step": head["tune_ms_per_step"],
     })
     if "fp64" in res and "mixed" in res:
         f = res["fp64"]
         line["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "hbm_gbs_step": f["hbm_gbs_step"],
-                        "tile": f["tile"], "roofline": f["roofline"], "phase_ms_per_step": f["phase_ms_per_step"]}
+                        "tile": f["tile"], "roofline": with_copy(f["roofline"], copy_gbs),
+                        "phase_ms_per_step": f["phase_ms_per_step"],
+                        "particle_steps_s_by_phase": f["particle_steps_s_by_phase"]}
         line["mixed_over_fp64"] = head["value"] / f["value"]
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (%d oracle steps)" % args.cpu_steps, file=sys.stderr, flush=True)

@@ -18,6 +18,10 @@ constexpr int kWaves = kBlock / 64;
 
 __device__ __forceinline__ void raise_err(int *err, int bit) { atomicOr(err, bit); }
 
+// s_waitcnt immediate (gfx9 layout) for vmcnt(0) with expcnt and lgkmcnt left
+// at their maximum: waits for every vector-memory load and store in flight.
+constexpr int kWaitVmem = 0x0F70;
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const unsigned lane = __lane_id();
     return (lane == 0) ? 0ull : (~0ull >> (64 - lane));

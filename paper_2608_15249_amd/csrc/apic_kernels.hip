@@ -893,7 +893,22 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
         const float tye = (float)tn.tye;
         double ke = 0.0, px = 0.0;
         constexpr int CH = kBlock * U;
+        // Two schedules over chunks of CH particles.
+        // FP64 (twice the bytes per particle, latency-exposed): a software
+        // pipeline whose loads of chunk c+1 and stores of chunk c-1 are both
+        // issued right after the wait for chunk c's data, so each has one
+        // compute period to complete (one vector-memory counter covers loads
+        // and stores, so a wait for a load also waits for every store issued
+        // before it). Mixed (measured faster): two register sets, the next
+        // chunk's loads issued before the current chunk is processed and its
+        // stores made inside the processing.
+        constexpr bool kPipe = !MIX;
         Raw<MIX> ra[U], rb[U];
+        Pt<MIX> pq[U];      // results of the previous chunk, stored at the next wait
+        int pslot[U], psrc[U];
+        bool pact[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) pact[j] = false;
         auto fetch = [&](Raw<MIX> *r, int base) {
 #pragma unroll
             for (int j = 0; j < U; ++j)
@@ -901,7 +916,20 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
             // keep these loads where they are: issued one chunk ahead of their use
             __builtin_amdgcn_sched_barrier(0);
         };
-        auto process = [&](Raw<MIX> *r, int base) {
+        auto commit = [&]() {
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                if (pact[j]) {
+                    if (pslot[j] >= 0) {
+                        store_pt<MIX, DIM, VDIM>(dst, pslot[j], pq[j]);
+                        if (perm) perm[pslot[j]] = psrc[j];
+                    } else {
+                        atomicOr(&sErr, ERR_ORDER);
+                    }
+                }
+            }
+        };
+        auto process = [&](const Raw<MIX> *r, int base) {
 #pragma unroll
             for (int j = 0; j < U; ++j) {
                 const int k = base + j * kBlock + threadIdx.x;
@@ -994,7 +1022,12 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                     const int v = atomicSub(&farcnt[nbk], 1);
                     slot = (v > 0) ? bstart_new[nbk + 1] - v : -1;
                 }
-                if (act) {
+                if constexpr (kPipe) {
+                    pq[j] = q;
+                    pslot[j] = slot;
+                    psrc[j] = i0 + k;
+                    pact[j] = act;
+                } else if (act) {
                     if (slot >= 0) {
                         store_pt<MIX, DIM, VDIM>(dst, slot, q);
                         if (perm) perm[slot] = i0 + k;
@@ -1005,11 +1038,25 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
             }
         };
         if (span > 0) fetch(ra, 0);
-        for (int base = 0; base < span; base += 2 * CH) {
-            if (base + CH < span) fetch(rb, base + CH);
-            process(ra, base);
-            if (base + 2 * CH < span) fetch(ra, base + 2 * CH);
-            if (base + CH < span) process(rb, base + CH);
+        if constexpr (kPipe) {
+            for (int base = 0; base < span; base += CH) {
+                __builtin_amdgcn_s_waitcnt(kWaitVmem);
+                __builtin_amdgcn_sched_barrier(0);
+                Raw<MIX> rc[U];
+#pragma unroll
+                for (int j = 0; j < U; ++j) rc[j] = ra[j];
+                commit();
+                fetch(ra, base + CH);  // index clamped to the span: harmless re-reads after the last chunk
+                process(rc, base);
+            }
+            commit();
+        } else {
+            for (int base = 0; base < span; base += 2 * CH) {
+                if (base + CH < span) fetch(rb, base + CH);
+                process(ra, base);
+                if (base + 2 * CH < span) fetch(ra, base + 2 * CH);
+                if (base + CH < span) process(rb, base + CH);
+            }
         }
         __syncthreads();
         if (threadIdx.x < kWaves) {
