@@ -25,8 +25,9 @@ n0 = 1, immobile uniform ion background rho_ion = +n0.
 Readings where the paper is silent (each listed with its reason in the design
 notes of the repository):
   * node-centred periodic grid X_j = j*dx, linear (CIC) weights;
-  * Poisson: the periodic 5-point (2D) / 3-point (1D) finite-difference
-    Laplacian, solved exactly in Fourier space with the modified wavenumber
+  * Poisson: the periodic 7-point (3D) / 5-point (2D) / 3-point (1D)
+    finite-difference Laplacian, solved exactly in Fourier space with the
+    modified wavenumber
     K^2 = sum_d (2/d_d)^2 sin^2(k_d d_d / 2); the k = 0 mode is zero;
   * E = -(centred difference of phi), i.e. E_hat = -i sin(k d)/d * phi_hat;
   * initial half push: backward, v^{-1/2} = Boris(v^0, E^0, -dt/2);
@@ -77,11 +78,15 @@ def _load():
     sig = {
         "or_deposit_1d": [_i64, _D, _int, _dbl, _dbl, _D],
         "or_deposit_2d": [_i64, _D, _D, _int, _int, _dbl, _dbl, _dbl, _D],
+        "or_deposit_3d": [_i64, _D, _D, _D, _int, _int, _int, _dbl, _dbl, _dbl, _dbl, _D],
+        "or_deposit_q_3d": [_i64, _I32, _I32, _I32, _F, _F, _F, _int, _int, _int, _int, _I64],
+        "or_gather_3d": [_i64, _D, _D, _D, _int, _int, _int, _dbl, _dbl, _dbl, _D, _D, _D, _D, _D, _D],
+        "or_move_3d": [_i64, _D, _D, _D, _D, _D, _D, _dbl, _dbl, _dbl, _dbl],
         "or_deposit_q_1d": [_i64, _I32, _F, _int, _int, _I64],
         "or_deposit_q_2d": [_i64, _I32, _I32, _F, _F, _int, _int, _int, _I64],
         "or_gather_1d": [_i64, _D, _int, _dbl, _D, _D],
         "or_gather_2d": [_i64, _D, _D, _int, _int, _dbl, _dbl, _D, _D, _D, _D],
-        "or_boris": [_i64, _int, _D, _D, _D, _D, _D, _dbl, _dbl, _dbl],
+        "or_boris": [_i64, _int, _D, _D, _D, _D, _D, _D, _dbl, _dbl, _dbl],
         "or_move_1d": [_i64, _D, _D, _dbl, _dbl],
         "or_move_2d": [_i64, _D, _D, _D, _D, _dbl, _dbl, _dbl],
         "or_adj_deposit_1d": [_i64, _D, _int, _dbl, _dbl, _D, _D],
@@ -117,8 +122,9 @@ def _c64(a):
 class Setup:
     """One periodic electrostatic plasma.
 
-    dim: 1 or 2 spatial dimensions; vdim: 1, 2 or 3 velocity components.
-    nx, ny: grid nodes per axis (ny = 1 in 1D); Lx, Ly: box lengths.
+    dim: 1, 2 or 3 spatial dimensions; vdim: 1, 2 or 3 velocity components
+    (3 when dim = 3). nx, ny, nz: grid nodes per axis (ny = 1 in 1D, nz = 1
+    below 3D); Lx, Ly, Lz: box lengths.
     n_particles: number of macro-electrons N. Macro charge Q = -n0 V / N and
     mass M = n0 V / N (so q/m = -1); ions are a uniform +n0 background."""
     dim: int
@@ -132,6 +138,8 @@ class Setup:
     qm: float = -1.0
     bz: float = 0.0
     n0: float = 1.0
+    nz: int = 1
+    Lz: float = 1.0
 
     @property
     def dx(self):
@@ -139,15 +147,19 @@ class Setup:
 
     @property
     def dy(self):
-        return self.Ly / self.ny if self.dim == 2 else 1.0
+        return self.Ly / self.ny if self.dim >= 2 else 1.0
+
+    @property
+    def dz(self):
+        return self.Lz / self.nz if self.dim == 3 else 1.0
 
     @property
     def volume(self):
-        return self.Lx * (self.Ly if self.dim == 2 else 1.0)
+        return self.Lx * (self.Ly if self.dim >= 2 else 1.0) * (self.Lz if self.dim == 3 else 1.0)
 
     @property
     def dV(self):
-        return self.dx * (self.dy if self.dim == 2 else 1.0)
+        return self.dx * self.dy * self.dz
 
     @property
     def Q(self):
@@ -163,7 +175,7 @@ class Setup:
 
     @property
     def grid_shape(self):
-        return (self.ny, self.nx) if self.dim == 2 else (self.nx,)
+        return {1: (self.nx,), 2: (self.ny, self.nx), 3: (self.nz, self.ny, self.nx)}[self.dim]
 
 
 @dataclass
@@ -174,15 +186,16 @@ class State:
     y: Optional[np.ndarray] = None
     vy: Optional[np.ndarray] = None
     vz: Optional[np.ndarray] = None
+    z: Optional[np.ndarray] = None
 
     def copy(self):
         c = lambda a: None if a is None else a.copy()
-        return State(c(self.x), c(self.vx), c(self.y), c(self.vy), c(self.vz))
+        return State(c(self.x), c(self.vx), c(self.y), c(self.vy), c(self.vz), c(self.z))
 
     @staticmethod
-    def from_arrays(x, vx, y=None, vy=None, vz=None):
+    def from_arrays(x, vx, y=None, vy=None, vz=None, z=None):
         c = lambda a: None if a is None else _c64(a).copy()
-        return State(c(x), c(vx), c(y), c(vy), c(vz))
+        return State(c(x), c(vx), c(y), c(vy), c(vz), c(z))
 
 
 # ---------------------------------------------------------------------------
@@ -195,11 +208,19 @@ def deposit(s: Setup, st: State) -> np.ndarray:
     n = st.x.shape[0]
     rho = np.full(s.grid_shape, s.rho_ion, dtype=np.float64)
     c = s.Q / s.dV
-    if s.dim == 1:
-        L.or_deposit_1d(n, _p(st.x, _D), s.nx, s.dx, c, _p(rho, _D))
-    else:
-        L.or_deposit_2d(n, _p(st.x, _D), _p(st.y, _D), s.nx, s.ny, s.dx, s.dy, c, _p(rho, _D))
+    _deposit_into(L, s, st, c, rho)
     return rho
+
+
+def _deposit_into(L, s: Setup, st: State, c: float, out: np.ndarray) -> None:
+    n = st.x.shape[0]
+    if s.dim == 1:
+        L.or_deposit_1d(n, _p(st.x, _D), s.nx, s.dx, c, _p(out, _D))
+    elif s.dim == 2:
+        L.or_deposit_2d(n, _p(st.x, _D), _p(st.y, _D), s.nx, s.ny, s.dx, s.dy, c, _p(out, _D))
+    else:
+        L.or_deposit_3d(n, _p(st.x, _D), _p(st.y, _D), _p(st.z, _D), s.nx, s.ny, s.nz, s.dx, s.dy, s.dz, c,
+                        _p(out, _D))
 
 
 def deposit_counts(s: Setup, st: State) -> np.ndarray:
@@ -207,17 +228,14 @@ def deposit_counts(s: Setup, st: State) -> np.ndarray:
     L = _load()
     n = st.x.shape[0]
     w = np.zeros(s.grid_shape, dtype=np.float64)
-    if s.dim == 1:
-        L.or_deposit_1d(n, _p(st.x, _D), s.nx, s.dx, 1.0, _p(w, _D))
-    else:
-        L.or_deposit_2d(n, _p(st.x, _D), _p(st.y, _D), s.nx, s.ny, s.dx, s.dy, 1.0, _p(w, _D))
+    _deposit_into(L, s, st, 1.0, w)
     return w
 
 
-def deposit_quantised(s: Setup, ix, ox, frac_bits: int, iy=None, oy=None) -> np.ndarray:
+def deposit_quantised(s: Setup, ix, ox, frac_bits: int, iy=None, oy=None, iz=None, oz=None) -> np.ndarray:
     """Integer CIC deposit: I_j = sum_p w_pj with w = round-half-even(o 2^S).
 
-    ix/iy: int32 cell indices, ox/oy: float32 in-cell offsets in [0,1).
+    ix/iy/iz: int32 cell indices, ox/oy/oz: float32 in-cell offsets in [0,1).
     Returns the int64 node sums; each particle contributes exactly 2^(S*dim)."""
     L = _load()
     ix = np.ascontiguousarray(ix, dtype=np.int32)
@@ -226,6 +244,11 @@ def deposit_quantised(s: Setup, ix, ox, frac_bits: int, iy=None, oy=None) -> np.
     I = np.zeros(s.grid_shape, dtype=np.int64)
     if s.dim == 1:
         L.or_deposit_q_1d(n, _p(ix, _I32), _p(ox, _F), s.nx, frac_bits, _p(I, _I64))
+    elif s.dim == 3:
+        a = [np.ascontiguousarray(v, dtype=np.int32) for v in (iy, iz)]
+        o = [np.ascontiguousarray(v, dtype=np.float32) for v in (oy, oz)]
+        L.or_deposit_q_3d(n, _p(ix, _I32), _p(a[0], _I32), _p(a[1], _I32), _p(ox, _F), _p(o[0], _F),
+                          _p(o[1], _F), s.nx, s.ny, s.nz, frac_bits, _p(I, _I64))
     else:
         iy = np.ascontiguousarray(iy, dtype=np.int32)
         oy = np.ascontiguousarray(oy, dtype=np.float32)
@@ -260,25 +283,52 @@ def centred_kappa(n: int, d: float) -> np.ndarray:
     return np.sin(k * d) / d
 
 
+def _axes(s: Setup):
+    """(n, d) per array axis of the grid, outermost first."""
+    return {1: [(s.nx, s.dx)], 2: [(s.ny, s.dy), (s.nx, s.dx)],
+            3: [(s.nz, s.dz), (s.ny, s.dy), (s.nx, s.dx)]}[s.dim]
+
+
+def _broadcast(v: np.ndarray, axis: int, ndim: int) -> np.ndarray:
+    shape = [1] * ndim
+    shape[axis] = v.shape[0]
+    return v.reshape(shape)
+
+
+def _k2_grid(s: Setup) -> np.ndarray:
+    """Sum over axes of the modified wavenumbers: the symbol of -lap_h."""
+    ax = _axes(s)
+    K2 = 0.0
+    for a, (n, d) in enumerate(ax):
+        K2 = K2 + _broadcast(modified_k2(n, d), a, len(ax))
+    return np.broadcast_to(K2, tuple(n for n, _ in ax)).copy()
+
+
 def solve_potential(s: Setup, rho: np.ndarray) -> np.ndarray:
     """phi with -lap_h phi = rho, sum(phi) = 0 (the k = 0 mode is dropped)."""
-    if s.dim == 1:
-        K2 = modified_k2(s.nx, s.dx)
-        rh = np.fft.fft(rho)
-    else:
-        K2 = modified_k2(s.ny, s.dy)[:, None] + modified_k2(s.nx, s.dx)[None, :]
-        rh = np.fft.fft2(rho)
-    K2 = K2.copy()
+    K2 = _k2_grid(s)
+    rh = np.fft.fftn(rho)
     K2.flat[0] = 1.0
     ph = rh / K2
     ph.flat[0] = 0.0
-    return np.real(np.fft.ifft(ph) if s.dim == 1 else np.fft.ifft2(ph))
+    return np.real(np.fft.ifftn(ph))
 
 
 def solve_field(s: Setup, rho: np.ndarray) -> Tuple[np.ndarray, ...]:
     """E = -centred_grad(phi) of the FD Poisson solution, via FFT.
 
-    Returns (E,) in 1D and (Ex, Ey) in 2D, FP64, on the nodes."""
+    Returns (E,) in 1D, (Ex, Ey) in 2D and (Ex, Ey, Ez) in 3D, FP64, on the
+    nodes."""
+    if s.dim == 3:
+        K2 = _k2_grid(s)
+        K2[0, 0, 0] = 1.0
+        ph = np.fft.fftn(rho) / K2
+        ph[0, 0, 0] = 0.0
+        out = []
+        for a, (n, d) in reversed(list(enumerate(_axes(s)))):   # x, then y, then z
+            Eh = -1j * _broadcast(centred_kappa(n, d), a, 3) * ph
+            out.append(np.real(np.fft.ifftn(Eh)))
+        return tuple(out)
     if s.dim == 1:
         K2 = modified_k2(s.nx, s.dx).copy()
         rh = np.fft.fft(rho)
@@ -323,6 +373,12 @@ def gather(s: Setup, st: State, E) -> Tuple[np.ndarray, ...]:
         Ep = np.empty(n)
         L.or_gather_1d(n, _p(st.x, _D), s.nx, s.dx, _p(_c64(E[0]), _D), _p(Ep, _D))
         return (Ep,)
+    if s.dim == 3:
+        Ex, Ey, Ez = (_c64(e) for e in E)
+        Ep = [np.empty(n) for _ in range(3)]
+        L.or_gather_3d(n, _p(st.x, _D), _p(st.y, _D), _p(st.z, _D), s.nx, s.ny, s.nz, s.dx, s.dy, s.dz,
+                       _p(Ex, _D), _p(Ey, _D), _p(Ez, _D), *[_p(e, _D) for e in Ep])
+        return tuple(Ep)
     Ex, Ey = _c64(E[0]), _c64(E[1])
     Epx = np.empty(n)
     Epy = np.empty(n)
@@ -336,8 +392,10 @@ def boris(s: Setup, st: State, Ep, dt: float) -> None:
     L = _load()
     n = st.x.shape[0]
     Epy = Ep[1] if len(Ep) > 1 else None
+    Epz = Ep[2] if len(Ep) > 2 else None
     L.or_boris(n, s.vdim, _p(st.vx, _D), _p(st.vy, _D), _p(st.vz, _D),
-               _p(_c64(Ep[0]), _D), _p(None if Epy is None else _c64(Epy), _D), s.qm, dt, s.bz)
+               _p(_c64(Ep[0]), _D), _p(None if Epy is None else _c64(Epy), _D),
+               _p(None if Epz is None else _c64(Epz), _D), s.qm, dt, s.bz)
 
 
 def move(s: Setup, st: State) -> None:
@@ -345,22 +403,30 @@ def move(s: Setup, st: State) -> None:
     n = st.x.shape[0]
     if s.dim == 1:
         L.or_move_1d(n, _p(st.x, _D), _p(st.vx, _D), s.dt, s.Lx)
-    else:
+    elif s.dim == 2:
         L.or_move_2d(n, _p(st.x, _D), _p(st.y, _D), _p(st.vx, _D), _p(st.vy, _D), s.dt, s.Lx, s.Ly)
+    else:
+        L.or_move_3d(n, _p(st.x, _D), _p(st.y, _D), _p(st.z, _D), _p(st.vx, _D), _p(st.vy, _D), _p(st.vz, _D),
+                     s.dt, s.Lx, s.Ly, s.Lz)
 
 
 # ---------------------------------------------------------------------------
 # Counting sort by cell bucket (the plain definition: stable sort by key)
 # ---------------------------------------------------------------------------
 
-def bucket_key(ix, iy, tile_x: int, tile_y: int, nx: int) -> np.ndarray:
-    """Bucket index of a cell: tiles of tile_x * tile_y cells, row-major tiles."""
+def bucket_key(ix, iy, tile_x: int, tile_y: int, nx: int, iz=None, tile_z: int = 1, ny: int = 1) -> np.ndarray:
+    """Bucket index of a cell: tiles of tile_x * tile_y (* tile_z) cells,
+    tiles numbered x fastest, then y, then z."""
     nbx = -(-nx // tile_x)
     ix = np.asarray(ix, dtype=np.int64)
     if iy is None:
         return (ix // tile_x).astype(np.int64)
     iy = np.asarray(iy, dtype=np.int64)
-    return (iy // tile_y) * nbx + ix // tile_x
+    key = (iy // tile_y) * nbx + ix // tile_x
+    if iz is None:
+        return key
+    nby = -(-ny // tile_y)
+    return (np.asarray(iz, dtype=np.int64) // tile_z) * (nbx * nby) + key
 
 
 def counting_sort(keys: np.ndarray, n_buckets: int):
@@ -399,7 +465,15 @@ def momentum(s: Setup, st: State) -> np.ndarray:
 
 
 def mode_amplitude(s: Setup, E, mx: int, my: int = 0) -> float:
-    """2|E_par_hat(m)| with E_par = k.E/|k| and E_hat = mean_j E_j e^{-i k.X_j}."""
+    """2|E_par_hat(m)| with E_par = k.E/|k| and E_hat = mean_j E_j e^{-i k.X_j}.
+    In 3D the mode is (mx, my, 0)."""
+    if s.dim == 3:
+        kx = 2 * np.pi * mx / s.Lx
+        ky = 2 * np.pi * my / s.Ly
+        kk = np.hypot(kx, ky)
+        epar = (kx * E[0] + ky * E[1]) / kk
+        Eh = np.fft.fftn(epar) / (s.nx * s.ny * s.nz)
+        return 2.0 * abs(Eh[0, my % s.ny, mx % s.nx])
     if s.dim == 1:
         e = E[0]
         Eh = np.fft.fft(e) / s.nx

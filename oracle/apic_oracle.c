@@ -17,7 +17,7 @@
  * Langdon and Hockney & Eastwood for them without restating formulas. The
  * formulas below are those textbook schemes:
  *   grid: periodic, node-centred, X_j = j*dx, j = 0..nx-1;
- *   shape: linear hat (CIC); in 2D the tensor product of 1D hats;
+ *   shape: linear hat (CIC); in 2D and 3D the tensor product of 1D hats;
  *   deposit: rho_j += (Q/dV) * sum_p W_j(x_p);
  *   gather:  E_p = sum_j W_j(x_p) E_j (same weights as the deposit);
  *   Boris (1970): half electric kick, magnetic rotation, half electric kick.
@@ -25,7 +25,10 @@
  * paper; it is the fixed-point reading of the same deposit, documented at
  * or_deposit_q_1d / or_deposit_q_2d.
  *
- * Layout: 2D grid arrays are row-major [ny][nx], node index j = iy*nx + ix.
+ * Layout: 2D grid arrays are row-major [ny][nx], node index j = iy*nx + ix;
+ * 3D grid arrays are [nz][ny][nx], node index (iz*ny + iy)*nx + ix. The 3D
+ * routines are the Cartesian three-dimensional forms the paper's two-stream
+ * driver calls (scatter B01, gather C01 and Boris A01 "3Dxyz").
  */
 #include <math.h>
 #include <stdint.h>
@@ -95,6 +98,25 @@ void or_deposit_2d(int64_t n, const double *x, const double *y, int nx, int ny,
     }
 }
 
+/* 3D: the eight nodes of the particle's cell, weight (wx * wy) * wz with
+ * wx in {1 - fx, fx} etc. */
+void or_deposit_3d(int64_t n, const double *x, const double *y, const double *z, int nx, int ny, int nz,
+                   double dx, double dy, double dz, double q_over_dv, double *rho)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t i[2], j[2], k[2]; double fx, fy, fz;
+        cic_cell(x[p], nx, dx, &i[0], &fx);
+        cic_cell(y[p], ny, dy, &j[0], &fy);
+        cic_cell(z[p], nz, dz, &k[0], &fz);
+        i[1] = (i[0] + 1) % nx; j[1] = (j[0] + 1) % ny; k[1] = (k[0] + 1) % nz;
+        double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+        for (int c = 0; c < 2; ++c)
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a)
+                    rho[(k[c] * ny + j[b]) * nx + i[a]] += q_over_dv * ((wx[a] * wy[b]) * wz[c]);
+    }
+}
+
 /* ---- quantised deposit (fixed-point reading of the same deposit) --------
  * A particle sits in cell (ix[, iy]) at in-cell offset o in [0,1) held in
  * binary32. Its 1D weights are the integers w1 = round-half-even(o * 2^S) and
@@ -138,6 +160,26 @@ void or_deposit_q_2d(int64_t n, const int32_t *ix, const int32_t *iy, const floa
     }
 }
 
+/* 3D: node weight (w_a * w_b) * w_c of the per-axis integer weights; the
+ * product of three S-bit weights is exact in int64 for S <= 20. */
+void or_deposit_q_3d(int64_t n, const int32_t *ix, const int32_t *iy, const int32_t *iz, const float *ox,
+                     const float *oy, const float *oz, int nx, int ny, int nz, int S, int64_t *I)
+{
+    const int64_t one = (int64_t)1 << S;
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t wx[2], wy[2], wz[2];
+        wx[1] = qweight(ox[p], S); wx[0] = one - wx[1];
+        wy[1] = qweight(oy[p], S); wy[0] = one - wy[1];
+        wz[1] = qweight(oz[p], S); wz[0] = one - wz[1];
+        int64_t i[2] = {ix[p], (ix[p] + 1) % nx}, j[2] = {iy[p], (iy[p] + 1) % ny};
+        int64_t k[2] = {iz[p], (iz[p] + 1) % nz};
+        for (int c = 0; c < 2; ++c)
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a)
+                    I[(k[c] * ny + j[b]) * nx + i[a]] += (wx[a] * wy[b]) * wz[c];
+    }
+}
+
 /* ---- gather (C_Gather) ------------------------------------------------- */
 
 void or_gather_1d(int64_t n, const double *x, int nx, double dx, const double *E, double *Ep)
@@ -165,8 +207,38 @@ void or_gather_2d(int64_t n, const double *x, const double *y, int nx, int ny, d
     }
 }
 
+/* 3D: E_p = sum over the eight nodes of (wx * wy) * wz * E, for each of the
+ * three components. */
+void or_gather_3d(int64_t n, const double *x, const double *y, const double *z, int nx, int ny, int nz,
+                  double dx, double dy, double dz, const double *Ex, const double *Ey, const double *Ez,
+                  double *Epx, double *Epy, double *Epz)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t i[2], j[2], k[2]; double fx, fy, fz;
+        cic_cell(x[p], nx, dx, &i[0], &fx);
+        cic_cell(y[p], ny, dy, &j[0], &fy);
+        cic_cell(z[p], nz, dz, &k[0], &fz);
+        i[1] = (i[0] + 1) % nx; j[1] = (j[0] + 1) % ny; k[1] = (k[0] + 1) % nz;
+        double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+        double ex = 0.0, ey = 0.0, ez = 0.0;
+        for (int c = 0; c < 2; ++c)
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a) {
+                    int64_t m = (k[c] * ny + j[b]) * nx + i[a];
+                    double w = (wx[a] * wy[b]) * wz[c];
+                    ex += w * Ex[m];
+                    ey += w * Ey[m];
+                    ez += w * Ez[m];
+                }
+        Epx[p] = ex;
+        Epy[p] = ey;
+        Epz[p] = ez;
+    }
+}
+
 /* ---- Boris velocity advance (A_Pusher, Boris 1970) ----------------------
- * Uniform magnetic field along z (bz), electric field in the plane (Ez = 0).
+ * Uniform magnetic field along z (bz); the electric field has an x, y and
+ * (3D only) z component.
  *   a   = (q/m) dt / 2
  *   v-  = v + a E
  *   t   = a bz z^ ,  s = 2 t / (1 + |t|^2)
@@ -174,16 +246,20 @@ void or_gather_2d(int64_t n, const double *x, const double *y, int nx, int ny, d
  *   v+  = v- + v' x s
  *   v   = v+ + a E
  * vdim = 1: only vx (no magnetic term); vdim = 2: (vx, vy), bz must be 0;
- * vdim = 3: (vx, vy, vz), vz is unchanged since Ez = 0 and B is along z.
+ * vdim = 3: (vx, vy, vz); the rotation about z leaves vz alone, so vz only
+ * takes the two half kicks of Ez (none when Epz is NULL, Ez = 0 in 2D).
  * Epy may be NULL when vdim = 1 (1D electric field). */
 void or_boris(int64_t n, int vdim, double *vx, double *vy, double *vz,
-              const double *Epx, const double *Epy, double qm, double dt, double bz)
+              const double *Epx, const double *Epy, const double *Epz, double qm, double dt, double bz)
 {
     const double a = qm * dt * 0.5;
     const double t = a * bz;
     const double s = 2.0 * t / (1.0 + t * t);
-    (void)vz;
     for (int64_t p = 0; p < n; ++p) {
+        if (vdim == 3 && Epz) {
+            double mz = vz[p] + a * Epz[p];
+            vz[p] = mz + a * Epz[p];
+        }
         if (vdim == 1) {
             double m1 = vx[p] + a * Epx[p];
             vx[p] = m1 + a * Epx[p];
@@ -215,6 +291,16 @@ void or_move_2d(int64_t n, double *x, double *y, const double *vx, const double 
     for (int64_t p = 0; p < n; ++p) {
         x[p] = wrap(x[p] + vx[p] * dt, Lx);
         y[p] = wrap(y[p] + vy[p] * dt, Ly);
+    }
+}
+
+void or_move_3d(int64_t n, double *x, double *y, double *z, const double *vx, const double *vy,
+                const double *vz, double dt, double Lx, double Ly, double Lz)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        x[p] = wrap(x[p] + vx[p] * dt, Lx);
+        y[p] = wrap(y[p] + vy[p] * dt, Ly);
+        z[p] = wrap(z[p] + vz[p] * dt, Lz);
     }
 }
 

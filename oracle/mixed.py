@@ -4,16 +4,18 @@ TEST INFRASTRUCTURE ONLY.
 
 The mixed representation (not in the paper; it is the fixed-point/binary32
 form of the same CIC-Boris-leapfrog step) holds a particle as an integer cell
-(ix[, iy]), a binary32 in-cell offset o in [0,1) (cell units) and binary32
+(ix[, iy[, iz]]), a binary32 in-cell offset o in [0,1) (cell units) and binary32
 velocities. The push reads the grid field rounded to binary32. Every
 operation below is one IEEE-754 binary32 operation (numpy float32, no fused
 multiply-add), in the order of the textbook formulas of the FP64 oracle:
 
   gather : w00 = (1-fx)(1-fy), w10 = fx(1-fy), w01 = (1-fx)fy, w11 = fx fy,
-           E_p = ((w00 E00 + w10 E10) + w01 E01) + w11 E11   (1D: (1-f)E0 + f E1)
+           E_p = ((w00 E00 + w10 E10) + w01 E01) + w11 E11   (1D: (1-f)E0 + f E1);
+           3D: w_abc = (wx_a wy_b) wz_c, the eight terms added left to right
+           with a (x) fastest, then b (y), then c (z)
   Boris  : a = (q/m) dt/2, t = a bz, s = 2t/(1+t^2) computed in FP64 and
            rounded to binary32; v- = v + aE; v' = v- + v- x t;
-           v+ = v- + v' x s; v = v+ + aE
+           v+ = v- + v' x s; v = v+ + aE (in 3D vz takes the two kicks of Ez)
   move   : o' = o + v * fl32(dt/dx); k = floor(o'); o' = o' - k;
            if o' >= 1 then o' = o' - 1, k = k + 1; cell = (cell + k) mod n.
 The deposit of the result is oracle.deposit_quantised (exact integers).
@@ -23,6 +25,27 @@ from __future__ import annotations
 import numpy as np
 
 f32 = np.float32
+
+
+def _gather3(ix, iy, iz, fx, fy, fz, E32, nx, ny, nz):
+    one = f32(1.0)
+    i = (ix, (ix + 1) % nx)
+    j = (iy, (iy + 1) % ny)
+    k = (iz, (iz + 1) % nz)
+    wx = (one - fx, fx)
+    wy = (one - fy, fy)
+    wz = (one - fz, fz)
+    out = []
+    for E in E32:
+        acc = None
+        for c in range(2):
+            for b in range(2):
+                for a in range(2):
+                    w = (wx[a] * wy[b]) * wz[c]
+                    term = w * E[k[c], j[b], i[a]]
+                    acc = term if acc is None else (acc + term).astype(f32)
+        out.append(acc.astype(f32))
+    return out
 
 
 def _gather(ix, iy, fx, fy, E32, nx, ny, dim):
@@ -50,20 +73,31 @@ def boris_coeffs(qm: float, dt: float, bz: float):
     return f32(a), f32(t), f32(s)
 
 
-def push(st: dict, E32, *, dim, vdim, nx, ny, dx, dy, qm, dt, bz, dt_scale=1.0, move=True) -> dict:
+def push(st: dict, E32, *, dim, vdim, nx, ny, dx, dy, qm, dt, bz, dt_scale=1.0, move=True,
+         nz=1, dz=1.0) -> dict:
     """One binary32 gather + Boris (+ move) of a mixed state.
 
-    st: dict with ix, iy (int32 or None), ox, oy, vx, vy, vz (float32 or None).
-    E32: tuple of float32 node fields shaped like the grid. Returns a new dict."""
+    st: dict with ix, iy, iz (int32 or None), ox, oy, oz, vx, vy, vz (float32
+    or None). E32: tuple of float32 node fields shaped like the grid. Returns
+    a new dict."""
     ix = st["ix"].astype(np.int64)
-    iy = st["iy"].astype(np.int64) if dim == 2 else None
+    iy = st["iy"].astype(np.int64) if dim >= 2 else None
+    iz = st["iz"].astype(np.int64) if dim == 3 else None
     fx = st["ox"].astype(f32)
-    fy = st["oy"].astype(f32) if dim == 2 else None
+    fy = st["oy"].astype(f32) if dim >= 2 else None
+    fz = st["oz"].astype(f32) if dim == 3 else None
     vx = st["vx"].astype(f32).copy()
     vy = st["vy"].astype(f32).copy() if vdim >= 2 else None
     vz = st["vz"].astype(f32).copy() if vdim >= 3 else None
-    ex, ey = _gather(ix, iy, fx, fy, E32, nx, ny, dim)
+    ez = None
+    if dim == 3:
+        ex, ey, ez = _gather3(ix, iy, iz, fx, fy, fz, E32, nx, ny, nz)
+    else:
+        ex, ey = _gather(ix, iy, fx, fy, E32, nx, ny, dim)
     a, t, s = boris_coeffs(qm, dt * dt_scale, bz)
+    if ez is not None:
+        mz = vz + a * ez
+        vz = (mz + a * ez).astype(f32)
     if vdim == 1:
         m1 = vx + a * ex
         vx = (m1 + a * ex).astype(f32)
@@ -90,15 +124,21 @@ def push(st: dict, E32, *, dim, vdim, nx, ny, dx, dy, qm, dt, bz, dt_scale=1.0, 
             return np.mod(c + k, n).astype(np.int32), o2.astype(f32)
 
         out["ix"], out["ox"] = mv(ix, fx, vx, dx, nx)
-        if dim == 2:
+        if dim >= 2:
             out["iy"], out["oy"] = mv(iy, fy, vy, dy, ny)
+        if dim == 3:
+            out["iz"], out["oz"] = mv(iz, fz, vz, dz, nz)
     return out
 
 
-def positions(st: dict, dx: float, dy: float, dim: int):
-    """FP64 positions (ix + ox) dx of a mixed state (for comparisons)."""
+def positions(st: dict, dx: float, dy: float, dim: int, dz: float = 1.0):
+    """FP64 positions (ix + ox) dx of a mixed state (for comparisons); a
+    third array (z) is returned in 3D."""
     x = (st["ix"].astype(np.float64) + st["ox"].astype(np.float64)) * dx
     y = None
-    if dim == 2:
+    if dim >= 2:
         y = (st["iy"].astype(np.float64) + st["oy"].astype(np.float64)) * dy
+    if dim == 3:
+        z = (st["iz"].astype(np.float64) + st["oz"].astype(np.float64)) * dz
+        return x, y, z
     return x, y

@@ -26,6 +26,9 @@ Workloads (lengths in Debye lengths of the stated v_th; omega_pe = 1):
   paper_two_stream 2D3V, 64 x 64 cells, L = 64, 64 per cell per beam (524,288),
                    beams N(+-3, 1) in v_x, N(0, 1) in v_y, v_z, delta0 = 0.005 at
                    mode (2, 1), dt = 0.05, 800 steps.
+  thermal_3d       3D3V, 128 x 128 x 128 cells, dx = 1, 8 per cell (16,777,216),
+                   Maxwellian v_th = 1 (3 components), uniform positions,
+                   dt = 0.1, 500 steps (the 3D Cartesian form of thermal_2d).
 Beam and thermal positions are iid uniform (no quiet start).
 """
 from __future__ import annotations
@@ -58,6 +61,8 @@ class Workload:
     # beams: list of (drift_x, spread); thermal plasmas use a single (0, v_th)
     beams: list = field(default_factory=lambda: [(0.0, 1.0)])
     spread_perp: Optional[float] = None  # spread of v_y, v_z (default: beam spread)
+    nz: int = 1
+    Lz: float = 1.0
 
     @property
     def dx(self):
@@ -65,7 +70,11 @@ class Workload:
 
     @property
     def dy(self):
-        return self.Ly / self.ny if self.dim == 2 else 1.0
+        return self.Ly / self.ny if self.dim >= 2 else 1.0
+
+    @property
+    def dz(self):
+        return self.Lz / self.nz if self.dim == 3 else 1.0
 
 
 def two_stream_1d(seed: int = 1000) -> Workload:
@@ -94,6 +103,14 @@ def two_stream_2d(seed: int = 1004, nx: int = 256, ppc: int = 16) -> Workload:
 def paper_two_stream(seed: int = 1005, nx: int = 64, ppc_per_beam: int = 64) -> Workload:
     return Workload("paper_two_stream", 2, 3, nx, nx, 64.0, 64.0, 2 * nx * nx * ppc_per_beam, 0.05, 800,
                     seed=seed, mode=(2, 1), delta0=0.005, beams=[(3.0, 1.0), (-3.0, 1.0)])
+
+
+def thermal_3d(seed: int = 1006, nx: int = 128, ppc: int = 8, ny: Optional[int] = None,
+               nz: Optional[int] = None) -> Workload:
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    return Workload("thermal_3d", 3, 3, nx, ny, float(nx), float(ny), nx * ny * nz * ppc, 0.1, 500,
+                    seed=seed, delta0=0.0, beams=[(0.0, 1.0)], nz=nz, Lz=float(nz))
 
 
 @dataclass
@@ -169,6 +186,36 @@ def sample(w: Workload, n: Optional[int] = None):
     return x, y, vx, vy, vz
 
 
+def sample3(w: Workload, n: Optional[int] = None):
+    """3D initial state (x, y, z, vx, vy, vz), FP64: per beam uniform
+    positions in the box, N(drift, spread^2) v_x and N(0, spread_perp^2) v_y,
+    v_z; the seeded mode (mode[0], mode[1], 0) displaces x and y as in
+    sample()."""
+    assert w.dim == 3 and w.vdim == 3
+    n = w.n_particles if n is None else n
+    rng = np.random.Generator(np.random.PCG64(w.seed))
+    nb = len(w.beams)
+    counts = [n // nb + (1 if b < n % nb else 0) for b in range(nb)]
+    cols = [[] for _ in range(6)]
+    for (drift, spread), c in zip(w.beams, counts):
+        sp = spread if w.spread_perp is None else w.spread_perp
+        cols[0].append(rng.uniform(0.0, w.Lx, c))
+        cols[1].append(rng.uniform(0.0, w.Ly, c))
+        cols[2].append(rng.uniform(0.0, w.Lz, c))
+        cols[3].append(rng.normal(drift, spread, c))
+        cols[4].append(rng.normal(0.0, sp, c))
+        cols[5].append(rng.normal(0.0, sp, c))
+    x, y, z, vx, vy, vz = (np.concatenate(c) for c in cols)
+    if w.delta0 != 0.0:
+        kx = TWO_PI * w.mode[0] / w.Lx
+        ky = TWO_PI * w.mode[1] / w.Ly
+        k2 = kx * kx + ky * ky
+        sn = np.sin(kx * x + ky * y)
+        x = x + w.delta0 * kx / k2 * sn
+        y = y + w.delta0 * ky / k2 * sn
+    return _wrap(x, w.Lx), _wrap(y, w.Ly), _wrap(z, w.Lz), vx, vy, vz
+
+
 def to_cell_offset(x: np.ndarray, d: float, n: int):
     """Position -> (int32 cell, float32 offset in [0,1)) on a periodic axis.
 
@@ -184,15 +231,22 @@ def to_cell_offset(x: np.ndarray, d: float, n: int):
     return c, o
 
 
-def pack_cell(ix: np.ndarray, iy: Optional[np.ndarray]) -> np.ndarray:
-    """Mixed-path cell word: iy << 16 | ix (2D) or ix (1D), int32."""
+def pack_cell(ix: np.ndarray, iy: Optional[np.ndarray], iz: Optional[np.ndarray] = None) -> np.ndarray:
+    """Mixed-path cell word, int32: ix (1D), iy << 16 | ix (2D),
+    iz << 20 | iy << 10 | ix (3D, 10 bits per axis)."""
     if iy is None:
         return ix.astype(np.int32)
+    if iz is not None:
+        return ((iz.astype(np.int64) << 20) | (iy.astype(np.int64) << 10) | ix.astype(np.int64)).astype(np.int32)
     return ((iy.astype(np.int64) << 16) | ix.astype(np.int64)).astype(np.int32)
 
 
 def unpack_cell(c: np.ndarray, dim: int):
+    """Inverse of pack_cell: (ix, iy) for dim <= 2 (iy None in 1D), (ix, iy, iz)
+    in 3D."""
     c = np.asarray(c).astype(np.int64)
     if dim == 1:
         return c.astype(np.int32), None
+    if dim == 3:
+        return (c & 0x3FF).astype(np.int32), ((c >> 10) & 0x3FF).astype(np.int32), (c >> 20).astype(np.int32)
     return (c & 0xFFFF).astype(np.int32), (c >> 16).astype(np.int32)
