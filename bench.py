@@ -5,9 +5,11 @@ Default workload (thermal_2d): 2D2V thermal plasma, 512 x 512 cells,
 dx = lambda_D = 1, 64 electrons per cell (16,777,216), Maxwellian v_th = 1,
 uniform positions, immobile ion background, CIC, dt = 0.1 (seeded synthetic
 input). Other workloads (--workload): magnetized_2d3v (1024 x 1024, 32 per
-cell, 33,554,432 electrons, B_z with omega_c/omega_p = 2, dt = 0.05) and
-landau_batch (256 uneven 1D1V Landau-damping replicas advanced by the batched
-path, one graph-replayed persistent launch per step).
+cell, 33,554,432 electrons, B_z with omega_c/omega_p = 2, dt = 0.05),
+thermal_3d (3D3V, 128 x 128 x 128 cells, 8 per cell, 16,777,216 electrons,
+dt = 0.1: the Cartesian 3D form of the coupling loop) and landau_batch (256
+uneven 1D1V Landau-damping replicas advanced by the batched path, one
+graph-replayed persistent launch per step).
 
 One step = one full PIC cycle: gather + Boris + move, deposit (CIC),
 counting sort by tile bucket, periodic Poisson solve and E. The headline value
@@ -113,7 +115,7 @@ def run_path(precision, w, state, steps, warmup, tile, torch):
     push_ms = ms[2] / max(nprof, 1)
     push_bytes = 2 * sb * n
     achieved = push_bytes / (push_ms * 1e-3) / 1e9
-    traffic = load_traffic(precision, "%s_%d" % (w.name, w.nx), sim.tile)
+    traffic = load_traffic(precision, "%s_%d" % (w.name, w.nx), list(sim.tile))
     d = diag.cpu().numpy().reshape(steps, 4)
     out = {
         "value": n * steps / elapsed,
@@ -185,17 +187,24 @@ def run_batch(reps, steps, warmup, chunk, torch):
 def cpu_baseline(w, state, nsteps):
     """Serial FP64 oracle on the same plasma (host, one core)."""
     import oracle as O
-    x, y, vx, vy, vz = state
-    s = O.Setup(w.dim, w.vdim, w.nx, w.Lx, len(x), w.dt, ny=w.ny, Ly=w.Ly, bz=w.bz)
-    st = O.State.from_arrays(x, vx, y, vy, vz)
+    if w.dim == 3:
+        x, y, z, vx, vy, vz = state
+    else:
+        (x, y, vx, vy, vz), z = state, None
+    s = O.Setup(w.dim, w.vdim, w.nx, w.Lx, len(x), w.dt, ny=w.ny, Ly=w.Ly, bz=w.bz, nz=w.nz, Lz=w.Lz)
+    st = O.State.from_arrays(x, vx, y, vy, vz, z)
     E, _ = O.initialise(s, st)
     t0 = time.perf_counter()
     for _ in range(nsteps):
         E, _, _ = O.step(s, st, E)
     t1 = time.perf_counter()
     return {"value": len(x) * nsteps / (t1 - t0), "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "full %dx%d / %d-particle plasma, %d oracle steps (serial C particle loops + numpy FFT, "
-                      "FP64), %.1f s" % (w.nx, w.ny, len(x), nsteps, t1 - t0)}
+            "sample": "full %s / %d-particle plasma, %d oracle steps (serial C particle loops + numpy FFT, "
+                      "FP64), %.1f s" % ("x".join(str(v) for v in _grid(w)), len(x), nsteps, t1 - t0)}
+
+
+def _grid(w):
+    return [w.nx, w.ny, w.nz] if w.dim == 3 else [w.nx, w.ny]
 
 
 def cpu_baseline_batch(reps, nsteps, target_particles=3_000_000):
@@ -226,8 +235,7 @@ def cpu_baseline_batch(reps, nsteps, target_particles=3_000_000):
 def parse_tile(t):
     if t == "auto":
         return "auto"
-    a, b = t.lower().split("x")
-    return (int(a), int(b))
+    return tuple(int(v) for v in t.lower().split("x"))
 
 
 WORKLOADS = {
@@ -236,6 +244,8 @@ WORKLOADS = {
     "magnetized_2d3v": "magnetized_2d3v: 2D3V Maxwellian plasma in uniform B_z (omega_c/omega_p=2), 1024x1024 cells, "
                        "32/cell, 33,554,432 electrons, 1% density perturbation at k=(2pi/64,0), dt=0.05, CIC, "
                        "periodic FFT Poisson",
+    "thermal_3d": "thermal_3d: 3D3V Maxwellian plasma, 128x128x128 cells, 8/cell, 16,777,216 electrons, dt=0.1, "
+                  "CIC (8 nodes), periodic FFT Poisson (7-point)",
     "landau_batch": "landau_batch: 256 independent 1D1V Landau-damping replicas, Nx log-uniform in [32,512], "
                     "particles log-uniform in [1e4,1e6], Maxwellian v_th=1, k=0.5 perturbation, dt=0.1, CIC",
 }
@@ -250,7 +260,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", default="mixed,fp64")
     ap.add_argument("--workload", default="thermal_2d", choices=sorted(WORKLOADS))
-    ap.add_argument("--tile", default="auto", help="sort-bucket tile TXxTY, or auto (autotuner)")
+    ap.add_argument("--tile", default="auto", help="sort-bucket tile TXxTY (TXxTYxTZ in 3D), or auto (autotuner; the default tile in 3D)")
     ap.add_argument("--chunk", default="auto", help="batch work-item size, or auto (autotuner)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -282,7 +292,7 @@ def main():
         print(json.dumps(line), flush=True)
         return
     w = getattr(W, args.workload)()
-    state = W.sample(w)
+    state = W.sample3(w) if w.dim == 3 else W.sample(w)
     tile = parse_tile(args.tile)
     res = {}
     for path in args.paths.split(","):
@@ -296,7 +306,7 @@ def main():
         "value": head["value"],
         "ms_per_step": head["ms_per_step"],
         "dtype": "f32+i64" if "mixed" in res else "f64",
-        "config": {"workload": WORKLOADS[args.workload], "grid": [w.nx, w.ny], "particles": w.n_particles,
+        "config": {"workload": WORKLOADS[args.workload], "grid": _grid(w), "particles": w.n_particles,
                    "tile": head["tile"], "precision": "mixed" if "mixed" in res else "fp64"},
         "hbm_gbs_step": head["hbm_gbs_step"],
         "roofline": with_copy(head["roofline"], copy_gbs),

@@ -28,6 +28,10 @@
  *     eps0 = 1, q/m = -1 for electrons).
  *   - Grids are periodic and node-centred: node j sits at X_j = j*dx.
  *     2D grid arrays are row-major [ny][nx]; a vector field is [dim][ny][nx].
+ *     3D grid arrays are [nz][ny][nx]; a vector field is [3][nz][ny][nx].
+ *     The 3D3V forms are the Cartesian three-dimensional scatter, gather and
+ *     Boris routines the paper's two-stream driver calls (B01, C01, A01 in
+ *     their "3Dxyz" form) with the 7-point finite-difference Poisson solve.
  *   - Return value: APIC_OK or a negative apic_status. No C++ exception
  *     crosses the ABI. apic_last_error() gives a message for the last failure.
  */
@@ -60,8 +64,9 @@ typedef enum {
 
 /* One periodic plasma (one replica). */
 typedef struct {
-    int dim;              /* 1 or 2 spatial dimensions                          */
-    int vdim;             /* velocity components: 1 (dim 1), 2 or 3 (dim 2)     */
+    int dim;              /* 1, 2 or 3 spatial dimensions                       */
+    int vdim;             /* velocity components: 1 (dim 1), 2 or 3 (dim 2),
+                             3 (dim 3)                                          */
     int nx, ny;           /* grid nodes per axis (ny = 1 when dim = 1); 2D
                              grids need nx, ny <= 32768                         */
     double lx, ly;        /* box lengths (ly ignored when dim = 1)              */
@@ -72,19 +77,28 @@ typedef struct {
     double bz;            /* uniform magnetic field along z (needs vdim >= 2)   */
     apic_precision prec;
     int frac_bits;        /* mixed path: S, fixed-point weight bits per axis;
-                             1..32 in 1D, 1..23 in 2D; 0 selects 32 (dim 1) or
-                             20 (dim 2)                                         */
-    int tile_x, tile_y;   /* sort bucket = tile of tile_x * tile_y cells, powers
-                             of two; 0 selects the default for the grid        */
+                             1..32 in 1D, 1..23 in 2D, 1..16 in 3D; 0 selects
+                             32 (dim 1), 20 (dim 2) or 15 (dim 3)               */
+    int tile_x, tile_y;   /* sort bucket = tile of tile_x * tile_y (* tile_z)
+                             cells, powers of two; 0 selects the default for
+                             the grid. A side longer than its axis is cut to
+                             the largest power of two that fits. The fused
+                             push's LDS (E tile + deposit region with a
+                             one-cell halo) must fit 64 KiB                     */
+    int nz;               /* 3D: grid nodes along z, 2..1024 (nx, ny <= 1024
+                             too); 0 or 1 below 3D                              */
+    double lz;            /* 3D: box length along z                             */
+    int tile_z;           /* 3D: bucket tile size along z (0 = default)         */
 } apic_grid_desc;
 
 /* Particle arrays (structure of arrays), all [dev], caller-owned, length n.
- * FP64 path : x (and y when dim = 2) are double positions in [0, L);
- *             vx, vy, vz are double.
- * MIXED path: cell is the packed cell word (iy << 16) | ix in 2D, ix in 1D;
- *             ox (and oy) are binary32 offsets in [0,1) in cell units;
- *             vx, vy, vz are float.
- * Unused components (y/oy in 1D, vy when vdim = 1, vz when vdim < 3) are NULL.
+ * FP64 path : x (and y when dim >= 2, z when dim = 3) are double positions
+ *             in [0, L); vx, vy, vz are double.
+ * MIXED path: cell is the packed cell word: ix in 1D, (iy << 16) | ix in 2D,
+ *             (iz << 20) | (iy << 10) | ix in 3D; ox (and oy, oz) are binary32
+ *             offsets in [0,1) in cell units; vx, vy, vz are float.
+ * Unused components (y/oy in 1D, z/oz below 3D, vy when vdim = 1, vz when
+ * vdim < 3) are NULL.
  * bucket_start [dev, int32, apic_num_buckets()+1] describes the current order:
  *             particles of bucket b occupy [bucket_start[b], bucket_start[b+1]).
  *             Written by apic_sort_by_cell and apic_step; read by apic_deposit,
@@ -100,6 +114,8 @@ typedef struct {
     void *vx, *vy, *vz;
     int32_t *bucket_start;
     int32_t *perm;
+    double *z;            /* 3D, FP64 path */
+    float *oz;            /* 3D, mixed path */
 } apic_particles;
 
 typedef struct apic_ctx apic_ctx;
@@ -121,6 +137,11 @@ int64_t apic_num_buckets(const apic_ctx *ctx);
 
 /* Fixed-point bits S the context uses (mixed path). */
 int apic_frac_bits(const apic_ctx *ctx);
+
+/* Side, in cells, of the context's sort-bucket tile along axis 0 (x), 1 (y)
+ * or 2 (z): 1 along an axis the grid does not have, -1 for a NULL context or
+ * another axis. */
+int apic_tile_size(const apic_ctx *ctx, int axis);
 
 /* Counting sort of the particles by bucket (a1): key = tile-major bucket of
  * each particle's cell; stable radix passes (tallies, exclusive scan,
@@ -220,6 +241,9 @@ apic_status apic_import_state(apic_ctx *ctx, const double *x, const double *y, c
  * of lam_rho), sort (each step's permutation inverted). The derivative of the
  * CIC hat is its slope inside the particle's cell.
  *
+ * The adjoint entry points (and apic_import_state) cover 1D and 2D plasmas;
+ * a 3D context returns APIC_EUNSUPPORTED.
+ *
  * Step checkpointing: apic_adjoint_forward stores the state every `stride`
  * steps in the caller's checkpoint buffer; apic_step_adjoint recomputes one
  * segment of at most `stride` steps at a time from its checkpoint and walks it
@@ -314,7 +338,8 @@ const char *apic_batch_last_error(const apic_batch *b);
  * same shape returns the cached pick with *ms_per_step = -1 (may be NULL).
  * Returns APIC_EINVAL for bad arguments, APIC_EHIP if no candidate ran.
  *
- * apic_autotune_tiles: sort-bucket tile (tile_x, tile_y) for apic_create, over
+ * apic_autotune_tiles: sort-bucket tile (tile_x, tile_y) for apic_create (1D
+ * and 2D; a 3D descriptor returns APIC_EUNSUPPORTED and keeps the default), over
  *   powers of two 4x4 .. 32x32 (2D) or 8 .. 1024 nodes (1D) plus the default
  *   (0, 0). p: unsorted or sorted particles as for apic_sort_by_cell (n > 0);
  *   bucket_start and perm are ignored. Cache key: dim, vdim, nx, ny,

@@ -33,14 +33,16 @@ class GridDesc(ctypes.Structure):
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("dt", ctypes.c_double),
                 ("qm", ctypes.c_double), ("q_macro", ctypes.c_double), ("rho_ion", ctypes.c_double),
                 ("bz", ctypes.c_double), ("prec", ctypes.c_int), ("frac_bits", ctypes.c_int),
-                ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int)]
+                ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int),
+                ("nz", ctypes.c_int), ("lz", ctypes.c_double), ("tile_z", ctypes.c_int)]
 
 
 class ParticlesC(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
                 ("cell", ctypes.c_void_p), ("ox", ctypes.c_void_p), ("oy", ctypes.c_void_p),
                 ("vx", ctypes.c_void_p), ("vy", ctypes.c_void_p), ("vz", ctypes.c_void_p),
-                ("bucket_start", ctypes.c_void_p), ("perm", ctypes.c_void_p)]
+                ("bucket_start", ctypes.c_void_p), ("perm", ctypes.c_void_p),
+                ("z", ctypes.c_void_p), ("oz", ctypes.c_void_p)]
 
 
 class ReplicaC(ctypes.Structure):
@@ -51,7 +53,7 @@ class BatchStateC(ctypes.Structure):
     _fields_ = [("cell", ctypes.c_void_p), ("ox", ctypes.c_void_p), ("vx", ctypes.c_void_p), ("E", ctypes.c_void_p)]
 
 
-EXPORTS = ["apic_create", "apic_destroy", "apic_workspace_size", "apic_num_buckets", "apic_frac_bits",
+EXPORTS = ["apic_create", "apic_destroy", "apic_workspace_size", "apic_num_buckets", "apic_frac_bits", "apic_tile_size",
            "apic_sort_by_cell", "apic_deposit", "apic_field_solve", "apic_gather_push", "apic_step",
            "apic_sync_status", "apic_last_error", "apic_profile_enable", "apic_profile_read",
            "apic_batch_create", "apic_batch_destroy", "apic_batch_sizes", "apic_batch_offsets",
@@ -78,6 +80,7 @@ def load_library(path: str = LIB_PATH):
         "apic_workspace_size": ([vp, P(ctypes.c_size_t)], cint),
         "apic_num_buckets": ([vp], i64),
         "apic_frac_bits": ([vp], cint),
+        "apic_tile_size": ([vp, cint], cint),
         "apic_sort_by_cell": ([vp, P(ParticlesC), vp, vp], cint),
         "apic_deposit": ([vp, P(ParticlesC), vp, vp], cint),
         "apic_field_solve": ([vp, vp, vp, vp, vp, vp, vp], cint),
@@ -126,7 +129,7 @@ class Context:
     """One plasma on the GPU: owns the libapic context and its workspace."""
 
     def __init__(self, *, dim, vdim, nx, ny, lx, ly, dt, n, qm=-1.0, q_macro=None, rho_ion=1.0, bz=0.0,
-                 precision="mixed", frac_bits=0, tile=(0, 0), device="cuda"):
+                 precision="mixed", frac_bits=0, tile=(0, 0), device="cuda", nz=1, lz=1.0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libapic needs a HIP GPU; none is visible")
@@ -135,10 +138,12 @@ class Context:
         self.device = torch.device(device)
         self.mixed = precision == "mixed"
         if q_macro is None:
-            vol = lx * (ly if dim == 2 else 1.0)
+            vol = lx * (ly if dim >= 2 else 1.0) * (lz if dim == 3 else 1.0)
             q_macro = -rho_ion * vol / n
-        self.desc = GridDesc(dim, vdim, nx, ny if dim == 2 else 1, lx, ly if dim == 2 else 1.0, dt, qm, q_macro,
-                             rho_ion, bz, APIC_MIXED if self.mixed else APIC_FP64, frac_bits, tile[0], tile[1])
+        tz = tile[2] if len(tile) > 2 else 0
+        self.desc = GridDesc(dim, vdim, nx, ny if dim >= 2 else 1, lx, ly if dim >= 2 else 1.0, dt, qm, q_macro,
+                             rho_ion, bz, APIC_MIXED if self.mixed else APIC_FP64, frac_bits, tile[0], tile[1],
+                             nz if dim == 3 else 1, lz if dim == 3 else 1.0, tz)
         self.n = int(n)
         h = ctypes.c_void_p()
         st = self.L.apic_create(ctypes.byref(self.desc), self.n, ctypes.byref(h))
@@ -150,9 +155,11 @@ class Context:
         self.ws = torch.empty(max(int(sz.value), 256), dtype=torch.uint8, device=self.device)
         self.nbuckets = int(self.L.apic_num_buckets(self.h))
         self.frac_bits = int(self.L.apic_frac_bits(self.h))
+        self.tile = tuple(int(self.L.apic_tile_size(self.h, a)) for a in range(dim))
         self.dim, self.vdim, self.nx = dim, vdim, nx
-        self.ny = ny if dim == 2 else 1
-        self.G = self.nx * self.ny
+        self.ny = ny if dim >= 2 else 1
+        self.nz = nz if dim == 3 else 1
+        self.G = self.nx * self.ny * self.nz
 
     def __del__(self):
         try:
@@ -339,16 +346,20 @@ class Particles:
         t = ctx.torch
         n, dev = ctx.n, ctx.device
         r = t.float32 if ctx.mixed else t.float64
-        self.x = self.y = self.cell = self.ox = self.oy = None
+        self.x = self.y = self.z = self.cell = self.ox = self.oy = self.oz = None
         if ctx.mixed:
             self.cell = t.zeros(n, dtype=t.int32, device=dev)
             self.ox = t.zeros(n, dtype=t.float32, device=dev)
-            if ctx.dim == 2:
+            if ctx.dim >= 2:
                 self.oy = t.zeros(n, dtype=t.float32, device=dev)
+            if ctx.dim == 3:
+                self.oz = t.zeros(n, dtype=t.float32, device=dev)
         else:
             self.x = t.zeros(n, dtype=t.float64, device=dev)
-            if ctx.dim == 2:
+            if ctx.dim >= 2:
                 self.y = t.zeros(n, dtype=t.float64, device=dev)
+            if ctx.dim == 3:
+                self.z = t.zeros(n, dtype=t.float64, device=dev)
         self.vx = t.zeros(n, dtype=r, device=dev)
         self.vy = t.zeros(n, dtype=r, device=dev) if ctx.vdim >= 2 else None
         self.vz = t.zeros(n, dtype=r, device=dev) if ctx.vdim >= 3 else None
@@ -357,9 +368,9 @@ class Particles:
     def struct(self, perm=None, tiled=True) -> ParticlesC:
         return ParticlesC(self.ctx.n, _ptr(self.x), _ptr(self.y), _ptr(self.cell), _ptr(self.ox), _ptr(self.oy),
                           _ptr(self.vx), _ptr(self.vy), _ptr(self.vz),
-                          _ptr(self.bucket_start) if tiled else None, _ptr(perm))
+                          _ptr(self.bucket_start) if tiled else None, _ptr(perm), _ptr(self.z), _ptr(self.oz))
 
-    def upload(self, x=None, y=None, vx=None, vy=None, vz=None, cell=None, ox=None, oy=None):
+    def upload(self, x=None, y=None, vx=None, vy=None, vz=None, cell=None, ox=None, oy=None, z=None, oz=None):
         t = self.ctx.torch
         dev = self.ctx.device
 
@@ -372,10 +383,13 @@ class Particles:
         put(self.cell, cell)
         put(self.ox, ox)
         put(self.oy, oy)
+        put(self.z, z)
+        put(self.oz, oz)
         put(self.vx, vx)
         put(self.vy, vy)
         put(self.vz, vz)
 
     def download(self):
         g = lambda a: None if a is None else a.cpu().numpy()
-        return {k: g(getattr(self, k)) for k in ("x", "y", "cell", "ox", "oy", "vx", "vy", "vz", "bucket_start")}
+        return {k: g(getattr(self, k))
+                for k in ("x", "y", "z", "cell", "ox", "oy", "oz", "vx", "vy", "vz", "bucket_start")}

@@ -615,7 +615,7 @@ apic_status launch_level(apic_ctx *c, AdjP<R> &P, hipStream_t s) {
     P.cq = (R)(c->d.q_macro / c->dV);
     boris_consts<R>(c, 1.0, P.a, P.t, P.s);
     boris_consts<R>(c, -0.5, P.ah, P.th, P.sh);
-    APIC_DISPATCH(c->g, c->mixed, {
+    APIC_DISPATCH_2D(c->g, c->mixed, {
         if constexpr (std::is_same<R, typename RealOf<MIX>::T>::value)
             hipLaunchKernelGGL((k_adj_level<MIX, DIM, VDIM>), dim3(nblocks(c->n)), dim3(kBlock), 0, s, P);
     });
@@ -624,6 +624,7 @@ apic_status launch_level(apic_ctx *c, AdjP<R> &P, hipStream_t s) {
 }
 
 apic_status check_adj_args(apic_ctx *c, int nsteps, int stride) {
+    if (c->d.dim == 3) return fail(c, APIC_EUNSUPPORTED, "the adjoint covers 1D and 2D plasmas");
     if (nsteps < 0) return fail(c, APIC_EINVAL, "nsteps must be >= 0");
     if (stride < 1) return fail(c, APIC_EINVAL, "checkpoint stride must be >= 1");
     if (c->n < 1) return fail(c, APIC_EINVAL, "the adjoint needs at least one particle");
@@ -737,6 +738,7 @@ extern "C" {
 apic_status apic_import_state(apic_ctx *c, const double *x, const double *y, const double *vx, const double *vy,
                               const double *vz, apic_particles *p, void *stream) {
     if (!c) return APIC_EINVAL;
+    if (c->d.dim == 3) return fail(c, APIC_EUNSUPPORTED, "state import covers 1D and 2D plasmas");
     apic_status st = check_parts(c, p, false);
     if (st != APIC_OK) return st;
     if (!x || (c->d.dim == 2 && !y) || !vx || (c->d.vdim >= 2 && !vy) || (c->d.vdim >= 3 && !vz))
@@ -744,7 +746,7 @@ apic_status apic_import_state(apic_ctx *c, const double *x, const double *y, con
     hipStream_t s = (hipStream_t)stream;
     const double dx = c->d.lx / c->d.nx, dy = c->d.dim == 2 ? c->d.ly / c->d.ny : 1.0;
     const Parts out = parts_of(p);
-    APIC_DISPATCH(c->g, c->mixed,
+    APIC_DISPATCH_2D(c->g, c->mixed,
                   hipLaunchKernelGGL((k_import<MIX, DIM, VDIM>), dim3(nblocks(c->n)), dim3(kBlock), 0, s, c->g, c->n,
                                      dx, dy, x, y, vx, vy, vz, out, c->dev.err));
     HIPCHK(c, hipGetLastError());
@@ -753,6 +755,7 @@ apic_status apic_import_state(apic_ctx *c, const double *x, const double *y, con
 
 apic_status apic_adjoint_sizes(const apic_ctx *c, int nsteps, int stride, size_t *ckpt_bytes, size_t *ws_bytes) {
     if (!c || nsteps < 0 || stride < 1) return APIC_EINVAL;
+    if (c->d.dim == 3) return APIC_EUNSUPPORTED;
     const CkLayout CL = ck_layout(c);
     if (ckpt_bytes) *ckpt_bytes = CL.bytes * (size_t)(n_checkpoints(nsteps, stride) + 1);
     if (ws_bytes) *ws_bytes = adj_layout(c, stride).bytes;

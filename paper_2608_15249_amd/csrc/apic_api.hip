@@ -36,15 +36,23 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 // Default bucket tile: about 4096 particles per bucket (the workgroup's work
 // item), tile side a power of two.
-void default_tiles(const apic_grid_desc &d, int64_t n, int &tsx, int &tsy) {
-    const double cells = (double)d.nx * (d.dim == 2 ? d.ny : 1);
+void default_tiles(const apic_grid_desc &d, int64_t n, int &tsx, int &tsy, int &tsz) {
+    const double cells = (double)d.nx * (d.dim >= 2 ? d.ny : 1) * (d.dim == 3 ? d.nz : 1);
     const double ppc = n > 0 ? (double)n / cells : 1.0;
     double target = 4096.0 / (ppc > 0 ? ppc : 1.0);
     if (target < 1.0) target = 1.0;
+    tsz = 0;
     if (d.dim == 1) {
         tsx = ilog2_floor((int64_t)target);
         if (tsx > 12) tsx = 12;
         tsy = 0;
+    } else if (d.dim == 3) {
+        // cube-like tiles of at most 8 cells per axis (E tile and deposit
+        // region of a workgroup stay within LDS)
+        const int t = ilog2_floor((int64_t)target);
+        tsx = std::min(3, std::max(1, (t + 2) / 3));
+        tsy = std::min(3, std::max(1, (t + 1) / 3));
+        tsz = std::min(3, std::max(1, t / 3));
     } else {
         int t = ilog2_floor((int64_t)target);
         tsx = (t + 1) / 2;
@@ -62,20 +70,23 @@ void layout(apic_ctx *c) {
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     const int dim = c->d.dim, vdim = c->d.vdim;
-    c->o_x = c->o_y = c->o_cell = c->o_ox = c->o_oy = c->o_vx = c->o_vy = c->o_vz = (size_t)-1;
+    c->o_x = c->o_y = c->o_z = c->o_cell = c->o_ox = c->o_oy = c->o_oz = (size_t)-1;
+    c->o_vx = c->o_vy = c->o_vz = (size_t)-1;
     if (c->mixed) {
         c->o_cell = take(4 * n);
         c->o_ox = take(4 * n);
-        if (dim == 2) c->o_oy = take(4 * n);
+        if (dim >= 2) c->o_oy = take(4 * n);
+        if (dim == 3) c->o_oz = take(4 * n);
     } else {
         c->o_x = take(8 * n);
-        if (dim == 2) c->o_y = take(8 * n);
+        if (dim >= 2) c->o_y = take(8 * n);
+        if (dim == 3) c->o_z = take(8 * n);
     }
     c->o_vx = take(r * n);
     if (vdim >= 2) c->o_vy = take(r * n);
     if (vdim >= 3) c->o_vz = take(r * n);
     const int64_t nb = c->g.nbuckets;
-    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny * c->d.nz;
     c->o_keys = take(4 * n);
     c->o_keys2 = take(4 * n);
     c->o_idx = take(4 * n);
@@ -92,10 +103,10 @@ void layout(apic_ctx *c) {
     c->o_deep = take(4 * nb * kDeepTab);
     c->o_acc = take(8 * G);
     c->o_rho = take(8 * G);
-    if (dim == 2) {
-        const int64_t H = (int64_t)(c->d.nx / 2 + 1) * c->d.ny;
+    if (dim >= 2) {
+        const int64_t H = (int64_t)(c->d.nx / 2 + 1) * c->d.ny * c->d.nz;
         c->o_rhat = take(16 * H);
-        c->o_ehat = take(32 * H);
+        c->o_ehat = take(16 * dim * H);
     } else {
         c->o_rhat = c->o_ehat = (size_t)-1;
     }
@@ -107,9 +118,11 @@ Parts parts_of(const apic_particles *p) {
     Parts q;
     q.x = p->x;
     q.y = p->y;
+    q.z = p->z;
     q.cell = p->cell;
     q.ox = p->ox;
     q.oy = p->oy;
+    q.oz = p->oz;
     q.vx = p->vx;
     q.vy = p->vy;
     q.vz = p->vz;
@@ -120,9 +133,11 @@ Parts parts_ws(const apic_ctx *c, void *ws) {
     Parts q;
     q.x = wsp<double>(ws, c->o_x);
     q.y = wsp<double>(ws, c->o_y);
+    q.z = wsp<double>(ws, c->o_z);
     q.cell = wsp<int32_t>(ws, c->o_cell);
     q.ox = wsp<float>(ws, c->o_ox);
     q.oy = wsp<float>(ws, c->o_oy);
+    q.oz = wsp<float>(ws, c->o_oz);
     q.vx = wsp<void>(ws, c->o_vx);
     q.vy = wsp<void>(ws, c->o_vy);
     q.vz = wsp<void>(ws, c->o_vz);
@@ -134,10 +149,11 @@ apic_status check_parts(apic_ctx *c, const apic_particles *p, bool need_bstart) 
     if (p->n != c->n) return fail(c, APIC_EINVAL, "particles.n differs from the context's particle count");
     const int dim = c->d.dim, vdim = c->d.vdim;
     if (c->mixed) {
-        if (!p->cell || !p->ox || (dim == 2 && !p->oy))
-            return fail(c, APIC_EINVAL, "mixed path needs cell, ox (and oy in 2D)");
+        if (!p->cell || !p->ox || (dim >= 2 && !p->oy) || (dim == 3 && !p->oz))
+            return fail(c, APIC_EINVAL, "mixed path needs cell, ox (and oy in 2D and 3D, oz in 3D)");
     } else {
-        if (!p->x || (dim == 2 && !p->y)) return fail(c, APIC_EINVAL, "FP64 path needs x (and y in 2D)");
+        if (!p->x || (dim >= 2 && !p->y) || (dim == 3 && !p->z))
+            return fail(c, APIC_EINVAL, "FP64 path needs x (and y in 2D and 3D, z in 3D)");
     }
     if (!p->vx || (vdim >= 2 && !p->vy) || (vdim >= 3 && !p->vz))
         return fail(c, APIC_EINVAL, "missing velocity component");
@@ -156,9 +172,11 @@ PushC push_coeffs(const apic_ctx *c, double dt_scale, int move) {
     pc.sf = (float)pc.s;
     pc.dt = c->d.dt;
     const double dx = c->d.lx / c->d.nx;
-    const double dy = c->d.dim == 2 ? c->d.ly / c->d.ny : 1.0;
+    const double dy = c->d.dim >= 2 ? c->d.ly / c->d.ny : 1.0;
+    const double dz = c->d.dim == 3 ? c->d.lz / c->d.nz : 1.0;
     pc.dtdx = (float)(c->d.dt / dx);
     pc.dtdy = (float)(c->d.dt / dy);
+    pc.dtdz = (float)(c->d.dt / dz);
     pc.move = move;
     pc.rot = c->d.bz != 0.0;
     pc.deep = 0.25f;
@@ -188,7 +206,7 @@ apic_status field_from_acc(apic_ctx *c, void *acc, bool acc_is_rho, double *E, f
     const double scale = acc_is_rho ? 1.0 : acc_scale(c);
     const double add = acc_is_rho ? 0.0 : c->d.rho_ion;
     const bool mixed_acc = c->mixed && !acc_is_rho;
-    const double G = (double)c->d.nx * c->d.ny;
+    const double G = (double)c->d.nx * c->d.ny * c->d.nz;
     if (c->d.dim == 1) {
         const int step_mode = diag ? 1 : 0;
         HIPCHK(c, launch_field1d(c->g, mixed_acc, acc, scale, add, c->d.rho_ion, c->d.lx / c->d.nx, clear, E, E32,
@@ -200,16 +218,16 @@ apic_status field_from_acc(apic_ctx *c, void *acc, bool acc_is_rho, double *E, f
     double *rho = wsp<double>(ws, c->o_rho);
     void *rhat = wsp<void>(ws, c->o_rhat);
     char *ehat = wsp<char>(ws, c->o_ehat);
-    const size_t H = (size_t)(c->d.nx / 2 + 1) * c->d.ny;
+    const size_t H = (size_t)(c->d.nx / 2 + 1) * c->d.ny * c->d.nz;
     HIPCHK(c, launch_rho(c->g, mixed_acc, acc, rho, scale, add, clear, s));
     FFTCHK(c, hipfftSetStream(c->fwd, s));
     FFTCHK(c, hipfftExecD2Z(c->fwd, (hipfftDoubleReal *)rho, (hipfftDoubleComplex *)rhat));
-    HIPCHK(c, launch_spectral(c->g, rhat, ehat, ehat + 16 * H, c->dev, s));
+    HIPCHK(c, launch_spectral(c->g, rhat, ehat, ehat + 16 * H, c->d.dim == 3 ? ehat + 32 * H : nullptr, c->dev, s));
     HIPCHK(c, launch_finalize(diag ? npush : 0, spectral_blocks(c->g), c->mass, c->dV, G, c->d.rho_ion, diag, we,
                               charge, c->dev, s));
     FFTCHK(c, hipfftSetStream(c->inv, s));
     FFTCHK(c, hipfftExecZ2D(c->inv, (hipfftDoubleComplex *)ehat, (hipfftDoubleReal *)E));
-    if (E32) HIPCHK(c, launch_to_f32(E, E32, 2 * (int64_t)G, s));
+    if (E32) HIPCHK(c, launch_to_f32(E, E32, c->d.dim * (int64_t)G, s));
     return APIC_OK;
 }
 
@@ -219,10 +237,12 @@ apic_status copy_parts(apic_ctx *c, const Parts &dst, const Parts &src, hipStrea
     if (c->mixed) {
         HIPCHK(c, launch_copy_bytes(dst.cell, src.cell, 4 * n, s));
         HIPCHK(c, launch_copy_bytes(dst.ox, src.ox, 4 * n, s));
-        if (c->d.dim == 2) HIPCHK(c, launch_copy_bytes(dst.oy, src.oy, 4 * n, s));
+        if (c->d.dim >= 2) HIPCHK(c, launch_copy_bytes(dst.oy, src.oy, 4 * n, s));
+        if (c->d.dim == 3) HIPCHK(c, launch_copy_bytes(dst.oz, src.oz, 4 * n, s));
     } else {
         HIPCHK(c, launch_copy_bytes(dst.x, src.x, 8 * n, s));
-        if (c->d.dim == 2) HIPCHK(c, launch_copy_bytes(dst.y, src.y, 8 * n, s));
+        if (c->d.dim >= 2) HIPCHK(c, launch_copy_bytes(dst.y, src.y, 8 * n, s));
+        if (c->d.dim == 3) HIPCHK(c, launch_copy_bytes(dst.z, src.z, 8 * n, s));
     }
     HIPCHK(c, launch_copy_bytes(dst.vx, src.vx, r * n, s));
     if (c->d.vdim >= 2) HIPCHK(c, launch_copy_bytes(dst.vy, src.vy, r * n, s));
@@ -238,17 +258,22 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     if (!desc || !out) return APIC_EINVAL;
     *out = nullptr;
     const apic_grid_desc &d = *desc;
-    if (d.dim != 1 && d.dim != 2) return APIC_EINVAL;
+    if (d.dim < 1 || d.dim > 3) return APIC_EINVAL;
     if (d.dim == 1 && (d.vdim != 1 || d.ny != 1)) return APIC_EINVAL;
     if (d.dim == 2 && (d.vdim != 2 && d.vdim != 3)) return APIC_EINVAL;
+    if (d.dim == 3 && d.vdim != 3) return APIC_EINVAL;
+    if (d.dim < 3 && d.nz != 0 && d.nz != 1) return APIC_EINVAL;
     if (d.nx < 2 || d.ny < 1 || (d.dim == 2 && (d.ny < 2 || d.nx > 32768 || d.ny > 32768))) return APIC_EINVAL;
+    if (d.dim == 3 && (d.ny < 2 || d.nz < 2 || d.nx > 1024 || d.ny > 1024 || d.nz > 1024)) return APIC_EINVAL;
     if (d.dim == 1 && d.nx > 8192) return APIC_EUNSUPPORTED;
-    if (!(d.lx > 0) || (d.dim == 2 && !(d.ly > 0)) || !(d.dt > 0) || !std::isfinite(d.qm) || d.qm == 0.0)
+    if (!(d.lx > 0) || (d.dim >= 2 && !(d.ly > 0)) || (d.dim == 3 && !(d.lz > 0)) || !(d.dt > 0) ||
+        !std::isfinite(d.qm) || d.qm == 0.0)
         return APIC_EINVAL;
     if (d.bz != 0.0 && d.vdim < 2) return APIC_EINVAL;
     if (n_particles < 0 || n_particles > (int64_t)INT32_MAX - 1) return APIC_EINVAL;
     if (d.prec != APIC_FP64 && d.prec != APIC_MIXED) return APIC_EINVAL;
-    if ((d.tile_x && !is_pow2(d.tile_x)) || (d.tile_y && !is_pow2(d.tile_y))) return APIC_EINVAL;
+    if ((d.tile_x && !is_pow2(d.tile_x)) || (d.tile_y && !is_pow2(d.tile_y)) || (d.tile_z && !is_pow2(d.tile_z)))
+        return APIC_EINVAL;
 
     apic_ctx *c = new (std::nothrow) apic_ctx();
     if (!c) return APIC_ENOMEM;
@@ -259,29 +284,56 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     g.dim = d.dim;
     g.vdim = d.vdim;
     g.nx = d.nx;
-    g.ny = d.dim == 2 ? d.ny : 1;
+    g.ny = d.dim >= 2 ? d.ny : 1;
+    g.nz = d.dim == 3 ? d.nz : 1;
     c->d.ny = g.ny;
-    int tsx, tsy;
-    default_tiles(d, n_particles, tsx, tsy);
+    c->d.nz = g.nz;
+    int tsx, tsy, tsz;
+    default_tiles(d, n_particles, tsx, tsy, tsz);
     if (d.tile_x) tsx = ilog2_floor(d.tile_x);
-    if (d.dim == 2 && d.tile_y) tsy = ilog2_floor(d.tile_y);
+    if (d.dim >= 2 && d.tile_y) tsy = ilog2_floor(d.tile_y);
+    if (d.dim == 3 && d.tile_z) tsz = ilog2_floor(d.tile_z);
     if (d.dim == 1) tsy = 0;
-    if (tsx > 10 || tsy > 10) { delete c; return APIC_EINVAL; }
+    if (d.dim < 3) tsz = 0;
+    if (tsx > 10 || tsy > 10 || tsz > 10) { delete c; return APIC_EINVAL; }
+    // a tile side never exceeds its axis (the tile loads wrap an index once)
+    auto fit = [](int ts, int n) {
+        while (ts > 0 && (1 << ts) > n) --ts;
+        return ts;
+    };
+    tsx = fit(tsx, g.nx);
+    tsy = fit(tsy, g.ny);
+    tsz = fit(tsz, g.nz);
+    {
+        // LDS of the fused push: E tile (dim components) + deposit region with
+        // a one-cell halo; must fit one workgroup's 64 KiB
+        const int64_t ex = (1 << tsx) + 1, ey = d.dim >= 2 ? (1 << tsy) + 1 : 1, ez = d.dim == 3 ? (1 << tsz) + 1 : 1;
+        const int64_t e_bytes = ex * ey * ez * d.dim * (c->mixed ? 4 : 8);
+        const int64_t a_bytes = (ex + 2) * (d.dim >= 2 ? ey + 2 : 1) * (d.dim == 3 ? ez + 2 : 1) * 8;
+        if (e_bytes + a_bytes + 16 > 65536) { delete c; return APIC_EINVAL; }
+    }
     g.tsx = tsx;
     g.tsy = tsy;
+    g.tsz = tsz;
     g.nbx = (g.nx + (1 << tsx) - 1) >> tsx;
-    g.nby = d.dim == 2 ? (g.ny + (1 << tsy) - 1) >> tsy : 1;
-    g.nbuckets = g.nbx * g.nby;
+    g.nby = d.dim >= 2 ? (g.ny + (1 << tsy) - 1) >> tsy : 1;
+    g.nbz = d.dim == 3 ? (g.nz + (1 << tsz) - 1) >> tsz : 1;
+    g.nbuckets = g.nbx * g.nby * g.nbz;
     g.halo = 1;
     g.np = (int)n_particles;
-    g.S = d.frac_bits ? d.frac_bits : (d.dim == 1 ? 32 : 20);
-    if (c->mixed && (g.S < 1 || g.S > 32 || (d.dim == 2 && g.S > 23))) { delete c; return APIC_EINVAL; }
+    g.S = d.frac_bits ? d.frac_bits : (d.dim == 1 ? 32 : d.dim == 2 ? 20 : 15);
+    if (c->mixed && (g.S < 1 || g.S > 32 || (d.dim == 2 && g.S > 23) || (d.dim == 3 && g.S > 16))) {
+        delete c;
+        return APIC_EINVAL;
+    }
     g.lx = d.lx;
-    g.ly = d.dim == 2 ? d.ly : 1.0;
-    const double dx = d.lx / d.nx, dy = d.dim == 2 ? d.ly / d.ny : 1.0;
+    g.ly = d.dim >= 2 ? d.ly : 1.0;
+    g.lz = d.dim == 3 ? d.lz : 1.0;
+    const double dx = d.lx / d.nx, dy = d.dim >= 2 ? d.ly / d.ny : 1.0, dz = d.dim == 3 ? d.lz / d.nz : 1.0;
     g.inv_dx = 1.0 / dx;
     g.inv_dy = 1.0 / dy;
-    c->dV = dx * dy;
+    g.inv_dz = 1.0 / dz;
+    c->dV = dx * dy * dz;
     c->mass = d.q_macro / d.qm;
     layout(c);
 
@@ -289,7 +341,8 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     const int hx = g.nx / 2 + 1;
     size_t bytes = align256(sizeof(int)) * 2 + align256(sizeof(double) * 2 * g.nbuckets) +
                    align256(sizeof(double) * kMaxSpecBlocks) + align256(sizeof(double)) +
-                   align256(sizeof(double) * hx) * 2 + align256(sizeof(double) * g.ny) * 2;
+                   align256(sizeof(double) * hx) * 2 + align256(sizeof(double) * g.ny) * 2 +
+                   align256(sizeof(double) * g.nz) * 2;
     if (hipMalloc(&c->dev_block, bytes) != hipSuccess) { delete c; return APIC_ENOMEM; }
     if (hipMemset(c->dev_block, 0, bytes) != hipSuccess) { (void)hipFree(c->dev_block); delete c; return APIC_EHIP; }
     char *b = (char *)c->dev_block;
@@ -304,10 +357,12 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     c->dev.kapx = (double *)take(sizeof(double) * hx);
     c->dev.ky2 = (double *)take(sizeof(double) * g.ny);
     c->dev.kapy = (double *)take(sizeof(double) * g.ny);
+    c->dev.kz2 = (double *)take(sizeof(double) * g.nz);
+    c->dev.kapz = (double *)take(sizeof(double) * g.nz);
     // modified wavenumbers of the periodic FD operators:
     //   K^2_d = (2/d sin(k d / 2))^2 (3-point second difference),
     //   kappa_d = sin(k d)/d (centred first difference), k = 2 pi m / L.
-    std::vector<double> kx2(hx), kapx(hx), ky2(g.ny), kapy(g.ny);
+    std::vector<double> kx2(hx), kapx(hx), ky2(g.ny), kapy(g.ny), kz2(g.nz), kapz(g.nz);
     for (int m = 0; m < hx; ++m) {
         double h = M_PI * m / g.nx;  // k dx / 2
         kx2[m] = std::pow(2.0 / dx * std::sin(h), 2);
@@ -319,11 +374,20 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
         ky2[m] = std::pow(2.0 / dy * std::sin(h), 2);
         kapy[m] = std::sin(2.0 * h) / dy;
     }
+    for (int m = 0; m < g.nz; ++m) {
+        int mm = (m <= g.nz / 2) ? m : m - g.nz;
+        double h = M_PI * mm / g.nz;
+        kz2[m] = std::pow(2.0 / dz * std::sin(h), 2);
+        kapz[m] = std::sin(2.0 * h) / dz;
+    }
     if (d.dim == 1) { ky2[0] = 0.0; kapy[0] = 0.0; }
+    if (d.dim < 3) { kz2[0] = 0.0; kapz[0] = 0.0; }
     bool copied = hipMemcpy(c->dev.kx2, kx2.data(), sizeof(double) * hx, hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->dev.kapx, kapx.data(), sizeof(double) * hx, hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->dev.ky2, ky2.data(), sizeof(double) * g.ny, hipMemcpyHostToDevice) == hipSuccess &&
-                  hipMemcpy(c->dev.kapy, kapy.data(), sizeof(double) * g.ny, hipMemcpyHostToDevice) == hipSuccess;
+                  hipMemcpy(c->dev.kapy, kapy.data(), sizeof(double) * g.ny, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(c->dev.kz2, kz2.data(), sizeof(double) * g.nz, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(c->dev.kapz, kapz.data(), sizeof(double) * g.nz, hipMemcpyHostToDevice) == hipSuccess;
     if (!copied) {
         (void)hipFree(c->dev_block);
         delete c;
@@ -333,6 +397,15 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
         int n2[2] = {g.ny, g.nx};
         if (hipfftPlan2d(&c->fwd, g.ny, g.nx, HIPFFT_D2Z) != HIPFFT_SUCCESS ||
             hipfftPlanMany(&c->inv, 2, n2, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_Z2D, 2) != HIPFFT_SUCCESS) {
+            (void)hipFree(c->dev_block);
+            delete c;
+            return APIC_EHIP;
+        }
+        c->have_fft = true;
+    } else if (d.dim == 3) {
+        int n3[3] = {g.nz, g.ny, g.nx};
+        if (hipfftPlan3d(&c->fwd, g.nz, g.ny, g.nx, HIPFFT_D2Z) != HIPFFT_SUCCESS ||
+            hipfftPlanMany(&c->inv, 3, n3, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_Z2D, 3) != HIPFFT_SUCCESS) {
             (void)hipFree(c->dev_block);
             delete c;
             return APIC_EHIP;
@@ -363,6 +436,12 @@ apic_status apic_workspace_size(const apic_ctx *c, size_t *bytes) {
 int64_t apic_num_buckets(const apic_ctx *c) { return c ? c->g.nbuckets : -1; }
 
 int apic_frac_bits(const apic_ctx *c) { return c ? c->g.S : -1; }
+
+int apic_tile_size(const apic_ctx *c, int axis) {
+    if (!c || axis < 0 || axis > 2) return -1;
+    if (axis >= c->d.dim) return 1;
+    return 1 << (axis == 0 ? c->g.tsx : axis == 1 ? c->g.tsy : c->g.tsz);
+}
 
 const char *apic_last_error(const apic_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
@@ -398,7 +477,7 @@ apic_status apic_deposit(apic_ctx *c, const apic_particles *p, void *rho, void *
     if (st != APIC_OK) return st;
     if (!rho) return fail(c, APIC_EINVAL, "rho is NULL");
     hipStream_t s = (hipStream_t)stream;
-    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny * c->d.nz;
     HIPCHK(c, launch_fill_u64((uint64_t *)rho, G, 0, s));
     HIPCHK(c, launch_deposit(c->g, c->mixed, parts_of(p), c->n, p->bucket_start, rho, c->dev, s));
     if (!c->mixed) HIPCHK(c, launch_rho(c->g, false, rho, (double *)rho, acc_scale(c), c->d.rho_ion, 0, s));
@@ -436,8 +515,9 @@ apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, floa
     if (nsteps == 0) return APIC_OK;
     hipStream_t s = (hipStream_t)stream;
     const int nb = c->g.nbuckets;
-    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny * c->d.nz;
     int32_t *cnt = wsp<int32_t>(ws, c->o_cnt);
+    int32_t *offs = wsp<int32_t>(ws, c->o_offs);
     int32_t *farcnt = wsp<int32_t>(ws, c->o_farcnt);
     int32_t *tot = wsp<int32_t>(ws, c->o_tot);
     int32_t *deep = wsp<int32_t>(ws, c->o_deep);
@@ -464,9 +544,10 @@ apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, floa
         HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, E, pc, cnt, tot, farcnt, deep, c->dev, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[1], s));
         HIPCHK(c, launch_scan_dir(c->g, tot, bs_dst, c->n, max_per_bucket(c), 1, c->dev, s));
+        HIPCHK(c, launch_dest_offsets(c->g, cnt, bs_dst, offs, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
-        HIPCHK(c, launch_step_push(c->g, c->mixed, src, dst, bs_src, bs_dst, cnt, farcnt, E, pc, acc, p->perm,
-                                   diag ? c->dev.part_push : nullptr, deep, c->dev, s));
+        HIPCHK(c, launch_step_push(c->g, c->mixed, src, dst, bs_src, bs_dst, cnt, offs, farcnt, E, pc, acc,
+                                   p->perm, diag ? c->dev.part_push : nullptr, deep, c->dev, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[3], s));
         if (rho && last) {
             if (c->mixed)

@@ -80,11 +80,31 @@ template <> struct RealOf<true> { using T = float; };
 template <bool MIX>
 struct Pt {
     using R = typename RealOf<MIX>::T;
-    int ix, iy;       // cell indices
-    R fx, fy;         // fractional position inside the cell
-    double x, y;      // absolute position (FP64 path only)
+    int ix, iy, iz;   // cell indices
+    R fx, fy, fz;     // fractional position inside the cell
+    double x, y, z;   // absolute position (FP64 path only)
     R vx, vy, vz;
 };
+
+// Mixed-path cell word: ix (1D), iy << 16 | ix (2D), iz << 20 | iy << 10 | ix
+// (3D, at most 1024 nodes per axis).
+template <int DIM>
+__device__ __forceinline__ void unpack_cell(int32_t c, int &ix, int &iy, int &iz) {
+    if constexpr (DIM == 1) {
+        ix = c; iy = 0; iz = 0;
+    } else if constexpr (DIM == 2) {
+        ix = c & 0xFFFF; iy = c >> 16; iz = 0;
+    } else {
+        ix = c & 0x3FF; iy = (c >> 10) & 0x3FF; iz = c >> 20;
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ int32_t pack_cell(int ix, int iy, int iz) {
+    if constexpr (DIM == 1) return ix;
+    if constexpr (DIM == 2) return (iy << 16) | ix;
+    return (iz << 20) | (iy << 10) | ix;
+}
 
 // FP64 cell of a coordinate: i = floor(x/d), f = x/d - i, computed with
 // x * (1/d). A coordinate that rounds onto the right edge wraps to node 0.
@@ -104,33 +124,30 @@ __device__ __forceinline__ bool load_pt(const Parts &s, int64_t i, const Geo &g,
     using R = typename Pt<MIX>::R;
     bool ok = true;
     if constexpr (MIX) {
-        int32_t c = s.cell[i];
-        if constexpr (DIM == 2) {
-            p.ix = c & 0xFFFF;
-            p.iy = c >> 16;
-            p.fy = s.oy[i];
-            ok = (p.iy >= 0) && (p.iy < g.ny) && (p.fy >= 0.0f) && (p.fy < 1.0f);
-        } else {
-            p.ix = c;
-            p.iy = 0;
-            p.fy = 0.0f;
-        }
+        unpack_cell<DIM>(s.cell[i], p.ix, p.iy, p.iz);
         p.fx = s.ox[i];
-        ok = ok && (p.ix >= 0) && (p.ix < g.nx) && (p.fx >= 0.0f) && (p.fx < 1.0f);
-        if (!ok) { p.ix = 0; p.iy = 0; p.fx = 0.0f; p.fy = 0.0f; }
+        p.fy = (DIM >= 2) ? s.oy[i] : 0.0f;
+        p.fz = (DIM == 3) ? s.oz[i] : 0.0f;
+        ok = (p.ix >= 0) && (p.ix < g.nx) && (p.fx >= 0.0f) && (p.fx < 1.0f);
+        if constexpr (DIM >= 2) ok = ok && (p.iy >= 0) && (p.iy < g.ny) && (p.fy >= 0.0f) && (p.fy < 1.0f);
+        if constexpr (DIM == 3) ok = ok && (p.iz >= 0) && (p.iz < g.nz) && (p.fz >= 0.0f) && (p.fz < 1.0f);
+        if (!ok) { p.ix = 0; p.iy = 0; p.iz = 0; p.fx = 0.0f; p.fy = 0.0f; p.fz = 0.0f; }
     } else {
         p.x = s.x[i];
         double f;
         ok = cell_f64(p.x, g.inv_dx, g.nx, p.ix, f);
         p.fx = f;
-        if constexpr (DIM == 2) {
+        p.y = 0.0; p.iy = 0; p.fy = 0.0;
+        p.z = 0.0; p.iz = 0; p.fz = 0.0;
+        if constexpr (DIM >= 2) {
             p.y = s.y[i];
             ok = cell_f64(p.y, g.inv_dy, g.ny, p.iy, f) && ok;
             p.fy = f;
-        } else {
-            p.y = 0.0;
-            p.iy = 0;
-            p.fy = 0.0;
+        }
+        if constexpr (DIM == 3) {
+            p.z = s.z[i];
+            ok = cell_f64(p.z, g.inv_dz, g.nz, p.iz, f) && ok;
+            p.fz = f;
         }
     }
     p.vx = ((const R *)s.vx)[i];
@@ -143,22 +160,26 @@ template <bool MIX, int DIM, int VDIM>
 __device__ __forceinline__ void store_pt(const Parts &d, int64_t j, const Pt<MIX> &p) {
     using R = typename Pt<MIX>::R;
     if constexpr (MIX) {
-        d.cell[j] = (DIM == 2) ? ((p.iy << 16) | p.ix) : p.ix;
+        d.cell[j] = pack_cell<DIM>(p.ix, p.iy, p.iz);
         d.ox[j] = p.fx;
-        if constexpr (DIM == 2) d.oy[j] = p.fy;
+        if constexpr (DIM >= 2) d.oy[j] = p.fy;
+        if constexpr (DIM == 3) d.oz[j] = p.fz;
     } else {
         d.x[j] = p.x;
-        if constexpr (DIM == 2) d.y[j] = p.y;
+        if constexpr (DIM >= 2) d.y[j] = p.y;
+        if constexpr (DIM == 3) d.z[j] = p.z;
     }
     ((R *)d.vx)[j] = p.vx;
     if constexpr (VDIM >= 2) ((R *)d.vy)[j] = p.vy;
     if constexpr (VDIM >= 3) ((R *)d.vz)[j] = p.vz;
 }
 
+// Bucket of a cell: tiles numbered x fastest, then y, then z.
 template <bool MIX, int DIM>
-__device__ __forceinline__ int bucket_of(const Geo &g, int ix, int iy) {
+__device__ __forceinline__ int bucket_of(const Geo &g, int ix, int iy, int iz = 0) {
     int bx = ix >> g.tsx;
     if constexpr (DIM == 2) return (iy >> g.tsy) * g.nbx + bx;
+    if constexpr (DIM == 3) return ((iz >> g.tsz) * g.nby + (iy >> g.tsy)) * g.nbx + bx;
     return bx;
 }
 
@@ -186,76 +207,85 @@ __device__ __forceinline__ void boris(R &vx, R &vy, R ex, R ey, R a, R t, R s) {
     }
 }
 
+// The z part of the Boris advance in 3D: the rotation about z leaves vz
+// alone, so vz takes the two half kicks of Ez.
+template <typename R>
+__device__ __forceinline__ void boris_z(R &vz, R ez, R a) {
+    R mz = vz + a * ez;
+    vz = mz + a * ez;
+}
+
 // Position update with periodic wrap. Returns the unwrapped cell shift
-// (new cell - old cell) per axis in sx, sy, and false for a non-finite or
+// (new cell - old cell) per axis in sx, sy, sz, and false for a non-finite or
 // runaway coordinate.
+//
+// Mixed path, one axis: offset o += v dt/d (binary32), k = floor(o),
+// o -= k (and o >= 1 after rounding moves one more cell), cell += k modulo n.
+__device__ __forceinline__ bool move_axis_mixed(int &ic, float &f, float v, float dtd, int n, int &shift) {
+    float o = f + v * dtd;
+    float fl = floorf(o);
+    o = o - fl;
+    const bool ok = fabsf(fl) < 1.0e8f;
+    int sh = ok ? (int)fl : 0;
+    if (o >= 1.0f) { o = o - 1.0f; sh += 1; }
+    int i = ic + sh;
+    if (i >= n || i < 0) { i %= n; if (i < 0) i += n; }
+    ic = i;
+    f = ok ? o : 0.0f;
+    shift = sh;
+    return ok;
+}
+
+// FP64 path, one axis: x += v dt wrapped into [0, L), then the new cell; the
+// shift is the cell difference taken modulo n into (-n/2, n/2].
+__device__ __forceinline__ bool move_axis_f64(double &xc, int &ic, double &f, double v, double dt, double L,
+                                              double inv_d, int n, int &shift) {
+    const int i0 = ic;
+    double x = xc + v * dt;
+    if (x < 0.0) x += L;
+    if (x >= L) x -= L;
+    if (!(x >= 0.0 && x < L)) {
+        x = x - L * floor(x / L);
+        if (!(x >= 0.0 && x < L)) x = 0.0;
+    }
+    xc = x;
+    const bool ok = cell_f64(x, inv_d, n, ic, f);
+    int d = ic - i0;
+    if (d > n / 2) d -= n;
+    if (d < -(n / 2)) d += n;
+    shift = d;
+    return ok;
+}
+
 template <bool MIX, int DIM>
-__device__ __forceinline__ bool move_pt(Pt<MIX> &p, const Geo &g, const PushC &pc, int &sx, int &sy) {
+__device__ __forceinline__ bool move_pt(Pt<MIX> &p, const Geo &g, const PushC &pc, int &sx, int &sy, int &sz) {
+    sy = 0;
+    sz = 0;
     if constexpr (MIX) {
-        bool ok = true;
-        float o = p.fx + p.vx * pc.dtdx;
-        float fl = floorf(o);
-        o = o - fl;
-        ok = ok && (fabsf(fl) < 1.0e8f);
-        int sh = ok ? (int)fl : 0;
-        if (o >= 1.0f) { o = o - 1.0f; sh += 1; }
-        int ix = p.ix + sh;
-        if (ix >= g.nx || ix < 0) { ix %= g.nx; if (ix < 0) ix += g.nx; }
-        p.ix = ix;
-        p.fx = ok ? o : 0.0f;
-        sx = sh;
-        sy = 0;
-        if constexpr (DIM == 2) {
-            float q = p.fy + p.vy * pc.dtdy;
-            float fq = floorf(q);
-            q = q - fq;
-            bool oky = fabsf(fq) < 1.0e8f;
-            int shy = oky ? (int)fq : 0;
-            if (q >= 1.0f) { q = q - 1.0f; shy += 1; }
-            int iy = p.iy + shy;
-            if (iy >= g.ny || iy < 0) { iy %= g.ny; if (iy < 0) iy += g.ny; }
-            p.iy = iy;
-            p.fy = oky ? q : 0.0f;
-            sy = shy;
-            ok = ok && oky;
-        }
+        bool ok = move_axis_mixed(p.ix, p.fx, p.vx, pc.dtdx, g.nx, sx);
+        if constexpr (DIM >= 2) ok = move_axis_mixed(p.iy, p.fy, p.vy, pc.dtdy, g.ny, sy) && ok;
+        if constexpr (DIM == 3) ok = move_axis_mixed(p.iz, p.fz, p.vz, pc.dtdz, g.nz, sz) && ok;
         return ok;
     } else {
-        const int ix0 = p.ix, iy0 = p.iy;
-        double x = p.x + p.vx * pc.dt;
-        if (x < 0.0) x += g.lx;
-        if (x >= g.lx) x -= g.lx;
-        if (!(x >= 0.0 && x < g.lx)) {
-            x = x - g.lx * floor(x / g.lx);
-            if (!(x >= 0.0 && x < g.lx)) x = 0.0;
-        }
-        p.x = x;
         double f;
-        bool ok = cell_f64(x, g.inv_dx, g.nx, p.ix, f);
+        bool ok = move_axis_f64(p.x, p.ix, f, p.vx, pc.dt, g.lx, g.inv_dx, g.nx, sx);
         p.fx = f;
-        int d = p.ix - ix0;
-        if (d > g.nx / 2) d -= g.nx;
-        if (d < -(g.nx / 2)) d += g.nx;
-        sx = d;
-        sy = 0;
-        if constexpr (DIM == 2) {
-            double y = p.y + p.vy * pc.dt;
-            if (y < 0.0) y += g.ly;
-            if (y >= g.ly) y -= g.ly;
-            if (!(y >= 0.0 && y < g.ly)) {
-                y = y - g.ly * floor(y / g.ly);
-                if (!(y >= 0.0 && y < g.ly)) y = 0.0;
-            }
-            p.y = y;
-            ok = cell_f64(y, g.inv_dy, g.ny, p.iy, f) && ok;
+        if constexpr (DIM >= 2) {
+            ok = move_axis_f64(p.y, p.iy, f, p.vy, pc.dt, g.ly, g.inv_dy, g.ny, sy) && ok;
             p.fy = f;
-            int e = p.iy - iy0;
-            if (e > g.ny / 2) e -= g.ny;
-            if (e < -(g.ny / 2)) e += g.ny;
-            sy = e;
+        }
+        if constexpr (DIM == 3) {
+            ok = move_axis_f64(p.z, p.iz, f, p.vz, pc.dt, g.lz, g.inv_dz, g.nz, sz) && ok;
+            p.fz = f;
         }
         return ok;
     }
+}
+
+template <bool MIX, int DIM>
+__device__ __forceinline__ bool move_pt(Pt<MIX> &p, const Geo &g, const PushC &pc, int &sx, int &sy) {
+    int sz;
+    return move_pt<MIX, DIM>(p, g, pc, sx, sy, sz);
 }
 
 // Fixed-point CIC weight along one axis: round-half-even(o * 2^S).
@@ -321,6 +351,77 @@ __device__ __forceinline__ void gather_global(const ET *E, const Geo &g, int ix,
     }
 }
 
+// E tile in 3D: nodes [x0, x0+TX] x [y0, y0+TY] x [z0, z0+TZ] (periodic),
+// three components, converted to R on the way into LDS.
+template <typename R, typename ET>
+__device__ void load_e_tile3(R *sE, const ET *E, const Geo &g, int x0, int y0, int z0, int wx, int wy, int wz) {
+    const int G = g.nx * g.ny * g.nz;
+    const int tot = wx * wy * wz;
+    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+        const int lx = t % wx, r = t / wx, ly = r % wy, lz = r / wy;
+        int gx = x0 + lx;
+        if (gx >= g.nx) gx -= g.nx;
+        int gy = y0 + ly;
+        if (gy >= g.ny) gy -= g.ny;
+        int gz = z0 + lz;
+        if (gz >= g.nz) gz -= g.nz;
+        const int gi = (gz * g.ny + gy) * g.nx + gx;
+        sE[t] = (R)E[gi];
+        sE[tot + t] = (R)E[G + gi];
+        sE[2 * tot + t] = (R)E[2 * G + gi];
+    }
+}
+
+// 3D CIC interpolation: node weight (wx_a wy_b) wz_c; the eight terms are
+// added left to right with a (x) fastest, then b (y), then c (z). e(k) gives
+// the value of component comp at corner k = c*4 + b*2 + a.
+template <typename R, typename F>
+__device__ __forceinline__ R cic3_sum(R fx, R fy, R fz, F e) {
+    const R wx0 = R(1) - fx, wy0 = R(1) - fy, wz0 = R(1) - fz;
+    const R w00 = wx0 * wy0, w10 = fx * wy0, w01 = wx0 * fy, w11 = fx * fy;
+    R acc = (w00 * wz0) * e(0);
+    acc = acc + (w10 * wz0) * e(1);
+    acc = acc + (w01 * wz0) * e(2);
+    acc = acc + (w11 * wz0) * e(3);
+    acc = acc + (w00 * fz) * e(4);
+    acc = acc + (w10 * fz) * e(5);
+    acc = acc + (w01 * fz) * e(6);
+    acc = acc + (w11 * fz) * e(7);
+    return acc;
+}
+
+template <typename R>
+__device__ __forceinline__ void gather_lds3(const R *sE, int wx, int wxy, int tot, int lx, int ly, int lz, R fx,
+                                            R fy, R fz, R &ex, R &ey, R &ez) {
+    const int a = (lz * wxy + ly * wx) + lx;
+    const int off[8] = {0, 1, wx, wx + 1, wxy, wxy + 1, wxy + wx, wxy + wx + 1};
+    ex = cic3_sum<R>(fx, fy, fz, [&](int k) { return sE[a + off[k]]; });
+    ey = cic3_sum<R>(fx, fy, fz, [&](int k) { return sE[tot + a + off[k]]; });
+    ez = cic3_sum<R>(fx, fy, fz, [&](int k) { return sE[2 * tot + a + off[k]]; });
+}
+
+// Node indices of the eight corners of cell (ix, iy, iz), periodic.
+__device__ __forceinline__ void corners3(const Geo &g, int ix, int iy, int iz, int m[8]) {
+    const int ip = (ix + 1 >= g.nx) ? 0 : ix + 1;
+    const int jp = (iy + 1 >= g.ny) ? 0 : iy + 1;
+    const int kp = (iz + 1 >= g.nz) ? 0 : iz + 1;
+    const int r0 = (iz * g.ny + iy) * g.nx, r1 = (iz * g.ny + jp) * g.nx;
+    const int r2 = (kp * g.ny + iy) * g.nx, r3 = (kp * g.ny + jp) * g.nx;
+    m[0] = r0 + ix; m[1] = r0 + ip; m[2] = r1 + ix; m[3] = r1 + ip;
+    m[4] = r2 + ix; m[5] = r2 + ip; m[6] = r3 + ix; m[7] = r3 + ip;
+}
+
+template <typename R, typename ET>
+__device__ __forceinline__ void gather_global3(const ET *E, const Geo &g, int ix, int iy, int iz, R fx, R fy, R fz,
+                                               R &ex, R &ey, R &ez) {
+    int m[8];
+    corners3(g, ix, iy, iz, m);
+    const int G = g.nx * g.ny * g.nz;
+    ex = cic3_sum<R>(fx, fy, fz, [&](int k) { return (R)E[m[k]]; });
+    ey = cic3_sum<R>(fx, fy, fz, [&](int k) { return (R)E[G + m[k]]; });
+    ez = cic3_sum<R>(fx, fy, fz, [&](int k) { return (R)E[2 * G + m[k]]; });
+}
+
 // Accumulator element: double weights (FP64 path) or int64 fixed-point sums.
 template <bool MIX> struct AccOf { using T = double; };
 template <> struct AccOf<true> { using T = unsigned long long; };
@@ -334,10 +435,28 @@ __device__ __forceinline__ void acc_add(typename AccOf<MIX>::T *a, typename AccO
 // w1 = round-half-even(o 2^S) (o 2^S is exact in binary32), w0 = 2^S - w1;
 // in 2D (S <= 23) both fit 24 bits and the node weight is their exact 48-bit
 // product (24-bit multiplies).
+// In 3D (S <= 16) the node weight is (w_a w_b) w_c, exact in 64 bits; the
+// eight weights are ordered k = c*4 + b*2 + a.
 template <bool MIX, int DIM>
 __device__ __forceinline__ void dep_weights(const Pt<MIX> &p, const Geo &g,
-                                            typename AccOf<MIX>::T w[4]) {
-    if constexpr (MIX) {
+                                            typename AccOf<MIX>::T *w) {
+    if constexpr (MIX && DIM == 3) {
+        const float scale = (float)(1ull << g.S);
+        const uint32_t one = 1u << g.S;
+        const uint32_t w1x = (uint32_t)rintf(p.fx * scale), w0x = one - w1x;
+        const uint32_t w1y = (uint32_t)rintf(p.fy * scale), w0y = one - w1y;
+        const uint32_t w1z = (uint32_t)rintf(p.fz * scale), w0z = one - w1z;
+        const unsigned long long a00 = (unsigned long long)w0x * w0y, a10 = (unsigned long long)w1x * w0y;
+        const unsigned long long a01 = (unsigned long long)w0x * w1y, a11 = (unsigned long long)w1x * w1y;
+        w[0] = a00 * w0z; w[1] = a10 * w0z; w[2] = a01 * w0z; w[3] = a11 * w0z;
+        w[4] = a00 * w1z; w[5] = a10 * w1z; w[6] = a01 * w1z; w[7] = a11 * w1z;
+    } else if constexpr (!MIX && DIM == 3) {
+        const double fx = p.fx, fy = p.fy, fz = p.fz;
+        const double wx0 = 1.0 - fx, wy0 = 1.0 - fy, wz0 = 1.0 - fz;
+        const double a00 = wx0 * wy0, a10 = fx * wy0, a01 = wx0 * fy, a11 = fx * fy;
+        w[0] = a00 * wz0; w[1] = a10 * wz0; w[2] = a01 * wz0; w[3] = a11 * wz0;
+        w[4] = a00 * fz; w[5] = a10 * fz; w[6] = a01 * fz; w[7] = a11 * fz;
+    } else if constexpr (MIX) {
         const float scale = (float)(1ull << g.S);
         if constexpr (DIM == 1) {
             const unsigned long long w1 = (uint32_t)rintf(p.fx * scale);
@@ -368,9 +487,18 @@ __device__ __forceinline__ void dep_weights(const Pt<MIX> &p, const Geo &g,
     }
 }
 
+template <bool MIX>
+__device__ __forceinline__ void deposit_global3(typename AccOf<MIX>::T *acc, const Geo &g, int ix, int iy, int iz,
+                                                const typename AccOf<MIX>::T *w) {
+    int m[8];
+    corners3(g, ix, iy, iz, m);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc_add<MIX>(&acc[m[k]], w[k]);
+}
+
 template <bool MIX, int DIM>
 __device__ __forceinline__ void deposit_global(typename AccOf<MIX>::T *acc, const Geo &g, int ix, int iy,
-                                               const typename AccOf<MIX>::T w[4]) {
+                                               const typename AccOf<MIX>::T *w) {
     int ip = ix + 1;
     if (ip >= g.nx) ip = 0;
     if constexpr (DIM == 1) {
@@ -406,6 +534,25 @@ __device__ void flush_region(typename AccOf<MIX>::T *acc, const typename AccOf<M
             if (gy < 0) gy += g.ny;
         }
         acc_add<MIX>(&acc[gy * g.nx + gx], v);
+    }
+}
+
+// 3D region (nodes [x0-H, x0+TX+H] x [y0-H, ..] x [z0-H, ..]).
+template <bool MIX>
+__device__ void flush_region3(typename AccOf<MIX>::T *acc, const typename AccOf<MIX>::T *sA, const Geo &g,
+                              int x0, int y0, int z0, int wx, int wy, int wz, int halo) {
+    const int tot = wx * wy * wz;
+    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+        typename AccOf<MIX>::T v = sA[t];
+        if (v == (typename AccOf<MIX>::T)0) continue;
+        const int lx = t % wx, r = t / wx, ly = r % wy, lz = r / wy;
+        int gx = (x0 - halo + lx) % g.nx;
+        if (gx < 0) gx += g.nx;
+        int gy = (y0 - halo + ly) % g.ny;
+        if (gy < 0) gy += g.ny;
+        int gz = (z0 - halo + lz) % g.nz;
+        if (gz < 0) gz += g.nz;
+        acc_add<MIX>(&acc[(gz * g.ny + gy) * g.nx + gx], v);
     }
 }
 
@@ -468,19 +615,32 @@ __device__ double field1d_block(double *sr, int nx, double dx, double *E, float 
 
 // Instantiates a statement for the precision / dimension combination of a
 // launch: MIX, DIM, VDIM (and the unroll factor U) are constexpr inside.
-#define APIC_DISPATCH(g, mixed, ...)                                                    \
+#define APIC_DISPATCH_2D(g, mixed, ...)                                                 \
     do {                                                                                \
         if (mixed) {                                                                    \
             constexpr bool MIX = true;                                                  \
-            [[maybe_unused]] constexpr int U = APIC_STEP_U;                                       \
+            [[maybe_unused]] constexpr int U = APIC_STEP_U;                             \
             if ((g).dim == 1) { [[maybe_unused]] constexpr int DIM = 1, VDIM = 1; __VA_ARGS__; }         \
             else if ((g).vdim == 2) { [[maybe_unused]] constexpr int DIM = 2, VDIM = 2; __VA_ARGS__; }   \
             else { [[maybe_unused]] constexpr int DIM = 2, VDIM = 3; __VA_ARGS__; }                      \
         } else {                                                                        \
             constexpr bool MIX = false;                                                 \
-            [[maybe_unused]] constexpr int U = APIC_STEP_U;                                       \
+            [[maybe_unused]] constexpr int U = APIC_STEP_U;                             \
             if ((g).dim == 1) { [[maybe_unused]] constexpr int DIM = 1, VDIM = 1; __VA_ARGS__; }         \
             else if ((g).vdim == 2) { [[maybe_unused]] constexpr int DIM = 2, VDIM = 2; __VA_ARGS__; }   \
             else { [[maybe_unused]] constexpr int DIM = 2, VDIM = 3; __VA_ARGS__; }                      \
+        }                                                                               \
+    } while (0)
+
+// Same, with the 3D3V case.
+#define APIC_DISPATCH(g, mixed, ...)                                                    \
+    do {                                                                                \
+        if ((g).dim == 3) {                                                             \
+            [[maybe_unused]] constexpr int U = APIC_STEP_U;                             \
+            [[maybe_unused]] constexpr int DIM = 3, VDIM = 3;                           \
+            if (mixed) { constexpr bool MIX = true; __VA_ARGS__; }                      \
+            else { constexpr bool MIX = false; __VA_ARGS__; }                           \
+        } else {                                                                        \
+            APIC_DISPATCH_2D(g, mixed, __VA_ARGS__);                                    \
         }                                                                               \
     } while (0)

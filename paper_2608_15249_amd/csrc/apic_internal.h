@@ -18,15 +18,15 @@ enum : int {
 // Grid geometry and bucket (tile) layout, passed to kernels by value.
 struct Geo {
     int dim, vdim;
-    int nx, ny;           // nodes per axis (ny = 1 in 1D)
-    int tsx, tsy;         // log2 of the tile size in cells
-    int nbx, nby;         // tiles per axis
+    int nx, ny, nz;       // nodes per axis (ny = 1 in 1D, nz = 1 below 3D)
+    int tsx, tsy, tsz;    // log2 of the tile size in cells
+    int nbx, nby, nbz;    // tiles per axis
     int nbuckets;
     int halo;             // deposit halo (cells) around a tile held in LDS
     int S;                // fixed-point weight bits per axis (mixed path)
     int np;               // number of particles (bounds for bucket tables)
-    double lx, ly;
-    double inv_dx, inv_dy;
+    double lx, ly, lz;
+    double inv_dx, inv_dy, inv_dz;
 };
 
 // Boris / move coefficients for one call (dt_eff = dt * dt_scale).
@@ -34,7 +34,7 @@ struct PushC {
     double a, t, s;       // a = (q/m) dt_eff / 2, t = a bz, s = 2t/(1+t^2)
     float af, tf, sf;
     double dt;            // position step (unscaled dt)
-    float dtdx, dtdy;     // dt/dx, dt/dy in binary32 (mixed path)
+    float dtdx, dtdy, dtdz;  // dt/dx, dt/dy, dt/dz in binary32 (mixed path)
     int move;
     int rot;              // bz != 0 (the push rotates v in the x-y plane)
     float deep;           // slack (cells) that makes a staying particle "deep"
@@ -42,9 +42,9 @@ struct PushC {
 
 // One particle buffer set (structure of arrays).
 struct Parts {
-    double *x, *y;
+    double *x, *y, *z;
     int32_t *cell;
-    float *ox, *oy;
+    float *ox, *oy, *oz;
     void *vx, *vy, *vz;
 };
 
@@ -57,10 +57,11 @@ struct CtxDev {
     double *rho0;         // rho_hat(0) = sum_j rho_j of the last spectral solve
     double *kx2, *kapx;   // modified wavenumber tables, x: [nx/2+1]
     double *ky2, *kapy;   // y: [ny]
+    double *kz2, *kapz;   // z: [nz]
 };
 
 constexpr int kMaxSpecBlocks = 1024;
-constexpr int kStepTab = 40;  // per-bucket direction table entries (4 waves x 10 directions)
+constexpr int kStepTab = 112; // per-bucket direction table entries, at most (4 waves x 28 directions in 3D)
 constexpr int kDeepTab = 8;   // per-bucket deep-range entries (4 waves x (start, count))
 
 // ---- launchers (apic_kernels.hip) -----------------------------------------
@@ -106,16 +107,20 @@ hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int
                              int32_t *farcnt, const int32_t *deep, const CtxDev &c, hipStream_t s);
 hipError_t launch_scan_dir(const Geo &g, int32_t *tot, int32_t *start, int64_t n, int64_t max_per_bucket,
                            int step_mode, const CtxDev &c, hipStream_t s);
+// first slot of every (source bucket, wave, direction) tally inside its
+// destination bucket: offs has the layout of cnt
+hipError_t launch_dest_offsets(const Geo &g, const int32_t *cnt, const int32_t *start, int32_t *offs,
+                               hipStream_t s);
 hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Parts &dst,
                             const int32_t *bstart, const int32_t *bstart_new, const int32_t *cnt,
-                            int32_t *farcnt, const double *E, const PushC &pc, void *acc, int32_t *perm,
-                            double *part, int32_t *deep, const CtxDev &c, hipStream_t s);
+                            const int32_t *offs, int32_t *farcnt, const double *E, const PushC &pc, void *acc,
+                            int32_t *perm, double *part, int32_t *deep, const CtxDev &c, hipStream_t s);
 
 // field: accumulation buffer -> rho (FP64): rho = add + scale * acc
 hipError_t launch_rho(const Geo &g, bool mixed, void *acc, double *rho, double scale, double add,
                       int clear, hipStream_t s);
 int spectral_blocks(const Geo &g);
-hipError_t launch_spectral(const Geo &g, const void *rho_hat, void *ex_hat, void *ey_hat,
+hipError_t launch_spectral(const Geo &g, const void *rho_hat, void *ex_hat, void *ey_hat, void *ez_hat,
                            const CtxDev &c, hipStream_t s);
 hipError_t launch_finalize(int npush, int nspec, double mass, double dV, double G, double rho_ion,
                            double *diag, double *we, double *charge, const CtxDev &c, hipStream_t s);

@@ -38,84 +38,120 @@ namespace {
 
 // ------------------------------------------------- step: bucket directions
 //
-// A particle of bucket (bx, by) lands after the move in bucket (bx+dbx,
-// by+dby) (periodic). Moves with |dbx|, |dby| <= 1 get the direction code
-// d = (dby+1)*3 + (dbx+1) in 0..8; larger jumps get kFar. The count pass
-// tallies particles per (source bucket, wave, d); the scan turns the tallies
-// into start offsets inside the destination buckets (ordered by d, then wave);
-// the push pass hands out consecutive slots per (wave, d) in the order the
-// wave meets its particles. The order is therefore fixed by the previous
-// order alone: no atomics decide where a near particle goes. Far movers
-// (rare) take slots from an atomic cursor at the end of their bucket.
-constexpr int kDirs = 10;
-constexpr int kFar = 9;
-constexpr int kStay = 4;   // the direction of a particle that stays in its bucket
+// A particle of bucket (bx, by[, bz]) lands after the move in bucket
+// (bx+dbx, by+dby[, bz+dbz]) (periodic). Moves with every |db| <= 1 get the
+// direction code d = (dby+1)*3 + (dbx+1) in 0..8 (1D, 2D), or
+// d = ((dbz+1)*3 + (dby+1))*3 + (dbx+1) in 0..26 (3D); larger jumps get the
+// far code. The count pass tallies particles per (source bucket, wave, d);
+// the scan turns the tallies into start offsets inside the destination
+// buckets (ordered by d, then wave); the push pass hands out consecutive
+// slots per (wave, d) in the order the wave meets its particles. The order is
+// therefore fixed by the previous order alone: no atomics decide where a near
+// particle goes. Far movers (rare) take slots from an atomic cursor at the
+// end of their bucket.
+template <int DIM> struct Dir {
+    static constexpr int kN = (DIM == 3) ? 28 : 10;      // direction codes (near + far)
+    static constexpr int kFar = kN - 1;
+    static constexpr int kStay = (DIM == 3) ? 13 : 4;    // the code of a particle that stays
+    static constexpr int kTab = kWaves * kN;             // per-bucket table entries
+};
+static_assert(Dir<3>::kTab <= kStepTab && Dir<2>::kTab <= kStepTab, "direction table size");
 static_assert(kDeepTab == 2 * kWaves, "deep table size");
-constexpr int kTab = kWaves * kDirs;  // per-bucket table entries
 
-__device__ __forceinline__ int dir_code(const Geo &g, int bx, int by, int nbx_new, int nby_new) {
-    int dbx = nbx_new - bx, dby = nby_new - by;
-    if (dbx > g.nbx / 2) dbx -= g.nbx;
-    if (dbx < -(g.nbx / 2)) dbx += g.nbx;
-    if (dby > g.nby / 2) dby -= g.nby;
-    if (dby < -(g.nby / 2)) dby += g.nby;
-    return (dbx >= -1 && dbx <= 1 && dby >= -1 && dby <= 1) ? (dby + 1) * 3 + (dbx + 1) : kFar;
+// Tile coordinates of bucket b (tiles numbered x fastest, then y, then z).
+template <int DIM>
+__device__ __forceinline__ void tile_coords(const Geo &g, int b, int &bx, int &by, int &bz) {
+    if constexpr (DIM == 1) {
+        bx = b; by = 0; bz = 0;
+    } else if constexpr (DIM == 2) {
+        bx = b % g.nbx; by = b / g.nbx; bz = 0;
+    } else {
+        bx = b % g.nbx; const int r = b / g.nbx; by = r % g.nby; bz = r / g.nby;
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ int bucket_index(const Geo &g, int bx, int by, int bz) {
+    if constexpr (DIM == 1) return bx;
+    if constexpr (DIM == 2) return by * g.nbx + bx;
+    return (bz * g.nby + by) * g.nbx + bx;
+}
+
+__device__ __forceinline__ int wrap_tile(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Bucket reached from (bx, by, bz) with near direction d.
+template <int DIM>
+__device__ __forceinline__ int dir_target(const Geo &g, int bx, int by, int bz, int d) {
+    const int tx = wrap_tile(bx + d % 3 - 1, g.nbx);
+    const int ty = (DIM >= 2) ? wrap_tile(by + (d / 3) % 3 - 1, g.nby) : 0;
+    const int tz = (DIM == 3) ? wrap_tile(bz + d / 9 - 1, g.nbz) : 0;
+    return bucket_index<DIM>(g, tx, ty, tz);
 }
 
 // Source bucket that reaches bucket nbk with direction d.
+template <int DIM>
 __device__ __forceinline__ int dir_source(const Geo &g, int nbk, int d) {
-    const int dbx = d % 3 - 1, dby = d / 3 - 1;
-    int sx = ((g.dim == 2) ? nbk % g.nbx : nbk) - dbx;
-    int sy = ((g.dim == 2) ? nbk / g.nbx : 0) - dby;
-    if (sx < 0) sx += g.nbx;
-    if (sx >= g.nbx) sx -= g.nbx;
-    if (sy < 0) sy += g.nby;
-    if (sy >= g.nby) sy -= g.nby;
-    return (g.dim == 2) ? sy * g.nbx + sx : sx;
+    int bx, by, bz;
+    tile_coords<DIM>(g, nbk, bx, by, bz);
+    const int sx = wrap_tile(bx - (d % 3 - 1), g.nbx);
+    const int sy = (DIM >= 2) ? wrap_tile(by - ((d / 3) % 3 - 1), g.nby) : 0;
+    const int sz = (DIM == 3) ? wrap_tile(bz - (d / 9 - 1), g.nbz) : 0;
+    return bucket_index<DIM>(g, sx, sy, sz);
 }
 
 // Direction code from a particle's tile-local cell after the move, (lxn,
-// lyn) = old tile-local cell + unwrapped cell shift: the widths of the tile
-// and of its neighbours (the last tile of an axis may be cut by the grid
+// lyn, lzn) = old tile-local cell + unwrapped cell shift: the widths of the
+// tile and of its neighbours (the last tile of an axis may be cut by the grid
 // edge; neighbours wrap periodically) decide whether it stayed, crossed into
-// a neighbour, or jumped farther (kFar). Same meaning as dir_code for every
-// move, without per-particle wrap arithmetic.
+// a neighbour, or jumped farther (the far code), without per-particle wrap
+// arithmetic.
 struct TileNb {
     int txe, lw, rw;   // widths (cells) of this tile and its left / right neighbour
     int tye, dw, uw;   // same along y
+    int tze, bw, fw;   // same along z
 };
 
 __device__ __forceinline__ int tile_width(int i, int t, int n) { return min(t, n - i * t); }
 
 template <int DIM>
-__device__ __forceinline__ TileNb tile_nb(const Geo &g, int bx, int by) {
+__device__ __forceinline__ TileNb tile_nb(const Geo &g, int bx, int by, int bz = 0) {
     TileNb t;
     const int T = 1 << g.tsx;
     t.txe = tile_width(bx, T, g.nx);
     t.lw = tile_width(bx == 0 ? g.nbx - 1 : bx - 1, T, g.nx);
     t.rw = tile_width(bx == g.nbx - 1 ? 0 : bx + 1, T, g.nx);
-    if constexpr (DIM == 2) {
+    t.tye = t.dw = t.uw = 1;
+    t.tze = t.bw = t.fw = 1;
+    if constexpr (DIM >= 2) {
         const int V = 1 << g.tsy;
         t.tye = tile_width(by, V, g.ny);
         t.dw = tile_width(by == 0 ? g.nby - 1 : by - 1, V, g.ny);
         t.uw = tile_width(by == g.nby - 1 ? 0 : by + 1, V, g.ny);
-    } else {
-        t.tye = 1;
-        t.dw = t.uw = 1;
+    }
+    if constexpr (DIM == 3) {
+        const int Z = 1 << g.tsz;
+        t.tze = tile_width(bz, Z, g.nz);
+        t.bw = tile_width(bz == 0 ? g.nbz - 1 : bz - 1, Z, g.nz);
+        t.fw = tile_width(bz == g.nbz - 1 ? 0 : bz + 1, Z, g.nz);
     }
     return t;
 }
 
 template <int DIM>
-__device__ __forceinline__ int dir_local(const TileNb &t, int lxn, int lyn) {
+__device__ __forceinline__ int dir_local(const TileNb &t, int lxn, int lyn, int lzn = 0) {
     const int dbx = (lxn < 0) ? -1 : (lxn >= t.txe) ? 1 : 0;
     bool far = lxn < -t.lw || lxn >= t.txe + t.rw;
-    int dby = 0;
-    if constexpr (DIM == 2) {
+    int dby = 0, dbz = 0;
+    if constexpr (DIM >= 2) {
         dby = (lyn < 0) ? -1 : (lyn >= t.tye) ? 1 : 0;
         far = far || lyn < -t.dw || lyn >= t.tye + t.uw;
     }
-    return far ? kFar : (dby + 1) * 3 + (dbx + 1);
+    if constexpr (DIM == 3) {
+        dbz = (lzn < 0) ? -1 : (lzn >= t.tze) ? 1 : 0;
+        far = far || lzn < -t.bw || lzn >= t.tze + t.fw;
+        return far ? Dir<3>::kFar : ((dbz + 1) * 3 + (dby + 1)) * 3 + (dbx + 1);
+    }
+    return far ? Dir<DIM>::kFar : (dby + 1) * 3 + (dbx + 1);
 }
 
 // |v|^2 of a particle for the kinetic-energy diagnostic (binary32 squares on
@@ -131,36 +167,49 @@ __device__ __forceinline__ double vsq(const Pt<MIX> &q) {
 // Gather + Boris + move of one loaded particle of the block's tile; shared by
 // the count and the push pass so that both compute identical bits. A particle
 // outside the tile (the bucket table does not match the order) is flagged
-// and clamped into the tile so that every access stays in bounds.
+// and clamped into the tile so that every access stays in bounds. The E tile
+// spans ex_w x ey_w x ez_w nodes from (x0, y0, z0).
 template <bool MIX, int DIM, int VDIM>
 __device__ __forceinline__ bool advance(Pt<MIX> &q, const Geo &g, const PushC &pc,
-                                        const typename Pt<MIX>::R *sE, int ex_w, int ey_w, int x0, int y0,
-                                        int &lx, int &ly, int &sx, int &sy) {
+                                        const typename Pt<MIX>::R *sE, int ex_w, int ey_w, int ez_w, int x0, int y0,
+                                        int z0, int &lx, int &ly, int &lz, int &sx, int &sy, int &sz) {
     using R = typename Pt<MIX>::R;
     const R a = MIX ? (R)pc.af : (R)pc.a, t = MIX ? (R)pc.tf : (R)pc.t, s = MIX ? (R)pc.sf : (R)pc.s;
     lx = q.ix - x0;
-    ly = (DIM == 2) ? q.iy - y0 : 0;
-    const bool in = (unsigned)lx < (unsigned)(ex_w - 1) && (DIM == 1 || (unsigned)ly < (unsigned)(ey_w - 1));
+    ly = (DIM >= 2) ? q.iy - y0 : 0;
+    lz = (DIM == 3) ? q.iz - z0 : 0;
+    bool in = (unsigned)lx < (unsigned)(ex_w - 1);
+    if constexpr (DIM >= 2) in = in && (unsigned)ly < (unsigned)(ey_w - 1);
+    if constexpr (DIM == 3) in = in && (unsigned)lz < (unsigned)(ez_w - 1);
     if (!in) {
         lx = min(max(lx, 0), ex_w - 2);
-        ly = (DIM == 2) ? min(max(ly, 0), ey_w - 2) : 0;
+        ly = (DIM >= 2) ? min(max(ly, 0), ey_w - 2) : 0;
+        lz = (DIM == 3) ? min(max(lz, 0), ez_w - 2) : 0;
         q.ix = x0 + lx;
         q.iy = y0 + ly;
+        q.iz = z0 + lz;
     }
     R ex, ey;
-    gather_lds<R, DIM>(sE, ex_w, ex_w * ey_w, lx, ly, q.fx, q.fy, ex, ey);
+    if constexpr (DIM == 3) {
+        R ez;
+        const int wxy = ex_w * ey_w;
+        gather_lds3<R>(sE, ex_w, wxy, wxy * ez_w, lx, ly, lz, q.fx, q.fy, q.fz, ex, ey, ez);
+        boris_z<R>(q.vz, ez, a);
+    } else {
+        gather_lds<R, DIM>(sE, ex_w, ex_w * ey_w, lx, ly, q.fx, q.fy, ex, ey);
+    }
     boris<R, VDIM>(q.vx, q.vy, ex, ey, a, t, s);
-    return move_pt<MIX, DIM>(q, g, pc, sx, sy) && in;
+    return move_pt<MIX, DIM>(q, g, pc, sx, sy, sz) && in;
 }
 
 // Raw stored words of one particle: loaded unconditionally (the caller clamps
 // the index) so that a wave issues all its loads before it needs any data.
 template <bool MIX> struct Raw {
     int32_t c;
-    float ox, oy, vx, vy, vz;
+    float ox, oy, oz, vx, vy, vz;
 };
 template <> struct Raw<false> {
-    double x, y, vx, vy, vz;
+    double x, y, z, vx, vy, vz;
 };
 
 template <bool MIX, int DIM, int VDIM>
@@ -168,13 +217,15 @@ __device__ __forceinline__ void load_raw(const Parts &s, int i, Raw<MIX> &r) {
     if constexpr (MIX) {
         r.c = s.cell[i];
         r.ox = s.ox[i];
-        r.oy = (DIM == 2) ? s.oy[i] : 0.0f;
+        r.oy = (DIM >= 2) ? s.oy[i] : 0.0f;
+        r.oz = (DIM == 3) ? s.oz[i] : 0.0f;
         r.vx = ((const float *)s.vx)[i];
         r.vy = (VDIM >= 2) ? ((const float *)s.vy)[i] : 0.0f;
         r.vz = (VDIM >= 3) ? ((const float *)s.vz)[i] : 0.0f;
     } else {
         r.x = s.x[i];
-        r.y = (DIM == 2) ? s.y[i] : 0.0;
+        r.y = (DIM >= 2) ? s.y[i] : 0.0;
+        r.z = (DIM == 3) ? s.z[i] : 0.0;
         r.vx = ((const double *)s.vx)[i];
         r.vy = (VDIM >= 2) ? ((const double *)s.vy)[i] : 0.0;
         r.vz = (VDIM >= 3) ? ((const double *)s.vz)[i] : 0.0;
@@ -186,26 +237,30 @@ template <bool MIX, int DIM, int VDIM>
 __device__ __forceinline__ bool decode(const Raw<MIX> &r, const Geo &g, Pt<MIX> &p) {
     bool ok;
     if constexpr (MIX) {
-        p.ix = (DIM == 2) ? (r.c & 0xFFFF) : r.c;
-        p.iy = (DIM == 2) ? (r.c >> 16) : 0;
+        unpack_cell<DIM>(r.c, p.ix, p.iy, p.iz);
         p.fx = r.ox;
-        p.fy = (DIM == 2) ? r.oy : 0.0f;
+        p.fy = (DIM >= 2) ? r.oy : 0.0f;
+        p.fz = (DIM == 3) ? r.oz : 0.0f;
         ok = (unsigned)p.ix < (unsigned)g.nx && (p.fx >= 0.0f) && (p.fx < 1.0f);
-        if constexpr (DIM == 2) ok = ok && (unsigned)p.iy < (unsigned)g.ny && (p.fy >= 0.0f) && (p.fy < 1.0f);
-        if (!ok) { p.ix = 0; p.iy = 0; p.fx = 0.0f; p.fy = 0.0f; }
+        if constexpr (DIM >= 2) ok = ok && (unsigned)p.iy < (unsigned)g.ny && (p.fy >= 0.0f) && (p.fy < 1.0f);
+        if constexpr (DIM == 3) ok = ok && (unsigned)p.iz < (unsigned)g.nz && (p.fz >= 0.0f) && (p.fz < 1.0f);
+        if (!ok) { p.ix = 0; p.iy = 0; p.iz = 0; p.fx = 0.0f; p.fy = 0.0f; p.fz = 0.0f; }
     } else {
         p.x = r.x;
         double f;
         ok = cell_f64(p.x, g.inv_dx, g.nx, p.ix, f);
         p.fx = f;
-        if constexpr (DIM == 2) {
+        p.y = 0.0; p.iy = 0; p.fy = 0.0;
+        p.z = 0.0; p.iz = 0; p.fz = 0.0;
+        if constexpr (DIM >= 2) {
             p.y = r.y;
             ok = cell_f64(p.y, g.inv_dy, g.ny, p.iy, f) && ok;
             p.fy = f;
-        } else {
-            p.y = 0.0;
-            p.iy = 0;
-            p.fy = 0.0;
+        }
+        if constexpr (DIM == 3) {
+            p.z = r.z;
+            ok = cell_f64(p.z, g.inv_dz, g.nz, p.iz, f) && ok;
+            p.fz = f;
         }
     }
     p.vx = r.vx;
@@ -333,7 +388,7 @@ __global__ void __launch_bounds__(kBlock) k_keys_init(Geo g, Parts p, int64_t n,
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         Pt<MIX> q;
         if (!load_pt<MIX, DIM, VDIM>(p, i, g, q)) raise_err(c.err, ERR_DOMAIN);
-        keys[i] = bucket_of<MIX, DIM>(g, q.ix, q.iy);
+        keys[i] = bucket_of<MIX, DIM>(g, q.ix, q.iy, q.iz);
         idx[i] = (int32_t)i;
     }
 }
@@ -492,10 +547,12 @@ __global__ void __launch_bounds__(kBlock) k_gather_parts(Parts src, Parts dst, i
         if constexpr (MIX) {
             dst.cell[j] = src.cell[i];
             dst.ox[j] = src.ox[i];
-            if constexpr (DIM == 2) dst.oy[j] = src.oy[i];
+            if constexpr (DIM >= 2) dst.oy[j] = src.oy[i];
+            if constexpr (DIM == 3) dst.oz[j] = src.oz[i];
         } else {
             dst.x[j] = src.x[i];
-            if constexpr (DIM == 2) dst.y[j] = src.y[i];
+            if constexpr (DIM >= 2) dst.y[j] = src.y[i];
+            if constexpr (DIM == 3) dst.z[j] = src.z[i];
         }
         ((R *)dst.vx)[j] = ((const R *)src.vx)[i];
         if constexpr (VDIM >= 2) ((R *)dst.vy)[j] = ((const R *)src.vy)[i];
@@ -515,9 +572,12 @@ __global__ void __launch_bounds__(kBlock) k_deposit_direct(Geo g, Parts p, int64
             raise_err(c.err, ERR_DOMAIN);
             continue;
         }
-        typename AccOf<MIX>::T w[4];
+        typename AccOf<MIX>::T w[8];
         dep_weights<MIX, DIM>(q, g, w);
-        deposit_global<MIX, DIM>(acc, g, q.ix, q.iy, w);
+        if constexpr (DIM == 3)
+            deposit_global3<MIX>(acc, g, q.ix, q.iy, q.iz, w);
+        else
+            deposit_global<MIX, DIM>(acc, g, q.ix, q.iy, w);
     }
 }
 
@@ -529,12 +589,13 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(Geo g, Parts p, const 
     A *sA = (A *)smem;
     const int b = bucket_of_block(g.nbuckets);
     if (b >= g.nbuckets) return;
-    const int bx = (DIM == 2) ? (b % g.nbx) : b;
-    const int by = (DIM == 2) ? (b / g.nbx) : 0;
-    const int x0 = bx << g.tsx, y0 = (DIM == 2) ? (by << g.tsy) : 0;
+    int bx, by, bz;
+    tile_coords<DIM>(g, b, bx, by, bz);
+    const int x0 = bx << g.tsx, y0 = (DIM >= 2) ? (by << g.tsy) : 0, z0 = (DIM == 3) ? (bz << g.tsz) : 0;
     const int wx = (1 << g.tsx) + 1;
-    const int wy = (DIM == 2) ? (1 << g.tsy) + 1 : 1;
-    for (int t = threadIdx.x; t < wx * wy; t += blockDim.x) sA[t] = (A)0;
+    const int wy = (DIM >= 2) ? (1 << g.tsy) + 1 : 1;
+    const int wz = (DIM == 3) ? (1 << g.tsz) + 1 : 1;
+    for (int t = threadIdx.x; t < wx * wy * wz; t += blockDim.x) sA[t] = (A)0;
     __syncthreads();
     const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
     for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
@@ -543,26 +604,42 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(Geo g, Parts p, const 
             raise_err(c.err, ERR_DOMAIN);
             continue;
         }
-        A w[4];
+        A w[8];
         dep_weights<MIX, DIM>(q, g, w);
         int lx = q.ix - x0;
-        int ly = (DIM == 2) ? q.iy - y0 : 0;
-        bool inl = (lx >= 0) && (lx <= wx - 2) && ((DIM == 1) || (ly >= 0 && ly <= wy - 2));
+        int ly = (DIM >= 2) ? q.iy - y0 : 0;
+        int lz = (DIM == 3) ? q.iz - z0 : 0;
+        bool inl = (lx >= 0) && (lx <= wx - 2);
+        if constexpr (DIM >= 2) inl = inl && ly >= 0 && ly <= wy - 2;
+        if constexpr (DIM == 3) inl = inl && lz >= 0 && lz <= wz - 2;
         if (inl) {
-            int a = ly * wx + lx;
+            int a = (lz * wy + ly) * wx + lx;
             acc_add<MIX>(&sA[a], w[0]);
             acc_add<MIX>(&sA[a + 1], w[1]);
-            if constexpr (DIM == 2) {
+            if constexpr (DIM >= 2) {
                 acc_add<MIX>(&sA[a + wx], w[2]);
                 acc_add<MIX>(&sA[a + wx + 1], w[3]);
             }
+            if constexpr (DIM == 3) {
+                const int wxy = wx * wy;
+                acc_add<MIX>(&sA[a + wxy], w[4]);
+                acc_add<MIX>(&sA[a + wxy + 1], w[5]);
+                acc_add<MIX>(&sA[a + wxy + wx], w[6]);
+                acc_add<MIX>(&sA[a + wxy + wx + 1], w[7]);
+            }
         } else {
             raise_err(c.err, ERR_ORDER);
-            deposit_global<MIX, DIM>(acc, g, q.ix, q.iy, w);
+            if constexpr (DIM == 3)
+                deposit_global3<MIX>(acc, g, q.ix, q.iy, q.iz, w);
+            else
+                deposit_global<MIX, DIM>(acc, g, q.ix, q.iy, w);
         }
     }
     __syncthreads();
-    flush_region<MIX, DIM>(acc, sA, g, x0, y0, wx, wy, 0);
+    if constexpr (DIM == 3)
+        flush_region3<MIX>(acc, sA, g, x0, y0, z0, wx, wy, wz, 0);
+    else
+        flush_region<MIX, DIM>(acc, sA, g, x0, y0, wx, wy, 0);
 }
 
 // ---- gather + push (+ move), in place -------------------------------------------
@@ -580,7 +657,13 @@ __global__ void __launch_bounds__(kBlock) k_gather_push_direct(Geo g, Parts p, i
             continue;
         }
         R ex, ey;
-        gather_global<R, R, DIM>(E, g, q.ix, q.iy, q.fx, q.fy, ex, ey);
+        if constexpr (DIM == 3) {
+            R ez;
+            gather_global3<R, R>(E, g, q.ix, q.iy, q.iz, q.fx, q.fy, q.fz, ex, ey, ez);
+            boris_z<R>(q.vz, ez, a);
+        } else {
+            gather_global<R, R, DIM>(E, g, q.ix, q.iy, q.fx, q.fy, ex, ey);
+        }
         boris<R, VDIM>(q.vx, q.vy, ex, ey, a, t, s);
         if (pc.move) {
             int sx, sy;
@@ -599,11 +682,15 @@ __global__ void __launch_bounds__(kBlock) k_gather_push_tiled(Geo g, Parts p, co
     R *sE = (R *)smem;
     const int b = bucket_of_block(g.nbuckets);
     if (b >= g.nbuckets) return;
-    const int bx = (DIM == 2) ? (b % g.nbx) : b;
-    const int by = (DIM == 2) ? (b / g.nbx) : 0;
-    const int x0 = bx << g.tsx, y0 = (DIM == 2) ? (by << g.tsy) : 0;
-    const int ex_w = (1 << g.tsx) + 1, ey_w = (DIM == 2) ? (1 << g.tsy) + 1 : 1;
-    load_e_tile<R, R, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
+    int bx, by, bz;
+    tile_coords<DIM>(g, b, bx, by, bz);
+    const int x0 = bx << g.tsx, y0 = (DIM >= 2) ? (by << g.tsy) : 0, z0 = (DIM == 3) ? (bz << g.tsz) : 0;
+    const int ex_w = (1 << g.tsx) + 1, ey_w = (DIM >= 2) ? (1 << g.tsy) + 1 : 1;
+    const int ez_w = (DIM == 3) ? (1 << g.tsz) + 1 : 1;
+    if constexpr (DIM == 3)
+        load_e_tile3<R, R>(sE, E, g, x0, y0, z0, ex_w, ey_w, ez_w);
+    else
+        load_e_tile<R, R, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
     __syncthreads();
     const R a = MIX ? (R)pc.af : (R)pc.a, t = MIX ? (R)pc.tf : (R)pc.t, s = MIX ? (R)pc.sf : (R)pc.s;
     const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
@@ -613,18 +700,33 @@ __global__ void __launch_bounds__(kBlock) k_gather_push_tiled(Geo g, Parts p, co
             raise_err(c.err, ERR_DOMAIN);
             continue;
         }
-        int lx = q.ix - x0, ly = (DIM == 2) ? q.iy - y0 : 0;
+        const int lx = q.ix - x0, ly = (DIM >= 2) ? q.iy - y0 : 0, lz = (DIM == 3) ? q.iz - z0 : 0;
+        bool inl = lx >= 0 && lx < ex_w - 1;
+        if constexpr (DIM >= 2) inl = inl && ly >= 0 && ly < ey_w - 1;
+        if constexpr (DIM == 3) inl = inl && lz >= 0 && lz < ez_w - 1;
         R ex, ey;
-        if (lx >= 0 && lx < ex_w - 1 && ly >= 0 && (DIM == 1 || ly < ey_w - 1)) {
-            gather_lds<R, DIM>(sE, ex_w, ex_w * ey_w, lx, ly, q.fx, q.fy, ex, ey);
+        if constexpr (DIM == 3) {
+            R ez;
+            if (inl) {
+                const int wxy = ex_w * ey_w;
+                gather_lds3<R>(sE, ex_w, wxy, wxy * ez_w, lx, ly, lz, q.fx, q.fy, q.fz, ex, ey, ez);
+            } else {
+                raise_err(c.err, ERR_ORDER);
+                gather_global3<R, R>(E, g, q.ix, q.iy, q.iz, q.fx, q.fy, q.fz, ex, ey, ez);
+            }
+            boris_z<R>(q.vz, ez, a);
         } else {
-            raise_err(c.err, ERR_ORDER);
-            gather_global<R, R, DIM>(E, g, q.ix, q.iy, q.fx, q.fy, ex, ey);
+            if (inl) {
+                gather_lds<R, DIM>(sE, ex_w, ex_w * ey_w, lx, ly, q.fx, q.fy, ex, ey);
+            } else {
+                raise_err(c.err, ERR_ORDER);
+                gather_global<R, R, DIM>(E, g, q.ix, q.iy, q.fx, q.fy, ex, ey);
+            }
         }
         boris<R, VDIM>(q.vx, q.vy, ex, ey, a, t, s);
         if (pc.move) {
-            int sx, sy;
-            if (!move_pt<MIX, DIM>(q, g, pc, sx, sy)) raise_err(c.err, ERR_DOMAIN);
+            int sx, sy, sz;
+            if (!move_pt<MIX, DIM>(q, g, pc, sx, sy, sz)) raise_err(c.err, ERR_DOMAIN);
         }
         store_pt<MIX, DIM, VDIM>(p, i, q);
     }
@@ -652,58 +754,69 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
                                                        PushC pc, int32_t *cnt, int32_t *tot, int32_t *farcnt,
                                                        const int32_t *deep, CtxDev c) {
     using R = typename Pt<MIX>::R;
+    constexpr int kDirs = Dir<DIM>::kN, kFar = Dir<DIM>::kFar, kStay = Dir<DIM>::kStay, kTab = Dir<DIM>::kTab;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sErr;
     __shared__ int32_t sCnt[kTab];
-    __shared__ float sMax[kWaves][2];
+    __shared__ float sMax[kWaves][3];
     R *sE = (R *)smem;
     const int w = threadIdx.x >> 6;
-    const int ex_w = (1 << g.tsx) + 1, ey_w = (DIM == 2) ? (1 << g.tsy) + 1 : 1;
+    const int ex_w = (1 << g.tsx) + 1, ey_w = (DIM >= 2) ? (1 << g.tsy) + 1 : 1;
+    const int ez_w = (DIM == 3) ? (1 << g.tsz) + 1 : 1;
     if (threadIdx.x == 0) sErr = 0;
     int first, end, stride;
     bucket_walk(g.nbuckets, first, end, stride);
     for (int b = first; b < end; b += stride) {
-        const int bx = (DIM == 2) ? (b % g.nbx) : b;
-        const int by = (DIM == 2) ? (b / g.nbx) : 0;
-        const int x0 = bx << g.tsx, y0 = (DIM == 2) ? (by << g.tsy) : 0;
-        const TileNb tn = tile_nb<DIM>(g, bx, by);
+        int bx, by, bz;
+        tile_coords<DIM>(g, b, bx, by, bz);
+        const int x0 = bx << g.tsx, y0 = (DIM >= 2) ? (by << g.tsy) : 0, z0 = (DIM == 3) ? (bz << g.tsz) : 0;
+        const TileNb tn = tile_nb<DIM>(g, bx, by, bz);
         if (threadIdx.x < kTab) sCnt[threadIdx.x] = 0;
-        load_e_tile<R, double, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
+        if constexpr (DIM == 3)
+            load_e_tile3<R, double>(sE, E, g, x0, y0, z0, ex_w, ey_w, ez_w);
+        else
+            load_e_tile<R, double, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
         __syncthreads();
         const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
         const int span = i1 - i0;
-        // field bound of the tile: per axis, or |E| when the push rotates v
+        // field bound of the tile: per axis, or the in-plane |E| when the push
+        // rotates v about z
         {
-            float e0 = 0.0f, e1 = 0.0f;
-            const int tn = ex_w * ey_w;
+            float e0 = 0.0f, e1 = 0.0f, e2 = 0.0f;
+            const int tn = ex_w * ey_w * ez_w;
             for (int t = threadIdx.x; t < tn; t += blockDim.x) {
                 const float ex = fabsf((float)sE[t]);
-                const float ey = (DIM == 2) ? fabsf((float)sE[tn + t]) : 0.0f;
+                const float ey = (DIM >= 2) ? fabsf((float)sE[tn + t]) : 0.0f;
                 if (pc.rot) {
                     e0 = fmaxf(e0, sqrtf(ex * ex + ey * ey));
                 } else {
                     e0 = fmaxf(e0, ex);
                     e1 = fmaxf(e1, ey);
                 }
+                if constexpr (DIM == 3) e2 = fmaxf(e2, fabsf((float)sE[2 * tn + t]));
             }
             for (int off = 32; off > 0; off >>= 1) {
                 e0 = fmaxf(e0, __shfl_xor(e0, off));
                 e1 = fmaxf(e1, __shfl_xor(e1, off));
+                e2 = fmaxf(e2, __shfl_xor(e2, off));
             }
             if ((threadIdx.x & 63) == 0) {
                 sMax[w][0] = e0;
                 sMax[w][1] = pc.rot ? e0 : e1;
+                sMax[w][2] = e2;
             }
         }
         __syncthreads();
-        float emx = 0.0f, emy = 0.0f;
+        float emx = 0.0f, emy = 0.0f, emz = 0.0f;
         for (int w2 = 0; w2 < kWaves; ++w2) {
             emx = fmaxf(emx, sMax[w2][0]);
             emy = fmaxf(emy, sMax[w2][1]);
+            emz = fmaxf(emz, sMax[w2][2]);
         }
         const float kick = 2.0f * fabsf(MIX ? pc.af : (float)pc.a) * 1.0009765625f;
         bool skip = kick * emx * pc.dtdx + 0.0009765625f <= pc.deep;
-        if constexpr (DIM == 2) skip = skip && kick * emy * pc.dtdy + 0.0009765625f <= pc.deep;
+        if constexpr (DIM >= 2) skip = skip && kick * emy * pc.dtdy + 0.0009765625f <= pc.deep;
+        if constexpr (DIM == 3) skip = skip && kick * emz * pc.dtdz + 0.0009765625f <= pc.deep;
         // deep ranges of this bucket: increasing, disjoint, inside [0, span)
         int da[kWaves], dc[kWaves], ndeep = 0;
         {
@@ -735,14 +848,15 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
                 load_raw<MIX, DIM, VDIM>(p, i0 + k, r1);
                 Pt<MIX> q;
                 bool good = decode<MIX, DIM, VDIM>(r1, g, q);
-                int lx, ly, sx, sy;
-                good = advance<MIX, DIM, VDIM>(q, g, pc, sE, ex_w, ey_w, x0, y0, lx, ly, sx, sy) && good;
+                int lx, ly, lz, sx, sy, sz;
+                good = advance<MIX, DIM, VDIM>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx, sy, sz) &&
+                       good;
                 if (!good) atomicOr(&sErr, ERR_DOMAIN);
-                const int code = dir_local<DIM>(tn, lx + sx, ly + sy);
+                const int code = dir_local<DIM>(tn, lx + sx, ly + sy, lz + sz);
                 if (code < kFar) {
                     atomicAdd(&sCnt[((k % kBlock) >> 6) * kDirs + code], 1);
                 } else {
-                    const int nbk = ((DIM == 2) ? (q.iy >> g.tsy) * g.nbx : 0) + (q.ix >> g.tsx);
+                    const int nbk = bucket_of<MIX, DIM>(g, q.ix, q.iy, q.iz);
                     atomicAdd(&farcnt[nbk], 1);
                     atomicAdd(&tot[nbk], 1);
                 }
@@ -767,11 +881,12 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
                 if (act) {
                     Pt<MIX> q;
                     bool good = decode<MIX, DIM, VDIM>(r[j], g, q);
-                    int lx, ly, sx, sy;
-                    good = advance<MIX, DIM, VDIM>(q, g, pc, sE, ex_w, ey_w, x0, y0, lx, ly, sx, sy) && good;
+                    int lx, ly, lz, sx, sy, sz;
+                    good = advance<MIX, DIM, VDIM>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx, sy,
+                                                   sz) && good;
                     if (!good) atomicOr(&sErr, ERR_DOMAIN);
-                    code = dir_local<DIM>(tn, lx + sx, ly + sy);
-                    if (code == kFar) nbk = ((DIM == 2) ? (q.iy >> g.tsy) * g.nbx : 0) + (q.ix >> g.tsx);
+                    code = dir_local<DIM>(tn, lx + sx, ly + sy, lz + sz);
+                    if (code == kFar) nbk = bucket_of<MIX, DIM>(g, q.ix, q.iy, q.iz);
                 }
                 uint64_t rem = __ballot(code >= 0 && code < kFar);
                 while (rem) {
@@ -800,20 +915,43 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
         if (threadIdx.x < kFar) {
             int v = 0;
             for (int w2 = 0; w2 < kWaves; ++w2) v += sCnt[w2 * kDirs + threadIdx.x];
-            if (v) {
-                const int d = threadIdx.x;
-                int nx_ = bx + d % 3 - 1, ny_ = by + d / 3 - 1;
-                if (nx_ < 0) nx_ += g.nbx;
-                if (nx_ >= g.nbx) nx_ -= g.nbx;
-                if (ny_ < 0) ny_ += g.nby;
-                if (ny_ >= g.nby) ny_ -= g.nby;
-                atomicAdd(&tot[(DIM == 2) ? ny_ * g.nbx + nx_ : nx_], v);
-            }
+            if (v) atomicAdd(&tot[dir_target<DIM>(g, bx, by, bz, threadIdx.x)], v);
         }
         __syncthreads();
     }
     __syncthreads();
     if (threadIdx.x == 0 && sErr) raise_err(c.err, sErr);
+}
+
+// ---- fused step: first slot of every tally inside its destination bucket -----
+// One wave per destination bucket nbk: its incoming tallies, in (direction,
+// source wave) order, are prefix-summed from the bucket's new start. Every
+// (source bucket, wave, near direction) entry has exactly one destination, so
+// each offs entry is written once.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_dest_offsets(Geo g, const int32_t *cnt, const int32_t *start,
+                                                         int32_t *offs) {
+    constexpr int kDirs = Dir<DIM>::kN, kFar = Dir<DIM>::kFar, kTab = Dir<DIM>::kTab;
+    constexpr int kIn = kFar * kWaves;  // incoming entries per destination
+    const int nbk = (int)blockIdx.x * kWaves + (int)(threadIdx.x >> 6);
+    if (nbk >= g.nbuckets) return;      // whole waves leave together; no barrier below
+    const int lane = threadIdx.x & 63;
+    int run = start[nbk];
+#pragma unroll
+    for (int r = 0; r < (kIn + 63) / 64; ++r) {
+        const int e = r * 64 + lane;    // entry e = d * kWaves + wave
+        const bool ok = e < kIn;
+        const int d = ok ? e / kWaves : 0, wv = ok ? e % kWaves : 0;
+        const int src = ok ? dir_source<DIM>(g, nbk, d) : 0;
+        const int v = ok ? cnt[src * kTab + wv * kDirs + d] : 0;
+        int inc = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
+        }
+        if (ok) offs[src * kTab + wv * kDirs + d] = run + inc - v;
+        run += __shfl(inc, 63);
+    }
 }
 
 // ---- fused step, pass 2: push, deposit, scatter into the next bucket order -----
@@ -828,11 +966,12 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
 template <bool MIX, int DIM, int VDIM, int U>
 __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts dst, const int32_t *bstart,
                                                       const int32_t *bstart_new, const int32_t *cnt,
-                                                      int32_t *farcnt, const double *E, PushC pc,
+                                                      const int32_t *offs, int32_t *farcnt, const double *E, PushC pc,
                                                       typename AccOf<MIX>::T *acc, int32_t *perm, double *part,
                                                       int32_t *deep_out, CtxDev c) {
     using R = typename Pt<MIX>::R;
     using A = typename AccOf<MIX>::T;
+    constexpr int kDirs = Dir<DIM>::kN, kFar = Dir<DIM>::kFar, kStay = Dir<DIM>::kStay, kTab = Dir<DIM>::kTab;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sErr;
     __shared__ double sRed[kWaves];
@@ -840,43 +979,33 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
     __shared__ int32_t sEnd[kFar];   // end of each neighbour destination bucket (slot bound)
     __shared__ int32_t sBack[kWaves];    // next free slot, from the back, of each wave's stay range
     __shared__ int32_t sFront0[kWaves];  // first slot of each wave's stay range
-    const int ex_w = (1 << g.tsx) + 1, ey_w = (DIM == 2) ? (1 << g.tsy) + 1 : 1;
+    const int ex_w = (1 << g.tsx) + 1, ey_w = (DIM >= 2) ? (1 << g.tsy) + 1 : 1;
+    const int ez_w = (DIM == 3) ? (1 << g.tsz) + 1 : 1;
     const int wx = (1 << g.tsx) + 1 + 2 * g.halo;
-    const int wy = (DIM == 2) ? (1 << g.tsy) + 1 + 2 * g.halo : 1;
+    const int wy = (DIM >= 2) ? (1 << g.tsy) + 1 + 2 * g.halo : 1;
+    const int wz = (DIM == 3) ? (1 << g.tsz) + 1 + 2 * g.halo : 1;
+    const int wxy = wx * wy;
     A *sA = (A *)smem;
-    R *sE = (R *)(smem + (((size_t)wx * wy * sizeof(A) + 15) & ~(size_t)15));
+    R *sE = (R *)(smem + (((size_t)wxy * wz * sizeof(A) + 15) & ~(size_t)15));
     const int w = threadIdx.x >> 6;
     const uint64_t lt = lanemask_lt();
     if (threadIdx.x == 0) sErr = 0;
     int first, end, stride;
     bucket_walk(g.nbuckets, first, end, stride);
     for (int b = first; b < end; b += stride) {
-        const int bx = (DIM == 2) ? (b % g.nbx) : b;
-        const int by = (DIM == 2) ? (b / g.nbx) : 0;
-        const int x0 = bx << g.tsx, y0 = (DIM == 2) ? (by << g.tsy) : 0;
-        const TileNb tn = tile_nb<DIM>(g, bx, by);
-        for (int t2 = threadIdx.x; t2 < wx * wy; t2 += blockDim.x) sA[t2] = (A)0;
-        // first slot of each (wave, direction) tally of this bucket: inside the
-        // destination bucket the tallies of its sources follow direction order,
-        // then wave order, so the offset is the destination's start plus the
-        // tallies that precede this one.
+        int bx, by, bz;
+        tile_coords<DIM>(g, b, bx, by, bz);
+        const int x0 = bx << g.tsx, y0 = (DIM >= 2) ? (by << g.tsy) : 0, z0 = (DIM == 3) ? (bz << g.tsz) : 0;
+        const TileNb tn = tile_nb<DIM>(g, bx, by, bz);
+        for (int t2 = threadIdx.x; t2 < wxy * wz; t2 += blockDim.x) sA[t2] = (A)0;
+        // first slot of each (wave, direction) tally of this bucket inside its
+        // destination bucket (from the offsets pass), and each destination's end
         if (threadIdx.x < kTab) {
             const int w2 = threadIdx.x / kDirs, d = threadIdx.x % kDirs;
             int off = 0;
             if (d < kFar) {
-                int nx_ = bx + d % 3 - 1, ny_ = by + d / 3 - 1;
-                if (nx_ < 0) nx_ += g.nbx;
-                if (nx_ >= g.nbx) nx_ -= g.nbx;
-                if (ny_ < 0) ny_ += g.nby;
-                if (ny_ >= g.nby) ny_ -= g.nby;
-                const int nb = (DIM == 2) ? ny_ * g.nbx + nx_ : nx_;
-                off = bstart_new[nb];
-                for (int d2 = 0; d2 < d; ++d2) {
-                    const int s2 = dir_source(g, nb, d2);
-                    for (int w3 = 0; w3 < kWaves; ++w3) off += cnt[s2 * kTab + w3 * kDirs + d2];
-                }
-                for (int w3 = 0; w3 < w2; ++w3) off += cnt[b * kTab + w3 * kDirs + d];
-                if (w2 == 0) sEnd[d] = bstart_new[nb + 1];
+                off = offs[b * kTab + threadIdx.x];
+                if (w2 == 0) sEnd[d] = bstart_new[dir_target<DIM>(g, bx, by, bz, d) + 1];
                 if (d == kStay) {
                     sFront0[w2] = off;
                     sBack[w2] = off + cnt[b * kTab + w2 * kDirs + kStay];
@@ -884,13 +1013,17 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
             }
             sRun[threadIdx.x] = off;
         }
-        load_e_tile<R, double, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
+        if constexpr (DIM == 3)
+            load_e_tile3<R, double>(sE, E, g, x0, y0, z0, ex_w, ey_w, ez_w);
+        else
+            load_e_tile<R, double, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
         __syncthreads();
         const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
         const int span = i1 - i0;
         // cells of this tile (the last tile of an axis may be cut by the grid edge)
         const float txe = (float)tn.txe;
         const float tye = (float)tn.tye;
+        const float tze = (float)tn.tze;
         double ke = 0.0, px = 0.0;
         constexpr int CH = kBlock * U;
         // Two schedules over chunks of CH particles.
@@ -940,14 +1073,15 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                 if (act) {
                     bool good = decode<MIX, DIM, VDIM>(r[j], g, q);
                     const double v2o = vsq<MIX, VDIM>(q);
-                    int lx, ly, sx, sy;
-                    good = advance<MIX, DIM, VDIM>(q, g, pc, sE, ex_w, ey_w, x0, y0, lx, ly, sx, sy) && good;
+                    int lx, ly, lz, sx, sy, sz;
+                    good = advance<MIX, DIM, VDIM>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx, sy,
+                                                   sz) && good;
                     if (!good) atomicOr(&sErr, ERR_DOMAIN);
                     const double v2n = vsq<MIX, VDIM>(q);
                     ke += 0.5 * (v2o + v2n);
                     px += (double)q.vx;
-                    code = dir_local<DIM>(tn, lx + sx, ly + sy);
-                    if (code == kFar) nbk = ((DIM == 2) ? (q.iy >> g.tsy) * g.nbx : 0) + (q.ix >> g.tsx);
+                    code = dir_local<DIM>(tn, lx + sx, ly + sy, lz + sz);
+                    if (code == kFar) nbk = bucket_of<MIX, DIM>(g, q.ix, q.iy, q.iz);
                     if (code == kStay) {
                         const float ux = (float)(q.ix - x0) + (float)q.fx;
                         const float mx = fminf(ux, txe - ux) - pc.deep;
@@ -965,22 +1099,39 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                                 const float vv = sqrtf(vx * vx + vy * vy);
                                 deep = mx >= vv * pc.dtdx && my >= vv * pc.dtdy;
                             }
+                            if constexpr (DIM == 3) {
+                                // vz only takes the kicks of Ez (the rotation is about z)
+                                const float uz = (float)(q.iz - z0) + (float)q.fz;
+                                const float mz = fminf(uz, tze - uz) - pc.deep;
+                                deep = deep && mz >= fabsf((float)q.vz) * pc.dtdz;
+                            }
                         }
                     }
                     // deposit rho^{n+1}: LDS tile + halo, global beyond it
-                    A wgt[4];
+                    A wgt[8];
                     dep_weights<MIX, DIM>(q, g, wgt);
                     const int dlx = lx + sx + g.halo;
-                    const int dly = (DIM == 2) ? ly + sy + g.halo : 0;
-                    const bool inl = (unsigned)dlx <= (unsigned)(wx - 2) && ((DIM == 1) || (unsigned)dly <= (unsigned)(wy - 2));
+                    const int dly = (DIM >= 2) ? ly + sy + g.halo : 0;
+                    const int dlz = (DIM == 3) ? lz + sz + g.halo : 0;
+                    bool inl = (unsigned)dlx <= (unsigned)(wx - 2);
+                    if constexpr (DIM >= 2) inl = inl && (unsigned)dly <= (unsigned)(wy - 2);
+                    if constexpr (DIM == 3) inl = inl && (unsigned)dlz <= (unsigned)(wz - 2);
                     if (inl) {
-                        const int a0 = dly * wx + dlx;
+                        const int a0 = (dlz * wy + dly) * wx + dlx;
                         acc_add<MIX>(&sA[a0], wgt[0]);
                         acc_add<MIX>(&sA[a0 + 1], wgt[1]);
-                        if constexpr (DIM == 2) {
+                        if constexpr (DIM >= 2) {
                             acc_add<MIX>(&sA[a0 + wx], wgt[2]);
                             acc_add<MIX>(&sA[a0 + wx + 1], wgt[3]);
                         }
+                        if constexpr (DIM == 3) {
+                            acc_add<MIX>(&sA[a0 + wxy], wgt[4]);
+                            acc_add<MIX>(&sA[a0 + wxy + 1], wgt[5]);
+                            acc_add<MIX>(&sA[a0 + wxy + wx], wgt[6]);
+                            acc_add<MIX>(&sA[a0 + wxy + wx + 1], wgt[7]);
+                        }
+                    } else if constexpr (DIM == 3) {
+                        deposit_global3<MIX>(acc, g, q.ix, q.iy, q.iz, wgt);
                     } else {
                         deposit_global<MIX, DIM>(acc, g, q.ix, q.iy, wgt);
                     }
@@ -1002,7 +1153,7 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                         const uint64_t gs = grp & ~gd;
                         const int back = sBack[w];
                         const int nd = (int)__popcll(gd), ns = (int)__popcll(gs);
-                        const bool fits = basek + nd <= back - ns;
+                        const bool fits = basek >= 0 && basek + nd <= back - ns && back <= sEnd[kStay];
                         if (code == kStay)
                             slot = !fits ? -1 : deep ? basek + (int)__popcll(gd & lt) : back - 1 - (int)__popcll(gs & lt);
                         if ((int)__lane_id() == leader) {
@@ -1010,7 +1161,7 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                             sBack[w] = back - ns;
                         }
                     } else {
-                        const bool fits = basek + cntk <= sEnd[kc];
+                        const bool fits = basek >= 0 && basek + cntk <= sEnd[kc];
                         if (code == kc) slot = fits ? basek + (int)__popcll(grp & lt) : -1;
                         if ((int)__lane_id() == leader) sRun[w * kDirs + kc] = basek + cntk;
                     }
@@ -1065,7 +1216,10 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
             deep_out[b * kDeepTab + 2 * t] = sFront0[t] - bstart_new[b];
             deep_out[b * kDeepTab + 2 * t + 1] = sRun[t * kDirs + kStay] - sFront0[t];
         }
-        flush_region<MIX, DIM>(acc, sA, g, x0, y0, wx, wy, g.halo);
+        if constexpr (DIM == 3)
+            flush_region3<MIX>(acc, sA, g, x0, y0, z0, wx, wy, wz, g.halo);
+        else
+            flush_region<MIX, DIM>(acc, sA, g, x0, y0, wx, wy, g.halo);
         if (part) {
             double kt = block_sum(ke, sRed);
             double pt = block_sum(px, sRed);
@@ -1104,25 +1258,28 @@ __global__ void __launch_bounds__(kBlock) k_rho(int64_t G, typename AccOf<MIX>::
 // spectrum, w = 1 on the kx = 0 and Nyquist columns, else 2) goes to
 // c.part_spec; rho_hat(0) (= sum_j rho_j) to c.rho0.
 __global__ void __launch_bounds__(kBlock) k_spectral(Geo g, const double2 *rh, double2 *exh, double2 *eyh,
-                                                     CtxDev c) {
+                                                     double2 *ezh, CtxDev c) {
     __shared__ double sRed[kWaves];
     const int hx = g.nx / 2 + 1;
-    const int64_t tot = (int64_t)hx * g.ny;
-    const double norm = 1.0 / ((double)g.nx * (double)g.ny);
+    const int64_t tot = (int64_t)hx * g.ny * g.nz;
+    const double norm = 1.0 / ((double)g.nx * (double)g.ny * (double)g.nz);
     double part = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
-        int kx = (int)(i % hx), ky = (int)(i / hx);
-        double K2 = c.kx2[kx] + c.ky2[ky];
-        double2 r = rh[i];
-        if (i == 0) *c.rho0 = r.x;
-        double inv = (kx == 0 && ky == 0) ? 0.0 : 1.0 / K2;
-        double pr = r.x * inv, pi = r.y * inv;
+        const int kx = (int)(i % hx);
+        const int64_t r = i / hx;
+        const int ky = (int)(r % g.ny), kz = (int)(r / g.ny);
+        double K2 = c.kx2[kx] + c.ky2[ky] + c.kz2[kz];
+        double2 rr = rh[i];
+        if (i == 0) *c.rho0 = rr.x;
+        double inv = (i == 0) ? 0.0 : 1.0 / K2;
+        double pr = rr.x * inv, pi = rr.y * inv;
         // -i * kappa * (pr + i pi) = kappa * pi - i kappa * pr
-        double kax = c.kapx[kx], kay = c.kapy[ky];
+        double kax = c.kapx[kx], kay = c.kapy[ky], kaz = c.kapz[kz];
         double wgt = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
-        part += wgt * (kax * kax + kay * kay) * (pr * pr + pi * pi);
+        part += wgt * (kax * kax + kay * kay + kaz * kaz) * (pr * pr + pi * pi);
         exh[i] = make_double2(kax * pi * norm, -kax * pr * norm);
         eyh[i] = make_double2(kay * pi * norm, -kay * pr * norm);
+        if (ezh) ezh[i] = make_double2(kaz * pi * norm, -kaz * pr * norm);
     }
     double bs = block_sum(part, sRed);
     if (threadIdx.x == 0) c.part_spec[blockIdx.x] = bs;
@@ -1201,14 +1358,16 @@ inline int blocks_for(int64_t n, int cap = 4096) {
 }
 
 inline size_t tile_e_bytes(const Geo &g, bool mixed) {
-    const int ex_w = (1 << g.tsx) + 1, ey_w = (g.dim == 2) ? (1 << g.tsy) + 1 : 1;
-    return (size_t)ex_w * ey_w * g.dim * (mixed ? 4 : 8);
+    const int ex_w = (1 << g.tsx) + 1, ey_w = (g.dim >= 2) ? (1 << g.tsy) + 1 : 1;
+    const int ez_w = (g.dim == 3) ? (1 << g.tsz) + 1 : 1;
+    return (size_t)ex_w * ey_w * ez_w * g.dim * (mixed ? 4 : 8);
 }
 
 inline size_t tile_acc_bytes(const Geo &g, int halo) {
     const int wx = (1 << g.tsx) + 1 + 2 * halo;
-    const int wy = (g.dim == 2) ? (1 << g.tsy) + 1 + 2 * halo : 1;
-    return (((size_t)wx * wy * 8) + 15) & ~(size_t)15;
+    const int wy = (g.dim >= 2) ? (1 << g.tsy) + 1 + 2 * halo : 1;
+    const int wz = (g.dim == 3) ? (1 << g.tsz) + 1 + 2 * halo : 1;
+    return (((size_t)wx * wy * wz * 8) + 15) & ~(size_t)15;
 }
 
 }  // namespace
@@ -1361,15 +1520,27 @@ hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int
     return hipGetLastError();
 }
 
+hipError_t launch_dest_offsets(const Geo &g, const int32_t *cnt, const int32_t *start, int32_t *offs,
+                               hipStream_t s) {
+    const dim3 grid((g.nbuckets + kWaves - 1) / kWaves);
+    if (g.dim == 3)
+        hipLaunchKernelGGL(k_dest_offsets<3>, grid, dim3(kBlock), 0, s, g, cnt, start, offs);
+    else if (g.dim == 2)
+        hipLaunchKernelGGL(k_dest_offsets<2>, grid, dim3(kBlock), 0, s, g, cnt, start, offs);
+    else
+        hipLaunchKernelGGL(k_dest_offsets<1>, grid, dim3(kBlock), 0, s, g, cnt, start, offs);
+    return hipGetLastError();
+}
+
 hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Parts &dst, const int32_t *bstart,
-                            const int32_t *bstart_new, const int32_t *cnt, int32_t *farcnt, const double *E,
-                            const PushC &pc, void *acc, int32_t *perm, double *part, int32_t *deep,
+                            const int32_t *bstart_new, const int32_t *cnt, const int32_t *offs, int32_t *farcnt,
+                            const double *E, const PushC &pc, void *acc, int32_t *perm, double *part, int32_t *deep,
                             const CtxDev &c, hipStream_t s) {
     size_t sh = tile_acc_bytes(g, g.halo) + tile_e_bytes(g, mixed);
     APIC_DISPATCH(g, mixed, {
         auto kern = k_step_push<MIX, DIM, VDIM, U>;
         hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, src, dst,
-                           bstart, bstart_new, cnt, farcnt, E, pc, (typename AccOf<MIX>::T *)acc, perm, part,
+                           bstart, bstart_new, cnt, offs, farcnt, E, pc, (typename AccOf<MIX>::T *)acc, perm, part,
                            deep, c);
     });
     return hipGetLastError();
@@ -1377,7 +1548,7 @@ hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Pa
 
 hipError_t launch_rho(const Geo &g, bool mixed, void *acc, double *rho, double scale, double add, int clear,
                       hipStream_t s) {
-    const int64_t G = (int64_t)g.nx * g.ny;
+    const int64_t G = (int64_t)g.nx * g.ny * g.nz;
     const int nb = blocks_for(G, 2048);
     if (mixed)
         hipLaunchKernelGGL(k_rho<true>, dim3(nb), dim3(kBlock), 0, s, G, (unsigned long long *)acc, rho, scale, add,
@@ -1387,12 +1558,12 @@ hipError_t launch_rho(const Geo &g, bool mixed, void *acc, double *rho, double s
     return hipGetLastError();
 }
 
-int spectral_blocks(const Geo &g) { return blocks_for((int64_t)(g.nx / 2 + 1) * g.ny, kMaxSpecBlocks); }
+int spectral_blocks(const Geo &g) { return blocks_for((int64_t)(g.nx / 2 + 1) * g.ny * g.nz, kMaxSpecBlocks); }
 
-hipError_t launch_spectral(const Geo &g, const void *rho_hat, void *ex_hat, void *ey_hat, const CtxDev &c,
-                           hipStream_t s) {
+hipError_t launch_spectral(const Geo &g, const void *rho_hat, void *ex_hat, void *ey_hat, void *ez_hat,
+                           const CtxDev &c, hipStream_t s) {
     hipLaunchKernelGGL(k_spectral, dim3(spectral_blocks(g)), dim3(kBlock), 0, s, g, (const double2 *)rho_hat,
-                       (double2 *)ex_hat, (double2 *)ey_hat, c);
+                       (double2 *)ex_hat, (double2 *)ey_hat, (double2 *)ez_hat, c);
     return hipGetLastError();
 }
 

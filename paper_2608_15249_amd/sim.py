@@ -23,11 +23,14 @@ class Simulation:
         self.torch = torch
         self.w = w
         if state is None:
-            state = W.sample(w, n)
+            state = W.sample3(w, n) if w.dim == 3 else W.sample(w, n)
         self.n = len(state[0])
         mk = lambda t: Context(dim=w.dim, vdim=w.vdim, nx=w.nx, ny=w.ny, lx=w.Lx, ly=w.Ly, dt=w.dt, n=self.n,
-                               bz=w.bz, precision=precision, frac_bits=frac_bits, tile=t, device=device)
+                               bz=w.bz, precision=precision, frac_bits=frac_bits, tile=t, device=device,
+                               nz=w.nz, lz=w.Lz)
         self.tune_ms = None
+        if tile == "auto" and w.dim == 3:
+            tile = (0, 0, 0)     # the tile autotuner covers 1D and 2D; 3D keeps the default tile
         if tile == "auto":
             # time the candidate tiles on this very state, then build the context with the pick
             ctx = mk((0, 0))
@@ -36,8 +39,8 @@ class Simulation:
             tx, ty, self.tune_ms = ctx.autotune_tiles(p)
             tile = (tx, ty)
             del p, ctx
-        self.tile = tuple(tile)
-        self.ctx = mk(self.tile)
+        self.ctx = mk(tuple(tile))
+        self.tile = self.ctx.tile      # the tile the context uses (defaults resolved)
         self.mixed = self.ctx.mixed
         self.p = Particles(self.ctx)
         self._upload(self.p, self.mixed, state)
@@ -50,6 +53,15 @@ class Simulation:
 
     def _upload(self, p, mixed, state):
         w = self.w
+        if w.dim == 3:
+            x, y, z, vx, vy, vz = state
+            if mixed:
+                c = [W.to_cell_offset(a, d, n) for a, d, n in ((x, w.dx, w.nx), (y, w.dy, w.ny), (z, w.dz, w.nz))]
+                p.upload(cell=W.pack_cell(c[0][0], c[1][0], c[2][0]), ox=c[0][1], oy=c[1][1], oz=c[2][1],
+                         vx=vx, vy=vy, vz=vz)
+            else:
+                p.upload(x=x, y=y, z=z, vx=vx, vy=vy, vz=vz)
+            return
         x, y, vx, vy, vz = state
         if mixed:
             ix, ox = W.to_cell_offset(x, w.dx, w.nx)
@@ -79,16 +91,18 @@ class Simulation:
         e = self.E.cpu().numpy()
         if self.w.dim == 1:
             return (e[:G].copy(),)
-        sh = (self.w.ny, self.w.nx)
-        return (e[:G].reshape(sh).copy(), e[G:].reshape(sh).copy())
+        sh = (self.w.nz, self.w.ny, self.w.nx) if self.w.dim == 3 else (self.w.ny, self.w.nx)
+        return tuple(e[k * G:(k + 1) * G].reshape(sh).copy() for k in range(self.w.dim))
 
     def state(self):
         """Host copy: dict of arrays in the device order (positions in FP64
         for the FP64 path; cell/offset for the mixed path)."""
         d = self.p.download()
         if self.mixed:
-            ix, iy = W.unpack_cell(d["cell"], self.w.dim)
-            d["ix"], d["iy"] = ix, iy
+            u = W.unpack_cell(d["cell"], self.w.dim)
+            d["ix"], d["iy"] = u[0], u[1]
+            if self.w.dim == 3:
+                d["iz"] = u[2]
         return d
 
 

@@ -36,8 +36,29 @@ def test_library_exports_every_declared_symbol():
         assert getattr(L, n).argtypes is not None or n in ("apic_destroy",), n
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """Size and every field offset of the binding's ctypes structs equal what
+    a C compiler gives for the structs of include/apic.h."""
+    import subprocess
     from paper_2608_15249_amd import apic
-    # apic_grid_desc: 4 ints, 7 doubles, 4 ints -> 88 bytes; apic_particles: int64 + 10 pointers
-    assert ctypes.sizeof(apic.GridDesc) == 88
-    assert ctypes.sizeof(apic.ParticlesC) == 8 + 10 * 8
+    structs = {"apic_grid_desc": apic.GridDesc, "apic_particles": apic.ParticlesC,
+               "apic_replica": apic.ReplicaC, "apic_batch_state": apic.BatchStateC}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "apic.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s sizeof %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = {}
+    for ln in subprocess.check_output([str(exe)]).decode().split("\n"):
+        if ln.strip():
+            a, b, v = ln.split()
+            got[(a, b)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
