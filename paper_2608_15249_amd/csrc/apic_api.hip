@@ -106,6 +106,7 @@ void layout(apic_ctx *c) {
     if (dim >= 2) {
         const int64_t H = (int64_t)(c->d.nx / 2 + 1) * c->d.ny * c->d.nz;
         c->o_rhat = take(16 * H);
+        // phi_hat (the field solve); the adjoint uses 2 spectra here in 2D
         c->o_ehat = take(16 * dim * H);
     } else {
         c->o_rhat = c->o_ehat = (size_t)-1;
@@ -218,16 +219,16 @@ apic_status field_from_acc(apic_ctx *c, void *acc, bool acc_is_rho, double *E, f
     double *rho = wsp<double>(ws, c->o_rho);
     void *rhat = wsp<void>(ws, c->o_rhat);
     char *ehat = wsp<char>(ws, c->o_ehat);
-    const size_t H = (size_t)(c->d.nx / 2 + 1) * c->d.ny * c->d.nz;
     HIPCHK(c, launch_rho(c->g, mixed_acc, acc, rho, scale, add, clear, s));
     FFTCHK(c, hipfftSetStream(c->fwd, s));
     FFTCHK(c, hipfftExecD2Z(c->fwd, (hipfftDoubleReal *)rho, (hipfftDoubleComplex *)rhat));
-    HIPCHK(c, launch_spectral(c->g, rhat, ehat, ehat + 16 * H, c->d.dim == 3 ? ehat + 32 * H : nullptr, c->dev, s));
+    HIPCHK(c, launch_spectral(c->g, rhat, ehat, c->dev, s));
     HIPCHK(c, launch_finalize(diag ? npush : 0, spectral_blocks(c->g), c->mass, c->dV, G, c->d.rho_ion, diag, we,
                               charge, c->dev, s));
+    // phi into the rho buffer (rho is no longer needed), then E from phi
     FFTCHK(c, hipfftSetStream(c->inv, s));
-    FFTCHK(c, hipfftExecZ2D(c->inv, (hipfftDoubleComplex *)ehat, (hipfftDoubleReal *)E));
-    if (E32) HIPCHK(c, launch_to_f32(E, E32, c->d.dim * (int64_t)G, s));
+    FFTCHK(c, hipfftExecZ2D(c->inv, (hipfftDoubleComplex *)ehat, (hipfftDoubleReal *)rho));
+    HIPCHK(c, launch_grad(c->g, rho, E, E32, s));
     return APIC_OK;
 }
 
@@ -394,18 +395,16 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
         return APIC_EHIP;
     }
     if (d.dim == 2) {
-        int n2[2] = {g.ny, g.nx};
         if (hipfftPlan2d(&c->fwd, g.ny, g.nx, HIPFFT_D2Z) != HIPFFT_SUCCESS ||
-            hipfftPlanMany(&c->inv, 2, n2, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_Z2D, 2) != HIPFFT_SUCCESS) {
+            hipfftPlan2d(&c->inv, g.ny, g.nx, HIPFFT_Z2D) != HIPFFT_SUCCESS) {
             (void)hipFree(c->dev_block);
             delete c;
             return APIC_EHIP;
         }
         c->have_fft = true;
     } else if (d.dim == 3) {
-        int n3[3] = {g.nz, g.ny, g.nx};
         if (hipfftPlan3d(&c->fwd, g.nz, g.ny, g.nx, HIPFFT_D2Z) != HIPFFT_SUCCESS ||
-            hipfftPlanMany(&c->inv, 3, n3, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_Z2D, 3) != HIPFFT_SUCCESS) {
+            hipfftPlan3d(&c->inv, g.nz, g.ny, g.nx, HIPFFT_Z2D) != HIPFFT_SUCCESS) {
             (void)hipFree(c->dev_block);
             delete c;
             return APIC_EHIP;

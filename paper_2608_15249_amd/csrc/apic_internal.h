@@ -71,7 +71,6 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_set_step(int *step, int v, hipStream_t s);
 hipError_t launch_copy_bytes(void *dst, const void *src, int64_t bytes, hipStream_t s);
-hipError_t launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 
 // general sort (arbitrary input order): stable LSD radix sort of
 // (bucket key, index), the bucket table of the sorted keys, then a gather of
@@ -120,8 +119,10 @@ hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Pa
 hipError_t launch_rho(const Geo &g, bool mixed, void *acc, double *rho, double scale, double add,
                       int clear, hipStream_t s);
 int spectral_blocks(const Geo &g);
-hipError_t launch_spectral(const Geo &g, const void *rho_hat, void *ex_hat, void *ey_hat, void *ez_hat,
-                           const CtxDev &c, hipStream_t s);
+// phi_hat = rho_hat / K^2 (scaled for the inverse transform) and the field
+// energy partials; then E = -(centred difference of phi) in real space
+hipError_t launch_spectral(const Geo &g, const void *rho_hat, void *phi_hat, const CtxDev &c, hipStream_t s);
+hipError_t launch_grad(const Geo &g, const double *phi, double *E, float *E32, hipStream_t s);
 hipError_t launch_finalize(int npush, int nspec, double mass, double dV, double G, double rho_ion,
                            double *diag, double *we, double *charge, const CtxDev &c, hipStream_t s);
 hipError_t launch_field1d(const Geo &g, bool mixed, void *acc, double scale, double add, double ion,

@@ -290,11 +290,6 @@ __global__ void k_copy_bytes(uint4 *dst, const uint4 *src, int64_t n16, char *dt
     if (blockIdx.x == 0 && (int)threadIdx.x < tail) dtail[threadIdx.x] = stail[threadIdx.x];
 }
 
-__global__ void k_to_f32(const double *src, float *dst, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = (float)src[i];
-}
-
 // ---- block-wide exclusive scan helper (1024 threads) ------------------------
 // Scans vals[0..nb) into out[0..nb] (out[nb] = total) in chunks of
 // 1024*kPer elements; returns the total in every thread.
@@ -1257,8 +1252,12 @@ __global__ void __launch_bounds__(kBlock) k_rho(int64_t G, typename AccOf<MIX>::
 // Per-block partial of sum_k w_k |E_hat_k|^2 (Parseval over the half
 // spectrum, w = 1 on the kx = 0 and Nyquist columns, else 2) goes to
 // c.part_spec; rho_hat(0) (= sum_j rho_j) to c.rho0.
-__global__ void __launch_bounds__(kBlock) k_spectral(Geo g, const double2 *rh, double2 *exh, double2 *eyh,
-                                                     double2 *ezh, CtxDev c) {
+// phi_hat = rho_hat / K^2 (K^2 = sum of the per-axis modified wavenumbers,
+// phi_hat(0) = 0), scaled by 1/G for the unnormalised inverse transform, and
+// the per-block partials of sum |E_hat|^2 = sum kappa^2 |phi_hat|^2 over the
+// full spectrum (Parseval; the half spectrum counts every kx other than 0
+// and nx/2 twice).
+__global__ void __launch_bounds__(kBlock) k_spectral(Geo g, const double2 *rh, double2 *ph, CtxDev c) {
     __shared__ double sRed[kWaves];
     const int hx = g.nx / 2 + 1;
     const int64_t tot = (int64_t)hx * g.ny * g.nz;
@@ -1273,16 +1272,46 @@ __global__ void __launch_bounds__(kBlock) k_spectral(Geo g, const double2 *rh, d
         if (i == 0) *c.rho0 = rr.x;
         double inv = (i == 0) ? 0.0 : 1.0 / K2;
         double pr = rr.x * inv, pi = rr.y * inv;
-        // -i * kappa * (pr + i pi) = kappa * pi - i kappa * pr
         double kax = c.kapx[kx], kay = c.kapy[ky], kaz = c.kapz[kz];
         double wgt = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
         part += wgt * (kax * kax + kay * kay + kaz * kaz) * (pr * pr + pi * pi);
-        exh[i] = make_double2(kax * pi * norm, -kax * pr * norm);
-        eyh[i] = make_double2(kay * pi * norm, -kay * pr * norm);
-        if (ezh) ezh[i] = make_double2(kaz * pi * norm, -kaz * pr * norm);
+        ph[i] = make_double2(pr * norm, pi * norm);
     }
     double bs = block_sum(part, sRed);
     if (threadIdx.x == 0) c.part_spec[blockIdx.x] = bs;
+}
+
+// E = -(centred difference of phi), periodic: E_d[j] = (phi[j - e_d] -
+// phi[j + e_d]) / (2 d_d), the real-space form of E_hat = -i sin(k d)/d
+// phi_hat. Writes E [dim][G] and, when E32 is not NULL, its binary32
+// rounding. h = 1 / (2 d) per axis.
+__global__ void __launch_bounds__(kBlock) k_grad(Geo g, const double *phi, double *E, float *E32, double hx,
+                                                 double hy, double hz) {
+    const int64_t G = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t sxy = (int64_t)g.nx * g.ny;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G; i += (int64_t)gridDim.x * blockDim.x) {
+        const int ix = (int)(i % g.nx);
+        const int64_t r = i / g.nx;
+        const int iy = (int)(r % g.ny), iz = (int)(r / g.ny);
+        const int64_t xm = (ix == 0) ? i + g.nx - 1 : i - 1, xp = (ix == g.nx - 1) ? i - (g.nx - 1) : i + 1;
+        const double ex = (phi[xm] - phi[xp]) * hx;
+        E[i] = ex;
+        if (E32) E32[i] = (float)ex;
+        if (g.dim >= 2) {
+            const int64_t ym = (iy == 0) ? i + sxy - g.nx : i - g.nx;
+            const int64_t yp = (iy == g.ny - 1) ? i - (sxy - g.nx) : i + g.nx;
+            const double ey = (phi[ym] - phi[yp]) * hy;
+            E[G + i] = ey;
+            if (E32) E32[G + i] = (float)ey;
+        }
+        if (g.dim == 3) {
+            const int64_t zm = (iz == 0) ? i + G - sxy : i - sxy;
+            const int64_t zp = (iz == g.nz - 1) ? i - (G - sxy) : i + sxy;
+            const double ez = (phi[zm] - phi[zp]) * hz;
+            E[2 * G + i] = ez;
+            if (E32) E32[2 * G + i] = (float)ez;
+        }
+    }
 }
 
 // Sums the per-block partials in a fixed order (deterministic) and writes the
@@ -1398,12 +1427,6 @@ hipError_t launch_copy_bytes(void *dst, const void *src, int64_t bytes, hipStrea
     int tail = (int)(bytes - n16 * 16);
     hipLaunchKernelGGL(k_copy_bytes, dim3(blocks_for(n16 > 0 ? n16 : 1)), dim3(kBlock), 0, s, (uint4 *)dst,
                        (const uint4 *)src, n16, (char *)dst + n16 * 16, (const char *)src + n16 * 16, tail);
-    return hipGetLastError();
-}
-
-hipError_t launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(n)), dim3(kBlock), 0, s, src, dst, n);
     return hipGetLastError();
 }
 
@@ -1560,10 +1583,16 @@ hipError_t launch_rho(const Geo &g, bool mixed, void *acc, double *rho, double s
 
 int spectral_blocks(const Geo &g) { return blocks_for((int64_t)(g.nx / 2 + 1) * g.ny * g.nz, kMaxSpecBlocks); }
 
-hipError_t launch_spectral(const Geo &g, const void *rho_hat, void *ex_hat, void *ey_hat, void *ez_hat,
-                           const CtxDev &c, hipStream_t s) {
+hipError_t launch_spectral(const Geo &g, const void *rho_hat, void *phi_hat, const CtxDev &c, hipStream_t s) {
     hipLaunchKernelGGL(k_spectral, dim3(spectral_blocks(g)), dim3(kBlock), 0, s, g, (const double2 *)rho_hat,
-                       (double2 *)ex_hat, (double2 *)ey_hat, (double2 *)ez_hat, c);
+                       (double2 *)phi_hat, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(const Geo &g, const double *phi, double *E, float *E32, hipStream_t s) {
+    const int64_t G = (int64_t)g.nx * g.ny * g.nz;
+    const double hx = 0.5 * g.inv_dx, hy = 0.5 * g.inv_dy, hz = 0.5 * g.inv_dz;
+    hipLaunchKernelGGL(k_grad, dim3(blocks_for(G, 8192)), dim3(kBlock), 0, s, g, phi, E, E32, hx, hy, hz);
     return hipGetLastError();
 }
 
