@@ -82,6 +82,8 @@ def _load():
         "or_deposit_q_3d": [_i64, _I32, _I32, _I32, _F, _F, _F, _int, _int, _int, _int, _I64],
         "or_gather_3d": [_i64, _D, _D, _D, _int, _int, _int, _dbl, _dbl, _dbl, _D, _D, _D, _D, _D, _D],
         "or_move_3d": [_i64, _D, _D, _D, _D, _D, _D, _dbl, _dbl, _dbl, _dbl],
+        "or_hc": [_i64, _D, _D, _D, _D, _D, _D, _dbl, _dbl, _dbl, _dbl],
+        "or_move_u": [_i64, _int, _D, _D, _D, _D, _D, _D, _dbl, _dbl, _dbl, _dbl, _dbl],
         "or_deposit_q_1d": [_i64, _I32, _F, _int, _int, _I64],
         "or_deposit_q_2d": [_i64, _I32, _I32, _F, _F, _int, _int, _int, _I64],
         "or_gather_1d": [_i64, _D, _int, _dbl, _D, _D],
@@ -140,6 +142,10 @@ class Setup:
     n0: float = 1.0
     nz: int = 1
     Lz: float = 1.0
+    # velocity advance: "boris", or "hc" (Higuera-Cary; the state's velocities
+    # are then u = gamma v, and c is the speed of light; needs vdim = 3)
+    pusher: str = "boris"
+    c: float = float("inf")
 
     @property
     def dx(self):
@@ -388,11 +394,16 @@ def gather(s: Setup, st: State, E) -> Tuple[np.ndarray, ...]:
 
 
 def boris(s: Setup, st: State, Ep, dt: float) -> None:
-    """In-place Boris advance of the velocities by dt under Ep and bz."""
+    """In-place velocity advance by dt under Ep and bz: Boris, or Higuera-Cary
+    when s.pusher == "hc"."""
     L = _load()
     n = st.x.shape[0]
     Epy = Ep[1] if len(Ep) > 1 else None
     Epz = Ep[2] if len(Ep) > 2 else None
+    if s.pusher == "hc":
+        L.or_hc(n, _p(st.vx, _D), _p(st.vy, _D), _p(st.vz, _D), _p(_c64(Ep[0]), _D), _p(_c64(Epy), _D),
+                _p(None if Epz is None else _c64(Epz), _D), s.qm, dt, s.bz, s.c)
+        return
     L.or_boris(n, s.vdim, _p(st.vx, _D), _p(st.vy, _D), _p(st.vz, _D),
                _p(_c64(Ep[0]), _D), _p(None if Epy is None else _c64(Epy), _D),
                _p(None if Epz is None else _c64(Epz), _D), s.qm, dt, s.bz)
@@ -401,6 +412,10 @@ def boris(s: Setup, st: State, Ep, dt: float) -> None:
 def move(s: Setup, st: State) -> None:
     L = _load()
     n = st.x.shape[0]
+    if s.pusher == "hc":
+        L.or_move_u(n, s.dim, _p(st.x, _D), _p(st.y, _D), _p(st.z, _D), _p(st.vx, _D), _p(st.vy, _D),
+                    _p(st.vz, _D), s.dt, s.c, s.Lx, s.Ly, s.Lz)
+        return
     if s.dim == 1:
         L.or_move_1d(n, _p(st.x, _D), _p(st.vx, _D), s.dt, s.Lx)
     elif s.dim == 2:
@@ -448,6 +463,16 @@ def counting_sort(keys: np.ndarray, n_buckets: int):
 
 def field_energy(s: Setup, E) -> float:
     return 0.5 * sum(float(np.sum(e * e)) for e in E) * s.dV
+
+
+def kinetic_sum(s: Setup, st: State) -> float:
+    """Sum over particles of twice the kinetic energy per unit mass: |v|^2,
+    or 2 (gamma - 1) c^2 = 2 |u|^2 / (gamma + 1) for the Higuera-Cary state."""
+    if s.pusher != "hc":
+        return kinetic_sum_v2(st)
+    u2 = st.vx * st.vx + st.vy * st.vy + st.vz * st.vz
+    g = np.sqrt(1.0 + u2 / (s.c * s.c))
+    return float(np.sum(2.0 * u2 / (g + 1.0)))
 
 
 def kinetic_sum_v2(st: State) -> float:
@@ -522,7 +547,7 @@ def initialise(s: Setup, st: State):
     Returns E^0 and the particle kinetic sum |v^0|^2 (for the t = 0 energy)."""
     rho = deposit(s, st)
     E = solve_field(s, rho)
-    v2_0 = kinetic_sum_v2(st)
+    v2_0 = kinetic_sum(s, st)
     boris(s, st, gather(s, st, E), -0.5 * s.dt)
     return E, v2_0
 
@@ -531,9 +556,9 @@ def step(s: Setup, st: State, E):
     """One leapfrog cycle: v^{n-1/2} -> v^{n+1/2} under E^n, x^n -> x^{n+1},
     deposit -> Poisson -> E^{n+1}. Returns (E^{n+1}, rho^{n+1}, KE^n) with KE^n
     the mean of the half-step kinetic energies around time level n."""
-    v2_old = kinetic_sum_v2(st)
+    v2_old = kinetic_sum(s, st)
     boris(s, st, gather(s, st, E), s.dt)
-    v2_new = kinetic_sum_v2(st)
+    v2_new = kinetic_sum(s, st)
     move(s, st)
     rho = deposit(s, st)
     E_new = solve_field(s, rho)

@@ -277,6 +277,41 @@ void or_boris(int64_t n, int vdim, double *vx, double *vy, double *vz,
     }
 }
 
+/* ---- Higuera-Cary velocity advance (A_Pusher, Higuera & Cary 2017) -------
+ * The paper lists it beside Boris among A_Pusher's algorithms. The state is
+ * u = gamma v (velocity units), gamma = sqrt(1 + |u|^2/c^2); B = bz z^.
+ *   a = (q/m) dt / 2,  tau = a bz
+ *   u-  = u + a E,  gamma-^2 = 1 + |u-|^2/c^2,  sigma = gamma-^2 - tau^2
+ *   gamma+ = sqrt((sigma + sqrt(sigma^2 + 4 (tau^2 + (u-.tau)^2/c^2))) / 2)
+ *   t = tau / gamma+ (along z),  s = 1 / (1 + t^2)
+ *   u+  = s (u- + (u-.t) t + u- x t)
+ *   u   = u+ + a E + u+ x t
+ * As c -> infinity gamma+ -> 1 and the map is the Boris rotation. Epz may be
+ * NULL (Ez = 0). vdim must be 3. */
+void or_hc(int64_t n, double *ux, double *uy, double *uz, const double *Epx, const double *Epy,
+           const double *Epz, double qm, double dt, double bz, double c)
+{
+    const double a = qm * dt * 0.5;
+    const double tau = a * bz;
+    const double ic2 = 1.0 / (c * c);
+    for (int64_t p = 0; p < n; ++p) {
+        double ex = Epx[p], ey = Epy[p], ez = Epz ? Epz[p] : 0.0;
+        double mx = ux[p] + a * ex, my = uy[p] + a * ey, mz = uz[p] + a * ez;
+        double g2 = 1.0 + (mx * mx + my * my + mz * mz) * ic2;
+        double sig = g2 - tau * tau;
+        double us = mz * tau;
+        double gp = sqrt(0.5 * (sig + sqrt(sig * sig + 4.0 * (tau * tau + us * us * ic2))));
+        double t = tau / gp;
+        double s = 1.0 / (1.0 + t * t);
+        double px = s * (mx + my * t);
+        double py = s * (my - mx * t);
+        double pz = s * (mz + (mz * t) * t);
+        ux[p] = px + a * ex + py * t;
+        uy[p] = py + a * ey - px * t;
+        uz[p] = pz + a * ez;
+    }
+}
+
 /* ---- position update with periodic boundaries ---------------------------
  * The paper leaves this to the application code ("move_particles" in the
  * two-stream driver): x <- x + v dt, then wrap into [0, L). */
@@ -301,6 +336,20 @@ void or_move_3d(int64_t n, double *x, double *y, double *z, const double *vx, co
         x[p] = wrap(x[p] + vx[p] * dt, Lx);
         y[p] = wrap(y[p] + vy[p] * dt, Ly);
         z[p] = wrap(z[p] + vz[p] * dt, Lz);
+    }
+}
+
+/* Position update from u = gamma v: x <- x + (u / gamma) dt with
+ * gamma = sqrt(1 + |u|^2/c^2), then wrap (dim 2 or 3; z, uz used in 3D). */
+void or_move_u(int64_t n, int dim, double *x, double *y, double *z, const double *ux, const double *uy,
+               const double *uz, double dt, double c, double Lx, double Ly, double Lz)
+{
+    const double ic2 = 1.0 / (c * c);
+    for (int64_t p = 0; p < n; ++p) {
+        double g = sqrt(1.0 + (ux[p] * ux[p] + uy[p] * uy[p] + uz[p] * uz[p]) * ic2);
+        x[p] = wrap(x[p] + (ux[p] / g) * dt, Lx);
+        y[p] = wrap(y[p] + (uy[p] / g) * dt, Ly);
+        if (dim == 3) z[p] = wrap(z[p] + (uz[p] / g) * dt, Lz);
     }
 }
 

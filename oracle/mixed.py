@@ -16,6 +16,14 @@ multiply-add), in the order of the textbook formulas of the FP64 oracle:
   Boris  : a = (q/m) dt/2, t = a bz, s = 2t/(1+t^2) computed in FP64 and
            rounded to binary32; v- = v + aE; v' = v- + v- x t;
            v+ = v- + v' x s; v = v+ + aE (in 3D vz takes the two kicks of Ez)
+  Higuera-Cary (pusher "hc", state u = gamma v, ic2 = fl32(1/c^2)):
+           m = u + aE; g2 = 1 + ((mx mx + my my) + mz mz) ic2;
+           sig = g2 - tau tau; us = mz tau;
+           gp = sqrt(0.5 (sig + sqrt(sig sig + 4 (tau tau + (us us) ic2))));
+           t = tau / gp; s = 1 / (1 + t t);
+           p = s (mx + my t, my - mx t, mz + (mz t) t);
+           u = (px + aEx + py t, py + aEy - px t, pz + aEz); the move uses
+           v = u / sqrt(1 + ((ux ux + uy uy) + uz uz) ic2)
   move   : o' = o + v * fl32(dt/dx); k = floor(o'); o' = o' - k;
            if o' >= 1 then o' = o' - 1, k = k + 1; cell = (cell + k) mod n.
 The deposit of the result is oracle.deposit_quantised (exact integers).
@@ -74,8 +82,8 @@ def boris_coeffs(qm: float, dt: float, bz: float):
 
 
 def push(st: dict, E32, *, dim, vdim, nx, ny, dx, dy, qm, dt, bz, dt_scale=1.0, move=True,
-         nz=1, dz=1.0) -> dict:
-    """One binary32 gather + Boris (+ move) of a mixed state.
+         nz=1, dz=1.0, pusher="boris", c=float("inf")) -> dict:
+    """One binary32 gather + Boris or Higuera-Cary (+ move) of a mixed state.
 
     st: dict with ix, iy, iz (int32 or None), ox, oy, oz, vx, vy, vz (float32
     or None). E32: tuple of float32 node fields shaped like the grid. Returns
@@ -95,21 +103,40 @@ def push(st: dict, E32, *, dim, vdim, nx, ny, dx, dy, qm, dt, bz, dt_scale=1.0, 
     else:
         ex, ey = _gather(ix, iy, fx, fy, E32, nx, ny, dim)
     a, t, s = boris_coeffs(qm, dt * dt_scale, bz)
-    if ez is not None:
-        mz = vz + a * ez
-        vz = (mz + a * ez).astype(f32)
-    if vdim == 1:
-        m1 = vx + a * ex
-        vx = (m1 + a * ex).astype(f32)
+    ic2 = f32(1.0 / (c * c))
+    if pusher == "hc":
+        ezz = ez if ez is not None else np.zeros_like(ex)
+        mx = (vx + a * ex).astype(f32)
+        my = (vy + a * ey).astype(f32)
+        mz = (vz + a * ezz).astype(f32)
+        g2 = f32(1.0) + (mx * mx + my * my + mz * mz) * ic2
+        sig = g2 - t * t
+        us = mz * t
+        gp = np.sqrt(f32(0.5) * (sig + np.sqrt(sig * sig + f32(4.0) * (t * t + (us * us) * ic2))))
+        tt = (t / gp).astype(f32)
+        ss = (f32(1.0) / (f32(1.0) + tt * tt)).astype(f32)
+        px = ss * (mx + my * tt)
+        py = ss * (my - mx * tt)
+        pz = ss * (mz + (mz * tt) * tt)
+        vx = (px + a * ex + py * tt).astype(f32)
+        vy = (py + a * ey - px * tt).astype(f32)
+        vz = (pz + a * ezz).astype(f32)
     else:
-        mx = vx + a * ex
-        my = vy + a * ey
-        px = mx + my * t
-        py = my - mx * t
-        qx = mx + py * s
-        qy = my - px * s
-        vx = (qx + a * ex).astype(f32)
-        vy = (qy + a * ey).astype(f32)
+        if ez is not None:
+            mz = vz + a * ez
+            vz = (mz + a * ez).astype(f32)
+        if vdim == 1:
+            m1 = vx + a * ex
+            vx = (m1 + a * ex).astype(f32)
+        else:
+            mx = vx + a * ex
+            my = vy + a * ey
+            px = mx + my * t
+            py = my - mx * t
+            qx = mx + py * s
+            qy = my - px * s
+            vx = (qx + a * ex).astype(f32)
+            vy = (qy + a * ey).astype(f32)
     out = dict(st)
     out["vx"], out["vy"], out["vz"] = vx, vy, vz
     if move:
@@ -123,11 +150,15 @@ def push(st: dict, E32, *, dim, vdim, nx, ny, dx, dy, qm, dt, bz, dt_scale=1.0, 
             k[up] += 1
             return np.mod(c + k, n).astype(np.int32), o2.astype(f32)
 
-        out["ix"], out["ox"] = mv(ix, fx, vx, dx, nx)
+        wx, wy, wz = vx, vy, vz
+        if pusher == "hc":
+            g = np.sqrt(f32(1.0) + (vx * vx + vy * vy + vz * vz) * ic2).astype(f32)
+            wx, wy, wz = (vx / g).astype(f32), (vy / g).astype(f32), (vz / g).astype(f32)
+        out["ix"], out["ox"] = mv(ix, fx, wx, dx, nx)
         if dim >= 2:
-            out["iy"], out["oy"] = mv(iy, fy, vy, dy, ny)
+            out["iy"], out["oy"] = mv(iy, fy, wy, dy, ny)
         if dim == 3:
-            out["iz"], out["oz"] = mv(iz, fz, vz, dz, nz)
+            out["iz"], out["oz"] = mv(iz, fz, wz, dz, nz)
     return out
 
 
