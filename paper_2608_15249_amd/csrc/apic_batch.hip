@@ -218,17 +218,21 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchP bp, int32_t *cell, floa
             const double kt = block_sum(ke, sRed);
             const double pt = block_sum(px, sRed);
             if (threadIdx.x == 0) {
-                bp.part[2 * item] = kt;
-                bp.part[2 * item + 1] = pt;
+                __hip_atomic_store(&bp.part[2 * item], kt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&bp.part[2 * item + 1], pt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        // publish this chunk; the block that completes the replica solves its field
-        __threadfence();
+        // publish this chunk; the block that completes the replica solves its
+        // field. Everything another block reads from it (the deposit in acc,
+        // the partial sums) is written and read with device-scope atomics, so
+        // completing those writes before the counter is enough: each thread
+        // waits for its own memory operations, the barrier for everyone's (no
+        // L2 write-back or invalidate)
+        __builtin_amdgcn_s_waitcnt(kWaitVmem);
         __syncthreads();
         if (threadIdx.x == 0) sLast = (atomicAdd(&bp.rep_done[it.r], 1) == rp.nitems - 1);
         __syncthreads();
         if (!sLast) continue;
-        __threadfence();
         double qpart = 0.0;
         for (int i = threadIdx.x; i < rp.nx; i += blockDim.x) {
             // read-and-clear at the device coherence point (sA is free again:
@@ -268,12 +272,13 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchP bp, int32_t *cell, floa
     __syncthreads();
     if (threadIdx.x == 0) {
         if (sErr) atomicOr(bp.err, sErr);
-        __threadfence();
+        // every work-queue atomic of this block has completed before its exit
+        // is counted; the resets are read by the next launch
+        __builtin_amdgcn_s_waitcnt(kWaitVmem);
         if (atomicAdd(bp.done, 1) == (int)gridDim.x - 1) {
             *bp.head = 0;
             *bp.done = 0;
             if (MODE == MODE_STEP) *bp.step = *bp.step + 1;
-            __threadfence();
         }
     }
 }
