@@ -91,9 +91,9 @@ def with_copy(roof, copy_gbs):
     return roof
 
 
-def run_path(precision, w, state, steps, warmup, tile, torch):
+def run_path(precision, w, state, steps, warmup, tile, torch, pusher="boris", c_light=0.0):
     from paper_2608_15249_amd.sim import Simulation
-    sim = Simulation(w, precision, state=state, tile=tile)
+    sim = Simulation(w, precision, state=state, tile=tile, pusher=pusher, c_light=c_light)
     sim.initialise()
     sim.ctx.sync()
     if warmup:
@@ -115,7 +115,8 @@ def run_path(precision, w, state, steps, warmup, tile, torch):
     push_ms = ms[2] / max(nprof, 1)
     push_bytes = 2 * sb * n
     achieved = push_bytes / (push_ms * 1e-3) / 1e9
-    traffic = load_traffic(precision, "%s_%d" % (w.name, w.nx), list(sim.tile))
+    # counters were taken for the Boris kernels only
+    traffic = load_traffic(precision, "%s_%d" % (w.name, w.nx), list(sim.tile)) if pusher == "boris" else None
     d = diag.cpu().numpy().reshape(steps, 4)
     out = {
         "value": n * steps / elapsed,
@@ -132,7 +133,7 @@ def run_path(precision, w, state, steps, warmup, tile, torch):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None if traffic is None else traffic / (push_ms * 1e-3) / 1e9,
-                     "kernel": "k_step_push (gather+Boris+move+deposit+scatter)",
+                     "kernel": "k_step_push (gather+%s+move+deposit+scatter)" % ("Higuera-Cary" if pusher == "hc" else "Boris"),
                      "bytes_per_launch": push_bytes},
         "final_WE": float(d[-1, 1]),
         "charge": float(d[-1, 0]),
@@ -184,14 +185,15 @@ def run_batch(reps, steps, warmup, chunk, torch):
     return out
 
 
-def cpu_baseline(w, state, nsteps):
+def cpu_baseline(w, state, nsteps, pusher="boris", c_light=float("inf")):
     """Serial FP64 oracle on the same plasma (host, one core)."""
     import oracle as O
     if w.dim == 3:
         x, y, z, vx, vy, vz = state
     else:
         (x, y, vx, vy, vz), z = state, None
-    s = O.Setup(w.dim, w.vdim, w.nx, w.Lx, len(x), w.dt, ny=w.ny, Ly=w.Ly, bz=w.bz, nz=w.nz, Lz=w.Lz)
+    s = O.Setup(w.dim, w.vdim, w.nx, w.Lx, len(x), w.dt, ny=w.ny, Ly=w.Ly, bz=w.bz, nz=w.nz, Lz=w.Lz, pusher=pusher,
+                c=c_light)
     st = O.State.from_arrays(x, vx, y, vy, vz, z)
     E, _ = O.initialise(s, st)
     t0 = time.perf_counter()
@@ -262,6 +264,9 @@ def main():
     ap.add_argument("--workload", default="thermal_2d", choices=sorted(WORKLOADS))
     ap.add_argument("--tile", default="auto", help="sort-bucket tile TXxTY (TXxTYxTZ in 3D), or auto (autotuner; the default tile in 3D)")
     ap.add_argument("--chunk", default="auto", help="batch work-item size, or auto (autotuner)")
+    ap.add_argument("--pusher", default="boris", choices=("boris", "hc"),
+                    help="velocity advance: Boris, or Higuera-Cary (relativistic, u = gamma v; 3V workloads)")
+    ap.add_argument("--c-light", type=float, default=8.0, help="speed of light for --pusher hc, in v_th units")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (N=%d requested)" % args.gpus,
@@ -294,11 +299,15 @@ def main():
     w = getattr(W, args.workload)()
     state = W.sample3(w) if w.dim == 3 else W.sample(w)
     tile = parse_tile(args.tile)
+    if args.pusher == "hc" and w.vdim != 3:
+        print("--pusher hc needs a 3V workload (magnetized_2d3v or thermal_3d)", file=sys.stderr)
+        sys.exit(2)
+    c_light = args.c_light if args.pusher == "hc" else 0.0
     res = {}
     for path in args.paths.split(","):
         print("bench: %s, %s path, %d warmup + %d timed steps" % (args.workload, path, args.warmup, args.steps),
               file=sys.stderr, flush=True)
-        res[path] = run_path(path, w, state, args.steps, args.warmup, tile, torch)
+        res[path] = run_path(path, w, state, args.steps, args.warmup, tile, torch, args.pusher, c_light)
     copy_gbs = measure_copy_gbs(torch)
     head = res.get("mixed") or res[list(res)[0]]
     line = dict(common)
@@ -307,7 +316,8 @@ def main():
         "ms_per_step": head["ms_per_step"],
         "dtype": "f32+i64" if "mixed" in res else "f64",
         "config": {"workload": WORKLOADS[args.workload], "grid": _grid(w), "particles": w.n_particles,
-                   "tile": head["tile"], "precision": "mixed" if "mixed" in res else "fp64"},
+                   "tile": head["tile"], "precision": "mixed" if "mixed" in res else "fp64",
+                   "pusher": "higuera-cary" if args.pusher == "hc" else "boris"},
         "hbm_gbs_step": head["hbm_gbs_step"],
         "roofline": with_copy(head["roofline"], copy_gbs),
         "phase_ms_per_step": head["phase_ms_per_step"],
@@ -323,7 +333,8 @@ def main():
         line["mixed_over_fp64"] = head["value"] / f["value"]
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (%d oracle steps)" % args.cpu_steps, file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(w, state, args.cpu_steps)
+        line["cpu_baseline"] = cpu_baseline(w, state, args.cpu_steps, args.pusher,
+                                             c_light if args.pusher == "hc" else float("inf"))
     print(json.dumps(line), flush=True)
 
 

@@ -56,6 +56,15 @@ typedef enum {
     APIC_EUNSUPPORTED = -6   /* valid but not implemented combination          */
 } apic_status;
 
+/* Velocity advance (the paper's A_Pusher lists both). */
+typedef enum {
+    APIC_BORIS = 0,          /* Boris (1970); the state's velocities are v     */
+    APIC_HIGUERA_CARY = 1    /* Higuera & Cary (2017), relativistic; the state's
+                                velocities are u = gamma v, gamma =
+                                sqrt(1 + |u|^2/c^2), and the move uses u/gamma.
+                                Needs vdim = 3                                 */
+} apic_pusher;
+
 typedef enum {
     APIC_FP64 = 0,  /* positions x,y in [0,L) and velocities as double          */
     APIC_MIXED = 1  /* cell index + binary32 in-cell offset, binary32 velocity,
@@ -89,6 +98,8 @@ typedef struct {
                              too); 0 or 1 below 3D                              */
     double lz;            /* 3D: box length along z                             */
     int tile_z;           /* 3D: bucket tile size along z (0 = default)         */
+    int pusher;           /* apic_pusher (0 = Boris)                            */
+    double c_light;       /* speed of light for APIC_HIGUERA_CARY (> 0)         */
 } apic_grid_desc;
 
 /* Particle arrays (structure of arrays), all [dev], caller-owned, length n.
@@ -241,8 +252,9 @@ apic_status apic_import_state(apic_ctx *ctx, const double *x, const double *y, c
  * of lam_rho), sort (each step's permutation inverted). The derivative of the
  * CIC hat is its slope inside the particle's cell.
  *
- * The adjoint entry points (and apic_import_state) cover 1D and 2D plasmas;
- * a 3D context returns APIC_EUNSUPPORTED.
+ * The adjoint entry points (and apic_import_state) cover 1D and 2D plasmas
+ * advanced with Boris; a 3D or Higuera-Cary context returns
+ * APIC_EUNSUPPORTED.
  *
  * Step checkpointing: apic_adjoint_forward stores the state every `stride`
  * steps in the caller's checkpoint buffer; apic_step_adjoint recomputes one

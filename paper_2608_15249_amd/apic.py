@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libapic.so")
 
 APIC_FP64 = 0
 APIC_MIXED = 1
+APIC_BORIS = 0
+APIC_HIGUERA_CARY = 1
 
 _STATUS = {0: "APIC_OK", -1: "APIC_EINVAL", -2: "APIC_EHIP", -3: "APIC_ENOMEM", -4: "APIC_EOVERFLOW",
            -5: "APIC_EDOMAIN", -6: "APIC_EUNSUPPORTED"}
@@ -34,7 +36,8 @@ class GridDesc(ctypes.Structure):
                 ("qm", ctypes.c_double), ("q_macro", ctypes.c_double), ("rho_ion", ctypes.c_double),
                 ("bz", ctypes.c_double), ("prec", ctypes.c_int), ("frac_bits", ctypes.c_int),
                 ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int),
-                ("nz", ctypes.c_int), ("lz", ctypes.c_double), ("tile_z", ctypes.c_int)]
+                ("nz", ctypes.c_int), ("lz", ctypes.c_double), ("tile_z", ctypes.c_int),
+                ("pusher", ctypes.c_int), ("c_light", ctypes.c_double)]
 
 
 class ParticlesC(ctypes.Structure):
@@ -129,7 +132,8 @@ class Context:
     """One plasma on the GPU: owns the libapic context and its workspace."""
 
     def __init__(self, *, dim, vdim, nx, ny, lx, ly, dt, n, qm=-1.0, q_macro=None, rho_ion=1.0, bz=0.0,
-                 precision="mixed", frac_bits=0, tile=(0, 0), device="cuda", nz=1, lz=1.0):
+                 precision="mixed", frac_bits=0, tile=(0, 0), device="cuda", nz=1, lz=1.0, pusher="boris",
+                 c_light=0.0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libapic needs a HIP GPU; none is visible")
@@ -143,7 +147,9 @@ class Context:
         tz = tile[2] if len(tile) > 2 else 0
         self.desc = GridDesc(dim, vdim, nx, ny if dim >= 2 else 1, lx, ly if dim >= 2 else 1.0, dt, qm, q_macro,
                              rho_ion, bz, APIC_MIXED if self.mixed else APIC_FP64, frac_bits, tile[0], tile[1],
-                             nz if dim == 3 else 1, lz if dim == 3 else 1.0, tz)
+                             nz if dim == 3 else 1, lz if dim == 3 else 1.0, tz,
+                             APIC_HIGUERA_CARY if pusher == "hc" else APIC_BORIS, float(c_light))
+        self.pusher, self.c_light = pusher, float(c_light)
         self.n = int(n)
         h = ctypes.c_void_p()
         st = self.L.apic_create(ctypes.byref(self.desc), self.n, ctypes.byref(h))

@@ -181,6 +181,8 @@ PushC push_coeffs(const apic_ctx *c, double dt_scale, int move) {
     pc.move = move;
     pc.rot = c->d.bz != 0.0;
     pc.deep = 0.25f;
+    pc.ic2 = c->g.hc ? 1.0 / (c->d.c_light * c->d.c_light) : 0.0;
+    pc.ic2f = (float)pc.ic2;
     return pc;
 }
 
@@ -223,12 +225,11 @@ apic_status field_from_acc(apic_ctx *c, void *acc, bool acc_is_rho, double *E, f
     FFTCHK(c, hipfftSetStream(c->fwd, s));
     FFTCHK(c, hipfftExecD2Z(c->fwd, (hipfftDoubleReal *)rho, (hipfftDoubleComplex *)rhat));
     HIPCHK(c, launch_spectral(c->g, rhat, ehat, c->dev, s));
-    HIPCHK(c, launch_finalize(diag ? npush : 0, spectral_blocks(c->g), c->mass, c->dV, G, c->d.rho_ion, diag, we,
-                              charge, c->dev, s));
+    const FinArgs fin{diag ? npush : 0, spectral_blocks(c->g), c->mass, c->dV, G, c->d.rho_ion, diag, we, charge};
     // phi into the rho buffer (rho is no longer needed), then E from phi
     FFTCHK(c, hipfftSetStream(c->inv, s));
     FFTCHK(c, hipfftExecZ2D(c->inv, (hipfftDoubleComplex *)ehat, (hipfftDoubleReal *)rho));
-    HIPCHK(c, launch_grad(c->g, rho, E, E32, s));
+    HIPCHK(c, launch_grad(c->g, rho, E, E32, fin, c->dev, s));
     return APIC_OK;
 }
 
@@ -274,6 +275,9 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     if (n_particles < 0 || n_particles > (int64_t)INT32_MAX - 1) return APIC_EINVAL;
     if (d.prec != APIC_FP64 && d.prec != APIC_MIXED) return APIC_EINVAL;
     if ((d.tile_x && !is_pow2(d.tile_x)) || (d.tile_y && !is_pow2(d.tile_y)) || (d.tile_z && !is_pow2(d.tile_z)))
+        return APIC_EINVAL;
+    if (d.pusher != APIC_BORIS && d.pusher != APIC_HIGUERA_CARY) return APIC_EINVAL;
+    if (d.pusher == APIC_HIGUERA_CARY && (d.vdim != 3 || !(d.c_light > 0) || !std::isfinite(d.c_light)))
         return APIC_EINVAL;
 
     apic_ctx *c = new (std::nothrow) apic_ctx();
@@ -322,6 +326,7 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     g.nbuckets = g.nbx * g.nby * g.nbz;
     g.halo = 1;
     g.np = (int)n_particles;
+    g.hc = d.pusher == APIC_HIGUERA_CARY;
     g.S = d.frac_bits ? d.frac_bits : (d.dim == 1 ? 32 : d.dim == 2 ? 20 : 15);
     if (c->mixed && (g.S < 1 || g.S > 32 || (d.dim == 2 && g.S > 23) || (d.dim == 3 && g.S > 16))) {
         delete c;

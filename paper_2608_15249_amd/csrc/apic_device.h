@@ -215,6 +215,36 @@ __device__ __forceinline__ void boris_z(R &vz, R ez, R a) {
     vz = mz + a * ez;
 }
 
+// Higuera-Cary advance (Higuera & Cary 2017) of u = gamma v under E and a
+// uniform B along z, tau = a bz, ic2 = 1/c^2: the half kick u- = u + a E;
+// gamma+ solves the method's implicit relation (the Lorentz factor of the
+// mean of u- and u+); t = tau / gamma+, s = 1 / (1 + t^2);
+// u+ = s (u- + (u-.t) t + u- x t); u = u+ + a E + u+ x t. The operations and
+// their order are the ones the binary32 reading of the oracle uses.
+template <typename R>
+__device__ __forceinline__ void higuera_cary(R &ux, R &uy, R &uz, R ex, R ey, R ez, R a, R tau, R ic2) {
+    const R mx = ux + a * ex, my = uy + a * ey, mz = uz + a * ez;
+    const R g2 = R(1) + ((mx * mx + my * my) + mz * mz) * ic2;
+    const R sig = g2 - tau * tau;
+    const R us = mz * tau;
+    const R gp = sqrt(R(0.5) * (sig + sqrt(sig * sig + R(4) * (tau * tau + (us * us) * ic2))));
+    const R t = tau / gp;
+    const R s = R(1) / (R(1) + t * t);
+    const R px = s * (mx + my * t);
+    const R py = s * (my - mx * t);
+    const R pz = s * (mz + (mz * t) * t);
+    ux = (px + a * ex) + py * t;
+    uy = (py + a * ey) - px * t;
+    uz = pz + a * ez;
+}
+
+// 1 / gamma of u = gamma v: 1 / sqrt(1 + |u|^2 / c^2), as a division of u by
+// gamma in the move.
+template <typename R>
+__device__ __forceinline__ R lorentz(R ux, R uy, R uz, R ic2) {
+    return sqrt(R(1) + ((ux * ux + uy * uy) + uz * uz) * ic2);
+}
+
 // Position update with periodic wrap. Returns the unwrapped cell shift
 // (new cell - old cell) per axis in sx, sy, sz, and false for a non-finite or
 // runaway coordinate.
@@ -257,28 +287,65 @@ __device__ __forceinline__ bool move_axis_f64(double &xc, int &ic, double &f, do
     return ok;
 }
 
+// Move by the velocity (vx, vy, vz) (the particle's v, or u / gamma).
 template <bool MIX, int DIM>
-__device__ __forceinline__ bool move_pt(Pt<MIX> &p, const Geo &g, const PushC &pc, int &sx, int &sy, int &sz) {
+__device__ __forceinline__ bool move_pt_v(Pt<MIX> &p, const Geo &g, const PushC &pc, typename Pt<MIX>::R vx,
+                                          typename Pt<MIX>::R vy, typename Pt<MIX>::R vz, int &sx, int &sy,
+                                          int &sz) {
     sy = 0;
     sz = 0;
     if constexpr (MIX) {
-        bool ok = move_axis_mixed(p.ix, p.fx, p.vx, pc.dtdx, g.nx, sx);
-        if constexpr (DIM >= 2) ok = move_axis_mixed(p.iy, p.fy, p.vy, pc.dtdy, g.ny, sy) && ok;
-        if constexpr (DIM == 3) ok = move_axis_mixed(p.iz, p.fz, p.vz, pc.dtdz, g.nz, sz) && ok;
+        bool ok = move_axis_mixed(p.ix, p.fx, vx, pc.dtdx, g.nx, sx);
+        if constexpr (DIM >= 2) ok = move_axis_mixed(p.iy, p.fy, vy, pc.dtdy, g.ny, sy) && ok;
+        if constexpr (DIM == 3) ok = move_axis_mixed(p.iz, p.fz, vz, pc.dtdz, g.nz, sz) && ok;
         return ok;
     } else {
         double f;
-        bool ok = move_axis_f64(p.x, p.ix, f, p.vx, pc.dt, g.lx, g.inv_dx, g.nx, sx);
+        bool ok = move_axis_f64(p.x, p.ix, f, vx, pc.dt, g.lx, g.inv_dx, g.nx, sx);
         p.fx = f;
         if constexpr (DIM >= 2) {
-            ok = move_axis_f64(p.y, p.iy, f, p.vy, pc.dt, g.ly, g.inv_dy, g.ny, sy) && ok;
+            ok = move_axis_f64(p.y, p.iy, f, vy, pc.dt, g.ly, g.inv_dy, g.ny, sy) && ok;
             p.fy = f;
         }
         if constexpr (DIM == 3) {
-            ok = move_axis_f64(p.z, p.iz, f, p.vz, pc.dt, g.lz, g.inv_dz, g.nz, sz) && ok;
+            ok = move_axis_f64(p.z, p.iz, f, vz, pc.dt, g.lz, g.inv_dz, g.nz, sz) && ok;
             p.fz = f;
         }
         return ok;
+    }
+}
+
+template <bool MIX, int DIM>
+__device__ __forceinline__ bool move_pt(Pt<MIX> &p, const Geo &g, const PushC &pc, int &sx, int &sy, int &sz) {
+    return move_pt_v<MIX, DIM>(p, g, pc, p.vx, p.vy, p.vz, sx, sy, sz);
+}
+
+// Velocity advance (Boris, or Higuera-Cary when HC) and move of a particle
+// whose E has been gathered (ez = 0 below 3D).
+template <bool MIX, int DIM, int VDIM, bool HC>
+__device__ __forceinline__ bool push_move(Pt<MIX> &p, const Geo &g, const PushC &pc, typename Pt<MIX>::R ex,
+                                          typename Pt<MIX>::R ey, typename Pt<MIX>::R ez, bool move, int &sx,
+                                          int &sy, int &sz) {
+    using R = typename Pt<MIX>::R;
+    const R a = MIX ? (R)pc.af : (R)pc.a, t = MIX ? (R)pc.tf : (R)pc.t, s = MIX ? (R)pc.sf : (R)pc.s;
+    if constexpr (HC) {
+        static_assert(VDIM == 3, "the Higuera-Cary state has three components");
+        const R ic2 = MIX ? (R)pc.ic2f : (R)pc.ic2;
+        higuera_cary<R>(p.vx, p.vy, p.vz, ex, ey, ez, a, t, ic2);
+        if (!move) {
+            sx = sy = sz = 0;
+            return true;
+        }
+        const R gm = lorentz<R>(p.vx, p.vy, p.vz, ic2);
+        return move_pt_v<MIX, DIM>(p, g, pc, p.vx / gm, p.vy / gm, p.vz / gm, sx, sy, sz);
+    } else {
+        if constexpr (DIM == 3) boris_z<R>(p.vz, ez, a);
+        boris<R, VDIM>(p.vx, p.vy, ex, ey, a, t, s);
+        if (!move) {
+            sx = sy = sz = 0;
+            return true;
+        }
+        return move_pt<MIX, DIM>(p, g, pc, sx, sy, sz);
     }
 }
 
@@ -617,6 +684,7 @@ __device__ double field1d_block(double *sr, int nx, double dx, double *E, float 
 // launch: MIX, DIM, VDIM (and the unroll factor U) are constexpr inside.
 #define APIC_DISPATCH_2D(g, mixed, ...)                                                 \
     do {                                                                                \
+        [[maybe_unused]] constexpr bool HC = false;                                     \
         if (mixed) {                                                                    \
             constexpr bool MIX = true;                                                  \
             [[maybe_unused]] constexpr int U = APIC_STEP_U;                             \
@@ -632,14 +700,25 @@ __device__ double field1d_block(double *sr, int nx, double dx, double *E, float 
         }                                                                               \
     } while (0)
 
-// Same, with the 3D3V case.
+// Both precisions, one velocity advance (HCV), a given (DIM, VDIM).
+#define APIC_DISPATCH_MIX(mixed, HCV, D, V, ...)                                       \
+    do {                                                                                \
+        [[maybe_unused]] constexpr bool HC = HCV;                                       \
+        [[maybe_unused]] constexpr int U = APIC_STEP_U;                                 \
+        [[maybe_unused]] constexpr int DIM = D, VDIM = V;                               \
+        if (mixed) { constexpr bool MIX = true; __VA_ARGS__; }                          \
+        else { constexpr bool MIX = false; __VA_ARGS__; }                               \
+    } while (0)
+
+// Every case, with the 3D3V one and the velocity advance (Higuera-Cary, g.hc,
+// only with three velocity components).
 #define APIC_DISPATCH(g, mixed, ...)                                                    \
     do {                                                                                \
-        if ((g).dim == 3) {                                                             \
-            [[maybe_unused]] constexpr int U = APIC_STEP_U;                             \
-            [[maybe_unused]] constexpr int DIM = 3, VDIM = 3;                           \
-            if (mixed) { constexpr bool MIX = true; __VA_ARGS__; }                      \
-            else { constexpr bool MIX = false; __VA_ARGS__; }                           \
+        if ((g).vdim == 3 && (g).hc) {                                                  \
+            if ((g).dim == 3) APIC_DISPATCH_MIX(mixed, true, 3, 3, __VA_ARGS__);        \
+            else APIC_DISPATCH_MIX(mixed, true, 2, 3, __VA_ARGS__);                     \
+        } else if ((g).dim == 3) {                                                      \
+            APIC_DISPATCH_MIX(mixed, false, 3, 3, __VA_ARGS__);                         \
         } else {                                                                        \
             APIC_DISPATCH_2D(g, mixed, __VA_ARGS__);                                    \
         }                                                                               \

@@ -25,6 +25,7 @@ struct Geo {
     int halo;             // deposit halo (cells) around a tile held in LDS
     int S;                // fixed-point weight bits per axis (mixed path)
     int np;               // number of particles (bounds for bucket tables)
+    int hc;               // velocity advance: 0 Boris, 1 Higuera-Cary (u = gamma v)
     double lx, ly, lz;
     double inv_dx, inv_dy, inv_dz;
 };
@@ -38,6 +39,8 @@ struct PushC {
     int move;
     int rot;              // bz != 0 (the push rotates v in the x-y plane)
     float deep;           // slack (cells) that makes a staying particle "deep"
+    double ic2;           // 1/c^2 (Higuera-Cary)
+    float ic2f;
 };
 
 // One particle buffer set (structure of arrays).
@@ -58,6 +61,15 @@ struct CtxDev {
     double *kx2, *kapx;   // modified wavenumber tables, x: [nx/2+1]
     double *ky2, *kapy;   // y: [ny]
     double *kz2, *kapz;   // z: [nz]
+};
+
+// Field diagnostics of one solve: charge and W_E (and, with npush, the
+// kinetic energy and momentum partials of the push) into diag[step] or
+// we/charge.
+struct FinArgs {
+    int npush, nspec;
+    double mass, dV, G, rho_ion;
+    double *diag, *we, *charge;
 };
 
 constexpr int kMaxSpecBlocks = 1024;
@@ -122,7 +134,9 @@ int spectral_blocks(const Geo &g);
 // phi_hat = rho_hat / K^2 (scaled for the inverse transform) and the field
 // energy partials; then E = -(centred difference of phi) in real space
 hipError_t launch_spectral(const Geo &g, const void *rho_hat, void *phi_hat, const CtxDev &c, hipStream_t s);
-hipError_t launch_grad(const Geo &g, const double *phi, double *E, float *E32, hipStream_t s);
+// (one extra workgroup of the same launch reduces the field diagnostics)
+hipError_t launch_grad(const Geo &g, const double *phi, double *E, float *E32, const FinArgs &f,
+                       const CtxDev &c, hipStream_t s);
 hipError_t launch_finalize(int npush, int nspec, double mass, double dV, double G, double rho_ion,
                            double *diag, double *we, double *charge, const CtxDev &c, hipStream_t s);
 hipError_t launch_field1d(const Geo &g, bool mixed, void *acc, double scale, double add, double ion,

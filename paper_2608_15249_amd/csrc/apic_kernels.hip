@@ -54,6 +54,7 @@ template <int DIM> struct Dir {
     static constexpr int kFar = kN - 1;
     static constexpr int kStay = (DIM == 3) ? 13 : 4;    // the code of a particle that stays
     static constexpr int kTab = kWaves * kN;             // per-bucket table entries
+    static constexpr int kCodeBits = (DIM == 3) ? 5 : 4; // bits of a near code
 };
 static_assert(Dir<3>::kTab <= kStepTab && Dir<2>::kTab <= kStepTab, "direction table size");
 static_assert(kDeepTab == 2 * kWaves, "deep table size");
@@ -154,10 +155,16 @@ __device__ __forceinline__ int dir_local(const TileNb &t, int lxn, int lyn, int 
     return far ? Dir<DIM>::kFar : (dby + 1) * 3 + (dbx + 1);
 }
 
-// |v|^2 of a particle for the kinetic-energy diagnostic (binary32 squares on
-// the mixed path, FP64 on the FP64 path).
-template <bool MIX, int VDIM>
-__device__ __forceinline__ double vsq(const Pt<MIX> &q) {
+// Twice the kinetic energy per unit mass of a particle for the diagnostic:
+// |v|^2 (binary32 squares on the mixed path, FP64 on the FP64 path), or for
+// the Higuera-Cary state 2 (gamma - 1) c^2 = 2 |u|^2 / (gamma + 1) in FP64.
+template <bool MIX, int VDIM, bool HC>
+__device__ __forceinline__ double vsq(const Pt<MIX> &q, const PushC &pc) {
+    if constexpr (HC) {
+        const double ux = q.vx, uy = q.vy, uz = q.vz;
+        const double u2 = (ux * ux + uy * uy) + uz * uz;
+        return 2.0 * u2 / (sqrt(1.0 + u2 * pc.ic2) + 1.0);
+    }
     auto v2 = q.vx * q.vx;
     if constexpr (VDIM >= 2) v2 = v2 + q.vy * q.vy;
     if constexpr (VDIM >= 3) v2 = v2 + q.vz * q.vz;
@@ -169,12 +176,11 @@ __device__ __forceinline__ double vsq(const Pt<MIX> &q) {
 // outside the tile (the bucket table does not match the order) is flagged
 // and clamped into the tile so that every access stays in bounds. The E tile
 // spans ex_w x ey_w x ez_w nodes from (x0, y0, z0).
-template <bool MIX, int DIM, int VDIM>
+template <bool MIX, int DIM, int VDIM, bool HC>
 __device__ __forceinline__ bool advance(Pt<MIX> &q, const Geo &g, const PushC &pc,
                                         const typename Pt<MIX>::R *sE, int ex_w, int ey_w, int ez_w, int x0, int y0,
                                         int z0, int &lx, int &ly, int &lz, int &sx, int &sy, int &sz) {
     using R = typename Pt<MIX>::R;
-    const R a = MIX ? (R)pc.af : (R)pc.a, t = MIX ? (R)pc.tf : (R)pc.t, s = MIX ? (R)pc.sf : (R)pc.s;
     lx = q.ix - x0;
     ly = (DIM >= 2) ? q.iy - y0 : 0;
     lz = (DIM == 3) ? q.iz - z0 : 0;
@@ -189,17 +195,14 @@ __device__ __forceinline__ bool advance(Pt<MIX> &q, const Geo &g, const PushC &p
         q.iy = y0 + ly;
         q.iz = z0 + lz;
     }
-    R ex, ey;
+    R ex, ey, ez = R(0);
     if constexpr (DIM == 3) {
-        R ez;
         const int wxy = ex_w * ey_w;
         gather_lds3<R>(sE, ex_w, wxy, wxy * ez_w, lx, ly, lz, q.fx, q.fy, q.fz, ex, ey, ez);
-        boris_z<R>(q.vz, ez, a);
     } else {
         gather_lds<R, DIM>(sE, ex_w, ex_w * ey_w, lx, ly, q.fx, q.fy, ex, ey);
     }
-    boris<R, VDIM>(q.vx, q.vy, ex, ey, a, t, s);
-    return move_pt<MIX, DIM>(q, g, pc, sx, sy, sz) && in;
+    return push_move<MIX, DIM, VDIM, HC>(q, g, pc, ex, ey, ez, true, sx, sy, sz) && in;
 }
 
 // Raw stored words of one particle: loaded unconditionally (the caller clamps
@@ -638,12 +641,11 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(Geo g, Parts p, const 
 }
 
 // ---- gather + push (+ move), in place -------------------------------------------
-template <bool MIX, int DIM, int VDIM>
+template <bool MIX, int DIM, int VDIM, bool HC>
 __global__ void __launch_bounds__(kBlock) k_gather_push_direct(Geo g, Parts p, int64_t n,
                                                                const typename Pt<MIX>::R *E, PushC pc,
                                                                CtxDev c) {
     using R = typename Pt<MIX>::R;
-    const R a = MIX ? (R)pc.af : (R)pc.a, t = MIX ? (R)pc.tf : (R)pc.t, s = MIX ? (R)pc.sf : (R)pc.s;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
         Pt<MIX> q;
@@ -651,24 +653,19 @@ __global__ void __launch_bounds__(kBlock) k_gather_push_direct(Geo g, Parts p, i
             raise_err(c.err, ERR_DOMAIN);
             continue;
         }
-        R ex, ey;
-        if constexpr (DIM == 3) {
-            R ez;
+        R ex, ey, ez = R(0);
+        if constexpr (DIM == 3)
             gather_global3<R, R>(E, g, q.ix, q.iy, q.iz, q.fx, q.fy, q.fz, ex, ey, ez);
-            boris_z<R>(q.vz, ez, a);
-        } else {
+        else
             gather_global<R, R, DIM>(E, g, q.ix, q.iy, q.fx, q.fy, ex, ey);
-        }
-        boris<R, VDIM>(q.vx, q.vy, ex, ey, a, t, s);
-        if (pc.move) {
-            int sx, sy;
-            if (!move_pt<MIX, DIM>(q, g, pc, sx, sy)) raise_err(c.err, ERR_DOMAIN);
-        }
+        int sx, sy, sz;
+        if (!push_move<MIX, DIM, VDIM, HC>(q, g, pc, ex, ey, ez, pc.move != 0, sx, sy, sz))
+            raise_err(c.err, ERR_DOMAIN);
         store_pt<MIX, DIM, VDIM>(p, i, q);
     }
 }
 
-template <bool MIX, int DIM, int VDIM>
+template <bool MIX, int DIM, int VDIM, bool HC>
 __global__ void __launch_bounds__(kBlock) k_gather_push_tiled(Geo g, Parts p, const int32_t *bstart,
                                                               const typename Pt<MIX>::R *E, PushC pc,
                                                               CtxDev c) {
@@ -687,7 +684,6 @@ __global__ void __launch_bounds__(kBlock) k_gather_push_tiled(Geo g, Parts p, co
     else
         load_e_tile<R, R, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
     __syncthreads();
-    const R a = MIX ? (R)pc.af : (R)pc.a, t = MIX ? (R)pc.tf : (R)pc.t, s = MIX ? (R)pc.sf : (R)pc.s;
     const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
     for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         Pt<MIX> q;
@@ -699,9 +695,8 @@ __global__ void __launch_bounds__(kBlock) k_gather_push_tiled(Geo g, Parts p, co
         bool inl = lx >= 0 && lx < ex_w - 1;
         if constexpr (DIM >= 2) inl = inl && ly >= 0 && ly < ey_w - 1;
         if constexpr (DIM == 3) inl = inl && lz >= 0 && lz < ez_w - 1;
-        R ex, ey;
+        R ex, ey, ez = R(0);
         if constexpr (DIM == 3) {
-            R ez;
             if (inl) {
                 const int wxy = ex_w * ey_w;
                 gather_lds3<R>(sE, ex_w, wxy, wxy * ez_w, lx, ly, lz, q.fx, q.fy, q.fz, ex, ey, ez);
@@ -709,7 +704,6 @@ __global__ void __launch_bounds__(kBlock) k_gather_push_tiled(Geo g, Parts p, co
                 raise_err(c.err, ERR_ORDER);
                 gather_global3<R, R>(E, g, q.ix, q.iy, q.iz, q.fx, q.fy, q.fz, ex, ey, ez);
             }
-            boris_z<R>(q.vz, ez, a);
         } else {
             if (inl) {
                 gather_lds<R, DIM>(sE, ex_w, ex_w * ey_w, lx, ly, q.fx, q.fy, ex, ey);
@@ -718,11 +712,9 @@ __global__ void __launch_bounds__(kBlock) k_gather_push_tiled(Geo g, Parts p, co
                 gather_global<R, R, DIM>(E, g, q.ix, q.iy, q.fx, q.fy, ex, ey);
             }
         }
-        boris<R, VDIM>(q.vx, q.vy, ex, ey, a, t, s);
-        if (pc.move) {
-            int sx, sy, sz;
-            if (!move_pt<MIX, DIM>(q, g, pc, sx, sy, sz)) raise_err(c.err, ERR_DOMAIN);
-        }
+        int sx, sy, sz;
+        if (!push_move<MIX, DIM, VDIM, HC>(q, g, pc, ex, ey, ez, pc.move != 0, sx, sy, sz))
+            raise_err(c.err, ERR_DOMAIN);
         store_pt<MIX, DIM, VDIM>(p, i, q);
     }
 }
@@ -744,7 +736,7 @@ __device__ __forceinline__ int owned_by(int lo, int hi, int w) {
     auto f = [w](int x) { return (x / kBlock) * 64 + min(max((x % kBlock) - 64 * w, 0), 64); };
     return hi > lo ? f(hi) - f(lo) : 0;
 }
-template <bool MIX, int DIM, int VDIM, int U>
+template <bool MIX, int DIM, int VDIM, int U, bool HC>
 __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int32_t *bstart, const double *E,
                                                        PushC pc, int32_t *cnt, int32_t *tot, int32_t *farcnt,
                                                        const int32_t *deep, CtxDev c) {
@@ -756,6 +748,7 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
     __shared__ float sMax[kWaves][3];
     R *sE = (R *)smem;
     const int w = threadIdx.x >> 6;
+    const uint64_t lt = lanemask_lt();
     const int ex_w = (1 << g.tsx) + 1, ey_w = (DIM >= 2) ? (1 << g.tsy) + 1 : 1;
     const int ez_w = (DIM == 3) ? (1 << g.tsz) + 1 : 1;
     if (threadIdx.x == 0) sErr = 0;
@@ -844,7 +837,7 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
                 Pt<MIX> q;
                 bool good = decode<MIX, DIM, VDIM>(r1, g, q);
                 int lx, ly, lz, sx, sy, sz;
-                good = advance<MIX, DIM, VDIM>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx, sy, sz) &&
+                good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx, sy, sz) &&
                        good;
                 if (!good) atomicOr(&sErr, ERR_DOMAIN);
                 const int code = dir_local<DIM>(tn, lx + sx, ly + sy, lz + sz);
@@ -877,20 +870,22 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
                     Pt<MIX> q;
                     bool good = decode<MIX, DIM, VDIM>(r[j], g, q);
                     int lx, ly, lz, sx, sy, sz;
-                    good = advance<MIX, DIM, VDIM>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx, sy,
+                    good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx, sy,
                                                    sz) && good;
                     if (!good) atomicOr(&sErr, ERR_DOMAIN);
                     code = dir_local<DIM>(tn, lx + sx, ly + sy, lz + sz);
                     if (code == kFar) nbk = bucket_of<MIX, DIM>(g, q.ix, q.iy, q.iz);
                 }
-                uint64_t rem = __ballot(code >= 0 && code < kFar);
-                while (rem) {
-                    const int leader = __ffsll((unsigned long long)rem) - 1;
-                    const int kc = __builtin_amdgcn_readlane(code, leader);
-                    const uint64_t grp = __ballot(code == kc);
-                    if ((int)__lane_id() == leader) sCnt[w * kDirs + kc] += (int)__popcll(grp);
-                    rem &= ~grp;
+                // lanes sharing a near code, from one ballot per code bit; the
+                // group's lowest lane adds the group's size
+                const bool near = code >= 0 && code < kFar;
+                uint64_t peers = __ballot(near);
+#pragma unroll
+                for (int bit = 0; bit < Dir<DIM>::kCodeBits; ++bit) {
+                    const uint64_t bb = __ballot(near && ((code >> bit) & 1));
+                    peers &= ((code >> bit) & 1) ? bb : ~bb;
                 }
+                if (near && (peers & lt) == 0) sCnt[w * kDirs + code] += (int)__popcll(peers);
                 if (code == kFar) {
                     atomicAdd(&farcnt[nbk], 1);
                     atomicAdd(&tot[nbk], 1);
@@ -958,7 +953,7 @@ __global__ void __launch_bounds__(kBlock) k_dest_offsets(Geo g, const int32_t *c
 // the deep table, so that the next count pass can credit those particles as
 // stays without reading them, as long as the field's share of the next move,
 // 2|a| max|E| dt/dx, stays below pc.deep.
-template <bool MIX, int DIM, int VDIM, int U>
+template <bool MIX, int DIM, int VDIM, int U, bool HC>
 __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts dst, const int32_t *bstart,
                                                       const int32_t *bstart_new, const int32_t *cnt,
                                                       const int32_t *offs, int32_t *farcnt, const double *E, PushC pc,
@@ -967,6 +962,7 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
     using R = typename Pt<MIX>::R;
     using A = typename AccOf<MIX>::T;
     constexpr int kDirs = Dir<DIM>::kN, kFar = Dir<DIM>::kFar, kStay = Dir<DIM>::kStay, kTab = Dir<DIM>::kTab;
+    constexpr int kCodeBits = Dir<DIM>::kCodeBits;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sErr;
     __shared__ double sRed[kWaves];
@@ -1013,6 +1009,11 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
         else
             load_e_tile<R, double, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
         __syncthreads();
+        // this wave's stay cursors (front: next deep slot, back: one past the
+        // next shallow slot) and the end of the bucket, uniform over the wave
+        int front = __builtin_amdgcn_readfirstlane(sRun[w * kDirs + kStay]);
+        int back = __builtin_amdgcn_readfirstlane(sBack[w]);
+        const int stayEnd = __builtin_amdgcn_readfirstlane(sEnd[kStay]);
         const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
         const int span = i1 - i0;
         // cells of this tile (the last tile of an axis may be cut by the grid edge)
@@ -1067,12 +1068,12 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                 Pt<MIX> q;
                 if (act) {
                     bool good = decode<MIX, DIM, VDIM>(r[j], g, q);
-                    const double v2o = vsq<MIX, VDIM>(q);
+                    const double v2o = vsq<MIX, VDIM, HC>(q, pc);
                     int lx, ly, lz, sx, sy, sz;
-                    good = advance<MIX, DIM, VDIM>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx, sy,
+                    good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx, sy,
                                                    sz) && good;
                     if (!good) atomicOr(&sErr, ERR_DOMAIN);
-                    const double v2n = vsq<MIX, VDIM>(q);
+                    const double v2n = vsq<MIX, VDIM, HC>(q, pc);
                     ke += 0.5 * (v2o + v2n);
                     px += (double)q.vx;
                     code = dir_local<DIM>(tn, lx + sx, ly + sy, lz + sz);
@@ -1135,32 +1136,37 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                 // them; each group's range is checked once against its bucket's end
                 // (the start is its offset-table entry, computed from the same scan).
                 int slot = -1;
-                uint64_t rem = __ballot(code >= 0 && code < kFar);
-                while (rem) {
-                    const int leader = __ffsll((unsigned long long)rem) - 1;
-                    const int kc = __builtin_amdgcn_readlane(code, leader);
-                    const uint64_t grp = __ballot(code == kc);
-                    const int basek = sRun[w * kDirs + kc];
-                    const int cntk = (int)__popcll(grp);
-                    if (kc == kStay) {
-                        // deep stays from the front of the wave's stay range, the rest from its back
-                        const uint64_t gd = __ballot(code == kStay && deep);
-                        const uint64_t gs = grp & ~gd;
-                        const int back = sBack[w];
-                        const int nd = (int)__popcll(gd), ns = (int)__popcll(gs);
-                        const bool fits = basek >= 0 && basek + nd <= back - ns && back <= sEnd[kStay];
-                        if (code == kStay)
-                            slot = !fits ? -1 : deep ? basek + (int)__popcll(gd & lt) : back - 1 - (int)__popcll(gs & lt);
-                        if ((int)__lane_id() == leader) {
-                            sRun[w * kDirs + kStay] = basek + nd;
-                            sBack[w] = back - ns;
-                        }
-                    } else {
-                        const bool fits = basek >= 0 && basek + cntk <= sEnd[kc];
-                        if (code == kc) slot = fits ? basek + (int)__popcll(grp & lt) : -1;
-                        if ((int)__lane_id() == leader) sRun[w * kDirs + kc] = basek + cntk;
+                // stays: deep ones from the front of the wave's stay range, the
+                // rest from its back (wave-private cursors held in registers)
+                const uint64_t gst = __ballot(code == kStay);
+                const uint64_t gd = __ballot(code == kStay && deep);
+                const uint64_t gs = gst & ~gd;
+                const int nd = (int)__popcll(gd), ns = (int)__popcll(gs);
+                const bool sfits = front >= 0 && front + nd <= back - ns && back <= stayEnd;
+                if (code == kStay)
+                    slot = !sfits ? -1 : deep ? front + (int)__popcll(gd & lt) : back - 1 - (int)__popcll(gs & lt);
+                front += nd;
+                back -= ns;
+                // movers to a neighbour bucket: the lanes sharing a code are found
+                // with one ballot per code bit; each lane reads its group's
+                // cursor, the group's lowest lane advances it
+                const bool mv = code >= 0 && code < kFar && code != kStay;
+                const uint64_t gmv = __ballot(mv);
+                if (gmv) {
+                    uint64_t peers = gmv;
+#pragma unroll
+                    for (int bit = 0; bit < kCodeBits; ++bit) {
+                        const uint64_t bb = __ballot(mv && ((code >> bit) & 1));
+                        peers &= ((code >> bit) & 1) ? bb : ~bb;
                     }
-                    rem &= ~grp;
+                    if (mv) {
+                        const int e = w * kDirs + code;
+                        const int basek = sRun[e];
+                        const int r = (int)__popcll(peers & lt), cntk = (int)__popcll(peers);
+                        const bool fits = basek >= 0 && basek + cntk <= sEnd[code];
+                        slot = fits ? basek + r : -1;
+                        if (r == 0) sRun[e] = basek + cntk;
+                    }
                 }
                 if (code == kFar) {
                     // far arrivals fill the end of their bucket; the counter
@@ -1203,6 +1209,10 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                 if (base + 2 * CH < span) fetch(ra, base + 2 * CH);
                 if (base + CH < span) process(rb, base + CH);
             }
+        }
+        if (__lane_id() == 0) {
+            sRun[w * kDirs + kStay] = front;
+            sBack[w] = back;
         }
         __syncthreads();
         if (threadIdx.x < kWaves) {
@@ -1252,6 +1262,40 @@ __global__ void __launch_bounds__(kBlock) k_rho(int64_t G, typename AccOf<MIX>::
 // Per-block partial of sum_k w_k |E_hat_k|^2 (Parseval over the half
 // spectrum, w = 1 on the kx = 0 and Nyquist columns, else 2) goes to
 // c.part_spec; rho_hat(0) (= sum_j rho_j) to c.rho0.
+// Field diagnostics of one solve (one workgroup): fixed-order sums of the
+// spectral and push partials into diag[step] or we/charge.
+__device__ void finalize_block(const FinArgs &f, const CtxDev &c) {
+    __shared__ double sRed[16];
+    double k = 0.0, p = 0.0, e = 0.0;
+    for (int i = threadIdx.x; i < f.npush; i += blockDim.x) {
+        k += c.part_push[2 * i];
+        p += c.part_push[2 * i + 1];
+    }
+    for (int i = threadIdx.x; i < f.nspec; i += blockDim.x) e += c.part_spec[i];
+    k = block_sum(k, sRed);
+    p = block_sum(p, sRed);
+    e = block_sum(e, sRed);
+    if (threadIdx.x == 0) {
+        double *d = f.diag ? step_slot(f.diag, c) : nullptr;
+        if (f.npush && d) {
+            d[2] = 0.5 * f.mass * k;
+            d[3] = f.mass * p;
+        }
+        if (f.nspec) {
+            double wE = 0.5 * f.dV / f.G * e;
+            double q = f.dV * (*c.rho0 - f.G * f.rho_ion);
+            if (d) {
+                d[0] = q;
+                d[1] = wE;
+            }
+            if (f.we) *f.we = wE;
+            if (f.charge) *f.charge = q;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_finalize(FinArgs f, CtxDev c) { finalize_block(f, c); }
+
 // phi_hat = rho_hat / K^2 (K^2 = sum of the per-axis modified wavenumbers,
 // phi_hat(0) = 0), scaled by 1/G for the unnormalised inverse transform, and
 // the per-block partials of sum |E_hat|^2 = sum kappa^2 |phi_hat|^2 over the
@@ -1285,11 +1329,18 @@ __global__ void __launch_bounds__(kBlock) k_spectral(Geo g, const double2 *rh, d
 // phi[j + e_d]) / (2 d_d), the real-space form of E_hat = -i sin(k d)/d
 // phi_hat. Writes E [dim][G] and, when E32 is not NULL, its binary32
 // rounding. h = 1 / (2 d) per axis.
+// The last workgroup of the launch reduces the field diagnostics instead
+// (it reads only what earlier launches wrote).
 __global__ void __launch_bounds__(kBlock) k_grad(Geo g, const double *phi, double *E, float *E32, double hx,
-                                                 double hy, double hz) {
+                                                 double hy, double hz, FinArgs f, CtxDev c) {
+    if (blockIdx.x == gridDim.x - 1) {
+        finalize_block(f, c);
+        return;
+    }
     const int64_t G = (int64_t)g.nx * g.ny * g.nz;
     const int64_t sxy = (int64_t)g.nx * g.ny;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t stride = (int64_t)(gridDim.x - 1) * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G; i += stride) {
         const int ix = (int)(i % g.nx);
         const int64_t r = i / g.nx;
         const int iy = (int)(r % g.ny), iz = (int)(r / g.ny);
@@ -1319,37 +1370,6 @@ __global__ void __launch_bounds__(kBlock) k_grad(Geo g, const double *phi, doubl
 //   kinetic  = 0.5 * mass * sum(part_push[2b]),   momentum = mass * sum(part_push[2b+1])
 //   W_E      = 0.5 * dV / G * sum(part_spec)      (Parseval)
 //   charge   = dV * (rho0 - G * rho_ion)
-__global__ void __launch_bounds__(1024) k_finalize(int npush, int nspec, double mass, double dV, double G,
-                                                   double rho_ion, double *diag, double *we, double *charge,
-                                                   CtxDev c) {
-    __shared__ double sRed[16];
-    double k = 0.0, p = 0.0, e = 0.0;
-    for (int i = threadIdx.x; i < npush; i += blockDim.x) {
-        k += c.part_push[2 * i];
-        p += c.part_push[2 * i + 1];
-    }
-    for (int i = threadIdx.x; i < nspec; i += blockDim.x) e += c.part_spec[i];
-    k = block_sum(k, sRed);
-    p = block_sum(p, sRed);
-    e = block_sum(e, sRed);
-    if (threadIdx.x == 0) {
-        double *d = diag ? step_slot(diag, c) : nullptr;
-        if (npush && d) {
-            d[2] = 0.5 * mass * k;
-            d[3] = mass * p;
-        }
-        if (nspec) {
-            double wE = 0.5 * dV / G * e;
-            double q = dV * (*c.rho0 - G * rho_ion);
-            if (d) {
-                d[0] = q;
-                d[1] = wE;
-            }
-            if (we) *we = wE;
-            if (charge) *charge = q;
-        }
-    }
-}
 
 // 1D field (one workgroup of kBlock threads; nodes held in LDS).
 template <bool MIX>
@@ -1430,12 +1450,6 @@ hipError_t launch_copy_bytes(void *dst, const void *src, int64_t bytes, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_scan_dir(const Geo &g, int32_t *tot, int32_t *start, int64_t n, int64_t max_per_bucket,
-                           int step_mode, const CtxDev &c, hipStream_t s) {
-    hipLaunchKernelGGL(k_scan_tot, dim3(1), dim3(1024), 0, s, tot, start, g.nbuckets, n, max_per_bucket, step_mode,
-                       c);
-    return hipGetLastError();
-}
 
 hipError_t launch_keys_init(const Geo &g, bool mixed, const Parts &p, int64_t n, int32_t *keys, int32_t *idx,
                             const CtxDev &c, hipStream_t s) {
@@ -1501,11 +1515,11 @@ hipError_t launch_gather_push(const Geo &g, bool mixed, const Parts &p, int64_t 
     if (bstart) {
         size_t sh = tile_e_bytes(g, mixed);
         APIC_DISPATCH(g, mixed,
-                      hipLaunchKernelGGL((k_gather_push_tiled<MIX, DIM, VDIM>), dim3(grid_for_buckets(g.nbuckets)),
+                      hipLaunchKernelGGL((k_gather_push_tiled<MIX, DIM, VDIM, HC>), dim3(grid_for_buckets(g.nbuckets)),
                                          dim3(kBlock), sh, s, g, p, bstart, (const typename Pt<MIX>::R *)E, pc, c));
     } else {
         APIC_DISPATCH(g, mixed,
-                      hipLaunchKernelGGL((k_gather_push_direct<MIX, DIM, VDIM>), dim3(blocks_for(n)), dim3(kBlock), 0,
+                      hipLaunchKernelGGL((k_gather_push_direct<MIX, DIM, VDIM, HC>), dim3(blocks_for(n)), dim3(kBlock), 0,
                                          s, g, p, n, (const typename Pt<MIX>::R *)E, pc, c));
     }
     return hipGetLastError();
@@ -1536,10 +1550,17 @@ hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int
                              const CtxDev &c, hipStream_t s) {
     size_t sh = tile_e_bytes(g, mixed);
     APIC_DISPATCH(g, mixed, {
-        auto kern = k_step_count<MIX, DIM, VDIM, U>;
+        auto kern = k_step_count<MIX, DIM, VDIM, U, HC>;
         hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, p, bstart, E,
                            pc, cnt, tot, farcnt, deep, c);
     });
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_dir(const Geo &g, int32_t *tot, int32_t *start, int64_t n, int64_t max_per_bucket,
+                           int step_mode, const CtxDev &c, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_tot, dim3(1), dim3(1024), 0, s, tot, start, g.nbuckets, n, max_per_bucket, step_mode,
+                       c);
     return hipGetLastError();
 }
 
@@ -1561,7 +1582,7 @@ hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Pa
                             const CtxDev &c, hipStream_t s) {
     size_t sh = tile_acc_bytes(g, g.halo) + tile_e_bytes(g, mixed);
     APIC_DISPATCH(g, mixed, {
-        auto kern = k_step_push<MIX, DIM, VDIM, U>;
+        auto kern = k_step_push<MIX, DIM, VDIM, U, HC>;
         hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, src, dst,
                            bstart, bstart_new, cnt, offs, farcnt, E, pc, (typename AccOf<MIX>::T *)acc, perm, part,
                            deep, c);
@@ -1589,17 +1610,18 @@ hipError_t launch_spectral(const Geo &g, const void *rho_hat, void *phi_hat, con
     return hipGetLastError();
 }
 
-hipError_t launch_grad(const Geo &g, const double *phi, double *E, float *E32, hipStream_t s) {
+hipError_t launch_grad(const Geo &g, const double *phi, double *E, float *E32, const FinArgs &f,
+                       const CtxDev &c, hipStream_t s) {
     const int64_t G = (int64_t)g.nx * g.ny * g.nz;
     const double hx = 0.5 * g.inv_dx, hy = 0.5 * g.inv_dy, hz = 0.5 * g.inv_dz;
-    hipLaunchKernelGGL(k_grad, dim3(blocks_for(G, 8192)), dim3(kBlock), 0, s, g, phi, E, E32, hx, hy, hz);
+    hipLaunchKernelGGL(k_grad, dim3(blocks_for(G, 8192) + 1), dim3(kBlock), 0, s, g, phi, E, E32, hx, hy, hz, f, c);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(int npush, int nspec, double mass, double dV, double G, double rho_ion, double *diag,
                            double *we, double *charge, const CtxDev &c, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, npush, nspec, mass, dV, G, rho_ion, diag, we, charge,
-                       c);
+    const FinArgs f{npush, nspec, mass, dV, G, rho_ion, diag, we, charge};
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, f, c);
     return hipGetLastError();
 }
 

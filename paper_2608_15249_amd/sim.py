@@ -18,7 +18,7 @@ from .apic import Batch, Context, Particles
 
 class Simulation:
     def __init__(self, w: W.Workload, precision: str = "mixed", n: Optional[int] = None, state=None,
-                 tile=(0, 0), frac_bits: int = 0, device="cuda"):
+                 tile=(0, 0), frac_bits: int = 0, device="cuda", pusher: str = "boris", c_light: float = 0.0):
         import torch
         self.torch = torch
         self.w = w
@@ -27,7 +27,7 @@ class Simulation:
         self.n = len(state[0])
         mk = lambda t: Context(dim=w.dim, vdim=w.vdim, nx=w.nx, ny=w.ny, lx=w.Lx, ly=w.Ly, dt=w.dt, n=self.n,
                                bz=w.bz, precision=precision, frac_bits=frac_bits, tile=t, device=device,
-                               nz=w.nz, lz=w.Lz)
+                               nz=w.nz, lz=w.Lz, pusher=pusher, c_light=c_light)
         self.tune_ms = None
         if tile == "auto" and w.dim == 3:
             tile = (0, 0, 0)     # the tile autotuner covers 1D and 2D; 3D keeps the default tile
