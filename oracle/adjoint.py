@@ -24,6 +24,15 @@ Adjoint of each module (lam_* is the derivative of W with respect to *):
              lam_v_old = R^T lam_v_new, lam_Ep = a (R + I)^T lam_v_new.
   move       x^{n+1} = wrap(x^n + v^{n+1/2} dt): lam_x^n = lam_x^{n+1},
              lam_v^{n+1/2} += dt lam_x^{n+1} (the periodic wrap has slope one).
+With the Higuera-Cary advance (pusher "hc", state u = gamma v) two modules
+are nonlinear in u and take the trajectory's velocities:
+  advance    u1 solves the implicit midpoint relation that defines the method,
+             F(u0, u1, E) = u1 - u0 - 2aE - (u0 + u1) x (tau / gamma(ubar)) z = 0
+             with ubar = (u0 + u1) / 2; by the implicit function theorem
+             lam_u0 = -J0^T J1^-T lam_u1 and lam_E = 2a J1^-T lam_u1, with
+             J0 = dF/du0 and J1 = dF/du1 (one 3 x 3 solve per particle);
+  move       x += (u / gamma(u)) dt: lam_u += dt M lam_x with the symmetric
+             M = (I - u u^T / (c^2 gamma^2)) / gamma.
 The CIC hat is piecewise linear, so dW/dx is its slope inside the particle's
 cell: the derivative almost everywhere, which is what central differences of
 the forward map see at steps small against a cell.
@@ -61,23 +70,37 @@ def _positions(st: State):
     return (st.x.copy(), None if st.y is None else st.y.copy())
 
 
-def forward_trajectory(s: Setup, st0: State, nsteps: int):
+def _velocities(st: State):
+    return [None if a is None else a.copy() for a in (st.vx, st.vy, st.vz)]
+
+
+def trajectory(s: Setup, st0: State, nsteps: int):
     """Run the cycle from (x^0, v^0) and keep what the reverse sweep needs.
 
-    Returns (W, xs, Es): W = W_E(T); xs[n] = positions at time level n
-    (n = 0..T); Es[n] = node field E^n. st0 is not modified."""
+    Returns (W, xs, vs, Es): W = W_E(T); xs[n] = positions at time level n
+    (n = 0..T); vs[n] = velocities held at level n, v^{n-1/2} (vs[0] is the
+    result of the backward half push); Es[n] = node field E^n. st0 is not
+    modified."""
     st = st0.copy()
     E = solve_field(s, deposit(s, st))
     xs = [_positions(st)]
     Es = [E]
     boris(s, st, gather(s, st, E), -0.5 * s.dt)
+    vs = [_velocities(st)]
     for _ in range(nsteps):
         boris(s, st, gather(s, st, E), s.dt)
         move(s, st)
         E = solve_field(s, deposit(s, st))
         xs.append(_positions(st))
+        vs.append(_velocities(st))
         Es.append(E)
-    return field_energy(s, E), xs, Es
+    return field_energy(s, E), xs, vs, Es
+
+
+def forward_trajectory(s: Setup, st0: State, nsteps: int):
+    """(W, xs, Es) of ``trajectory``."""
+    W, xs, _, Es = trajectory(s, st0, nsteps)
+    return W, xs, Es
 
 
 def _pos_state(s: Setup, pos) -> State:
@@ -126,12 +149,62 @@ def adj_boris(s: Setup, lam_v, dt: float):
     return [lEx] if s.dim == 1 else [lEx, lEy]
 
 
+def adj_hc(s: Setup, u_old, Ep, lam_v, dt: float):
+    """Higuera-Cary adjoint for one advance by dt from u_old (3 arrays) under
+    Ep (dim arrays): lam_v (3 arrays, lam of u_new) becomes lam of u_old in
+    place; returns lam_Ep (one array per component of Ep).
+
+    From the defining relation F(u0, u1, E) = 0 (module header), with
+    w = u0 + u1, beta = tau / gamma(w / 2) and K the matrix of w -> w x z:
+      dF/du1 = I - beta K - (w x z) dbeta^T,
+      dF/du0 = -I - beta K - (w x z) dbeta^T,
+      dbeta/du0 = dbeta/du1 = -beta ubar / (2 c^2 gamma(ubar)^2),
+      dF/dE = -2a I."""
+    n = u_old[0].shape[0]
+    st = State(np.zeros(n), u_old[0].copy(), np.zeros(n), u_old[1].copy(), u_old[2].copy())
+    boris(s, st, Ep, dt)
+    u0 = np.stack(u_old, axis=1)
+    u1 = np.stack([st.vx, st.vy, st.vz], axis=1)
+    a = s.qm * dt / 2.0
+    tau = a * s.bz
+    ic2 = 1.0 / (s.c * s.c)
+    w = u0 + u1
+    ub = 0.5 * w
+    gb2 = 1.0 + ic2 * np.sum(ub * ub, axis=1)
+    beta = tau / np.sqrt(gb2)
+    wxz = np.stack([w[:, 1], -w[:, 0], np.zeros(n)], axis=1)
+    dbeta = (-beta * ic2 / (2.0 * gb2))[:, None] * ub
+    K = np.array([[0.0, 1.0, 0.0], [-1.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    common = beta[:, None, None] * K + wxz[:, :, None] * dbeta[:, None, :]
+    J1 = np.eye(3) - common
+    J0 = -np.eye(3) - common
+    lam = np.stack(lam_v, axis=1)
+    mu = np.linalg.solve(np.transpose(J1, (0, 2, 1)), lam[:, :, None])[:, :, 0]
+    lam_u0 = -np.einsum("pji,pj->pi", J0, mu)
+    for k in range(3):
+        lam_v[k][:] = lam_u0[:, k]
+    return [2.0 * a * mu[:, k] for k in range(len(Ep))]
+
+
+def adj_move_u(s: Setup, u, lam_x, lam_v) -> None:
+    """Move x += (u / gamma) dt (each of the dim position axes):
+    lam_v += dt M lam_x with M = (I - u u^T / (c^2 gamma^2)) / gamma."""
+    ic2 = 1.0 / (s.c * s.c)
+    u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2]
+    g = np.sqrt(1.0 + ic2 * u2)
+    lx = [lam_x[k] if k < s.dim else np.zeros_like(u[0]) for k in range(3)]
+    dot = u[0] * lx[0] + u[1] * lx[1] + u[2] * lx[2]
+    for k in range(3):
+        lam_v[k] += s.dt / g * (lx[k] - ic2 * u[k] * dot / (g * g))
+
+
 def adjoint(s: Setup, st0: State, nsteps: int, seed: float = 1.0):
     """Reverse sweep of the cycle from (x^0, v^0) over nsteps steps.
 
     Returns (W, lam_x, lam_v): W = W_E(T), lam_x = [dW/dx^0 (, dW/dy^0)],
     lam_v = [dW/dv_x^0, ...] (vdim arrays), all multiplied by seed."""
-    W, xs, Es = forward_trajectory(s, st0, nsteps)
+    W, xs, vs, Es = trajectory(s, st0, nsteps)
+    hc = s.pusher == "hc"
     n = st0.x.shape[0]
     lam_x = [np.zeros(n) for _ in range(s.dim)]
     lam_v = [np.zeros(n) for _ in range(s.vdim)]
@@ -143,13 +216,22 @@ def adjoint(s: Setup, st0: State, nsteps: int, seed: float = 1.0):
         if lev == 0:
             break
         # reverse step lev-1: x^lev = x^{lev-1} + v^{lev-1/2} dt, v^{lev-1/2} = Boris(v^{lev-3/2}, E_p^{lev-1})
-        for d in range(s.dim):
-            lam_v[d] += s.dt * lam_x[d]
-        lam_Ep = adj_boris(s, lam_v, s.dt)
-        if lev - 1 == 0:
-            # the backward half push v^{-1/2} = Boris(v^0, E_p^0, -dt/2) uses the same E_p^0
-            lam_h = adj_boris(s, lam_v, -0.5 * s.dt)
-            lam_Ep = [a + b for a, b in zip(lam_Ep, lam_h)]
+        if hc:
+            Ep = gather(s, _pos_state(s, xs[lev - 1]), Es[lev - 1])
+            adj_move_u(s, vs[lev], lam_x, lam_v)
+            lam_Ep = adj_hc(s, vs[lev - 1], Ep, lam_v, s.dt)
+            if lev - 1 == 0:
+                u0 = [st0.vx, st0.vy, st0.vz]
+                lam_h = adj_hc(s, u0, Ep, lam_v, -0.5 * s.dt)
+                lam_Ep = [a + b for a, b in zip(lam_Ep, lam_h)]
+        else:
+            for d in range(s.dim):
+                lam_v[d] += s.dt * lam_x[d]
+            lam_Ep = adj_boris(s, lam_v, s.dt)
+            if lev - 1 == 0:
+                # the backward half push v^{-1/2} = Boris(v^0, E_p^0, -dt/2) uses the same E_p^0
+                lam_h = adj_boris(s, lam_v, -0.5 * s.dt)
+                lam_Ep = [a + b for a, b in zip(lam_Ep, lam_h)]
         lam_E = [np.zeros(s.grid_shape) for _ in range(s.dim)]
         adj_gather(s, xs[lev - 1], Es[lev - 1], lam_Ep, lam_E, lam_x)
     return W, lam_x, lam_v

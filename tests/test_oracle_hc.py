@@ -172,3 +172,130 @@ def test_mixed_hc_tracks_fp64_hc():
         for p_, ref, L in zip(pos, (st.x, st.y, st.z), (s.Lx, s.Ly, s.Lz)):
             d = np.abs(p_ - ref)
             assert np.max(np.minimum(d, L - d)) < 3e-5
+
+
+# ---------------------------------------------------------------------------
+# The oracle's reference gradient through the Higuera-Cary advance
+# ---------------------------------------------------------------------------
+
+from oracle import adjoint as A   # noqa: E402
+
+
+@pytest.mark.parametrize("c", [0.7, 2.0, 50.0])
+def test_hc_adjoint_matches_central_differences_of_the_advance(c):
+    """lam^T J of one advance (in u_old and in E_p, full and backward half
+    step) against central differences of the forward advance itself."""
+    rng = np.random.default_rng(31)
+    n = 64
+    for dim, dt in ((2, 0.1), (2, -0.05), (3, 0.1)):
+        s = _s(dim, bz=1.9, c=c, dt=abs(dt), n=n)
+        u0 = [rng.normal(size=n) * 1.5 for _ in range(3)]
+        Ep = [rng.normal(size=n) for _ in range(dim)]
+        lam = [rng.normal(size=n) for _ in range(3)]
+
+        def f(uu, ee):
+            st = _st(np.stack(uu, axis=1), n)
+            O.boris(s, st, tuple(ee), dt)
+            return st.vx * lam[0] + st.vy * lam[1] + st.vz * lam[2]
+
+        lv = [l.copy() for l in lam]
+        lE = A.adj_hc(s, u0, Ep, lv, dt)
+        h = 1e-6
+        for k in range(3):
+            up = [a.copy() for a in u0]
+            um = [a.copy() for a in u0]
+            up[k] += h
+            um[k] -= h
+            fd = (f(up, Ep) - f(um, Ep)) / (2 * h)
+            assert np.max(np.abs(fd - lv[k])) < 1e-8 * (1 + np.max(np.abs(fd))), (dim, dt, k)
+        for k in range(dim):
+            ep = [a.copy() for a in Ep]
+            em = [a.copy() for a in Ep]
+            ep[k] += h
+            em[k] -= h
+            fd = (f(u0, ep) - f(u0, em)) / (2 * h)
+            assert np.max(np.abs(fd - lE[k])) < 1e-8 * (1 + np.max(np.abs(fd))), (dim, dt, "E", k)
+
+
+def test_hc_adjoint_reduces_to_boris_at_large_c():
+    rng = np.random.default_rng(32)
+    n = 40
+    sh = _s(2, bz=1.3, c=1e30, n=n)
+    sb = O.Setup(2, 3, 8, 100.0, n, 0.05, ny=8, Ly=100.0, bz=1.3)
+    u0 = [rng.normal(size=n) for _ in range(3)]
+    Ep = [rng.normal(size=n) for _ in range(2)]
+    lam = [rng.normal(size=n) for _ in range(3)]
+    lh = [l.copy() for l in lam]
+    lb = [l.copy() for l in lam]
+    eh = A.adj_hc(sh, u0, Ep, lh, sh.dt)
+    eb = A.adj_boris(sb, lb, sb.dt)
+    for a, b in zip(lh + eh, lb + eb):
+        assert np.max(np.abs(a - b)) < 1e-13
+
+
+def test_move_u_adjoint_matches_central_differences():
+    rng = np.random.default_rng(33)
+    n = 50
+    for dim in (2, 3):
+        s = _s(dim, bz=0.0, c=1.3, dt=0.2, n=n)
+        u = [rng.normal(size=n) * 2 for _ in range(3)]
+        lx = [rng.normal(size=n) for _ in range(dim)]
+        lv = [np.zeros(n) for _ in range(3)]
+        A.adj_move_u(s, u, lx, lv)
+
+        def f(uu):
+            st = _st(np.stack(uu, axis=1), n)
+            O.move(s, st)
+            out = (st.x - 50.0) * lx[0] + (st.y - 50.0) * lx[1]
+            return out + ((st.z - 50.0) * lx[2] if dim == 3 else 0.0)
+
+        h = 1e-6
+        for k in range(3):
+            up = [a.copy() for a in u]
+            um = [a.copy() for a in u]
+            up[k] += h
+            um[k] -= h
+            fd = (f(up) - f(um)) / (2 * h)
+            # positions near 50 carry rounding of 1e-14, i.e. 1e-8 after the 2h division
+            assert np.max(np.abs(fd - lv[k])) < 1e-7, (dim, k)
+
+
+def _hc_plasma(c=2.5, nx=16, ppc=16):
+    w = dataclasses.replace(W.magnetized_2d3v(nx=nx, ppc=ppc), mode=(1, 0))
+    x, y, vx, vy, vz = W.sample(w)
+    s = O.Setup(2, 3, w.nx, w.Lx, len(x), w.dt, ny=w.ny, Ly=w.Ly, bz=w.bz, pusher="hc", c=c)
+    return w, s, (x, y, vx, vy, vz)
+
+
+def test_hc_adjoint_matches_independent_torch_autograd():
+    torch = pytest.importorskip("torch")
+    from tests.torch_pic import Plasma
+    w, s, (x, y, vx, vy, vz) = _hc_plasma()
+    nsteps = 20
+    Wo, lx, lv = A.adjoint(s, O.State.from_arrays(x, vx, y, vy, vz), nsteps)
+    P = Plasma(2, 3, w.nx, w.Lx, len(x), w.dt, ny=w.ny, Ly=w.Ly, bz=w.bz, pusher="hc", c=s.c)
+    tx = torch.tensor(x, dtype=torch.float64, requires_grad=True)
+    ty = torch.tensor(y, dtype=torch.float64, requires_grad=True)
+    tv = [torch.tensor(a, dtype=torch.float64, requires_grad=True) for a in (vx, vy, vz)]
+    Wt = P.run(tx, ty, tv, nsteps)
+    grads = torch.autograd.grad(Wt, [tx, ty] + tv)
+    assert abs(Wt.item() / Wo - 1.0) < 1e-11
+    for a, b in zip(lx + lv, grads):
+        b = b.numpy()
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-9
+    # u_z now reaches the field (gamma couples it to the in-plane motion)
+    assert np.linalg.norm(lv[2]) > 1e-3 * np.linalg.norm(lv[0])
+
+
+def test_hc_adjoint_matches_central_differences_in_single_velocities():
+    w, s, (x, y, vx, vy, vz) = _hc_plasma(c=2.0, nx=8, ppc=16)
+    nsteps = 12
+    _, lx, lv = A.adjoint(s, O.State.from_arrays(x, vx, y, vy, vz), nsteps)
+    for p in (3, 400, 1000):
+        for k in range(3):
+            def Wv(dv):
+                st = O.State.from_arrays(x, vx, y, vy, vz)
+                (st.vx, st.vy, st.vz)[k][p] += dv
+                return A.forward_trajectory(s, st, nsteps)[0]
+            fd = (Wv(1e-5) - Wv(-1e-5)) / 2e-5
+            assert abs(fd - lv[k][p]) <= 2e-5 * abs(lv[k][p]) + 1e-12 * abs(lv[0]).max(), (p, k, fd, lv[k][p])

@@ -32,7 +32,8 @@ def _kmod(n, d):
 
 
 class Plasma:
-    def __init__(self, dim, vdim, nx, Lx, n, dt, ny=1, Ly=1.0, qm=-1.0, bz=0.0, n0=1.0):
+    def __init__(self, dim, vdim, nx, Lx, n, dt, ny=1, Ly=1.0, qm=-1.0, bz=0.0, n0=1.0, pusher="boris", c=math.inf):
+        self.pusher, self.c = pusher, c
         self.dim, self.vdim, self.nx, self.ny = dim, vdim, nx, (ny if dim == 2 else 1)
         self.Lx, self.Ly = Lx, (Ly if dim == 2 else 1.0)
         self.dx, self.dy = Lx / nx, (self.Ly / self.ny if dim == 2 else 1.0)
@@ -84,7 +85,36 @@ class Plasma:
                        + e[jp, ip] * fx * fy)
         return tuple(out)
 
+    def higuera_cary(self, u, Ep, dt):
+        """Higuera & Cary (2017) in its vector form, u = gamma v, B = bz z:
+        u- = u + a E; gamma_new^2 = (sigma + sqrt(sigma^2 + 4 (|tau|^2 + (u-.tau)^2/c^2))) / 2
+        with sigma = gamma(u-)^2 - |tau|^2; t = tau / gamma_new; s = 1/(1+|t|^2);
+        u+ = s (u- + (u-.t) t + u- x t); u_new = u+ + a E + u+ x t."""
+        a = self.qm * dt / 2.0
+        n = u[0].shape[0]
+        E3 = torch.stack(list(Ep) + [torch.zeros(n, dtype=DT)] * (3 - len(Ep)), dim=1)
+        um = torch.stack(u, dim=1) + a * E3
+        tau = torch.tensor([0.0, 0.0, a * self.bz], dtype=DT).expand(n, 3)
+        ic2 = 1.0 / (self.c * self.c)
+        sig = 1.0 + ic2 * (um * um).sum(1) - (tau * tau).sum(1)
+        ust = (um * tau).sum(1)
+        gnew = torch.sqrt(0.5 * (sig + torch.sqrt(sig * sig + 4.0 * ((tau * tau).sum(1) + ic2 * ust * ust))))
+        t = tau / gnew[:, None]
+        sfac = 1.0 / (1.0 + (t * t).sum(1))
+        up = sfac[:, None] * (um + (um * t).sum(1, keepdim=True) * t + torch.linalg.cross(um, t, dim=1))
+        out = up + a * E3 + torch.linalg.cross(up, t, dim=1)
+        return [out[:, 0], out[:, 1], out[:, 2]]
+
+    def velocity(self, u):
+        """dx/dt of the state: v, or u / gamma for the relativistic state."""
+        if self.pusher != "hc":
+            return u
+        g = torch.sqrt(1.0 + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / (self.c * self.c))
+        return [a / g for a in u]
+
     def boris(self, v, Ep, dt):
+        if self.pusher == "hc":
+            return self.higuera_cary(v, Ep, dt)
         a = self.qm * dt / 2.0
         if self.vdim == 1:
             return [v[0] + 2.0 * a * Ep[0]]
@@ -104,8 +134,9 @@ class Plasma:
         v = self.boris(v, self.gather(x, y, E), -0.5 * self.dt)
         for _ in range(nsteps):
             v = self.boris(v, self.gather(x, y, E), self.dt)
-            x = torch.remainder(x + v[0] * self.dt, self.Lx)
+            vel = self.velocity(v)
+            x = torch.remainder(x + vel[0] * self.dt, self.Lx)
             if self.dim == 2:
-                y = torch.remainder(y + v[1] * self.dt, self.Ly)
+                y = torch.remainder(y + vel[1] * self.dt, self.Ly)
             E = self.field(self.deposit(x, y))
         return 0.5 * sum((e * e).sum() for e in E) * self.dV
