@@ -252,16 +252,21 @@ apic_status apic_import_state(apic_ctx *ctx, const double *x, const double *y, c
  * of lam_rho), sort (each step's permutation inverted). The derivative of the
  * CIC hat is its slope inside the particle's cell.
  *
- * The adjoint entry points (and apic_import_state) cover 1D and 2D plasmas
- * advanced with Boris; a 3D or Higuera-Cary context returns
- * APIC_EUNSUPPORTED.
+ * With the Higuera-Cary advance (2D3V, state u = gamma v) the reverse of the
+ * advance is the transpose of its Jacobian at the step's own velocity (the
+ * advance is nonlinear in u through gamma), and the move's is
+ * lam_u += dt (I - u u^T / (c^2 gamma^2)) lam_x / gamma; lam_vx, lam_vy and
+ * lam_vz are then derivatives with respect to u^0.
+ *
+ * The adjoint entry points (and apic_import_state) cover 1D and 2D plasmas;
+ * a 3D context returns APIC_EUNSUPPORTED.
  *
  * Step checkpointing: apic_adjoint_forward stores the state every `stride`
  * steps in the caller's checkpoint buffer; apic_step_adjoint recomputes one
  * segment of at most `stride` steps at a time from its checkpoint and walks it
  * backwards. Memory: ckpt_bytes ~ (nsteps/stride + 1) states; ws_bytes holds
  * the context workspace plus `stride` per-step snapshots (positions, sort
- * permutation, E) and the lam arrays.
+ * permutation, E, and with Higuera-Cary the velocities) and the lam arrays.
  *
  * Precision: the mixed path runs the per-particle adjoint in binary32, the
  * FP64 path in FP64; grid adjoints are FP64 in both (accumulated with atomics,

@@ -19,11 +19,11 @@ from .apic import Context, Particles
 
 class FieldEnergyRun:
     def __init__(self, *, dim, vdim, nx, ny, lx, ly, dt, n, nsteps, stride=20, bz=0.0, qm=-1.0, rho_ion=1.0,
-                 precision="mixed", tile=(0, 0), device="cuda"):
+                 precision="mixed", tile=(0, 0), device="cuda", pusher="boris", c_light=0.0):
         import torch
         self.torch = torch
         self.ctx = Context(dim=dim, vdim=vdim, nx=nx, ny=ny, lx=lx, ly=ly, dt=dt, n=n, qm=qm, rho_ion=rho_ion, bz=bz,
-                           precision=precision, tile=tile, device=device)
+                           precision=precision, tile=tile, device=device, pusher=pusher, c_light=c_light)
         self.parts = Particles(self.ctx)
         self.nsteps, self.stride = int(nsteps), int(stride)
         ck, ws = self.ctx.adjoint_sizes(self.nsteps, self.stride)

@@ -11,6 +11,17 @@
 //   gather   lam_E += scatter of W_j lam_Ep, lam_x += sum_j dW_j/dx E_j.lam_Ep;
 //   Boris    linear for fixed B: lam_v_old = R^T lam_v, lam_Ep = a (R+I)^T lam_v;
 //   move     lam_v^{n+1/2} += dt lam_x^{n+1} (the wrap has slope one);
+//   Higuera-Cary (state u = gamma v): the advance is u1 = R(t(m)) m + aE with
+//            m = u0 + aE, R the rotation of the method's closed form and
+//            t = tau / gamma+(m); its adjoint adds to R^T lam the term
+//            (lam . dR/dt m) dt/dm from the dependence of gamma+ on m. The
+//            move x += (u / gamma) dt gives lam_u += dt M lam_x with
+//            M = (I - u u^T / (c^2 gamma^2)) / gamma. Both need the velocity
+//            before the advance, so the recomputed segment also keeps the
+//            velocities of every level; the advance is then re-run from them.
+//            The backward half push needs u^0, which the checkpoints do not
+//            hold: the method solves a time-symmetric implicit relation, so
+//            u^0 is the advance of v^{-1/2} by +dt/2 under the same E_p^0;
 //   sort     a permutation: each reverse step sends lam back to the order the
 //            particles had before that step (perm from the forward step).
 // dW/dx of the CIC hat is its slope inside the particle's cell.
@@ -81,8 +92,13 @@ struct AdjP {
     double *out_x, *out_y, *out_vx, *out_vy, *out_vz;
     // coefficients
     R dt, cq;               // dt; Q/dV
-    R a, t, s;              // Boris of a full step
+    R a, t, s;              // Boris of a full step (t = tau = a bz for Higuera-Cary)
     R ah, th, sh;           // Boris of the backward half step
+    // Higuera-Cary: level-(n-1) velocities (before the advance, level-(n-1)
+    // order), E^{n-1}, and 1/c^2
+    const R *vprev;         // [3][n]
+    const double *Eprev;    // [dim][G]
+    R ic2;
     int *err;
 };
 
@@ -134,7 +150,38 @@ __device__ __forceinline__ void boris_adj(R &gx, R &gy, R a, R t, R s, R &ex, R 
     }
 }
 
-template <bool MIX, int DIM, int VDIM>
+// Higuera-Cary adjoint of one advance u1 = R(t) m + aE, m = u0 + aE (E_z = 0):
+// l (lam of u1) -> lam of u0 in place; returns lam_Ep (x, y) in ex, ey.
+//   R = [[C, S], [-S, C]] on (x, y), identity on z, C = (1-t^2)/(1+t^2),
+//   S = 2t/(1+t^2); t = tau / gamma+, gamma+^2 = (sigma + D)/2,
+//   sigma = 1 + |m|^2/c^2 - tau^2, D = sqrt(sigma^2 + 4 tau^2 (1 + mz^2/c^2));
+//   dt/dm = -t/(2 gamma+^2) d(gamma+^2)/dm,
+//   d(gamma+^2)/dm = (m (1 + sigma/D) + 2 tau^2 mz z / D) / c^2.
+template <typename R>
+__device__ __forceinline__ void hc_adj(R mx, R my, R mz, R a, R tau, R ic2, R &lx, R &ly, R &lz, R &ex, R &ey) {
+    const R g2 = R(1) + ((mx * mx + my * my) + mz * mz) * ic2;
+    const R sig = g2 - tau * tau;
+    const R us = mz * tau;
+    const R D = sqrt(sig * sig + R(4) * (tau * tau + (us * us) * ic2));
+    const R gp2 = R(0.5) * (sig + D);
+    const R t = tau / sqrt(gp2);
+    const R q = R(1) / (R(1) + t * t);
+    const R C = (R(1) - t * t) * q, S = R(2) * t * q;
+    const R dC = R(-4) * t * q * q, dS = R(2) * (R(1) - t * t) * q * q;
+    const R w = lx * (dC * mx + dS * my) + ly * (dC * my - dS * mx);
+    const R f = -t / (R(2) * gp2) * ic2 * w;
+    const R k = R(1) + sig / D;
+    const R ox = (C * lx - S * ly) + f * k * mx;
+    const R oy = (S * lx + C * ly) + f * k * my;
+    const R oz = lz + f * (k * mz + R(2) * tau * tau * mz / D);
+    ex = a * (ox + lx);
+    ey = a * (oy + ly);
+    lx = ox;
+    ly = oy;
+    lz = oz;
+}
+
+template <bool MIX, int DIM, int VDIM, bool HC>
 __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>::T> P) {
     using R = typename RealOf<MIX>::T;
     const Geo &g = P.g;
@@ -190,6 +237,65 @@ __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>:
             continue;
         }
         if (!P.back) continue;
+        if constexpr (HC) {
+            static_assert(DIM == 2 && VDIM == 3, "the Higuera-Cary adjoint is 2D3V");
+            // reverse of the step n-1 -> n: re-run the advance from the
+            // level-(n-1) velocity, then the move and advance adjoints
+            const int32_t j = P.perm[i];
+            if ((uint32_t)j >= (uint32_t)n) {
+                raise_err(P.err, ERR_ORDER);
+                continue;
+            }
+            int jx, jy;
+            R qx, qy;
+            if (!load_pos<MIX, DIM>(P.prev, j, g, jx, jy, qx, qy)) raise_err(P.err, ERR_DOMAIN);
+            int jxp = jx + 1, jyp = jy + 1;
+            if (jxp >= g.nx) jxp = 0;
+            if (jyp >= g.ny) jyp = 0;
+            const R w00 = (R(1) - qx) * (R(1) - qy), w10 = qx * (R(1) - qy);
+            const R w01 = (R(1) - qx) * qy, w11 = qx * qy;
+            const int b00 = jy * g.nx + jx, b10 = jy * g.nx + jxp, b01 = jyp * g.nx + jx, b11 = jyp * g.nx + jxp;
+            const R epx = w00 * (R)P.Eprev[b00] + w10 * (R)P.Eprev[b10] + w01 * (R)P.Eprev[b01] +
+                          w11 * (R)P.Eprev[b11];
+            const R epy = w00 * (R)P.Eprev[G + b00] + w10 * (R)P.Eprev[G + b10] + w01 * (R)P.Eprev[G + b01] +
+                          w11 * (R)P.Eprev[G + b11];
+            const R u0x = P.vprev[j], u0y = P.vprev[n + j], u0z = P.vprev[2 * n + j];
+            R ux = u0x, uy = u0y, uz = u0z;
+            higuera_cary<R>(ux, uy, uz, epx, epy, R(0), P.a, P.t, P.ic2);
+            // move: lam_u1 = lam_v + dt M(u1) lam_x
+            const R ig = R(1) / lorentz<R>(ux, uy, uz, P.ic2);
+            const R cf = P.ic2 * (ux * lx + uy * ly) * ig * ig;
+            R gx = lvx + P.dt * ig * (lx - ux * cf);
+            R gy = lvy + P.dt * ig * (ly - uy * cf);
+            R gz = lvz - P.dt * ig * (uz * cf);
+            R ex, ey;
+            hc_adj<R>(u0x + P.a * epx, u0y + P.a * epy, u0z, P.a, P.t, P.ic2, gx, gy, gz, ex, ey);
+            if (P.init) {
+                // v^{-1/2} = advance(u^0, E_p^0, -dt/2); u^0 = advance(v^{-1/2}, E_p^0, +dt/2)
+                R hx = u0x, hy = u0y, hz = u0z;
+                higuera_cary<R>(hx, hy, hz, epx, epy, R(0), -P.ah, -P.th, P.ic2);
+                R fx, fy;
+                hc_adj<R>(hx + P.ah * epx, hy + P.ah * epy, hz, P.ah, P.th, P.ic2, gx, gy, gz, fx, fy);
+                ex += fx;
+                ey += fy;
+            }
+            unsafeAtomicAdd(&P.lE_prev[b00], (double)(w00 * ex));
+            unsafeAtomicAdd(&P.lE_prev[b10], (double)(w10 * ex));
+            unsafeAtomicAdd(&P.lE_prev[b01], (double)(w01 * ex));
+            unsafeAtomicAdd(&P.lE_prev[b11], (double)(w11 * ex));
+            unsafeAtomicAdd(&P.lE_prev[G + b00], (double)(w00 * ey));
+            unsafeAtomicAdd(&P.lE_prev[G + b10], (double)(w10 * ey));
+            unsafeAtomicAdd(&P.lE_prev[G + b01], (double)(w01 * ey));
+            unsafeAtomicAdd(&P.lE_prev[G + b11], (double)(w11 * ey));
+            P.lxp_out[j] = lx;
+            P.lxp_out[n + j] = ly;
+            P.lep_out[j] = ex;
+            P.lep_out[n + j] = ey;
+            P.lv_out[j] = gx;
+            P.lv_out[n + j] = gy;
+            P.lv_out[2 * n + j] = gz;
+            continue;
+        }
         // reverse of the step n-1 -> n: move, then Boris
         R gx = lvx + P.dt * lx;
         R gy = (DIM == 2) ? lvy + P.dt * ly : lvy;
@@ -419,6 +525,7 @@ struct AdjWs {
     size_t snap_pos;            // stride entries of positions
     size_t snap_pos_bytes;
     size_t snap_perm, snap_E;   // stride entries
+    size_t snap_vel;            // stride entries of [3][n] velocities (Higuera-Cary)
     size_t lam[2][3];           // ping-pong: lam_x carried, lam_Ep, lam_v
     size_t lE, lrho, W;
     size_t bytes;
@@ -462,6 +569,7 @@ AdjWs adj_layout(const apic_ctx *c, int stride) {
     L.snap_pos = take(L.snap_pos_bytes * (size_t)stride);
     L.snap_perm = take(align256(4 * n) * (size_t)stride);
     L.snap_E = take(align256(8 * (size_t)dim * G) * (size_t)stride);
+    L.snap_vel = c->g.hc ? take(align256(r * 3 * n) * (size_t)stride) : (size_t)-1;
     for (int b = 0; b < 2; ++b) {
         L.lam[b][0] = take(r * dim * n);
         L.lam[b][1] = take(r * dim * n);
@@ -592,6 +700,16 @@ apic_status adj_solve(apic_ctx *c, double *lE, double *lrho, char *ws_ctx, hipSt
     return APIC_OK;
 }
 
+// Velocities of p into a [3][n] block (Higuera-Cary snapshots).
+apic_status save_vel(apic_ctx *c, const apic_particles &p, char *dst, hipStream_t s) {
+    const int64_t n = c->n;
+    const size_t r = c->mixed ? 4 : 8;
+    HIPCHK(c, launch_copy_bytes(dst, p.vx, (int64_t)(r * n), s));
+    HIPCHK(c, launch_copy_bytes(dst + r * n, p.vy, (int64_t)(r * n), s));
+    HIPCHK(c, launch_copy_bytes(dst + 2 * r * n, p.vz, (int64_t)(r * n), s));
+    return APIC_OK;
+}
+
 template <typename R>
 void boris_consts(const apic_ctx *c, double dt_scale, R &a, R &t, R &s) {
     const PushC pc = push_coeffs(c, dt_scale, 1);
@@ -615,17 +733,29 @@ apic_status launch_level(apic_ctx *c, AdjP<R> &P, hipStream_t s) {
     P.cq = (R)(c->d.q_macro / c->dV);
     boris_consts<R>(c, 1.0, P.a, P.t, P.s);
     boris_consts<R>(c, -0.5, P.ah, P.th, P.sh);
-    APIC_DISPATCH_2D(c->g, c->mixed, {
-        if constexpr (std::is_same<R, typename RealOf<MIX>::T>::value)
-            hipLaunchKernelGGL((k_adj_level<MIX, DIM, VDIM>), dim3(nblocks(c->n)), dim3(kBlock), 0, s, P);
-    });
+    const PushC pc = push_coeffs(c, 1.0, 1);
+    P.ic2 = c->mixed ? (R)pc.ic2f : (R)pc.ic2;
+    if (c->g.hc) {
+        if (c->mixed) {
+            if constexpr (std::is_same<R, float>::value)
+                hipLaunchKernelGGL((k_adj_level<true, 2, 3, true>), dim3(nblocks(c->n)), dim3(kBlock), 0, s, P);
+        } else {
+            if constexpr (std::is_same<R, double>::value)
+                hipLaunchKernelGGL((k_adj_level<false, 2, 3, true>), dim3(nblocks(c->n)), dim3(kBlock), 0, s, P);
+        }
+    } else {
+        APIC_DISPATCH_2D(c->g, c->mixed, {
+            if constexpr (std::is_same<R, typename RealOf<MIX>::T>::value)
+                hipLaunchKernelGGL((k_adj_level<MIX, DIM, VDIM, false>), dim3(nblocks(c->n)), dim3(kBlock), 0, s,
+                                   P);
+        });
+    }
     HIPCHK(c, hipGetLastError());
     return APIC_OK;
 }
 
 apic_status check_adj_args(apic_ctx *c, int nsteps, int stride) {
     if (c->d.dim == 3) return fail(c, APIC_EUNSUPPORTED, "the adjoint covers 1D and 2D plasmas");
-    if (c->g.hc) return fail(c, APIC_EUNSUPPORTED, "the adjoint covers the Boris advance");
     if (nsteps < 0) return fail(c, APIC_EINVAL, "nsteps must be >= 0");
     if (stride < 1) return fail(c, APIC_EINVAL, "checkpoint stride must be >= 1");
     if (c->n < 1) return fail(c, APIC_EINVAL, "the adjoint needs at least one particle");
@@ -652,6 +782,8 @@ apic_status step_adjoint_impl(apic_ctx *c, char *ck, int nsteps, int stride, dou
     auto snap_pos = [&](int k) { return ws + L.snap_pos + (size_t)k * L.snap_pos_bytes; };
     auto snap_perm = [&](int k) { return (int32_t *)(ws + L.snap_perm + (size_t)k * align256(4 * n)); };
     auto snap_E = [&](int k) { return (double *)(ws + L.snap_E + (size_t)k * align256(8 * (size_t)dim * G)); };
+    const size_t r = c->mixed ? 4 : 8;
+    auto snap_vel = [&](int k) { return ws + L.snap_vel + (size_t)k * align256(r * 3 * n); };
     // level T: only the objective depends on E^T
     hipLaunchKernelGGL(k_adj_scale, dim3(nblocks(dim * G)), dim3(kBlock), 0, s, (int64_t)dim * G,
                        (const double *)(ckp(C) + CL.E), lE, seed * c->dV);
@@ -669,6 +801,10 @@ apic_status step_adjoint_impl(apic_ctx *c, char *ck, int nsteps, int stride, dou
         for (int k = 0; k < m; ++k) {
             st = save_pos(c, pw, snap_pos(k), s);
             if (st != APIC_OK) return st;
+            if (c->g.hc) {
+                st = save_vel(c, pw, snap_vel(k), s);
+                if (st != APIC_OK) return st;
+            }
             HIPCHK(c, launch_copy_bytes(snap_E(k), E_w, 8 * (int64_t)dim * G, s));
             pw.perm = snap_perm(k);
             st = apic_step(c, &pw, nullptr, E_w, nullptr, 1, nullptr, ws_ctx, s);
@@ -703,6 +839,10 @@ apic_status step_adjoint_impl(apic_ctx *c, char *ck, int nsteps, int stride, dou
             P.lep_out = wsp<R>(ws, L.lam[cur ^ 1][1]);
             P.lv_out = wsp<R>(ws, L.lam[cur ^ 1][2]);
             P.init = (lvl - 1 == 0) ? 1 : 0;
+            if (c->g.hc) {
+                P.vprev = (const R *)snap_vel(k - 1);
+                P.Eprev = snap_E(k - 1);
+            }
             hipLaunchKernelGGL(k_adj_fill, dim3(nblocks(dim * G)), dim3(kBlock), 0, s, (int64_t)dim * G, lE);
             HIPCHK(c, hipGetLastError());
             st = launch_level<R>(c, P, s);
@@ -756,7 +896,7 @@ apic_status apic_import_state(apic_ctx *c, const double *x, const double *y, con
 
 apic_status apic_adjoint_sizes(const apic_ctx *c, int nsteps, int stride, size_t *ckpt_bytes, size_t *ws_bytes) {
     if (!c || nsteps < 0 || stride < 1) return APIC_EINVAL;
-    if (c->d.dim == 3 || c->g.hc) return APIC_EUNSUPPORTED;
+    if (c->d.dim == 3) return APIC_EUNSUPPORTED;
     const CkLayout CL = ck_layout(c);
     if (ckpt_bytes) *ckpt_bytes = CL.bytes * (size_t)(n_checkpoints(nsteps, stride) + 1);
     if (ws_bytes) *ws_bytes = adj_layout(c, stride).bytes;

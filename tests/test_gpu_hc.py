@@ -225,8 +225,89 @@ def test_hc_at_large_c_is_the_boris_path(torch, case):
             assert np.max(np.minimum(dd, L - dd)) <= 1e-11 * L, k
 
 
-def test_hc_adjoint_is_unsupported(torch):
-    from paper_2608_15249_amd.apic import ApicError
-    c, p = _ctx(torch, CASES[0], "fp64")
-    with pytest.raises(ApicError):
-        c.adjoint_sizes(4, 2)
+def _adj_case():
+    import dataclasses
+    w = dataclasses.replace(W.magnetized_2d3v(nx=16, ppc=32), mode=(1, 0))
+    return w, W.sample(w)
+
+
+def _gpu_grad(torch, w, state, nsteps, stride, precision, c=C_LIGHT):
+    from paper_2608_15249_amd.adjoint import FieldEnergyRun
+    x, y, vx, vy, vz = state
+    run = FieldEnergyRun(dim=2, vdim=3, nx=w.nx, ny=w.ny, lx=w.Lx, ly=w.Ly, dt=w.dt, n=len(x), nsteps=nsteps,
+                         stride=stride, bz=w.bz, precision=precision, pusher="hc", c_light=c)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    Wv = run.forward(*[dev(a) for a in (x, y, vx, vy, vz)])
+    g = run.backward()
+    run.sync()
+    return float(Wv.item()), [a.cpu().numpy() for a in g]
+
+
+def _oracle_grad(w, state, nsteps, c=C_LIGHT):
+    from oracle import adjoint as OA
+    x, y, vx, vy, vz = state
+    s = O.Setup(2, 3, w.nx, w.Lx, len(x), w.dt, ny=w.ny, Ly=w.Ly, bz=w.bz, pusher="hc", c=c)
+    Wv, lx, lv = OA.adjoint(s, O.State.from_arrays(x, vx, y, vy, vz), nsteps)
+    return Wv, lx + lv
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_hc_fp64_adjoint_matches_oracle_gradient(torch):
+    w, state = _adj_case()
+    Wg, gg = _gpu_grad(torch, w, state, 20, 6, "fp64")
+    Wo, go = _oracle_grad(w, state, 20)
+    assert abs(Wg / Wo - 1.0) < 1e-11, (Wg, Wo)
+    for k, (a, b) in enumerate(zip(gg, go)):
+        assert _rel(a, b) < 1e-9, (k, _rel(a, b))
+
+
+def test_hc_mixed_adjoint_matches_oracle_gradient(torch):
+    """binary32 forward and adjoint against the FP64 reference gradient (the
+    trajectories differ by binary32 rounding, as for Boris)."""
+    w, state = _adj_case()
+    Wg, gg = _gpu_grad(torch, w, state, 20, 6, "mixed")
+    Wo, go = _oracle_grad(w, state, 20)
+    assert abs(Wg / Wo - 1.0) < 1e-5, (Wg, Wo)
+    for k, (a, b) in enumerate(zip(gg, go)):
+        assert _rel(a, b) < 5e-5, (k, _rel(a, b))
+
+
+def test_hc_adjoint_does_not_depend_on_checkpoint_stride(torch):
+    w, state = _adj_case()
+    ref = None
+    for stride in (1, 7, 40):
+        _, g = _gpu_grad(torch, w, state, 15, stride, "fp64")
+        if ref is None:
+            ref = g
+            continue
+        for a, b in zip(g, ref):
+            assert _rel(a, b) < 1e-10, stride
+
+
+def test_hc_zero_and_one_step_adjoint(torch):
+    """0 steps: only the initial charge and the backward half push (whose
+    gradient in u is zero: E^0 does not depend on u^0); 1 step: the half push
+    inversion by time symmetry enters."""
+    w, state = _adj_case()
+    for nsteps in (0, 1):
+        Wg, gg = _gpu_grad(torch, w, state, nsteps, 3, "fp64")
+        Wo, go = _oracle_grad(w, state, nsteps)
+        assert abs(Wg / Wo - 1.0) < 1e-12
+        for a, b in zip(gg, go):
+            if np.any(b):
+                assert _rel(a, b) < 1e-10, nsteps
+            else:
+                assert np.max(np.abs(a)) == 0.0, nsteps
+
+
+def test_hc_adjoint_strongly_relativistic(torch):
+    """c = 0.8 v_th: gamma up to about 5 in the tails."""
+    w, state = _adj_case()
+    Wg, gg = _gpu_grad(torch, w, state, 10, 4, "fp64", c=0.8)
+    Wo, go = _oracle_grad(w, state, 10, c=0.8)
+    assert abs(Wg / Wo - 1.0) < 1e-11
+    for k, (a, b) in enumerate(zip(gg, go)):
+        assert _rel(a, b) < 1e-9, (k, _rel(a, b))
