@@ -65,6 +65,8 @@ def build(force: bool = True) -> str:
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
                                "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _SO)
+    from . import em
+    em.build(force)
     return _SO
 
 
