@@ -65,6 +65,15 @@ typedef enum {
                                 Needs vdim = 3                                 */
 } apic_pusher;
 
+/* Field model (the paper's D_Poisson or E_Maxwell). */
+typedef enum {
+    APIC_ELECTROSTATIC = 0,  /* periodic Poisson solve each step (apic_step)  */
+    APIC_ELECTROMAGNETIC = 1 /* Yee FDTD update with a charge-conserving
+                                current deposit (apic_em_step); FP64 2D3V,
+                                Boris, c_light > 0 with the Courant condition
+                                c dt sqrt(1/dx^2 + 1/dy^2) < 1              */
+} apic_field_model;
+
 typedef enum {
     APIC_FP64 = 0,  /* positions x,y in [0,L) and velocities as double          */
     APIC_MIXED = 1  /* cell index + binary32 in-cell offset, binary32 velocity,
@@ -99,7 +108,9 @@ typedef struct {
     double lz;            /* 3D: box length along z                             */
     int tile_z;           /* 3D: bucket tile size along z (0 = default)         */
     int pusher;           /* apic_pusher (0 = Boris)                            */
-    double c_light;       /* speed of light for APIC_HIGUERA_CARY (> 0)         */
+    double c_light;       /* speed of light (> 0) for APIC_HIGUERA_CARY and for
+                             APIC_ELECTROMAGNETIC                               */
+    int model;            /* apic_field_model (0 = electrostatic)               */
 } apic_grid_desc;
 
 /* Particle arrays (structure of arrays), all [dev], caller-owned, length n.
@@ -290,6 +301,57 @@ apic_status apic_adjoint_forward(apic_ctx *ctx, const apic_particles *p0, int ns
  * lam_vx, lam_vy, lam_vz [dev, n] (NULL beyond vdim) with respect to v^0. */
 apic_status apic_step_adjoint(apic_ctx *ctx, const void *ckpt, int nsteps, int stride, double seed, double *lam_x,
                               double *lam_y, double *lam_vx, double *lam_vy, double *lam_vz, void *ws, void *stream);
+
+/* ---- electromagnetic step --------------------------------------------------
+ * The paper lists B_Scatter of current densities and E_Maxwell
+ * ("finite-difference time-domain updates", citing Yee 1966) among its
+ * modules. A context created with model = APIC_ELECTROMAGNETIC runs the
+ * electromagnetic PIC cycle on the same sorted, tiled particle layout, in
+ * FP64, 2D3V, on a periodic Yee grid in normalised units eps0 = 1,
+ * mu0 = 1/c^2 (c = c_light):
+ *   - F [dev, double, 6*G] holds Ex, Ey, Ez, Bx, By, Bz, each [ny][nx], with
+ *     element [j][i] of Ex at ((i+1/2) dx, j dy), Ey at (i dx, (j+1/2) dy),
+ *     Ez at (i dx, j dy), Bx at (i dx, (j+1/2) dy), By at ((i+1/2) dx, j dy)
+ *     and Bz at ((i+1/2) dx, (j+1/2) dy); B includes the uniform bz (the grid
+ *     Bz starts at bz and the update keeps a uniform field);
+ *   - J [dev, double, 3*G]: Jx, Jy, Jz at the Ex, Ey, Ez locations;
+ *   - one step: E and B interpolated to x^n (linear weights on each
+ *     component's own staggered lattice), Boris v^{n-1/2} -> v^{n+1/2} in that
+ *     B, move with periodic wrap, the current J^{n+1/2} of the move by the
+ *     charge-conserving scheme of Esirkepov (2001) for the linear shape
+ *     (a displacement of a cell or more along an axis is an APIC_EDOMAIN
+ *     error), counting sort into the next bucket order, then
+ *     B^{n+1/2} = B^n - dt/2 curl E^n, E^{n+1} = E^n + dt (c^2 curl B^{n+1/2}
+ *     - J^{n+1/2}), B^{n+1} = B^{n+1/2} - dt/2 curl E^{n+1} (Yee leapfrog with
+ *     B also held at integer times).
+ * The discrete continuity equation holds for the CIC charge of the same
+ * particles, so a field that satisfies Gauss's law at the start keeps it.
+ * The electrostatic entry points (apic_step, apic_gather_push,
+ * apic_field_solve, the adjoint and the tuner) return APIC_EUNSUPPORTED on an
+ * electromagnetic context; apic_sort_by_cell and apic_deposit (charge) work
+ * as for an electrostatic one. */
+
+/* F^0: E as the staggered gradient -(phi(i+1) - phi(i))/d of the periodic
+ * Poisson potential of the particles' charge (5-point Laplacian, so the
+ * discrete Gauss law div E = rho holds), Ez = Bx = By = 0, Bz = bz. p sorted
+ * (bucket_start valid) or not; ws: the context workspace. */
+apic_status apic_em_init_fields(apic_ctx *ctx, const apic_particles *p, double *F, void *ws, void *stream);
+
+/* E and B gathered at each particle, Boris advance by dt_scale * dt (the
+ * initial backward half push uses -0.5), then the move when move != 0;
+ * in place, any order. */
+apic_status apic_em_gather_push(apic_ctx *ctx, apic_particles *p, const double *F, double dt_scale, int move,
+                                void *stream);
+
+/* nsteps electromagnetic cycles from (x^n, v^{n-1/2}, F^n); p sorted by
+ * bucket on entry and on exit (as apic_step), perm as apic_step. F is updated
+ * in place. J [dev, double, 3*G] or NULL: J^{n+1/2} of the last step.
+ * diag [dev, double, nsteps*4] or NULL: per step (W_B, W_E, kinetic energy,
+ * x-momentum) with W_B = c^2/2 dV sum |B - bz z|^2 and W_E = 1/2 dV sum |E|^2
+ * of F^{n+1}, the kinetic energy the mean over v^{n-1/2} and v^{n+1/2} as in
+ * apic_step. */
+apic_status apic_em_step(apic_ctx *ctx, apic_particles *p, double *F, double *J, int nsteps, double *diag,
+                         void *ws, void *stream);
 
 /* ---- batched replicas (a9) ------------------------------------------------
  * Many independent 1D1V periodic electrostatic plasmas ("replicas") with

@@ -19,6 +19,8 @@ APIC_FP64 = 0
 APIC_MIXED = 1
 APIC_BORIS = 0
 APIC_HIGUERA_CARY = 1
+APIC_ELECTROSTATIC = 0
+APIC_ELECTROMAGNETIC = 1
 
 _STATUS = {0: "APIC_OK", -1: "APIC_EINVAL", -2: "APIC_EHIP", -3: "APIC_ENOMEM", -4: "APIC_EOVERFLOW",
            -5: "APIC_EDOMAIN", -6: "APIC_EUNSUPPORTED"}
@@ -37,7 +39,7 @@ class GridDesc(ctypes.Structure):
                 ("bz", ctypes.c_double), ("prec", ctypes.c_int), ("frac_bits", ctypes.c_int),
                 ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int),
                 ("nz", ctypes.c_int), ("lz", ctypes.c_double), ("tile_z", ctypes.c_int),
-                ("pusher", ctypes.c_int), ("c_light", ctypes.c_double)]
+                ("pusher", ctypes.c_int), ("c_light", ctypes.c_double), ("model", ctypes.c_int)]
 
 
 class ParticlesC(ctypes.Structure):
@@ -62,7 +64,8 @@ EXPORTS = ["apic_create", "apic_destroy", "apic_workspace_size", "apic_num_bucke
            "apic_batch_create", "apic_batch_destroy", "apic_batch_sizes", "apic_batch_offsets",
            "apic_batch_work_items", "apic_batch_init", "apic_batch_step", "apic_batch_sync_status",
            "apic_batch_last_error", "apic_autotune_tiles", "apic_batch_autotune_chunk",
-           "apic_import_state", "apic_adjoint_sizes", "apic_adjoint_forward", "apic_step_adjoint"]
+           "apic_import_state", "apic_adjoint_sizes", "apic_adjoint_forward", "apic_step_adjoint",
+           "apic_em_init_fields", "apic_em_gather_push", "apic_em_step"]
 
 _lib = None
 
@@ -107,6 +110,9 @@ def load_library(path: str = LIB_PATH):
         "apic_adjoint_forward": ([vp, P(ParticlesC), cint, cint, vp, vp, vp, vp, vp], cint),
         "apic_step_adjoint": ([vp, vp, cint, cint, dbl, vp, vp, vp, vp, vp, vp, vp], cint),
         "apic_autotune_tiles": ([P(GridDesc), P(ParticlesC), cint, P(cint), P(cint), P(dbl), vp], cint),
+        "apic_em_init_fields": ([vp, P(ParticlesC), vp, vp, vp], cint),
+        "apic_em_gather_push": ([vp, P(ParticlesC), vp, dbl, cint, vp], cint),
+        "apic_em_step": ([vp, P(ParticlesC), vp, vp, cint, vp, vp, vp], cint),
         "apic_batch_autotune_chunk": ([P(ReplicaC), cint, dbl, dbl, dbl, P(BatchStateC), cint, P(cint), P(dbl), vp],
                                       cint),
     }
@@ -133,7 +139,7 @@ class Context:
 
     def __init__(self, *, dim, vdim, nx, ny, lx, ly, dt, n, qm=-1.0, q_macro=None, rho_ion=1.0, bz=0.0,
                  precision="mixed", frac_bits=0, tile=(0, 0), device="cuda", nz=1, lz=1.0, pusher="boris",
-                 c_light=0.0):
+                 c_light=0.0, model="es"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libapic needs a HIP GPU; none is visible")
@@ -148,7 +154,9 @@ class Context:
         self.desc = GridDesc(dim, vdim, nx, ny if dim >= 2 else 1, lx, ly if dim >= 2 else 1.0, dt, qm, q_macro,
                              rho_ion, bz, APIC_MIXED if self.mixed else APIC_FP64, frac_bits, tile[0], tile[1],
                              nz if dim == 3 else 1, lz if dim == 3 else 1.0, tz,
-                             APIC_HIGUERA_CARY if pusher == "hc" else APIC_BORIS, float(c_light))
+                             APIC_HIGUERA_CARY if pusher == "hc" else APIC_BORIS, float(c_light),
+                             APIC_ELECTROMAGNETIC if model == "em" else APIC_ELECTROSTATIC)
+        self.model = model
         self.pusher, self.c_light = pusher, float(c_light)
         self.n = int(n)
         h = ctypes.c_void_p()
@@ -249,6 +257,22 @@ class Context:
                                              ctypes.c_void_p(_ptr(lam_vx)), ctypes.c_void_p(_ptr(lam_vy)),
                                              ctypes.c_void_p(_ptr(lam_vz)), ctypes.c_void_p(ws.data_ptr()),
                                              _stream()))
+
+    def em_init_fields(self, parts: "Particles", F):
+        s = parts.struct(tiled=False)
+        self._check(self.L.apic_em_init_fields(self.h, ctypes.byref(s), ctypes.c_void_p(F.data_ptr()),
+                                               ctypes.c_void_p(self.ws.data_ptr()), _stream()))
+
+    def em_gather_push(self, parts: "Particles", F, dt_scale=1.0, move=True):
+        s = parts.struct(tiled=False)
+        self._check(self.L.apic_em_gather_push(self.h, ctypes.byref(s), ctypes.c_void_p(F.data_ptr()),
+                                               float(dt_scale), 1 if move else 0, _stream()))
+
+    def em_step(self, parts: "Particles", F, nsteps, diag=None, J=None, perm=None):
+        s = parts.struct(perm=perm)
+        self._check(self.L.apic_em_step(self.h, ctypes.byref(s), ctypes.c_void_p(F.data_ptr()),
+                                        ctypes.c_void_p(_ptr(J)), int(nsteps), ctypes.c_void_p(_ptr(diag)),
+                                        ctypes.c_void_p(self.ws.data_ptr()), _stream()))
 
     def step(self, parts: "Particles", E, E32, nsteps, diag=None, rho=None, perm=None):
         s = parts.struct(perm=perm)

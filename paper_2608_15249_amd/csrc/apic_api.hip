@@ -102,6 +102,7 @@ void layout(apic_ctx *c) {
     c->o_tot = take(4 * nb);
     c->o_deep = take(4 * nb * kDeepTab);
     c->o_acc = take(8 * G);
+    c->o_jacc = c->d.model == APIC_ELECTROMAGNETIC ? take(24 * G) : (size_t)-1;
     c->o_rho = take(8 * G);
     if (dim >= 2) {
         const int64_t H = (int64_t)(c->d.nx / 2 + 1) * c->d.ny * c->d.nz;
@@ -183,6 +184,9 @@ PushC push_coeffs(const apic_ctx *c, double dt_scale, int move) {
     pc.deep = 0.25f;
     pc.ic2 = c->g.hc ? 1.0 / (c->d.c_light * c->d.c_light) : 0.0;
     pc.ic2f = (float)pc.ic2;
+    pc.jx = -c->d.q_macro / (dy * c->d.dt);
+    pc.jy = -c->d.q_macro / (dx * c->d.dt);
+    pc.jz = c->d.q_macro / (dx * dy);
     return pc;
 }
 
@@ -279,6 +283,15 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     if (d.pusher != APIC_BORIS && d.pusher != APIC_HIGUERA_CARY) return APIC_EINVAL;
     if (d.pusher == APIC_HIGUERA_CARY && (d.vdim != 3 || !(d.c_light > 0) || !std::isfinite(d.c_light)))
         return APIC_EINVAL;
+    if (d.model != APIC_ELECTROSTATIC && d.model != APIC_ELECTROMAGNETIC) return APIC_EINVAL;
+    if (d.model == APIC_ELECTROMAGNETIC) {
+        if (d.dim != 2 || d.vdim != 3 || d.pusher != APIC_BORIS || !(d.c_light > 0) || !std::isfinite(d.c_light))
+            return APIC_EINVAL;
+        if (d.prec != APIC_FP64) return APIC_EUNSUPPORTED;
+        // Courant condition of the Yee update
+        const double dx = d.lx / d.nx, dy = d.ly / d.ny;
+        if (!(d.c_light * d.dt * std::sqrt(1.0 / (dx * dx) + 1.0 / (dy * dy)) < 1.0)) return APIC_EINVAL;
+    }
 
     apic_ctx *c = new (std::nothrow) apic_ctx();
     if (!c) return APIC_ENOMEM;
@@ -295,6 +308,11 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     c->d.nz = g.nz;
     int tsx, tsy, tsz;
     default_tiles(d, n_particles, tsx, tsy, tsz);
+    if (d.model == APIC_ELECTROMAGNETIC) {
+        // the six-component field tile and the current tile stay within LDS
+        tsx = std::min(tsx, 4);
+        tsy = std::min(tsy, 4);
+    }
     if (d.tile_x) tsx = ilog2_floor(d.tile_x);
     if (d.dim >= 2 && d.tile_y) tsy = ilog2_floor(d.tile_y);
     if (d.dim == 3 && d.tile_z) tsz = ilog2_floor(d.tile_z);
@@ -316,6 +334,11 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
         const int64_t e_bytes = ex * ey * ez * d.dim * (c->mixed ? 4 : 8);
         const int64_t a_bytes = (ex + 2) * (d.dim >= 2 ? ey + 2 : 1) * (d.dim == 3 ? ez + 2 : 1) * 8;
         if (e_bytes + a_bytes + 16 > 65536) { delete c; return APIC_EINVAL; }
+        if (d.model == APIC_ELECTROMAGNETIC) {
+            const int64_t tx = 1 << tsx, ty = 1 << tsy;
+            const int64_t em_bytes = 6 * (tx + 2) * (ty + 2) * 8 + 3 * (tx + 3) * (ty + 3) * 8;
+            if (em_bytes + 32 > 65536) { delete c; return APIC_EINVAL; }
+        }
     }
     g.tsx = tsx;
     g.tsy = tsy;
@@ -327,6 +350,7 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     g.halo = 1;
     g.np = (int)n_particles;
     g.hc = d.pusher == APIC_HIGUERA_CARY;
+    g.em = d.model == APIC_ELECTROMAGNETIC;
     g.S = d.frac_bits ? d.frac_bits : (d.dim == 1 ? 32 : d.dim == 2 ? 20 : 15);
     if (c->mixed && (g.S < 1 || g.S > 32 || (d.dim == 2 && g.S > 23) || (d.dim == 3 && g.S > 16))) {
         delete c;
@@ -491,6 +515,7 @@ apic_status apic_deposit(apic_ctx *c, const apic_particles *p, void *rho, void *
 apic_status apic_field_solve(apic_ctx *c, const void *rho, double *E, float *E32, double *we, void *ws,
                              void *stream) {
     if (!c) return APIC_EINVAL;
+    if (c->g.em) return fail(c, APIC_EUNSUPPORTED, "electromagnetic context: use apic_em_init_fields");
     if (!rho || !E || !ws) return fail(c, APIC_EINVAL, "rho, E and workspace are required");
     hipStream_t s = (hipStream_t)stream;
     // FP64 input already is rho; mixed input is the fixed-point node sums.
@@ -500,6 +525,7 @@ apic_status apic_field_solve(apic_ctx *c, const void *rho, double *E, float *E32
 apic_status apic_gather_push(apic_ctx *c, apic_particles *p, const void *E, double dt_scale, int move,
                              void *stream) {
     if (!c) return APIC_EINVAL;
+    if (c->g.em) return fail(c, APIC_EUNSUPPORTED, "electromagnetic context: use apic_em_gather_push");
     apic_status st = check_parts(c, p, false);
     if (st != APIC_OK) return st;
     if (!E) return fail(c, APIC_EINVAL, "E is NULL");
@@ -513,6 +539,7 @@ apic_status apic_gather_push(apic_ctx *c, apic_particles *p, const void *E, doub
 apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, float *E32, int nsteps, double *diag,
                       void *ws, void *stream) {
     if (!c) return APIC_EINVAL;
+    if (c->g.em) return fail(c, APIC_EUNSUPPORTED, "electromagnetic context: use apic_em_step");
     apic_status st = check_parts(c, p, true);
     if (st != APIC_OK) return st;
     if (!E || !ws || nsteps < 0) return fail(c, APIC_EINVAL, "E, workspace and nsteps >= 0 are required");

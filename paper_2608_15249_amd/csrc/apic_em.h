@@ -1,0 +1,165 @@
+// Device helpers of the electromagnetic 2D3V step on a periodic Yee grid
+// (FP64): the six-component field tile and its staggered gather, the Boris
+// advance in a general magnetic field, and the charge-conserving current
+// deposit of Esirkepov (2001) for the linear shape into an LDS tile.
+//
+// Yee staggering: element [j][i] of each component sits at
+//   Ex, Jx: ((i+1/2) dx, j dy)      Bx: (i dx, (j+1/2) dy)
+//   Ey, Jy: (i dx, (j+1/2) dy)      By: ((i+1/2) dx, j dy)
+//   Ez, Jz: (i dx, j dy)            Bz: ((i+1/2) dx, (j+1/2) dy)
+// Fields are [6][ny][nx] (Ex, Ey, Ez, Bx, By, Bz), currents [3][ny][nx].
+#pragma once
+
+#include "apic_device.h"
+
+namespace apic {
+namespace {
+
+// Field tile: the six components on nodes [x0-1, x0+T] x [y0-1, y0+T]
+// (fw x fh = (T+2)^2 entries each, periodic), component-major.
+__device__ void load_f_tile(double *sF, const double *F, const Geo &g, int x0, int y0, int fw, int fh) {
+    const int64_t G = (int64_t)g.nx * g.ny;
+    const int tot = fw * fh;
+    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+        const int lx = t % fw, ly = t / fw;
+        int gx = x0 - 1 + lx;
+        gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
+        int gy = y0 - 1 + ly;
+        gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
+        const int64_t gi = (int64_t)gy * g.nx + gx;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sF[c * tot + t] = F[c * G + gi];
+    }
+}
+
+// Linear interpolation of one staggered component from the tile: (bx, by)
+// the tile index of the lower node, (fx, fy) the fractions.
+__device__ __forceinline__ double lerp_tile(const double *f, int fw, int bx, int by, double fx, double fy) {
+    const int a = by * fw + bx;
+    return (1.0 - fx) * (1.0 - fy) * f[a] + fx * (1.0 - fy) * f[a + 1] + (1.0 - fx) * fy * f[a + fw] +
+           fx * fy * f[a + fw + 1];
+}
+
+// E and B at a particle in local cell (lx, ly) of the tile at fractions
+// (fx, fy). A component offset by half a cell along an axis uses the lower
+// node and fraction of the coordinate shifted back by half a cell.
+__device__ __forceinline__ void gather_em(const double *sF, int fw, int tot, int lx, int ly, double fx, double fy,
+                                          double e[3], double b[3]) {
+    const int ax0 = lx + 1, ay0 = ly + 1;                 // unshifted lattice
+    const bool hx = fx >= 0.5, hy = fy >= 0.5;
+    const int ax1 = hx ? lx + 1 : lx, ay1 = hy ? ly + 1 : ly;  // half-shifted lattice
+    const double fx1 = hx ? fx - 0.5 : fx + 0.5, fy1 = hy ? fy - 0.5 : fy + 0.5;
+    e[0] = lerp_tile(sF + 0 * tot, fw, ax1, ay0, fx1, fy);
+    e[1] = lerp_tile(sF + 1 * tot, fw, ax0, ay1, fx, fy1);
+    e[2] = lerp_tile(sF + 2 * tot, fw, ax0, ay0, fx, fy);
+    b[0] = lerp_tile(sF + 3 * tot, fw, ax0, ay1, fx, fy1);
+    b[1] = lerp_tile(sF + 4 * tot, fw, ax1, ay0, fx1, fy);
+    b[2] = lerp_tile(sF + 5 * tot, fw, ax1, ay1, fx1, fy1);
+}
+
+// Boris (1970) in a general B: a = (q/m) dt_eff / 2, t = a B,
+// s = 2 t / (1 + |t|^2), v- = v + a E, v' = v- + v- x t, v+ = v- + v' x s,
+// v = v+ + a E.
+__device__ __forceinline__ void boris3(double &vx, double &vy, double &vz, const double e[3], const double b[3],
+                                       double a) {
+    const double tx = a * b[0], ty = a * b[1], tz = a * b[2];
+    const double t2 = tx * tx + ty * ty + tz * tz;
+    const double sx = 2.0 * tx / (1.0 + t2), sy = 2.0 * ty / (1.0 + t2), sz = 2.0 * tz / (1.0 + t2);
+    const double mx = vx + a * e[0], my = vy + a * e[1], mz = vz + a * e[2];
+    const double qx = mx + (my * tz - mz * ty);
+    const double qy = my + (mz * tx - mx * tz);
+    const double qz = mz + (mx * ty - my * tx);
+    const double px = mx + (qy * sz - qz * sy);
+    const double py = my + (qz * sx - qx * sz);
+    const double pz = mz + (qx * sy - qy * sx);
+    vx = px + a * e[0];
+    vy = py + a * e[1];
+    vz = pz + a * e[2];
+}
+
+// Hat weights of one axis on a three-node window starting at node s0 of the
+// old cell (s0 = min(0, c1)): S0 of the old fraction f0, S1 after a move by d
+// cells (new cell c1 = floor(f0 + d) in {-1, 0, 1}). False when |d| >= 1.
+__device__ __forceinline__ bool hat3(double f0, double d, double S0[3], double DS[3], int &s0) {
+    const bool ok = fabs(d) < 1.0;
+    const double g1 = f0 + (ok ? d : 0.0);
+    const double fl = floor(g1);
+    const int c1 = (int)fl;
+    const double f1 = g1 - fl;
+    s0 = c1 < 0 ? -1 : 0;
+    double S1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int node = s0 + k;   // relative to the old cell
+        S0[k] = node == 0 ? 1.0 - f0 : (node == 1 ? f0 : 0.0);
+        S1[k] = node == c1 ? 1.0 - f1 : (node == c1 + 1 ? f1 : 0.0);
+        DS[k] = S1[k] - S0[k];
+    }
+    return ok;
+}
+
+// Esirkepov current of one particle into the LDS tile sJ (three components of
+// jw x jh entries, node (x0-1, y0-1) at index 0). (lx, ly): old local cell in
+// [0, T); (fx, fy): old fractions; (dx, dy): displacement in cells; cj:
+// (-Q/(dy dt), -Q/(dx dt), Q vz/(dx dy)). Returns false (and deposits
+// nothing) for a displacement of a cell or more.
+__device__ __forceinline__ bool esirkepov_lds(double *sJ, int jw, int jtot, int lx, int ly, double fx, double fy,
+                                              double dx, double dy, double cx, double cy, double cz) {
+    double S0x[3], DSx[3], S0y[3], DSy[3];
+    int sx, sy;
+    const bool okx = hat3(fx, dx, S0x, DSx, sx);
+    const bool oky = hat3(fy, dy, S0y, DSy, sy);
+    const bool ok = okx && oky;
+    if (!ok) return false;
+    const int bx = lx + 1 + sx, by = ly + 1 + sy;   // tile index of window node (0, 0)
+    double *jx = sJ, *jy = sJ + jtot, *jz = sJ + 2 * jtot;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const double wy = S0y[l] + 0.5 * DSy[l];
+        double run = 0.0;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            run += DSx[k] * wy;
+            atomicAdd(&jx[(by + l) * jw + bx + k], cx * run);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double wx = S0x[k] + 0.5 * DSx[k];
+        double run = 0.0;
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            run += DSy[l] * wx;
+            atomicAdd(&jy[(by + l) * jw + bx + k], cy * run);
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double wz = S0x[k] * S0y[l] + 0.5 * DSx[k] * S0y[l] + 0.5 * S0x[k] * DSy[l] +
+                              DSx[k] * DSy[l] / 3.0;
+            atomicAdd(&jz[(by + l) * jw + bx + k], cz * wz);
+        }
+    }
+    return true;
+}
+
+// Add the current tile to the global J (one atomic per non-zero entry).
+__device__ void flush_j(double *J, const double *sJ, const Geo &g, int x0, int y0, int jw, int jh) {
+    const int64_t G = (int64_t)g.nx * g.ny;
+    const int tot = jw * jh;
+    for (int t = threadIdx.x; t < 3 * tot; t += blockDim.x) {
+        const double v = sJ[t];
+        if (v == 0.0) continue;
+        const int c = t / tot, r = t % tot;
+        int gx = x0 - 1 + r % jw;
+        gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
+        int gy = y0 - 1 + r / jw;
+        gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
+        atomicAdd(&J[c * G + (int64_t)gy * g.nx + gx], v);
+    }
+}
+
+}  // namespace
+}  // namespace apic

@@ -1,0 +1,313 @@
+// Electromagnetic step (FP64, 2D3V, periodic Yee grid): the field kernels of
+// the finite-difference time-domain update (E_Maxwell, Yee 1966), the
+// initial field, the standalone gather + Boris, and the C-ABI entry points
+// apic_em_init_fields, apic_em_gather_push and apic_em_step. The particle
+// pass of the step is the fused count/push pair of apic_kernels.hip in its
+// electromagnetic form (staggered gather, Boris in the gathered B,
+// Esirkepov current deposit), on the same sorted, tiled particle layout.
+//
+// Cycle (normalised units eps0 = 1, mu0 = 1/c^2): gather E^n, B^n at x^n;
+// Boris v^{n-1/2} -> v^{n+1/2}; move; J^{n+1/2} of the move; then
+// B^{n+1/2} = B^n - dt/2 curl E^n, E^{n+1} = E^n + dt (c^2 curl B^{n+1/2} -
+// J^{n+1/2}), B^{n+1} = B^{n+1/2} - dt/2 curl E^{n+1}.
+#include "apic.h"
+#include "apic_ctx.h"
+#include "apic_em.h"
+
+#include <cmath>
+
+using namespace apic;
+using namespace apic_host;
+
+namespace apic {
+namespace {
+
+constexpr int kEmDiagBlocks = 512;   // partials per energy in part_spec (two halves)
+
+__device__ __forceinline__ int wrap_up(int i, int n) { return i + 1 == n ? 0 : i + 1; }
+__device__ __forceinline__ int wrap_dn(int i, int n) { return i == 0 ? n - 1 : i - 1; }
+
+__global__ void __launch_bounds__(kBlock) k_em_init(Geo g, const double *phi, double bz, double *F) {
+    const int64_t G = (int64_t)g.nx * g.ny;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G; i += (int64_t)gridDim.x * blockDim.x) {
+        const int ix = (int)(i % g.nx), iy = (int)(i / g.nx);
+        const double p = phi[i];
+        F[i] = -(phi[(int64_t)iy * g.nx + wrap_up(ix, g.nx)] - p) * g.inv_dx;
+        F[G + i] = -(phi[(int64_t)wrap_up(iy, g.ny) * g.nx + ix] - p) * g.inv_dy;
+        F[2 * G + i] = 0.0;
+        F[3 * G + i] = 0.0;
+        F[4 * G + i] = 0.0;
+        F[5 * G + i] = bz;
+    }
+}
+
+// Faraday on the B locations: Bx -= h dEz/dy, By += h dEz/dx,
+// Bz -= h (dEy/dx - dEx/dy) (forward differences). With diag, the per-block
+// partials of sum |E|^2 and sum |B - B0|^2 after the update.
+template <bool DIAG>
+__global__ void __launch_bounds__(kBlock) k_fdtd_b(Geo g, double *F, double h, double bz, double *part) {
+    const int64_t G = (int64_t)g.nx * g.ny;
+    double we = 0.0, wb = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G; i += (int64_t)gridDim.x * blockDim.x) {
+        const int ix = (int)(i % g.nx), iy = (int)(i / g.nx);
+        const int64_t xp = (int64_t)iy * g.nx + wrap_up(ix, g.nx), yp = (int64_t)wrap_up(iy, g.ny) * g.nx + ix;
+        const double ex = F[i], ey = F[G + i], ez = F[2 * G + i];
+        const double bx = F[3 * G + i] - h * ((F[2 * G + yp] - ez) * g.inv_dy);
+        const double by = F[4 * G + i] + h * ((F[2 * G + xp] - ez) * g.inv_dx);
+        const double bzn = F[5 * G + i] - h * ((F[G + xp] - ey) * g.inv_dx - (F[yp] - ex) * g.inv_dy);
+        F[3 * G + i] = bx;
+        F[4 * G + i] = by;
+        F[5 * G + i] = bzn;
+        if constexpr (DIAG) {
+            we += (ex * ex + ey * ey) + ez * ez;
+            wb += (bx * bx + by * by) + (bzn - bz) * (bzn - bz);
+        }
+    }
+    if constexpr (DIAG) {
+        __shared__ double sRed[kWaves];
+        const double a = block_sum(we, sRed), b = block_sum(wb, sRed);
+        if (threadIdx.x == 0) {
+            part[blockIdx.x] = a;
+            part[kEmDiagBlocks + blockIdx.x] = b;
+        }
+    }
+}
+
+// Ampere on the E locations: Ex += dt (c^2 dBz/dy - Jx),
+// Ey += dt (-c^2 dBz/dx - Jy), Ez += dt (c^2 (dBy/dx - dBx/dy) - Jz)
+// (backward differences); J is read, optionally copied out, and cleared.
+__global__ void __launch_bounds__(kBlock) k_fdtd_e(Geo g, double *F, double *J, double *Jout, double dt,
+                                                   double c2) {
+    const int64_t G = (int64_t)g.nx * g.ny;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G; i += (int64_t)gridDim.x * blockDim.x) {
+        const int ix = (int)(i % g.nx), iy = (int)(i / g.nx);
+        const int64_t xm = (int64_t)iy * g.nx + wrap_dn(ix, g.nx), ym = (int64_t)wrap_dn(iy, g.ny) * g.nx + ix;
+        const double jx = J[i], jy = J[G + i], jz = J[2 * G + i];
+        if (Jout) {
+            Jout[i] = jx;
+            Jout[G + i] = jy;
+            Jout[2 * G + i] = jz;
+        }
+        J[i] = 0.0;
+        J[G + i] = 0.0;
+        J[2 * G + i] = 0.0;
+        const double bz = F[5 * G + i], by = F[4 * G + i], bx = F[3 * G + i];
+        F[i] += dt * (c2 * ((bz - F[5 * G + ym]) * g.inv_dy) - jx);
+        F[G + i] += dt * (-c2 * ((bz - F[5 * G + xm]) * g.inv_dx) - jy);
+        F[2 * G + i] += dt * (c2 * ((by - F[4 * G + xm]) * g.inv_dx - (bx - F[3 * G + ym]) * g.inv_dy) - jz);
+    }
+}
+
+// diag[step] = (W_B, W_E, kinetic, momentum) from fixed-order sums of the
+// field partials and the push partials.
+__global__ void __launch_bounds__(1024) k_em_finalize(int nblk, int npush, double c2, double dV, double mass,
+                                                      double *diag, CtxDev c) {
+    __shared__ double sRed[16];
+    double we = 0.0, wb = 0.0, k = 0.0, p = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+        we += c.part_spec[i];
+        wb += c.part_spec[kEmDiagBlocks + i];
+    }
+    for (int i = threadIdx.x; i < npush; i += blockDim.x) {
+        k += c.part_push[2 * i];
+        p += c.part_push[2 * i + 1];
+    }
+    we = block_sum(we, sRed);
+    wb = block_sum(wb, sRed);
+    k = block_sum(k, sRed);
+    p = block_sum(p, sRed);
+    if (threadIdx.x == 0) {
+        double *d = step_slot(diag, c);
+        d[0] = 0.5 * c2 * dV * wb;
+        d[1] = 0.5 * dV * we;
+        d[2] = 0.5 * mass * k;
+        d[3] = mass * p;
+    }
+}
+
+// E, B at a particle from the global field: the tile gather's arithmetic with
+// global (periodic) node indices.
+__device__ __forceinline__ double lerp_glob(const double *f, const Geo &g, int i, int j, double fx, double fy) {
+    const int ip = wrap_up(i, g.nx), jp = wrap_up(j, g.ny);
+    const int64_t r0 = (int64_t)j * g.nx, r1 = (int64_t)jp * g.nx;
+    return (1.0 - fx) * (1.0 - fy) * f[r0 + i] + fx * (1.0 - fy) * f[r0 + ip] + (1.0 - fx) * fy * f[r1 + i] +
+           fx * fy * f[r1 + ip];
+}
+
+__global__ void __launch_bounds__(kBlock) k_em_gather_push(Geo g, Parts p, int64_t n, const double *F, PushC pc,
+                                                           CtxDev c) {
+    const int64_t G = (int64_t)g.nx * g.ny;
+    int bad = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        Pt<false> q;
+        bool ok = load_pt<false, 2, 3>(p, i, g, q);
+        const bool hx = q.fx >= 0.5, hy = q.fy >= 0.5;
+        const int ax1 = hx ? q.ix : wrap_dn(q.ix, g.nx), ay1 = hy ? q.iy : wrap_dn(q.iy, g.ny);
+        const double fx1 = hx ? q.fx - 0.5 : q.fx + 0.5, fy1 = hy ? q.fy - 0.5 : q.fy + 0.5;
+        double e[3], b[3];
+        e[0] = lerp_glob(F, g, ax1, q.iy, fx1, q.fy);
+        e[1] = lerp_glob(F + G, g, q.ix, ay1, q.fx, fy1);
+        e[2] = lerp_glob(F + 2 * G, g, q.ix, q.iy, q.fx, q.fy);
+        b[0] = lerp_glob(F + 3 * G, g, q.ix, ay1, q.fx, fy1);
+        b[1] = lerp_glob(F + 4 * G, g, ax1, q.iy, fx1, q.fy);
+        b[2] = lerp_glob(F + 5 * G, g, ax1, ay1, fx1, fy1);
+        boris3(q.vx, q.vy, q.vz, e, b, pc.a);
+        if (pc.move) {
+            int sx, sy, sz;
+            ok = move_pt<false, 2>(q, g, pc, sx, sy, sz) && ok;
+        }
+        if (!ok) bad = 1;
+        store_pt<false, 2, 3>(p, i, q);
+    }
+    if (bad) raise_err(c.err, ERR_DOMAIN);
+}
+
+inline int em_blocks(int64_t G, int cap) {
+    int64_t b = (G + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    return (int)(b > cap ? cap : b);
+}
+
+}  // namespace
+
+hipError_t launch_em_init(const Geo &g, const double *phi, double bz, double *F, hipStream_t s) {
+    hipLaunchKernelGGL(k_em_init, dim3(em_blocks((int64_t)g.nx * g.ny, 4096)), dim3(kBlock), 0, s, g, phi, bz, F);
+    return hipGetLastError();
+}
+
+hipError_t launch_em_gather_push(const Geo &g, const Parts &p, int64_t n, const double *F, const PushC &pc,
+                                 const CtxDev &c, hipStream_t s) {
+    hipLaunchKernelGGL(k_em_gather_push, dim3(em_blocks(n, 8192)), dim3(kBlock), 0, s, g, p, n, F, pc, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_fdtd_b(const Geo &g, double *F, double h, hipStream_t s) {
+    hipLaunchKernelGGL(k_fdtd_b<false>, dim3(em_blocks((int64_t)g.nx * g.ny, 4096)), dim3(kBlock), 0, s, g, F, h,
+                       0.0, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_fdtd_e(const Geo &g, double *F, double *J, double *Jout, double dt, double c2, hipStream_t s) {
+    hipLaunchKernelGGL(k_fdtd_e, dim3(em_blocks((int64_t)g.nx * g.ny, 4096)), dim3(kBlock), 0, s, g, F, J, Jout, dt,
+                       c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_fdtd_b_diag(const Geo &g, double *F, double h, double bz, double c2, double dV, double mass,
+                              int npush, double *diag, const CtxDev &c, hipStream_t s) {
+    const int nblk = em_blocks((int64_t)g.nx * g.ny, kEmDiagBlocks);
+    hipLaunchKernelGGL(k_fdtd_b<true>, dim3(nblk), dim3(kBlock), 0, s, g, F, h, bz, c.part_spec);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_em_finalize, dim3(1), dim3(1024), 0, s, nblk, npush, c2, dV, mass, diag, c);
+    return hipGetLastError();
+}
+
+static_assert(2 * kEmDiagBlocks <= kMaxSpecBlocks, "field partials fit part_spec");
+
+}  // namespace apic
+
+extern "C" {
+
+static apic_status check_em(apic_ctx *c) {
+    if (!c) return APIC_EINVAL;
+    if (!c->g.em) return fail(c, APIC_EINVAL, "the context is electrostatic (model = APIC_ELECTROSTATIC)");
+    return APIC_OK;
+}
+
+apic_status apic_em_init_fields(apic_ctx *c, const apic_particles *p, double *F, void *ws, void *stream) {
+    apic_status st = check_em(c);
+    if (st != APIC_OK) return st;
+    st = check_parts(c, p, false);
+    if (st != APIC_OK) return st;
+    if (!F || !ws) return fail(c, APIC_EINVAL, "F and workspace are required");
+    hipStream_t s = (hipStream_t)stream;
+    double *rho = wsp<double>(ws, c->o_acc);
+    double *phi = wsp<double>(ws, c->o_rho);
+    void *rhat = wsp<void>(ws, c->o_rhat);
+    void *phat = wsp<void>(ws, c->o_ehat);
+    st = apic_deposit(c, p, rho, stream);
+    if (st != APIC_OK) return st;
+    FFTCHK(c, hipfftSetStream(c->fwd, s));
+    FFTCHK(c, hipfftExecD2Z(c->fwd, (hipfftDoubleReal *)rho, (hipfftDoubleComplex *)rhat));
+    HIPCHK(c, launch_spectral(c->g, rhat, phat, c->dev, s));
+    FFTCHK(c, hipfftSetStream(c->inv, s));
+    FFTCHK(c, hipfftExecZ2D(c->inv, (hipfftDoubleComplex *)phat, (hipfftDoubleReal *)phi));
+    HIPCHK(c, launch_em_init(c->g, phi, c->d.bz, F, s));
+    return APIC_OK;
+}
+
+apic_status apic_em_gather_push(apic_ctx *c, apic_particles *p, const double *F, double dt_scale, int move,
+                                void *stream) {
+    apic_status st = check_em(c);
+    if (st != APIC_OK) return st;
+    st = check_parts(c, p, false);
+    if (st != APIC_OK) return st;
+    if (!F) return fail(c, APIC_EINVAL, "F is NULL");
+    if (!std::isfinite(dt_scale)) return fail(c, APIC_EINVAL, "dt_scale is not finite");
+    const PushC pc = push_coeffs(c, dt_scale, move);
+    HIPCHK(c, launch_em_gather_push(c->g, parts_of(p), c->n, F, pc, c->dev, (hipStream_t)stream));
+    return APIC_OK;
+}
+
+apic_status apic_em_step(apic_ctx *c, apic_particles *p, double *F, double *J, int nsteps, double *diag, void *ws,
+                         void *stream) {
+    apic_status st = check_em(c);
+    if (st != APIC_OK) return st;
+    st = check_parts(c, p, true);
+    if (st != APIC_OK) return st;
+    if (!F || !ws || nsteps < 0) return fail(c, APIC_EINVAL, "F, workspace and nsteps >= 0 are required");
+    if (nsteps == 0) return APIC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = c->g.nbuckets;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    int32_t *cnt = wsp<int32_t>(ws, c->o_cnt);
+    int32_t *offs = wsp<int32_t>(ws, c->o_offs);
+    int32_t *farcnt = wsp<int32_t>(ws, c->o_farcnt);
+    int32_t *tot = wsp<int32_t>(ws, c->o_tot);
+    int32_t *deep = wsp<int32_t>(ws, c->o_deep);
+    double *jacc = wsp<double>(ws, c->o_jacc);
+    Parts A = parts_of(p), B = parts_ws(c, ws);
+    int32_t *bsA = p->bucket_start, *bsB = wsp<int32_t>(ws, c->o_bstart);
+    const PushC pc = push_coeffs(c, 1.0, 1);
+    const double c2 = c->d.c_light * c->d.c_light, dt = c->d.dt;
+    HIPCHK(c, launch_fill_i32(farcnt, nb, 0, s));
+    HIPCHK(c, launch_fill_i32(tot, nb, 0, s));
+    HIPCHK(c, launch_fill_i32(deep, (int64_t)nb * kDeepTab, 0, s));
+    HIPCHK(c, launch_fill_u64((uint64_t *)jacc, 3 * G, 0, s));
+    HIPCHK(c, launch_set_step(c->dev.step, -1, s));
+    for (int k = 0; k < nsteps; ++k) {
+        const bool even = (k & 1) == 0;
+        const Parts &src = even ? A : B;
+        const Parts &dst = even ? B : A;
+        int32_t *bs_src = even ? bsA : bsB;
+        int32_t *bs_dst = even ? bsB : bsA;
+        const bool last = k == nsteps - 1;
+        hipEvent_t *ev = nullptr;
+        if (c->prof_used < c->prof_max) ev = &c->ev[5 * (size_t)c->prof_used++];
+        if (ev) HIPCHK(c, hipEventRecord(ev[0], s));
+        HIPCHK(c, launch_step_count(c->g, false, src, bs_src, F, pc, cnt, tot, farcnt, deep, c->dev, s));
+        if (ev) HIPCHK(c, hipEventRecord(ev[1], s));
+        HIPCHK(c, launch_scan_dir(c->g, tot, bs_dst, c->n, max_per_bucket(c), 1, c->dev, s));
+        HIPCHK(c, launch_dest_offsets(c->g, cnt, bs_dst, offs, s));
+        if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
+        HIPCHK(c, launch_step_push(c->g, false, src, dst, bs_src, bs_dst, cnt, offs, farcnt, F, pc, jacc, p->perm,
+                                   diag ? c->dev.part_push : nullptr, deep, c->dev, s));
+        if (ev) HIPCHK(c, hipEventRecord(ev[3], s));
+        HIPCHK(c, launch_fdtd_b(c->g, F, 0.5 * dt, s));
+        HIPCHK(c, launch_fdtd_e(c->g, F, jacc, (J && last) ? J : nullptr, dt, c2, s));
+        if (diag)
+            HIPCHK(c, launch_fdtd_b_diag(c->g, F, 0.5 * dt, c->d.bz, c2, c->dV, c->mass, nb, diag, c->dev, s));
+        else
+            HIPCHK(c, launch_fdtd_b(c->g, F, 0.5 * dt, s));
+        if (ev) HIPCHK(c, hipEventRecord(ev[4], s));
+    }
+    if (nsteps & 1) {
+        st = copy_parts(c, A, B, s);
+        if (st != APIC_OK) return st;
+        HIPCHK(c, launch_copy_bytes(bsA, bsB, 4 * (int64_t)(nb + 1), s));
+    }
+    return APIC_OK;
+}
+
+}  // extern "C"

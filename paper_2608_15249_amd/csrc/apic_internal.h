@@ -26,6 +26,7 @@ struct Geo {
     int S;                // fixed-point weight bits per axis (mixed path)
     int np;               // number of particles (bounds for bucket tables)
     int hc;               // velocity advance: 0 Boris, 1 Higuera-Cary (u = gamma v)
+    int em;               // field model: 0 electrostatic, 1 electromagnetic (Yee, FP64 2D3V)
     double lx, ly, lz;
     double inv_dx, inv_dy, inv_dz;
 };
@@ -41,6 +42,7 @@ struct PushC {
     float deep;           // slack (cells) that makes a staying particle "deep"
     double ic2;           // 1/c^2 (Higuera-Cary)
     float ic2f;
+    double jx, jy, jz;    // current deposit: -Q/(dy dt), -Q/(dx dt), Q/(dx dy) (electromagnetic step)
 };
 
 // One particle buffer set (structure of arrays).
@@ -142,5 +144,22 @@ hipError_t launch_finalize(int npush, int nspec, double mass, double dV, double 
 hipError_t launch_field1d(const Geo &g, bool mixed, void *acc, double scale, double add, double ion,
                           double dx, int clear, double *E, float *E32, double *we_out,
                           double *charge_out, int step_mode, const CtxDev &c, hipStream_t s);
+
+// ---- electromagnetic step (FP64 2D3V, Yee grid; F = [6][G], J = [3][G]) ----
+// F^0 from the potential phi [G]: (Ex, Ey) = -(forward differences of phi),
+// Ez = Bx = By = 0, Bz = bz
+hipError_t launch_em_init(const Geo &g, const double *phi, double bz, double *F, hipStream_t s);
+// gather E, B + Boris (+ move), in place (no ordering needed)
+hipError_t launch_em_gather_push(const Geo &g, const Parts &p, int64_t n, const double *F, const PushC &pc,
+                                 const CtxDev &c, hipStream_t s);
+// B -= h curl E
+hipError_t launch_fdtd_b(const Geo &g, double *F, double h, hipStream_t s);
+// E += dt (c^2 curl B - J), then J = 0 (Jout, when not NULL, receives J first)
+hipError_t launch_fdtd_e(const Geo &g, double *F, double *J, double *Jout, double dt, double c2, hipStream_t s);
+// B -= h curl E with the per-block partials of sum |E|^2 and sum |B - B0|^2,
+// then one workgroup writes diag[step] = (c^2/2 dV sum |B - B0|^2,
+// 1/2 dV sum |E|^2, kinetic, momentum) from them and the push partials
+hipError_t launch_fdtd_b_diag(const Geo &g, double *F, double h, double bz, double c2, double dV, double mass,
+                              int npush, double *diag, const CtxDev &c, hipStream_t s);
 
 }  // namespace apic

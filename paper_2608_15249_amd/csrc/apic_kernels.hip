@@ -31,6 +31,7 @@
 //  * This file is compiled with -ffp-contract=off: the count pass and the push
 //    pass must produce identical bits for the same particle.
 #include "apic_device.h"
+#include "apic_em.h"
 
 namespace apic {
 
@@ -203,6 +204,31 @@ __device__ __forceinline__ bool advance(Pt<MIX> &q, const Geo &g, const PushC &p
         gather_lds<R, DIM>(sE, ex_w, ex_w * ey_w, lx, ly, q.fx, q.fy, ex, ey);
     }
     return push_move<MIX, DIM, VDIM, HC>(q, g, pc, ex, ey, ez, true, sx, sy, sz) && in;
+}
+
+// Electromagnetic form (FP64, 2D3V): E and B gathered from the Yee field
+// tile (nodes from (x0-1, y0-1), width fw), Boris in B, move. (lx, ly) and
+// (fx0, fy0) return the old local cell and fractions for the current deposit.
+__device__ __forceinline__ bool advance_em(Pt<false> &q, const Geo &g, const PushC &pc, const double *sF, int fw,
+                                           int x0, int y0, int &lx, int &ly, int &sx, int &sy, double &fx0,
+                                           double &fy0) {
+    const int tx = 1 << g.tsx, ty = 1 << g.tsy;
+    lx = q.ix - x0;
+    ly = q.iy - y0;
+    const bool in = (unsigned)lx < (unsigned)tx && (unsigned)ly < (unsigned)ty;
+    if (!in) {
+        lx = min(max(lx, 0), tx - 1);
+        ly = min(max(ly, 0), ty - 1);
+        q.ix = x0 + lx;
+        q.iy = y0 + ly;
+    }
+    fx0 = q.fx;
+    fy0 = q.fy;
+    double e[3], b[3];
+    gather_em(sF, fw, fw * (ty + 2), lx, ly, q.fx, q.fy, e, b);
+    boris3(q.vx, q.vy, q.vz, e, b, pc.a);
+    int sz;
+    return move_pt<false, 2>(q, g, pc, sx, sy, sz) && in;
 }
 
 // Raw stored words of one particle: loaded unconditionally (the caller clamps
@@ -736,10 +762,12 @@ __device__ __forceinline__ int owned_by(int lo, int hi, int w) {
     auto f = [w](int x) { return (x / kBlock) * 64 + min(max((x % kBlock) - 64 * w, 0), 64); };
     return hi > lo ? f(hi) - f(lo) : 0;
 }
-template <bool MIX, int DIM, int VDIM, int U, bool HC>
+// EM: the electromagnetic form (FP64 2D3V): E is the [6][G] Yee field.
+template <bool MIX, int DIM, int VDIM, int U, bool HC, bool EM>
 __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int32_t *bstart, const double *E,
                                                        PushC pc, int32_t *cnt, int32_t *tot, int32_t *farcnt,
                                                        const int32_t *deep, CtxDev c) {
+    static_assert(!EM || (!MIX && DIM == 2 && VDIM == 3 && !HC), "the electromagnetic step is FP64 2D3V");
     using R = typename Pt<MIX>::R;
     constexpr int kDirs = Dir<DIM>::kN, kFar = Dir<DIM>::kFar, kStay = Dir<DIM>::kStay, kTab = Dir<DIM>::kTab;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -751,6 +779,7 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
     const uint64_t lt = lanemask_lt();
     const int ex_w = (1 << g.tsx) + 1, ey_w = (DIM >= 2) ? (1 << g.tsy) + 1 : 1;
     const int ez_w = (DIM == 3) ? (1 << g.tsz) + 1 : 1;
+    const int fw = EM ? (1 << g.tsx) + 2 : 0, fh = EM ? (1 << g.tsy) + 2 : 0;
     if (threadIdx.x == 0) sErr = 0;
     int first, end, stride;
     bucket_walk(g.nbuckets, first, end, stride);
@@ -760,7 +789,9 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
         const int x0 = bx << g.tsx, y0 = (DIM >= 2) ? (by << g.tsy) : 0, z0 = (DIM == 3) ? (bz << g.tsz) : 0;
         const TileNb tn = tile_nb<DIM>(g, bx, by, bz);
         if (threadIdx.x < kTab) sCnt[threadIdx.x] = 0;
-        if constexpr (DIM == 3)
+        if constexpr (EM)
+            load_f_tile((double *)smem, E, g, x0, y0, fw, fh);
+        else if constexpr (DIM == 3)
             load_e_tile3<R, double>(sE, E, g, x0, y0, z0, ex_w, ey_w, ez_w);
         else
             load_e_tile<R, double, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
@@ -768,14 +799,17 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
         const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
         const int span = i1 - i0;
         // field bound of the tile: per axis, or the in-plane |E| when the push
-        // rotates v about z
+        // rotates v about z, or |E| when the rotation axis is any (EM)
         {
             float e0 = 0.0f, e1 = 0.0f, e2 = 0.0f;
-            const int tn = ex_w * ey_w * ez_w;
+            const int tn = EM ? fw * fh : ex_w * ey_w * ez_w;
             for (int t = threadIdx.x; t < tn; t += blockDim.x) {
                 const float ex = fabsf((float)sE[t]);
                 const float ey = (DIM >= 2) ? fabsf((float)sE[tn + t]) : 0.0f;
-                if (pc.rot) {
+                if constexpr (EM) {
+                    const float ez = fabsf((float)sE[2 * tn + t]);
+                    e0 = fmaxf(e0, sqrtf(ex * ex + ey * ey + ez * ez));
+                } else if (pc.rot) {
                     e0 = fmaxf(e0, sqrtf(ex * ex + ey * ey));
                 } else {
                     e0 = fmaxf(e0, ex);
@@ -790,7 +824,7 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
             }
             if ((threadIdx.x & 63) == 0) {
                 sMax[w][0] = e0;
-                sMax[w][1] = pc.rot ? e0 : e1;
+                sMax[w][1] = (pc.rot || EM) ? e0 : e1;
                 sMax[w][2] = e2;
             }
         }
@@ -836,9 +870,14 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
                 load_raw<MIX, DIM, VDIM>(p, i0 + k, r1);
                 Pt<MIX> q;
                 bool good = decode<MIX, DIM, VDIM>(r1, g, q);
-                int lx, ly, lz, sx, sy, sz;
-                good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx, sy, sz) &&
-                       good;
+                int lx, ly, lz = 0, sx, sy, sz = 0;
+                if constexpr (EM) {
+                    double f0x, f0y;
+                    good = advance_em(q, g, pc, (const double *)smem, fw, x0, y0, lx, ly, sx, sy, f0x, f0y) && good;
+                } else {
+                    good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx, sy,
+                                                       sz) && good;
+                }
                 if (!good) atomicOr(&sErr, ERR_DOMAIN);
                 const int code = dir_local<DIM>(tn, lx + sx, ly + sy, lz + sz);
                 if (code < kFar) {
@@ -869,9 +908,15 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
                 if (act) {
                     Pt<MIX> q;
                     bool good = decode<MIX, DIM, VDIM>(r[j], g, q);
-                    int lx, ly, lz, sx, sy, sz;
-                    good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx, sy,
-                                                   sz) && good;
+                    int lx, ly, lz = 0, sx, sy, sz = 0;
+                    if constexpr (EM) {
+                        double f0x, f0y;
+                        good = advance_em(q, g, pc, (const double *)smem, fw, x0, y0, lx, ly, sx, sy, f0x, f0y) &&
+                               good;
+                    } else {
+                        good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx,
+                                                           sy, sz) && good;
+                    }
                     if (!good) atomicOr(&sErr, ERR_DOMAIN);
                     code = dir_local<DIM>(tn, lx + sx, ly + sy, lz + sz);
                     if (code == kFar) nbk = bucket_of<MIX, DIM>(g, q.ix, q.iy, q.iz);
@@ -953,7 +998,9 @@ __global__ void __launch_bounds__(kBlock) k_dest_offsets(Geo g, const int32_t *c
 // the deep table, so that the next count pass can credit those particles as
 // stays without reading them, as long as the field's share of the next move,
 // 2|a| max|E| dt/dx, stays below pc.deep.
-template <bool MIX, int DIM, int VDIM, int U, bool HC>
+// EM: the electromagnetic form (FP64 2D3V): E is the [6][G] Yee field and
+// acc the [3][G] current J^{n+1/2} (Esirkepov), accumulated with atomics.
+template <bool MIX, int DIM, int VDIM, int U, bool HC, bool EM>
 __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts dst, const int32_t *bstart,
                                                       const int32_t *bstart_new, const int32_t *cnt,
                                                       const int32_t *offs, int32_t *farcnt, const double *E, PushC pc,
@@ -976,8 +1023,13 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
     const int wy = (DIM >= 2) ? (1 << g.tsy) + 1 + 2 * g.halo : 1;
     const int wz = (DIM == 3) ? (1 << g.tsz) + 1 + 2 * g.halo : 1;
     const int wxy = wx * wy;
+    // EM: current tile jw x jh per component from node (x0-1, y0-1), then the
+    // six-component field tile fw x fh
+    const int jw = EM ? (1 << g.tsx) + 3 : 0, jh = EM ? (1 << g.tsy) + 3 : 0;
+    const int fw = EM ? (1 << g.tsx) + 2 : 0, fh = EM ? (1 << g.tsy) + 2 : 0;
+    const size_t acc_bytes = EM ? (size_t)3 * jw * jh * sizeof(double) : (size_t)wxy * wz * sizeof(A);
     A *sA = (A *)smem;
-    R *sE = (R *)(smem + (((size_t)wxy * wz * sizeof(A) + 15) & ~(size_t)15));
+    R *sE = (R *)(smem + ((acc_bytes + 15) & ~(size_t)15));
     const int w = threadIdx.x >> 6;
     const uint64_t lt = lanemask_lt();
     if (threadIdx.x == 0) sErr = 0;
@@ -988,7 +1040,10 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
         tile_coords<DIM>(g, b, bx, by, bz);
         const int x0 = bx << g.tsx, y0 = (DIM >= 2) ? (by << g.tsy) : 0, z0 = (DIM == 3) ? (bz << g.tsz) : 0;
         const TileNb tn = tile_nb<DIM>(g, bx, by, bz);
-        for (int t2 = threadIdx.x; t2 < wxy * wz; t2 += blockDim.x) sA[t2] = (A)0;
+        {
+            const int na = EM ? 3 * jw * jh : wxy * wz;
+            for (int t2 = threadIdx.x; t2 < na; t2 += blockDim.x) sA[t2] = (A)0;
+        }
         // first slot of each (wave, direction) tally of this bucket inside its
         // destination bucket (from the offsets pass), and each destination's end
         if (threadIdx.x < kTab) {
@@ -1004,7 +1059,9 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
             }
             sRun[threadIdx.x] = off;
         }
-        if constexpr (DIM == 3)
+        if constexpr (EM)
+            load_f_tile((double *)sE, E, g, x0, y0, fw, fh);
+        else if constexpr (DIM == 3)
             load_e_tile3<R, double>(sE, E, g, x0, y0, z0, ex_w, ey_w, ez_w);
         else
             load_e_tile<R, double, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
@@ -1069,9 +1126,14 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                 if (act) {
                     bool good = decode<MIX, DIM, VDIM>(r[j], g, q);
                     const double v2o = vsq<MIX, VDIM, HC>(q, pc);
-                    int lx, ly, lz, sx, sy, sz;
-                    good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx, sy,
-                                                   sz) && good;
+                    int lx, ly, lz = 0, sx, sy, sz = 0;
+                    double f0x = 0.0, f0y = 0.0;
+                    if constexpr (EM) {
+                        good = advance_em(q, g, pc, (const double *)sE, fw, x0, y0, lx, ly, sx, sy, f0x, f0y) && good;
+                    } else {
+                        good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx,
+                                                           sy, sz) && good;
+                    }
                     if (!good) atomicOr(&sErr, ERR_DOMAIN);
                     const double v2n = vsq<MIX, VDIM, HC>(q, pc);
                     ke += 0.5 * (v2o + v2n);
@@ -1088,7 +1150,12 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                             const float uy = (float)(q.iy - y0) + (float)q.fy;
                             const float my = fminf(uy, tye - uy) - pc.deep;
                             const float vy = fabsf((float)q.vy);
-                            if (!pc.rot) {
+                            if constexpr (EM) {
+                                // a general B can turn the whole speed along either axis
+                                const float vz = (float)q.vz;
+                                const float vv = sqrtf(vx * vx + vy * vy + vz * vz);
+                                deep = mx >= vv * pc.dtdx && my >= vv * pc.dtdy;
+                            } else if (!pc.rot) {
                                 deep = mx >= vx * pc.dtdx && my >= vy * pc.dtdy;
                             } else {
                                 // the rotation can turn the in-plane speed along either axis
@@ -1103,6 +1170,13 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                             }
                         }
                     }
+                    if constexpr (EM) {
+                        // current J^{n+1/2} of the move x^n -> x^{n+1} (Esirkepov)
+                        const double ddx = (q.vx * pc.dt) * g.inv_dx, ddy = (q.vy * pc.dt) * g.inv_dy;
+                        if (!esirkepov_lds((double *)sA, jw, jw * jh, lx, ly, f0x, f0y, ddx, ddy, pc.jx, pc.jy,
+                                           pc.jz * q.vz))
+                            atomicOr(&sErr, ERR_DOMAIN);
+                    } else {
                     // deposit rho^{n+1}: LDS tile + halo, global beyond it
                     A wgt[8];
                     dep_weights<MIX, DIM>(q, g, wgt);
@@ -1130,6 +1204,7 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                         deposit_global3<MIX>(acc, g, q.ix, q.iy, q.iz, wgt);
                     } else {
                         deposit_global<MIX, DIM>(acc, g, q.ix, q.iy, wgt);
+                    }
                     }
                 }
                 // slot: consecutive per (wave, direction) in the order the wave meets
@@ -1221,7 +1296,9 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
             deep_out[b * kDeepTab + 2 * t] = sFront0[t] - bstart_new[b];
             deep_out[b * kDeepTab + 2 * t + 1] = sRun[t * kDirs + kStay] - sFront0[t];
         }
-        if constexpr (DIM == 3)
+        if constexpr (EM)
+            flush_j((double *)acc, (const double *)sA, g, x0, y0, jw, jh);
+        else if constexpr (DIM == 3)
             flush_region3<MIX>(acc, sA, g, x0, y0, z0, wx, wy, wz, g.halo);
         else
             flush_region<MIX, DIM>(acc, sA, g, x0, y0, wx, wy, g.halo);
@@ -1412,6 +1489,15 @@ inline size_t tile_e_bytes(const Geo &g, bool mixed) {
     return (size_t)ex_w * ey_w * ez_w * g.dim * (mixed ? 4 : 8);
 }
 
+// electromagnetic step: six-component field tile ((T+2)^2 each) and the
+// three-component current tile ((T+3)^2 each), rounded to 16 bytes
+inline size_t em_f_tile_bytes(const Geo &g) {
+    return ((size_t)6 * ((1 << g.tsx) + 2) * ((1 << g.tsy) + 2) * sizeof(double) + 15) & ~(size_t)15;
+}
+inline size_t em_j_tile_bytes(const Geo &g) {
+    return ((size_t)3 * ((1 << g.tsx) + 3) * ((1 << g.tsy) + 3) * sizeof(double) + 15) & ~(size_t)15;
+}
+
 inline size_t tile_acc_bytes(const Geo &g, int halo) {
     const int wx = (1 << g.tsx) + 1 + 2 * halo;
     const int wy = (g.dim >= 2) ? (1 << g.tsy) + 1 + 2 * halo : 1;
@@ -1548,9 +1634,16 @@ int persistent_grid(K kernel, size_t shmem, int nbuckets) {
 hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int32_t *bstart, const double *E,
                              const PushC &pc, int32_t *cnt, int32_t *tot, int32_t *farcnt, const int32_t *deep,
                              const CtxDev &c, hipStream_t s) {
+    if (g.em) {
+        const size_t sh = em_f_tile_bytes(g);
+        auto kern = k_step_count<false, 2, 3, APIC_STEP_U, false, true>;
+        hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, p, bstart, E,
+                           pc, cnt, tot, farcnt, deep, c);
+        return hipGetLastError();
+    }
     size_t sh = tile_e_bytes(g, mixed);
     APIC_DISPATCH(g, mixed, {
-        auto kern = k_step_count<MIX, DIM, VDIM, U, HC>;
+        auto kern = k_step_count<MIX, DIM, VDIM, U, HC, false>;
         hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, p, bstart, E,
                            pc, cnt, tot, farcnt, deep, c);
     });
@@ -1580,9 +1673,16 @@ hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Pa
                             const int32_t *bstart_new, const int32_t *cnt, const int32_t *offs, int32_t *farcnt,
                             const double *E, const PushC &pc, void *acc, int32_t *perm, double *part, int32_t *deep,
                             const CtxDev &c, hipStream_t s) {
+    if (g.em) {
+        const size_t sh = em_j_tile_bytes(g) + em_f_tile_bytes(g);
+        auto kern = k_step_push<false, 2, 3, APIC_STEP_U, false, true>;
+        hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, src, dst,
+                           bstart, bstart_new, cnt, offs, farcnt, E, pc, (double *)acc, perm, part, deep, c);
+        return hipGetLastError();
+    }
     size_t sh = tile_acc_bytes(g, g.halo) + tile_e_bytes(g, mixed);
     APIC_DISPATCH(g, mixed, {
-        auto kern = k_step_push<MIX, DIM, VDIM, U, HC>;
+        auto kern = k_step_push<MIX, DIM, VDIM, U, HC, false>;
         hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, src, dst,
                            bstart, bstart_new, cnt, offs, farcnt, E, pc, (typename AccOf<MIX>::T *)acc, perm, part,
                            deep, c);

@@ -1,0 +1,239 @@
+"""GPU parity of the electromagnetic step (FP64 2D3V, periodic Yee grid)
+against the oracle, through the C ABI: initial field, gather + Boris, the
+current of one step (Esirkepov), the field update, several steps with the
+energy diagnostics, and the discrete Gauss law kept on the GPU."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import em as M
+from paper_2608_15249_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+C_LIGHT = 5.0
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_2608_15249_amd import apic
+    apic.load_library()
+    return t
+
+
+CASES = [
+    # nx, ny, lx, ly, n, tile, dt, bz
+    (37, 29, 37.0, 29.0 * 0.9, 30011, (8, 8), 0.1, 1.5),
+    (40, 24, 40.0 * 1.1, 24.0, 40003, (16, 16), 0.1, 0.0),
+]
+
+
+def _setup(case):
+    nx, ny, lx, ly, n, tile, dt, bz = case
+    return O.Setup(2, 3, nx, lx, n, dt, ny=ny, Ly=ly, bz=bz, c=C_LIGHT)
+
+
+def _ctx(torch, case):
+    from paper_2608_15249_amd.apic import Context, Particles
+    nx, ny, lx, ly, n, tile, dt, bz = case
+    c = Context(dim=2, vdim=3, nx=nx, ny=ny, lx=lx, ly=ly, dt=dt, n=n, bz=bz, precision="fp64", tile=tile,
+                c_light=C_LIGHT, model="em")
+    return c, Particles(c)
+
+
+def _state(rng, case):
+    nx, ny, lx, ly, n, tile, dt, bz = case
+    return (rng.uniform(0, lx, n), rng.uniform(0, ly, n), rng.normal(0, 1, n), rng.normal(0, 1, n),
+            rng.normal(0, 1, n))
+
+
+def _upload(p, st):
+    x, y, vx, vy, vz = st
+    p.upload(x=x, y=y, vx=vx, vy=vy, vz=vz)
+
+
+def _compose(ids, perm):
+    return ids[perm.cpu().numpy().astype(np.int64)]
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel()).cuda()
+
+
+def _pdist(a, b, L):
+    d = np.abs(a - b)
+    return np.minimum(d, L - d)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_initial_fields_match_oracle(torch, case):
+    rng = np.random.default_rng(71)
+    s = _setup(case)
+    st0 = _state(rng, case)
+    c, p = _ctx(torch, case)
+    _upload(p, st0)
+    F = torch.zeros(6 * c.G, dtype=torch.float64, device="cuda")
+    c.em_init_fields(p, F)
+    c.sync()
+    x, y, vx, vy, vz = st0
+    Fo = M.initial_fields(s, O.State.from_arrays(x, vx, y, vy, vz))
+    Fg = F.cpu().numpy().reshape(6, s.ny, s.nx)
+    scale = np.max(np.abs(Fo[:2]))
+    assert np.max(np.abs(Fg - Fo)) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("dt_scale,move", [(1.0, True), (-0.5, False)])
+def test_gather_push_matches_oracle(torch, case, dt_scale, move):
+    rng = np.random.default_rng(72)
+    s = _setup(case)
+    st0 = _state(rng, case)
+    F = rng.normal(size=(6, s.ny, s.nx))
+    F[5] += s.bz
+    c, p = _ctx(torch, case)
+    _upload(p, st0)
+    c.em_gather_push(p, _dev(torch, F), dt_scale=dt_scale, move=move)
+    c.sync()
+    d = p.download()
+    x, y, vx, vy, vz = st0
+    st = O.State.from_arrays(x, vx, y, vy, vz)
+    Ep, Bp = M.gather(s, st, F)
+    M.boris(s, st, Ep, Bp, dt_scale * s.dt)
+    if move:
+        O.move(s, st)
+    for k, ref in (("vx", st.vx), ("vy", st.vy), ("vz", st.vz)):
+        assert np.max(np.abs(d[k] - ref)) <= 1e-12, k
+    for k, ref, L in (("x", st.x, s.Lx), ("y", st.y, s.Ly)):
+        assert np.max(_pdist(d[k], ref, L)) <= 1e-12 * L, k
+
+
+def _start(torch, case, rng):
+    """Sorted GPU plasma with F^0 and the backward half push, and the oracle's
+    copy in the input order (ids maps GPU slots to input indices)."""
+    s = _setup(case)
+    st0 = _state(rng, case)
+    n = case[4]
+    c, p = _ctx(torch, case)
+    _upload(p, st0)
+    perm = torch.zeros(n, dtype=torch.int32, device="cuda")
+    c.sort_by_cell(p, perm=perm)
+    ids = _compose(np.arange(n), perm)
+    F = torch.zeros(6 * c.G, dtype=torch.float64, device="cuda")
+    c.em_init_fields(p, F)
+    c.em_gather_push(p, F, dt_scale=-0.5, move=False)
+    x, y, vx, vy, vz = st0
+    st = O.State.from_arrays(x, vx, y, vy, vz)
+    Fo = M.initialise(s, st)
+    return s, c, p, perm, ids, F, st, Fo
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_one_step_current_fields_and_particles(torch, case):
+    rng = np.random.default_rng(73)
+    s, c, p, perm, ids, F, st, Fo = _start(torch, case, rng)
+    J = torch.zeros(3 * c.G, dtype=torch.float64, device="cuda")
+    c.em_step(p, F, 1, J=J, perm=perm)
+    ids = _compose(ids, perm)
+    c.sync()
+    Jo, _ = M.step(s, st, Fo)
+    Jg = J.cpu().numpy().reshape(3, s.ny, s.nx)
+    assert np.max(np.abs(Jg - Jo)) <= 1e-12 * np.max(np.abs(Jo))
+    Fg = F.cpu().numpy().reshape(6, s.ny, s.nx)
+    assert np.max(np.abs(Fg[:3] - Fo[:3])) <= 1e-12 * np.max(np.abs(Fo[:3]))
+    assert np.max(np.abs(Fg[3:] - Fo[3:])) <= 1e-12 * max(1.0, np.max(np.abs(Fo[3:])))
+    d = p.download()
+    for k, ref in (("vx", st.vx), ("vy", st.vy), ("vz", st.vz)):
+        assert np.max(np.abs(d[k] - ref[ids])) <= 1e-12, k
+    for k, ref, L in (("x", st.x, s.Lx), ("y", st.y, s.Ly)):
+        assert np.max(_pdist(d[k], ref[ids], L)) <= 1e-12 * L, k
+    # the new order is the stable bucket order of the new positions
+    key = O.bucket_key(np.floor(d["x"] / s.dx).astype(np.int64) % s.nx, np.floor(d["y"] / s.dy).astype(np.int64) % s.ny,
+                       c.tile[0], c.tile[1], s.nx)
+    assert np.all(np.diff(key) >= 0)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_eight_steps_and_diagnostics_match_oracle(torch, case):
+    rng = np.random.default_rng(74)
+    s, c, p, perm, ids, F, st, Fo = _start(torch, case, rng)
+    nsteps = 8
+    diag = torch.zeros(4 * nsteps, dtype=torch.float64, device="cuda")
+    ref = []
+    for k in range(nsteps):
+        c.em_step(p, F, 1, diag=diag[4 * k:4 * k + 4], perm=perm)
+        ids = _compose(ids, perm)
+        _, ke = M.step(s, st, Fo)
+        ref.append(M.field_energies(s, Fo) + (ke,))
+    c.sync()
+    d = p.download()
+    for k, r in (("vx", st.vx), ("vy", st.vy), ("vz", st.vz)):
+        assert np.max(np.abs(d[k] - r[ids])) <= 1e-10, k
+    for k, r, L in (("x", st.x, s.Lx), ("y", st.y, s.Ly)):
+        assert np.max(_pdist(d[k], r[ids], L)) <= 1e-10 * L, k
+    Fg = F.cpu().numpy().reshape(6, s.ny, s.nx)
+    assert np.max(np.abs(Fg - Fo)) <= 1e-10 * max(1.0, np.max(np.abs(Fo)))
+    dg = diag.cpu().numpy().reshape(nsteps, 4)
+    ref = np.array(ref)
+    assert np.allclose(dg[:, 1], ref[:, 0], rtol=1e-9, atol=0)          # W_E
+    assert np.allclose(dg[:, 0], ref[:, 1], rtol=1e-8, atol=1e-300)     # W_B (starts at zero)
+    assert np.allclose(dg[:, 2], ref[:, 2], rtol=1e-12, atol=0)         # kinetic
+
+
+def test_gauss_law_and_div_b_are_kept_on_the_gpu(torch):
+    case = CASES[0]
+    rng = np.random.default_rng(75)
+    s, c, p, perm, ids, F, st, Fo = _start(torch, case, rng)
+    c.em_step(p, F, 20)
+    rho = torch.zeros(c.G, dtype=torch.float64, device="cuda")
+    c.deposit(p, rho, tiled=False)
+    c.sync()
+    Fg = F.cpu().numpy().reshape(6, s.ny, s.nx)
+    r = rho.cpu().numpy().reshape(s.ny, s.nx)
+    assert np.max(np.abs(M.divergence_e(s, Fg) - r)) <= 1e-11 * np.max(np.abs(r))
+    assert np.max(np.abs(M.divergence_b(s, Fg))) <= 1e-11 * max(1.0, np.max(np.abs(Fg[3:])))
+    assert np.max(np.abs(Fg[3:5])) > 1e-6
+
+
+def test_electromagnetic_context_checks(torch):
+    from paper_2608_15249_amd.apic import ApicError, Context
+    nx, ny = 16, 16
+    with pytest.raises(ApicError):       # Courant condition: 8 * 0.1 * sqrt(2) > 1
+        Context(dim=2, vdim=3, nx=nx, ny=ny, lx=16.0, ly=16.0, dt=0.1, n=100, precision="fp64", c_light=8.0,
+                model="em")
+    with pytest.raises(ApicError):       # binary32 form not built
+        Context(dim=2, vdim=3, nx=nx, ny=ny, lx=16.0, ly=16.0, dt=0.1, n=100, precision="mixed", c_light=5.0,
+                model="em")
+    with pytest.raises(ApicError):       # 2D3V only
+        Context(dim=2, vdim=2, nx=nx, ny=ny, lx=16.0, ly=16.0, dt=0.1, n=100, precision="fp64", c_light=5.0,
+                model="em")
+    c, p = _ctx(torch, CASES[0])
+    E = torch.zeros(2 * c.G, dtype=torch.float64, device="cuda")
+    with pytest.raises(ApicError):
+        c.gather_push(p, E)
+    with pytest.raises(ApicError):
+        c.step(p, E, None, 1)
+
+
+def test_a_move_of_a_cell_is_reported(torch):
+    """A particle displaced a cell or more in one step is outside the current
+    deposit's window: the step flags APIC_EDOMAIN (the host forces the
+    condition with one fast particle; every kernel exits normally)."""
+    from paper_2608_15249_amd.apic import ApicError
+    case = CASES[0]
+    rng = np.random.default_rng(76)
+    s = _setup(case)
+    x, y, vx, vy, vz = _state(rng, case)
+    vx[17] = 15.0                       # 1.5 cells per step
+    c, p = _ctx(torch, case)
+    _upload(p, (x, y, vx, vy, vz))
+    c.sort_by_cell(p)
+    F = torch.zeros(6 * c.G, dtype=torch.float64, device="cuda")
+    c.em_init_fields(p, F)
+    c.em_step(p, F, 1)
+    with pytest.raises(ApicError):
+        c.sync()
