@@ -143,6 +143,82 @@ def run_path(precision, w, state, steps, warmup, tile, torch, pusher="boris", c_
     return out
 
 
+def run_em(w, state, steps, warmup, tile, c_light, torch):
+    """Electromagnetic cycle (FP64 2D3V, Yee grid) on the plasma of w."""
+    from paper_2608_15249_amd.apic import Context, Particles
+    x, y, vx, vy, vz = state
+    n = len(x)
+    ctx = Context(dim=2, vdim=3, nx=w.nx, ny=w.ny, lx=w.Lx, ly=w.Ly, dt=w.dt, n=n, bz=w.bz, precision="fp64",
+                  tile=(0, 0) if tile in (None, "auto") else tile, c_light=c_light, model="em")
+    p = Particles(ctx)
+    p.upload(x=x, y=y, vx=vx, vy=vy, vz=vz)
+    ctx.sort_by_cell(p)
+    F = torch.zeros(6 * ctx.G, dtype=torch.float64, device="cuda")
+    ctx.em_init_fields(p, F)
+    ctx.em_gather_push(p, F, dt_scale=-0.5, move=False)
+    if warmup:
+        ctx.em_step(p, F, warmup)
+    ctx.sync()
+    diag = torch.zeros(steps * 4, dtype=torch.float64, device="cuda")
+    ctx.profile_enable(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.em_step(p, F, steps, diag=diag)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.sync()
+    ms, nprof = ctx.profile_read()
+    ctx.profile_enable(0)
+    elapsed = t1 - t0
+    sb = state_bytes("fp64", 2, 3)
+    push_ms = ms[2] / max(nprof, 1)
+    push_bytes = 2 * sb * n
+    achieved = push_bytes / (push_ms * 1e-3) / 1e9
+    d = diag.cpu().numpy().reshape(steps, 4)
+    out = {
+        "value": n * steps / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "hbm_gbs_step": (3 * sb * n * steps) / elapsed / 1e9,
+        "tile": list(ctx.tile),
+        "phase_ms_per_step": {"count": ms[0] / nprof, "scan": ms[1] / nprof, "push": push_ms,
+                              "field": ms[3] / nprof},
+        "particle_steps_s_by_phase": {"push": n / (push_ms * 1e-3),
+                                      "count+scan+push": n / ((ms[0] + ms[1] + ms[2]) / nprof * 1e-3)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_step_push, electromagnetic form (staggered gather+Boris+move+Esirkepov "
+                               "current+scatter)",
+                     "bytes_per_launch": push_bytes},
+        "final_W_B": float(d[-1, 0]),
+        "final_W_E": float(d[-1, 1]),
+        "final_KE": float(d[-1, 2]),
+    }
+    del ctx, p, F
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline_em(w, state, nsteps, c_light, max_particles=1 << 22):
+    """Serial FP64 electromagnetic oracle (host, one core) on a bounded sample
+    of the same plasma: the first max_particles particles of the state on the
+    full grid (the rate per particle-step is what is reported)."""
+    import oracle as O
+    from oracle import em as M
+    x, y, vx, vy, vz = (a[:max_particles] for a in state)
+    s = O.Setup(2, 3, w.nx, w.Lx, len(x), w.dt, ny=w.ny, Ly=w.Ly, bz=w.bz, c=c_light)
+    st = O.State.from_arrays(x, vx, y, vy, vz)
+    F = M.initialise(s, st)
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        M.step(s, st, F)
+    t1 = time.perf_counter()
+    return {"value": len(x) * nsteps / (t1 - t0), "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of the %d particles on the full %s grid, %d electromagnetic oracle steps (serial C "
+                      "particle loops + numpy Yee update, FP64), %.1f s" % (len(x), len(state[0]),
+                                                                             "x".join(str(v) for v in _grid(w)),
+                                                                             nsteps, t1 - t0)}
+
+
 def run_batch(reps, steps, warmup, chunk, torch):
     """The batched replicas: one graph-replayed persistent launch per step on
     torch's current stream, timed with HIP events on that stream."""
@@ -266,7 +342,11 @@ def main():
     ap.add_argument("--chunk", default="auto", help="batch work-item size, or auto (autotuner)")
     ap.add_argument("--pusher", default="boris", choices=("boris", "hc"),
                     help="velocity advance: Boris, or Higuera-Cary (relativistic, u = gamma v; 3V workloads)")
-    ap.add_argument("--c-light", type=float, default=8.0, help="speed of light for --pusher hc, in v_th units")
+    ap.add_argument("--c-light", type=float, default=None,
+                    help="speed of light in v_th units (--pusher hc: default 8; --model em: default 10)")
+    ap.add_argument("--model", default="es", choices=("es", "em"),
+                    help="field model: electrostatic (Poisson), or electromagnetic (Yee FDTD with Esirkepov "
+                         "current; FP64 2D3V, magnetized_2d3v)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (N=%d requested)" % args.gpus,
@@ -299,10 +379,34 @@ def main():
     w = getattr(W, args.workload)()
     state = W.sample3(w) if w.dim == 3 else W.sample(w)
     tile = parse_tile(args.tile)
+    if args.model == "em":
+        if w.dim != 2 or w.vdim != 3:
+            print("--model em needs a 2D3V workload (magnetized_2d3v)", file=sys.stderr)
+            sys.exit(2)
+        c_light = 10.0 if args.c_light is None else args.c_light
+        print("bench: %s, electromagnetic FP64 path, %d warmup + %d timed steps" % (args.workload, args.warmup,
+                                                                                   args.steps),
+              file=sys.stderr, flush=True)
+        r = run_em(w, state, args.steps, args.warmup, tile, c_light, torch)
+        copy_gbs = measure_copy_gbs(torch)
+        line = dict(common)
+        line.update({"value": r["value"], "ms_per_step": r["ms_per_step"], "dtype": "f64",
+                     "config": {"workload": WORKLOADS[args.workload] + "; electromagnetic (Yee FDTD, c=%g)" % c_light,
+                                "grid": _grid(w), "particles": w.n_particles, "tile": r["tile"], "precision": "fp64",
+                                "model": "electromagnetic"},
+                     "hbm_gbs_step": r["hbm_gbs_step"], "roofline": with_copy(r["roofline"], copy_gbs),
+                     "phase_ms_per_step": r["phase_ms_per_step"],
+                     "particle_steps_s_by_phase": r["particle_steps_s_by_phase"],
+                     "final_energies": {"W_B": r["final_W_B"], "W_E": r["final_W_E"], "KE": r["final_KE"]}})
+        if not args.no_cpu_baseline:
+            print("bench: cpu baseline (%d oracle steps)" % args.cpu_steps, file=sys.stderr, flush=True)
+            line["cpu_baseline"] = cpu_baseline_em(w, state, min(args.cpu_steps, 3), c_light)
+        print(json.dumps(line), flush=True)
+        return
     if args.pusher == "hc" and w.vdim != 3:
         print("--pusher hc needs a 3V workload (magnetized_2d3v or thermal_3d)", file=sys.stderr)
         sys.exit(2)
-    c_light = args.c_light if args.pusher == "hc" else 0.0
+    c_light = (8.0 if args.c_light is None else args.c_light) if args.pusher == "hc" else 0.0
     res = {}
     for path in args.paths.split(","):
         print("bench: %s, %s path, %d warmup + %d timed steps" % (args.workload, path, args.warmup, args.steps),
