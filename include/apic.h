@@ -111,6 +111,8 @@ typedef struct {
     double c_light;       /* speed of light (> 0) for APIC_HIGUERA_CARY and for
                              APIC_ELECTROMAGNETIC                               */
     int model;            /* apic_field_model (0 = electrostatic)               */
+    int walls_x;          /* 1: grounded absorbing walls at x = 0 and x = lx
+                             (2D electrostatic; see "walls" below); 0: periodic */
 } apic_grid_desc;
 
 /* Particle arrays (structure of arrays), all [dev], caller-owned, length n.
@@ -301,6 +303,34 @@ apic_status apic_adjoint_forward(apic_ctx *ctx, const apic_particles *p0, int ns
  * lam_vx, lam_vy, lam_vz [dev, n] (NULL beyond vdim) with respect to v^0. */
 apic_status apic_step_adjoint(apic_ctx *ctx, const void *ckpt, int nsteps, int stride, double seed, double *lam_x,
                               double *lam_y, double *lam_vx, double *lam_vy, double *lam_vz, void *ws, void *stream);
+
+/* ---- walls: non-periodic Poisson with absorbing walls -----------------------
+ * The paper's D_Poisson solves Poisson under general boundary conditions
+ * (through HYPRE). A 2D electrostatic context created with walls_x = 1 has
+ * grounded (phi = 0) walls at x = 0 and x = lx that absorb particles, and
+ * stays periodic in y:
+ *   - nodes X_i = i dx, i = 0..nx along x (dx = lx/nx); every grid array
+ *     (rho, E, the fixed-point sums) has rows of 2 nx entries: entries
+ *     0..nx are the physical nodes (0 and nx on the walls), the others the
+ *     odd mirror the solver uses, so arrays are [ny][2 nx] and the context's
+ *     G is 2 nx ny;
+ *   - the field solves -lap(phi) = rho on the interior nodes with phi = 0 on
+ *     the walls (5-point FD operator), exactly, as the periodic solve of the
+ *     odd extension of rho (a type-I sine transform along x); E is the
+ *     centred difference inside and the one-sided difference on the walls;
+ *   - a particle whose move takes it to x < 0 or x >= lx is absorbed: it gets
+ *     no slot in the next order, so apic_step leaves bucket_start[nb] (the
+ *     live count) below n and the entries beyond it unused; the diagnostics
+ *     then report charge = q_macro * live count, W_E = 1/2 dV sum w |E|^2
+ *     over the physical nodes with w = 1/2 on the wall nodes, and the
+ *     kinetic energy of every particle pushed in the step;
+ *   - the tile along x divides nx (the walls are tile edges); particles must
+ *     start inside [0, lx) (apic_sort_by_cell flags others with
+ *     APIC_EDOMAIN);
+ *   - the tiled forms of apic_deposit and apic_gather_push follow
+ *     bucket_start; their untiled forms treat all n entries as particles.
+ * 3D, 1D, the electromagnetic model, the adjoint and the tuner do not take
+ * walls (APIC_EUNSUPPORTED). */
 
 /* ---- electromagnetic step --------------------------------------------------
  * The paper lists B_Scatter of current densities and E_Maxwell

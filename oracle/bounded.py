@@ -169,9 +169,11 @@ class Plasma:
     v: list
     lost_left: int = 0
     lost_right: int = 0
+    ids: np.ndarray = None      # optional labels carried with the particles
 
     def copy(self):
-        return Plasma(self.x.copy(), self.y.copy(), [a.copy() for a in self.v], self.lost_left, self.lost_right)
+        return Plasma(self.x.copy(), self.y.copy(), [a.copy() for a in self.v], self.lost_left, self.lost_right,
+                      None if self.ids is None else self.ids.copy())
 
 
 def initialise(b: Box, p: Plasma):
@@ -197,5 +199,7 @@ def step(b: Box, p: Plasma, E):
     p.lost_right += int(right.sum())
     p.x, p.y = x[keep], y[keep]
     p.v = [a[keep] for a in p.v]
+    if p.ids is not None:
+        p.ids = p.ids[keep]
     rho = deposit(b, p.x, p.y)
     return solve_field(b, rho), rho, 0.5 * b.M * 0.5 * (v2_old + v2_new)

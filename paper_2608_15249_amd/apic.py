@@ -39,7 +39,8 @@ class GridDesc(ctypes.Structure):
                 ("bz", ctypes.c_double), ("prec", ctypes.c_int), ("frac_bits", ctypes.c_int),
                 ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int),
                 ("nz", ctypes.c_int), ("lz", ctypes.c_double), ("tile_z", ctypes.c_int),
-                ("pusher", ctypes.c_int), ("c_light", ctypes.c_double), ("model", ctypes.c_int)]
+                ("pusher", ctypes.c_int), ("c_light", ctypes.c_double), ("model", ctypes.c_int),
+                ("walls_x", ctypes.c_int)]
 
 
 class ParticlesC(ctypes.Structure):
@@ -139,7 +140,7 @@ class Context:
 
     def __init__(self, *, dim, vdim, nx, ny, lx, ly, dt, n, qm=-1.0, q_macro=None, rho_ion=1.0, bz=0.0,
                  precision="mixed", frac_bits=0, tile=(0, 0), device="cuda", nz=1, lz=1.0, pusher="boris",
-                 c_light=0.0, model="es"):
+                 c_light=0.0, model="es", walls=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libapic needs a HIP GPU; none is visible")
@@ -155,8 +156,9 @@ class Context:
                              rho_ion, bz, APIC_MIXED if self.mixed else APIC_FP64, frac_bits, tile[0], tile[1],
                              nz if dim == 3 else 1, lz if dim == 3 else 1.0, tz,
                              APIC_HIGUERA_CARY if pusher == "hc" else APIC_BORIS, float(c_light),
-                             APIC_ELECTROMAGNETIC if model == "em" else APIC_ELECTROSTATIC)
+                             APIC_ELECTROMAGNETIC if model == "em" else APIC_ELECTROSTATIC, 1 if walls else 0)
         self.model = model
+        self.walls = bool(walls)
         self.pusher, self.c_light = pusher, float(c_light)
         self.n = int(n)
         h = ctypes.c_void_p()
@@ -173,7 +175,9 @@ class Context:
         self.dim, self.vdim, self.nx = dim, vdim, nx
         self.ny = ny if dim >= 2 else 1
         self.nz = nz if dim == 3 else 1
-        self.G = self.nx * self.ny * self.nz
+        # grid arrays of a walls context are the odd extension along x (2 nx nodes per row)
+        self.nx_grid = 2 * nx if self.walls else nx
+        self.G = self.nx_grid * self.ny * self.nz
 
     def __del__(self):
         try:

@@ -757,6 +757,7 @@ apic_status launch_level(apic_ctx *c, AdjP<R> &P, hipStream_t s) {
 apic_status check_adj_args(apic_ctx *c, int nsteps, int stride) {
     if (c->d.dim == 3) return fail(c, APIC_EUNSUPPORTED, "the adjoint covers 1D and 2D plasmas");
     if (c->g.em) return fail(c, APIC_EUNSUPPORTED, "the adjoint covers the electrostatic step");
+    if (c->g.walls) return fail(c, APIC_EUNSUPPORTED, "the adjoint covers periodic plasmas (no absorbing walls)");
     if (nsteps < 0) return fail(c, APIC_EINVAL, "nsteps must be >= 0");
     if (stride < 1) return fail(c, APIC_EINVAL, "checkpoint stride must be >= 1");
     if (c->n < 1) return fail(c, APIC_EINVAL, "the adjoint needs at least one particle");
@@ -881,6 +882,7 @@ apic_status apic_import_state(apic_ctx *c, const double *x, const double *y, con
                               const double *vz, apic_particles *p, void *stream) {
     if (!c) return APIC_EINVAL;
     if (c->d.dim == 3) return fail(c, APIC_EUNSUPPORTED, "state import covers 1D and 2D plasmas");
+    if (c->g.walls) return fail(c, APIC_EUNSUPPORTED, "state import covers periodic plasmas");
     apic_status st = check_parts(c, p, false);
     if (st != APIC_OK) return st;
     if (!x || (c->d.dim == 2 && !y) || !vx || (c->d.vdim >= 2 && !vy) || (c->d.vdim >= 3 && !vz))
@@ -897,7 +899,7 @@ apic_status apic_import_state(apic_ctx *c, const double *x, const double *y, con
 
 apic_status apic_adjoint_sizes(const apic_ctx *c, int nsteps, int stride, size_t *ckpt_bytes, size_t *ws_bytes) {
     if (!c || nsteps < 0 || stride < 1) return APIC_EINVAL;
-    if (c->d.dim == 3 || c->g.em) return APIC_EUNSUPPORTED;
+    if (c->d.dim == 3 || c->g.em || c->g.walls) return APIC_EUNSUPPORTED;
     const CkLayout CL = ck_layout(c);
     if (ckpt_bytes) *ckpt_bytes = CL.bytes * (size_t)(n_checkpoints(nsteps, stride) + 1);
     if (ws_bytes) *ws_bytes = adj_layout(c, stride).bytes;

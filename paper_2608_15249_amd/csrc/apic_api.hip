@@ -209,7 +209,8 @@ int64_t max_per_bucket(const apic_ctx *c) {
 // the push-pass partials (npush buckets); otherwise we/charge are written
 // directly when non-NULL.
 apic_status field_from_acc(apic_ctx *c, void *acc, bool acc_is_rho, double *E, float *E32, double *diag,
-                           double *we, double *charge, int npush, int clear, void *ws, hipStream_t s) {
+                           double *we, double *charge, int npush, int clear, void *ws, hipStream_t s,
+                           const int32_t *nlive) {
     const double scale = acc_is_rho ? 1.0 : acc_scale(c);
     const double add = acc_is_rho ? 0.0 : c->d.rho_ion;
     const bool mixed_acc = c->mixed && !acc_is_rho;
@@ -225,11 +226,15 @@ apic_status field_from_acc(apic_ctx *c, void *acc, bool acc_is_rho, double *E, f
     double *rho = wsp<double>(ws, c->o_rho);
     void *rhat = wsp<void>(ws, c->o_rhat);
     char *ehat = wsp<char>(ws, c->o_ehat);
-    HIPCHK(c, launch_rho(c->g, mixed_acc, acc, rho, scale, add, clear, s));
+    if (c->g.walls)
+        HIPCHK(c, launch_rho_odd(c->g, mixed_acc, acc, rho, scale, add, clear, s));
+    else
+        HIPCHK(c, launch_rho(c->g, mixed_acc, acc, rho, scale, add, clear, s));
     FFTCHK(c, hipfftSetStream(c->fwd, s));
     FFTCHK(c, hipfftExecD2Z(c->fwd, (hipfftDoubleReal *)rho, (hipfftDoubleComplex *)rhat));
     HIPCHK(c, launch_spectral(c->g, rhat, ehat, c->dev, s));
-    const FinArgs fin{diag ? npush : 0, spectral_blocks(c->g), c->mass, c->dV, G, c->d.rho_ion, diag, we, charge};
+    const FinArgs fin{diag ? npush : 0, spectral_blocks(c->g), c->mass, c->dV, G, c->d.rho_ion, diag, we, charge,
+                      c->g.walls, c->d.q_macro, nlive};
     // phi into the rho buffer (rho is no longer needed), then E from phi
     FFTCHK(c, hipfftSetStream(c->inv, s));
     FFTCHK(c, hipfftExecZ2D(c->inv, (hipfftDoubleComplex *)ehat, (hipfftDoubleReal *)rho));
@@ -284,6 +289,11 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     if (d.pusher == APIC_HIGUERA_CARY && (d.vdim != 3 || !(d.c_light > 0) || !std::isfinite(d.c_light)))
         return APIC_EINVAL;
     if (d.model != APIC_ELECTROSTATIC && d.model != APIC_ELECTROMAGNETIC) return APIC_EINVAL;
+    if (d.walls_x != 0 && d.walls_x != 1) return APIC_EINVAL;
+    if (d.walls_x) {
+        if (d.dim != 2 || d.model != APIC_ELECTROSTATIC) return APIC_EUNSUPPORTED;
+        if (d.nx > 16384) return APIC_EINVAL;
+    }
     if (d.model == APIC_ELECTROMAGNETIC) {
         if (d.dim != 2 || d.vdim != 3 || d.pusher != APIC_BORIS || !(d.c_light > 0) || !std::isfinite(d.c_light))
             return APIC_EINVAL;
@@ -306,6 +316,15 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     g.nz = d.dim == 3 ? d.nz : 1;
     c->d.ny = g.ny;
     c->d.nz = g.nz;
+    // walls: every grid array is the odd extension along x (2 nx nodes over
+    // 2 lx); particles live in the first nx cells
+    g.walls = d.walls_x;
+    g.nxp = d.nx;
+    if (g.walls) {
+        g.nx = 2 * d.nx;
+        c->d.nx = g.nx;
+        c->d.lx = 2.0 * d.lx;
+    }
     int tsx, tsy, tsz;
     default_tiles(d, n_particles, tsx, tsy, tsz);
     if (d.model == APIC_ELECTROMAGNETIC) {
@@ -324,7 +343,10 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
         while (ts > 0 && (1 << ts) > n) --ts;
         return ts;
     };
-    tsx = fit(tsx, g.nx);
+    tsx = fit(tsx, g.nxp);
+    // walls: the wall is a tile edge (the deep classification measures the
+    // distance to the tile edges)
+    while (g.walls && tsx > 0 && g.nxp % (1 << tsx) != 0) --tsx;
     tsy = fit(tsy, g.ny);
     tsz = fit(tsz, g.nz);
     {
@@ -343,7 +365,7 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     g.tsx = tsx;
     g.tsy = tsy;
     g.tsz = tsz;
-    g.nbx = (g.nx + (1 << tsx) - 1) >> tsx;
+    g.nbx = g.walls ? g.nxp >> tsx : (g.nx + (1 << tsx) - 1) >> tsx;
     g.nby = d.dim >= 2 ? (g.ny + (1 << tsy) - 1) >> tsy : 1;
     g.nbz = d.dim == 3 ? (g.nz + (1 << tsz) - 1) >> tsz : 1;
     g.nbuckets = g.nbx * g.nby * g.nbz;
@@ -356,7 +378,7 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
         delete c;
         return APIC_EINVAL;
     }
-    g.lx = d.lx;
+    g.lx = c->d.lx;
     g.ly = d.dim >= 2 ? d.ly : 1.0;
     g.lz = d.dim == 3 ? d.lz : 1.0;
     const double dx = d.lx / d.nx, dy = d.dim >= 2 ? d.ly / d.ny : 1.0, dz = d.dim == 3 ? d.lz / d.nz : 1.0;
@@ -586,7 +608,8 @@ apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, floa
             else
                 HIPCHK(c, launch_rho(c->g, false, acc, (double *)rho, acc_scale(c), c->d.rho_ion, 0, s));
         }
-        st = field_from_acc(c, acc, false, E, last ? E32 : nullptr, diag, nullptr, nullptr, diag ? nb : 0, 1, ws, s);
+        st = field_from_acc(c, acc, false, E, last ? E32 : nullptr, diag, nullptr, nullptr, diag ? nb : 0, 1, ws, s,
+                            bs_dst + nb);
         if (st != APIC_OK) return st;
         if (ev) HIPCHK(c, hipEventRecord(ev[4], s));
     }

@@ -72,7 +72,8 @@ PushC push_coeffs(const apic_ctx *c, double dt_scale, int move);
 double acc_scale(const apic_ctx *c);
 int64_t max_per_bucket(const apic_ctx *c);
 apic_status field_from_acc(apic_ctx *c, void *acc, bool acc_is_rho, double *E, float *E32, double *diag,
-                           double *we, double *charge, int npush, int clear, void *ws, hipStream_t s);
+                           double *we, double *charge, int npush, int clear, void *ws, hipStream_t s,
+                           const int32_t *nlive = nullptr);
 apic_status copy_parts(apic_ctx *c, const Parts &dst, const Parts &src, hipStream_t s);
 
 }  // namespace apic_host

@@ -27,6 +27,9 @@ struct Geo {
     int np;               // number of particles (bounds for bucket tables)
     int hc;               // velocity advance: 0 Boris, 1 Higuera-Cary (u = gamma v)
     int em;               // field model: 0 electrostatic, 1 electromagnetic (Yee, FP64 2D3V)
+    int walls;            // grounded absorbing walls at x = 0 and x = lx/2 (2D): nx, lx are then those of the
+                          // odd extension (2 nxp nodes, length 2 Lx) and particles live in cells [0, nxp)
+    int nxp;              // physical cells along x (nx without walls)
     double lx, ly, lz;
     double inv_dx, inv_dy, inv_dz;
 };
@@ -72,6 +75,11 @@ struct FinArgs {
     int npush, nspec;
     double mass, dV, G, rho_ion;
     double *diag, *we, *charge;
+    // walls: W_E of the physical half of the odd extension (with half weight
+    // on the wall nodes) and the charge Q * (live particles) when nlive
+    int walls;
+    double q_macro;
+    const int32_t *nlive;
 };
 
 constexpr int kMaxSpecBlocks = 1024;
@@ -120,6 +128,7 @@ hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int
                              int32_t *farcnt, const int32_t *deep, const CtxDev &c, hipStream_t s);
 hipError_t launch_scan_dir(const Geo &g, int32_t *tot, int32_t *start, int64_t n, int64_t max_per_bucket,
                            int step_mode, const CtxDev &c, hipStream_t s);
+// (with walls the total may fall below n: absorbed particles leave the order)
 // first slot of every (source bucket, wave, direction) tally inside its
 // destination bucket: offs has the layout of cnt
 hipError_t launch_dest_offsets(const Geo &g, const int32_t *cnt, const int32_t *start, int32_t *offs,
@@ -132,6 +141,10 @@ hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Pa
 // field: accumulation buffer -> rho (FP64): rho = add + scale * acc
 hipError_t launch_rho(const Geo &g, bool mixed, void *acc, double *rho, double scale, double add,
                       int clear, hipStream_t s);
+// walls: rho of the odd extension along x: the physical interior nodes
+// (add + scale acc), zero on the wall nodes, the negated mirror beyond
+hipError_t launch_rho_odd(const Geo &g, bool mixed, void *acc, double *rho, double scale, double add, int clear,
+                          hipStream_t s);
 int spectral_blocks(const Geo &g);
 // phi_hat = rho_hat / K^2 (scaled for the inverse transform) and the field
 // energy partials; then E = -(centred difference of phi) in real space

@@ -379,14 +379,14 @@ __device__ int64_t block_exclusive_scan(const int32_t *vals, int32_t *out, int n
 // tot [nb] (summed by the count pass) is scanned into start (the next bucket
 // table) and cleared; the device step index advances when step_mode.
 __global__ void __launch_bounds__(1024) k_scan_tot(int32_t *tot, int32_t *start, int nb, int64_t n,
-                                                   int64_t max_per, int step_mode, CtxDev c) {
+                                                   int64_t max_per, int step_mode, int walls, CtxDev c) {
     __shared__ int64_t sh[32];
     int bad = 0;
     int64_t total = block_exclusive_scan(tot, start, nb, max_per, bad, sh);
     if (bad) raise_err(c.err, ERR_OVERFLOW);
     for (int b = threadIdx.x; b < nb; b += blockDim.x) tot[b] = 0;
     if (threadIdx.x == 0) {
-        if (total != n) raise_err(c.err, ERR_COUNT);
+        if (walls ? total > n : total != n) raise_err(c.err, ERR_COUNT);
         if (step_mode) *c.step = *c.step + 1;
     }
 }
@@ -411,7 +411,13 @@ __global__ void __launch_bounds__(kBlock) k_keys_init(Geo g, Parts p, int64_t n,
                                                       CtxDev c) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         Pt<MIX> q;
-        if (!load_pt<MIX, DIM, VDIM>(p, i, g, q)) raise_err(c.err, ERR_DOMAIN);
+        bool ok = load_pt<MIX, DIM, VDIM>(p, i, g, q);
+        if (g.walls && q.ix >= g.nxp) {
+            // outside the box between the walls
+            ok = false;
+            q.ix = 0;
+        }
+        if (!ok) raise_err(c.err, ERR_DOMAIN);
         keys[i] = bucket_of<MIX, DIM>(g, q.ix, q.iy, q.iz);
         idx[i] = (int32_t)i;
     }
@@ -879,6 +885,7 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
                                                        sz) && good;
                 }
                 if (!good) atomicOr(&sErr, ERR_DOMAIN);
+                if (g.walls && q.ix >= g.nxp) continue;   // absorbed by a wall: leaves the order
                 const int code = dir_local<DIM>(tn, lx + sx, ly + sy, lz + sz);
                 if (code < kFar) {
                     atomicAdd(&sCnt[((k % kBlock) >> 6) * kDirs + code], 1);
@@ -919,6 +926,7 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
                     }
                     if (!good) atomicOr(&sErr, ERR_DOMAIN);
                     code = dir_local<DIM>(tn, lx + sx, ly + sy, lz + sz);
+                    if (g.walls && q.ix >= g.nxp) code = -1;   // absorbed by a wall: leaves the order
                     if (code == kFar) nbk = bucket_of<MIX, DIM>(g, q.ix, q.iy, q.iz);
                 }
                 // lanes sharing a near code, from one ballot per code bit; the
@@ -1139,6 +1147,9 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                     ke += 0.5 * (v2o + v2n);
                     px += (double)q.vx;
                     code = dir_local<DIM>(tn, lx + sx, ly + sy, lz + sz);
+                    // absorbed by a wall: no deposit, no slot
+                    const bool dead = g.walls && q.ix >= g.nxp;
+                    if (dead) code = -1;
                     if (code == kFar) nbk = bucket_of<MIX, DIM>(g, q.ix, q.iy, q.iz);
                     if (code == kStay) {
                         const float ux = (float)(q.ix - x0) + (float)q.fx;
@@ -1170,7 +1181,8 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                             }
                         }
                     }
-                    if constexpr (EM) {
+                    if (dead) {
+                    } else if constexpr (EM) {
                         // current J^{n+1/2} of the move x^n -> x^{n+1} (Esirkepov)
                         const double ddx = (q.vx * pc.dt) * g.inv_dx, ddy = (q.vy * pc.dt) * g.inv_dy;
                         if (!esirkepov_lds((double *)sA, jw, jw * jh, lx, ly, f0x, f0y, ddx, ddy, pc.jx, pc.jy,
@@ -1253,8 +1265,8 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                     pq[j] = q;
                     pslot[j] = slot;
                     psrc[j] = i0 + k;
-                    pact[j] = act;
-                } else if (act) {
+                    pact[j] = act && code >= 0;
+                } else if (act && code >= 0) {
                     if (slot >= 0) {
                         store_pt<MIX, DIM, VDIM>(dst, slot, q);
                         if (perm) perm[slot] = i0 + k;
@@ -1332,6 +1344,34 @@ __global__ void __launch_bounds__(kBlock) k_rho(int64_t G, typename AccOf<MIX>::
     }
 }
 
+// Walls: rho of the odd extension along x (rows of nx = 2 nxp nodes): the
+// physical interior node i in (0, nxp) holds add + scale acc_i and its mirror
+// nx - i the negated value; the wall nodes 0 and nxp hold zero (phi is zero
+// there, so their charge does not enter the solve). One thread per
+// (physical node, row) writes both halves, so acc can be cleared in place.
+template <bool MIX>
+__global__ void __launch_bounds__(kBlock) k_rho_odd(Geo g, typename AccOf<MIX>::T *acc, double *rho, double scale,
+                                                    double add, int clear) {
+    const int half = g.nxp + 1;
+    const int64_t tot = (int64_t)half * g.ny;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int ix = (int)(t % half);
+        const int64_t row = (t / half) * g.nx;
+        typename AccOf<MIX>::T v = acc[row + ix];
+        double w;
+        if constexpr (MIX) w = (double)(int64_t)v;
+        else w = v;
+        const bool wall = ix == 0 || ix == g.nxp;
+        const double r = wall ? 0.0 : add + scale * w;
+        rho[row + ix] = r;
+        if (!wall) rho[row + g.nx - ix] = -r;
+        if (clear) {
+            acc[row + ix] = (typename AccOf<MIX>::T)0;
+            if (!wall) acc[row + g.nx - ix] = (typename AccOf<MIX>::T)0;
+        }
+    }
+}
+
 // Spectral Poisson + centred gradient on the half-spectrum [ny][nx/2+1]:
 //   phi_hat = rho_hat / K^2 (K^2 = modified wavenumber of the FD Laplacian,
 //   phi_hat(0) = 0), E_hat_d = -i kappa_d phi_hat with kappa = sin(k d)/d,
@@ -1361,6 +1401,11 @@ __device__ void finalize_block(const FinArgs &f, const CtxDev &c) {
         if (f.nspec) {
             double wE = 0.5 * f.dV / f.G * e;
             double q = f.dV * (*c.rho0 - f.G * f.rho_ion);
+            if (f.walls) {
+                // the physical half of the odd extension, wall nodes at half weight
+                wE = 0.5 * wE;
+                q = f.nlive ? f.q_macro * (double)*f.nlive : 0.0;
+            }
             if (d) {
                 d[0] = q;
                 d[1] = wE;
@@ -1653,7 +1698,7 @@ hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int
 hipError_t launch_scan_dir(const Geo &g, int32_t *tot, int32_t *start, int64_t n, int64_t max_per_bucket,
                            int step_mode, const CtxDev &c, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_tot, dim3(1), dim3(1024), 0, s, tot, start, g.nbuckets, n, max_per_bucket, step_mode,
-                       c);
+                       g.walls, c);
     return hipGetLastError();
 }
 
@@ -1699,6 +1744,17 @@ hipError_t launch_rho(const Geo &g, bool mixed, void *acc, double *rho, double s
                            clear);
     else
         hipLaunchKernelGGL(k_rho<false>, dim3(nb), dim3(kBlock), 0, s, G, (double *)acc, rho, scale, add, clear);
+    return hipGetLastError();
+}
+
+hipError_t launch_rho_odd(const Geo &g, bool mixed, void *acc, double *rho, double scale, double add, int clear,
+                          hipStream_t s) {
+    const int nb = blocks_for((int64_t)(g.nxp + 1) * g.ny, 2048);
+    if (mixed)
+        hipLaunchKernelGGL(k_rho_odd<true>, dim3(nb), dim3(kBlock), 0, s, g, (unsigned long long *)acc, rho, scale,
+                           add, clear);
+    else
+        hipLaunchKernelGGL(k_rho_odd<false>, dim3(nb), dim3(kBlock), 0, s, g, (double *)acc, rho, scale, add, clear);
     return hipGetLastError();
 }
 

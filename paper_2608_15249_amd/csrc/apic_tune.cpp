@@ -174,7 +174,7 @@ apic_status apic_autotune_tiles(const apic_grid_desc *desc, const apic_particles
                                 int *tile_y, double *ms_per_step, void *stream) {
     if (!desc || !p || !tile_x || !tile_y || nsteps <= 0 || p->n <= 0) return APIC_EINVAL;
     const apic_grid_desc &d = *desc;
-    if (d.dim == 3 || d.model == APIC_ELECTROMAGNETIC) return APIC_EUNSUPPORTED;
+    if (d.dim == 3 || d.model == APIC_ELECTROMAGNETIC || d.walls_x) return APIC_EUNSUPPORTED;
     if (d.prec == APIC_MIXED ? (!p->cell || !p->ox) : !p->x) return APIC_EINVAL;
     const int ny = d.dim == 2 ? d.ny : 1;
     const TileKey key{d.dim, d.vdim, d.nx, ny, (int)d.prec, floor_log2((double)p->n / ((double)d.nx * ny))};
