@@ -91,15 +91,16 @@ def with_copy(roof, copy_gbs):
     return roof
 
 
-def run_path(precision, w, state, steps, warmup, tile, torch, pusher="boris", c_light=0.0):
+def run_path(precision, w, state, steps, warmup, tile, torch, pusher="boris", c_light=0.0, walls=False):
     from paper_2608_15249_amd.sim import Simulation
-    sim = Simulation(w, precision, state=state, tile=tile, pusher=pusher, c_light=c_light)
+    sim = Simulation(w, precision, state=state, tile=tile, pusher=pusher, c_light=c_light, walls=walls)
     sim.initialise()
     sim.ctx.sync()
     if warmup:
         sim.run(warmup, diag=False)
     sim.ctx.sync()
     n = sim.n
+    n_start = int(sim.p.bucket_start[-1].item()) if walls else n
     diag = torch.zeros(steps * 4, dtype=torch.float64, device="cuda")
     sim.ctx.profile_enable(steps)
     torch.cuda.synchronize()
@@ -116,10 +117,17 @@ def run_path(precision, w, state, steps, warmup, tile, torch, pusher="boris", c_
     push_bytes = 2 * sb * n
     achieved = push_bytes / (push_ms * 1e-3) / 1e9
     # counters were taken for the Boris kernels only
-    traffic = load_traffic(precision, "%s_%d" % (w.name, w.nx), list(sim.tile)) if pusher == "boris" else None
+    traffic = load_traffic(precision, "%s_%d" % (w.name, w.nx), list(sim.tile)) \
+        if pusher == "boris" and not walls else None
     d = diag.cpu().numpy().reshape(steps, 4)
+    # particle pushes of the timed steps: with absorbing walls the count falls
+    # (diag charge = q_macro * live count after each step)
+    pushes = n * steps
+    if walls:
+        live = [int(round(v)) for v in d[:, 0] / sim.ctx.desc.q_macro]
+        pushes = n_start + sum(live[:-1])
     out = {
-        "value": n * steps / elapsed,
+        "value": pushes / elapsed,
         "ms_per_step": 1e3 * elapsed / steps,
         "hbm_gbs_step": (3 * sb * n * steps) / elapsed / 1e9,
         "tile": list(sim.tile),
@@ -138,6 +146,8 @@ def run_path(precision, w, state, steps, warmup, tile, torch, pusher="boris", c_
         "final_WE": float(d[-1, 1]),
         "charge": float(d[-1, 0]),
     }
+    if walls:
+        out["live_particles"] = {"start": n_start, "end": live[-1]}
     del sim
     torch.cuda.empty_cache()
     return out
@@ -217,6 +227,26 @@ def cpu_baseline_em(w, state, nsteps, c_light, max_particles=1 << 22):
                       "particle loops + numpy Yee update, FP64), %.1f s" % (len(x), len(state[0]),
                                                                              "x".join(str(v) for v in _grid(w)),
                                                                              nsteps, t1 - t0)}
+
+
+def cpu_baseline_walls(w, state, nsteps, max_particles=1 << 24):
+    """Serial FP64 oracle of the plasma between absorbing walls (host, numpy)
+    on a bounded sample: the first max_particles particles on the full grid."""
+    from oracle import bounded as B
+    x, y, vx, vy = (a[:max_particles] for a in state[:4])
+    b = B.Box(w.nx, w.Lx, w.ny, w.Ly, len(x), w.dt, bz=w.bz, vdim=2)
+    p = B.Plasma(x.copy(), y.copy(), [vx.copy(), vy.copy()])
+    E = B.initialise(b, p)
+    t0 = time.perf_counter()
+    pushes = 0
+    for _ in range(nsteps):
+        pushes += len(p.x)
+        E, _, _ = B.step(b, p, E)
+    t1 = time.perf_counter()
+    return {"value": pushes / (t1 - t0), "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of the %d particles on the full %s grid between the walls, %d oracle steps "
+                      "(numpy, FP64), %.1f s" % (len(x), len(state[0]), "x".join(str(v) for v in _grid(w)), nsteps,
+                                                 t1 - t0)}
 
 
 def run_batch(reps, steps, warmup, chunk, torch):
@@ -344,6 +374,8 @@ def main():
                     help="velocity advance: Boris, or Higuera-Cary (relativistic, u = gamma v; 3V workloads)")
     ap.add_argument("--c-light", type=float, default=None,
                     help="speed of light in v_th units (--pusher hc: default 8; --model em: default 10)")
+    ap.add_argument("--walls", action="store_true",
+                    help="grounded absorbing walls at x = 0 and x = Lx (2D electrostatic workloads)")
     ap.add_argument("--model", default="es", choices=("es", "em"),
                     help="field model: electrostatic (Poisson), or electromagnetic (Yee FDTD with Esirkepov "
                          "current; FP64 2D3V, magnetized_2d3v)")
@@ -403,6 +435,9 @@ def main():
             line["cpu_baseline"] = cpu_baseline_em(w, state, min(args.cpu_steps, 3), c_light)
         print(json.dumps(line), flush=True)
         return
+    if args.walls and (w.dim != 2 or args.pusher != "boris"):
+        print("--walls needs a 2D workload with the Boris advance", file=sys.stderr)
+        sys.exit(2)
     if args.pusher == "hc" and w.vdim != 3:
         print("--pusher hc needs a 3V workload (magnetized_2d3v or thermal_3d)", file=sys.stderr)
         sys.exit(2)
@@ -411,7 +446,7 @@ def main():
     for path in args.paths.split(","):
         print("bench: %s, %s path, %d warmup + %d timed steps" % (args.workload, path, args.warmup, args.steps),
               file=sys.stderr, flush=True)
-        res[path] = run_path(path, w, state, args.steps, args.warmup, tile, torch, args.pusher, c_light)
+        res[path] = run_path(path, w, state, args.steps, args.warmup, tile, torch, args.pusher, c_light, args.walls)
     copy_gbs = measure_copy_gbs(torch)
     head = res.get("mixed") or res[list(res)[0]]
     line = dict(common)
@@ -421,13 +456,16 @@ def main():
         "dtype": "f32+i64" if "mixed" in res else "f64",
         "config": {"workload": WORKLOADS[args.workload], "grid": _grid(w), "particles": w.n_particles,
                    "tile": head["tile"], "precision": "mixed" if "mixed" in res else "fp64",
-                   "pusher": "higuera-cary" if args.pusher == "hc" else "boris"},
+                   "pusher": "higuera-cary" if args.pusher == "hc" else "boris",
+                   "boundaries": "grounded absorbing walls in x" if args.walls else "periodic"},
         "hbm_gbs_step": head["hbm_gbs_step"],
         "roofline": with_copy(head["roofline"], copy_gbs),
         "phase_ms_per_step": head["phase_ms_per_step"],
         "particle_steps_s_by_phase": head["particle_steps_s_by_phase"],
         "tune_ms_per_step": head["tune_ms_per_step"],
     })
+    if "live_particles" in head:
+        line["live_particles"] = head["live_particles"]
     if "fp64" in res and "mixed" in res:
         f = res["fp64"]
         line["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "hbm_gbs_step": f["hbm_gbs_step"],
@@ -437,8 +475,11 @@ def main():
         line["mixed_over_fp64"] = head["value"] / f["value"]
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (%d oracle steps)" % args.cpu_steps, file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(w, state, args.cpu_steps, args.pusher,
-                                             c_light if args.pusher == "hc" else float("inf"))
+        if args.walls:
+            line["cpu_baseline"] = cpu_baseline_walls(w, state, min(args.cpu_steps, 6))
+        else:
+            line["cpu_baseline"] = cpu_baseline(w, state, args.cpu_steps, args.pusher,
+                                                c_light if args.pusher == "hc" else float("inf"))
     print(json.dumps(line), flush=True)
 
 

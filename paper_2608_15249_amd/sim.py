@@ -18,7 +18,8 @@ from .apic import Batch, Context, Particles
 
 class Simulation:
     def __init__(self, w: W.Workload, precision: str = "mixed", n: Optional[int] = None, state=None,
-                 tile=(0, 0), frac_bits: int = 0, device="cuda", pusher: str = "boris", c_light: float = 0.0):
+                 tile=(0, 0), frac_bits: int = 0, device="cuda", pusher: str = "boris", c_light: float = 0.0,
+                 walls: bool = False):
         import torch
         self.torch = torch
         self.w = w
@@ -27,10 +28,11 @@ class Simulation:
         self.n = len(state[0])
         mk = lambda t: Context(dim=w.dim, vdim=w.vdim, nx=w.nx, ny=w.ny, lx=w.Lx, ly=w.Ly, dt=w.dt, n=self.n,
                                bz=w.bz, precision=precision, frac_bits=frac_bits, tile=t, device=device,
-                               nz=w.nz, lz=w.Lz, pusher=pusher, c_light=c_light)
+                               nz=w.nz, lz=w.Lz, pusher=pusher, c_light=c_light, walls=walls)
         self.tune_ms = None
-        if tile == "auto" and w.dim == 3:
-            tile = (0, 0, 0)     # the tile autotuner covers 1D and 2D; 3D keeps the default tile
+        if tile == "auto" and (w.dim == 3 or walls):
+            # the tile autotuner covers periodic 1D and 2D plasmas; the others keep the default tile
+            tile = (0, 0, 0) if w.dim == 3 else (0, 0)
         if tile == "auto":
             # time the candidate tiles on this very state, then build the context with the pick
             ctx = mk((0, 0))
@@ -91,8 +93,12 @@ class Simulation:
         e = self.E.cpu().numpy()
         if self.w.dim == 1:
             return (e[:G].copy(),)
-        sh = (self.w.nz, self.w.ny, self.w.nx) if self.w.dim == 3 else (self.w.ny, self.w.nx)
-        return tuple(e[k * G:(k + 1) * G].reshape(sh).copy() for k in range(self.w.dim))
+        sh = (self.w.nz, self.w.ny, self.w.nx) if self.w.dim == 3 else (self.w.ny, self.ctx.nx_grid)
+        out = tuple(e[k * G:(k + 1) * G].reshape(sh).copy() for k in range(self.w.dim))
+        if self.ctx.walls:
+            # the physical nodes 0..nx of the odd extension
+            out = tuple(a[:, :self.w.nx + 1].copy() for a in out)
+        return out
 
     def state(self):
         """Host copy: dict of arrays in the device order (positions in FP64
