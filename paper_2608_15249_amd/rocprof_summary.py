@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 result databases (kernel trace and PMC counters).
 
 Usage:
-  python -m paper_2608_15249_amd.rocprof_summary trace <results.db> [--cmd "..."]
+  python -m paper_2608_15249_amd.rocprof_summary trace <results.db> [--cmd "..."] [--last N]
   python -m paper_2608_15249_amd.rocprof_summary traffic <fetch.db> <write.db> \
         --kernel k_step --copy-bytes N [--cmd "..."] [--tag mixed] \
         [--merge-into profiles/step_push_<workload>_traffic.json --tile 8x8 --main k_step_push]
@@ -26,7 +26,7 @@ import re
 import sqlite3
 
 _CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
-KERNEL_SOURCES = ("apic_kernels.hip", "apic_device.h", "apic_internal.h")
+KERNEL_SOURCES = ("apic_kernels.hip", "apic_device.h", "apic_internal.h", "apic_em.h")
 
 
 def kernel_source_sha() -> str:
@@ -44,10 +44,18 @@ def _short(name: str) -> str:
     return (m.group(1) + (m.group(2) or "")) if m else n[:60]
 
 
-def kernel_stats(db: str):
+def kernel_stats(db: str, last: int = 0):
+    """(kernel, calls, avg_us, total_ms, avg_us of the last `last` dispatches
+    by start time or None), sorted by total time."""
     con = sqlite3.connect(db)
-    rows = con.execute("select name, count(*), avg(end-start), sum(end-start) from kernels group by name").fetchall()
-    out = [(_short(n), c, a / 1e3, s / 1e6) for n, c, a, s in rows]
+    rows = con.execute("select name, start, end from kernels order by start").fetchall()
+    per = collections.defaultdict(list)
+    for n, st, en in rows:
+        per[_short(n)].append((en - st) / 1e3)
+    out = []
+    for n, d in per.items():
+        tail = d[-last:] if last and len(d) >= last else None
+        out.append((n, len(d), sum(d) / len(d), sum(d) / 1e3, None if tail is None else sum(tail) / len(tail)))
     out.sort(key=lambda r: -r[3])
     return out
 
@@ -74,6 +82,8 @@ def main():
     t = sub.add_parser("trace")
     t.add_argument("db")
     t.add_argument("--cmd", default="")
+    t.add_argument("--last", type=int, default=0,
+                   help="also average the last N dispatches of each kernel (the timed steps of a run)")
     f = sub.add_parser("traffic")
     f.add_argument("fetch_db")
     f.add_argument("write_db")
@@ -88,9 +98,15 @@ def main():
     if a.cmd_name == "trace":
         if a.cmd:
             print("command: %s" % a.cmd)
-        print("%-46s %7s %12s %12s" % ("kernel", "calls", "avg_us", "total_ms"))
-        for n, c, avg, tot in kernel_stats(a.db):
-            print("%-46s %7d %12.2f %12.3f" % (n[:46], c, avg, tot))
+        head = "%-46s %7s %12s %12s" % ("kernel", "calls", "avg_us", "total_ms")
+        if a.last:
+            head += " %14s" % ("avg_last%d_us" % a.last)
+        print(head)
+        for n, c, avg, tot, tail in kernel_stats(a.db, a.last):
+            line = "%-46s %7d %12.2f %12.3f" % (n[:46], c, avg, tot)
+            if a.last:
+                line += " %14s" % ("" if tail is None else "%.2f" % tail)
+            print(line)
         return
     fe = pmc_per_dispatch(a.fetch_db, "FETCH_SIZE")
     wr = pmc_per_dispatch(a.write_db, "WRITE_SIZE")
