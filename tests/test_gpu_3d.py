@@ -380,31 +380,43 @@ def test_mixed_local_field_energy_error_3d(torch):
 
 def test_full_size_3d_sampled(torch):
     """The benchmarked 3D plasma at full size (128^3 cells, 16,777,216
-    electrons, default 8^3 tiles): after initialisation and 3 mixed steps,
-    one more step with the permutation recorded; sampled particles equal the
-    oracle's binary32 push of their pre-step state, every particle sits in the
-    bucket the table says, and the deposited charge is exact."""
+    electrons, default 8^3 tiles), from the seeded host state: the GPU runs
+    the field of the initial charge, the backward half push and one step with
+    the permutations recorded; sampled particles equal the oracle's binary32
+    half push and push of their initial state in the oracle's field of the
+    initial charge (its own quantised deposit and FFT solve), every particle
+    sits in the bucket the table says, and the deposited charge is exact."""
     from paper_2608_15249_amd.sim import Simulation
     w = W.thermal_3d()
-    sim = Simulation(w, "mixed")
-    sim.initialise()
-    sim.run(3, diag=False)
-    c = sim.ctx
-    c.sync()
-    before = sim.p.download()
-    E32 = sim.E.cpu().numpy().astype(np.float32).reshape(3, w.nz, w.ny, w.nx)
-    n = sim.n
-    perm = torch.zeros(n, dtype=torch.int32, device="cuda")
+    x, y, z, vx, vy, vz = W.sample3(w)
+    n = len(x)
+    sim = Simulation(w, "mixed", state=(x, y, z, vx, vy, vz))
+    c, p = sim.ctx, sim.p
+    perm0 = torch.zeros(n, dtype=torch.int32, device="cuda")
+    c.sort_by_cell(p, perm=perm0)
+    c.deposit(p, sim.rho)
+    c.field_solve(sim.rho, sim.E, sim.E32, sim.we0)
+    c.gather_push(p, sim.E32, dt_scale=-0.5, move=False)
+    perm1 = torch.zeros(n, dtype=torch.int32, device="cuda")
     Iout = torch.zeros(c.G, dtype=torch.int64, device="cuda")
-    c.step(sim.p, sim.E, sim.E32, 1, None, rho=Iout, perm=perm)
+    c.step(p, sim.E, sim.E32, 1, None, rho=Iout, perm=perm1)
     c.sync()
-    after = sim.p.download()
-    pm = perm.cpu().numpy().astype(np.int64)
+    ids = perm0.cpu().numpy().astype(np.int64)[perm1.cpu().numpy().astype(np.int64)]
+    after = p.download()
+    S = c.frac_bits
+    s = O.Setup(3, 3, w.nx, w.Lx, n, w.dt, ny=w.ny, Ly=w.Ly, nz=w.nz, Lz=w.Lz)
+    cx, ox = W.to_cell_offset(x, w.dx, w.nx)
+    cy, oy = W.to_cell_offset(y, w.dy, w.ny)
+    cz, oz = W.to_cell_offset(z, w.dz, w.nz)
+    I0 = O.deposit_quantised(s, cx, ox, S, cy, oy, cz, oz)
+    E32 = tuple(e.astype(np.float32) for e in O.solve_field(s, O.rho_from_quantised(s, I0, S)))
     rng = np.random.default_rng(5)
     idx = rng.choice(n, 4096, replace=False)
-    m0 = _mstate({k: (v[pm[idx]] if v is not None and k != "bucket_start" else v) for k, v in before.items()})
-    ref = OM.push(m0, tuple(E32), dim=3, vdim=3, nx=w.nx, ny=w.ny, dx=w.dx, dy=w.dy, qm=-1.0, dt=w.dt, bz=0.0,
-                  nz=w.nz, dz=w.dz)
+    src = ids[idx]
+    m0 = {"ix": cx[src], "iy": cy[src], "iz": cz[src], "ox": ox[src], "oy": oy[src], "oz": oz[src],
+          "vx": vx[src].astype(np.float32), "vy": vy[src].astype(np.float32), "vz": vz[src].astype(np.float32)}
+    kw = dict(dim=3, vdim=3, nx=w.nx, ny=w.ny, dx=w.dx, dy=w.dy, qm=-1.0, dt=w.dt, bz=0.0, nz=w.nz, dz=w.dz)
+    ref = OM.push(OM.push(m0, E32, dt_scale=-0.5, move=False, **kw), E32, **kw)
     m1 = _mstate({k: (v[idx] if v is not None and k != "bucket_start" else v) for k, v in after.items()})
     for k in ("ix", "iy", "iz", "ox", "oy", "oz", "vx", "vy", "vz"):
         assert np.array_equal(m1[k], ref[k]), k
@@ -417,4 +429,4 @@ def test_full_size_3d_sampled(torch):
     # 32-bit halves of the node sums separately, then combine exactly
     I = Iout.cpu().numpy()
     total = (int((I >> 32).sum()) << 32) + int((I & 0xFFFFFFFF).sum())
-    assert total == n << (3 * c.frac_bits)
+    assert total == n << (3 * S)

@@ -1,0 +1,182 @@
+"""Full-size parity checks in the launch configuration the benchmark times
+(the autotuned tile in 2D, the default tile otherwise), from the seeded host
+state: the GPU runs the field of the initial charge, the backward half push
+and one step; 4096 sampled particles are compared with the oracle applied to
+their initial state in the oracle's own field of the initial charge, and
+properties that hold at any size are checked on the whole plasma (every
+particle in the bucket the table says, the exact fixed-point charge).
+
+The oracle's field comes from its own quantised deposit (bit-identical to
+the GPU's by construction of the fixed-point scheme) and its numpy FFT solve;
+binary32 rounding of that field equals the GPU's except when an FP64 value
+sits within rounding noise of a binary32 boundary (about 1e-9 per value)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import bounded as B
+from oracle import mixed as OM
+from paper_2608_15249_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_2608_15249_amd import apic
+    apic.load_library()
+    return t
+
+
+def _mixed_cells(w, x, y, z=None):
+    ix, ox = W.to_cell_offset(x, w.dx, w.nx)
+    iy, oy = W.to_cell_offset(y, w.dy, w.ny)
+    m = {"ix": ix, "iy": iy, "ox": ox, "oy": oy}
+    if z is not None:
+        m["iz"], m["oz"] = W.to_cell_offset(z, w.dz, w.nz)
+    return m
+
+
+def _exact_total(I):
+    # the total can exceed int64 (N 2^(S dim)): sum 32-bit halves separately
+    return (int((I >> 32).sum()) << 32) + int((I & 0xFFFFFFFF).sum())
+
+
+def _gpu_init_and_step(torch, sim, walls=False):
+    """Initial sort (perm0), field, half push, one step (perm1). Returns
+    (input index of each final slot, fixed-point sums of the step, live count)."""
+    c, p = sim.ctx, sim.p
+    n = sim.n
+    perm0 = torch.zeros(n, dtype=torch.int32, device="cuda")
+    c.sort_by_cell(p, perm=perm0)
+    c.deposit(p, sim.rho)
+    c.field_solve(sim.rho, sim.E, sim.E32, sim.we0)
+    c.gather_push(p, sim.E32 if sim.mixed else sim.E, dt_scale=-0.5, move=False)
+    perm1 = torch.zeros(n, dtype=torch.int32, device="cuda")
+    Iout = torch.zeros(c.G, dtype=torch.int64 if sim.mixed else torch.float64, device="cuda")
+    c.step(p, sim.E, sim.E32, 1, None, rho=Iout, perm=perm1)
+    c.sync()
+    nlive = int(p.bucket_start[-1].item())
+    ids = perm0.cpu().numpy().astype(np.int64)[perm1.cpu().numpy().astype(np.int64)[:nlive]]
+    return ids, Iout.cpu().numpy(), nlive
+
+
+def _check_buckets(d, w, tile, nlive):
+    ix, iy = W.unpack_cell(d["cell"][:nlive], 2)
+    key = O.bucket_key(ix, iy, tile[0], tile[1], w.nx)
+    bs = d["bucket_start"].astype(np.int64)
+    assert bs[0] == 0 and bs[-1] == nlive and np.all(np.diff(bs) >= 0)
+    assert np.array_equal(np.repeat(np.arange(len(bs) - 1), np.diff(bs)), key)
+
+
+@pytest.mark.parametrize("name,pusher", [("thermal_2d", "boris"), ("magnetized_2d3v", "boris"),
+                                         ("magnetized_2d3v", "hc")])
+def test_full_size_mixed_2d_sampled(torch, name, pusher):
+    from paper_2608_15249_amd.sim import Simulation
+    w = getattr(W, name)()
+    c_light = 8.0 if pusher == "hc" else 0.0
+    state = W.sample(w)
+    x, y, vx, vy, vz = state
+    n = len(x)
+    sim = Simulation(w, "mixed", state=state, tile="auto" if pusher == "boris" else (16, 16), pusher=pusher,
+                     c_light=c_light)
+    ids, I, nlive = _gpu_init_and_step(torch, sim)
+    d = sim.p.download()
+    S = sim.ctx.frac_bits
+    s = O.Setup(2, w.vdim, w.nx, w.Lx, n, w.dt, ny=w.ny, Ly=w.Ly, bz=w.bz)
+    m = _mixed_cells(w, x, y)
+    I0 = O.deposit_quantised(s, m["ix"], m["ox"], S, m["iy"], m["oy"])
+    E32 = tuple(e.astype(np.float32) for e in O.solve_field(s, O.rho_from_quantised(s, I0, S)))
+    rng = np.random.default_rng(101)
+    idx = rng.choice(n, 4096, replace=False)
+    src = ids[idx]
+    m0 = {k: v[src] for k, v in m.items()}
+    m0["vx"], m0["vy"] = vx[src].astype(np.float32), vy[src].astype(np.float32)
+    if w.vdim == 3:
+        m0["vz"] = vz[src].astype(np.float32)
+    kw = dict(dim=2, vdim=w.vdim, nx=w.nx, ny=w.ny, dx=w.dx, dy=w.dy, qm=-1.0, dt=w.dt, bz=w.bz, pusher=pusher,
+              c=c_light if pusher == "hc" else float("inf"))
+    half = OM.push(m0, E32, dt_scale=-0.5, move=False, **kw)
+    ref = OM.push(half, E32, **kw)
+    ix, iy = W.unpack_cell(d["cell"][idx], 2)
+    got = {"ix": ix, "iy": iy, "ox": d["ox"][idx], "oy": d["oy"][idx], "vx": d["vx"][idx], "vy": d["vy"][idx]}
+    if w.vdim == 3:
+        got["vz"] = d["vz"][idx]
+    for k in got:
+        assert np.array_equal(got[k], ref[k]), k
+    assert nlive == n
+    _check_buckets(d, w, sim.ctx.tile, n)
+    assert _exact_total(I) == n << (2 * S)
+
+
+def test_full_size_fp64_thermal_2d_sampled(torch):
+    from paper_2608_15249_amd.sim import Simulation
+    w = W.thermal_2d()
+    state = W.sample(w)
+    x, y, vx, vy, _ = state
+    n = len(x)
+    sim = Simulation(w, "fp64", state=state, tile="auto")
+    ids, _, nlive = _gpu_init_and_step(torch, sim)
+    d = sim.p.download()
+    s = O.Setup(2, 2, w.nx, w.Lx, n, w.dt, ny=w.ny, Ly=w.Ly)
+    E0 = O.solve_field(s, O.deposit(s, O.State.from_arrays(x, vx, y, vy)))
+    rng = np.random.default_rng(102)
+    idx = rng.choice(n, 4096, replace=False)
+    src = ids[idx]
+    sub = dataclasses.replace(s, n_particles=len(src))
+    st = O.State.from_arrays(x[src], vx[src], y[src], vy[src])
+    O.boris(sub, st, O.gather(sub, st, E0), -0.5 * s.dt)
+    O.boris(sub, st, O.gather(sub, st, E0), s.dt)
+    O.move(sub, st)
+    for k, r in (("vx", st.vx), ("vy", st.vy)):
+        assert np.max(np.abs(d[k][idx] - r)) <= 1e-12, k
+    for k, r, L in (("x", st.x, s.Lx), ("y", st.y, s.Ly)):
+        dd = np.abs(d[k][idx] - r)
+        assert np.max(np.minimum(dd, L - dd)) <= 1e-12 * L, k
+
+
+def test_full_size_mixed_walls_sampled(torch):
+    """thermal_2d between grounded absorbing walls at full size: the live
+    count equals the number of particles whose binary32 push (over the whole
+    plasma, in the oracle's Dirichlet field) keeps them inside, sampled live
+    particles are bit-exact, the bucket table holds the live particles and the
+    fixed-point charge is exactly that of the live ones."""
+    from paper_2608_15249_amd.sim import Simulation
+    w = W.thermal_2d()
+    state = W.sample(w)
+    x, y, vx, vy, _ = state
+    n = len(x)
+    sim = Simulation(w, "mixed", state=state, tile=(16, 16), walls=True)
+    ids, I, nlive = _gpu_init_and_step(torch, sim, walls=True)
+    d = sim.p.download()
+    S = sim.ctx.frac_bits
+    nx2 = 2 * w.nx
+    se = O.Setup(2, 2, nx2, 2 * w.Lx, n, w.dt, ny=w.ny, Ly=w.Ly)
+    m = _mixed_cells(w, x, y)
+    I0 = O.deposit_quantised(se, m["ix"], m["ox"], S, m["iy"], m["oy"])
+    b = B.Box(w.nx, w.Lx, w.ny, w.Ly, n, w.dt)
+    rho = se.rho_ion + I0[:, :w.nx + 1].astype(np.float64) * (b.Q * np.ldexp(1.0, -2 * S) / b.dV)
+    Eb = B.solve_field(b, rho)
+    E32 = tuple(np.pad(e, ((0, 0), (0, nx2 - w.nx - 1))).astype(np.float32) for e in Eb)
+    m0 = dict(m)
+    m0["vx"], m0["vy"] = vx.astype(np.float32), vy.astype(np.float32)
+    kw = dict(dim=2, vdim=2, nx=nx2, ny=w.ny, dx=w.dx, dy=w.dy, qm=-1.0, dt=w.dt, bz=0.0)
+    half = OM.push(m0, E32, dt_scale=-0.5, move=False, **kw)
+    ref = OM.push(half, E32, **kw)
+    live = ref["ix"] < w.nx
+    assert nlive == int(live.sum()) < n
+    rng = np.random.default_rng(103)
+    idx = rng.choice(nlive, 4096, replace=False)
+    src = ids[idx]
+    assert np.all(live[src])
+    ix, iy = W.unpack_cell(d["cell"][idx], 2)
+    got = {"ix": ix, "iy": iy, "ox": d["ox"][idx], "oy": d["oy"][idx], "vx": d["vx"][idx], "vy": d["vy"][idx]}
+    for k in got:
+        assert np.array_equal(got[k], ref[k][src]), k
+    _check_buckets(d, w, sim.ctx.tile, nlive)
+    assert _exact_total(I) == nlive << (2 * S)
