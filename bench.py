@@ -153,15 +153,21 @@ def run_path(precision, w, state, steps, warmup, tile, torch, pusher="boris", c_
     return out
 
 
-def run_em(w, state, steps, warmup, tile, c_light, torch):
-    """Electromagnetic cycle (FP64 2D3V, Yee grid) on the plasma of w."""
+def run_em(precision, w, state, steps, warmup, tile, c_light, torch):
+    """Electromagnetic cycle (2D3V, Yee grid) on the plasma of w."""
+    from paper_2608_15249_amd import workloads as W
     from paper_2608_15249_amd.apic import Context, Particles
     x, y, vx, vy, vz = state
     n = len(x)
-    ctx = Context(dim=2, vdim=3, nx=w.nx, ny=w.ny, lx=w.Lx, ly=w.Ly, dt=w.dt, n=n, bz=w.bz, precision="fp64",
+    ctx = Context(dim=2, vdim=3, nx=w.nx, ny=w.ny, lx=w.Lx, ly=w.Ly, dt=w.dt, n=n, bz=w.bz, precision=precision,
                   tile=(0, 0) if tile in (None, "auto") else tile, c_light=c_light, model="em")
     p = Particles(ctx)
-    p.upload(x=x, y=y, vx=vx, vy=vy, vz=vz)
+    if ctx.mixed:
+        ix, ox = W.to_cell_offset(x, w.dx, w.nx)
+        iy, oy = W.to_cell_offset(y, w.dy, w.ny)
+        p.upload(cell=W.pack_cell(ix, iy), ox=ox, oy=oy, vx=vx, vy=vy, vz=vz)
+    else:
+        p.upload(x=x, y=y, vx=vx, vy=vy, vz=vz)
     ctx.sort_by_cell(p)
     F = torch.zeros(6 * ctx.G, dtype=torch.float64, device="cuda")
     ctx.em_init_fields(p, F)
@@ -180,7 +186,7 @@ def run_em(w, state, steps, warmup, tile, c_light, torch):
     ms, nprof = ctx.profile_read()
     ctx.profile_enable(0)
     elapsed = t1 - t0
-    sb = state_bytes("fp64", 2, 3)
+    sb = state_bytes(precision, 2, 3)
     push_ms = ms[2] / max(nprof, 1)
     push_bytes = 2 * sb * n
     achieved = push_bytes / (push_ms * 1e-3) / 1e9
@@ -416,20 +422,30 @@ def main():
             print("--model em needs a 2D3V workload (magnetized_2d3v)", file=sys.stderr)
             sys.exit(2)
         c_light = 10.0 if args.c_light is None else args.c_light
-        print("bench: %s, electromagnetic FP64 path, %d warmup + %d timed steps" % (args.workload, args.warmup,
-                                                                                   args.steps),
-              file=sys.stderr, flush=True)
-        r = run_em(w, state, args.steps, args.warmup, tile, c_light, torch)
+        res = {}
+        for path in args.paths.split(","):
+            print("bench: %s, electromagnetic %s path, %d warmup + %d timed steps" % (args.workload, path,
+                                                                                     args.warmup, args.steps),
+                  file=sys.stderr, flush=True)
+            res[path] = run_em(path, w, state, args.steps, args.warmup, tile, c_light, torch)
         copy_gbs = measure_copy_gbs(torch)
+        r = res.get("mixed") or res[list(res)[0]]
         line = dict(common)
-        line.update({"value": r["value"], "ms_per_step": r["ms_per_step"], "dtype": "f64",
+        line.update({"value": r["value"], "ms_per_step": r["ms_per_step"],
+                     "dtype": "f32+f64" if "mixed" in res else "f64",
                      "config": {"workload": WORKLOADS[args.workload] + "; electromagnetic (Yee FDTD, c=%g)" % c_light,
-                                "grid": _grid(w), "particles": w.n_particles, "tile": r["tile"], "precision": "fp64",
-                                "model": "electromagnetic"},
+                                "grid": _grid(w), "particles": w.n_particles, "tile": r["tile"],
+                                "precision": "mixed" if "mixed" in res else "fp64", "model": "electromagnetic"},
                      "hbm_gbs_step": r["hbm_gbs_step"], "roofline": with_copy(r["roofline"], copy_gbs),
                      "phase_ms_per_step": r["phase_ms_per_step"],
                      "particle_steps_s_by_phase": r["particle_steps_s_by_phase"],
                      "final_energies": {"W_B": r["final_W_B"], "W_E": r["final_W_E"], "KE": r["final_KE"]}})
+        if "fp64" in res and "mixed" in res:
+            f = res["fp64"]
+            line["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "tile": f["tile"],
+                            "roofline": with_copy(f["roofline"], copy_gbs), "phase_ms_per_step": f["phase_ms_per_step"],
+                            "final_energies": {"W_B": f["final_W_B"], "W_E": f["final_W_E"], "KE": f["final_KE"]}}
+            line["mixed_over_fp64"] = r["value"] / f["value"]
         if not args.no_cpu_baseline:
             print("bench: cpu baseline (%d oracle steps)" % args.cpu_steps, file=sys.stderr, flush=True)
             line["cpu_baseline"] = cpu_baseline_em(w, state, min(args.cpu_steps, 3), c_light)

@@ -69,9 +69,9 @@ typedef enum {
 typedef enum {
     APIC_ELECTROSTATIC = 0,  /* periodic Poisson solve each step (apic_step)  */
     APIC_ELECTROMAGNETIC = 1 /* Yee FDTD update with a charge-conserving
-                                current deposit (apic_em_step); FP64 2D3V,
-                                Boris, c_light > 0 with the Courant condition
-                                c dt sqrt(1/dx^2 + 1/dy^2) < 1              */
+                                current deposit (apic_em_step); 2D3V, either
+                                precision, Boris, c_light > 0 with the Courant
+                                condition c dt sqrt(1/dx^2 + 1/dy^2) < 1     */
 } apic_field_model;
 
 typedef enum {
@@ -336,9 +336,13 @@ apic_status apic_step_adjoint(apic_ctx *ctx, const void *ckpt, int nsteps, int s
  * The paper lists B_Scatter of current densities and E_Maxwell
  * ("finite-difference time-domain updates", citing Yee 1966) among its
  * modules. A context created with model = APIC_ELECTROMAGNETIC runs the
- * electromagnetic PIC cycle on the same sorted, tiled particle layout, in
- * FP64, 2D3V, on a periodic Yee grid in normalised units eps0 = 1,
- * mu0 = 1/c^2 (c = c_light):
+ * electromagnetic PIC cycle on the same sorted, tiled particle layout, 2D3V,
+ * on a periodic Yee grid in normalised units eps0 = 1, mu0 = 1/c^2
+ * (c = c_light). The FP64 path pushes in FP64; the mixed path keeps its
+ * particle representation (cell + binary32 offsets and velocities) and runs
+ * the field tile, gather, Boris and the current weights in binary32, the
+ * displacement of the current deposit being the binary32 product its move
+ * adds; the current sums, the field update and F stay FP64 in both:
  *   - F [dev, double, 6*G] holds Ex, Ey, Ez, Bx, By, Bz, each [ny][nx], with
  *     element [j][i] of Ex at ((i+1/2) dx, j dy), Ey at (i dx, (j+1/2) dy),
  *     Ez at (i dx, j dy), Bx at (i dx, (j+1/2) dy), By at ((i+1/2) dx, j dy)

@@ -1,4 +1,4 @@
-// Electromagnetic step (FP64, 2D3V, periodic Yee grid): the field kernels of
+// Electromagnetic step (2D3V, periodic Yee grid): the field kernels of
 // the finite-difference time-domain update (E_Maxwell, Yee 1966), the
 // initial field, the standalone gather + Boris, and the C-ABI entry points
 // apic_em_init_fields, apic_em_gather_push and apic_em_step. The particle
@@ -126,38 +126,42 @@ __global__ void __launch_bounds__(1024) k_em_finalize(int nblk, int npush, doubl
 }
 
 // E, B at a particle from the global field: the tile gather's arithmetic with
-// global (periodic) node indices.
-__device__ __forceinline__ double lerp_glob(const double *f, const Geo &g, int i, int j, double fx, double fy) {
+// global (periodic) node indices (node values converted to R first, as the
+// tile holds them).
+template <typename R>
+__device__ __forceinline__ R lerp_glob(const double *f, const Geo &g, int i, int j, R fx, R fy) {
     const int ip = wrap_up(i, g.nx), jp = wrap_up(j, g.ny);
     const int64_t r0 = (int64_t)j * g.nx, r1 = (int64_t)jp * g.nx;
-    return (1.0 - fx) * (1.0 - fy) * f[r0 + i] + fx * (1.0 - fy) * f[r0 + ip] + (1.0 - fx) * fy * f[r1 + i] +
-           fx * fy * f[r1 + ip];
+    return (R(1) - fx) * (R(1) - fy) * (R)f[r0 + i] + fx * (R(1) - fy) * (R)f[r0 + ip] +
+           (R(1) - fx) * fy * (R)f[r1 + i] + fx * fy * (R)f[r1 + ip];
 }
 
+template <bool MIX>
 __global__ void __launch_bounds__(kBlock) k_em_gather_push(Geo g, Parts p, int64_t n, const double *F, PushC pc,
                                                            CtxDev c) {
+    using R = typename Pt<MIX>::R;
     const int64_t G = (int64_t)g.nx * g.ny;
     int bad = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        Pt<false> q;
-        bool ok = load_pt<false, 2, 3>(p, i, g, q);
-        const bool hx = q.fx >= 0.5, hy = q.fy >= 0.5;
+        Pt<MIX> q;
+        bool ok = load_pt<MIX, 2, 3>(p, i, g, q);
+        const bool hx = q.fx >= R(0.5), hy = q.fy >= R(0.5);
         const int ax1 = hx ? q.ix : wrap_dn(q.ix, g.nx), ay1 = hy ? q.iy : wrap_dn(q.iy, g.ny);
-        const double fx1 = hx ? q.fx - 0.5 : q.fx + 0.5, fy1 = hy ? q.fy - 0.5 : q.fy + 0.5;
-        double e[3], b[3];
-        e[0] = lerp_glob(F, g, ax1, q.iy, fx1, q.fy);
-        e[1] = lerp_glob(F + G, g, q.ix, ay1, q.fx, fy1);
-        e[2] = lerp_glob(F + 2 * G, g, q.ix, q.iy, q.fx, q.fy);
-        b[0] = lerp_glob(F + 3 * G, g, q.ix, ay1, q.fx, fy1);
-        b[1] = lerp_glob(F + 4 * G, g, ax1, q.iy, fx1, q.fy);
-        b[2] = lerp_glob(F + 5 * G, g, ax1, ay1, fx1, fy1);
-        boris3(q.vx, q.vy, q.vz, e, b, pc.a);
+        const R fx1 = hx ? q.fx - R(0.5) : q.fx + R(0.5), fy1 = hy ? q.fy - R(0.5) : q.fy + R(0.5);
+        R e[3], b[3];
+        e[0] = lerp_glob<R>(F, g, ax1, q.iy, fx1, q.fy);
+        e[1] = lerp_glob<R>(F + G, g, q.ix, ay1, q.fx, fy1);
+        e[2] = lerp_glob<R>(F + 2 * G, g, q.ix, q.iy, q.fx, q.fy);
+        b[0] = lerp_glob<R>(F + 3 * G, g, q.ix, ay1, q.fx, fy1);
+        b[1] = lerp_glob<R>(F + 4 * G, g, ax1, q.iy, fx1, q.fy);
+        b[2] = lerp_glob<R>(F + 5 * G, g, ax1, ay1, fx1, fy1);
+        boris3<R>(q.vx, q.vy, q.vz, e, b, MIX ? (R)pc.af : (R)pc.a);
         if (pc.move) {
             int sx, sy, sz;
-            ok = move_pt<false, 2>(q, g, pc, sx, sy, sz) && ok;
+            ok = move_pt<MIX, 2>(q, g, pc, sx, sy, sz) && ok;
         }
         if (!ok) bad = 1;
-        store_pt<false, 2, 3>(p, i, q);
+        store_pt<MIX, 2, 3>(p, i, q);
     }
     if (bad) raise_err(c.err, ERR_DOMAIN);
 }
@@ -175,9 +179,12 @@ hipError_t launch_em_init(const Geo &g, const double *phi, double bz, double *F,
     return hipGetLastError();
 }
 
-hipError_t launch_em_gather_push(const Geo &g, const Parts &p, int64_t n, const double *F, const PushC &pc,
-                                 const CtxDev &c, hipStream_t s) {
-    hipLaunchKernelGGL(k_em_gather_push, dim3(em_blocks(n, 8192)), dim3(kBlock), 0, s, g, p, n, F, pc, c);
+hipError_t launch_em_gather_push(const Geo &g, bool mixed, const Parts &p, int64_t n, const double *F,
+                                 const PushC &pc, const CtxDev &c, hipStream_t s) {
+    if (mixed)
+        hipLaunchKernelGGL(k_em_gather_push<true>, dim3(em_blocks(n, 8192)), dim3(kBlock), 0, s, g, p, n, F, pc, c);
+    else
+        hipLaunchKernelGGL(k_em_gather_push<false>, dim3(em_blocks(n, 8192)), dim3(kBlock), 0, s, g, p, n, F, pc, c);
     return hipGetLastError();
 }
 
@@ -222,12 +229,18 @@ apic_status apic_em_init_fields(apic_ctx *c, const apic_particles *p, double *F,
     if (st != APIC_OK) return st;
     if (!F || !ws) return fail(c, APIC_EINVAL, "F and workspace are required");
     hipStream_t s = (hipStream_t)stream;
-    double *rho = wsp<double>(ws, c->o_acc);
-    double *phi = wsp<double>(ws, c->o_rho);
+    // charge (FP64 weights or fixed-point sums) -> rho -> phi -> F
+    void *acc = wsp<void>(ws, c->o_acc);
+    double *rho = wsp<double>(ws, c->o_rho);
+    double *phi = rho;
     void *rhat = wsp<void>(ws, c->o_rhat);
     void *phat = wsp<void>(ws, c->o_ehat);
-    st = apic_deposit(c, p, rho, stream);
+    st = apic_deposit(c, p, acc, stream);
     if (st != APIC_OK) return st;
+    if (c->mixed)
+        HIPCHK(c, launch_rho(c->g, true, acc, rho, acc_scale(c), c->d.rho_ion, 1, s));
+    else
+        HIPCHK(c, launch_copy_bytes(rho, acc, 8 * (int64_t)c->d.nx * c->d.ny, s));
     FFTCHK(c, hipfftSetStream(c->fwd, s));
     FFTCHK(c, hipfftExecD2Z(c->fwd, (hipfftDoubleReal *)rho, (hipfftDoubleComplex *)rhat));
     HIPCHK(c, launch_spectral(c->g, rhat, phat, c->dev, s));
@@ -246,7 +259,7 @@ apic_status apic_em_gather_push(apic_ctx *c, apic_particles *p, const double *F,
     if (!F) return fail(c, APIC_EINVAL, "F is NULL");
     if (!std::isfinite(dt_scale)) return fail(c, APIC_EINVAL, "dt_scale is not finite");
     const PushC pc = push_coeffs(c, dt_scale, move);
-    HIPCHK(c, launch_em_gather_push(c->g, parts_of(p), c->n, F, pc, c->dev, (hipStream_t)stream));
+    HIPCHK(c, launch_em_gather_push(c->g, c->mixed, parts_of(p), c->n, F, pc, c->dev, (hipStream_t)stream));
     return APIC_OK;
 }
 
@@ -286,12 +299,12 @@ apic_status apic_em_step(apic_ctx *c, apic_particles *p, double *F, double *J, i
         hipEvent_t *ev = nullptr;
         if (c->prof_used < c->prof_max) ev = &c->ev[5 * (size_t)c->prof_used++];
         if (ev) HIPCHK(c, hipEventRecord(ev[0], s));
-        HIPCHK(c, launch_step_count(c->g, false, src, bs_src, F, pc, cnt, tot, farcnt, deep, c->dev, s));
+        HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, F, pc, cnt, tot, farcnt, deep, c->dev, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[1], s));
         HIPCHK(c, launch_scan_dir(c->g, tot, bs_dst, c->n, max_per_bucket(c), 1, c->dev, s));
         HIPCHK(c, launch_dest_offsets(c->g, cnt, bs_dst, offs, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
-        HIPCHK(c, launch_step_push(c->g, false, src, dst, bs_src, bs_dst, cnt, offs, farcnt, F, pc, jacc, p->perm,
+        HIPCHK(c, launch_step_push(c->g, c->mixed, src, dst, bs_src, bs_dst, cnt, offs, farcnt, F, pc, jacc, p->perm,
                                    diag ? c->dev.part_push : nullptr, deep, c->dev, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[3], s));
         HIPCHK(c, launch_fdtd_b(c->g, F, 0.5 * dt, s));

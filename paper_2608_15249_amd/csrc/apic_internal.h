@@ -163,8 +163,8 @@ hipError_t launch_field1d(const Geo &g, bool mixed, void *acc, double scale, dou
 // Ez = Bx = By = 0, Bz = bz
 hipError_t launch_em_init(const Geo &g, const double *phi, double bz, double *F, hipStream_t s);
 // gather E, B + Boris (+ move), in place (no ordering needed)
-hipError_t launch_em_gather_push(const Geo &g, const Parts &p, int64_t n, const double *F, const PushC &pc,
-                                 const CtxDev &c, hipStream_t s);
+hipError_t launch_em_gather_push(const Geo &g, bool mixed, const Parts &p, int64_t n, const double *F,
+                                 const PushC &pc, const CtxDev &c, hipStream_t s);
 // B -= h curl E
 hipError_t launch_fdtd_b(const Geo &g, double *F, double h, hipStream_t s);
 // E += dt (c^2 curl B - J), then J = 0 (Jout, when not NULL, receives J first)

@@ -206,12 +206,14 @@ __device__ __forceinline__ bool advance(Pt<MIX> &q, const Geo &g, const PushC &p
     return push_move<MIX, DIM, VDIM, HC>(q, g, pc, ex, ey, ez, true, sx, sy, sz) && in;
 }
 
-// Electromagnetic form (FP64, 2D3V): E and B gathered from the Yee field
-// tile (nodes from (x0-1, y0-1), width fw), Boris in B, move. (lx, ly) and
+// Electromagnetic form (2D3V): E and B gathered from the Yee field tile
+// (nodes from (x0-1, y0-1), width fw), Boris in B, move. (lx, ly) and
 // (fx0, fy0) return the old local cell and fractions for the current deposit.
-__device__ __forceinline__ bool advance_em(Pt<false> &q, const Geo &g, const PushC &pc, const double *sF, int fw,
-                                           int x0, int y0, int &lx, int &ly, int &sx, int &sy, double &fx0,
-                                           double &fy0) {
+template <bool MIX>
+__device__ __forceinline__ bool advance_em(Pt<MIX> &q, const Geo &g, const PushC &pc,
+                                           const typename Pt<MIX>::R *sF, int fw, int x0, int y0, int &lx, int &ly,
+                                           int &sx, int &sy, typename Pt<MIX>::R &fx0, typename Pt<MIX>::R &fy0) {
+    using R = typename Pt<MIX>::R;
     const int tx = 1 << g.tsx, ty = 1 << g.tsy;
     lx = q.ix - x0;
     ly = q.iy - y0;
@@ -224,11 +226,11 @@ __device__ __forceinline__ bool advance_em(Pt<false> &q, const Geo &g, const Pus
     }
     fx0 = q.fx;
     fy0 = q.fy;
-    double e[3], b[3];
-    gather_em(sF, fw, fw * (ty + 2), lx, ly, q.fx, q.fy, e, b);
-    boris3(q.vx, q.vy, q.vz, e, b, pc.a);
+    R e[3], b[3];
+    gather_em<R>(sF, fw, fw * (ty + 2), lx, ly, q.fx, q.fy, e, b);
+    boris3<R>(q.vx, q.vy, q.vz, e, b, MIX ? (R)pc.af : (R)pc.a);
     int sz;
-    return move_pt<false, 2>(q, g, pc, sx, sy, sz) && in;
+    return move_pt<MIX, 2>(q, g, pc, sx, sy, sz) && in;
 }
 
 // Raw stored words of one particle: loaded unconditionally (the caller clamps
@@ -773,7 +775,7 @@ template <bool MIX, int DIM, int VDIM, int U, bool HC, bool EM>
 __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int32_t *bstart, const double *E,
                                                        PushC pc, int32_t *cnt, int32_t *tot, int32_t *farcnt,
                                                        const int32_t *deep, CtxDev c) {
-    static_assert(!EM || (!MIX && DIM == 2 && VDIM == 3 && !HC), "the electromagnetic step is FP64 2D3V");
+    static_assert(!EM || (DIM == 2 && VDIM == 3 && !HC), "the electromagnetic step is 2D3V with Boris");
     using R = typename Pt<MIX>::R;
     constexpr int kDirs = Dir<DIM>::kN, kFar = Dir<DIM>::kFar, kStay = Dir<DIM>::kStay, kTab = Dir<DIM>::kTab;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -796,7 +798,7 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
         const TileNb tn = tile_nb<DIM>(g, bx, by, bz);
         if (threadIdx.x < kTab) sCnt[threadIdx.x] = 0;
         if constexpr (EM)
-            load_f_tile((double *)smem, E, g, x0, y0, fw, fh);
+            load_f_tile<R>((R *)smem, E, g, x0, y0, fw, fh);
         else if constexpr (DIM == 3)
             load_e_tile3<R, double>(sE, E, g, x0, y0, z0, ex_w, ey_w, ez_w);
         else
@@ -878,8 +880,8 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
                 bool good = decode<MIX, DIM, VDIM>(r1, g, q);
                 int lx, ly, lz = 0, sx, sy, sz = 0;
                 if constexpr (EM) {
-                    double f0x, f0y;
-                    good = advance_em(q, g, pc, (const double *)smem, fw, x0, y0, lx, ly, sx, sy, f0x, f0y) && good;
+                    R f0x, f0y;
+                    good = advance_em<MIX>(q, g, pc, (const R *)smem, fw, x0, y0, lx, ly, sx, sy, f0x, f0y) && good;
                 } else {
                     good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx, sy,
                                                        sz) && good;
@@ -917,8 +919,8 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
                     bool good = decode<MIX, DIM, VDIM>(r[j], g, q);
                     int lx, ly, lz = 0, sx, sy, sz = 0;
                     if constexpr (EM) {
-                        double f0x, f0y;
-                        good = advance_em(q, g, pc, (const double *)smem, fw, x0, y0, lx, ly, sx, sy, f0x, f0y) &&
+                        R f0x, f0y;
+                        good = advance_em<MIX>(q, g, pc, (const R *)smem, fw, x0, y0, lx, ly, sx, sy, f0x, f0y) &&
                                good;
                     } else {
                         good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx,
@@ -1068,7 +1070,7 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
             sRun[threadIdx.x] = off;
         }
         if constexpr (EM)
-            load_f_tile((double *)sE, E, g, x0, y0, fw, fh);
+            load_f_tile<R>(sE, E, g, x0, y0, fw, fh);
         else if constexpr (DIM == 3)
             load_e_tile3<R, double>(sE, E, g, x0, y0, z0, ex_w, ey_w, ez_w);
         else
@@ -1135,9 +1137,9 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                     bool good = decode<MIX, DIM, VDIM>(r[j], g, q);
                     const double v2o = vsq<MIX, VDIM, HC>(q, pc);
                     int lx, ly, lz = 0, sx, sy, sz = 0;
-                    double f0x = 0.0, f0y = 0.0;
+                    R f0x = R(0), f0y = R(0);
                     if constexpr (EM) {
-                        good = advance_em(q, g, pc, (const double *)sE, fw, x0, y0, lx, ly, sx, sy, f0x, f0y) && good;
+                        good = advance_em<MIX>(q, g, pc, sE, fw, x0, y0, lx, ly, sx, sy, f0x, f0y) && good;
                     } else {
                         good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx,
                                                            sy, sz) && good;
@@ -1183,10 +1185,18 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                     }
                     if (dead) {
                     } else if constexpr (EM) {
-                        // current J^{n+1/2} of the move x^n -> x^{n+1} (Esirkepov)
-                        const double ddx = (q.vx * pc.dt) * g.inv_dx, ddy = (q.vy * pc.dt) * g.inv_dy;
-                        if (!esirkepov_lds((double *)sA, jw, jw * jh, lx, ly, f0x, f0y, ddx, ddy, pc.jx, pc.jy,
-                                           pc.jz * q.vz))
+                        // current J^{n+1/2} of the move x^n -> x^{n+1} (Esirkepov); the
+                        // mixed path's displacement is the binary32 product its move adds
+                        R ddx, ddy;
+                        if constexpr (MIX) {
+                            ddx = q.vx * pc.dtdx;
+                            ddy = q.vy * pc.dtdy;
+                        } else {
+                            ddx = (q.vx * pc.dt) * g.inv_dx;
+                            ddy = (q.vy * pc.dt) * g.inv_dy;
+                        }
+                        if (!esirkepov_lds<R>((double *)sA, jw, jw * jh, lx, ly, f0x, f0y, ddx, ddy, pc.jx, pc.jy,
+                                              pc.jz * (double)q.vz))
                             atomicOr(&sErr, ERR_DOMAIN);
                     } else {
                     // deposit rho^{n+1}: LDS tile + halo, global beyond it
@@ -1536,8 +1546,8 @@ inline size_t tile_e_bytes(const Geo &g, bool mixed) {
 
 // electromagnetic step: six-component field tile ((T+2)^2 each) and the
 // three-component current tile ((T+3)^2 each), rounded to 16 bytes
-inline size_t em_f_tile_bytes(const Geo &g) {
-    return ((size_t)6 * ((1 << g.tsx) + 2) * ((1 << g.tsy) + 2) * sizeof(double) + 15) & ~(size_t)15;
+inline size_t em_f_tile_bytes(const Geo &g, bool mixed) {
+    return ((size_t)6 * ((1 << g.tsx) + 2) * ((1 << g.tsy) + 2) * (mixed ? 4 : 8) + 15) & ~(size_t)15;
 }
 inline size_t em_j_tile_bytes(const Geo &g) {
     return ((size_t)3 * ((1 << g.tsx) + 3) * ((1 << g.tsy) + 3) * sizeof(double) + 15) & ~(size_t)15;
@@ -1680,10 +1690,16 @@ hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int
                              const PushC &pc, int32_t *cnt, int32_t *tot, int32_t *farcnt, const int32_t *deep,
                              const CtxDev &c, hipStream_t s) {
     if (g.em) {
-        const size_t sh = em_f_tile_bytes(g);
-        auto kern = k_step_count<false, 2, 3, APIC_STEP_U, false, true>;
-        hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, p, bstart, E,
-                           pc, cnt, tot, farcnt, deep, c);
+        const size_t sh = em_f_tile_bytes(g, mixed);
+        if (mixed) {
+            auto kern = k_step_count<true, 2, 3, APIC_STEP_U, false, true>;
+            hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, p, bstart,
+                               E, pc, cnt, tot, farcnt, deep, c);
+        } else {
+            auto kern = k_step_count<false, 2, 3, APIC_STEP_U, false, true>;
+            hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, p, bstart,
+                               E, pc, cnt, tot, farcnt, deep, c);
+        }
         return hipGetLastError();
     }
     size_t sh = tile_e_bytes(g, mixed);
@@ -1719,10 +1735,17 @@ hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Pa
                             const double *E, const PushC &pc, void *acc, int32_t *perm, double *part, int32_t *deep,
                             const CtxDev &c, hipStream_t s) {
     if (g.em) {
-        const size_t sh = em_j_tile_bytes(g) + em_f_tile_bytes(g);
-        auto kern = k_step_push<false, 2, 3, APIC_STEP_U, false, true>;
-        hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, src, dst,
-                           bstart, bstart_new, cnt, offs, farcnt, E, pc, (double *)acc, perm, part, deep, c);
+        const size_t sh = em_j_tile_bytes(g) + em_f_tile_bytes(g, mixed);
+        if (mixed) {
+            auto kern = k_step_push<true, 2, 3, APIC_STEP_U, false, true>;
+            hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, src, dst,
+                               bstart, bstart_new, cnt, offs, farcnt, E, pc, (unsigned long long *)acc, perm, part,
+                               deep, c);
+        } else {
+            auto kern = k_step_push<false, 2, 3, APIC_STEP_U, false, true>;
+            hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, src, dst,
+                               bstart, bstart_new, cnt, offs, farcnt, E, pc, (double *)acc, perm, part, deep, c);
+        }
         return hipGetLastError();
     }
     size_t sh = tile_acc_bytes(g, g.halo) + tile_e_bytes(g, mixed);

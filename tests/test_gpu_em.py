@@ -205,9 +205,6 @@ def test_electromagnetic_context_checks(torch):
     with pytest.raises(ApicError):       # Courant condition: 8 * 0.1 * sqrt(2) > 1
         Context(dim=2, vdim=3, nx=nx, ny=ny, lx=16.0, ly=16.0, dt=0.1, n=100, precision="fp64", c_light=8.0,
                 model="em")
-    with pytest.raises(ApicError):       # binary32 form not built
-        Context(dim=2, vdim=3, nx=nx, ny=ny, lx=16.0, ly=16.0, dt=0.1, n=100, precision="mixed", c_light=5.0,
-                model="em")
     with pytest.raises(ApicError):       # 2D3V only
         Context(dim=2, vdim=2, nx=nx, ny=ny, lx=16.0, ly=16.0, dt=0.1, n=100, precision="fp64", c_light=5.0,
                 model="em")
@@ -291,3 +288,115 @@ def test_full_size_magnetized_plasma_sampled(torch):
     tot = Jg.sum(axis=1) * s.dV
     ref = s.Q * np.array([d["vx"].sum(), d["vy"].sum(), d["vz"].sum()])
     assert np.max(np.abs(tot - ref)) <= 1e-9 * np.sum(np.abs(s.Q * d["vx"]))
+
+
+# ------------------------------------------------------------------ mixed form
+# binary32 field tile, gather, Boris and current weights; FP64 current sums
+# and field update. Compared with the FP64 oracle at binary32 tolerances, and
+# held to the local field-energy criterion of the mixed path.
+
+def _mctx(torch, case):
+    from paper_2608_15249_amd.apic import Context, Particles
+    nx, ny, lx, ly, n, tile, dt, bz = case
+    c = Context(dim=2, vdim=3, nx=nx, ny=ny, lx=lx, ly=ly, dt=dt, n=n, bz=bz, precision="mixed", tile=tile,
+                c_light=C_LIGHT, model="em")
+    return c, Particles(c)
+
+
+def _mixed_state(rng, case, s):
+    """A mixed-representation state and its exact FP64 positions."""
+    x, y, vx, vy, vz = _state(rng, case)
+    cx, ox = W.to_cell_offset(x, s.dx, s.nx)
+    cy, oy = W.to_cell_offset(y, s.dy, s.ny)
+    xe = (cx + ox.astype(np.float64)) * s.dx
+    ye = (cy + oy.astype(np.float64)) * s.dy
+    v32 = [a.astype(np.float32) for a in (vx, vy, vz)]
+    return (cx, ox, cy, oy), (xe, ye), v32
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_mixed_gather_push_tracks_oracle(torch, case):
+    rng = np.random.default_rng(78)
+    s = _setup(case)
+    (cx, ox, cy, oy), (xe, ye), v32 = _mixed_state(rng, case, s)
+    F = rng.normal(size=(6, s.ny, s.nx))
+    F[5] += s.bz
+    c, p = _mctx(torch, case)
+    p.upload(cell=W.pack_cell(cx, cy), ox=ox, oy=oy, vx=v32[0], vy=v32[1], vz=v32[2])
+    c.em_gather_push(p, _dev(torch, F), dt_scale=1.0, move=True)
+    c.sync()
+    d = p.download()
+    st = O.State.from_arrays(xe, v32[0].astype(np.float64), ye, v32[1].astype(np.float64), v32[2].astype(np.float64))
+    Ep, Bp = M.gather(s, st, F)
+    M.boris(s, st, Ep, Bp, s.dt)
+    O.move(s, st)
+    for k, ref in (("vx", st.vx), ("vy", st.vy), ("vz", st.vz)):
+        assert np.max(np.abs(d[k] - ref)) <= 2e-5 * (1 + np.max(np.abs(ref))), k
+    ix, iy = W.unpack_cell(d["cell"], 2)
+    for pos, ref, dd, L in (((ix + d["ox"].astype(np.float64)) * s.dx, st.x, s.dx, s.Lx),
+                            ((iy + d["oy"].astype(np.float64)) * s.dy, st.y, s.dy, s.Ly)):
+        assert np.max(_pdist(pos, ref, L)) <= 2e-6 * dd * 10
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_mixed_step_current_and_local_field_energy(torch, case):
+    """From the same state: the mixed step's J and fields agree with the FP64
+    oracle step in the oracle's field of the same quantised charge to binary32
+    accuracy, and its field energy W_E + W_B within 1e-5 (relative)."""
+    rng = np.random.default_rng(79)
+    s = _setup(case)
+    n = case[4]
+    (cx, ox, cy, oy), (xe, ye), v32 = _mixed_state(rng, case, s)
+    c, p = _mctx(torch, case)
+    p.upload(cell=W.pack_cell(cx, cy), ox=ox, oy=oy, vx=v32[0], vy=v32[1], vz=v32[2])
+    perm = torch.zeros(n, dtype=torch.int32, device="cuda")
+    c.sort_by_cell(p, perm=perm)
+    ids = _compose(np.arange(n), perm)
+    F = torch.zeros(6 * c.G, dtype=torch.float64, device="cuda")
+    c.em_init_fields(p, F)
+    S = c.frac_bits
+    I0 = O.deposit_quantised(s, cx, ox, S, cy, oy)
+    Fo = np.zeros((6, s.ny, s.nx))
+    Fo[0], Fo[1] = M.staggered_e(s, O.solve_potential(s, O.rho_from_quantised(s, I0, S)))
+    Fo[5] = s.bz
+    c.sync()
+    Fg0 = F.cpu().numpy().reshape(6, s.ny, s.nx)
+    assert np.max(np.abs(Fg0 - Fo)) <= 1e-12 * np.max(np.abs(Fo[:2])) + 1e-15
+    J = torch.zeros(3 * c.G, dtype=torch.float64, device="cuda")
+    diag = torch.zeros(4, dtype=torch.float64, device="cuda")
+    c.em_step(p, F, 1, diag=diag, J=J, perm=perm)
+    c.sync()
+    st = O.State.from_arrays(xe, v32[0].astype(np.float64), ye, v32[1].astype(np.float64), v32[2].astype(np.float64))
+    Jo, _ = M.step(s, st, Fo)
+    Jg = J.cpu().numpy().reshape(3, s.ny, s.nx)
+    assert np.max(np.abs(Jg - Jo)) <= 1e-5 * np.max(np.abs(Jo))
+    Fg = F.cpu().numpy().reshape(6, s.ny, s.nx)
+    assert np.max(np.abs(Fg[:3] - Fo[:3])) <= 1e-5 * np.max(np.abs(Fo[:3]))
+    we, wb = M.field_energies(s, Fo)
+    dg = diag.cpu().numpy()
+    assert abs((dg[0] + dg[1]) / (we + wb) - 1) <= 1e-5
+    ids = _compose(ids, perm)
+    d = p.download()
+    for k, ref in (("vx", st.vx), ("vy", st.vy), ("vz", st.vz)):
+        assert np.max(np.abs(d[k] - ref[ids])) <= 2e-5 * (1 + np.max(np.abs(ref))), k
+
+
+def test_mixed_gauss_law_is_kept_to_binary32_accuracy(torch):
+    case = CASES[0]
+    rng = np.random.default_rng(80)
+    s = _setup(case)
+    (cx, ox, cy, oy), _, v32 = _mixed_state(rng, case, s)
+    c, p = _mctx(torch, case)
+    p.upload(cell=W.pack_cell(cx, cy), ox=ox, oy=oy, vx=v32[0], vy=v32[1], vz=v32[2])
+    c.sort_by_cell(p)
+    F = torch.zeros(6 * c.G, dtype=torch.float64, device="cuda")
+    c.em_init_fields(p, F)
+    c.em_gather_push(p, F, dt_scale=-0.5, move=False)
+    c.em_step(p, F, 20)
+    I = torch.zeros(c.G, dtype=torch.int64, device="cuda")
+    c.deposit(p, I)
+    c.sync()
+    r = O.rho_from_quantised(s, I.cpu().numpy().reshape(s.ny, s.nx), c.frac_bits)
+    Fg = F.cpu().numpy().reshape(6, s.ny, s.nx)
+    assert np.max(np.abs(M.divergence_e(s, Fg) - r)) <= 1e-4 * np.max(np.abs(r))
+    assert np.max(np.abs(M.divergence_b(s, Fg))) <= 1e-11 * max(1.0, np.max(np.abs(Fg[3:])))
