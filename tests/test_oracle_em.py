@@ -232,3 +232,66 @@ def test_cycle_keeps_gauss_law_and_div_b():
     assert np.max(np.abs(M.divergence_b(s, F))) < 1e-11 * (1 + np.max(np.abs(F[3:])))
     # the fields did evolve (the check above is not vacuous)
     assert np.max(np.abs(F[3:5])) > 1e-6
+
+
+def _cold_lattice(nx, ny, Lx, Ly, per):
+    """Electrons on a regular lattice (per x per in every cell), at rest."""
+    gx = (np.arange(nx * per) + 0.5) * (Lx / (nx * per))
+    gy = (np.arange(ny * per) + 0.5) * (Ly / (ny * per))
+    X, Y = np.meshgrid(gx, gy)
+    return X.ravel(), Y.ravel()
+
+
+def _frequency(t, a):
+    """Angular frequency of a ~cos(w t) record from its zero crossings."""
+    s = np.sign(a)
+    idx = np.where(s[:-1] * s[1:] < 0)[0]
+    tz = t[idx] - a[idx] * (t[idx + 1] - t[idx]) / (a[idx + 1] - a[idx])
+    return np.pi / np.mean(np.diff(tz))
+
+
+def test_cold_plasma_transverse_wave_frequency():
+    """A transverse standing wave E_z = E0 cos(k x) in a cold uniform plasma
+    oscillates at w^2 = w_p^2 + c^2 k^2 (w_p = 1): the plasma's current and the
+    curl terms of the update together."""
+    nx, ny, Lx, c = 64, 2, 20.0, 5.0
+    Ly = 2 * Lx / nx
+    x, y = _cold_lattice(nx, ny, Lx, Ly, 8)
+    n = len(x)
+    s = O.Setup(2, 3, nx, Lx, n, 0.03, ny=ny, Ly=Ly, c=c)
+    st = O.State.from_arrays(x, np.zeros(n), y, np.zeros(n), np.zeros(n))
+    F = M.initialise(s, st)
+    k = 2 * np.pi / Lx
+    xi = np.arange(nx) * s.dx
+    F[2] += 1e-3 * np.cos(k * xi)[None, :]
+    ts, amp = [], []
+    for step in range(300):
+        M.step(s, st, F)
+        ts.append((step + 1) * s.dt)
+        amp.append(np.mean(F[2] * np.cos(k * xi)[None, :]))
+    w = _frequency(np.array(ts), np.array(amp))
+    assert abs(w / np.sqrt(1 + (c * k) ** 2) - 1) < 0.01, w
+
+
+def test_cold_plasma_langmuir_oscillation():
+    """A longitudinal displacement of a cold lattice plasma oscillates at the
+    plasma frequency (w_p = 1) in the electromagnetic step too, with no
+    magnetic field generated."""
+    nx, ny, Lx, c = 32, 2, 16.0, 5.0
+    Ly = 2 * Lx / nx
+    x, y = _cold_lattice(nx, ny, Lx, Ly, 8)
+    n = len(x)
+    k = 2 * np.pi / Lx
+    x = np.mod(x + 1e-3 / k * np.sin(k * x), Lx)
+    s = O.Setup(2, 3, nx, Lx, n, 0.05, ny=ny, Ly=Ly, c=c)
+    st = O.State.from_arrays(x, np.zeros(n), y, np.zeros(n), np.zeros(n))
+    F = M.initialise(s, st)
+    xi = (np.arange(nx) + 0.5) * s.dx
+    ts, amp = [], []
+    for step in range(300):
+        M.step(s, st, F)
+        ts.append((step + 1) * s.dt)
+        amp.append(np.mean(F[0] * np.sin(k * xi)[None, :]))
+    w = _frequency(np.array(ts), np.array(amp))
+    assert abs(w - 1.0) < 0.01, w
+    assert np.max(np.abs(F[3:])) < 1e-12
