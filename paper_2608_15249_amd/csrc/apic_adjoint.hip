@@ -82,6 +82,7 @@ struct AdjP {
     // reverse step n-1 (back != 0): lam in the level-(n-1) order
     int back;
     const int32_t *perm;    // level-n slot i came from level-(n-1) slot perm[i]
+    const int32_t *bs;      // bucket table of the level-n order (NULL: no LDS tiling)
     PosP prev;
     double *lE_prev;        // [dim][G] accumulated with atomics
     R *lxp_out, *lep_out, *lv_out;
@@ -181,6 +182,13 @@ __device__ __forceinline__ void hc_adj(R mx, R my, R mz, R a, R tau, R ic2, R &l
     lz = oz;
 }
 
+// Tile coordinates of bucket b of a 1D or 2D plasma (tiles x fastest).
+template <int DIM>
+__device__ __forceinline__ void tile_coords2(const Geo &g, int b, int &bx, int &by) {
+    bx = DIM == 2 ? b % g.nbx : b;
+    by = DIM == 2 ? b / g.nbx : 0;
+}
+
 template <bool MIX, int DIM, int VDIM, bool HC>
 __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>::T> P) {
     using R = typename RealOf<MIX>::T;
@@ -188,7 +196,28 @@ __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>:
     const int64_t n = P.n;
     const int G = g.nx * g.ny;
     const R idx = (R)g.inv_dx, idy = (R)g.inv_dy;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    // lam_Ep scattered at x^{n-1}: into the block's LDS tile when the level's
+    // bucket table is given and the node lies in the tile's window, else
+    // straight to global memory
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *sT = (double *)smem;
+    const bool tiled = P.bs != nullptr;
+    constexpr int H = 2;
+    const int tw = (1 << g.tsx) + 1 + 2 * H, th = (DIM == 2) ? (1 << g.tsy) + 1 + 2 * H : 1;
+    int wx0 = 0, wy0 = 0;
+    auto scat = [&](int comp, int gx, int gy, double v) {
+        if (tiled) {
+            int dx = gx - wx0, dy = gy - wy0;
+            if (dx < 0) dx += g.nx;
+            if (dy < 0) dy += g.ny;
+            if (dx < tw && dy < th) {
+                atomicAdd(&sT[(comp * th + dy) * tw + dx], v);
+                return;
+            }
+        }
+        unsafeAtomicAdd(&P.lE_prev[comp * G + gy * g.nx + gx], v);
+    };
+    auto body = [&](int64_t i) {
         int ix, iy;
         R fx, fy;
         if (!load_pos<MIX, DIM>(P.pos, i, g, ix, iy, fx, fy)) raise_err(P.err, ERR_DOMAIN);
@@ -227,16 +256,16 @@ __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>:
             const int32_t o = P.id0[i];
             if ((uint32_t)o >= (uint32_t)n) {
                 raise_err(P.err, ERR_ORDER);
-                continue;
+                return;
             }
             P.out_x[o] = (double)lx;
             if constexpr (DIM == 2) P.out_y[o] = (double)ly;
             P.out_vx[o] = (double)lvx;
             if constexpr (VDIM >= 2) P.out_vy[o] = (double)lvy;
             if constexpr (VDIM >= 3) P.out_vz[o] = (double)lvz;
-            continue;
+            return;
         }
-        if (!P.back) continue;
+        if (!P.back) return;
         if constexpr (HC) {
             static_assert(DIM == 2 && VDIM == 3, "the Higuera-Cary adjoint is 2D3V");
             // reverse of the step n-1 -> n: re-run the advance from the
@@ -244,7 +273,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>:
             const int32_t j = P.perm[i];
             if ((uint32_t)j >= (uint32_t)n) {
                 raise_err(P.err, ERR_ORDER);
-                continue;
+                return;
             }
             int jx, jy;
             R qx, qy;
@@ -279,14 +308,14 @@ __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>:
                 ex += fx;
                 ey += fy;
             }
-            unsafeAtomicAdd(&P.lE_prev[b00], (double)(w00 * ex));
-            unsafeAtomicAdd(&P.lE_prev[b10], (double)(w10 * ex));
-            unsafeAtomicAdd(&P.lE_prev[b01], (double)(w01 * ex));
-            unsafeAtomicAdd(&P.lE_prev[b11], (double)(w11 * ex));
-            unsafeAtomicAdd(&P.lE_prev[G + b00], (double)(w00 * ey));
-            unsafeAtomicAdd(&P.lE_prev[G + b10], (double)(w10 * ey));
-            unsafeAtomicAdd(&P.lE_prev[G + b01], (double)(w01 * ey));
-            unsafeAtomicAdd(&P.lE_prev[G + b11], (double)(w11 * ey));
+            scat(0, jx, jy, (double)(w00 * ex));
+            scat(0, jxp, jy, (double)(w10 * ex));
+            scat(0, jx, jyp, (double)(w01 * ex));
+            scat(0, jxp, jyp, (double)(w11 * ex));
+            scat(1, jx, jy, (double)(w00 * ey));
+            scat(1, jxp, jy, (double)(w10 * ey));
+            scat(1, jx, jyp, (double)(w01 * ey));
+            scat(1, jxp, jyp, (double)(w11 * ey));
             P.lxp_out[j] = lx;
             P.lxp_out[n + j] = ly;
             P.lep_out[j] = ex;
@@ -294,7 +323,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>:
             P.lv_out[j] = gx;
             P.lv_out[n + j] = gy;
             P.lv_out[2 * n + j] = gz;
-            continue;
+            return;
         }
         // reverse of the step n-1 -> n: move, then Boris
         R gx = lvx + P.dt * lx;
@@ -311,7 +340,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>:
         const int32_t j = P.perm[i];
         if ((uint32_t)j >= (uint32_t)n) {
             raise_err(P.err, ERR_ORDER);
-            continue;
+            return;
         }
         int jx, jy;
         R qx, qy;
@@ -320,22 +349,21 @@ __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>:
         int jxp = jx + 1;
         if (jxp >= g.nx) jxp = 0;
         if constexpr (DIM == 1) {
-            unsafeAtomicAdd(&P.lE_prev[jx], (double)((R(1) - qx) * ex));
-            unsafeAtomicAdd(&P.lE_prev[jxp], (double)(qx * ex));
+            scat(0, jx, 0, (double)((R(1) - qx) * ex));
+            scat(0, jxp, 0, (double)(qx * ex));
         } else {
             int jyp = jy + 1;
             if (jyp >= g.ny) jyp = 0;
             const R w00 = (R(1) - qx) * (R(1) - qy), w10 = qx * (R(1) - qy);
             const R w01 = (R(1) - qx) * qy, w11 = qx * qy;
-            const int b00 = jy * g.nx + jx, b10 = jy * g.nx + jxp, b01 = jyp * g.nx + jx, b11 = jyp * g.nx + jxp;
-            unsafeAtomicAdd(&P.lE_prev[b00], (double)(w00 * ex));
-            unsafeAtomicAdd(&P.lE_prev[b10], (double)(w10 * ex));
-            unsafeAtomicAdd(&P.lE_prev[b01], (double)(w01 * ex));
-            unsafeAtomicAdd(&P.lE_prev[b11], (double)(w11 * ex));
-            unsafeAtomicAdd(&P.lE_prev[G + b00], (double)(w00 * ey));
-            unsafeAtomicAdd(&P.lE_prev[G + b10], (double)(w10 * ey));
-            unsafeAtomicAdd(&P.lE_prev[G + b01], (double)(w01 * ey));
-            unsafeAtomicAdd(&P.lE_prev[G + b11], (double)(w11 * ey));
+            scat(0, jx, jy, (double)(w00 * ex));
+            scat(0, jxp, jy, (double)(w10 * ex));
+            scat(0, jx, jyp, (double)(w01 * ex));
+            scat(0, jxp, jyp, (double)(w11 * ex));
+            scat(1, jx, jy, (double)(w00 * ey));
+            scat(1, jxp, jy, (double)(w10 * ey));
+            scat(1, jx, jyp, (double)(w01 * ey));
+            scat(1, jxp, jyp, (double)(w11 * ey));
         }
         P.lxp_out[j] = lx;
         P.lep_out[j] = ex;
@@ -346,6 +374,43 @@ __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>:
         }
         if constexpr (VDIM >= 2) P.lv_out[n + j] = gy;
         if constexpr (VDIM >= 3) P.lv_out[2 * n + j] = lvz;   // no E_z and no z motion
+    };
+    if (!tiled) {
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+            body(i);
+        return;
+    }
+    // level-n buckets: the particles of one tile, their old positions within
+    // a couple of cells of it
+    int first, end, stride;
+    bucket_walk(g.nbuckets, first, end, stride);
+    const int nt = (DIM == 2 ? 2 : 1) * tw * th;
+    for (int b = first; b < end; b += stride) {
+        int bx, by;
+        tile_coords2<DIM>(g, b, bx, by);
+        wx0 = (bx << g.tsx) - H;
+        wx0 = wx0 < 0 ? wx0 + g.nx : wx0;
+        wy0 = 0;
+        if constexpr (DIM == 2) {
+            wy0 = (by << g.tsy) - H;
+            wy0 = wy0 < 0 ? wy0 + g.ny : wy0;
+        }
+        for (int t = threadIdx.x; t < nt; t += blockDim.x) sT[t] = 0.0;
+        __syncthreads();
+        const int64_t i0 = min(max((int64_t)P.bs[b], (int64_t)0), n);
+        const int64_t i1 = min(max((int64_t)P.bs[b + 1], i0), n);
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) body(i);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+            const double v = sT[t];
+            if (v == 0.0) continue;
+            const int comp = t / (tw * th), r = t % (tw * th);
+            int gx = wx0 + r % tw, gy = wy0 + r / tw;
+            gx = gx >= g.nx ? gx - g.nx : gx;
+            gy = gy >= g.ny ? gy - g.ny : gy;
+            unsafeAtomicAdd(&P.lE_prev[comp * G + gy * g.nx + gx], v);
+        }
+        __syncthreads();
     }
 }
 
@@ -526,6 +591,7 @@ struct AdjWs {
     size_t snap_pos_bytes;
     size_t snap_perm, snap_E;   // stride entries
     size_t snap_vel;            // stride entries of [3][n] velocities (Higuera-Cary)
+    size_t snap_bs;             // stride entries of the bucket table (nb + 1)
     size_t lam[2][3];           // ping-pong: lam_x carried, lam_Ep, lam_v
     size_t lE, lrho, W;
     size_t bytes;
@@ -570,6 +636,7 @@ AdjWs adj_layout(const apic_ctx *c, int stride) {
     L.snap_perm = take(align256(4 * n) * (size_t)stride);
     L.snap_E = take(align256(8 * (size_t)dim * G) * (size_t)stride);
     L.snap_vel = c->g.hc ? take(align256(r * 3 * n) * (size_t)stride) : (size_t)-1;
+    L.snap_bs = take(align256(4 * (size_t)(c->g.nbuckets + 1)) * (size_t)stride);
     for (int b = 0; b < 2; ++b) {
         L.lam[b][0] = take(r * dim * n);
         L.lam[b][1] = take(r * dim * n);
@@ -735,19 +802,32 @@ apic_status launch_level(apic_ctx *c, AdjP<R> &P, hipStream_t s) {
     boris_consts<R>(c, -0.5, P.ah, P.th, P.sh);
     const PushC pc = push_coeffs(c, 1.0, 1);
     P.ic2 = c->mixed ? (R)pc.ic2f : (R)pc.ic2;
+    // with the level's bucket table: one workgroup per bucket and the lam_Ep
+    // scatter into an LDS tile (tile + 2-cell halo per scattered component)
+    dim3 grid(nblocks(c->n));
+    size_t sh = 0;
+    if (P.bs) {
+        const int tw = (1 << c->g.tsx) + 5, th = c->d.dim == 2 ? (1 << c->g.tsy) + 5 : 1;
+        sh = (size_t)c->d.dim * tw * th * sizeof(double);
+        grid = dim3(grid_for_buckets(c->g.nbuckets));
+        if (sh > 65536) {
+            P.bs = nullptr;
+            sh = 0;
+            grid = dim3(nblocks(c->n));
+        }
+    }
     if (c->g.hc) {
         if (c->mixed) {
             if constexpr (std::is_same<R, float>::value)
-                hipLaunchKernelGGL((k_adj_level<true, 2, 3, true>), dim3(nblocks(c->n)), dim3(kBlock), 0, s, P);
+                hipLaunchKernelGGL((k_adj_level<true, 2, 3, true>), grid, dim3(kBlock), sh, s, P);
         } else {
             if constexpr (std::is_same<R, double>::value)
-                hipLaunchKernelGGL((k_adj_level<false, 2, 3, true>), dim3(nblocks(c->n)), dim3(kBlock), 0, s, P);
+                hipLaunchKernelGGL((k_adj_level<false, 2, 3, true>), grid, dim3(kBlock), sh, s, P);
         }
     } else {
         APIC_DISPATCH_2D(c->g, c->mixed, {
             if constexpr (std::is_same<R, typename RealOf<MIX>::T>::value)
-                hipLaunchKernelGGL((k_adj_level<MIX, DIM, VDIM, false>), dim3(nblocks(c->n)), dim3(kBlock), 0, s,
-                                   P);
+                hipLaunchKernelGGL((k_adj_level<MIX, DIM, VDIM, false>), grid, dim3(kBlock), sh, s, P);
         });
     }
     HIPCHK(c, hipGetLastError());
@@ -786,6 +866,8 @@ apic_status step_adjoint_impl(apic_ctx *c, char *ck, int nsteps, int stride, dou
     auto snap_E = [&](int k) { return (double *)(ws + L.snap_E + (size_t)k * align256(8 * (size_t)dim * G)); };
     const size_t r = c->mixed ? 4 : 8;
     auto snap_vel = [&](int k) { return ws + L.snap_vel + (size_t)k * align256(r * 3 * n); };
+    const size_t bs_bytes = 4 * (size_t)(c->g.nbuckets + 1);
+    auto snap_bs = [&](int k) { return (int32_t *)(ws + L.snap_bs + (size_t)k * align256(bs_bytes)); };
     // level T: only the objective depends on E^T
     hipLaunchKernelGGL(k_adj_scale, dim3(nblocks(dim * G)), dim3(kBlock), 0, s, (int64_t)dim * G,
                        (const double *)(ckp(C) + CL.E), lE, seed * c->dV);
@@ -807,6 +889,7 @@ apic_status step_adjoint_impl(apic_ctx *c, char *ck, int nsteps, int stride, dou
                 st = save_vel(c, pw, snap_vel(k), s);
                 if (st != APIC_OK) return st;
             }
+            HIPCHK(c, launch_copy_bytes(snap_bs(k), pw.bucket_start, (int64_t)bs_bytes, s));
             HIPCHK(c, launch_copy_bytes(snap_E(k), E_w, 8 * (int64_t)dim * G, s));
             pw.perm = snap_perm(k);
             st = apic_step(c, &pw, nullptr, E_w, nullptr, 1, nullptr, ws_ctx, s);
@@ -828,6 +911,7 @@ apic_status step_adjoint_impl(apic_ctx *c, char *ck, int nsteps, int stride, dou
             AdjP<R> P{};
             P.pos = (lvl == e) ? pos_ck(c, CL, ckp(seg + 1)) : pos_block(c, snap_pos(k));
             P.E = (lvl == e) ? (const double *)(ckp(seg + 1) + CL.E) : snap_E(k);
+            P.bs = (lvl == e) ? (const int32_t *)(ckp(seg + 1) + CL.bstart) : snap_bs(k);
             P.lrho = lrho;
             P.lxp_in = wsp<R>(ws, L.lam[cur][0]);
             P.lep_in = wsp<R>(ws, L.lam[cur][1]);
