@@ -25,6 +25,9 @@ here (each listed in the design notes of the repository):
     B^{n+1} = B^{n+1/2} - dt/2 curl E^{n+1} (the Yee leapfrog with B also
     held at integer times for the push);
   * the initial half push is backward, v^{-1/2} = Boris(v^0, E^0, B^0, -dt/2);
+  * with pusher "hc" the velocity advance is Higuera & Cary (2017) in its
+    general-field form, the state holds u = gamma v, the move and the current
+    use u / gamma;
   * energies: W_E = 1/2 sum |E|^2 dV, W_B = c^2/2 sum |B - B0|^2 dV (the
     self-consistent part), KE as in the electrostatic cycle.
 The particle loops are serial C (``em_oracle.c``); the field update is
@@ -72,6 +75,8 @@ def _load():
     L.or_em_gather_2d.restype = None
     L.or_boris3.argtypes = [_i64, _D, _D, _D, _D, _D, _dbl, _dbl]
     L.or_boris3.restype = None
+    L.or_hc3.argtypes = [_i64, _D, _D, _D, _D, _D, _dbl, _dbl, _dbl]
+    L.or_hc3.restype = None
     L.or_esirkepov_2d.argtypes = [_i64, _D, _D, _D, _D, _D, _int, _int, _dbl, _dbl, _dbl, _dbl, _D]
     L.or_esirkepov_2d.restype = _i64
     _lib = L
@@ -96,9 +101,22 @@ def gather(s: Setup, st: State, F: np.ndarray):
 
 
 def boris(s: Setup, st: State, Ep: np.ndarray, Bp: np.ndarray, dt: float) -> None:
-    """In-place Boris advance by dt in the gathered E and B ([3][n] each)."""
+    """In-place velocity advance by dt in the gathered E and B ([3][n] each):
+    Boris, or Higuera-Cary in its general-field form when s.pusher == "hc"
+    (the state then holds u = gamma v)."""
     n = st.x.shape[0]
+    if s.pusher == "hc":
+        _load().or_hc3(n, _p(st.vx), _p(st.vy), _p(st.vz), _p(_c64(Ep)), _p(_c64(Bp)), s.qm, dt, s.c)
+        return
     _load().or_boris3(n, _p(st.vx), _p(st.vy), _p(st.vz), _p(_c64(Ep)), _p(_c64(Bp)), s.qm, dt)
+
+
+def velocity(s: Setup, st: State):
+    """dx/dt of the state: v, or u / gamma with gamma = sqrt(1 + |u|^2/c^2)."""
+    if s.pusher != "hc":
+        return st.vx, st.vy, st.vz
+    g = np.sqrt(1.0 + (st.vx * st.vx + st.vy * st.vy + st.vz * st.vz) * (1.0 / (s.c * s.c)))
+    return st.vx / g, st.vy / g, st.vz / g
 
 
 def current(s: Setup, x0, y0, ddx, ddy, vz, q: float = None) -> np.ndarray:
@@ -194,7 +212,8 @@ def step(s: Setup, st: State, F: np.ndarray):
     boris(s, st, Ep, Bp, s.dt)
     v2_new = kinetic_sum(s, st)
     x0, y0 = st.x.copy(), st.y.copy()
-    J = current(s, x0, y0, st.vx * s.dt, st.vy * s.dt, st.vz)
+    vx, vy, vz = velocity(s, st)
+    J = current(s, x0, y0, vx * s.dt, vy * s.dt, vz)
     move(s, st)
     maxwell(s, F, J)
     return J, 0.5 * s.M * 0.5 * (v2_old + v2_new)

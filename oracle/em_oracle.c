@@ -102,6 +102,36 @@ void or_boris3(int64_t n, double *vx, double *vy, double *vz, const double *Ep, 
     }
 }
 
+/* Higuera & Cary (2017) in a general field, state u = gamma v:
+ * u- = u + a E, tau = a B, sigma = 1 + |u-|^2/c^2 - |tau|^2,
+ * gamma+^2 = (sigma + sqrt(sigma^2 + 4 (|tau|^2 + (u- . tau)^2 / c^2))) / 2,
+ * t = tau / gamma+, s = 1 / (1 + |t|^2),
+ * u+ = s (u- + (u- . t) t + u- x t), u = u+ + a E + u+ x t. */
+void or_hc3(int64_t n, double *ux, double *uy, double *uz, const double *Ep, const double *Bp, double qm, double dt,
+            double c)
+{
+    const double a = qm * dt * 0.5;
+    const double ic2 = 1.0 / (c * c);
+    for (int64_t p = 0; p < n; ++p) {
+        double ex = Ep[p], ey = Ep[n + p], ez = Ep[2 * n + p];
+        double tx = a * Bp[p], ty = a * Bp[n + p], tz = a * Bp[2 * n + p];
+        double mx = ux[p] + a * ex, my = uy[p] + a * ey, mz = uz[p] + a * ez;
+        double tau2 = tx * tx + ty * ty + tz * tz;
+        double sig = 1.0 + (mx * mx + my * my + mz * mz) * ic2 - tau2;
+        double us = mx * tx + my * ty + mz * tz;
+        double gp = sqrt(0.5 * (sig + sqrt(sig * sig + 4.0 * (tau2 + us * us * ic2))));
+        double wx = tx / gp, wy = ty / gp, wz = tz / gp;
+        double s = 1.0 / (1.0 + (wx * wx + wy * wy + wz * wz));
+        double mw = mx * wx + my * wy + mz * wz;
+        double px = s * (mx + mw * wx + (my * wz - mz * wy));
+        double py = s * (my + mw * wy + (mz * wx - mx * wz));
+        double pz = s * (mz + mw * wz + (mx * wy - my * wx));
+        ux[p] = px + a * ex + (py * wz - pz * wy);
+        uy[p] = py + a * ey + (pz * wx - px * wz);
+        uz[p] = pz + a * ez + (px * wy - py * wx);
+    }
+}
+
 /* Hat weights of a particle at fraction f0 of cell 0, moved by d cells, on the
  * local nodes k = -1..2 (index k + 1): S0, and S1 with the new cell in
  * {-1, 0, 1}. Returns 0 when |d| >= 1. */

@@ -295,3 +295,89 @@ def test_cold_plasma_langmuir_oscillation():
     w = _frequency(np.array(ts), np.array(amp))
     assert abs(w - 1.0) < 0.01, w
     assert np.max(np.abs(F[3:])) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Higuera-Cary in the electromagnetic step (general field, state u = gamma v)
+# ---------------------------------------------------------------------------
+
+def _hc_setup(n, c=2.0, dt=0.1, bz=0.0):
+    return O.Setup(2, 3, 8, 8.0, n, dt, ny=8, Ly=8.0, bz=bz, pusher="hc", c=c)
+
+
+def test_hc3_with_b_along_z_is_the_electrostatic_higuera_cary():
+    rng = np.random.default_rng(111)
+    n = 300
+    s = _hc_setup(n, bz=1.7)
+    u = rng.normal(size=(n, 3)) * 2
+    E = rng.normal(size=(3, n))
+    a = _st(u, n)
+    b = _st(u, n)
+    M.boris(s, a, E, np.vstack([np.zeros((2, n)), np.full(n, s.bz)]), s.dt)
+    O.boris(s, b, (E[0], E[1], E[2]), s.dt)
+    for x, y in ((a.vx, b.vx), (a.vy, b.vy), (a.vz, b.vz)):
+        assert np.max(np.abs(x - y)) < 1e-13
+
+
+def test_hc3_satisfies_the_implicit_midpoint_relation_in_a_general_field():
+    """u1 - u0 = 2 a E + (u0 + u1) x (a B / gamma(ubar)), ubar = (u0 + u1)/2."""
+    rng = np.random.default_rng(112)
+    n = 400
+    for c in (0.8, 2.0, 9.0):
+        s = _hc_setup(n, c=c)
+        a = s.qm * s.dt / 2
+        u0 = rng.normal(size=(n, 3)) * 2
+        E = rng.normal(size=(3, n))
+        B = rng.normal(size=(3, n)) * 2
+        st = _st(u0, n)
+        M.boris(s, st, E, B, s.dt)
+        u1 = np.stack([st.vx, st.vy, st.vz], axis=1)
+        ub = 0.5 * (u0 + u1)
+        gb = np.sqrt(1 + np.sum(ub * ub, axis=1) / c ** 2)
+        r = u1 - u0 - 2 * a * E.T - np.cross(u0 + u1, (a * B / gb).T)
+        assert np.max(np.abs(r)) < 1e-13 * (1 + np.abs(u1).max()), c
+
+
+def test_hc3_limits_and_exb_drift():
+    rng = np.random.default_rng(113)
+    n = 200
+    E = rng.normal(size=(3, n))
+    B = rng.normal(size=(3, n)) * 2
+    u = rng.normal(size=(n, 3))
+    # c -> infinity: the general-field Boris advance
+    sh = _hc_setup(n, c=1e30)
+    sb = O.Setup(2, 3, 8, 8.0, n, 0.1, ny=8, Ly=8.0, c=5.0)
+    a, b = _st(u, n), _st(u, n)
+    for _ in range(5):
+        M.boris(sh, a, E, B, sh.dt)
+        M.boris(sb, b, E, B, sb.dt)
+    for x, y in ((a.vx, b.vx), (a.vy, b.vy), (a.vz, b.vz)):
+        assert np.max(np.abs(x - y)) < 1e-12
+    # E perpendicular to B with |E x B| / B^2 < c: u = gamma_d v_d is a fixed point
+    c = 3.0
+    s = _hc_setup(n, c=c)
+    E = E - B * (np.sum(E * B, axis=0) / np.sum(B * B, axis=0))
+    E *= 0.5 * c * np.linalg.norm(B, axis=0) / np.linalg.norm(E, axis=0)       # |v_d| = c / 2
+    vd = np.cross(E.T, B.T) / np.sum(B * B, axis=0)[:, None]
+    ud = vd / np.sqrt(1 - np.sum(vd * vd, axis=1) / c ** 2)[:, None]
+    st = _st(ud, n)
+    for _ in range(50):
+        M.boris(s, st, E, B, s.dt)
+    got = np.stack([st.vx, st.vy, st.vz], axis=1)
+    assert np.max(np.abs(got - ud)) < 1e-12 * (1 + np.abs(ud).max())
+
+
+def test_hc_cycle_keeps_gauss_law():
+    """The current of the move by u / gamma keeps div E = rho over 20 steps of a
+    mildly relativistic magnetized plasma."""
+    w = dataclasses.replace(W.magnetized_2d3v(seed=114, nx=16, ppc=16), mode=(1, 0))
+    x, y, vx, vy, vz = W.sample(w)
+    n = len(x)
+    s = O.Setup(2, 3, w.nx, w.Lx, n, 0.1, ny=w.ny, Ly=w.Ly, bz=w.bz, c=5.0, pusher="hc")
+    st = O.State.from_arrays(x, 1.5 * vx, y, 1.5 * vy, 1.5 * vz)
+    F = M.initialise(s, st)
+    scale = np.max(np.abs(O.deposit(s, st)))
+    for _ in range(20):
+        M.step(s, st, F)
+    assert np.max(np.abs(M.divergence_e(s, F) - O.deposit(s, st))) < 1e-11 * scale
+    assert np.max(np.abs(M.divergence_b(s, F))) < 1e-11 * (1 + np.max(np.abs(F[3:])))
