@@ -109,7 +109,7 @@ typedef struct {
     int tile_z;           /* 3D: bucket tile size along z (0 = default)         */
     int pusher;           /* apic_pusher (0 = Boris)                            */
     double c_light;       /* speed of light (> 0) for APIC_HIGUERA_CARY and for
-                             APIC_ELECTROMAGNETIC                               */
+                             APIC_ELECTROMAGNETIC (either pusher)               */
     int model;            /* apic_field_model (0 = electrostatic)               */
     int walls_x;          /* 1: grounded absorbing walls at x = 0 and x = lx
                              (2D electrostatic; see "walls" below); 0: periodic */
@@ -340,9 +340,12 @@ apic_status apic_step_adjoint(apic_ctx *ctx, const void *ckpt, int nsteps, int s
  * on a periodic Yee grid in normalised units eps0 = 1, mu0 = 1/c^2
  * (c = c_light). The FP64 path pushes in FP64; the mixed path keeps its
  * particle representation (cell + binary32 offsets and velocities) and runs
- * the field tile, gather, Boris and the current weights in binary32, the
- * displacement of the current deposit being the binary32 product its move
- * adds; the current sums, the field update and F stay FP64 in both:
+ * the field tile, gather, velocity advance and the current weights in
+ * binary32, the displacement of the current deposit being the binary32
+ * product its move adds; the current sums, the field update and F stay FP64
+ * in both. The velocity advance is Boris, or with pusher =
+ * APIC_HIGUERA_CARY the general-field Higuera-Cary advance of u = gamma v,
+ * the move and the current then using u / gamma (the same quotient):
  *   - F [dev, double, 6*G] holds Ex, Ey, Ez, Bx, By, Bz, each [ny][nx], with
  *     element [j][i] of Ex at ((i+1/2) dx, j dy), Ey at (i dx, (j+1/2) dy),
  *     Ez at (i dx, j dy), Bx at (i dx, (j+1/2) dy), By at ((i+1/2) dx, j dy)
@@ -350,8 +353,8 @@ apic_status apic_step_adjoint(apic_ctx *ctx, const void *ckpt, int nsteps, int s
  *     Bz starts at bz and the update keeps a uniform field);
  *   - J [dev, double, 3*G]: Jx, Jy, Jz at the Ex, Ey, Ez locations;
  *   - one step: E and B interpolated to x^n (linear weights on each
- *     component's own staggered lattice), Boris v^{n-1/2} -> v^{n+1/2} in that
- *     B, move with periodic wrap, the current J^{n+1/2} of the move by the
+ *     component's own staggered lattice), the advance v^{n-1/2} -> v^{n+1/2}
+ *     in that E and B, move with periodic wrap, the current J^{n+1/2} of the move by the
  *     charge-conserving scheme of Esirkepov (2001) for the linear shape
  *     (a displacement of a cell or more along an axis is an APIC_EDOMAIN
  *     error), counting sort into the next bucket order, then
@@ -371,9 +374,9 @@ apic_status apic_step_adjoint(apic_ctx *ctx, const void *ckpt, int nsteps, int s
  * (bucket_start valid) or not; ws: the context workspace. */
 apic_status apic_em_init_fields(apic_ctx *ctx, const apic_particles *p, double *F, void *ws, void *stream);
 
-/* E and B gathered at each particle, Boris advance by dt_scale * dt (the
- * initial backward half push uses -0.5), then the move when move != 0;
- * in place, any order. */
+/* E and B gathered at each particle, the context's velocity advance by
+ * dt_scale * dt (the initial backward half push uses -0.5), then the move
+ * when move != 0; in place, any order. */
 apic_status apic_em_gather_push(apic_ctx *ctx, apic_particles *p, const double *F, double dt_scale, int move,
                                 void *stream);
 

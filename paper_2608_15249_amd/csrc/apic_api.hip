@@ -295,8 +295,7 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
         if (d.nx > 16384) return APIC_EINVAL;
     }
     if (d.model == APIC_ELECTROMAGNETIC) {
-        if (d.dim != 2 || d.vdim != 3 || d.pusher != APIC_BORIS || !(d.c_light > 0) || !std::isfinite(d.c_light))
-            return APIC_EINVAL;
+        if (d.dim != 2 || d.vdim != 3 || !(d.c_light > 0) || !std::isfinite(d.c_light)) return APIC_EINVAL;
         // Courant condition of the Yee update
         const double dx = d.lx / d.nx, dy = d.ly / d.ny;
         if (!(d.c_light * d.dt * std::sqrt(1.0 / (dx * dx) + 1.0 / (dy * dy)) < 1.0)) return APIC_EINVAL;

@@ -83,6 +83,31 @@ __device__ __forceinline__ void boris3(R &vx, R &vy, R &vz, const R e[3], const 
     vz = pz + a * e[2];
 }
 
+// Higuera & Cary (2017) in a general field, state u = gamma v (a = (q/m)
+// dt_eff / 2, ic2 = 1/c^2): u- = u + a E, tau = a B,
+// sigma = 1 + |u-|^2/c^2 - |tau|^2,
+// gamma+ = sqrt((sigma + sqrt(sigma^2 + 4 (|tau|^2 + (u- . tau)^2/c^2))) / 2),
+// t = tau / gamma+, s = 1 / (1 + |t|^2), u+ = s (u- + (u- . t) t + u- x t),
+// u = u+ + a E + u+ x t.
+template <typename R>
+__device__ __forceinline__ void hc3(R &ux, R &uy, R &uz, const R e[3], const R b[3], R a, R ic2) {
+    const R tx = a * b[0], ty = a * b[1], tz = a * b[2];
+    const R mx = ux + a * e[0], my = uy + a * e[1], mz = uz + a * e[2];
+    const R tau2 = tx * tx + ty * ty + tz * tz;
+    const R sig = R(1) + (mx * mx + my * my + mz * mz) * ic2 - tau2;
+    const R us = mx * tx + my * ty + mz * tz;
+    const R gp = sqrt(R(0.5) * (sig + sqrt(sig * sig + R(4) * (tau2 + us * us * ic2))));
+    const R wx = tx / gp, wy = ty / gp, wz = tz / gp;
+    const R s = R(1) / (R(1) + (wx * wx + wy * wy + wz * wz));
+    const R mw = mx * wx + my * wy + mz * wz;
+    const R px = s * (mx + mw * wx + (my * wz - mz * wy));
+    const R py = s * (my + mw * wy + (mz * wx - mx * wz));
+    const R pz = s * (mz + mw * wz + (mx * wy - my * wx));
+    ux = px + a * e[0] + (py * wz - pz * wy);
+    uy = py + a * e[1] + (pz * wx - px * wz);
+    uz = pz + a * e[2] + (px * wy - py * wx);
+}
+
 // Hat weights of one axis on a three-node window starting at node s0 of the
 // old cell (s0 = min(0, c1)): S0 of the old fraction f0, S1 after a move by d
 // cells (new cell c1 = floor(f0 + d) in {-1, 0, 1}). False when |d| >= 1.

@@ -136,7 +136,7 @@ __device__ __forceinline__ R lerp_glob(const double *f, const Geo &g, int i, int
            (R(1) - fx) * fy * (R)f[r1 + i] + fx * fy * (R)f[r1 + ip];
 }
 
-template <bool MIX>
+template <bool MIX, bool HC>
 __global__ void __launch_bounds__(kBlock) k_em_gather_push(Geo g, Parts p, int64_t n, const double *F, PushC pc,
                                                            CtxDev c) {
     using R = typename Pt<MIX>::R;
@@ -155,10 +155,18 @@ __global__ void __launch_bounds__(kBlock) k_em_gather_push(Geo g, Parts p, int64
         b[0] = lerp_glob<R>(F + 3 * G, g, q.ix, ay1, q.fx, fy1);
         b[1] = lerp_glob<R>(F + 4 * G, g, ax1, q.iy, fx1, q.fy);
         b[2] = lerp_glob<R>(F + 5 * G, g, ax1, ay1, fx1, fy1);
-        boris3<R>(q.vx, q.vy, q.vz, e, b, MIX ? (R)pc.af : (R)pc.a);
-        if (pc.move) {
-            int sx, sy, sz;
-            ok = move_pt<MIX, 2>(q, g, pc, sx, sy, sz) && ok;
+        const R a = MIX ? (R)pc.af : (R)pc.a;
+        int sx, sy, sz;
+        if constexpr (HC) {
+            const R ic2 = MIX ? (R)pc.ic2f : (R)pc.ic2;
+            hc3<R>(q.vx, q.vy, q.vz, e, b, a, ic2);
+            if (pc.move) {
+                const R gm = lorentz<R>(q.vx, q.vy, q.vz, ic2);
+                ok = move_pt_v<MIX, 2>(q, g, pc, q.vx / gm, q.vy / gm, q.vz / gm, sx, sy, sz) && ok;
+            }
+        } else {
+            boris3<R>(q.vx, q.vy, q.vz, e, b, a);
+            if (pc.move) ok = move_pt<MIX, 2>(q, g, pc, sx, sy, sz) && ok;
         }
         if (!ok) bad = 1;
         store_pt<MIX, 2, 3>(p, i, q);
@@ -181,10 +189,15 @@ hipError_t launch_em_init(const Geo &g, const double *phi, double bz, double *F,
 
 hipError_t launch_em_gather_push(const Geo &g, bool mixed, const Parts &p, int64_t n, const double *F,
                                  const PushC &pc, const CtxDev &c, hipStream_t s) {
-    if (mixed)
-        hipLaunchKernelGGL(k_em_gather_push<true>, dim3(em_blocks(n, 8192)), dim3(kBlock), 0, s, g, p, n, F, pc, c);
+    const dim3 grid(em_blocks(n, 8192));
+    if (mixed && g.hc)
+        hipLaunchKernelGGL((k_em_gather_push<true, true>), grid, dim3(kBlock), 0, s, g, p, n, F, pc, c);
+    else if (mixed)
+        hipLaunchKernelGGL((k_em_gather_push<true, false>), grid, dim3(kBlock), 0, s, g, p, n, F, pc, c);
+    else if (g.hc)
+        hipLaunchKernelGGL((k_em_gather_push<false, true>), grid, dim3(kBlock), 0, s, g, p, n, F, pc, c);
     else
-        hipLaunchKernelGGL(k_em_gather_push<false>, dim3(em_blocks(n, 8192)), dim3(kBlock), 0, s, g, p, n, F, pc, c);
+        hipLaunchKernelGGL((k_em_gather_push<false, false>), grid, dim3(kBlock), 0, s, g, p, n, F, pc, c);
     return hipGetLastError();
 }
 

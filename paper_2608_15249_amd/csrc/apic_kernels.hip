@@ -207,12 +207,15 @@ __device__ __forceinline__ bool advance(Pt<MIX> &q, const Geo &g, const PushC &p
 }
 
 // Electromagnetic form (2D3V): E and B gathered from the Yee field tile
-// (nodes from (x0-1, y0-1), width fw), Boris in B, move. (lx, ly) and
-// (fx0, fy0) return the old local cell and fractions for the current deposit.
-template <bool MIX>
+// (nodes from (x0-1, y0-1), width fw), Boris (or Higuera-Cary with the state
+// u = gamma v) in B, move. (lx, ly) and (fx0, fy0) return the old local cell
+// and fractions for the current deposit, gm the Lorentz factor the move
+// divided u by (1 for Boris).
+template <bool MIX, bool HC>
 __device__ __forceinline__ bool advance_em(Pt<MIX> &q, const Geo &g, const PushC &pc,
                                            const typename Pt<MIX>::R *sF, int fw, int x0, int y0, int &lx, int &ly,
-                                           int &sx, int &sy, typename Pt<MIX>::R &fx0, typename Pt<MIX>::R &fy0) {
+                                           int &sx, int &sy, typename Pt<MIX>::R &fx0, typename Pt<MIX>::R &fy0,
+                                           typename Pt<MIX>::R &gm) {
     using R = typename Pt<MIX>::R;
     const int tx = 1 << g.tsx, ty = 1 << g.tsy;
     lx = q.ix - x0;
@@ -228,9 +231,17 @@ __device__ __forceinline__ bool advance_em(Pt<MIX> &q, const Geo &g, const PushC
     fy0 = q.fy;
     R e[3], b[3];
     gather_em<R>(sF, fw, fw * (ty + 2), lx, ly, q.fx, q.fy, e, b);
-    boris3<R>(q.vx, q.vy, q.vz, e, b, MIX ? (R)pc.af : (R)pc.a);
     int sz;
-    return move_pt<MIX, 2>(q, g, pc, sx, sy, sz) && in;
+    if constexpr (HC) {
+        const R ic2 = MIX ? (R)pc.ic2f : (R)pc.ic2;
+        hc3<R>(q.vx, q.vy, q.vz, e, b, MIX ? (R)pc.af : (R)pc.a, ic2);
+        gm = lorentz<R>(q.vx, q.vy, q.vz, ic2);
+        return move_pt_v<MIX, 2>(q, g, pc, q.vx / gm, q.vy / gm, q.vz / gm, sx, sy, sz) && in;
+    } else {
+        boris3<R>(q.vx, q.vy, q.vz, e, b, MIX ? (R)pc.af : (R)pc.a);
+        gm = R(1);
+        return move_pt<MIX, 2>(q, g, pc, sx, sy, sz) && in;
+    }
 }
 
 // Raw stored words of one particle: loaded unconditionally (the caller clamps
@@ -775,7 +786,7 @@ template <bool MIX, int DIM, int VDIM, int U, bool HC, bool EM>
 __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int32_t *bstart, const double *E,
                                                        PushC pc, int32_t *cnt, int32_t *tot, int32_t *farcnt,
                                                        const int32_t *deep, CtxDev c) {
-    static_assert(!EM || (DIM == 2 && VDIM == 3 && !HC), "the electromagnetic step is 2D3V with Boris");
+    static_assert(!EM || (DIM == 2 && VDIM == 3), "the electromagnetic step is 2D3V");
     using R = typename Pt<MIX>::R;
     constexpr int kDirs = Dir<DIM>::kN, kFar = Dir<DIM>::kFar, kStay = Dir<DIM>::kStay, kTab = Dir<DIM>::kTab;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -880,8 +891,9 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
                 bool good = decode<MIX, DIM, VDIM>(r1, g, q);
                 int lx, ly, lz = 0, sx, sy, sz = 0;
                 if constexpr (EM) {
-                    R f0x, f0y;
-                    good = advance_em<MIX>(q, g, pc, (const R *)smem, fw, x0, y0, lx, ly, sx, sy, f0x, f0y) && good;
+                    R f0x, f0y, gm;
+                    good = advance_em<MIX, HC>(q, g, pc, (const R *)smem, fw, x0, y0, lx, ly, sx, sy, f0x, f0y, gm) &&
+                           good;
                 } else {
                     good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx, sy,
                                                        sz) && good;
@@ -919,9 +931,9 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
                     bool good = decode<MIX, DIM, VDIM>(r[j], g, q);
                     int lx, ly, lz = 0, sx, sy, sz = 0;
                     if constexpr (EM) {
-                        R f0x, f0y;
-                        good = advance_em<MIX>(q, g, pc, (const R *)smem, fw, x0, y0, lx, ly, sx, sy, f0x, f0y) &&
-                               good;
+                        R f0x, f0y, gm;
+                        good = advance_em<MIX, HC>(q, g, pc, (const R *)smem, fw, x0, y0, lx, ly, sx, sy, f0x, f0y,
+                                                   gm) && good;
                     } else {
                         good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx,
                                                            sy, sz) && good;
@@ -1137,9 +1149,9 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                     bool good = decode<MIX, DIM, VDIM>(r[j], g, q);
                     const double v2o = vsq<MIX, VDIM, HC>(q, pc);
                     int lx, ly, lz = 0, sx, sy, sz = 0;
-                    R f0x = R(0), f0y = R(0);
+                    R f0x = R(0), f0y = R(0), gm = R(1);
                     if constexpr (EM) {
-                        good = advance_em<MIX>(q, g, pc, sE, fw, x0, y0, lx, ly, sx, sy, f0x, f0y) && good;
+                        good = advance_em<MIX, HC>(q, g, pc, sE, fw, x0, y0, lx, ly, sx, sy, f0x, f0y, gm) && good;
                     } else {
                         good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx,
                                                            sy, sz) && good;
@@ -1187,16 +1199,18 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
                     } else if constexpr (EM) {
                         // current J^{n+1/2} of the move x^n -> x^{n+1} (Esirkepov); the
                         // mixed path's displacement is the binary32 product its move adds
+                        // (with Higuera-Cary the velocity is u / gamma, the quotient the move used)
+                        const R wvx = q.vx / gm, wvy = q.vy / gm, wvz = q.vz / gm;
                         R ddx, ddy;
                         if constexpr (MIX) {
-                            ddx = q.vx * pc.dtdx;
-                            ddy = q.vy * pc.dtdy;
+                            ddx = wvx * pc.dtdx;
+                            ddy = wvy * pc.dtdy;
                         } else {
-                            ddx = (q.vx * pc.dt) * g.inv_dx;
-                            ddy = (q.vy * pc.dt) * g.inv_dy;
+                            ddx = (wvx * pc.dt) * g.inv_dx;
+                            ddy = (wvy * pc.dt) * g.inv_dy;
                         }
                         if (!esirkepov_lds<R>((double *)sA, jw, jw * jh, lx, ly, f0x, f0y, ddx, ddy, pc.jx, pc.jy,
-                                              pc.jz * (double)q.vz))
+                                              pc.jz * (double)wvz))
                             atomicOr(&sErr, ERR_DOMAIN);
                     } else {
                     // deposit rho^{n+1}: LDS tile + halo, global beyond it
@@ -1691,15 +1705,14 @@ hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int
                              const CtxDev &c, hipStream_t s) {
     if (g.em) {
         const size_t sh = em_f_tile_bytes(g, mixed);
-        if (mixed) {
-            auto kern = k_step_count<true, 2, 3, APIC_STEP_U, false, true>;
+        auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, p, bstart,
                                E, pc, cnt, tot, farcnt, deep, c);
-        } else {
-            auto kern = k_step_count<false, 2, 3, APIC_STEP_U, false, true>;
-            hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, p, bstart,
-                               E, pc, cnt, tot, farcnt, deep, c);
-        }
+        };
+        if (mixed && g.hc) go(k_step_count<true, 2, 3, APIC_STEP_U, true, true>);
+        else if (mixed) go(k_step_count<true, 2, 3, APIC_STEP_U, false, true>);
+        else if (g.hc) go(k_step_count<false, 2, 3, APIC_STEP_U, true, true>);
+        else go(k_step_count<false, 2, 3, APIC_STEP_U, false, true>);
         return hipGetLastError();
     }
     size_t sh = tile_e_bytes(g, mixed);
@@ -1736,16 +1749,16 @@ hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Pa
                             const CtxDev &c, hipStream_t s) {
     if (g.em) {
         const size_t sh = em_j_tile_bytes(g) + em_f_tile_bytes(g, mixed);
-        if (mixed) {
-            auto kern = k_step_push<true, 2, 3, APIC_STEP_U, false, true>;
+        auto go = [&](auto kern, auto *accp) {
             hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, src, dst,
-                               bstart, bstart_new, cnt, offs, farcnt, E, pc, (unsigned long long *)acc, perm, part,
-                               deep, c);
-        } else {
-            auto kern = k_step_push<false, 2, 3, APIC_STEP_U, false, true>;
-            hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, src, dst,
-                               bstart, bstart_new, cnt, offs, farcnt, E, pc, (double *)acc, perm, part, deep, c);
-        }
+                               bstart, bstart_new, cnt, offs, farcnt, E, pc, accp, perm, part, deep, c);
+        };
+        unsigned long long *am = (unsigned long long *)acc;
+        double *ad = (double *)acc;
+        if (mixed && g.hc) go(k_step_push<true, 2, 3, APIC_STEP_U, true, true>, am);
+        else if (mixed) go(k_step_push<true, 2, 3, APIC_STEP_U, false, true>, am);
+        else if (g.hc) go(k_step_push<false, 2, 3, APIC_STEP_U, true, true>, ad);
+        else go(k_step_push<false, 2, 3, APIC_STEP_U, false, true>, ad);
         return hipGetLastError();
     }
     size_t sh = tile_acc_bytes(g, g.halo) + tile_e_bytes(g, mixed);
