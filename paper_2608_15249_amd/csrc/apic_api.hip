@@ -3,6 +3,8 @@
 #include "apic.h"
 #include "apic_ctx.h"
 
+#include <cstdlib>
+
 #include <hipfft/hipfft.h>
 
 #include <cmath>
@@ -226,6 +228,14 @@ apic_status field_from_acc(apic_ctx *c, void *acc, bool acc_is_rho, double *E, f
     double *rho = wsp<double>(ws, c->o_rho);
     void *rhat = wsp<void>(ws, c->o_rhat);
     char *ehat = wsp<char>(ws, c->o_ehat);
+    if (c->fused_fft) {
+        // half spectra in rhat, the x-spectrum of Ex + i Ey ([ny][nx] complex) in ehat
+        const FinArgs fin{diag ? npush : 0, 0, c->mass, c->dV, G, c->d.rho_ion, diag, we, charge, c->g.walls,
+                          c->d.q_macro, nlive};
+        HIPCHK(c, launch_fused_field(c->g, mixed_acc, acc, scale, add, clear, rhat, ehat, E, E32, c->dev.tw, fin,
+                                     c->dev, s));
+        return APIC_OK;
+    }
     if (c->g.walls)
         HIPCHK(c, launch_rho_odd(c->g, mixed_acc, acc, rho, scale, add, clear, s));
     else
@@ -389,10 +399,16 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
 
     // context device words + wavenumber tables
     const int hx = g.nx / 2 + 1;
+    // the fused field solve (unless APIC_FIELD_FFT=library asks for the
+    // library transforms, for comparison)
+    const char *fft_env = std::getenv("APIC_FIELD_FFT");
+    c->fused_fft = fused_fft_supported(d.dim, g.nx, g.ny, g.nz) && !(fft_env && std::string(fft_env) == "library");
+    const int nmax = g.nx > g.ny ? g.nx : g.ny;
+    const size_t tw_bytes = c->fused_fft ? 2 * sizeof(double) * nmax : 0;   // nmax complex
     size_t bytes = align256(sizeof(int)) * 2 + align256(sizeof(double) * 2 * g.nbuckets) +
                    align256(sizeof(double) * kMaxSpecBlocks) + align256(sizeof(double)) +
                    align256(sizeof(double) * hx) * 2 + align256(sizeof(double) * g.ny) * 2 +
-                   align256(sizeof(double) * g.nz) * 2;
+                   align256(sizeof(double) * g.nz) * 2 + align256(tw_bytes);
     if (hipMalloc(&c->dev_block, bytes) != hipSuccess) { delete c; return APIC_ENOMEM; }
     if (hipMemset(c->dev_block, 0, bytes) != hipSuccess) { (void)hipFree(c->dev_block); delete c; return APIC_EHIP; }
     char *b = (char *)c->dev_block;
@@ -409,6 +425,7 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     c->dev.kapy = (double *)take(sizeof(double) * g.ny);
     c->dev.kz2 = (double *)take(sizeof(double) * g.nz);
     c->dev.kapz = (double *)take(sizeof(double) * g.nz);
+    c->dev.tw = c->fused_fft ? (double *)take(tw_bytes) : nullptr;
     // modified wavenumbers of the periodic FD operators:
     //   K^2_d = (2/d sin(k d / 2))^2 (3-point second difference),
     //   kappa_d = sin(k d)/d (centred first difference), k = 2 pi m / L.
@@ -438,6 +455,16 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
                   hipMemcpy(c->dev.kapy, kapy.data(), sizeof(double) * g.ny, hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->dev.kz2, kz2.data(), sizeof(double) * g.nz, hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->dev.kapz, kapz.data(), sizeof(double) * g.nz, hipMemcpyHostToDevice) == hipSuccess;
+    if (copied && c->fused_fft) {
+        // exp(-2 pi i k / nmax), k < nmax; the angle 2 pi k / nmax is one rounding of pi times an exact ratio
+        std::vector<double> tw(2 * nmax);
+        for (int k = 0; k < nmax; ++k) {
+            const double ang = M_PI * (2.0 * k / nmax);
+            tw[2 * k] = std::cos(ang);
+            tw[2 * k + 1] = -std::sin(ang);
+        }
+        copied = hipMemcpy(c->dev.tw, tw.data(), tw_bytes, hipMemcpyHostToDevice) == hipSuccess;
+    }
     if (!copied) {
         (void)hipFree(c->dev_block);
         delete c;

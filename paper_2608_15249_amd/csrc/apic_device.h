@@ -672,6 +672,44 @@ __device__ double field1d_block(double *sr, int nx, double dx, double *E, float 
     return wsum;
 }
 
+// Field diagnostics of one solve (one workgroup): fixed-order sums of the
+// spectral and push partials into diag[step] or we/charge.
+__device__ void finalize_block(const FinArgs &f, const CtxDev &c) {
+    __shared__ double sRed[16];
+    double k = 0.0, p = 0.0, e = 0.0;
+    for (int i = threadIdx.x; i < f.npush; i += blockDim.x) {
+        k += c.part_push[2 * i];
+        p += c.part_push[2 * i + 1];
+    }
+    for (int i = threadIdx.x; i < f.nspec; i += blockDim.x) e += c.part_spec[i];
+    k = block_sum(k, sRed);
+    p = block_sum(p, sRed);
+    e = block_sum(e, sRed);
+    if (threadIdx.x == 0) {
+        double *d = f.diag ? step_slot(f.diag, c) : nullptr;
+        if (f.npush && d) {
+            d[2] = 0.5 * f.mass * k;
+            d[3] = f.mass * p;
+        }
+        if (f.nspec) {
+            double wE = 0.5 * f.dV / f.G * e;
+            double q = f.dV * (*c.rho0 - f.G * f.rho_ion);
+            if (f.walls) {
+                // the physical half of the odd extension, wall nodes at half weight
+                wE = 0.5 * wE;
+                q = f.nlive ? f.q_macro * (double)*f.nlive : 0.0;
+            }
+            if (d) {
+                d[0] = q;
+                d[1] = wE;
+            }
+            if (f.we) *f.we = wE;
+            if (f.charge) *f.charge = q;
+        }
+    }
+}
+
+
 }  // namespace
 }  // namespace apic
 

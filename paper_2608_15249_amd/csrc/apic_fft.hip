@@ -1,0 +1,349 @@
+// Periodic 2D Poisson solve on power-of-two grids (up to 1024 nodes per
+// axis) in three launches, for the field step of the cycle: charge
+// accumulation -> rho -> phi (5-point Laplacian, zero mean) -> E = -(centred
+// difference of phi), with the field-energy and charge diagnostics.
+//
+//   1. k_fft_rows: one workgroup per pair of rows. rho of both rows from the
+//      accumulation buffer (cleared behind it), one complex FFT along x of
+//      rho_j0 + i rho_j1 in LDS, split into the two rows' half spectra
+//      H [ny][nx/2+1] (the layout of a real-to-complex transform).
+//   2. k_fft_cols: one workgroup per column kx of H. FFT along y, then
+//      phi_hat = rho_hat / K^2 (K^2 the Laplacian's modified wavenumber,
+//      phi_hat(0) = 0) and E_hat_d = -i kappa_d phi_hat (kappa_d = sin(k d)/d,
+//      the centred difference), with the per-block Parseval partial of
+//      sum |E_hat|^2. Inverse FFT along y of phi_hat and kappa_y phi_hat; the
+//      x-spectrum Z of the complex field Ex + i Ey follows at columns kx and
+//      nx - kx from the Hermitian symmetry of the two real fields.
+//   3. k_fft_rows_inv: one workgroup per row. Inverse FFT along x of Z:
+//      Ex = Re, Ey = Im (and their binary32 rounding). The launch's last
+//      workgroup reduces the diagnostics.
+// The same mathematics as the general path (library real-to-complex
+// transforms, spectral division, real-space centred difference); the
+// gradient is taken in spectral form, -i sin(k d)/d, which is the transform
+// of the centred difference exactly.
+//
+// Transforms: Stockham passes between two LDS buffers (the output in natural
+// order, one barrier per pass), radix 8 in registers after one radix-2 or
+// radix-4 pass; twiddles exp(-2 pi i k / nmax) from a table in global memory
+// (16 KiB at most, cache resident).
+#include "apic_device.h"
+
+namespace apic {
+namespace {
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// x * (SIGN i)
+template <int SIGN>
+__device__ __forceinline__ double2 rot_i(double2 x) {
+    return SIGN < 0 ? make_double2(x.y, -x.x) : make_double2(-x.y, x.x);
+}
+
+// In-register DFTs of 2, 4 and 8 points, kernel exp(SIGN 2 pi i j k / R),
+// outputs in natural order. The 8-point one combines the 4-point DFTs of
+// the even and odd inputs with the factors w^k, w = exp(SIGN 2 pi i / 8).
+__device__ __forceinline__ void dft2(double2 &a, double2 &b) {
+    const double2 t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+template <int SIGN>
+__device__ __forceinline__ void dft4(double2 &v0, double2 &v1, double2 &v2, double2 &v3) {
+    const double2 t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3), u = rot_i<SIGN>(csub(v1, v3));
+    v0 = cadd(t0, t2);
+    v2 = csub(t0, t2);
+    v1 = cadd(t1, u);
+    v3 = csub(t1, u);
+}
+
+template <int SIGN>
+__device__ __forceinline__ void dft8(double2 *v) {
+    double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    double2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<SIGN>(e0, e1, e2, e3);
+    dft4<SIGN>(o0, o1, o2, o3);
+    const double h = 0.70710678118654752440;  // sqrt(1/2)
+    const double sg = (double)SIGN;
+    const double2 p1 = make_double2(h * (o1.x - sg * o1.y), h * (o1.y + sg * o1.x));    // w o1
+    const double2 p2 = rot_i<SIGN>(o2);                                                 // w^2 o2
+    const double2 p3 = make_double2(h * (-o3.x - sg * o3.y), h * (-o3.y + sg * o3.x));  // w^3 o3
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, p1);
+    v[5] = csub(e1, p1);
+    v[2] = cadd(e2, p2);
+    v[6] = csub(e2, p2);
+    v[3] = cadd(e3, p3);
+    v[7] = csub(e3, p3);
+}
+
+// One radix-2^LR Stockham pass over m transforms of length 2^lgn stored back
+// to back, sub-transform length ns = 2^lgns so far: butterfly j (of n/R per
+// transform) takes the R inputs j + q n/R, twists input q by
+// exp(SIGN 2 pi i q k / (R ns)) with k = j mod ns, and writes its R-point DFT
+// to (j - k) R + k + q ns. Ends with a barrier.
+template <int SIGN, int LR>
+__device__ __forceinline__ void fft_pass(const double2 *a, double2 *b, int lgn, int m, int lgns, const double2 *tw,
+                                         int lgmax) {
+    constexpr int R = 1 << LR;
+    const int lgnr = lgn - LR;
+    const int nr = 1 << lgnr;
+    const int ns = 1 << lgns;
+    const int total = nr * m;
+    const int tsh = lgmax - lgns - LR;
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        const int j = t & (nr - 1);
+        const int base = (t >> lgnr) << lgn;
+        const int k = j & (ns - 1);
+        double2 v[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) v[q] = a[base + j + q * nr];
+        if (lgns > 0) {
+#pragma unroll
+            for (int q = 1; q < R; ++q) {
+                double2 w = tw[(q * k) << tsh];
+                if (SIGN > 0) w.y = -w.y;
+                v[q] = cmul(v[q], w);
+            }
+        }
+        if constexpr (LR == 1) dft2(v[0], v[1]);
+        else if constexpr (LR == 2) dft4<SIGN>(v[0], v[1], v[2], v[3]);
+        else dft8<SIGN>(v);
+        const int d = base + ((j - k) << LR) + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) b[d + q * ns] = v[q];
+    }
+    __syncthreads();
+}
+
+// m transforms of length 2^lgn stored back to back in a; SIGN = -1 forward,
+// +1 inverse (unnormalised). b is a buffer of the same size. The data must be
+// visible to the whole block on entry; the result (in a or b, returned) is
+// visible on return. Radix-8 passes after one radix-2 or radix-4 pass for
+// the remaining factor. tw[k] = exp(-2 pi i k / 2^lgmax), k < 2^lgmax.
+template <int SIGN>
+__device__ double2 *fft_lds(double2 *a, double2 *b, int lgn, int m, const double2 *tw, int lgmax) {
+    int lgns = lgn % 3;
+    if (lgns == 1) fft_pass<SIGN, 1>(a, b, lgn, m, 0, tw, lgmax);
+    if (lgns == 2) fft_pass<SIGN, 2>(a, b, lgn, m, 0, tw, lgmax);
+    if (lgns) {
+        double2 *t = a;
+        a = b;
+        b = t;
+    }
+    for (; lgns < lgn; lgns += 3) {
+        fft_pass<SIGN, 3>(a, b, lgn, m, lgns, tw, lgmax);
+        double2 *t = a;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+template <bool MIX>
+__device__ __forceinline__ double acc_value(const typename AccOf<MIX>::T *acc, int64_t i, double scale, double add) {
+    const typename AccOf<MIX>::T v = acc[i];
+    double w;
+    if constexpr (MIX) w = (double)(int64_t)v;
+    else w = v;
+    return add + scale * w;
+}
+
+// LDS: two buffers of nx complex.
+template <bool MIX, bool WALLS>
+__global__ void __launch_bounds__(kBlock) k_fft_rows(Geo g, typename AccOf<MIX>::T *acc, double scale, double add,
+                                                     int clear, double2 *H, const double2 *tw, int lgnx,
+                                                     int lgmax) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nx = g.nx;
+    double2 *b0 = (double2 *)smem, *b1 = b0 + nx;
+    const int64_t r0 = (int64_t)(2 * blockIdx.x) * nx, r1 = r0 + nx;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+        double v0, v1;
+        if constexpr (WALLS) {
+            // odd extension of the physical rows [0, nxp]: zero on the walls
+            const int nxp = g.nxp;
+            if (i == 0 || i == nxp) {
+                v0 = v1 = 0.0;
+            } else {
+                const int src = i < nxp ? i : nx - i;
+                const double sg = i < nxp ? 1.0 : -1.0;
+                v0 = sg * acc_value<MIX>(acc, r0 + src, scale, add);
+                v1 = sg * acc_value<MIX>(acc, r1 + src, scale, add);
+            }
+        } else {
+            v0 = acc_value<MIX>(acc, r0 + i, scale, add);
+            v1 = acc_value<MIX>(acc, r1 + i, scale, add);
+        }
+        b0[i] = make_double2(v0, v1);
+    }
+    __syncthreads();
+    if (clear) {
+        // after every read of the two rows (the walls read mirrored entries)
+        for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+            acc[r0 + i] = (typename AccOf<MIX>::T)0;
+            acc[r1 + i] = (typename AccOf<MIX>::T)0;
+        }
+    }
+    const double2 *R = fft_lds<-1>(b0, b1, lgnx, 1, tw, lgmax);
+    // split: rho_j0_hat(k) = (Z(k) + conj Z(-k)) / 2, rho_j1_hat(k) = (Z(k) - conj Z(-k)) / (2i)
+    const int hx = nx / 2 + 1;
+    const int64_t h0 = (int64_t)(2 * blockIdx.x) * hx, h1 = h0 + hx;
+    for (int k = threadIdx.x; k < hx; k += blockDim.x) {
+        const double2 zk = R[k], zm = R[(nx - k) & (nx - 1)];
+        H[h0 + k] = make_double2(0.5 * (zk.x + zm.x), 0.5 * (zk.y - zm.y));
+        H[h1 + k] = make_double2(0.5 * (zk.y + zm.y), -0.5 * (zk.x - zm.x));
+    }
+}
+
+// LDS: two buffers of 2 ny complex when pair (the two inverse transforms
+// run together), else three of ny (one after the other). Block b handles
+// column (b % 8) * per + b / 8 (per = ceil(hx / 8)), so that neighbouring
+// columns share an XCD's L2; blocks past the last column only write their
+// zero partial.
+__global__ void __launch_bounds__(kBlock) k_fft_cols(Geo g, const double2 *H, double2 *Z, const double2 *tw,
+                                                     int lgny, int lgmax, int per, int pair, CtxDev c) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double sRed[kWaves];
+    const int nx = g.nx, ny = g.ny, hx = nx / 2 + 1;
+    double2 *A = (double2 *)smem, *B = A + (pair ? 2 * ny : ny), *C = B + ny;
+    const int kx = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    double part = 0.0;
+    if (kx < hx) {
+        for (int y = threadIdx.x; y < ny; y += blockDim.x) A[y] = H[(int64_t)y * hx + kx];
+        __syncthreads();
+        double2 *R = fft_lds<-1>(A, B, lgny, 1, tw, lgmax);
+        double2 *S = pair ? ((R == A) ? B : A) : C;
+        double2 *S2 = pair ? S + ny : R;
+        const double norm = 1.0 / ((double)nx * (double)ny);
+        const double kx2 = c.kx2[kx], kax = c.kapx[kx];
+        const double wgt = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
+        // phi_hat and kappa_y phi_hat (scaled by 1/G for the unnormalised
+        // inverses) into S and S2 (side by side, or over rho_hat in place)
+        for (int ky = threadIdx.x; ky < ny; ky += blockDim.x) {
+            const double2 r = R[ky];
+            if (kx == 0 && ky == 0) *c.rho0 = r.x;
+            const double inv = (kx == 0 && ky == 0) ? 0.0 : 1.0 / (kx2 + c.ky2[ky]);
+            const double pr = r.x * inv, pi = r.y * inv;
+            const double kay = c.kapy[ky];
+            part += wgt * (kax * kax + kay * kay) * (pr * pr + pi * pi);
+            S[ky] = make_double2(pr * norm, pi * norm);
+            S2[ky] = make_double2(kay * pr * norm, kay * pi * norm);
+        }
+        __syncthreads();
+        // P = inverse_y(phi_hat), Q = inverse_y(kappa_y phi_hat); Ex~ = -i kappa_x P, Ey~ = -i Q
+        const double2 *P, *Q;
+        if (pair) {
+            P = fft_lds<+1>(S, R, lgny, 2, tw, lgmax);
+            Q = P + ny;
+        } else {
+            double2 *F = (R == A) ? B : A;
+            P = fft_lds<+1>(S, F, lgny, 1, tw, lgmax);
+            Q = fft_lds<+1>(S2, (P == S) ? F : S, lgny, 1, tw, lgmax);
+        }
+        const bool self = kx == 0 || 2 * kx == nx;
+        for (int y = threadIdx.x; y < ny; y += blockDim.x) {
+            const double2 p = P[y], q = Q[y];
+            const int64_t row = (int64_t)y * nx;
+            if (self) {
+                // a self-conjugate column of two real fields: their real parts
+                Z[row + kx] = make_double2(kax * p.y, q.y);
+            } else {
+                Z[row + kx] = make_double2(kax * p.y + q.x, -kax * p.x + q.y);
+                Z[row + nx - kx] = make_double2(kax * p.y - q.x, kax * p.x + q.y);
+            }
+        }
+    }
+    const double bs = block_sum(part, sRed);
+    if (threadIdx.x == 0) c.part_spec[blockIdx.x] = bs;
+}
+
+// LDS: two buffers of nx complex. Block ny (the last)
+// reduces the diagnostics from the partials of the earlier launches.
+__global__ void __launch_bounds__(kBlock) k_fft_rows_inv(Geo g, const double2 *Z, double *E, float *E32,
+                                                         const double2 *tw, int lgnx, int lgmax, FinArgs f,
+                                                         CtxDev c) {
+    if (blockIdx.x == gridDim.x - 1) {
+        finalize_block(f, c);
+        return;
+    }
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nx = g.nx;
+    const int64_t G = (int64_t)nx * g.ny;
+    double2 *b0 = (double2 *)smem, *b1 = b0 + nx;
+    const int64_t row = (int64_t)blockIdx.x * nx;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) b0[i] = Z[row + i];
+    __syncthreads();
+    const double2 *U = fft_lds<+1>(b0, b1, lgnx, 1, tw, lgmax);
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+        const double2 e = U[i];
+        E[row + i] = e.x;
+        E[G + row + i] = e.y;
+        if (E32) {
+            E32[row + i] = (float)e.x;
+            E32[G + row + i] = (float)e.y;
+        }
+    }
+}
+
+inline int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+}  // namespace
+
+bool fused_fft_supported(int dim, int nx, int ny, int nz) {
+    auto pow2 = [](int v) { return v >= 4 && v <= kFusedFftMax && (v & (v - 1)) == 0; };
+    return dim == 2 && nz <= 1 && pow2(nx) && pow2(ny);
+}
+
+hipError_t launch_fused_field(const Geo &g, bool mixed_acc, void *acc, double scale, double add, int clear,
+                              void *H, void *Z, double *E, float *E32, const double *tw_table, const FinArgs &f0,
+                              const CtxDev &c, hipStream_t s) {
+    const int lgnx = ilog2(g.nx), lgny = ilog2(g.ny);
+    const int lgmax = lgnx > lgny ? lgnx : lgny;
+    const double2 *tw = (const double2 *)tw_table;
+    const size_t sh_rows = 2 * (size_t)g.nx * sizeof(double2);
+    // the paired inverse needs 4 ny complex; keep within 64 KiB with the static reduction array
+    const int pair = 4 * (size_t)g.ny * sizeof(double2) + 256 <= 65536 ? 1 : 0;
+    const size_t sh_cols = (pair ? 4 : 3) * (size_t)g.ny * sizeof(double2);
+    const dim3 rows(g.ny / 2);
+    if (mixed_acc) {
+        auto *a = (unsigned long long *)acc;
+        if (g.walls)
+            hipLaunchKernelGGL((k_fft_rows<true, true>), rows, dim3(kBlock), sh_rows, s, g, a, scale, add, clear,
+                               (double2 *)H, tw, lgnx, lgmax);
+        else
+            hipLaunchKernelGGL((k_fft_rows<true, false>), rows, dim3(kBlock), sh_rows, s, g, a, scale, add, clear,
+                               (double2 *)H, tw, lgnx, lgmax);
+    } else {
+        auto *a = (double *)acc;
+        if (g.walls)
+            hipLaunchKernelGGL((k_fft_rows<false, true>), rows, dim3(kBlock), sh_rows, s, g, a, scale, add, clear,
+                               (double2 *)H, tw, lgnx, lgmax);
+        else
+            hipLaunchKernelGGL((k_fft_rows<false, false>), rows, dim3(kBlock), sh_rows, s, g, a, scale, add, clear,
+                               (double2 *)H, tw, lgnx, lgmax);
+    }
+    const int hx = g.nx / 2 + 1;
+    const int per = (hx + 7) / 8;
+    const int ncol = 8 * per;
+    hipLaunchKernelGGL(k_fft_cols, dim3(ncol), dim3(kBlock), sh_cols, s, g, (const double2 *)H, (double2 *)Z, tw,
+                       lgny, lgmax, per, pair, c);
+    FinArgs f = f0;
+    f.nspec = ncol;
+    hipLaunchKernelGGL(k_fft_rows_inv, dim3(g.ny + 1), dim3(kBlock), sh_rows, s, g, (const double2 *)Z, E, E32, tw,
+                       lgnx, lgmax, f, c);
+    return hipGetLastError();
+}
+
+int fused_fft_spec_blocks(const Geo &g) { return 8 * ((g.nx / 2 + 1 + 7) / 8); }
+
+}  // namespace apic

@@ -66,6 +66,7 @@ struct CtxDev {
     double *kx2, *kapx;   // modified wavenumber tables, x: [nx/2+1]
     double *ky2, *kapy;   // y: [ny]
     double *kz2, *kapz;   // z: [nz]
+    double *tw;           // fused 2D field solve: exp(-2 pi i k / nmax), k < nmax, interleaved (re, im)
 };
 
 // Field diagnostics of one solve: charge and W_E (and, with npush, the
@@ -152,6 +153,17 @@ hipError_t launch_spectral(const Geo &g, const void *rho_hat, void *phi_hat, con
 // (one extra workgroup of the same launch reduces the field diagnostics)
 hipError_t launch_grad(const Geo &g, const double *phi, double *E, float *E32, const FinArgs &f,
                        const CtxDev &c, hipStream_t s);
+
+// Fused periodic 2D field solve (apic_fft.hip): power-of-two nx, ny in
+// [4, kFusedFftMax], walls included (nx the extended grid). acc -> rho (acc
+// cleared when clear) -> E [2][G] (+ E32) and the diagnostics of f (nspec is
+// set by the launcher). H: [ny][nx/2+1] complex, Z: [ny][nx] complex
+// scratch. tw: the twiddle table of CtxDev for nmax = max(nx, ny).
+constexpr int kFusedFftMax = 1024;
+bool fused_fft_supported(int dim, int nx, int ny, int nz);
+hipError_t launch_fused_field(const Geo &g, bool mixed_acc, void *acc, double scale, double add, int clear,
+                              void *H, void *Z, double *E, float *E32, const double *tw, const FinArgs &f,
+                              const CtxDev &c, hipStream_t s);
 hipError_t launch_finalize(int npush, int nspec, double mass, double dV, double G, double rho_ion,
                            double *diag, double *we, double *charge, const CtxDev &c, hipStream_t s);
 hipError_t launch_field1d(const Geo &g, bool mixed, void *acc, double scale, double add, double ion,

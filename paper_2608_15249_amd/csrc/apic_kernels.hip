@@ -1396,50 +1396,6 @@ __global__ void __launch_bounds__(kBlock) k_rho_odd(Geo g, typename AccOf<MIX>::
     }
 }
 
-// Spectral Poisson + centred gradient on the half-spectrum [ny][nx/2+1]:
-//   phi_hat = rho_hat / K^2 (K^2 = modified wavenumber of the FD Laplacian,
-//   phi_hat(0) = 0), E_hat_d = -i kappa_d phi_hat with kappa = sin(k d)/d,
-//   scaled by 1/(nx ny) for the unnormalised inverse transform.
-// Per-block partial of sum_k w_k |E_hat_k|^2 (Parseval over the half
-// spectrum, w = 1 on the kx = 0 and Nyquist columns, else 2) goes to
-// c.part_spec; rho_hat(0) (= sum_j rho_j) to c.rho0.
-// Field diagnostics of one solve (one workgroup): fixed-order sums of the
-// spectral and push partials into diag[step] or we/charge.
-__device__ void finalize_block(const FinArgs &f, const CtxDev &c) {
-    __shared__ double sRed[16];
-    double k = 0.0, p = 0.0, e = 0.0;
-    for (int i = threadIdx.x; i < f.npush; i += blockDim.x) {
-        k += c.part_push[2 * i];
-        p += c.part_push[2 * i + 1];
-    }
-    for (int i = threadIdx.x; i < f.nspec; i += blockDim.x) e += c.part_spec[i];
-    k = block_sum(k, sRed);
-    p = block_sum(p, sRed);
-    e = block_sum(e, sRed);
-    if (threadIdx.x == 0) {
-        double *d = f.diag ? step_slot(f.diag, c) : nullptr;
-        if (f.npush && d) {
-            d[2] = 0.5 * f.mass * k;
-            d[3] = f.mass * p;
-        }
-        if (f.nspec) {
-            double wE = 0.5 * f.dV / f.G * e;
-            double q = f.dV * (*c.rho0 - f.G * f.rho_ion);
-            if (f.walls) {
-                // the physical half of the odd extension, wall nodes at half weight
-                wE = 0.5 * wE;
-                q = f.nlive ? f.q_macro * (double)*f.nlive : 0.0;
-            }
-            if (d) {
-                d[0] = q;
-                d[1] = wE;
-            }
-            if (f.we) *f.we = wE;
-            if (f.charge) *f.charge = q;
-        }
-    }
-}
-
 __global__ void __launch_bounds__(1024) k_finalize(FinArgs f, CtxDev c) { finalize_block(f, c); }
 
 // phi_hat = rho_hat / K^2 (K^2 = sum of the per-axis modified wavenumbers,
