@@ -101,7 +101,7 @@ void layout(apic_ctx *c) {
     c->o_offs = take(4 * nb * kStepTab);
     c->o_farcnt = take(4 * nb);
     c->o_farcur = take(4 * nb);
-    c->o_tot = take(4 * nb);
+    c->o_tot = take(4 * 2 * nb);   // two alternating buffers
     c->o_deep = take(4 * nb * kDeepTab);
     c->o_acc = take(8 * G);
     c->o_jacc = c->d.model == APIC_ELECTROMAGNETIC ? take(24 * G) : (size_t)-1;
@@ -604,7 +604,8 @@ apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, floa
     int32_t *bsA = p->bucket_start, *bsB = wsp<int32_t>(ws, c->o_bstart);
     const PushC pc = push_coeffs(c, 1.0, 1);
     HIPCHK(c, launch_fill_i32(farcnt, nb, 0, s));
-    HIPCHK(c, launch_fill_i32(tot, nb, 0, s));
+    // the bucket totals: two buffers, alternating by step
+    HIPCHK(c, launch_fill_i32(tot, 2 * (int64_t)nb, 0, s));
     // no deep ranges known for the incoming order: the first count reads all
     HIPCHK(c, launch_fill_i32(deep, (int64_t)nb * kDeepTab, 0, s));
     HIPCHK(c, launch_fill_u64((uint64_t *)acc, G, 0, s));
@@ -619,10 +620,16 @@ apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, floa
         hipEvent_t *ev = nullptr;
         if (c->prof_used < c->prof_max) ev = &c->ev[5 * (size_t)c->prof_used++];
         if (ev) HIPCHK(c, hipEventRecord(ev[0], s));
-        HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, E, pc, cnt, tot, farcnt, deep, c->dev, s));
+        int32_t *tot_k = tot + (even ? 0 : nb), *tot_n = tot + (even ? nb : 0);
+        HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, E, pc, cnt, tot_k, farcnt, deep, c->dev, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[1], s));
-        HIPCHK(c, launch_scan_dir(c->g, tot, bs_dst, c->n, max_per_bucket(c), 1, c->dev, s));
-        HIPCHK(c, launch_dest_offsets(c->g, cnt, bs_dst, offs, s));
+        if (fused_scan_offsets(c->g)) {
+            HIPCHK(c, launch_scan_offsets(c->g, tot_k, tot_n, bs_dst, c->n, max_per_bucket(c), 1, cnt, offs, c->dev,
+                                          s));
+        } else {
+            HIPCHK(c, launch_scan_dir(c->g, tot_k, bs_dst, c->n, max_per_bucket(c), 1, c->dev, s));
+            HIPCHK(c, launch_dest_offsets(c->g, cnt, bs_dst, offs, s));
+        }
         if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
         HIPCHK(c, launch_step_push(c->g, c->mixed, src, dst, bs_src, bs_dst, cnt, offs, farcnt, E, pc, acc,
                                    p->perm, diag ? c->dev.part_push : nullptr, deep, c->dev, s));

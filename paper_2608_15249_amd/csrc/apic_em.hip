@@ -298,7 +298,8 @@ apic_status apic_em_step(apic_ctx *c, apic_particles *p, double *F, double *J, i
     const PushC pc = push_coeffs(c, 1.0, 1);
     const double c2 = c->d.c_light * c->d.c_light, dt = c->d.dt;
     HIPCHK(c, launch_fill_i32(farcnt, nb, 0, s));
-    HIPCHK(c, launch_fill_i32(tot, nb, 0, s));
+    // the bucket totals: two buffers, alternating by step
+    HIPCHK(c, launch_fill_i32(tot, 2 * (int64_t)nb, 0, s));
     HIPCHK(c, launch_fill_i32(deep, (int64_t)nb * kDeepTab, 0, s));
     HIPCHK(c, launch_fill_u64((uint64_t *)jacc, 3 * G, 0, s));
     HIPCHK(c, launch_set_step(c->dev.step, -1, s));
@@ -312,10 +313,16 @@ apic_status apic_em_step(apic_ctx *c, apic_particles *p, double *F, double *J, i
         hipEvent_t *ev = nullptr;
         if (c->prof_used < c->prof_max) ev = &c->ev[5 * (size_t)c->prof_used++];
         if (ev) HIPCHK(c, hipEventRecord(ev[0], s));
-        HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, F, pc, cnt, tot, farcnt, deep, c->dev, s));
+        int32_t *tot_k = tot + (even ? 0 : nb), *tot_n = tot + (even ? nb : 0);
+        HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, F, pc, cnt, tot_k, farcnt, deep, c->dev, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[1], s));
-        HIPCHK(c, launch_scan_dir(c->g, tot, bs_dst, c->n, max_per_bucket(c), 1, c->dev, s));
-        HIPCHK(c, launch_dest_offsets(c->g, cnt, bs_dst, offs, s));
+        if (fused_scan_offsets(c->g)) {
+            HIPCHK(c, launch_scan_offsets(c->g, tot_k, tot_n, bs_dst, c->n, max_per_bucket(c), 1, cnt, offs, c->dev,
+                                          s));
+        } else {
+            HIPCHK(c, launch_scan_dir(c->g, tot_k, bs_dst, c->n, max_per_bucket(c), 1, c->dev, s));
+            HIPCHK(c, launch_dest_offsets(c->g, cnt, bs_dst, offs, s));
+        }
         if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
         HIPCHK(c, launch_step_push(c->g, c->mixed, src, dst, bs_src, bs_dst, cnt, offs, farcnt, F, pc, jacc, p->perm,
                                    diag ? c->dev.part_push : nullptr, deep, c->dev, s));

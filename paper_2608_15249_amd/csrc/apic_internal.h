@@ -134,6 +134,13 @@ hipError_t launch_scan_dir(const Geo &g, int32_t *tot, int32_t *start, int64_t n
 // destination bucket: offs has the layout of cnt
 hipError_t launch_dest_offsets(const Geo &g, const int32_t *cnt, const int32_t *start, int32_t *offs,
                                hipStream_t s);
+// The scan of the bucket totals and the offsets in one launch (when
+// fused_scan_offsets(g)): tot is read, tot_next (the totals buffer of the
+// next step) is cleared; otherwise launch_scan_dir + launch_dest_offsets.
+bool fused_scan_offsets(const Geo &g);
+hipError_t launch_scan_offsets(const Geo &g, const int32_t *tot, int32_t *tot_next, int32_t *start, int64_t n,
+                               int64_t max_per_bucket, int step_mode, const int32_t *cnt, int32_t *offs,
+                               const CtxDev &c, hipStream_t s);
 hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Parts &dst,
                             const int32_t *bstart, const int32_t *bstart_new, const int32_t *cnt,
                             const int32_t *offs, int32_t *farcnt, const double *E, const PushC &pc, void *acc,

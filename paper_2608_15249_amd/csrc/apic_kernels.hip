@@ -1013,14 +1013,10 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
 // (source bucket, wave, near direction) entry has exactly one destination, so
 // each offs entry is written once.
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_dest_offsets(Geo g, const int32_t *cnt, const int32_t *start,
-                                                         int32_t *offs) {
+__device__ __forceinline__ void dest_offsets_wave(const Geo &g, int nbk, int run, const int32_t *cnt, int32_t *offs) {
     constexpr int kDirs = Dir<DIM>::kN, kFar = Dir<DIM>::kFar, kTab = Dir<DIM>::kTab;
     constexpr int kIn = kFar * kWaves;  // incoming entries per destination
-    const int nbk = (int)blockIdx.x * kWaves + (int)(threadIdx.x >> 6);
-    if (nbk >= g.nbuckets) return;      // whole waves leave together; no barrier below
     const int lane = threadIdx.x & 63;
-    int run = start[nbk];
 #pragma unroll
     for (int r = 0; r < (kIn + 63) / 64; ++r) {
         const int e = r * 64 + lane;    // entry e = d * kWaves + wave
@@ -1036,6 +1032,64 @@ __global__ void __launch_bounds__(kBlock) k_dest_offsets(Geo g, const int32_t *c
         if (ok) offs[src * kTab + wv * kDirs + d] = run + inc - v;
         run += __shfl(inc, 63);
     }
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_dest_offsets(Geo g, const int32_t *cnt, const int32_t *start,
+                                                         int32_t *offs) {
+    const int nbk = (int)blockIdx.x * kWaves + (int)(threadIdx.x >> 6);
+    if (nbk >= g.nbuckets) return;      // whole waves leave together; no barrier below
+    dest_offsets_wave<DIM>(g, nbk, start[nbk], cnt, offs);
+}
+
+// The bucket-total scan and the offsets in one launch, for grids of at most
+// kFusedScanMax buckets: every workgroup sums the totals of the buckets before
+// its own (a few KiB, cache resident) instead of waiting for a separate scan.
+// Also as k_scan_tot: the per-bucket headroom check, the new bucket_start
+// (start[nb] by the last workgroup, with the count check), the step counter
+// (workgroup 0). The totals of the next step live in tot_next, cleared here
+// bucket by bucket; tot itself is read by every workgroup and is cleared by
+// the next step's launch (the two buffers alternate).
+constexpr int kFusedScanMax = 4096;
+
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *sh /* [kWaves] */) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    int64_t t = 0;
+    for (int i = 0; i < kWaves; ++i) t += sh[i];
+    return t;
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_scan_offsets(Geo g, const int32_t *tot, int32_t *tot_next,
+                                                         int32_t *start, int64_t n, int64_t max_per, int step_mode,
+                                                         int walls, const int32_t *cnt, int32_t *offs, CtxDev c) {
+    __shared__ int64_t sh[kWaves];
+    const int nb = g.nbuckets;
+    const int first = (int)blockIdx.x * kWaves;
+    int64_t part = 0;
+    for (int b = threadIdx.x; b < first; b += blockDim.x) part += tot[b];
+    const int64_t base = block_sum_i64(part, sh);
+    const int w = threadIdx.x >> 6;
+    const int nbk = first + w;
+    int64_t run = base;
+    for (int w2 = 0; w2 < w && first + w2 < nb; ++w2) run += tot[first + w2];
+    if (nbk >= nb) return;              // whole waves leave together; no barrier below
+    const int own = tot[nbk];
+    if ((threadIdx.x & 63) == 0) {
+        start[nbk] = (int32_t)run;
+        tot_next[nbk] = 0;
+        if (own > max_per) raise_err(c.err, ERR_OVERFLOW);
+        if (nbk == nb - 1) {
+            const int64_t total = run + own;
+            start[nb] = (int32_t)total;
+            if (walls ? total > n : total != n) raise_err(c.err, ERR_COUNT);
+        }
+        if (nbk == 0 && step_mode) *c.step = *c.step + 1;
+    }
+    dest_offsets_wave<DIM>(g, nbk, (int)run, cnt, offs);
 }
 
 // ---- fused step, pass 2: push, deposit, scatter into the next bucket order -----
@@ -1715,6 +1769,25 @@ hipError_t launch_scan_dir(const Geo &g, int32_t *tot, int32_t *start, int64_t n
                            int step_mode, const CtxDev &c, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_tot, dim3(1), dim3(1024), 0, s, tot, start, g.nbuckets, n, max_per_bucket, step_mode,
                        g.walls, c);
+    return hipGetLastError();
+}
+
+bool fused_scan_offsets(const Geo &g) { return g.nbuckets <= kFusedScanMax; }
+
+hipError_t launch_scan_offsets(const Geo &g, const int32_t *tot, int32_t *tot_next, int32_t *start, int64_t n,
+                               int64_t max_per_bucket, int step_mode, const int32_t *cnt, int32_t *offs,
+                               const CtxDev &c, hipStream_t s) {
+    const dim3 grid((g.nbuckets + kWaves - 1) / kWaves);
+    const int walls = g.walls ? 1 : 0;
+    if (g.dim == 3)
+        hipLaunchKernelGGL(k_scan_offsets<3>, grid, dim3(kBlock), 0, s, g, tot, tot_next, start, n, max_per_bucket,
+                           step_mode, walls, cnt, offs, c);
+    else if (g.dim == 2)
+        hipLaunchKernelGGL(k_scan_offsets<2>, grid, dim3(kBlock), 0, s, g, tot, tot_next, start, n, max_per_bucket,
+                           step_mode, walls, cnt, offs, c);
+    else
+        hipLaunchKernelGGL(k_scan_offsets<1>, grid, dim3(kBlock), 0, s, g, tot, tot_next, start, n, max_per_bucket,
+                           step_mode, walls, cnt, offs, c);
     return hipGetLastError();
 }
 
