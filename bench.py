@@ -44,6 +44,26 @@ def state_bytes(precision, dim, vdim):
     return 4 + 4 * dim + 4 * vdim if precision == "mixed" else 8 * dim + 8 * vdim
 
 
+PHASE_NOTE = ("from a separate run of %d steps after the timed one, with HIP events between all phases (each "
+              "event drains the queue, so these sum to more than ms_per_step); the timed run records only the two "
+              "events around the push, whose duration gives roofline.achieved")
+
+
+def phase_breakdown(ctx, run, steps):
+    """Summed per-phase milliseconds (count, scan, push, field) of a short run
+    with events around every phase, and its step count."""
+    import torch
+    k = min(steps, 20)
+    dg = torch.zeros(4 * k, dtype=torch.float64, device="cuda")
+    ctx.profile_phases(True)
+    ctx.profile_enable(k)
+    run(k, dg)
+    ctx.sync()
+    ms, nprof = ctx.profile_read()
+    ctx.profile_enable(0)
+    return ms, max(nprof, 1)
+
+
 def load_traffic(precision, workload, tile):
     """HBM bytes per push-pass launch from committed rocprofv3 counter runs,
     if they were taken on the current kernel source, workload and tile;
@@ -102,6 +122,9 @@ def run_path(precision, w, state, steps, warmup, tile, torch, pusher="boris", c_
     n = sim.n
     n_start = int(sim.p.bucket_start[-1].item()) if walls else n
     diag = torch.zeros(steps * 4, dtype=torch.float64, device="cuda")
+    # the timed run records HIP events around the push pass only (each event
+    # makes the queue drain between kernels)
+    sim.ctx.profile_phases(False)
     sim.ctx.profile_enable(steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -109,17 +132,18 @@ def run_path(precision, w, state, steps, warmup, tile, torch, pusher="boris", c_
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sim.ctx.sync()
-    ms, nprof = sim.ctx.profile_read()
+    ms_t, nprof_t = sim.ctx.profile_read()
     sim.ctx.profile_enable(0)
     elapsed = t1 - t0
     sb = state_bytes(precision, w.dim, w.vdim)
-    push_ms = ms[2] / max(nprof, 1)
+    push_ms = ms_t[2] / max(nprof_t, 1)
+    d = diag.cpu().numpy().reshape(steps, 4)
+    ms, nprof = phase_breakdown(sim.ctx, lambda k, dg: sim.ctx.step(sim.p, sim.E, sim.E32, k, dg), steps)
     push_bytes = 2 * sb * n
     achieved = push_bytes / (push_ms * 1e-3) / 1e9
     # counters were taken for the Boris kernels only
     traffic = load_traffic(precision, "%s_%d" % (w.name, w.nx), list(sim.tile)) \
         if pusher == "boris" and not walls else None
-    d = diag.cpu().numpy().reshape(steps, 4)
     # particle pushes of the timed steps: with absorbing walls the count falls
     # (diag charge = q_macro * live count after each step)
     pushes = n * steps
@@ -132,8 +156,8 @@ def run_path(precision, w, state, steps, warmup, tile, torch, pusher="boris", c_
         "hbm_gbs_step": (3 * sb * n * steps) / elapsed / 1e9,
         "tile": list(sim.tile),
         "tune_ms_per_step": sim.tune_ms,
-        "phase_ms_per_step": {"count": ms[0] / nprof, "scan": ms[1] / nprof, "push": push_ms,
-                              "field": ms[3] / nprof},
+        "phase_ms_per_step": {"count": ms[0] / nprof, "scan": ms[1] / nprof, "push": ms[2] / nprof,
+                              "field": ms[3] / nprof, "note": PHASE_NOTE % nprof},
         # particle-steps/s of the fused push kernel alone and of the whole
         # particle part of the step (tallies + scan + push), field excluded
         "particle_steps_s_by_phase": {"push": n / (push_ms * 1e-3),
@@ -176,6 +200,7 @@ def run_em(precision, w, state, steps, warmup, tile, c_light, torch):
         ctx.em_step(p, F, warmup)
     ctx.sync()
     diag = torch.zeros(steps * 4, dtype=torch.float64, device="cuda")
+    ctx.profile_phases(False)
     ctx.profile_enable(steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -183,21 +208,22 @@ def run_em(precision, w, state, steps, warmup, tile, c_light, torch):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.sync()
-    ms, nprof = ctx.profile_read()
+    ms_t, nprof_t = ctx.profile_read()
     ctx.profile_enable(0)
     elapsed = t1 - t0
     sb = state_bytes(precision, 2, 3)
-    push_ms = ms[2] / max(nprof, 1)
+    push_ms = ms_t[2] / max(nprof_t, 1)
     push_bytes = 2 * sb * n
     achieved = push_bytes / (push_ms * 1e-3) / 1e9
     d = diag.cpu().numpy().reshape(steps, 4)
+    ms, nprof = phase_breakdown(ctx, lambda k, dg: ctx.em_step(p, F, k, diag=dg), steps)
     out = {
         "value": n * steps / elapsed,
         "ms_per_step": 1e3 * elapsed / steps,
         "hbm_gbs_step": (3 * sb * n * steps) / elapsed / 1e9,
         "tile": list(ctx.tile),
-        "phase_ms_per_step": {"count": ms[0] / nprof, "scan": ms[1] / nprof, "push": push_ms,
-                              "field": ms[3] / nprof},
+        "phase_ms_per_step": {"count": ms[0] / nprof, "scan": ms[1] / nprof, "push": ms[2] / nprof,
+                              "field": ms[3] / nprof, "note": PHASE_NOTE % nprof},
         "particle_steps_s_by_phase": {"push": n / (push_ms * 1e-3),
                                       "count+scan+push": n / ((ms[0] + ms[1] + ms[2]) / nprof * 1e-3)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -241,6 +241,14 @@ apic_status apic_step(apic_ctx *ctx, apic_particles *p, void *rho, double *E, fl
 apic_status apic_profile_enable(apic_ctx *ctx, int max_steps);
 apic_status apic_profile_read(apic_ctx *ctx, double ms[4], int *steps);
 
+/* Which events apic_step records while profiling: all != 0 (the default) the
+ * five per step above; all = 0 only the two around the push pass (ms[2];
+ * the other phases read 0). Every recorded event makes the queue finish the
+ * work before it, which costs time between kernels (about 16 us per step
+ * with all five at 512^2, 16.8M particles), so a throughput measurement
+ * records only the push pass. Discards the steps profiled so far. */
+apic_status apic_profile_phases(apic_ctx *ctx, int all);
+
 /* Convert a physical FP64 state to the context's particle representation (any
  * order): x, y [dev, double, n] positions (y NULL in 1D), vx, vy, vz [dev,
  * double, n] velocities (NULL beyond vdim). FP64 path: copies into p->x, p->y,

@@ -619,10 +619,10 @@ apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, floa
         const bool last = k == nsteps - 1;
         hipEvent_t *ev = nullptr;
         if (c->prof_used < c->prof_max) ev = &c->ev[5 * (size_t)c->prof_used++];
-        if (ev) HIPCHK(c, hipEventRecord(ev[0], s));
+        if (ev && c->prof_all) HIPCHK(c, hipEventRecord(ev[0], s));
         int32_t *tot_k = tot + (even ? 0 : nb), *tot_n = tot + (even ? nb : 0);
         HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, E, pc, cnt, tot_k, farcnt, deep, c->dev, s));
-        if (ev) HIPCHK(c, hipEventRecord(ev[1], s));
+        if (ev && c->prof_all) HIPCHK(c, hipEventRecord(ev[1], s));
         if (fused_scan_offsets(c->g)) {
             HIPCHK(c, launch_scan_offsets(c->g, tot_k, tot_n, bs_dst, c->n, max_per_bucket(c), 1, cnt, offs, c->dev,
                                           s));
@@ -643,7 +643,7 @@ apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, floa
         st = field_from_acc(c, acc, false, E, last ? E32 : nullptr, diag, nullptr, nullptr, diag ? nb : 0, 1, ws, s,
                             bs_dst + nb);
         if (st != APIC_OK) return st;
-        if (ev) HIPCHK(c, hipEventRecord(ev[4], s));
+        if (ev && c->prof_all) HIPCHK(c, hipEventRecord(ev[4], s));
     }
     if (nsteps & 1) {
         st = copy_parts(c, A, B, s);
@@ -665,14 +665,21 @@ apic_status apic_profile_enable(apic_ctx *c, int max_steps) {
     return APIC_OK;
 }
 
+apic_status apic_profile_phases(apic_ctx *c, int all) {
+    if (!c) return APIC_EINVAL;
+    c->prof_all = all != 0;
+    c->prof_used = 0;
+    return APIC_OK;
+}
+
 apic_status apic_profile_read(apic_ctx *c, double ms[4], int *steps) {
     if (!c || !ms || !steps) return APIC_EINVAL;
     for (int k = 0; k < 4; ++k) ms[k] = 0.0;
     *steps = c->prof_used;
     if (c->prof_used == 0) return APIC_OK;
-    HIPCHK(c, hipEventSynchronize(c->ev[5 * (size_t)(c->prof_used - 1) + 4]));
+    HIPCHK(c, hipEventSynchronize(c->ev[5 * (size_t)(c->prof_used - 1) + (c->prof_all ? 4 : 3)]));
     for (int st = 0; st < c->prof_used; ++st) {
-        for (int k = 0; k < 4; ++k) {
+        for (int k = c->prof_all ? 0 : 2; k < (c->prof_all ? 4 : 3); ++k) {
             float t = 0.0f;
             HIPCHK(c, hipEventElapsedTime(&t, c->ev[5 * (size_t)st + k], c->ev[5 * (size_t)st + k + 1]));
             ms[k] += t;

@@ -33,6 +33,7 @@ struct apic_ctx {
     // per-phase timing (apic_profile_enable)
     std::vector<hipEvent_t> ev;   // 5 events per profiled step
     int prof_max = 0, prof_used = 0;
+    bool prof_all = true;          // events around every phase, or only around the push pass
 };
 
 namespace apic_host {

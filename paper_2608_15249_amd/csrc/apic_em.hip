@@ -312,10 +312,10 @@ apic_status apic_em_step(apic_ctx *c, apic_particles *p, double *F, double *J, i
         const bool last = k == nsteps - 1;
         hipEvent_t *ev = nullptr;
         if (c->prof_used < c->prof_max) ev = &c->ev[5 * (size_t)c->prof_used++];
-        if (ev) HIPCHK(c, hipEventRecord(ev[0], s));
+        if (ev && c->prof_all) HIPCHK(c, hipEventRecord(ev[0], s));
         int32_t *tot_k = tot + (even ? 0 : nb), *tot_n = tot + (even ? nb : 0);
         HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, F, pc, cnt, tot_k, farcnt, deep, c->dev, s));
-        if (ev) HIPCHK(c, hipEventRecord(ev[1], s));
+        if (ev && c->prof_all) HIPCHK(c, hipEventRecord(ev[1], s));
         if (fused_scan_offsets(c->g)) {
             HIPCHK(c, launch_scan_offsets(c->g, tot_k, tot_n, bs_dst, c->n, max_per_bucket(c), 1, cnt, offs, c->dev,
                                           s));
@@ -333,7 +333,7 @@ apic_status apic_em_step(apic_ctx *c, apic_particles *p, double *F, double *J, i
             HIPCHK(c, launch_fdtd_b_diag(c->g, F, 0.5 * dt, c->d.bz, c2, c->dV, c->mass, nb, diag, c->dev, s));
         else
             HIPCHK(c, launch_fdtd_b(c->g, F, 0.5 * dt, s));
-        if (ev) HIPCHK(c, hipEventRecord(ev[4], s));
+        if (ev && c->prof_all) HIPCHK(c, hipEventRecord(ev[4], s));
     }
     if (nsteps & 1) {
         st = copy_parts(c, A, B, s);
