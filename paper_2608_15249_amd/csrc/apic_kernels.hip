@@ -54,11 +54,11 @@ template <int DIM> struct Dir {
     static constexpr int kN = (DIM == 3) ? 28 : 10;      // direction codes (near + far)
     static constexpr int kFar = kN - 1;
     static constexpr int kStay = (DIM == 3) ? 13 : 4;    // the code of a particle that stays
-    static constexpr int kTab = kWaves * kN;             // per-bucket table entries
+    static constexpr int kTab = kSWaves * kN;            // per-bucket table entries
     static constexpr int kCodeBits = (DIM == 3) ? 5 : 4; // bits of a near code
 };
 static_assert(Dir<3>::kTab <= kStepTab && Dir<2>::kTab <= kStepTab, "direction table size");
-static_assert(kDeepTab == 2 * kWaves, "deep table size");
+static_assert(kDeepTab == 2 * kSWaves, "deep table size");
 
 // Tile coordinates of bucket b (tiles numbered x fastest, then y, then z).
 template <int DIM>
@@ -780,14 +780,14 @@ __global__ void __launch_bounds__(kBlock) k_gather_push_tiled(Geo g, Parts p, co
 // that own their indices; the remaining particles run the full computation and
 // are tallied with LDS atomics into their owning waves' entries.
 
-// Number of indices k in [lo, hi) owned by wave w (k mod kBlock in [64w, 64w+64)).
+// Number of indices k in [lo, hi) owned by wave w (k mod kSBlock in [64w, 64w+64)).
 __device__ __forceinline__ int owned_by(int lo, int hi, int w) {
-    auto f = [w](int x) { return (x / kBlock) * 64 + min(max((x % kBlock) - 64 * w, 0), 64); };
+    auto f = [w](int x) { return (x / kSBlock) * 64 + min(max((x % kSBlock) - 64 * w, 0), 64); };
     return hi > lo ? f(hi) - f(lo) : 0;
 }
 // EM: the electromagnetic form (FP64 2D3V): E is the [6][G] Yee field.
 template <bool MIX, int DIM, int VDIM, int U, bool HC, bool EM>
-__global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int32_t *bstart, const double *E,
+__global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const int32_t *bstart, const double *E,
                                                        PushC pc, int32_t *cnt, int32_t *tot, int32_t *farcnt,
                                                        const int32_t *deep, CtxDev c) {
     static_assert(!EM || (DIM == 2 && VDIM == 3), "the electromagnetic step is 2D3V");
@@ -796,7 +796,7 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sErr;
     __shared__ int32_t sCnt[kTab];
-    __shared__ float sMax[kWaves][3];
+    __shared__ float sMax[kSWaves][3];
     R *sE = (R *)smem;
     const int w = threadIdx.x >> 6;
     const uint64_t lt = lanemask_lt();
@@ -816,9 +816,9 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
         // field tile (one memory round trip for all three)
         const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
         const int span = i1 - i0;
-        int draw[2 * kWaves];
+        int draw[2 * kSWaves];
 #pragma unroll
-        for (int r = 0; r < 2 * kWaves; ++r) draw[r] = deep[b * kDeepTab + r];
+        for (int r = 0; r < 2 * kSWaves; ++r) draw[r] = deep[b * kDeepTab + r];
         if constexpr (EM)
             load_f_tile<R>((R *)smem, E, g, x0, y0, fw, fh);
         else if constexpr (DIM == 3)
@@ -858,7 +858,7 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
         }
         __syncthreads();
         float emx = 0.0f, emy = 0.0f, emz = 0.0f;
-        for (int w2 = 0; w2 < kWaves; ++w2) {
+        for (int w2 = 0; w2 < kSWaves; ++w2) {
             emx = fmaxf(emx, sMax[w2][0]);
             emy = fmaxf(emy, sMax[w2][1]);
             emz = fmaxf(emz, sMax[w2][2]);
@@ -868,11 +868,11 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
         if constexpr (DIM >= 2) skip = skip && kick * emy * pc.dtdy + 0.0009765625f <= pc.deep;
         if constexpr (DIM == 3) skip = skip && kick * emz * pc.dtdz + 0.0009765625f <= pc.deep;
         // deep ranges of this bucket: increasing, disjoint, inside [0, span)
-        int da[kWaves], dc[kWaves], ndeep = 0;
+        int da[kSWaves], dc[kSWaves], ndeep = 0;
         {
             int lo = 0;
 #pragma unroll
-            for (int r = 0; r < kWaves; ++r) {
+            for (int r = 0; r < kSWaves; ++r) {
                 const int st = skip ? min(max(draw[2 * r], lo), span) : lo;
                 const int ct = skip ? min(max(draw[2 * r + 1], 0), span - st) : 0;
                 da[r] = st;
@@ -885,7 +885,7 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
             if ((threadIdx.x & 63) == 0) {
                 int st = 0;
 #pragma unroll
-                for (int r = 0; r < kWaves; ++r) st += owned_by(da[r], da[r] + dc[r], w);
+                for (int r = 0; r < kSWaves; ++r) st += owned_by(da[r], da[r] + dc[r], w);
                 atomicAdd(&sCnt[w * kDirs + kStay], st);
             }
             // the shallow particles: indices of [0, span) outside the deep
@@ -895,7 +895,7 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
             auto kmap = [&](int t) {
                 int k = t;
 #pragma unroll
-                for (int r = 0; r < kWaves; ++r)
+                for (int r = 0; r < kSWaves; ++r)
                     if (k >= da[r]) k += dc[r];
                 return k;
             };
@@ -921,7 +921,7 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
                 if (g.walls && q.ix >= g.nxp) return;   // absorbed by a wall: leaves the order
                 const int code = dir_local<DIM>(tn, lx + sx, ly + sy, lz + sz);
                 if (code < kFar) {
-                    atomicAdd(&sCnt[((k % kBlock) >> 6) * kDirs + code], 1);
+                    atomicAdd(&sCnt[((k % kSBlock) >> 6) * kDirs + code], 1);
                 } else {
                     const int nbk = bucket_of<MIX, DIM>(g, q.ix, q.iy, q.iz);
                     atomicAdd(&farcnt[nbk], 1);
@@ -930,27 +930,27 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
             };
             Raw<MIX> sa, sb;
             if (nsh > 0) sfetch(sa, threadIdx.x);
-            for (int t0 = 0; t0 < nsh; t0 += 2 * kBlock) {
-                if (t0 + kBlock < nsh) sfetch(sb, t0 + kBlock + threadIdx.x);
+            for (int t0 = 0; t0 < nsh; t0 += 2 * kSBlock) {
+                if (t0 + kSBlock < nsh) sfetch(sb, t0 + kSBlock + threadIdx.x);
                 sprocess(sa, t0 + threadIdx.x);
-                if (t0 + 2 * kBlock < nsh) sfetch(sa, t0 + 2 * kBlock + threadIdx.x);
-                if (t0 + kBlock < nsh) sprocess(sb, t0 + kBlock + threadIdx.x);
+                if (t0 + 2 * kSBlock < nsh) sfetch(sa, t0 + 2 * kSBlock + threadIdx.x);
+                if (t0 + kSBlock < nsh) sprocess(sb, t0 + kSBlock + threadIdx.x);
             }
         } else {
         // two register sets, each chunk's loads issued one chunk ahead of its use
-        constexpr int CH = kBlock * U;
+        constexpr int CH = kSBlock * U;
         Raw<MIX> ra[U], rb[U];
         auto fetch = [&](Raw<MIX> *r, int base) {
 #pragma unroll
             for (int j = 0; j < U; ++j)
-                load_raw<MIX, DIM, VDIM>(p, i0 + min(base + j * kBlock + (int)threadIdx.x, span - 1), r[j]);
+                load_raw<MIX, DIM, VDIM>(p, i0 + min(base + j * kSBlock + (int)threadIdx.x, span - 1), r[j]);
             // keep these loads where they are: issued one chunk ahead of their use
             __builtin_amdgcn_sched_barrier(0);
         };
         auto process = [&](Raw<MIX> *r, int base) {
 #pragma unroll
             for (int j = 0; j < U; ++j) {
-                const int k = base + j * kBlock + threadIdx.x;
+                const int k = base + j * kSBlock + threadIdx.x;
                 const bool act = k < span;
                 int code = -1, nbk = 0;
                 if (act) {
@@ -998,7 +998,7 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
         if (threadIdx.x < kTab) cnt[b * kTab + threadIdx.x] = sCnt[threadIdx.x];
         if (threadIdx.x < kFar) {
             int v = 0;
-            for (int w2 = 0; w2 < kWaves; ++w2) v += sCnt[w2 * kDirs + threadIdx.x];
+            for (int w2 = 0; w2 < kSWaves; ++w2) v += sCnt[w2 * kDirs + threadIdx.x];
             if (v) atomicAdd(&tot[dir_target<DIM>(g, bx, by, bz, threadIdx.x)], v);
         }
         __syncthreads();
@@ -1015,13 +1015,13 @@ __global__ void __launch_bounds__(kBlock) k_step_count(Geo g, Parts p, const int
 template <int DIM>
 __device__ __forceinline__ void dest_offsets_wave(const Geo &g, int nbk, int run, const int32_t *cnt, int32_t *offs) {
     constexpr int kDirs = Dir<DIM>::kN, kFar = Dir<DIM>::kFar, kTab = Dir<DIM>::kTab;
-    constexpr int kIn = kFar * kWaves;  // incoming entries per destination
+    constexpr int kIn = kFar * kSWaves;  // incoming entries per destination
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int r = 0; r < (kIn + 63) / 64; ++r) {
-        const int e = r * 64 + lane;    // entry e = d * kWaves + wave
+        const int e = r * 64 + lane;    // entry e = d * kSWaves + wave
         const bool ok = e < kIn;
-        const int d = ok ? e / kWaves : 0, wv = ok ? e % kWaves : 0;
+        const int d = ok ? e / kSWaves : 0, wv = ok ? e % kSWaves : 0;
         const int src = ok ? dir_source<DIM>(g, nbk, d) : 0;
         const int v = ok ? cnt[src * kTab + wv * kDirs + d] : 0;
         int inc = v;
@@ -1035,9 +1035,9 @@ __device__ __forceinline__ void dest_offsets_wave(const Geo &g, int nbk, int run
 }
 
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_dest_offsets(Geo g, const int32_t *cnt, const int32_t *start,
+__global__ void __launch_bounds__(kSBlock) k_dest_offsets(Geo g, const int32_t *cnt, const int32_t *start,
                                                          int32_t *offs) {
-    const int nbk = (int)blockIdx.x * kWaves + (int)(threadIdx.x >> 6);
+    const int nbk = (int)blockIdx.x * kSWaves + (int)(threadIdx.x >> 6);
     if (nbk >= g.nbuckets) return;      // whole waves leave together; no barrier below
     dest_offsets_wave<DIM>(g, nbk, start[nbk], cnt, offs);
 }
@@ -1052,23 +1052,23 @@ __global__ void __launch_bounds__(kBlock) k_dest_offsets(Geo g, const int32_t *c
 // the next step's launch (the two buffers alternate).
 constexpr int kFusedScanMax = 4096;
 
-__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *sh /* [kWaves] */) {
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *sh /* [kSWaves] */) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) sh[w] = v;
     __syncthreads();
     int64_t t = 0;
-    for (int i = 0; i < kWaves; ++i) t += sh[i];
+    for (int i = 0; i < kSWaves; ++i) t += sh[i];
     return t;
 }
 
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_scan_offsets(Geo g, const int32_t *tot, int32_t *tot_next,
+__global__ void __launch_bounds__(kSBlock) k_scan_offsets(Geo g, const int32_t *tot, int32_t *tot_next,
                                                          int32_t *start, int64_t n, int64_t max_per, int step_mode,
                                                          int walls, const int32_t *cnt, int32_t *offs, CtxDev c) {
-    __shared__ int64_t sh[kWaves];
+    __shared__ int64_t sh[kSWaves];
     const int nb = g.nbuckets;
-    const int first = (int)blockIdx.x * kWaves;
+    const int first = (int)blockIdx.x * kSWaves;
     int64_t part = 0;
     for (int b = threadIdx.x; b < first; b += blockDim.x) part += tot[b];
     const int64_t base = block_sum_i64(part, sh);
@@ -1104,7 +1104,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_offsets(Geo g, const int32_t *t
 // EM: the electromagnetic form (FP64 2D3V): E is the [6][G] Yee field and
 // acc the [3][G] current J^{n+1/2} (Esirkepov), accumulated with atomics.
 template <bool MIX, int DIM, int VDIM, int U, bool HC, bool EM>
-__global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts dst, const int32_t *bstart,
+__global__ void __launch_bounds__(kSBlock) k_step_push(Geo g, Parts src, Parts dst, const int32_t *bstart,
                                                       const int32_t *bstart_new, const int32_t *cnt,
                                                       const int32_t *offs, int32_t *farcnt, const double *E, PushC pc,
                                                       typename AccOf<MIX>::T *acc, int32_t *perm, double *part,
@@ -1115,11 +1115,11 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
     constexpr int kCodeBits = Dir<DIM>::kCodeBits;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sErr;
-    __shared__ double sRed[kWaves];
+    __shared__ double sRed[kSWaves];
     __shared__ int32_t sRun[kTab];
     __shared__ int32_t sEnd[kFar];   // end of each neighbour destination bucket (slot bound)
-    __shared__ int32_t sBack[kWaves];    // next free slot, from the back, of each wave's stay range
-    __shared__ int32_t sFront0[kWaves];  // first slot of each wave's stay range
+    __shared__ int32_t sBack[kSWaves];    // next free slot, from the back, of each wave's stay range
+    __shared__ int32_t sFront0[kSWaves];  // first slot of each wave's stay range
     const int ex_w = (1 << g.tsx) + 1, ey_w = (DIM >= 2) ? (1 << g.tsy) + 1 : 1;
     const int ez_w = (DIM == 3) ? (1 << g.tsz) + 1 : 1;
     const int wx = (1 << g.tsx) + 1 + 2 * g.halo;
@@ -1152,7 +1152,7 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
         auto fetch = [&](Raw<MIX> *r, int base) {
 #pragma unroll
             for (int j = 0; j < U; ++j)
-                load_raw<MIX, DIM, VDIM>(src, i0 + min(base + j * kBlock + (int)threadIdx.x, span - 1), r[j]);
+                load_raw<MIX, DIM, VDIM>(src, i0 + min(base + j * kSBlock + (int)threadIdx.x, span - 1), r[j]);
             // keep these loads where they are: issued one chunk ahead of their use
             __builtin_amdgcn_sched_barrier(0);
         };
@@ -1193,7 +1193,7 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
         const float tye = (float)tn.tye;
         const float tze = (float)tn.tze;
         double ke = 0.0, px = 0.0;
-        constexpr int CH = kBlock * U;
+        constexpr int CH = kSBlock * U;
         // Two schedules over chunks of CH particles.
         // FP64 (twice the bytes per particle, latency-exposed): a software
         // pipeline whose loads of chunk c+1 and stores of chunk c-1 are both
@@ -1225,7 +1225,7 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
         auto process = [&](const Raw<MIX> *r, int base) {
 #pragma unroll
             for (int j = 0; j < U; ++j) {
-                const int k = base + j * kBlock + threadIdx.x;
+                const int k = base + j * kSBlock + threadIdx.x;
                 const bool act = k < span;
                 int code = -1, nbk = 0;
                 bool deep = false;
@@ -1411,7 +1411,7 @@ __global__ void __launch_bounds__(kBlock) k_step_push(Geo g, Parts src, Parts ds
             sBack[w] = back;
         }
         __syncthreads();
-        if (threadIdx.x < kWaves) {
+        if (threadIdx.x < kSWaves) {
             // deep range of each wave's stays, relative to this bucket's new start
             const int t = threadIdx.x;
             deep_out[b * kDeepTab + 2 * t] = sFront0[t] - bstart_new[b];
@@ -1724,7 +1724,7 @@ hipError_t launch_gather_push(const Geo &g, bool mixed, const Parts &p, int64_t 
 // Persistent grid: as many blocks as fit on the device at once (a multiple of
 // 8 for the XCD walk), never more than the bucket count needs.
 template <typename K>
-int persistent_grid(K kernel, size_t shmem, int nbuckets) {
+int persistent_grid(K kernel, size_t shmem, int nbuckets, int block = kBlock) {
     static int cus = 0;
     if (!cus) {
         int dev = 0;
@@ -1733,7 +1733,7 @@ int persistent_grid(K kernel, size_t shmem, int nbuckets) {
             cus = 256;
     }
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, shmem) != hipSuccess || per_cu <= 0)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, shmem) != hipSuccess || per_cu <= 0)
         per_cu = 4;
     int g = cus * per_cu;
     const int need = grid_for_buckets(nbuckets);
@@ -1747,7 +1747,7 @@ hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int
     if (g.em) {
         const size_t sh = em_f_tile_bytes(g, mixed);
         auto go = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, p, bstart,
+            hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets, kSBlock)), dim3(kSBlock), sh, s, g, p, bstart,
                                E, pc, cnt, tot, farcnt, deep, c);
         };
         if (mixed && g.hc) go(k_step_count<true, 2, 3, APIC_STEP_U, true, true>);
@@ -1759,7 +1759,7 @@ hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int
     size_t sh = tile_e_bytes(g, mixed);
     APIC_DISPATCH(g, mixed, {
         auto kern = k_step_count<MIX, DIM, VDIM, U, HC, false>;
-        hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, p, bstart, E,
+        hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets, kSBlock)), dim3(kSBlock), sh, s, g, p, bstart, E,
                            pc, cnt, tot, farcnt, deep, c);
     });
     return hipGetLastError();
@@ -1777,29 +1777,29 @@ bool fused_scan_offsets(const Geo &g) { return g.nbuckets <= kFusedScanMax; }
 hipError_t launch_scan_offsets(const Geo &g, const int32_t *tot, int32_t *tot_next, int32_t *start, int64_t n,
                                int64_t max_per_bucket, int step_mode, const int32_t *cnt, int32_t *offs,
                                const CtxDev &c, hipStream_t s) {
-    const dim3 grid((g.nbuckets + kWaves - 1) / kWaves);
+    const dim3 grid((g.nbuckets + kSWaves - 1) / kSWaves);
     const int walls = g.walls ? 1 : 0;
     if (g.dim == 3)
-        hipLaunchKernelGGL(k_scan_offsets<3>, grid, dim3(kBlock), 0, s, g, tot, tot_next, start, n, max_per_bucket,
+        hipLaunchKernelGGL(k_scan_offsets<3>, grid, dim3(kSBlock), 0, s, g, tot, tot_next, start, n, max_per_bucket,
                            step_mode, walls, cnt, offs, c);
     else if (g.dim == 2)
-        hipLaunchKernelGGL(k_scan_offsets<2>, grid, dim3(kBlock), 0, s, g, tot, tot_next, start, n, max_per_bucket,
+        hipLaunchKernelGGL(k_scan_offsets<2>, grid, dim3(kSBlock), 0, s, g, tot, tot_next, start, n, max_per_bucket,
                            step_mode, walls, cnt, offs, c);
     else
-        hipLaunchKernelGGL(k_scan_offsets<1>, grid, dim3(kBlock), 0, s, g, tot, tot_next, start, n, max_per_bucket,
+        hipLaunchKernelGGL(k_scan_offsets<1>, grid, dim3(kSBlock), 0, s, g, tot, tot_next, start, n, max_per_bucket,
                            step_mode, walls, cnt, offs, c);
     return hipGetLastError();
 }
 
 hipError_t launch_dest_offsets(const Geo &g, const int32_t *cnt, const int32_t *start, int32_t *offs,
                                hipStream_t s) {
-    const dim3 grid((g.nbuckets + kWaves - 1) / kWaves);
+    const dim3 grid((g.nbuckets + kSWaves - 1) / kSWaves);
     if (g.dim == 3)
-        hipLaunchKernelGGL(k_dest_offsets<3>, grid, dim3(kBlock), 0, s, g, cnt, start, offs);
+        hipLaunchKernelGGL(k_dest_offsets<3>, grid, dim3(kSBlock), 0, s, g, cnt, start, offs);
     else if (g.dim == 2)
-        hipLaunchKernelGGL(k_dest_offsets<2>, grid, dim3(kBlock), 0, s, g, cnt, start, offs);
+        hipLaunchKernelGGL(k_dest_offsets<2>, grid, dim3(kSBlock), 0, s, g, cnt, start, offs);
     else
-        hipLaunchKernelGGL(k_dest_offsets<1>, grid, dim3(kBlock), 0, s, g, cnt, start, offs);
+        hipLaunchKernelGGL(k_dest_offsets<1>, grid, dim3(kSBlock), 0, s, g, cnt, start, offs);
     return hipGetLastError();
 }
 
@@ -1810,7 +1810,7 @@ hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Pa
     if (g.em) {
         const size_t sh = em_j_tile_bytes(g) + em_f_tile_bytes(g, mixed);
         auto go = [&](auto kern, auto *accp) {
-            hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, src, dst,
+            hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets, kSBlock)), dim3(kSBlock), sh, s, g, src, dst,
                                bstart, bstart_new, cnt, offs, farcnt, E, pc, accp, perm, part, deep, c);
         };
         unsigned long long *am = (unsigned long long *)acc;
@@ -1824,7 +1824,7 @@ hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Pa
     size_t sh = tile_acc_bytes(g, g.halo) + tile_e_bytes(g, mixed);
     APIC_DISPATCH(g, mixed, {
         auto kern = k_step_push<MIX, DIM, VDIM, U, HC, false>;
-        hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets)), dim3(kBlock), sh, s, g, src, dst,
+        hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets, kSBlock)), dim3(kSBlock), sh, s, g, src, dst,
                            bstart, bstart_new, cnt, offs, farcnt, E, pc, (typename AccOf<MIX>::T *)acc, perm, part,
                            deep, c);
     });
