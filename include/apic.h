@@ -129,7 +129,9 @@ typedef struct {
  *             apic_gather_push and apic_step. NULL in apic_deposit /
  *             apic_gather_push selects the unsorted (untiled) kernels.
  * perm        [dev, int32, n] optional output of apic_sort_by_cell:
- *             sorted[i] = unsorted[perm[i]]. NULL = not written. */
+ *             sorted[i] = unsorted[perm[i]]. NULL = not written.
+ * n may be 0 (an empty plasma: the particle arrays are not read and may be
+ * NULL; the charge is the ion background alone and E stays zero). */
 typedef struct {
     int64_t n;
     double *x, *y;

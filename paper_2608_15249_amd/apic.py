@@ -151,7 +151,7 @@ class Context:
         self.mixed = precision == "mixed"
         if q_macro is None:
             vol = lx * (ly if dim >= 2 else 1.0) * (lz if dim == 3 else 1.0)
-            q_macro = -rho_ion * vol / n
+            q_macro = -rho_ion * vol / n if n > 0 else 0.0
         tz = tile[2] if len(tile) > 2 else 0
         self.desc = GridDesc(dim, vdim, nx, ny if dim >= 2 else 1, lx, ly if dim >= 2 else 1.0, dt, qm, q_macro,
                              rho_ion, bz, APIC_MIXED if self.mixed else APIC_FP64, frac_bits, tile[0], tile[1],

@@ -151,6 +151,8 @@ Parts parts_ws(const apic_ctx *c, void *ws) {
 apic_status check_parts(apic_ctx *c, const apic_particles *p, bool need_bstart) {
     if (!p) return fail(c, APIC_EINVAL, "particles is NULL");
     if (p->n != c->n) return fail(c, APIC_EINVAL, "particles.n differs from the context's particle count");
+    if (need_bstart && !p->bucket_start) return fail(c, APIC_EINVAL, "bucket_start is NULL");
+    if (c->n == 0) return APIC_OK;   // an empty plasma: no particle array is read
     const int dim = c->d.dim, vdim = c->d.vdim;
     if (c->mixed) {
         if (!p->cell || !p->ox || (dim >= 2 && !p->oy) || (dim == 3 && !p->oz))
