@@ -256,18 +256,29 @@ template <> struct Raw<false> {
 
 template <bool MIX, int DIM, int VDIM>
 __device__ __forceinline__ void load_raw(const Parts &s, int i, Raw<MIX> &r) {
-    // each particle is read once per pass: the mixed path loads with the
-    // nontemporal hint (measured 1-2% faster on the push; the same hint made
-    // the FP64 push 5% slower, and nontemporal stores of the scattered
-    // destination slots made the mixed push 1.6x slower)
-    if constexpr (MIX) {
+    // each particle is read once per pass. The 2D2V mixed state loads with the
+    // nontemporal hint: measured 4% faster on the push at 512^2, 16.8M
+    // particles (the counters show 27% more bytes fetched, lines shared by
+    // neighbouring waves being fetched again). The same hint made the 2D3V
+    // mixed push 10% slower at 1024^2, 33.5M particles, and the FP64 push 5%
+    // slower, so the other forms load through the caches. Nontemporal stores
+    // of the scattered destination slots made the mixed push 1.6x slower.
+    if constexpr (MIX && DIM == 2 && VDIM == 2) {
         r.c = __builtin_nontemporal_load(&s.cell[i]);
         r.ox = __builtin_nontemporal_load(&s.ox[i]);
-        r.oy = (DIM >= 2) ? __builtin_nontemporal_load(&s.oy[i]) : 0.0f;
-        r.oz = (DIM == 3) ? __builtin_nontemporal_load(&s.oz[i]) : 0.0f;
+        r.oy = __builtin_nontemporal_load(&s.oy[i]);
+        r.oz = 0.0f;
         r.vx = __builtin_nontemporal_load(&((const float *)s.vx)[i]);
-        r.vy = (VDIM >= 2) ? __builtin_nontemporal_load(&((const float *)s.vy)[i]) : 0.0f;
-        r.vz = (VDIM >= 3) ? __builtin_nontemporal_load(&((const float *)s.vz)[i]) : 0.0f;
+        r.vy = __builtin_nontemporal_load(&((const float *)s.vy)[i]);
+        r.vz = 0.0f;
+    } else if constexpr (MIX) {
+        r.c = s.cell[i];
+        r.ox = s.ox[i];
+        r.oy = (DIM >= 2) ? s.oy[i] : 0.0f;
+        r.oz = (DIM == 3) ? s.oz[i] : 0.0f;
+        r.vx = ((const float *)s.vx)[i];
+        r.vy = (VDIM >= 2) ? ((const float *)s.vy)[i] : 0.0f;
+        r.vz = (VDIM >= 3) ? ((const float *)s.vz)[i] : 0.0f;
     } else {
         r.x = s.x[i];
         r.y = (DIM >= 2) ? s.y[i] : 0.0;
