@@ -104,7 +104,10 @@ void layout(apic_ctx *c) {
     c->o_tot = take(4 * 2 * nb);   // two alternating buffers
     c->o_deep = take(4 * nb * kDeepTab);
     c->o_acc = take(8 * G);
-    c->o_jacc = c->d.model == APIC_ELECTROMAGNETIC ? take(24 * G) : (size_t)-1;
+    // electromagnetic step: two current buffers and a second field buffer,
+    // alternating by step (the one-launch field update reads one, writes the other)
+    c->o_jacc = c->d.model == APIC_ELECTROMAGNETIC ? take(2 * 24 * G) : (size_t)-1;
+    c->o_f2 = c->d.model == APIC_ELECTROMAGNETIC ? take(48 * G) : (size_t)-1;
     c->o_rho = take(8 * G);
     if (dim >= 2) {
         const int64_t H = (int64_t)(c->d.nx / 2 + 1) * c->d.ny * c->d.nz;

@@ -22,7 +22,7 @@ using namespace apic_host;
 namespace apic {
 namespace {
 
-constexpr int kEmDiagBlocks = 512;   // partials per energy in part_spec (two halves)
+constexpr int kEmStepBlocks = 2048;  // most workgroups (and partials per energy) of the one-launch field update
 
 __device__ __forceinline__ int wrap_up(int i, int n) { return i + 1 == n ? 0 : i + 1; }
 __device__ __forceinline__ int wrap_dn(int i, int n) { return i == 0 ? n - 1 : i - 1; }
@@ -41,72 +41,135 @@ __global__ void __launch_bounds__(kBlock) k_em_init(Geo g, const double *phi, do
     }
 }
 
-// Faraday on the B locations: Bx -= h dEz/dy, By += h dEz/dx,
-// Bz -= h (dEy/dx - dEx/dy) (forward differences). With diag, the per-block
-// partials of sum |E|^2 and sum |B - B0|^2 after the update.
+// The whole field update of one step in one launch, tile by tile (32 x 8
+// nodes, one per thread): B^{n+1/2}, E^{n+1} and B^{n+1} with the operations
+// of the three kernels above, in the same order, so the results are the same
+// bits. A tile stages E^n from one node below its first to two beyond its
+// last along each axis and B^n from one below to one beyond (the second B
+// half step needs E^{n+1} one node beyond the tile, that needs B^{n+1/2} one
+// node below, and that needs E^n one node beyond), computes the intermediate
+// values over that halo, and writes its own nodes of E^{n+1} and B^{n+1} to
+// Fn. The step reads F and J and writes Fn: neighbouring tiles
+// read F while this one writes, so the caller alternates two field buffers,
+// and J is only read here; Jnext (the current buffer of the next step) is
+// cleared instead. With diag, per-block partials of sum |E^{n+1}|^2 and
+// sum |B^{n+1} - B0|^2 over the tiles the block owns.
+constexpr int kFTX = 32, kFTY = 8;
+static_assert(kFTX * kFTY == kBlock, "one node per thread");
+
 template <bool DIAG>
-__global__ void __launch_bounds__(kBlock) k_fdtd_b(Geo g, double *F, double h, double bz, double *part) {
-    const int64_t G = (int64_t)g.nx * g.ny;
+__global__ void __launch_bounds__(kBlock) k_fdtd_step(Geo g, const double *F, double *Fn, const double *J,
+                                                      double *Jnext, double *Jout, double dt, double c2, double bz,
+                                                      double *part) {
+    __shared__ double sE[3][kFTY + 3][kFTX + 3];   // E^n from node (x0 - 1, y0 - 1)
+    __shared__ double sB[3][kFTY + 2][kFTX + 2];   // B^n, then B^{n+1/2}, from (x0 - 1, y0 - 1)
+    __shared__ double sN[3][kFTY + 1][kFTX + 1];   // E^{n+1} from (x0, y0)
+    const int nx = g.nx, ny = g.ny;
+    const int64_t G = (int64_t)nx * ny;
+    const double h = 0.5 * dt;
+    const int ntx = (nx + kFTX - 1) / kFTX, nty = (ny + kFTY - 1) / kFTY;
+    const int lx0 = threadIdx.x % kFTX, ly0 = threadIdx.x / kFTX;
+    // periodic node index (the halo can reach more than one period on grids
+    // narrower than a tile)
+    auto wrapx = [nx](int x) {
+        const int r = x % nx;
+        return r < 0 ? r + nx : r;
+    };
+    auto wrapy = [ny](int y) {
+        const int r = y % ny;
+        return r < 0 ? r + ny : r;
+    };
     double we = 0.0, wb = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G; i += (int64_t)gridDim.x * blockDim.x) {
-        const int ix = (int)(i % g.nx), iy = (int)(i / g.nx);
-        const int64_t xp = (int64_t)iy * g.nx + wrap_up(ix, g.nx), yp = (int64_t)wrap_up(iy, g.ny) * g.nx + ix;
-        const double ex = F[i], ey = F[G + i], ez = F[2 * G + i];
-        const double bx = F[3 * G + i] - h * ((F[2 * G + yp] - ez) * g.inv_dy);
-        const double by = F[4 * G + i] + h * ((F[2 * G + xp] - ez) * g.inv_dx);
-        const double bzn = F[5 * G + i] - h * ((F[G + xp] - ey) * g.inv_dx - (F[yp] - ex) * g.inv_dy);
-        F[3 * G + i] = bx;
-        F[4 * G + i] = by;
-        F[5 * G + i] = bzn;
-        if constexpr (DIAG) {
-            we += (ex * ex + ey * ey) + ez * ez;
-            wb += (bx * bx + by * by) + (bzn - bz) * (bzn - bz);
+    for (int t = blockIdx.x; t < ntx * nty; t += gridDim.x) {
+        const int x0 = (t % ntx) * kFTX, y0 = (t / ntx) * kFTY;
+        for (int k = threadIdx.x; k < 3 * (kFTY + 3) * (kFTX + 3); k += blockDim.x) {
+            const int c = k / ((kFTY + 3) * (kFTX + 3)), r = k % ((kFTY + 3) * (kFTX + 3));
+            const int ly = r / (kFTX + 3), lx = r % (kFTX + 3);
+            sE[c][ly][lx] = F[c * G + (int64_t)wrapy(y0 - 1 + ly) * nx + wrapx(x0 - 1 + lx)];
         }
+        for (int k = threadIdx.x; k < 3 * (kFTY + 2) * (kFTX + 2); k += blockDim.x) {
+            const int c = k / ((kFTY + 2) * (kFTX + 2)), r = k % ((kFTY + 2) * (kFTX + 2));
+            const int ly = r / (kFTX + 2), lx = r % (kFTX + 2);
+            sB[c][ly][lx] = F[(3 + c) * G + (int64_t)wrapy(y0 - 1 + ly) * nx + wrapx(x0 - 1 + lx)];
+        }
+        __syncthreads();
+        // B^{n+1/2} over the staged B nodes (forward differences of E^n)
+        for (int k = threadIdx.x; k < (kFTY + 2) * (kFTX + 2); k += blockDim.x) {
+            const int ly = k / (kFTX + 2), lx = k % (kFTX + 2);
+            const double ex = sE[0][ly][lx], ey = sE[1][ly][lx], ez = sE[2][ly][lx];
+            const double bx = sB[0][ly][lx] - h * ((sE[2][ly + 1][lx] - ez) * g.inv_dy);
+            const double by = sB[1][ly][lx] + h * ((sE[2][ly][lx + 1] - ez) * g.inv_dx);
+            const double bzn =
+                sB[2][ly][lx] - h * ((sE[1][ly][lx + 1] - ey) * g.inv_dx - (sE[0][ly + 1][lx] - ex) * g.inv_dy);
+            sB[0][ly][lx] = bx;
+            sB[1][ly][lx] = by;
+            sB[2][ly][lx] = bzn;
+        }
+        __syncthreads();
+        // E^{n+1} over the tile and one node beyond (backward differences of B^{n+1/2})
+        for (int k = threadIdx.x; k < (kFTY + 1) * (kFTX + 1); k += blockDim.x) {
+            const int ey_ = k / (kFTX + 1), ex_ = k % (kFTX + 1);
+            const int64_t gi = (int64_t)wrapy(y0 + ey_) * nx + wrapx(x0 + ex_);
+            const double jx = J[gi], jy = J[G + gi], jz = J[2 * G + gi];
+            const double bzc = sB[2][ey_ + 1][ex_ + 1], byc = sB[1][ey_ + 1][ex_ + 1], bxc = sB[0][ey_ + 1][ex_ + 1];
+            sN[0][ey_][ex_] = sE[0][ey_ + 1][ex_ + 1] + dt * (c2 * ((bzc - sB[2][ey_][ex_ + 1]) * g.inv_dy) - jx);
+            sN[1][ey_][ex_] = sE[1][ey_ + 1][ex_ + 1] + dt * (-c2 * ((bzc - sB[2][ey_ + 1][ex_]) * g.inv_dx) - jy);
+            sN[2][ey_][ex_] = sE[2][ey_ + 1][ex_ + 1] +
+                              dt * (c2 * ((byc - sB[1][ey_ + 1][ex_]) * g.inv_dx - (bxc - sB[0][ey_][ex_ + 1]) * g.inv_dy) -
+                                    jz);
+        }
+        __syncthreads();
+        // B^{n+1} and the writes of this tile's own nodes
+        {
+            const int gx = x0 + lx0, gy = y0 + ly0;
+            if (gx < nx && gy < ny) {
+                const int64_t gi = (int64_t)gy * nx + gx;
+                const double ex = sN[0][ly0][lx0], ey = sN[1][ly0][lx0], ez = sN[2][ly0][lx0];
+                const double bx = sB[0][ly0 + 1][lx0 + 1] - h * ((sN[2][ly0 + 1][lx0] - ez) * g.inv_dy);
+                const double by = sB[1][ly0 + 1][lx0 + 1] + h * ((sN[2][ly0][lx0 + 1] - ez) * g.inv_dx);
+                const double bzn = sB[2][ly0 + 1][lx0 + 1] -
+                                   h * ((sN[1][ly0][lx0 + 1] - ey) * g.inv_dx - (sN[0][ly0 + 1][lx0] - ex) * g.inv_dy);
+                Fn[gi] = ex;
+                Fn[G + gi] = ey;
+                Fn[2 * G + gi] = ez;
+                Fn[3 * G + gi] = bx;
+                Fn[4 * G + gi] = by;
+                Fn[5 * G + gi] = bzn;
+                if (Jout) {
+                    Jout[gi] = J[gi];
+                    Jout[G + gi] = J[G + gi];
+                    Jout[2 * G + gi] = J[2 * G + gi];
+                }
+                Jnext[gi] = 0.0;
+                Jnext[G + gi] = 0.0;
+                Jnext[2 * G + gi] = 0.0;
+                if constexpr (DIAG) {
+                    we += (ex * ex + ey * ey) + ez * ez;
+                    wb += (bx * bx + by * by) + (bzn - bz) * (bzn - bz);
+                }
+            }
+        }
+        __syncthreads();
     }
     if constexpr (DIAG) {
         __shared__ double sRed[kWaves];
         const double a = block_sum(we, sRed), b = block_sum(wb, sRed);
         if (threadIdx.x == 0) {
             part[blockIdx.x] = a;
-            part[kEmDiagBlocks + blockIdx.x] = b;
+            part[kEmStepBlocks + blockIdx.x] = b;
         }
-    }
-}
-
-// Ampere on the E locations: Ex += dt (c^2 dBz/dy - Jx),
-// Ey += dt (-c^2 dBz/dx - Jy), Ez += dt (c^2 (dBy/dx - dBx/dy) - Jz)
-// (backward differences); J is read, optionally copied out, and cleared.
-__global__ void __launch_bounds__(kBlock) k_fdtd_e(Geo g, double *F, double *J, double *Jout, double dt,
-                                                   double c2) {
-    const int64_t G = (int64_t)g.nx * g.ny;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G; i += (int64_t)gridDim.x * blockDim.x) {
-        const int ix = (int)(i % g.nx), iy = (int)(i / g.nx);
-        const int64_t xm = (int64_t)iy * g.nx + wrap_dn(ix, g.nx), ym = (int64_t)wrap_dn(iy, g.ny) * g.nx + ix;
-        const double jx = J[i], jy = J[G + i], jz = J[2 * G + i];
-        if (Jout) {
-            Jout[i] = jx;
-            Jout[G + i] = jy;
-            Jout[2 * G + i] = jz;
-        }
-        J[i] = 0.0;
-        J[G + i] = 0.0;
-        J[2 * G + i] = 0.0;
-        const double bz = F[5 * G + i], by = F[4 * G + i], bx = F[3 * G + i];
-        F[i] += dt * (c2 * ((bz - F[5 * G + ym]) * g.inv_dy) - jx);
-        F[G + i] += dt * (-c2 * ((bz - F[5 * G + xm]) * g.inv_dx) - jy);
-        F[2 * G + i] += dt * (c2 * ((by - F[4 * G + xm]) * g.inv_dx - (bx - F[3 * G + ym]) * g.inv_dy) - jz);
     }
 }
 
 // diag[step] = (W_B, W_E, kinetic, momentum) from fixed-order sums of the
 // field partials and the push partials.
-__global__ void __launch_bounds__(1024) k_em_finalize(int nblk, int npush, double c2, double dV, double mass,
-                                                      double *diag, CtxDev c) {
+__global__ void __launch_bounds__(1024) k_em_finalize(int nblk, int half, int npush, double c2, double dV,
+                                                      double mass, double *diag, CtxDev c) {
     __shared__ double sRed[16];
     double we = 0.0, wb = 0.0, k = 0.0, p = 0.0;
     for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
         we += c.part_spec[i];
-        wb += c.part_spec[kEmDiagBlocks + i];
+        wb += c.part_spec[half + i];
     }
     for (int i = threadIdx.x; i < npush; i += blockDim.x) {
         k += c.part_push[2 * i];
@@ -201,29 +264,40 @@ hipError_t launch_em_gather_push(const Geo &g, bool mixed, const Parts &p, int64
     return hipGetLastError();
 }
 
-hipError_t launch_fdtd_b(const Geo &g, double *F, double h, hipStream_t s) {
-    hipLaunchKernelGGL(k_fdtd_b<false>, dim3(em_blocks((int64_t)g.nx * g.ny, 4096)), dim3(kBlock), 0, s, g, F, h,
-                       0.0, nullptr);
+static_assert(2 * kEmStepBlocks <= kMaxSpecBlocks, "field partials fit part_spec");
+
+hipError_t launch_fdtd_step(const Geo &g, const double *F, double *Fn, const double *J, double *Jnext, double *Jout,
+                            double dt, double c2, double bz, double dV, double mass, int npush, double *diag,
+                            const CtxDev &c, hipStream_t s) {
+    // one round of resident workgroups (measured at 1024^2: 53 us with one
+    // round, 60 us with 2048 workgroups, 62 us with 1024)
+    static int resident = 0;
+    if (!resident) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fdtd_step<true>, kBlock, 0) != hipSuccess ||
+            per_cu <= 0)
+            per_cu = 4;
+        resident = cus * per_cu;
+    }
+    const int nt = ((g.nx + kFTX - 1) / kFTX) * ((g.ny + kFTY - 1) / kFTY);
+    int nblk = nt < resident ? nt : resident;
+    if (nblk > kEmStepBlocks) nblk = kEmStepBlocks;
+    if (diag) {
+        hipLaunchKernelGGL(k_fdtd_step<true>, dim3(nblk), dim3(kBlock), 0, s, g, F, Fn, J, Jnext, Jout, dt, c2, bz,
+                           c.part_spec);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_em_finalize, dim3(1), dim3(1024), 0, s, nblk, kEmStepBlocks, npush, c2, dV, mass, diag,
+                           c);
+    } else {
+        hipLaunchKernelGGL(k_fdtd_step<false>, dim3(nblk), dim3(kBlock), 0, s, g, F, Fn, J, Jnext, Jout, dt, c2, bz,
+                           nullptr);
+    }
     return hipGetLastError();
 }
-
-hipError_t launch_fdtd_e(const Geo &g, double *F, double *J, double *Jout, double dt, double c2, hipStream_t s) {
-    hipLaunchKernelGGL(k_fdtd_e, dim3(em_blocks((int64_t)g.nx * g.ny, 4096)), dim3(kBlock), 0, s, g, F, J, Jout, dt,
-                       c2);
-    return hipGetLastError();
-}
-
-hipError_t launch_fdtd_b_diag(const Geo &g, double *F, double h, double bz, double c2, double dV, double mass,
-                              int npush, double *diag, const CtxDev &c, hipStream_t s) {
-    const int nblk = em_blocks((int64_t)g.nx * g.ny, kEmDiagBlocks);
-    hipLaunchKernelGGL(k_fdtd_b<true>, dim3(nblk), dim3(kBlock), 0, s, g, F, h, bz, c.part_spec);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_em_finalize, dim3(1), dim3(1024), 0, s, nblk, npush, c2, dV, mass, diag, c);
-    return hipGetLastError();
-}
-
-static_assert(2 * kEmDiagBlocks <= kMaxSpecBlocks, "field partials fit part_spec");
 
 }  // namespace apic
 
@@ -301,7 +375,8 @@ apic_status apic_em_step(apic_ctx *c, apic_particles *p, double *F, double *J, i
     // the bucket totals: two buffers, alternating by step
     HIPCHK(c, launch_fill_i32(tot, 2 * (int64_t)nb, 0, s));
     HIPCHK(c, launch_fill_i32(deep, (int64_t)nb * kDeepTab, 0, s));
-    HIPCHK(c, launch_fill_u64((uint64_t *)jacc, 3 * G, 0, s));
+    double *F2 = wsp<double>(ws, c->o_f2);
+    HIPCHK(c, launch_fill_u64((uint64_t *)jacc, 2 * 3 * G, 0, s));
     HIPCHK(c, launch_set_step(c->dev.step, -1, s));
     for (int k = 0; k < nsteps; ++k) {
         const bool even = (k & 1) == 0;
@@ -314,7 +389,10 @@ apic_status apic_em_step(apic_ctx *c, apic_particles *p, double *F, double *J, i
         if (c->prof_used < c->prof_max) ev = &c->ev[5 * (size_t)c->prof_used++];
         if (ev && c->prof_all) HIPCHK(c, hipEventRecord(ev[0], s));
         int32_t *tot_k = tot + (even ? 0 : nb), *tot_n = tot + (even ? nb : 0);
-        HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, F, pc, cnt, tot_k, farcnt, deep, c->dev, s));
+        // F^n in F on even steps and in F2 on odd ones; J^{n+1/2} alternates likewise
+        double *Fk = even ? F : F2, *Fk1 = even ? F2 : F;
+        double *Jk = jacc + (even ? 0 : 3 * G), *Jk1 = jacc + (even ? 3 * G : 0);
+        HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, Fk, pc, cnt, tot_k, farcnt, deep, c->dev, s));
         if (ev && c->prof_all) HIPCHK(c, hipEventRecord(ev[1], s));
         if (fused_scan_offsets(c->g)) {
             HIPCHK(c, launch_scan_offsets(c->g, tot_k, tot_n, bs_dst, c->n, max_per_bucket(c), 1, cnt, offs, c->dev,
@@ -324,21 +402,18 @@ apic_status apic_em_step(apic_ctx *c, apic_particles *p, double *F, double *J, i
             HIPCHK(c, launch_dest_offsets(c->g, cnt, bs_dst, offs, s));
         }
         if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
-        HIPCHK(c, launch_step_push(c->g, c->mixed, src, dst, bs_src, bs_dst, cnt, offs, farcnt, F, pc, jacc, p->perm,
+        HIPCHK(c, launch_step_push(c->g, c->mixed, src, dst, bs_src, bs_dst, cnt, offs, farcnt, Fk, pc, Jk, p->perm,
                                    diag ? c->dev.part_push : nullptr, deep, c->dev, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[3], s));
-        HIPCHK(c, launch_fdtd_b(c->g, F, 0.5 * dt, s));
-        HIPCHK(c, launch_fdtd_e(c->g, F, jacc, (J && last) ? J : nullptr, dt, c2, s));
-        if (diag)
-            HIPCHK(c, launch_fdtd_b_diag(c->g, F, 0.5 * dt, c->d.bz, c2, c->dV, c->mass, nb, diag, c->dev, s));
-        else
-            HIPCHK(c, launch_fdtd_b(c->g, F, 0.5 * dt, s));
+        HIPCHK(c, launch_fdtd_step(c->g, Fk, Fk1, Jk, Jk1, (J && last) ? J : nullptr, dt, c2, c->d.bz, c->dV, c->mass,
+                                   nb, diag, c->dev, s));
         if (ev && c->prof_all) HIPCHK(c, hipEventRecord(ev[4], s));
     }
     if (nsteps & 1) {
         st = copy_parts(c, A, B, s);
         if (st != APIC_OK) return st;
         HIPCHK(c, launch_copy_bytes(bsA, bsB, 4 * (int64_t)(nb + 1), s));
+        HIPCHK(c, launch_copy_bytes(F, F2, 48 * G, s));
     }
     return APIC_OK;
 }

@@ -83,7 +83,7 @@ struct FinArgs {
     const int32_t *nlive;
 };
 
-constexpr int kMaxSpecBlocks = 1024;
+constexpr int kMaxSpecBlocks = 4096;   // per-block partials of the field energies
 // Waves per workgroup of the fused step passes (tally, offsets, push): one
 // workgroup per bucket, so this sets the waves a tile's particles share.
 // Measured at 512^2, 16.8M particles: 6 or 8 waves per bucket were slower
@@ -194,14 +194,13 @@ hipError_t launch_em_init(const Geo &g, const double *phi, double bz, double *F,
 // gather E, B + Boris (+ move), in place (no ordering needed)
 hipError_t launch_em_gather_push(const Geo &g, bool mixed, const Parts &p, int64_t n, const double *F,
                                  const PushC &pc, const CtxDev &c, hipStream_t s);
-// B -= h curl E
-hipError_t launch_fdtd_b(const Geo &g, double *F, double h, hipStream_t s);
-// E += dt (c^2 curl B - J), then J = 0 (Jout, when not NULL, receives J first)
-hipError_t launch_fdtd_e(const Geo &g, double *F, double *J, double *Jout, double dt, double c2, hipStream_t s);
-// B -= h curl E with the per-block partials of sum |E|^2 and sum |B - B0|^2,
-// then one workgroup writes diag[step] = (c^2/2 dV sum |B - B0|^2,
-// 1/2 dV sum |E|^2, kinetic, momentum) from them and the push partials
-hipError_t launch_fdtd_b_diag(const Geo &g, double *F, double h, double bz, double c2, double dV, double mass,
-                              int npush, double *diag, const CtxDev &c, hipStream_t s);
+// The whole field update of a step in one launch: reads F [6][G] and J
+// [3][G], writes Fn [6][G] (a buffer other than F), clears Jnext [3][G] (the
+// next step's current) and copies J to Jout when not NULL. With diag, one
+// workgroup then writes diag[step] = (c^2/2 dV sum |B - B0|^2, 1/2 dV sum
+// |E|^2, kinetic, momentum) from the field partials and the push partials.
+hipError_t launch_fdtd_step(const Geo &g, const double *F, double *Fn, const double *J, double *Jnext, double *Jout,
+                            double dt, double c2, double bz, double dV, double mass, int npush, double *diag,
+                            const CtxDev &c, hipStream_t s);
 
 }  // namespace apic

@@ -1865,7 +1865,7 @@ hipError_t launch_rho_odd(const Geo &g, bool mixed, void *acc, double *rho, doub
     return hipGetLastError();
 }
 
-int spectral_blocks(const Geo &g) { return blocks_for((int64_t)(g.nx / 2 + 1) * g.ny * g.nz, kMaxSpecBlocks); }
+int spectral_blocks(const Geo &g) { return blocks_for((int64_t)(g.nx / 2 + 1) * g.ny * g.nz, 1024); }
 
 hipError_t launch_spectral(const Geo &g, const void *rho_hat, void *phi_hat, const CtxDev &c, hipStream_t s) {
     hipLaunchKernelGGL(k_spectral, dim3(spectral_blocks(g)), dim3(kBlock), 0, s, g, (const double2 *)rho_hat,

@@ -30,6 +30,8 @@ CASES = [
     # nx, ny, lx, ly, n, tile, dt, bz
     (37, 29, 37.0, 29.0 * 0.9, 30011, (8, 8), 0.1, 1.5),
     (40, 24, 40.0 * 1.1, 24.0, 40003, (16, 16), 0.1, 0.0),
+    # narrower than a field-update tile and its halo along both axes
+    (16, 12, 16.0, 12.0 * 1.1, 8011, (8, 4), 0.1, 0.7),
 ]
 
 
