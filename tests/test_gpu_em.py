@@ -32,6 +32,8 @@ CASES = [
     (40, 24, 40.0 * 1.1, 24.0, 40003, (16, 16), 0.1, 0.0),
     # narrower than a field-update tile and its halo along both axes
     (16, 12, 16.0, 12.0 * 1.1, 8011, (8, 4), 0.1, 0.7),
+    # the mixed path's default tile shape
+    (64, 48, 64.0, 48.0, 60013, (32, 16), 0.1, 1.0),
 ]
 
 
