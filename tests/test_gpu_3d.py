@@ -380,7 +380,7 @@ def test_mixed_local_field_energy_error_3d(torch):
 
 def test_full_size_3d_sampled(torch):
     """The benchmarked 3D plasma at full size (128^3 cells, 16,777,216
-    electrons, default 8^3 tiles), from the seeded host state: the GPU runs
+    electrons, the default tile), from the seeded host state: the GPU runs
     the field of the initial charge, the backward half push and one step with
     the permutations recorded; sampled particles equal the oracle's binary32
     half push and push of their initial state in the oracle's field of the
@@ -421,7 +421,8 @@ def test_full_size_3d_sampled(torch):
     for k in ("ix", "iy", "iz", "ox", "oy", "oz", "vx", "vy", "vz"):
         assert np.array_equal(m1[k], ref[k]), k
     ix, iy, iz = W.unpack_cell(after["cell"], 3)
-    key = O.bucket_key(ix, iy, 8, 8, w.nx, iz=iz, tile_z=8, ny=w.ny)
+    tx, ty, tz = c.tile
+    key = O.bucket_key(ix, iy, tx, ty, w.nx, iz=iz, tile_z=tz, ny=w.ny)
     bs = after["bucket_start"].astype(np.int64)
     assert bs[0] == 0 and bs[-1] == n and np.all(np.diff(bs) >= 0)
     assert np.array_equal(np.repeat(np.arange(len(bs) - 1), np.diff(bs)), key)
