@@ -345,9 +345,9 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     default_tiles(d, n_particles, tsx, tsy, tsz);
     if (d.model == APIC_ELECTROMAGNETIC) {
         // the six-component field tile and the current tile stay within LDS:
-        // 32 x 16 in the mixed path (4% faster than 16 x 16 at 1024^2, 33.5M
-        // particles; 32 x 32 leaves too few workgroups per CU), 16 x 16 in FP64
-        tsx = std::min(tsx, c->mixed ? 5 : 4);
+        // 32 x 16 (at 1024^2, 33.5M particles 4% faster than 16 x 16 in both
+        // precisions; 32 x 32 leaves too few workgroups per CU)
+        tsx = std::min(tsx, 5);
         tsy = std::min(tsy, 4);
     }
     if (d.tile_x) tsx = ilog2_floor(d.tile_x);
