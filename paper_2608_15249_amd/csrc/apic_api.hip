@@ -59,7 +59,12 @@ void default_tiles(const apic_grid_desc &d, int64_t n, int &tsx, int &tsy, int &
         tsy = std::min(3, std::max(1, (t + 1) / 3));
         tsz = std::min(3, std::max(1, t / 3));
     } else {
-        int t = ilog2_floor((int64_t)target);
+        // about 16384 particles per tile where the grid still has 1024 tiles
+        // or more (the autotuner's picks at 512^2 and 1024^2 hold 16384-32768
+        // particles: fewer cross a tile edge), else about 4096 (enough
+        // workgroups on small grids)
+        const double big = 4.0 * target;
+        int t = ilog2_floor((int64_t)(cells / big >= 1024.0 ? big : target));
         tsx = (t + 1) / 2;
         tsy = t / 2;
         if (tsx > 5) tsx = 5;
@@ -344,11 +349,11 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     int tsx, tsy, tsz;
     default_tiles(d, n_particles, tsx, tsy, tsz);
     if (d.model == APIC_ELECTROMAGNETIC) {
-        // the six-component field tile and the current tile stay within LDS:
-        // 32 x 16 (at 1024^2, 33.5M particles 4% faster than 16 x 16 in both
-        // precisions; 32 x 32 leaves too few workgroups per CU)
-        tsx = std::min(tsx, 5);
-        tsy = std::min(tsy, 4);
+        // 32 x 16: the six-component field tile and the current tile stay
+        // within LDS, and at 1024^2, 33.5M particles it is 4% faster than
+        // 16 x 16 in both precisions (32 x 32 leaves too few workgroups per CU)
+        tsx = 5;
+        tsy = 4;
     }
     if (d.tile_x) tsx = ilog2_floor(d.tile_x);
     if (d.dim >= 2 && d.tile_y) tsy = ilog2_floor(d.tile_y);
