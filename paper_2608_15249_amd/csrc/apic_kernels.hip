@@ -827,6 +827,13 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
         // field tile (one memory round trip for all three)
         const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
         const int span = i1 - i0;
+        // the 2D2V mixed state (loaded with the nontemporal hint) is read in
+        // whole 128-byte lines per wave: chunks start at the line boundary at
+        // or below the bucket's first particle, index k at chunk position
+        // k + sh (the push uses the same positions, so the waves' tallies agree)
+        constexpr bool kAlign = MIX && DIM == 2 && VDIM == 2 && !EM;
+        const int sh = kAlign ? (i0 & 31) : 0;
+        const int send = span > 0 ? span + sh : 0;
         int draw[2 * kSWaves];
 #pragma unroll
         for (int r = 0; r < 2 * kSWaves; ++r) draw[r] = deep[b * kDeepTab + r];
@@ -896,7 +903,7 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
             if ((threadIdx.x & 63) == 0) {
                 int st = 0;
 #pragma unroll
-                for (int r = 0; r < kSWaves; ++r) st += owned_by(da[r], da[r] + dc[r], w);
+                for (int r = 0; r < kSWaves; ++r) st += owned_by(da[r] + sh, da[r] + dc[r] + sh, w);
                 atomicAdd(&sCnt[w * kDirs + kStay], st);
             }
             // the shallow particles: indices of [0, span) outside the deep
@@ -932,7 +939,7 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
                 if (g.walls && q.ix >= g.nxp) return;   // absorbed by a wall: leaves the order
                 const int code = dir_local<DIM>(tn, lx + sx, ly + sy, lz + sz);
                 if (code < kFar) {
-                    atomicAdd(&sCnt[((k % kSBlock) >> 6) * kDirs + code], 1);
+                    atomicAdd(&sCnt[(((k + sh) % kSBlock) >> 6) * kDirs + code], 1);
                 } else {
                     const int nbk = bucket_of<MIX, DIM>(g, q.ix, q.iy, q.iz);
                     atomicAdd(&farcnt[nbk], 1);
@@ -954,15 +961,16 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
         auto fetch = [&](Raw<MIX> *r, int base) {
 #pragma unroll
             for (int j = 0; j < U; ++j)
-                load_raw<MIX, DIM, VDIM>(p, i0 + min(base + j * kSBlock + (int)threadIdx.x, span - 1), r[j]);
+                load_raw<MIX, DIM, VDIM>(p, i0 + min(max(base + j * kSBlock + (int)threadIdx.x - sh, 0), span - 1),
+                                         r[j]);
             // keep these loads where they are: issued one chunk ahead of their use
             __builtin_amdgcn_sched_barrier(0);
         };
         auto process = [&](Raw<MIX> *r, int base) {
 #pragma unroll
             for (int j = 0; j < U; ++j) {
-                const int k = base + j * kSBlock + threadIdx.x;
-                const bool act = k < span;
+                const int k = base + j * kSBlock + (int)threadIdx.x - sh;
+                const bool act = k >= 0 && k < span;
                 int code = -1, nbk = 0;
                 if (act) {
                     Pt<MIX> q;
@@ -998,11 +1006,11 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
             }
         };
         if (span > 0) fetch(ra, 0);
-        for (int base = 0; base < span; base += 2 * CH) {
-            if (base + CH < span) fetch(rb, base + CH);
+        for (int base = 0; base < send; base += 2 * CH) {
+            if (base + CH < send) fetch(rb, base + CH);
             process(ra, base);
-            if (base + 2 * CH < span) fetch(ra, base + 2 * CH);
-            if (base + CH < span) process(rb, base + CH);
+            if (base + 2 * CH < send) fetch(ra, base + 2 * CH);
+            if (base + CH < send) process(rb, base + CH);
         }
         }
         __syncthreads();
@@ -1159,11 +1167,17 @@ __global__ void __launch_bounds__(kSBlock) k_step_push(Geo g, Parts src, Parts d
         // trips overlap; the FP64 pipeline issues its first chunk below
         const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
         const int span = i1 - i0;
+        // whole 128-byte lines per wave for the 2D2V mixed state, as in the
+        // tally pass (index k at chunk position k + sh)
+        constexpr bool kAlign = MIX && DIM == 2 && VDIM == 2 && !EM;
+        const int sh = kAlign ? (i0 & 31) : 0;
+        const int send = span > 0 ? span + sh : 0;
         Raw<MIX> ra[U], rb[U];
         auto fetch = [&](Raw<MIX> *r, int base) {
 #pragma unroll
             for (int j = 0; j < U; ++j)
-                load_raw<MIX, DIM, VDIM>(src, i0 + min(base + j * kSBlock + (int)threadIdx.x, span - 1), r[j]);
+                load_raw<MIX, DIM, VDIM>(src, i0 + min(max(base + j * kSBlock + (int)threadIdx.x - sh, 0), span - 1),
+                                         r[j]);
             // keep these loads where they are: issued one chunk ahead of their use
             __builtin_amdgcn_sched_barrier(0);
         };
@@ -1236,8 +1250,8 @@ __global__ void __launch_bounds__(kSBlock) k_step_push(Geo g, Parts src, Parts d
         auto process = [&](const Raw<MIX> *r, int base) {
 #pragma unroll
             for (int j = 0; j < U; ++j) {
-                const int k = base + j * kSBlock + threadIdx.x;
-                const bool act = k < span;
+                const int k = base + j * kSBlock + (int)threadIdx.x - sh;
+                const bool act = k >= 0 && k < span;
                 int code = -1, nbk = 0;
                 bool deep = false;
                 Pt<MIX> q;
@@ -1398,7 +1412,7 @@ __global__ void __launch_bounds__(kSBlock) k_step_push(Geo g, Parts src, Parts d
         };
         if constexpr (kPipe) {
             if (span > 0) fetch(ra, 0);
-            for (int base = 0; base < span; base += CH) {
+            for (int base = 0; base < send; base += CH) {
                 __builtin_amdgcn_s_waitcnt(kWaitVmem);
                 __builtin_amdgcn_sched_barrier(0);
                 Raw<MIX> rc[U];
@@ -1410,11 +1424,11 @@ __global__ void __launch_bounds__(kSBlock) k_step_push(Geo g, Parts src, Parts d
             }
             commit();
         } else {
-            for (int base = 0; base < span; base += 2 * CH) {
-                if (base + CH < span) fetch(rb, base + CH);
+            for (int base = 0; base < send; base += 2 * CH) {
+                if (base + CH < send) fetch(rb, base + CH);
                 process(ra, base);
-                if (base + 2 * CH < span) fetch(ra, base + 2 * CH);
-                if (base + CH < span) process(rb, base + CH);
+                if (base + 2 * CH < send) fetch(ra, base + 2 * CH);
+                if (base + CH < send) process(rb, base + CH);
             }
         }
         if (__lane_id() == 0) {
