@@ -256,29 +256,20 @@ template <> struct Raw<false> {
 
 template <bool MIX, int DIM, int VDIM>
 __device__ __forceinline__ void load_raw(const Parts &s, int i, Raw<MIX> &r) {
-    // each particle is read once per pass. The 2D2V mixed state loads with the
-    // nontemporal hint: measured 4% faster on the push at 512^2, 16.8M
-    // particles (the counters show 27% more bytes fetched, lines shared by
-    // neighbouring waves being fetched again). The same hint made the 2D3V
-    // mixed push 10% slower at 1024^2, 33.5M particles, and the FP64 push 5%
-    // slower, so the other forms load through the caches. Nontemporal stores
-    // of the scattered destination slots made the mixed push 1.6x slower.
-    if constexpr (MIX && DIM == 2 && VDIM == 2) {
+    // each particle is read once per pass, in whole 128-byte lines per wave
+    // (the passes align their chunks). The mixed state loads with the
+    // nontemporal hint: measured at 512^2 (2D2V), 1024^2 (2D3V) and 128^3,
+    // it was faster or equal; the FP64 state loads through the caches (the
+    // hint made its push 5% slower). Nontemporal stores of the scattered
+    // destination slots made the mixed push 1.6x slower.
+    if constexpr (MIX) {
         r.c = __builtin_nontemporal_load(&s.cell[i]);
         r.ox = __builtin_nontemporal_load(&s.ox[i]);
-        r.oy = __builtin_nontemporal_load(&s.oy[i]);
-        r.oz = 0.0f;
+        r.oy = (DIM >= 2) ? __builtin_nontemporal_load(&s.oy[i]) : 0.0f;
+        r.oz = (DIM == 3) ? __builtin_nontemporal_load(&s.oz[i]) : 0.0f;
         r.vx = __builtin_nontemporal_load(&((const float *)s.vx)[i]);
-        r.vy = __builtin_nontemporal_load(&((const float *)s.vy)[i]);
-        r.vz = 0.0f;
-    } else if constexpr (MIX) {
-        r.c = s.cell[i];
-        r.ox = s.ox[i];
-        r.oy = (DIM >= 2) ? s.oy[i] : 0.0f;
-        r.oz = (DIM == 3) ? s.oz[i] : 0.0f;
-        r.vx = ((const float *)s.vx)[i];
-        r.vy = (VDIM >= 2) ? ((const float *)s.vy)[i] : 0.0f;
-        r.vz = (VDIM >= 3) ? ((const float *)s.vz)[i] : 0.0f;
+        r.vy = (VDIM >= 2) ? __builtin_nontemporal_load(&((const float *)s.vy)[i]) : 0.0f;
+        r.vz = (VDIM >= 3) ? __builtin_nontemporal_load(&((const float *)s.vz)[i]) : 0.0f;
     } else {
         r.x = s.x[i];
         r.y = (DIM >= 2) ? s.y[i] : 0.0;
@@ -827,12 +818,12 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
         // field tile (one memory round trip for all three)
         const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
         const int span = i1 - i0;
-        // the 2D2V mixed state (loaded with the nontemporal hint) is read in
-        // whole 128-byte lines per wave: chunks start at the line boundary at
-        // or below the bucket's first particle, index k at chunk position
-        // k + sh (the push uses the same positions, so the waves' tallies agree)
-        constexpr bool kAlign = MIX && DIM == 2 && VDIM == 2 && !EM;
-        const int sh = kAlign ? (i0 & 31) : 0;
+        // every wave reads whole 128-byte lines of the particle arrays: chunks
+        // start at the line boundary at or below the bucket's first particle
+        // (32 binary32 or 16 FP64 elements per line), index k at chunk
+        // position k + sh (the push uses the same positions, so the waves'
+        // tallies agree)
+        const int sh = i0 & (MIX ? 31 : 15);
         const int send = span > 0 ? span + sh : 0;
         int draw[2 * kSWaves];
 #pragma unroll
@@ -1167,10 +1158,9 @@ __global__ void __launch_bounds__(kSBlock) k_step_push(Geo g, Parts src, Parts d
         // trips overlap; the FP64 pipeline issues its first chunk below
         const int i0 = min(max(bstart[b], 0), g.np), i1 = min(max(bstart[b + 1], i0), g.np);
         const int span = i1 - i0;
-        // whole 128-byte lines per wave for the 2D2V mixed state, as in the
-        // tally pass (index k at chunk position k + sh)
-        constexpr bool kAlign = MIX && DIM == 2 && VDIM == 2 && !EM;
-        const int sh = kAlign ? (i0 & 31) : 0;
+        // whole 128-byte lines per wave, as in the tally pass (index k at
+        // chunk position k + sh)
+        const int sh = i0 & (MIX ? 31 : 15);
         const int send = span > 0 ? span + sh : 0;
         Raw<MIX> ra[U], rb[U];
         auto fetch = [&](Raw<MIX> *r, int base) {
