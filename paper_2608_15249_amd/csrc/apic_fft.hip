@@ -344,6 +344,4 @@ hipError_t launch_fused_field(const Geo &g, bool mixed_acc, void *acc, double sc
     return hipGetLastError();
 }
 
-int fused_fft_spec_blocks(const Geo &g) { return 8 * ((g.nx / 2 + 1 + 7) / 8); }
-
 }  // namespace apic
