@@ -213,3 +213,70 @@ def test_mixed_step_on_cell_tile_and_domain_edges(torch):
     key = O.bucket_key(ref["ix"], ref["iy"], 8, 8, nx)
     _, start = O.counting_sort(key, c.nbuckets)
     assert np.array_equal(d["bucket_start"].astype(np.int64), start)
+
+
+def test_more_buckets_than_the_one_launch_scan_covers(torch):
+    """256 x 256 cells in 4 x 2 tiles (8192 buckets, above the 4096 that the
+    one-launch scan of bucket totals serves): the separate scan and offsets
+    launches with the alternating totals buffers; one mixed step bit-exact
+    against the oracle's binary32 push and quantised deposit, then three
+    FP64 steps of the same plasma against the oracle."""
+    nx, ny, lx, ly, n, tile = 256, 256, 256.0, 256.0 * 0.75, 60011, (4, 2)
+    rng = np.random.default_rng(303)
+    x, y = rng.uniform(0, lx, n), rng.uniform(0, ly, n)
+    vx, vy = rng.normal(0, 1, n), rng.normal(0, 1, n)
+    s = O.Setup(2, 2, nx, lx, n, 0.1, ny=ny, Ly=ly)
+    # mixed: one step from the oracle's field of the quantised charge
+    c, p = _ctx(n, "mixed", nx=nx, ny=ny, lx=lx, ly=ly, tile=tile)
+    assert c.nbuckets == 8192
+    ix, ox = W.to_cell_offset(x, s.dx, nx)
+    iy, oy = W.to_cell_offset(y, s.dy, ny)
+    p.upload(cell=W.pack_cell(ix, iy), ox=ox, oy=oy, vx=vx.astype(np.float32), vy=vy.astype(np.float32))
+    S = c.frac_bits
+    E0 = O.solve_field(s, O.rho_from_quantised(s, O.deposit_quantised(s, ix, ox, S, iy, oy), S))
+    E32 = tuple(e.astype(np.float32) for e in E0)
+    perm = torch.zeros(n, dtype=torch.int32, device="cuda")
+    c.sort_by_cell(p, perm=perm)
+    ids = _compose(np.arange(n), perm)
+    Ed = torch.from_numpy(np.concatenate([e.ravel() for e in E0])).cuda()
+    E32d = torch.from_numpy(np.concatenate([e.ravel() for e in E32])).cuda()
+    Iout = torch.zeros(c.G, dtype=torch.int64, device="cuda")
+    c.step(p, Ed, E32d, 1, None, rho=Iout, perm=perm)
+    c.sync()
+    ids = _compose(ids, perm)
+    st = {"ix": ix, "iy": iy, "ox": ox, "oy": oy, "vx": vx.astype(np.float32), "vy": vy.astype(np.float32),
+          "vz": None}
+    ref = OM.push(st, E32, dim=2, vdim=2, nx=nx, ny=ny, dx=s.dx, dy=s.dy, qm=s.qm, dt=s.dt, bz=0.0)
+    d = p.download()
+    kx, ky = W.unpack_cell(d["cell"], 2)
+    for got, k in ((kx, "ix"), (ky, "iy"), (d["ox"], "ox"), (d["oy"], "oy"), (d["vx"], "vx"), (d["vy"], "vy")):
+        assert np.array_equal(got, ref[k][ids]), k
+    I1 = O.deposit_quantised(s, ref["ix"], ref["ox"], S, ref["iy"], ref["oy"])
+    assert np.array_equal(Iout.cpu().numpy().reshape(I1.shape), I1)
+    _, start = O.counting_sort(O.bucket_key(ref["ix"], ref["iy"], 4, 2, nx), c.nbuckets)
+    assert np.array_equal(d["bucket_start"].astype(np.int64), start)
+    # FP64: three steps in calls of two and one (both totals buffers are used)
+    c, p = _ctx(n, "fp64", nx=nx, ny=ny, lx=lx, ly=ly, tile=tile)
+    p.upload(x=x, y=y, vx=vx, vy=vy)
+    c.sort_by_cell(p)
+    rho = torch.zeros(c.G, dtype=torch.float64, device="cuda")
+    c.deposit(p, rho)
+    E = torch.zeros(2 * c.G, dtype=torch.float64, device="cuda")
+    c.field_solve(rho, E)
+    c.gather_push(p, E, dt_scale=-0.5, move=False)
+    c.step(p, E, None, 2)
+    c.step(p, E, None, 1)
+    c.sync()
+    sto = O.State.from_arrays(x, vx, y, vy)
+    Eo, _ = O.initialise(s, sto)
+    for _ in range(3):
+        Eo, _, _ = O.step(s, sto, Eo)
+    d = p.download()
+    # the permutation of a multi-step call is not recorded: match each GPU
+    # particle to the oracle's nearest in (x, y, vx, vy); the match must be
+    # one to one and close
+    from scipy.spatial import cKDTree
+    tree = cKDTree(np.stack([sto.x, sto.y, sto.vx, sto.vy], axis=1))
+    dist, idx = tree.query(np.stack([d["x"], d["y"], d["vx"], d["vy"]], axis=1))
+    assert len(np.unique(idx)) == n
+    assert np.max(dist) <= 1e-9
