@@ -465,3 +465,34 @@ def test_autotuned_tile_gives_the_same_plasma(torch):
                      sb["ox"].view(np.uint32), sb["cell"]))
     for f in ("cell", "ox", "oy", "vx", "vy"):
         assert np.array_equal(sa[f][ka], sb[f][kb]), f
+
+
+def test_profile_phases_modes(torch):
+    """Per-phase timing: with every phase profiled all four sums are positive;
+    with the push only, the other three read zero and the push is timed."""
+    dim, vdim, nx, ny, lx, ly, n, tile = CASES[1]
+    rng = np.random.default_rng(23)
+    x, y, vx, vy, vz = _random_state(rng, dim, vdim, lx, ly, n)
+    c, p = _ctx(torch, dim=dim, vdim=vdim, nx=nx, ny=ny, lx=lx, ly=ly, n=n, precision="mixed", tile=tile)
+    s = _setup(dim, vdim, nx, ny, lx, ly, n)
+    _upload_mixed(p, x, y, vx, vy, vz, s.dx, s.dy, nx, ny)
+    c.sort_by_cell(p)
+    I = torch.zeros(c.G, dtype=torch.int64, device="cuda")
+    c.deposit(p, I)
+    E = torch.zeros(2 * c.G, dtype=torch.float64, device="cuda")
+    E32 = torch.zeros(2 * c.G, dtype=torch.float32, device="cuda")
+    c.field_solve(I, E, E32)
+    for all_phases in (True, False):
+        c.profile_phases(all_phases)
+        c.profile_enable(4)
+        c.step(p, E, E32, 6)
+        c.sync()
+        ms, steps = c.profile_read()
+        c.profile_enable(0)
+        assert steps == 4
+        assert ms[2] > 0
+        if all_phases:
+            assert all(m > 0 for m in ms)
+        else:
+            assert ms[0] == 0 and ms[1] == 0 and ms[3] == 0
+    c.profile_phases(True)
