@@ -404,3 +404,37 @@ def test_mixed_gauss_law_is_kept_to_binary32_accuracy(torch):
     Fg = F.cpu().numpy().reshape(6, s.ny, s.nx)
     assert np.max(np.abs(M.divergence_e(s, Fg) - r)) <= 1e-4 * np.max(np.abs(r))
     assert np.max(np.abs(M.divergence_b(s, Fg))) <= 1e-11 * max(1.0, np.max(np.abs(Fg[3:])))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_empty_plasma_evolves_the_vacuum_field(torch, precision):
+    """No particles: an empty bucket table, zero current, and the field update
+    alone, against the oracle's steps of the same field with an empty state."""
+    from paper_2608_15249_amd.apic import Context, Particles
+    nx, ny, lx, ly, dt, bz = 16, 12, 16.0, 13.2, 0.1, 0.7
+    c = Context(dim=2, vdim=3, nx=nx, ny=ny, lx=lx, ly=ly, dt=dt, n=0, bz=bz, precision=precision, tile=(8, 4),
+                c_light=C_LIGHT, model="em")
+    p = Particles(c)
+    e = np.zeros(0)
+    if precision == "mixed":
+        f = e.astype(np.float32)
+        p.upload(cell=np.zeros(0, np.int32), ox=f, oy=f, vx=f, vy=f, vz=f)
+    else:
+        p.upload(x=e, y=e, vx=e, vy=e, vz=e)
+    c.sort_by_cell(p)
+    rng = np.random.default_rng(91)
+    Fo = rng.normal(size=(6, ny, nx))
+    F = _dev(torch, Fo)
+    J = torch.ones(3 * c.G, dtype=torch.float64, device="cuda")
+    c.em_step(p, F, 5, J=J)
+    c.sync()
+    # the oracle's setup takes one nominal particle for its macro-charge,
+    # which no particle carries
+    s = O.Setup(2, 3, nx, lx, 1, dt, ny=ny, Ly=ly, bz=bz, c=C_LIGHT)
+    st = O.State.from_arrays(e, e, e, e, e)
+    for _ in range(5):
+        M.step(s, st, Fo)
+    assert np.all(p.bucket_start.cpu().numpy() == 0)
+    assert np.all(J.cpu().numpy() == 0.0)
+    Fg = F.cpu().numpy().reshape(6, ny, nx)
+    assert np.max(np.abs(Fg - Fo)) <= 1e-12 * np.max(np.abs(Fo))
