@@ -431,3 +431,27 @@ def test_full_size_3d_sampled(torch):
     I = Iout.cpu().numpy()
     total = (int((I >> 32).sum()) << 32) + int((I & 0xFFFFFFFF).sum())
     assert total == n << (3 * S)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_empty_plasma(torch, precision):
+    """No particles in 3D: an empty bucket table, the ion background alone as
+    the charge (zero field), and steps whose diagnostics are all zero."""
+    c, p = _ctx(torch, (16, 8, 12, 16.0, 8.0, 12.0, 0, (8, 4, 4)), precision)
+    e = np.zeros(0)
+    if precision == "mixed":
+        f = e.astype(np.float32)
+        p.upload(cell=np.zeros(0, np.int32), ox=f, oy=f, oz=f, vx=f, vy=f, vz=f)
+    else:
+        p.upload(x=e, y=e, z=e, vx=e, vy=e, vz=e)
+    c.sort_by_cell(p)
+    E = torch.ones(3 * c.G, dtype=torch.float64, device="cuda")
+    E32 = torch.ones(3 * c.G, dtype=torch.float32, device="cuda")
+    diag = torch.ones(4 * 3, dtype=torch.float64, device="cuda")
+    c.step(p, E, E32, 3, diag)
+    c.sync()
+    assert np.all(p.bucket_start.cpu().numpy() == 0)
+    # a uniform charge has no field; the transform's rounding may leave
+    # residues of order 1e-16
+    assert np.max(np.abs(E.cpu().numpy())) <= 1e-12 and np.max(np.abs(E32.cpu().numpy())) <= 1e-12
+    assert np.max(np.abs(diag.cpu().numpy())) <= 1e-12
