@@ -148,7 +148,7 @@ def run_path(precision, w, state, steps, warmup, tile, torch, pusher="boris", c_
     # (diag charge = q_macro * live count after each step)
     pushes = n * steps
     if walls:
-        live = [int(round(v)) for v in d[:, 0] / sim.ctx.desc.q_macro]
+        live = [int(round(v)) for v in d[:, 0] / sim.ctx.q_macro]
         pushes = n_start + sum(live[:-1])
     out = {
         "value": pushes / elapsed,

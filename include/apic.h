@@ -90,7 +90,12 @@ typedef struct {
     double lx, ly;        /* box lengths (ly ignored when dim = 1)              */
     double dt;            /* time step                                          */
     double qm;            /* charge-to-mass ratio of the particles              */
-    double q_macro;       /* charge of one macro-particle                       */
+    double q_macro;       /* charge of one macro-particle; 0 selects the
+                             neutralising charge -rho_ion * V / n (V the box
+                             volume lx ly lz of the dimensions present, n the
+                             particle count), the ion background of the
+                             paper's two-stream example balanced by n equal
+                             electrons; apic_q_macro() reports the value used  */
     double rho_ion;       /* uniform immobile background charge density         */
     double bz;            /* uniform magnetic field along z (needs vdim >= 2)   */
     apic_precision prec;
@@ -164,6 +169,10 @@ int64_t apic_num_buckets(const apic_ctx *ctx);
 /* Fixed-point bits S the context uses (mixed path). */
 int apic_frac_bits(const apic_ctx *ctx);
 
+/* Charge of one macro-particle the context uses (the descriptor's q_macro, or
+ * its neutralising default); NaN for a NULL context. */
+double apic_q_macro(const apic_ctx *ctx);
+
 /* Side, in cells, of the context's sort-bucket tile along axis 0 (x), 1 (y)
  * or 2 (z): 1 along an axis the grid does not have, -1 for a NULL context or
  * another axis. */
@@ -217,7 +226,10 @@ apic_status apic_gather_push(apic_ctx *ctx, apic_particles *p, const void *E, do
  * E32  [dev]: optional float [dim*G] output (NULL = none): E^{n+nsteps} rounded
  *        to binary32.
  * diag [dev, double, nsteps*4] per step k (time level n+k -> n+k+1):
- *        [0] total deposited charge at n+k+1, sum_j (rho_j - rho_ion) dV
+ *        [0] total deposited charge at n+k+1: FP64 path sum_j (rho_j - rho_ion)
+ *            dV; mixed path q_macro times the exact integer total of the
+ *            fixed-point node sums (see apic_charge_exact), which is
+ *            q_macro * n bit for bit when every particle deposited its 2^(S*dim)
  *        [1] field energy W_E at n+k+1
  *        [2] kinetic energy at n+k: M/2 * sum_p (|v^{-}|^2 + |v^{+}|^2)/2
  *            with M = q_macro/qm
@@ -310,9 +322,19 @@ apic_status apic_adjoint_forward(apic_ctx *ctx, const apic_particles *p0, int ns
  * same nsteps and stride (ws contents between the two calls are not needed).
  * Writes seed * dW/d(state at t = 0) in the input order of p0, as FP64:
  * lam_x, lam_y [dev, n] (lam_y NULL in 1D) with respect to positions,
- * lam_vx, lam_vy, lam_vz [dev, n] (NULL beyond vdim) with respect to v^0. */
+ * lam_vx, lam_vy, lam_vz [dev, n] (NULL beyond vdim) with respect to v^0.
+ * grad_delta0 [dev, double, 1] (NULL = not computed): seed * dW/d delta0 for
+ * the mode seeding of the paper's two-stream example ("Example setup and
+ * implementation": every particle displaced by delta0 k/|k|^2 sin(k.x_u)),
+ * i.e. sum_p lam_x[p] dx_ddelta0[p] + lam_y[p] dy_ddelta0[p], with
+ * dx_ddelta0, dy_ddelta0 [dev, double, n] the derivative of each initial
+ * position with respect to delta0 in the same order (dy NULL in 1D; the
+ * caller knows its unperturbed positions x_u, the library does not); summed
+ * in a fixed order on the device. */
 apic_status apic_step_adjoint(apic_ctx *ctx, const void *ckpt, int nsteps, int stride, double seed, double *lam_x,
-                              double *lam_y, double *lam_vx, double *lam_vy, double *lam_vz, void *ws, void *stream);
+                              double *lam_y, double *lam_vx, double *lam_vy, double *lam_vz,
+                              const double *dx_ddelta0, const double *dy_ddelta0, double *grad_delta0, void *ws,
+                              void *stream);
 
 /* ---- walls: non-periodic Poisson with absorbing walls -----------------------
  * The paper's D_Poisson solves Poisson under general boundary conditions
@@ -478,6 +500,19 @@ apic_status apic_autotune_tiles(const apic_grid_desc *desc, const apic_particles
 apic_status apic_batch_autotune_chunk(const apic_replica *reps, int nrep, double dt, double qm, double rho_ion,
                                       const apic_batch_state *st, int nsteps, int *chunk, double *ms_per_step,
                                       void *stream);
+
+/* Exact charge of the last field solve of a mixed-path context (apic_step,
+ * apic_field_solve): the integer total of its int64
+ * fixed-point node sums, computed on the device without rounding (each sum
+ * split into whole particles and a remainder, both summed in 64-bit
+ * integers), returned as *whole particles plus *frac units of 2^-(S*dim)
+ * particle, 0 <= *frac < 2^(S*dim). A deposit of n particles gives
+ * *whole = n and *frac = 0 (between walls: the particles still inside, as
+ * the node sums of the physical nodes, walls included). The paper's
+ * "Results and validation" judges its run by conserved totals; this is the
+ * charge total of the fixed-point form. Waits for the stream. [host]
+ * outputs. APIC_EUNSUPPORTED on an FP64 context. */
+apic_status apic_charge_exact(apic_ctx *ctx, int64_t *whole, int64_t *frac, void *stream);
 
 /* Waits for the stream, then returns and clears the device error flags
  * (APIC_OK, APIC_EDOMAIN or APIC_EOVERFLOW). */

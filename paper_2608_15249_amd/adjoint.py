@@ -32,6 +32,8 @@ class FieldEnergyRun:
         self.ws = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
         self.W = torch.zeros(1, dtype=torch.float64, device=dev)
         self.dim, self.vdim, self.n = dim, vdim, int(n)
+        # forward() runs so far: the checkpoints belong to the latest one only
+        self.generation = 0
 
     @classmethod
     def for_workload(cls, w, stride=20, precision="mixed", nsteps: Optional[int] = None, **kw):
@@ -42,16 +44,21 @@ class FieldEnergyRun:
         """W_E(T) (a 1-element FP64 device tensor) from the FP64 initial state."""
         self.ctx.import_state(self.parts, x, y, vx, vy, vz)
         self.ctx.adjoint_forward(self.parts, self.nsteps, self.stride, self.ckpt, self.ws, W=self.W, E_out=E_out)
+        self.generation += 1
         return self.W.clone()
 
-    def backward(self, seed: float = 1.0):
-        """seed * dW/d(x, y, vx, vy, vz) after forward(); None for absent components."""
+    def backward(self, seed: float = 1.0, dx_ddelta0=None, dy_ddelta0=None):
+        """seed * dW/d(x, y, vx, vy, vz) after forward(); None for absent
+        components. With dx_ddelta0 (and dy_ddelta0 in 2D), the derivative of
+        each initial position with respect to the mode amplitude delta0, a
+        sixth entry holds seed * dW/d delta0 (a 1-element device tensor)."""
         t = self.torch
         mk = lambda on: t.empty(self.n, dtype=t.float64, device=self.ctx.device) if on else None
         out = [mk(True), mk(self.dim == 2), mk(True), mk(self.vdim >= 2), mk(self.vdim >= 3)]
+        gd = t.zeros(1, dtype=t.float64, device=self.ctx.device) if dx_ddelta0 is not None else None
         self.ctx.step_adjoint(self.ckpt, self.nsteps, self.stride, self.ws, out[0], out[1], out[2], out[3], out[4],
-                              seed=seed)
-        return out
+                              seed=seed, dx_ddelta0=dx_ddelta0, dy_ddelta0=dy_ddelta0, grad_delta0=gd)
+        return out + [gd] if gd is not None else out
 
     def sync(self):
         self.ctx.sync()
@@ -64,11 +71,20 @@ def _function():
         @staticmethod
         def forward(ctx, run: FieldEnergyRun, x, y, vx, vy, vz):
             ctx.run = run
-            return run.forward(x, y, vx, vy, vz)
+            ctx.inputs = (x, y, vx, vy, vz)
+            W = run.forward(x, y, vx, vy, vz)
+            ctx.generation = run.generation
+            return W
 
         @staticmethod
         def backward(ctx, gW):
-            grads = ctx.run.backward(1.0)
+            run = ctx.run
+            if run.generation != ctx.generation:
+                # a later forward of the same run overwrote the checkpoints:
+                # recompute them from this graph's own inputs
+                with torch.no_grad():
+                    run.forward(*[None if a is None else a.detach() for a in ctx.inputs])
+            grads = run.backward(1.0)
             return (None,) + tuple(None if g is None else g * gW for g in grads)
 
     return FieldEnergy

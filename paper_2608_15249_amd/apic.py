@@ -66,7 +66,7 @@ EXPORTS = ["apic_create", "apic_destroy", "apic_workspace_size", "apic_num_bucke
            "apic_batch_work_items", "apic_batch_init", "apic_batch_step", "apic_batch_sync_status",
            "apic_batch_last_error", "apic_autotune_tiles", "apic_batch_autotune_chunk",
            "apic_import_state", "apic_adjoint_sizes", "apic_adjoint_forward", "apic_step_adjoint",
-           "apic_em_init_fields", "apic_em_gather_push", "apic_em_step"]
+           "apic_em_init_fields", "apic_em_gather_push", "apic_em_step", "apic_charge_exact", "apic_q_macro"]
 
 _lib = None
 
@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH):
         "apic_workspace_size": ([vp, P(ctypes.c_size_t)], cint),
         "apic_num_buckets": ([vp], i64),
         "apic_frac_bits": ([vp], cint),
+        "apic_q_macro": ([vp], dbl),
         "apic_tile_size": ([vp, cint], cint),
         "apic_sort_by_cell": ([vp, P(ParticlesC), vp, vp], cint),
         "apic_deposit": ([vp, P(ParticlesC), vp, vp], cint),
@@ -110,11 +111,12 @@ def load_library(path: str = LIB_PATH):
         "apic_import_state": ([vp, vp, vp, vp, vp, vp, P(ParticlesC), vp], cint),
         "apic_adjoint_sizes": ([vp, cint, cint, P(ctypes.c_size_t), P(ctypes.c_size_t)], cint),
         "apic_adjoint_forward": ([vp, P(ParticlesC), cint, cint, vp, vp, vp, vp, vp], cint),
-        "apic_step_adjoint": ([vp, vp, cint, cint, dbl, vp, vp, vp, vp, vp, vp, vp], cint),
+        "apic_step_adjoint": ([vp, vp, cint, cint, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp], cint),
         "apic_autotune_tiles": ([P(GridDesc), P(ParticlesC), cint, P(cint), P(cint), P(dbl), vp], cint),
         "apic_em_init_fields": ([vp, P(ParticlesC), vp, vp, vp], cint),
         "apic_em_gather_push": ([vp, P(ParticlesC), vp, dbl, cint, vp], cint),
         "apic_em_step": ([vp, P(ParticlesC), vp, vp, cint, vp, vp, vp], cint),
+        "apic_charge_exact": ([vp, P(i64), P(i64), vp], cint),
         "apic_batch_autotune_chunk": ([P(ReplicaC), cint, dbl, dbl, dbl, P(BatchStateC), cint, P(cint), P(dbl), vp],
                                       cint),
     }
@@ -129,6 +131,25 @@ def load_library(path: str = LIB_PATH):
 
 def _ptr(t) -> Optional[int]:
     return None if t is None else t.data_ptr()
+
+
+def _need(t, dtype, numel, name, optional=False):
+    """Raise ApicError unless t is a contiguous device tensor of dtype with at
+    least numel elements (None passes when optional): the kernels read and
+    write exactly that many elements through its pointer."""
+    if t is None:
+        if optional:
+            return
+        raise ApicError(-1, "%s is required" % name)
+    import torch
+    if t.device.type != "cuda":
+        raise ApicError(-1, "%s must be a device tensor (got %s)" % (name, t.device))
+    if t.dtype != dtype:
+        raise ApicError(-1, "%s must be %s (got %s)" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ApicError(-1, "%s must be contiguous" % name)
+    if t.numel() < numel:
+        raise ApicError(-1, "%s holds %d elements, %d needed" % (name, t.numel(), numel))
 
 
 def _stream():
@@ -150,8 +171,7 @@ class Context:
         self.device = torch.device(device)
         self.mixed = precision == "mixed"
         if q_macro is None:
-            vol = lx * (ly if dim >= 2 else 1.0) * (lz if dim == 3 else 1.0)
-            q_macro = -rho_ion * vol / n if n > 0 else 0.0
+            q_macro = 0.0       # the library's neutralising default
         tz = tile[2] if len(tile) > 2 else 0
         self.desc = GridDesc(dim, vdim, nx, ny if dim >= 2 else 1, lx, ly if dim >= 2 else 1.0, dt, qm, q_macro,
                              rho_ion, bz, APIC_MIXED if self.mixed else APIC_FP64, frac_bits, tile[0], tile[1],
@@ -172,6 +192,7 @@ class Context:
         self.ws = torch.empty(max(int(sz.value), 256), dtype=torch.uint8, device=self.device)
         self.nbuckets = int(self.L.apic_num_buckets(self.h))
         self.frac_bits = int(self.L.apic_frac_bits(self.h))
+        self.q_macro = float(self.L.apic_q_macro(self.h))
         self.tile = tuple(int(self.L.apic_tile_size(self.h, a)) for a in range(dim))
         self.dim, self.vdim, self.nx = dim, vdim, nx
         self.ny = ny if dim >= 2 else 1
@@ -196,6 +217,13 @@ class Context:
     def sync(self):
         self._check(self.L.apic_sync_status(self.h, _stream()))
 
+    def charge_exact(self):
+        """Exact charge of the last mixed-path field solve: (whole particles,
+        remainder in units of 2^-(S dim) particle), from apic_charge_exact."""
+        w, f = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.L.apic_charge_exact(self.h, ctypes.byref(w), ctypes.byref(f), _stream()))
+        return int(w.value), int(f.value)
+
     def profile_enable(self, max_steps: int):
         self._check(self.L.apic_profile_enable(self.h, int(max_steps)))
 
@@ -213,19 +241,29 @@ class Context:
 
     # -- entry points -------------------------------------------------------
     def sort_by_cell(self, parts: "Particles", perm=None):
+        _need(perm, self.torch.int32, self.n, "perm", optional=True)
         s = parts.struct(perm=perm)
         self._check(self.L.apic_sort_by_cell(self.h, ctypes.byref(s), ctypes.c_void_p(self.ws.data_ptr()), _stream()))
 
     def deposit(self, parts: "Particles", rho, tiled=True):
+        t = self.torch
+        _need(rho, t.int64 if self.mixed else t.float64, self.G, "rho")
         s = parts.struct(tiled=tiled)
         self._check(self.L.apic_deposit(self.h, ctypes.byref(s), ctypes.c_void_p(rho.data_ptr()), _stream()))
 
     def field_solve(self, rho, E, E32=None, we=None):
+        t = self.torch
+        _need(rho, t.int64 if self.mixed else t.float64, self.G, "rho")
+        _need(E, t.float64, self.dim * self.G, "E")
+        _need(E32, t.float32, self.dim * self.G, "E32", optional=True)
+        _need(we, t.float64, 1, "we", optional=True)
         self._check(self.L.apic_field_solve(self.h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(E.data_ptr()),
                                             ctypes.c_void_p(_ptr(E32)), ctypes.c_void_p(_ptr(we)),
                                             ctypes.c_void_p(self.ws.data_ptr()), _stream()))
 
     def gather_push(self, parts: "Particles", E, dt_scale=1.0, move=True, tiled=True):
+        t = self.torch
+        _need(E, t.float32 if self.mixed else t.float64, self.dim * self.G, "E")
         s = parts.struct(tiled=tiled)
         self._check(self.L.apic_gather_push(self.h, ctypes.byref(s), ctypes.c_void_p(E.data_ptr()),
                                             float(dt_scale), 1 if move else 0, _stream()))
@@ -244,6 +282,10 @@ class Context:
 
     def import_state(self, parts: "Particles", x, y, vx, vy=None, vz=None):
         """Physical FP64 device state -> this context's representation (apic_import_state)."""
+        t = self.torch
+        for a, name, on in ((x, "x", True), (y, "y", self.dim >= 2), (vx, "vx", True), (vy, "vy", self.vdim >= 2),
+                            (vz, "vz", self.vdim >= 3)):
+            _need(a, t.float64, self.n, name, optional=not on)
         s = parts.struct()
         self._check(self.L.apic_import_state(self.h, ctypes.c_void_p(_ptr(x)), ctypes.c_void_p(_ptr(y)),
                                              ctypes.c_void_p(_ptr(vx)), ctypes.c_void_p(_ptr(vy)),
@@ -255,40 +297,75 @@ class Context:
         return int(ck.value), int(ws.value)
 
     def adjoint_forward(self, parts: "Particles", nsteps, stride, ckpt, ws, W=None, E_out=None):
+        t = self.torch
+        ck, wb = self.adjoint_sizes(nsteps, stride)
+        _need(ckpt, t.uint8, ck, "ckpt")
+        _need(ws, t.uint8, wb, "ws")
+        _need(W, t.float64, 1, "W", optional=True)
+        _need(E_out, t.float64, self.dim * self.G, "E_out", optional=True)
         s = parts.struct()
         self._check(self.L.apic_adjoint_forward(self.h, ctypes.byref(s), int(nsteps), int(stride),
                                                 ctypes.c_void_p(ckpt.data_ptr()), ctypes.c_void_p(_ptr(W)),
                                                 ctypes.c_void_p(_ptr(E_out)), ctypes.c_void_p(ws.data_ptr()),
                                                 _stream()))
 
-    def step_adjoint(self, ckpt, nsteps, stride, ws, lam_x, lam_y, lam_vx, lam_vy=None, lam_vz=None, seed=1.0):
+    def step_adjoint(self, ckpt, nsteps, stride, ws, lam_x, lam_y, lam_vx, lam_vy=None, lam_vz=None, seed=1.0,
+                     dx_ddelta0=None, dy_ddelta0=None, grad_delta0=None):
+        t = self.torch
+        ck, wb = self.adjoint_sizes(nsteps, stride)
+        _need(ckpt, t.uint8, ck, "ckpt")
+        _need(ws, t.uint8, wb, "ws")
+        for a, name, on in ((lam_x, "lam_x", True), (lam_y, "lam_y", self.dim == 2), (lam_vx, "lam_vx", True),
+                            (lam_vy, "lam_vy", self.vdim >= 2), (lam_vz, "lam_vz", self.vdim >= 3),
+                            (dx_ddelta0, "dx_ddelta0", grad_delta0 is not None),
+                            (dy_ddelta0, "dy_ddelta0", grad_delta0 is not None and self.dim == 2)):
+            _need(a, t.float64, self.n, name, optional=not on)
+        _need(grad_delta0, t.float64, 1, "grad_delta0", optional=True)
         self._check(self.L.apic_step_adjoint(self.h, ctypes.c_void_p(ckpt.data_ptr()), int(nsteps), int(stride),
                                              float(seed), ctypes.c_void_p(_ptr(lam_x)), ctypes.c_void_p(_ptr(lam_y)),
                                              ctypes.c_void_p(_ptr(lam_vx)), ctypes.c_void_p(_ptr(lam_vy)),
-                                             ctypes.c_void_p(_ptr(lam_vz)), ctypes.c_void_p(ws.data_ptr()),
-                                             _stream()))
+                                             ctypes.c_void_p(_ptr(lam_vz)), ctypes.c_void_p(_ptr(dx_ddelta0)),
+                                             ctypes.c_void_p(_ptr(dy_ddelta0)), ctypes.c_void_p(_ptr(grad_delta0)),
+                                             ctypes.c_void_p(ws.data_ptr()), _stream()))
 
     def em_init_fields(self, parts: "Particles", F):
+        _need(F, self.torch.float64, 6 * self.G, "F")
         s = parts.struct(tiled=False)
         self._check(self.L.apic_em_init_fields(self.h, ctypes.byref(s), ctypes.c_void_p(F.data_ptr()),
                                                ctypes.c_void_p(self.ws.data_ptr()), _stream()))
 
     def em_gather_push(self, parts: "Particles", F, dt_scale=1.0, move=True):
+        _need(F, self.torch.float64, 6 * self.G, "F")
         s = parts.struct(tiled=False)
         self._check(self.L.apic_em_gather_push(self.h, ctypes.byref(s), ctypes.c_void_p(F.data_ptr()),
                                                float(dt_scale), 1 if move else 0, _stream()))
 
     def em_step(self, parts: "Particles", F, nsteps, diag=None, J=None, perm=None):
+        t = self.torch
+        _need(F, t.float64, 6 * self.G, "F")
+        _need(J, t.float64, 3 * self.G, "J", optional=True)
+        _need(diag, t.float64, 4 * max(int(nsteps), 0), "diag", optional=True)
+        _need(perm, t.int32, self.n, "perm", optional=True)
         s = parts.struct(perm=perm)
         self._check(self.L.apic_em_step(self.h, ctypes.byref(s), ctypes.c_void_p(F.data_ptr()),
                                         ctypes.c_void_p(_ptr(J)), int(nsteps), ctypes.c_void_p(_ptr(diag)),
                                         ctypes.c_void_p(self.ws.data_ptr()), _stream()))
 
+    def _check_step(self, E, E32, nsteps, diag, rho, perm):
+        t = self.torch
+        _need(E, t.float64, self.dim * self.G, "E")
+        _need(E32, t.float32, self.dim * self.G, "E32", optional=True)
+        _need(diag, t.float64, 4 * max(int(nsteps), 0), "diag", optional=True)
+        _need(rho, t.int64 if self.mixed else t.float64, self.G, "rho", optional=True)
+        _need(perm, t.int32, self.n, "perm", optional=True)
+
     def step(self, parts: "Particles", E, E32, nsteps, diag=None, rho=None, perm=None):
+        self._check_step(E, E32, nsteps, diag, rho, perm)
         s = parts.struct(perm=perm)
         self._check(self.L.apic_step(self.h, ctypes.byref(s), ctypes.c_void_p(_ptr(rho)), ctypes.c_void_p(E.data_ptr()),
                                      ctypes.c_void_p(_ptr(E32)), int(nsteps), ctypes.c_void_p(_ptr(diag)),
                                      ctypes.c_void_p(self.ws.data_ptr()), _stream()))
+
 
 
 class Batch:

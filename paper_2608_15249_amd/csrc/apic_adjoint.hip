@@ -535,6 +535,21 @@ __global__ void __launch_bounds__(kBlock) k_adj_field1d(int nx, const double *lE
     for (int i = threadIdx.x; i < nx; i += blockDim.x) lrho[i] = -lrho[i];
 }
 
+// dW/d delta0 = sum_p (lam_x[p] dx[p] + lam_y[p] dy[p]): the chain rule through
+// the seeded displacement x_p^0 = x_p,u + delta0 d_p; one workgroup, fixed order
+// (ly, dy NULL in 1D)
+__global__ void __launch_bounds__(1024) k_adj_delta0(int64_t n, const double *lx, const double *dx, const double *ly,
+                                                    const double *dy, double *out) {
+    __shared__ double sRed[16];
+    double p = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        p += lx[i] * dx[i];
+        if (ly) p += ly[i] * dy[i];
+    }
+    p = block_sum(p, sRed);
+    if (threadIdx.x == 0) *out = p;
+}
+
 // W = 1/2 dV sum_i E_i^2 in a fixed order (one workgroup)
 __global__ void __launch_bounds__(1024) k_adj_energy(int64_t m, const double *E, double dV, double *W) {
     __shared__ double sRed[16];
@@ -1050,7 +1065,8 @@ apic_status apic_adjoint_forward(apic_ctx *c, const apic_particles *p0, int nste
 }
 
 apic_status apic_step_adjoint(apic_ctx *c, const void *ckpt, int nsteps, int stride, double seed, double *lam_x,
-                              double *lam_y, double *lam_vx, double *lam_vy, double *lam_vz, void *ws, void *stream) {
+                              double *lam_y, double *lam_vx, double *lam_vy, double *lam_vz, const double *dx_ddelta0,
+                              const double *dy_ddelta0, double *grad_delta0, void *ws, void *stream) {
     if (!c) return APIC_EINVAL;
     apic_status st = check_adj_args(c, nsteps, stride);
     if (st != APIC_OK) return st;
@@ -1058,12 +1074,20 @@ apic_status apic_step_adjoint(apic_ctx *c, const void *ckpt, int nsteps, int str
     if (!lam_x || (c->d.dim == 2 && !lam_y) || !lam_vx || (c->d.vdim >= 2 && !lam_vy) || (c->d.vdim >= 3 && !lam_vz))
         return fail(c, APIC_EINVAL, "a gradient output array is NULL");
     if (!std::isfinite(seed)) return fail(c, APIC_EINVAL, "seed is not finite");
+    if (grad_delta0 && (!dx_ddelta0 || (c->d.dim == 2 && !dy_ddelta0)))
+        return fail(c, APIC_EINVAL, "grad_delta0 needs the displacement direction of every particle (dx, dy in 2D)");
     hipStream_t s = (hipStream_t)stream;
     if (c->mixed)
-        return step_adjoint_impl<float>(c, (char *)const_cast<void *>(ckpt), nsteps, stride, seed, lam_x, lam_y,
-                                        lam_vx, lam_vy, lam_vz, (char *)ws, s);
-    return step_adjoint_impl<double>(c, (char *)const_cast<void *>(ckpt), nsteps, stride, seed, lam_x, lam_y, lam_vx,
-                                     lam_vy, lam_vz, (char *)ws, s);
+        st = step_adjoint_impl<float>(c, (char *)const_cast<void *>(ckpt), nsteps, stride, seed, lam_x, lam_y, lam_vx,
+                                      lam_vy, lam_vz, (char *)ws, s);
+    else
+        st = step_adjoint_impl<double>(c, (char *)const_cast<void *>(ckpt), nsteps, stride, seed, lam_x, lam_y,
+                                       lam_vx, lam_vy, lam_vz, (char *)ws, s);
+    if (st != APIC_OK || !grad_delta0) return st;
+    hipLaunchKernelGGL(apic::k_adj_delta0, dim3(1), dim3(1024), 0, s, c->n, lam_x, dx_ddelta0,
+                       c->d.dim == 2 ? lam_y : nullptr, c->d.dim == 2 ? dy_ddelta0 : nullptr, grad_delta0);
+    HIPCHK(c, hipGetLastError());
+    return APIC_OK;
 }
 
 }  // extern "C"

@@ -16,6 +16,7 @@
 using namespace apic;
 using namespace apic_host;
 
+
 namespace apic_host {
 
 apic_status fail(apic_ctx *c, apic_status st, const char *msg) {
@@ -233,7 +234,7 @@ apic_status field_from_acc(apic_ctx *c, void *acc, bool acc_is_rho, double *E, f
     if (c->d.dim == 1) {
         const int step_mode = diag ? 1 : 0;
         HIPCHK(c, launch_field1d(c->g, mixed_acc, acc, scale, add, c->d.rho_ion, c->d.lx / c->d.nx, clear, E, E32,
-                                 diag ? diag + 1 : we, diag ? diag + 0 : charge, step_mode, c->dev, s));
+                                 diag ? diag + 1 : we, diag ? diag + 0 : charge, step_mode, c->d.q_macro, c->dev, s));
         if (diag && npush)
             HIPCHK(c, launch_finalize(npush, 0, c->mass, c->dV, G, c->d.rho_ion, diag, nullptr, nullptr, c->dev, s));
         return APIC_OK;
@@ -244,20 +245,20 @@ apic_status field_from_acc(apic_ctx *c, void *acc, bool acc_is_rho, double *E, f
     if (c->fused_fft) {
         // half spectra in rhat, the x-spectrum of Ex + i Ey ([ny][nx] complex) in ehat
         const FinArgs fin{diag ? npush : 0, 0, c->mass, c->dV, G, c->d.rho_ion, diag, we, charge, c->g.walls,
-                          c->d.q_macro, nlive};
+                          c->d.q_macro, nlive, mixed_acc ? c->g.S * c->d.dim : 0};
         HIPCHK(c, launch_fused_field(c->g, mixed_acc, acc, scale, add, clear, rhat, ehat, E, E32, c->dev.tw, fin,
                                      c->dev, s));
         return APIC_OK;
     }
     if (c->g.walls)
-        HIPCHK(c, launch_rho_odd(c->g, mixed_acc, acc, rho, scale, add, clear, s));
+        HIPCHK(c, launch_rho_odd(c->g, mixed_acc, acc, rho, scale, add, clear, c->dev.qacc, s));
     else
-        HIPCHK(c, launch_rho(c->g, mixed_acc, acc, rho, scale, add, clear, s));
+        HIPCHK(c, launch_rho(c->g, mixed_acc, acc, rho, scale, add, clear, c->dev.qacc, s));
     FFTCHK(c, hipfftSetStream(c->fwd, s));
     FFTCHK(c, hipfftExecD2Z(c->fwd, (hipfftDoubleReal *)rho, (hipfftDoubleComplex *)rhat));
     HIPCHK(c, launch_spectral(c->g, rhat, ehat, c->dev, s));
     const FinArgs fin{diag ? npush : 0, spectral_blocks(c->g), c->mass, c->dV, G, c->d.rho_ion, diag, we, charge,
-                      c->g.walls, c->d.q_macro, nlive};
+                      c->g.walls, c->d.q_macro, nlive, mixed_acc ? c->g.S * c->d.dim : 0};
     // phi into the rho buffer (rho is no longer needed), then E from phi
     FFTCHK(c, hipfftSetStream(c->inv, s));
     FFTCHK(c, hipfftExecZ2D(c->inv, (hipfftDoubleComplex *)ehat, (hipfftDoubleReal *)rho));
@@ -410,7 +411,15 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     g.inv_dy = 1.0 / dy;
     g.inv_dz = 1.0 / dz;
     c->dV = dx * dy * dz;
-    c->mass = d.q_macro / d.qm;
+    // the neutralising macro-charge by default: n electrons carry the
+    // opposite of the ion charge rho_ion V of the box (V of the physical box,
+    // before the odd extension of walls)
+    if (c->d.q_macro == 0.0 && n_particles > 0) {
+        const double vol = d.lx * (d.dim >= 2 ? d.ly : 1.0) * (d.dim == 3 ? d.lz : 1.0);
+        c->d.q_macro = -d.rho_ion * vol / (double)n_particles;
+    }
+    if (!std::isfinite(c->d.q_macro)) { delete c; return APIC_EINVAL; }
+    c->mass = c->d.q_macro / d.qm;
     layout(c);
 
     // context device words + wavenumber tables
@@ -424,7 +433,7 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     size_t bytes = align256(sizeof(int)) * 2 + align256(sizeof(double) * 2 * g.nbuckets) +
                    align256(sizeof(double) * kMaxSpecBlocks) + align256(sizeof(double)) +
                    align256(sizeof(double) * hx) * 2 + align256(sizeof(double) * g.ny) * 2 +
-                   align256(sizeof(double) * g.nz) * 2 + align256(tw_bytes);
+                   align256(sizeof(double) * g.nz) * 2 + align256(tw_bytes) + align256(4 * sizeof(int64_t));
     if (hipMalloc(&c->dev_block, bytes) != hipSuccess) { delete c; return APIC_ENOMEM; }
     if (hipMemset(c->dev_block, 0, bytes) != hipSuccess) { (void)hipFree(c->dev_block); delete c; return APIC_EHIP; }
     char *b = (char *)c->dev_block;
@@ -442,6 +451,11 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     c->dev.kz2 = (double *)take(sizeof(double) * g.nz);
     c->dev.kapz = (double *)take(sizeof(double) * g.nz);
     c->dev.tw = c->fused_fft ? (double *)take(tw_bytes) : nullptr;
+    {
+        int64_t *q = (int64_t *)take(4 * sizeof(int64_t));
+        c->dev.qacc = (unsigned long long *)q;
+        c->dev.qexact = q + 2;
+    }
     // modified wavenumbers of the periodic FD operators:
     //   K^2_d = (2/d sin(k d / 2))^2 (3-point second difference),
     //   kappa_d = sin(k d)/d (centred first difference), k = 2 pi m / L.
@@ -528,6 +542,8 @@ int64_t apic_num_buckets(const apic_ctx *c) { return c ? c->g.nbuckets : -1; }
 
 int apic_frac_bits(const apic_ctx *c) { return c ? c->g.S : -1; }
 
+double apic_q_macro(const apic_ctx *c) { return c ? c->d.q_macro : NAN; }
+
 int apic_tile_size(const apic_ctx *c, int axis) {
     if (!c || axis < 0 || axis > 2) return -1;
     if (axis >= c->d.dim) return 1;
@@ -571,7 +587,7 @@ apic_status apic_deposit(apic_ctx *c, const apic_particles *p, void *rho, void *
     const int64_t G = (int64_t)c->d.nx * c->d.ny * c->d.nz;
     HIPCHK(c, launch_fill_u64((uint64_t *)rho, G, 0, s));
     HIPCHK(c, launch_deposit(c->g, c->mixed, parts_of(p), c->n, p->bucket_start, rho, c->dev, s));
-    if (!c->mixed) HIPCHK(c, launch_rho(c->g, false, rho, (double *)rho, acc_scale(c), c->d.rho_ion, 0, s));
+    if (!c->mixed) HIPCHK(c, launch_rho(c->g, false, rho, (double *)rho, acc_scale(c), c->d.rho_ion, 0, nullptr, s));
     return APIC_OK;
 }
 
@@ -654,7 +670,7 @@ apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, floa
             if (c->mixed)
                 HIPCHK(c, launch_copy_bytes(rho, acc, 8 * G, s));
             else
-                HIPCHK(c, launch_rho(c->g, false, acc, (double *)rho, acc_scale(c), c->d.rho_ion, 0, s));
+                HIPCHK(c, launch_rho(c->g, false, acc, (double *)rho, acc_scale(c), c->d.rho_ion, 0, nullptr, s));
         }
         st = field_from_acc(c, acc, false, E, last ? E32 : nullptr, diag, nullptr, nullptr, diag ? nb : 0, 1, ws, s,
                             bs_dst + nb);
@@ -702,6 +718,17 @@ apic_status apic_profile_read(apic_ctx *c, double ms[4], int *steps) {
         }
     }
     c->prof_used = 0;
+    return APIC_OK;
+}
+
+apic_status apic_charge_exact(apic_ctx *c, int64_t *whole, int64_t *frac, void *stream) {
+    if (!c || !whole || !frac) return APIC_EINVAL;
+    if (!c->mixed) return fail(c, APIC_EUNSUPPORTED, "the exact charge is a mixed-path (fixed-point) figure");
+    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    int64_t q[2];
+    HIPCHK(c, hipMemcpy(q, c->dev.qexact, sizeof(q), hipMemcpyDeviceToHost));
+    *whole = q[0];
+    *frac = q[1];
     return APIC_OK;
 }
 

@@ -46,6 +46,7 @@ struct RepP {
     int n;                       // particles
     float dtdx;                  // dt / dx in binary32
     double dx, acc_scale, mass;  // acc_scale = q_macro 2^-S / dx
+    double q_macro;              // charge of one particle
 };
 
 struct Item {
@@ -233,7 +234,9 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchP bp, int32_t *cell, floa
         if (threadIdx.x == 0) sLast = (atomicAdd(&bp.rep_done[it.r], 1) == rp.nitems - 1);
         __syncthreads();
         if (!sLast) continue;
-        double qpart = 0.0;
+        // the replica's charge: the exact integer total of its node sums
+        // (whole particles + remainder in units of 2^-S particle)
+        QSum qs{0, 0};
         for (int i = threadIdx.x; i < rp.nx; i += blockDim.x) {
             // read-and-clear at the device coherence point (sA is free again:
             // this block's own flush above has completed)
@@ -241,9 +244,10 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchP bp, int32_t *cell, floa
             if (rho_out) rho_out[rp.g0 + i] = (int64_t)v;
             const double rr = bp.rho_ion + rp.acc_scale * (double)(int64_t)v;
             sR[i] = rr;
-            qpart += rr - bp.rho_ion;
+            qsum_add(qs, (int64_t)v, bp.S);
         }
-        const double qsum = block_sum(qpart, sRed);
+        // (block-local: this block alone reduces the replica's grid)
+        const QSum qt = qsum_block(qs, bp.S);
         const double wsum = field1d_block(sR, rp.nx, rp.dx, E + rp.g0, nullptr, sRed, sScan);
         double kt = 0.0, pt = 0.0;
         if constexpr (MODE == MODE_STEP) {
@@ -259,7 +263,7 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchP bp, int32_t *cell, floa
         if (threadIdx.x == 0) {
             if (diag) {
                 double *d = diag + ((size_t)(*bp.step) * bp.nrep + it.r) * 4;
-                d[0] = qsum * rp.dx;
+                d[0] = qsum_charge(qt, bp.S, uniform_d(rp.q_macro));
                 d[1] = 0.5 * wsum * rp.dx;
                 d[2] = 0.5 * rp.mass * kt;
                 d[3] = rp.mass * pt;
@@ -417,6 +421,7 @@ apic_status apic_batch_create(const apic_replica *reps, int nrep, double dt, dou
         q.dtdx = (float)(dt / q.dx);
         const double q_macro = R.n > 0 ? -rho_ion * R.lx / (double)R.n : 0.0;
         q.acc_scale = std::ldexp(q_macro / q.dx, -32);
+        q.q_macro = q_macro;
         q.mass = q_macro / qm;
         q.item0 = (int)items.size();
         int64_t left = R.n, at = 0;

@@ -68,6 +68,82 @@ __device__ double block_sum(double v, double *sh /* [waves] */) {
     return t;
 }
 
+// ---- exact charge of fixed-point node sums ------------------------------------
+// A node sum I of the mixed deposit counts weight units of 2^-sd particle
+// (sd = S * dim). It splits exactly into whole particles, I >> sd, and a
+// remainder, I & (2^sd - 1). Both parts are summed in 64-bit integers, each
+// remainder carried into the whole part once it reaches 2^sd, so no sum can
+// overflow (the total of a grid, N 2^sd units, would overflow int64 for
+// N 2^sd >= 2^63) and the result is exact and independent of the order of
+// the additions. A correct deposit of N particles sums to N whole particles
+// and a zero remainder.
+struct QSum {
+    int64_t whole;
+    uint64_t rem;
+};
+
+__device__ __forceinline__ void qsum_add(QSum &q, int64_t I, int sd) {
+    const uint64_t mask = (1ull << sd) - 1;
+    q.whole += I >> sd;
+    q.rem += (uint64_t)I & mask;
+    q.whole += (int64_t)(q.rem >> sd);
+    q.rem &= mask;
+}
+
+// Wave sums (64 remainders below 2^sd stay below 2^(sd+6) <= 2^54), then the
+// block's waves in order: the normalised block total, valid in thread 0.
+__device__ QSum qsum_block(QSum q, int sd) {
+    __shared__ int64_t sQw[16];
+    __shared__ uint64_t sQr[16];
+    for (int off = 32; off > 0; off >>= 1) {
+        q.whole += __shfl_xor(q.whole, off);
+        q.rem += __shfl_xor(q.rem, off);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sQw[w] = q.whole;
+        sQr[w] = q.rem;
+    }
+    __syncthreads();
+    QSum t{0, 0};
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+            t.whole += sQw[i];
+            t.rem += sQr[i];
+            t.whole += (int64_t)(t.rem >> sd);
+            t.rem &= (1ull << sd) - 1;
+        }
+    }
+    __syncthreads();
+    return t;
+}
+
+// The block total added to acc[0] (whole) and acc[1] (remainder) with one
+// integer atomic each (read by a later launch).
+__device__ void qsum_flush(QSum q, int sd, unsigned long long *acc) {
+    const QSum t = qsum_block(q, sd);
+    if (threadIdx.x == 0) {
+        if (t.whole) atomicAdd(&acc[0], (unsigned long long)t.whole);
+        if (t.rem) atomicAdd(&acc[1], (unsigned long long)t.rem);
+    }
+}
+
+// The normalised total of acc, which is then cleared for the next solve
+// (one thread of a launch after every launch that added to acc).
+__device__ __forceinline__ QSum qsum_take(unsigned long long *acc, int sd) {
+    QSum t{(int64_t)acc[0], (uint64_t)acc[1]};
+    t.whole += (int64_t)(t.rem >> sd);
+    t.rem &= (1ull << sd) - 1;
+    acc[0] = 0ull;
+    acc[1] = 0ull;
+    return t;
+}
+
+// Charge of an exact particle count whole + rem 2^-sd.
+__device__ __forceinline__ double qsum_charge(const QSum &t, int sd, double q_macro) {
+    return q_macro * ((double)t.whole + ldexp((double)t.rem, -sd));
+}
+
 __device__ __forceinline__ double *step_slot(double *base, const CtxDev &c) {
     return base ? base + 4 * (*c.step) : nullptr;
 }
@@ -694,6 +770,13 @@ __device__ void finalize_block(const FinArgs &f, const CtxDev &c) {
         if (f.nspec) {
             double wE = 0.5 * f.dV / f.G * e;
             double q = f.dV * (*c.rho0 - f.G * f.rho_ion);
+            if (f.sd) {
+                // fixed-point node sums: the exact integer total
+                const QSum t = qsum_take(c.qacc, f.sd);
+                c.qexact[0] = t.whole;
+                c.qexact[1] = (int64_t)t.rem;
+                q = qsum_charge(t, f.sd, f.q_macro);
+            }
             if (f.walls) {
                 // the physical half of the odd extension, wall nodes at half weight
                 wE = 0.5 * wE;

@@ -325,7 +325,7 @@ apic_status apic_em_init_fields(apic_ctx *c, const apic_particles *p, double *F,
     st = apic_deposit(c, p, acc, stream);
     if (st != APIC_OK) return st;
     if (c->mixed)
-        HIPCHK(c, launch_rho(c->g, true, acc, rho, acc_scale(c), c->d.rho_ion, 1, s));
+        HIPCHK(c, launch_rho(c->g, true, acc, rho, acc_scale(c), c->d.rho_ion, 1, nullptr, s));
     else
         HIPCHK(c, launch_copy_bytes(rho, acc, 8 * (int64_t)c->d.nx * c->d.ny, s));
     FFTCHK(c, hipfftSetStream(c->fwd, s));

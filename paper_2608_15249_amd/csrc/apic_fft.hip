@@ -6,7 +6,8 @@
 //   1. k_fft_rows: one workgroup per pair of rows. rho of both rows from the
 //      accumulation buffer (cleared behind it), one complex FFT along x of
 //      rho_j0 + i rho_j1 in LDS, split into the two rows' half spectra
-//      H [ny][nx/2+1] (the layout of a real-to-complex transform).
+//      H [ny][nx/2+1] (the layout of a real-to-complex transform). Fixed-point
+//      node sums are also reduced exactly (integer sums) for the charge.
 //   2. k_fft_cols: one workgroup per column kx of H. FFT along y, then
 //      phi_hat = rho_hat / K^2 (K^2 the Laplacian's modified wavenumber,
 //      phi_hat(0) = 0) and E_hat_d = -i kappa_d phi_hat (kappa_d = sin(k d)/d,
@@ -146,23 +147,31 @@ __device__ double2 *fft_lds(double2 *a, double2 *b, int lgn, int m, const double
 }
 
 template <bool MIX>
-__device__ __forceinline__ double acc_value(const typename AccOf<MIX>::T *acc, int64_t i, double scale, double add) {
-    const typename AccOf<MIX>::T v = acc[i];
+__device__ __forceinline__ double acc_to_rho(typename AccOf<MIX>::T v, double scale, double add) {
     double w;
     if constexpr (MIX) w = (double)(int64_t)v;
     else w = v;
     return add + scale * w;
 }
 
+template <bool MIX>
+__device__ __forceinline__ double acc_value(const typename AccOf<MIX>::T *acc, int64_t i, double scale, double add) {
+    return acc_to_rho<MIX>(acc[i], scale, add);
+}
+
 // LDS: two buffers of nx complex.
+// qacc (fixed-point sums only, may be NULL): the exact total of the two rows'
+// node sums (the physical nodes 0..nxp between walls) is added to it.
 template <bool MIX, bool WALLS>
 __global__ void __launch_bounds__(kBlock) k_fft_rows(Geo g, typename AccOf<MIX>::T *acc, double scale, double add,
                                                      int clear, double2 *H, const double2 *tw, int lgnx,
-                                                     int lgmax) {
+                                                     int lgmax, unsigned long long *qacc) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nx = g.nx;
     double2 *b0 = (double2 *)smem, *b1 = b0 + nx;
     const int64_t r0 = (int64_t)(2 * blockIdx.x) * nx, r1 = r0 + nx;
+    const int sd = g.S * g.dim;
+    QSum q{0, 0};
     for (int i = threadIdx.x; i < nx; i += blockDim.x) {
         double v0, v1;
         if constexpr (WALLS) {
@@ -177,10 +186,29 @@ __global__ void __launch_bounds__(kBlock) k_fft_rows(Geo g, typename AccOf<MIX>:
                 v1 = sg * acc_value<MIX>(acc, r1 + src, scale, add);
             }
         } else {
-            v0 = acc_value<MIX>(acc, r0 + i, scale, add);
-            v1 = acc_value<MIX>(acc, r1 + i, scale, add);
+            const typename AccOf<MIX>::T a0 = acc[r0 + i], a1 = acc[r1 + i];
+            if constexpr (MIX) {
+                if (qacc) {
+                    qsum_add(q, (int64_t)a0, sd);
+                    qsum_add(q, (int64_t)a1, sd);
+                }
+            }
+            v0 = acc_to_rho<MIX>(a0, scale, add);
+            v1 = acc_to_rho<MIX>(a1, scale, add);
         }
         b0[i] = make_double2(v0, v1);
+    }
+    if constexpr (MIX) {
+        if (qacc) {
+            // between walls: the physical nodes 0..nxp, walls included
+            if constexpr (WALLS) {
+                for (int i = threadIdx.x; i <= g.nxp; i += blockDim.x) {
+                    qsum_add(q, (int64_t)acc[r0 + i], sd);
+                    qsum_add(q, (int64_t)acc[r1 + i], sd);
+                }
+            }
+            qsum_flush(q, sd, qacc);
+        }
     }
     __syncthreads();
     if (clear) {
@@ -319,18 +347,18 @@ hipError_t launch_fused_field(const Geo &g, bool mixed_acc, void *acc, double sc
         auto *a = (unsigned long long *)acc;
         if (g.walls)
             hipLaunchKernelGGL((k_fft_rows<true, true>), rows, dim3(kBlock), sh_rows, s, g, a, scale, add, clear,
-                               (double2 *)H, tw, lgnx, lgmax);
+                               (double2 *)H, tw, lgnx, lgmax, f0.sd ? c.qacc : nullptr);
         else
             hipLaunchKernelGGL((k_fft_rows<true, false>), rows, dim3(kBlock), sh_rows, s, g, a, scale, add, clear,
-                               (double2 *)H, tw, lgnx, lgmax);
+                               (double2 *)H, tw, lgnx, lgmax, f0.sd ? c.qacc : nullptr);
     } else {
         auto *a = (double *)acc;
         if (g.walls)
             hipLaunchKernelGGL((k_fft_rows<false, true>), rows, dim3(kBlock), sh_rows, s, g, a, scale, add, clear,
-                               (double2 *)H, tw, lgnx, lgmax);
+                               (double2 *)H, tw, lgnx, lgmax, nullptr);
         else
             hipLaunchKernelGGL((k_fft_rows<false, false>), rows, dim3(kBlock), sh_rows, s, g, a, scale, add, clear,
-                               (double2 *)H, tw, lgnx, lgmax);
+                               (double2 *)H, tw, lgnx, lgmax, nullptr);
     }
     const int hx = g.nx / 2 + 1;
     const int per = (hx + 7) / 8;

@@ -67,6 +67,12 @@ struct CtxDev {
     double *ky2, *kapy;   // y: [ny]
     double *kz2, *kapz;   // z: [nz]
     double *tw;           // fused 2D field solve: exp(-2 pi i k / nmax), k < nmax, interleaved (re, im)
+    // exact charge of a fixed-point accumulation (mixed path): the launch that
+    // converts the node sums adds (whole particles, remainder in units of
+    // 2^-(S dim) particle) to qacc with integer atomics; the diagnostics
+    // workgroup moves the normalised pair to qexact and clears qacc
+    unsigned long long *qacc;   // [2]
+    int64_t *qexact;            // [2]
 };
 
 // Field diagnostics of one solve: charge and W_E (and, with npush, the
@@ -81,6 +87,9 @@ struct FinArgs {
     int walls;
     double q_macro;
     const int32_t *nlive;
+    // S * dim when the solve converted fixed-point node sums (their exact
+    // total is in CtxDev::qacc), 0 for an FP64 accumulation
+    int sd;
 };
 
 constexpr int kMaxSpecBlocks = 4096;   // per-block partials of the field energies
@@ -157,12 +166,13 @@ hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Pa
                             int32_t *perm, double *part, int32_t *deep, const CtxDev &c, hipStream_t s);
 
 // field: accumulation buffer -> rho (FP64): rho = add + scale * acc
+// (fixed-point sums with qacc set: their exact total is added to qacc)
 hipError_t launch_rho(const Geo &g, bool mixed, void *acc, double *rho, double scale, double add,
-                      int clear, hipStream_t s);
+                      int clear, unsigned long long *qacc, hipStream_t s);
 // walls: rho of the odd extension along x: the physical interior nodes
 // (add + scale acc), zero on the wall nodes, the negated mirror beyond
 hipError_t launch_rho_odd(const Geo &g, bool mixed, void *acc, double *rho, double scale, double add, int clear,
-                          hipStream_t s);
+                          unsigned long long *qacc, hipStream_t s);
 int spectral_blocks(const Geo &g);
 // phi_hat = rho_hat / K^2 (scaled for the inverse transform) and the field
 // energy partials; then E = -(centred difference of phi) in real space
@@ -185,7 +195,7 @@ hipError_t launch_finalize(int npush, int nspec, double mass, double dV, double 
                            double *diag, double *we, double *charge, const CtxDev &c, hipStream_t s);
 hipError_t launch_field1d(const Geo &g, bool mixed, void *acc, double scale, double add, double ion,
                           double dx, int clear, double *E, float *E32, double *we_out,
-                          double *charge_out, int step_mode, const CtxDev &c, hipStream_t s);
+                          double *charge_out, int step_mode, double q_macro, const CtxDev &c, hipStream_t s);
 
 // ---- electromagnetic step (FP64 2D3V, Yee grid; F = [6][G], J = [3][G]) ----
 // F^0 from the potential phi [G]: (Ex, Ey) = -(forward differences of phi),

@@ -836,7 +836,11 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
             load_e_tile<R, double, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
         __syncthreads();
         // field bound of the tile: per axis, or the in-plane |E| when the push
-        // rotates v about z, or |E| when the rotation axis is any (EM)
+        // rotates v about z (on the node-centred grid the gathered E is a
+        // convex combination of node vectors, so its norm is at most the
+        // largest node norm), or, on the staggered Yee grid (EM), where each
+        // component is interpolated with its own weights,
+        // sqrt(max|Ex|^2 + max|Ey|^2 + max|Ez|^2) from per-component maxima
         {
             float e0 = 0.0f, e1 = 0.0f, e2 = 0.0f;
             const int tn = EM ? fw * fh : ex_w * ey_w * ez_w;
@@ -844,8 +848,9 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
                 const float ex = fabsf((float)sE[t]);
                 const float ey = (DIM >= 2) ? fabsf((float)sE[tn + t]) : 0.0f;
                 if constexpr (EM) {
-                    const float ez = fabsf((float)sE[2 * tn + t]);
-                    e0 = fmaxf(e0, sqrtf(ex * ex + ey * ey + ez * ez));
+                    e0 = fmaxf(e0, ex);
+                    e1 = fmaxf(e1, ey);
+                    e2 = fmaxf(e2, fabsf((float)sE[2 * tn + t]));
                 } else if (pc.rot) {
                     e0 = fmaxf(e0, sqrtf(ex * ex + ey * ey));
                 } else {
@@ -861,7 +866,7 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
             }
             if ((threadIdx.x & 63) == 0) {
                 sMax[w][0] = e0;
-                sMax[w][1] = (pc.rot || EM) ? e0 : e1;
+                sMax[w][1] = (pc.rot && !EM) ? e0 : e1;
                 sMax[w][2] = e2;
             }
         }
@@ -871,6 +876,10 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
             emx = fmaxf(emx, sMax[w2][0]);
             emy = fmaxf(emy, sMax[w2][1]);
             emz = fmaxf(emz, sMax[w2][2]);
+        }
+        if constexpr (EM) {
+            // a general B can turn the whole kick along either axis
+            emx = emy = sqrtf(emx * emx + emy * emy + emz * emz);
         }
         const float kick = 2.0f * fabsf(MIX ? pc.af : (float)pc.a) * 1.0009765625f;
         bool skip = kick * emx * pc.dtdx + 0.0009765625f <= pc.deep;
@@ -1113,8 +1122,20 @@ __global__ void __launch_bounds__(kSBlock) k_scan_offsets(Geo g, const int32_t *
 // 2|a| max|E| dt/dx, stays below pc.deep.
 // EM: the electromagnetic form (FP64 2D3V): E is the [6][G] Yee field and
 // acc the [3][G] current J^{n+1/2} (Esirkepov), accumulated with atomics.
+// Waves per SIMD the push is compiled for (0: the compiler's choice). Each
+// push workgroup owns one bucket, so the resident waves per SIMD are at most
+// kSWaves * (buckets per CU) / 4 whatever the register count.
+#ifndef APIC_PUSH_WAVES_PER_EU
+#define APIC_PUSH_WAVES_PER_EU 0
+#endif
+#if APIC_PUSH_WAVES_PER_EU > 0
+#define APIC_PUSH_BOUNDS __launch_bounds__(kSBlock, APIC_PUSH_WAVES_PER_EU)
+#else
+#define APIC_PUSH_BOUNDS __launch_bounds__(kSBlock)
+#endif
+
 template <bool MIX, int DIM, int VDIM, int U, bool HC, bool EM>
-__global__ void __launch_bounds__(kSBlock) k_step_push(Geo g, Parts src, Parts dst, const int32_t *bstart,
+__global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const int32_t *bstart,
                                                       const int32_t *bstart_new, const int32_t *cnt,
                                                       const int32_t *offs, int32_t *farcnt, const double *E, PushC pc,
                                                       typename AccOf<MIX>::T *acc, int32_t *perm, double *part,
@@ -1127,6 +1148,7 @@ __global__ void __launch_bounds__(kSBlock) k_step_push(Geo g, Parts src, Parts d
     __shared__ int sErr;
     __shared__ double sRed[kSWaves];
     __shared__ int32_t sRun[kTab];
+    __shared__ int32_t sRunEnd[kTab];  // end of each (wave, direction) tally's slot range
     __shared__ int32_t sEnd[kFar];   // end of each neighbour destination bucket (slot bound)
     __shared__ int32_t sBack[kSWaves];    // next free slot, from the back, of each wave's stay range
     __shared__ int32_t sFront0[kSWaves];  // first slot of each wave's stay range
@@ -1180,16 +1202,18 @@ __global__ void __launch_bounds__(kSBlock) k_step_push(Geo g, Parts src, Parts d
         // destination bucket (from the offsets pass), and each destination's end
         if (threadIdx.x < kTab) {
             const int w2 = threadIdx.x / kDirs, d = threadIdx.x % kDirs;
-            int off = 0;
+            int off = 0, ct = 0;
             if (d < kFar) {
                 off = offs[b * kTab + threadIdx.x];
+                ct = cnt[b * kTab + threadIdx.x];
                 if (w2 == 0) sEnd[d] = bstart_new[dir_target<DIM>(g, bx, by, bz, d) + 1];
                 if (d == kStay) {
                     sFront0[w2] = off;
-                    sBack[w2] = off + cnt[b * kTab + w2 * kDirs + kStay];
+                    sBack[w2] = off + ct;
                 }
             }
             sRun[threadIdx.x] = off;
+            sRunEnd[threadIdx.x] = off + ct;
         }
         if constexpr (EM)
             load_f_tile<R>(sE, E, g, x0, y0, fw, fh);
@@ -1374,7 +1398,8 @@ __global__ void __launch_bounds__(kSBlock) k_step_push(Geo g, Parts src, Parts d
                         const int e = w * kDirs + code;
                         const int basek = sRun[e];
                         const int r = (int)__popcll(peers & lt), cntk = (int)__popcll(peers);
-                        const bool fits = basek >= 0 && basek + cntk <= sEnd[code];
+                        // inside this tally's own range (and so inside its bucket)
+                        const bool fits = basek >= 0 && basek + cntk <= sRunEnd[e] && sRunEnd[e] <= sEnd[code];
                         slot = fits ? basek + r : -1;
                         if (r == 0) sRun[e] = basek + cntk;
                     }
@@ -1426,6 +1451,16 @@ __global__ void __launch_bounds__(kSBlock) k_step_push(Geo g, Parts src, Parts d
             sBack[w] = back;
         }
         __syncthreads();
+        // every tally's range filled exactly: a count that differs from the
+        // push's (a particle the count pass credited as staying that moved,
+        // or the reverse) leaves a slot empty or overflows a range
+        if (threadIdx.x < kTab) {
+            const int w2 = threadIdx.x / kDirs, d = threadIdx.x % kDirs;
+            if (d < kFar) {
+                const bool full = d == kStay ? sRun[threadIdx.x] == sBack[w2] : sRun[threadIdx.x] == sRunEnd[threadIdx.x];
+                if (!full) atomicOr(&sErr, ERR_ORDER);
+            }
+        }
         if (threadIdx.x < kSWaves) {
             // deep range of each wave's stays, relative to this bucket's new start
             const int t = threadIdx.x;
@@ -1454,17 +1489,27 @@ __global__ void __launch_bounds__(kSBlock) k_step_push(Geo g, Parts src, Parts d
 
 // ---- field: accumulation -> rho --------------------------------------------------
 // rho_j = add + scale * acc_j (acc: double weights or int64 fixed-point sums);
-// acc is cleared when clear != 0.
+// acc is cleared when clear != 0. Fixed-point sums with qacc set: their exact
+// total (sd = S * dim weight bits per particle) is added to qacc.
 template <bool MIX>
 __global__ void __launch_bounds__(kBlock) k_rho(int64_t G, typename AccOf<MIX>::T *acc, double *rho,
-                                                double scale, double add, int clear) {
+                                                double scale, double add, int clear, int sd,
+                                                unsigned long long *qacc) {
+    QSum q{0, 0};
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G; i += (int64_t)gridDim.x * blockDim.x) {
         typename AccOf<MIX>::T v = acc[i];
         double w;
-        if constexpr (MIX) w = (double)(int64_t)v;
-        else w = v;
+        if constexpr (MIX) {
+            w = (double)(int64_t)v;
+            if (qacc) qsum_add(q, (int64_t)v, sd);
+        } else {
+            w = v;
+        }
         rho[i] = add + scale * w;
         if (clear) acc[i] = (typename AccOf<MIX>::T)0;
+    }
+    if constexpr (MIX) {
+        if (qacc) qsum_flush(q, sd, qacc);
     }
 }
 
@@ -1473,18 +1518,26 @@ __global__ void __launch_bounds__(kBlock) k_rho(int64_t G, typename AccOf<MIX>::
 // nx - i the negated value; the wall nodes 0 and nxp hold zero (phi is zero
 // there, so their charge does not enter the solve). One thread per
 // (physical node, row) writes both halves, so acc can be cleared in place.
+// Fixed-point sums with qacc set: the exact total of the physical nodes
+// (walls included) is added to qacc.
 template <bool MIX>
 __global__ void __launch_bounds__(kBlock) k_rho_odd(Geo g, typename AccOf<MIX>::T *acc, double *rho, double scale,
-                                                    double add, int clear) {
+                                                    double add, int clear, unsigned long long *qacc) {
     const int half = g.nxp + 1;
     const int64_t tot = (int64_t)half * g.ny;
+    const int sd = g.S * g.dim;
+    QSum q{0, 0};
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
         const int ix = (int)(t % half);
         const int64_t row = (t / half) * g.nx;
         typename AccOf<MIX>::T v = acc[row + ix];
         double w;
-        if constexpr (MIX) w = (double)(int64_t)v;
-        else w = v;
+        if constexpr (MIX) {
+            w = (double)(int64_t)v;
+            if (qacc) qsum_add(q, (int64_t)v, sd);
+        } else {
+            w = v;
+        }
         const bool wall = ix == 0 || ix == g.nxp;
         const double r = wall ? 0.0 : add + scale * w;
         rho[row + ix] = r;
@@ -1493,6 +1546,9 @@ __global__ void __launch_bounds__(kBlock) k_rho_odd(Geo g, typename AccOf<MIX>::
             acc[row + ix] = (typename AccOf<MIX>::T)0;
             if (!wall) acc[row + g.nx - ix] = (typename AccOf<MIX>::T)0;
         }
+    }
+    if constexpr (MIX) {
+        if (qacc) qsum_flush(q, sd, qacc);
     }
 }
 
@@ -1574,31 +1630,46 @@ __global__ void __launch_bounds__(kBlock) k_grad(Geo g, const double *phi, doubl
 //   charge   = dV * (rho0 - G * rho_ion)
 
 // 1D field (one workgroup of kBlock threads; nodes held in LDS).
+// Fixed-point sums (MIX): the charge is their exact integer total (sd = S
+// weight bits per particle) times q_macro, also stored in c.qexact.
 template <bool MIX>
 __global__ void __launch_bounds__(kBlock) k_field1d(int nx, typename AccOf<MIX>::T *acc, double scale,
                                                     double add, double ion, double dx, int clear, double *E,
                                                     float *E32, double *we, double *charge, int step_mode,
-                                                    CtxDev c) {
+                                                    int sd, double q_macro, CtxDev c) {
     extern __shared__ __align__(16) unsigned char smem[];
     double *sr = (double *)smem;          // [nx] rho, then half-node field
     __shared__ double sRed[kWaves];
     __shared__ double sScan[kBlock];
     double part = 0.0;
+    QSum q{0, 0};
     for (int i = threadIdx.x; i < nx; i += blockDim.x) {
         typename AccOf<MIX>::T v = acc[i];
         double w;
-        if constexpr (MIX) w = (double)(int64_t)v;
-        else w = v;
+        if constexpr (MIX) {
+            w = (double)(int64_t)v;
+            qsum_add(q, (int64_t)v, sd);
+        } else {
+            w = v;
+        }
         double r = add + scale * w;
         sr[i] = r;
         part += r - ion;
         if (clear) acc[i] = (typename AccOf<MIX>::T)0;
     }
-    const double qsum = block_sum(part, sRed);
+    double qtot = block_sum(part, sRed) * dx;
+    if constexpr (MIX) {
+        const QSum t = qsum_block(q, sd);
+        if (threadIdx.x == 0) {
+            c.qexact[0] = t.whole;
+            c.qexact[1] = (int64_t)t.rem;
+            qtot = qsum_charge(t, sd, q_macro);
+        }
+    }
     const double wsum = field1d_block(sr, nx, dx, E, E32, sRed, sScan);
     if (threadIdx.x == 0) {
         if (we) *(step_mode ? step_slot(we, c) : we) = 0.5 * wsum * dx;
-        if (charge) *(step_mode ? step_slot(charge, c) : charge) = qsum * dx;
+        if (charge) *(step_mode ? step_slot(charge, c) : charge) = qtot;
     }
 }
 
@@ -1847,25 +1918,27 @@ hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Pa
 }
 
 hipError_t launch_rho(const Geo &g, bool mixed, void *acc, double *rho, double scale, double add, int clear,
-                      hipStream_t s) {
+                      unsigned long long *qacc, hipStream_t s) {
     const int64_t G = (int64_t)g.nx * g.ny * g.nz;
     const int nb = blocks_for(G, 2048);
     if (mixed)
         hipLaunchKernelGGL(k_rho<true>, dim3(nb), dim3(kBlock), 0, s, G, (unsigned long long *)acc, rho, scale, add,
-                           clear);
+                           clear, g.S * g.dim, qacc);
     else
-        hipLaunchKernelGGL(k_rho<false>, dim3(nb), dim3(kBlock), 0, s, G, (double *)acc, rho, scale, add, clear);
+        hipLaunchKernelGGL(k_rho<false>, dim3(nb), dim3(kBlock), 0, s, G, (double *)acc, rho, scale, add, clear, 0,
+                           nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_rho_odd(const Geo &g, bool mixed, void *acc, double *rho, double scale, double add, int clear,
-                          hipStream_t s) {
+                          unsigned long long *qacc, hipStream_t s) {
     const int nb = blocks_for((int64_t)(g.nxp + 1) * g.ny, 2048);
     if (mixed)
         hipLaunchKernelGGL(k_rho_odd<true>, dim3(nb), dim3(kBlock), 0, s, g, (unsigned long long *)acc, rho, scale,
-                           add, clear);
+                           add, clear, qacc);
     else
-        hipLaunchKernelGGL(k_rho_odd<false>, dim3(nb), dim3(kBlock), 0, s, g, (double *)acc, rho, scale, add, clear);
+        hipLaunchKernelGGL(k_rho_odd<false>, dim3(nb), dim3(kBlock), 0, s, g, (double *)acc, rho, scale, add, clear,
+                           nullptr);
     return hipGetLastError();
 }
 
@@ -1894,14 +1967,14 @@ hipError_t launch_finalize(int npush, int nspec, double mass, double dV, double 
 
 hipError_t launch_field1d(const Geo &g, bool mixed, void *acc, double scale, double add, double ion, double dx,
                           int clear, double *E, float *E32, double *we_out, double *charge_out, int step_mode,
-                          const CtxDev &c, hipStream_t s) {
+                          double q_macro, const CtxDev &c, hipStream_t s) {
     size_t sh = (size_t)g.nx * sizeof(double);
     if (mixed)
         hipLaunchKernelGGL(k_field1d<true>, dim3(1), dim3(kBlock), sh, s, g.nx, (unsigned long long *)acc, scale, add,
-                           ion, dx, clear, E, E32, we_out, charge_out, step_mode, c);
+                           ion, dx, clear, E, E32, we_out, charge_out, step_mode, g.S * g.dim, q_macro, c);
     else
         hipLaunchKernelGGL(k_field1d<false>, dim3(1), dim3(kBlock), sh, s, g.nx, (double *)acc, scale, add, ion, dx,
-                           clear, E, E32, we_out, charge_out, step_mode, c);
+                           clear, E, E32, we_out, charge_out, step_mode, 0, q_macro, c);
     return hipGetLastError();
 }
 

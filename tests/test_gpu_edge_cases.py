@@ -280,3 +280,24 @@ def test_more_buckets_than_the_one_launch_scan_covers(torch):
     dist, idx = tree.query(np.stack([d["x"], d["y"], d["vx"], d["vy"]], axis=1))
     assert len(np.unique(idx)) == n
     assert np.max(dist) <= 1e-9
+
+
+def test_binding_rejects_mismatched_caller_tensors(torch):
+    """The binding checks dtype, device, contiguity and length of every
+    caller tensor before the C call: a binary32 E on the FP64 path, a short
+    diag, a host tensor or a strided view raise ApicError and launch
+    nothing."""
+    from paper_2608_15249_amd.apic import ApicError
+    c, p = _ctx(100, "fp64")
+    E = torch.zeros(2 * c.G, dtype=torch.float64, device="cuda")
+    bad = [
+        lambda: c.step(p, E.float(), None, 1),
+        lambda: c.step(p, E, None, 3, torch.zeros(8, dtype=torch.float64, device="cuda")),
+        lambda: c.step(p, E.cpu(), None, 1),
+        lambda: c.step(p, torch.zeros(4 * c.G, dtype=torch.float64, device="cuda")[::2], None, 1),
+        lambda: c.field_solve(torch.zeros(c.G - 1, dtype=torch.float64, device="cuda"), E),
+        lambda: c.gather_push(p, E[: c.G]),
+    ]
+    for f in bad:
+        with pytest.raises(ApicError):
+            f()

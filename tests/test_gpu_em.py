@@ -438,3 +438,55 @@ def test_empty_plasma_evolves_the_vacuum_field(torch, precision):
     assert np.all(J.cpu().numpy() == 0.0)
     Fg = F.cpu().numpy().reshape(6, ny, nx)
     assert np.max(np.abs(Fg - Fo)) <= 1e-12 * np.max(np.abs(Fo))
+
+
+def test_steps_near_the_count_skip_threshold(torch):
+    """A field near the count pass's skip threshold with the peaks of Ex and
+    Ey on different Yee indices (so no single index carries the largest
+    |E| a particle can gather), a B_z that turns the kick, and particles a
+    quarter cell or more inside the tiles' edges: eight steps in one call
+    match the oracle particle for particle, and the step reports no error
+    (every (wave, direction) range of the scatter filled exactly)."""
+    nx = ny = 32
+    T = 8
+    n = 20000
+    bz, E0 = -2.47, 24.85
+    s = O.Setup(2, 3, nx, float(nx), n, 0.1, ny=ny, Ly=float(ny), bz=bz, c=C_LIGHT)
+    rng = np.random.default_rng(77)
+    k = rng.integers(0, nx // T, n)
+    x = k * T + rng.uniform(0.2505, 0.6, n)
+    y = rng.uniform(0, ny, n)
+    vx, vy, vz = (rng.normal(0, 0.3, n) for _ in range(3))
+    F0 = np.zeros((6, ny, nx))
+    i = np.arange(nx)
+    F0[0][:, (i % 4 == 3) | (i % 4 == 0)] = E0
+    F0[1][:, i % 4 == 1] = E0
+    F0[5] += bz
+    # the largest |E| at one index is E0, below the threshold the count pass
+    # uses with that bound; a particle between the columns gathers more
+    assert np.max(np.sqrt(F0[0] ** 2 + F0[1] ** 2 + F0[2] ** 2)) == E0
+    assert 2 * 0.05 * 1.0009765625 * E0 * 0.1 + 0.0009765625 <= 0.25
+    from paper_2608_15249_amd.apic import Context, Particles
+    c = Context(dim=2, vdim=3, nx=nx, ny=ny, lx=float(nx), ly=float(ny), dt=0.1, n=n, bz=bz, precision="fp64",
+                tile=(T, T), c_light=C_LIGHT, model="em")
+    p = Particles(c)
+    p.upload(x=x, y=y, vx=vx, vy=vy, vz=vz)
+    c.sort_by_cell(p)
+    F = _dev(torch, F0)
+    nsteps = 6
+    c.em_step(p, F, nsteps)
+    c.sync()
+    st = O.State.from_arrays(x, vx, y, vy, vz)
+    Fo = F0.copy()
+    for _ in range(nsteps):
+        M.step(s, st, Fo)
+    # compare as sets of particles, matched through their velocities
+    d = p.download()
+    key_g = np.lexsort((d["vz"], d["vy"], d["vx"]))
+    key_o = np.lexsort((st.vz, st.vy, st.vx))
+    for k_, ref in (("vx", st.vx), ("vy", st.vy), ("vz", st.vz)):
+        assert np.max(np.abs(d[k_][key_g] - ref[key_o])) <= 1e-9, k_
+    for k_, ref, L in (("x", st.x, s.Lx), ("y", st.y, s.Ly)):
+        assert np.max(_pdist(d[k_][key_g], ref[key_o], L)) <= 1e-9 * L, k_
+    Fg = F.cpu().numpy().reshape(6, ny, nx)
+    assert np.max(np.abs(Fg - Fo)) <= 1e-9 * np.max(np.abs(Fo))
