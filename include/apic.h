@@ -246,6 +246,23 @@ apic_status apic_gather_push(apic_ctx *ctx, apic_particles *p, const void *E, do
 apic_status apic_step(apic_ctx *ctx, apic_particles *p, void *rho, double *E, float *E32, int nsteps,
                       double *diag, void *ws, void *stream);
 
+/* apic_step without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation). The workspace is a fixed array of
+ * APIC_STATIC_WS_BYTES bytes inside the library, one per GPU the library runs
+ * on (held until the process ends); the call allocates nothing and otherwise
+ * behaves as apic_step with that array as ws (the same kernels, results and
+ * errors). Returns APIC_EINVAL, with a message, when the context's workspace
+ * (apic_workspace_size) exceeds the array, and APIC_EUNSUPPORTED for 3D
+ * contexts and 2D grids whose sides are not powers of two in [4, 1024] (their
+ * field solve goes through the FFT library). Every call on one GPU uses that
+ * GPU's one array, so calls that overlap on one GPU (other streams, other
+ * threads, other contexts) race; the array keeps the last call's contents,
+ * and each call clears what it needs cleared. */
+#define APIC_STATIC_WS_BYTES (64u << 20)
+apic_status apic_step_static(apic_ctx *ctx, apic_particles *p, void *rho, double *E, float *E32, int nsteps,
+                             double *diag, void *stream);
+
 /* Per-phase timing of apic_step with HIP events recorded on the caller's
  * stream around each phase of each step (count pass, scan, push pass, field
  * solve). apic_profile_enable(ctx, max_steps) creates the events (host call,

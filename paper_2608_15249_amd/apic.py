@@ -66,7 +66,8 @@ EXPORTS = ["apic_create", "apic_destroy", "apic_workspace_size", "apic_num_bucke
            "apic_batch_work_items", "apic_batch_init", "apic_batch_step", "apic_batch_sync_status",
            "apic_batch_last_error", "apic_autotune_tiles", "apic_batch_autotune_chunk",
            "apic_import_state", "apic_adjoint_sizes", "apic_adjoint_forward", "apic_step_adjoint",
-           "apic_em_init_fields", "apic_em_gather_push", "apic_em_step", "apic_charge_exact", "apic_q_macro"]
+           "apic_em_init_fields", "apic_em_gather_push", "apic_em_step", "apic_charge_exact", "apic_q_macro",
+           "apic_step_static"]
 
 _lib = None
 
@@ -117,6 +118,7 @@ def load_library(path: str = LIB_PATH):
         "apic_em_gather_push": ([vp, P(ParticlesC), vp, dbl, cint, vp], cint),
         "apic_em_step": ([vp, P(ParticlesC), vp, vp, cint, vp, vp, vp], cint),
         "apic_charge_exact": ([vp, P(i64), P(i64), vp], cint),
+        "apic_step_static": ([vp, P(ParticlesC), vp, vp, vp, cint, vp, vp], cint),
         "apic_batch_autotune_chunk": ([P(ReplicaC), cint, dbl, dbl, dbl, P(BatchStateC), cint, P(cint), P(dbl), vp],
                                       cint),
     }
@@ -366,6 +368,15 @@ class Context:
                                      ctypes.c_void_p(_ptr(E32)), int(nsteps), ctypes.c_void_p(_ptr(diag)),
                                      ctypes.c_void_p(self.ws.data_ptr()), _stream()))
 
+
+    def step_static(self, parts: "Particles", E, E32, nsteps, diag=None, rho=None, perm=None):
+        """apic_step on the library's fixed device workspace (apic_step_static:
+        no allocation, for callers that cannot allocate)."""
+        self._check_step(E, E32, nsteps, diag, rho, perm)
+        s = parts.struct(perm=perm)
+        self._check(self.L.apic_step_static(self.h, ctypes.byref(s), ctypes.c_void_p(_ptr(rho)),
+                                            ctypes.c_void_p(E.data_ptr()), ctypes.c_void_p(_ptr(E32)), int(nsteps),
+                                            ctypes.c_void_p(_ptr(diag)), _stream()))
 
 
 class Batch:

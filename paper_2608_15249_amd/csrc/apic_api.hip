@@ -10,12 +10,43 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 using namespace apic;
 using namespace apic_host;
 
+// ---- fixed device workspace of apic_step_static -------------------------------
+// One array per GPU the library runs on, held until the process ends. In host
+// code its name is only a host-side stand-in: every use goes through the
+// device address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[APIC_STATIC_WS_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_ok[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// The current device's address of scratch (looked up once per device).
+hipError_t scratch_address(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ok[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = ptr;
+        g_scratch_ok[dev] = true;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
 
 namespace apic_host {
 
@@ -683,6 +714,23 @@ apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, floa
         HIPCHK(c, launch_copy_bytes(bsA, bsB, 4 * (int64_t)(nb + 1), s));
     }
     return APIC_OK;
+}
+
+apic_status apic_step_static(apic_ctx *c, apic_particles *p, void *rho, double *E, float *E32, int nsteps,
+                             double *diag, void *stream) {
+    if (!c) return APIC_EINVAL;
+    if (c->ws_bytes > APIC_STATIC_WS_BYTES) {
+        c->err = "apic_step_static: the context needs " + std::to_string(c->ws_bytes) +
+                 " bytes of workspace, above the fixed array's " + std::to_string((size_t)APIC_STATIC_WS_BYTES);
+        return APIC_EINVAL;
+    }
+    if (c->d.dim >= 2 && !c->fused_fft)
+        return fail(c, APIC_EUNSUPPORTED,
+                    "apic_step_static: the field solve of this grid uses the FFT library (3D, or 2D sides that "
+                    "are not powers of two up to 1024)");
+    void *ws = nullptr;
+    HIPCHK(c, scratch_address(&ws));
+    return apic_step(c, p, rho, E, E32, nsteps, diag, ws, stream);
 }
 
 apic_status apic_profile_enable(apic_ctx *c, int max_steps) {
