@@ -98,6 +98,9 @@ def _load():
         "or_adj_gather_1d": [_i64, _D, _int, _dbl, _D, _D, _D, _D],
         "or_adj_gather_2d": [_i64, _D, _D, _int, _int, _dbl, _dbl, _D, _D, _D, _D, _D, _D, _D, _D],
         "or_adj_boris": [_i64, _int, _D, _D, _D, _D, _dbl, _dbl, _dbl],
+        "or_adj_deposit_3d": [_i64, _D, _D, _D, _int, _int, _int, _dbl, _dbl, _dbl, _dbl, _D, _D, _D, _D],
+        "or_adj_gather_3d": [_i64, _D, _D, _D, _int, _int, _int, _dbl, _dbl, _dbl, _D, _D, _D, _D, _D, _D, _D, _D,
+                             _D, _D, _D, _D],
     }
     for name, args in sig.items():
         fn = getattr(L, name)

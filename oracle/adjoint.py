@@ -9,7 +9,9 @@ gather E^n -> Boris -> move -> deposit -> Poisson -> E^{n+1}, after the field
 of the initial charge and the backward half push of "Example setup and
 implementation"). The objective is the final field energy
 W = 1/2 sum_j |E_j^T|^2 dV, and the gradients are taken with respect to the
-initial positions x^0 and velocities v^0 of every particle.
+initial positions x^0 and velocities v^0 of every particle. Plasmas in 1D,
+2D and 3D (the Cartesian three-dimensional form: trilinear weights, the
+7-point solve, E_z kicks).
 
 Adjoint of each module (lam_* is the derivative of W with respect to *):
   field      E = A rho, with A the FFT solve of the FD Poisson problem and the
@@ -58,6 +60,15 @@ def solve_field_adjoint(s: Setup, lam_E) -> np.ndarray:
         h = 1j * centred_kappa(s.nx, s.dx) * np.fft.fft(lam_E[0]) / K2
         h[0] = 0.0
         return np.real(np.fft.ifft(h))
+    if s.dim == 3:
+        kz2, ky2, kx2 = modified_k2(s.nz, s.dz), modified_k2(s.ny, s.dy), modified_k2(s.nx, s.dx)
+        K2 = kz2[:, None, None] + ky2[None, :, None] + kx2[None, None, :]
+        K2[0, 0, 0] = 1.0
+        h = (1j * centred_kappa(s.nx, s.dx)[None, None, :] * np.fft.fftn(lam_E[0])
+             + 1j * centred_kappa(s.ny, s.dy)[None, :, None] * np.fft.fftn(lam_E[1])
+             + 1j * centred_kappa(s.nz, s.dz)[:, None, None] * np.fft.fftn(lam_E[2])) / K2
+        h[0, 0, 0] = 0.0
+        return np.real(np.fft.ifftn(h))
     K2 = modified_k2(s.ny, s.dy)[:, None] + modified_k2(s.nx, s.dx)[None, :]
     K2[0, 0] = 1.0
     h = (1j * centred_kappa(s.nx, s.dx)[None, :] * np.fft.fft2(lam_E[0])
@@ -67,7 +78,7 @@ def solve_field_adjoint(s: Setup, lam_E) -> np.ndarray:
 
 
 def _positions(st: State):
-    return (st.x.copy(), None if st.y is None else st.y.copy())
+    return (st.x.copy(), None if st.y is None else st.y.copy(), None if st.z is None else st.z.copy())
 
 
 def _velocities(st: State):
@@ -104,17 +115,20 @@ def forward_trajectory(s: Setup, st0: State, nsteps: int):
 
 
 def _pos_state(s: Setup, pos) -> State:
-    return State(pos[0], np.zeros_like(pos[0]), pos[1], None, None)
+    return State(pos[0], np.zeros_like(pos[0]), pos[1], None, None, pos[2])
 
 
 def adj_deposit(s: Setup, pos, lam_rho, lam_x) -> None:
     """lam_x += (Q/dV) sum_j lam_rho_j dW_j/dx at the positions pos (in place)."""
     L = _load()
-    x, y = pos
+    x, y, z = pos
     n = x.shape[0]
     c = s.Q / s.dV
     lr = _c64(lam_rho)
-    if s.dim == 1:
+    if s.dim == 3:
+        L.or_adj_deposit_3d(n, _p(x, _D), _p(y, _D), _p(z, _D), s.nx, s.ny, s.nz, s.dx, s.dy, s.dz, c, _p(lr, _D),
+                            _p(lam_x[0], _D), _p(lam_x[1], _D), _p(lam_x[2], _D))
+    elif s.dim == 1:
         L.or_adj_deposit_1d(n, _p(x, _D), s.nx, s.dx, c, _p(lr, _D), _p(lam_x[0], _D))
     else:
         L.or_adj_deposit_2d(n, _p(x, _D), _p(y, _D), s.nx, s.ny, s.dx, s.dy, c, _p(lr, _D),
@@ -124,9 +138,15 @@ def adj_deposit(s: Setup, pos, lam_rho, lam_x) -> None:
 def adj_gather(s: Setup, pos, E, lam_Ep, lam_E, lam_x) -> None:
     """Scatter lam_Ep into lam_E and add the field-gradient term to lam_x."""
     L = _load()
-    x, y = pos
+    x, y, z = pos
     n = x.shape[0]
-    if s.dim == 1:
+    if s.dim == 3:
+        Ex, Ey, Ez = (_c64(e) for e in E)
+        L.or_adj_gather_3d(n, _p(x, _D), _p(y, _D), _p(z, _D), s.nx, s.ny, s.nz, s.dx, s.dy, s.dz, _p(Ex, _D),
+                           _p(Ey, _D), _p(Ez, _D), _p(lam_Ep[0], _D), _p(lam_Ep[1], _D), _p(lam_Ep[2], _D),
+                           _p(lam_E[0], _D), _p(lam_E[1], _D), _p(lam_E[2], _D), _p(lam_x[0], _D), _p(lam_x[1], _D),
+                           _p(lam_x[2], _D))
+    elif s.dim == 1:
         L.or_adj_gather_1d(n, _p(x, _D), s.nx, s.dx, _p(_c64(E[0]), _D), _p(lam_Ep[0], _D), _p(lam_E[0], _D),
                            _p(lam_x[0], _D))
     else:
@@ -141,11 +161,15 @@ def adj_boris(s: Setup, lam_v, dt: float):
     L = _load()
     n = lam_v[0].shape[0]
     lEx = np.zeros(n)
-    lEy = np.zeros(n) if s.dim == 2 else None
+    lEy = np.zeros(n) if s.dim >= 2 else None
     lvy = lam_v[1] if s.vdim >= 2 else None
     L.or_adj_boris(n, s.vdim, _p(lam_v[0], _D), _p(lvy, _D), _p(lEx, _D), _p(lEy, _D), s.qm, dt, s.bz)
     # the pusher's electric field has dim components; with vdim > dim (2D3V
     # has no E_z) the extra velocity components take no kick
+    if s.dim == 3:
+        # the rotation about z leaves v_z alone: v_z gains the two half kicks
+        # a E_z, so lam_Ez = 2a lam_vz and lam_vz passes through
+        return [lEx, lEy, 2.0 * (s.qm * dt * 0.5) * lam_v[2]]
     return [lEx] if s.dim == 1 else [lEx, lEy]
 
 
@@ -239,15 +263,18 @@ def adjoint(s: Setup, st0: State, nsteps: int, seed: float = 1.0):
 
 def delta0_direction(s: Setup, x_u, y_u, mode) -> List[np.ndarray]:
     """d x^0 / d delta0 for the mode seeding x = x_u + delta0 k/|k|^2 sin(k.x_u)
-    (per axis; the periodic wrap has slope one)."""
+    (per axis; the periodic wrap has slope one). In 3D the mode is
+    (mx, my, 0): z is not displaced."""
     kx = 2.0 * np.pi * mode[0] / s.Lx
-    ky = 2.0 * np.pi * mode[1] / s.Ly if s.dim == 2 else 0.0
+    ky = 2.0 * np.pi * mode[1] / s.Ly if s.dim >= 2 else 0.0
     k2 = kx * kx + ky * ky
-    ph = kx * x_u + (ky * y_u if s.dim == 2 else 0.0)
+    ph = kx * x_u + (ky * y_u if s.dim >= 2 else 0.0)
     sn = np.sin(ph)
     out = [kx / k2 * sn]
-    if s.dim == 2:
+    if s.dim >= 2:
         out.append(ky / k2 * sn)
+    if s.dim == 3:
+        out.append(np.zeros_like(sn))
     return out
 
 

@@ -433,6 +433,78 @@ void or_adj_gather_2d(int64_t n, const double *x, const double *y, int nx, int n
     }
 }
 
+/* 3D deposit adjoint: lx, ly, lz += c * the slope of the trilinear hat, i.e.
+ * d/dx of sum_abc (wx_a wy_b) wz_c lrho_abc over the particle's cell:
+ * (sum_bc wy_b wz_c (lrho_1bc - lrho_0bc)) / dx, and likewise along y, z. */
+void or_adj_deposit_3d(int64_t n, const double *x, const double *y, const double *z, int nx, int ny, int nz,
+                       double dx, double dy, double dz, double c, const double *lrho, double *lx, double *ly,
+                       double *lz)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t i[2], j[2], k[2]; double fx, fy, fz;
+        cic_cell(x[p], nx, dx, &i[0], &fx);
+        cic_cell(y[p], ny, dy, &j[0], &fy);
+        cic_cell(z[p], nz, dz, &k[0], &fz);
+        i[1] = (i[0] + 1) % nx; j[1] = (j[0] + 1) % ny; k[1] = (k[0] + 1) % nz;
+        double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+        double l[2][2][2];
+        for (int cc = 0; cc < 2; ++cc)
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a)
+                    l[cc][b][a] = lrho[(k[cc] * ny + j[b]) * nx + i[a]];
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 2; ++v) {
+                gx += wy[u] * wz[v] * (l[v][u][1] - l[v][u][0]);
+                gy += wx[u] * wz[v] * (l[v][1][u] - l[v][0][u]);
+                gz += wx[u] * wy[v] * (l[1][v][u] - l[0][v][u]);
+            }
+        lx[p] += c * gx / dx;
+        ly[p] += c * gy / dy;
+        lz[p] += c * gz / dz;
+    }
+}
+
+/* 3D gather adjoint: lam_E of each component += (wx wy) wz lam_Ep at the
+ * particle's eight nodes; lx, ly, lz += the slope of the interpolated field
+ * along each axis dotted with lam_Ep. */
+void or_adj_gather_3d(int64_t n, const double *x, const double *y, const double *z, int nx, int ny, int nz,
+                      double dx, double dy, double dz, const double *Ex, const double *Ey, const double *Ez,
+                      const double *lEpx, const double *lEpy, const double *lEpz, double *lEx, double *lEy,
+                      double *lEz, double *lx, double *ly, double *lz)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t i[2], j[2], k[2]; double fx, fy, fz;
+        cic_cell(x[p], nx, dx, &i[0], &fx);
+        cic_cell(y[p], ny, dy, &j[0], &fy);
+        cic_cell(z[p], nz, dz, &k[0], &fz);
+        i[1] = (i[0] + 1) % nx; j[1] = (j[0] + 1) % ny; k[1] = (k[0] + 1) % nz;
+        double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+        double ax = lEpx[p], ay = lEpy[p], az = lEpz[p];
+        double g[2][2][2];
+        for (int cc = 0; cc < 2; ++cc)
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a) {
+                    int64_t m = (k[cc] * ny + j[b]) * nx + i[a];
+                    double w = (wx[a] * wy[b]) * wz[cc];
+                    lEx[m] += w * ax;
+                    lEy[m] += w * ay;
+                    lEz[m] += w * az;
+                    g[cc][b][a] = Ex[m] * ax + Ey[m] * ay + Ez[m] * az;
+                }
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 2; ++v) {
+                gx += wy[u] * wz[v] * (g[v][u][1] - g[v][u][0]);
+                gy += wx[u] * wz[v] * (g[v][1][u] - g[v][0][u]);
+                gz += wx[u] * wy[v] * (g[1][v][u] - g[0][v][u]);
+            }
+        lx[p] += gx / dx;
+        ly[p] += gy / dy;
+        lz[p] += gz / dz;
+    }
+}
+
 /* Adjoint of the Boris map. For a fixed uniform bz the map is linear in
  * (v, E_p): v_new = R v + a (R + I) E_p, with R the rotation
  *   R = [[1 - s t, s], [-s, 1 - s t]]   acting on (vx, vy),
