@@ -121,7 +121,7 @@ def _pos_state(s: Setup, pos) -> State:
 def adj_deposit(s: Setup, pos, lam_rho, lam_x) -> None:
     """lam_x += (Q/dV) sum_j lam_rho_j dW_j/dx at the positions pos (in place)."""
     L = _load()
-    x, y, z = pos
+    x, y, z = (tuple(pos) + (None, None))[:3]
     n = x.shape[0]
     c = s.Q / s.dV
     lr = _c64(lam_rho)
@@ -138,7 +138,7 @@ def adj_deposit(s: Setup, pos, lam_rho, lam_x) -> None:
 def adj_gather(s: Setup, pos, E, lam_Ep, lam_E, lam_x) -> None:
     """Scatter lam_Ep into lam_E and add the field-gradient term to lam_x."""
     L = _load()
-    x, y, z = pos
+    x, y, z = (tuple(pos) + (None, None))[:3]
     n = x.shape[0]
     if s.dim == 3:
         Ex, Ey, Ez = (_c64(e) for e in E)
