@@ -1,15 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark of the PIC particle-grid coupling loop on one MI355X.
 
-Default workload (thermal_2d): 2D2V thermal plasma, 512 x 512 cells,
-dx = lambda_D = 1, 64 electrons per cell (16,777,216), Maxwellian v_th = 1,
-uniform positions, immobile ion background, CIC, dt = 0.1 (seeded synthetic
-input). Other workloads (--workload): magnetized_2d3v (1024 x 1024, 32 per
-cell, 33,554,432 electrons, B_z with omega_c/omega_p = 2, dt = 0.05),
-thermal_3d (3D3V, 128 x 128 x 128 cells, 8 per cell, 16,777,216 electrons,
-dt = 0.1: the Cartesian 3D form of the coupling loop) and landau_batch (256
-uneven 1D1V Landau-damping replicas advanced by the batched path, one
-graph-replayed persistent launch per step).
+Default workload (magnetized_2d3v, the largest single-plasma configuration):
+2D3V Maxwellian plasma in a uniform B_z (omega_c/omega_p = 2), 1024 x 1024
+cells, dx = lambda_D = 1, 32 electrons per cell (33,554,432), v_th = 1 in all
+three components, 1% density perturbation at k = (2 pi/64, 0), Boris push,
+CIC, dt = 0.05 (seeded synthetic input); the default run also measures
+thermal_2d (2D2V, 512 x 512 cells, 64 per cell, 16,777,216 electrons,
+dt = 0.1) and reports it under "thermal_2d". Other workloads (--workload):
+thermal_2d alone, thermal_3d (3D3V, 128 x 128 x 128 cells, 8 per cell,
+16,777,216 electrons, dt = 0.1: the Cartesian 3D form of the coupling loop)
+and landau_batch (256 uneven 1D1V Landau-damping replicas advanced by the
+batched path, one graph-replayed persistent launch per step).
 
 One step = one full PIC cycle: gather + Boris + move, deposit (CIC),
 counting sort by tile bucket, periodic Poisson solve and E. The headline value
@@ -82,6 +84,52 @@ def load_traffic(precision, workload, tile):
         return None
 
 
+# Atomic-throughput peaks, derived from unit counts and clock (256 CUs,
+# 2.4 GHz): LDS 128 bytes per clock per CU, of which a 64-bit atomic lane
+# operation uses 8; L2 one atomic per channel per clock, 16 channels in each of
+# the 8 XCDs.
+LDS_ATOMIC_PEAK_OPS = 256 * 2.4e9 * 128 / 8
+L2_ATOMIC_PEAK_OPS = 8 * 16 * 2.4e9
+
+
+def load_counters(precision, workload, tile):
+    """Per-launch counter values of the push from the committed rocprofv3
+    counter runs, if taken on the current kernel source, workload and tile."""
+    p = os.path.join(ROOT, "profiles", "step_push_%s_counters.json" % workload)
+    if not os.path.exists(p):
+        return None
+    from paper_2608_15249_amd.rocprof_summary import kernel_source_sha
+    try:
+        d = json.load(open(p))
+        e = d.get(precision)
+        if not e or d.get("kernel_src_sha") != kernel_source_sha() or list(d.get("tile", [])) != list(tile):
+            return None
+        return e["per_launch"]
+    except Exception:
+        return None
+
+
+def atomics_of(counters, n, push_ms):
+    """Atomic counts per launch of the push (LDS deposit atomics as active
+    64-bit lane operations from SQ_INSTS_LDS_ATOMIC_BANDWIDTH, 64-byte units;
+    L2 atomics of the tile flushes and far movers from TCC_ATOMIC_sum), per
+    particle, and their rates over the measured launch time against the
+    derived peaks."""
+    if not counters:
+        return None
+    lds_ops = counters.get("SQ_INSTS_LDS_ATOMIC_BANDWIDTH", 0.0) * 64 / 8
+    l2 = counters.get("TCC_ATOMIC_sum", 0.0)
+    t = push_ms * 1e-3
+    return {"lds_atomic_ops": lds_ops, "lds_atomic_ops_per_particle": lds_ops / n,
+            "lds_atomic_rate": lds_ops / t, "lds_atomic_peak": LDS_ATOMIC_PEAK_OPS,
+            "lds_atomic_frac": lds_ops / t / LDS_ATOMIC_PEAK_OPS,
+            "l2_atomics": l2, "l2_atomics_per_particle": l2 / n, "l2_atomic_rate": l2 / t,
+            "l2_atomic_peak": L2_ATOMIC_PEAK_OPS, "l2_atomic_frac": l2 / t / L2_ATOMIC_PEAK_OPS,
+            "unit": "operations/s",
+            "source": "rocprofv3 counters of the same kernel source and tile (profiles/), rates over this run's "
+                      "push time"}
+
+
 def measure_copy_gbs(torch, nbytes=512 << 20, reps=20):
     """Device-to-device copy rate (bytes read + bytes written per second) of
     the runtime's plain copy on a buffer larger than the last-level cache:
@@ -116,8 +164,12 @@ def run_path(precision, w, state, steps, warmup, tile, torch, pusher="boris", c_
     sim = Simulation(w, precision, state=state, tile=tile, pusher=pusher, c_light=c_light, walls=walls)
     sim.initialise()
     sim.ctx.sync()
+    # the warm-up steps start from the seeded state: their field energies are
+    # compared with the oracle's (cpu_baseline leg) for the field-energy error
+    warm_we = []
     if warmup:
-        sim.run(warmup, diag=False)
+        dw = sim.run(warmup, diag=True)
+        warm_we = [float(v) for v in dw.cpu().numpy().reshape(warmup, 4)[:, 1]]
     sim.ctx.sync()
     n = sim.n
     n_start = int(sim.p.bucket_start[-1].item()) if walls else n
@@ -144,6 +196,8 @@ def run_path(precision, w, state, steps, warmup, tile, torch, pusher="boris", c_
     # counters were taken for the Boris kernels only
     traffic = load_traffic(precision, "%s_%d" % (w.name, w.nx), list(sim.tile)) \
         if pusher == "boris" and not walls else None
+    counters = load_counters(precision, "%s_%d" % (w.name, w.nx), list(sim.tile)) \
+        if pusher == "boris" and not walls else None
     # particle pushes of the timed steps: with absorbing walls the count falls
     # (diag charge = q_macro * live count after each step)
     pushes = n * steps
@@ -153,7 +207,8 @@ def run_path(precision, w, state, steps, warmup, tile, torch, pusher="boris", c_
     out = {
         "value": pushes / elapsed,
         "ms_per_step": 1e3 * elapsed / steps,
-        "hbm_gbs_step": (3 * sb * n * steps) / elapsed / 1e9,
+        # the fused step's algorithmic bytes (state read + written once) over the step time
+        "hbm_gbs_step": (2 * sb * n * steps) / elapsed / 1e9,
         "tile": list(sim.tile),
         "tune_ms_per_step": sim.tune_ms,
         "phase_ms_per_step": {"count": ms[0] / nprof, "scan": ms[1] / nprof, "push": ms[2] / nprof,
@@ -166,9 +221,14 @@ def run_path(precision, w, state, steps, warmup, tile, torch, pusher="boris", c_
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None if traffic is None else traffic / (push_ms * 1e-3) / 1e9,
                      "kernel": "k_step_push (gather+%s+move+deposit+scatter)" % ("Higuera-Cary" if pusher == "hc" else "Boris"),
-                     "bytes_per_launch": push_bytes},
+                     "bytes_per_launch": push_bytes,
+                     "atomics": atomics_of(counters, n, push_ms)},
         "final_WE": float(d[-1, 1]),
         "charge": float(d[-1, 0]),
+        "warmup_WE": warm_we,
+        "push_ms": push_ms,
+        "n": n,
+        "exact_charge": list(sim.ctx.charge_exact()) if sim.mixed else None,
     }
     if walls:
         out["live_particles"] = {"start": n_start, "end": live[-1]}
@@ -220,7 +280,7 @@ def run_em(precision, w, state, steps, warmup, tile, c_light, torch):
     out = {
         "value": n * steps / elapsed,
         "ms_per_step": 1e3 * elapsed / steps,
-        "hbm_gbs_step": (3 * sb * n * steps) / elapsed / 1e9,
+        "hbm_gbs_step": (2 * sb * n * steps) / elapsed / 1e9,
         "tile": list(ctx.tile),
         "phase_ms_per_step": {"count": ms[0] / nprof, "scan": ms[1] / nprof, "push": ms[2] / nprof,
                               "field": ms[3] / nprof, "note": PHASE_NOTE % nprof},
@@ -323,8 +383,29 @@ def run_batch(reps, steps, warmup, chunk, torch):
     return out
 
 
-def cpu_baseline(w, state, nsteps, pusher="boris", c_light=float("inf")):
-    """Serial FP64 oracle on the same plasma (host, one core)."""
+def cpu_model():
+    """Model name of the host CPU, from /proc/cpuinfo."""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.lower().startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores():
+    """Cores this process may run on, at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_steps(w, state, nsteps, pusher, c_light, record_we=False):
+    """The serial FP64 oracle from the seeded state: initialise, then nsteps
+    steps; returns (seconds of the steps, W_E after each step)."""
     import oracle as O
     if w.dim == 3:
         x, y, z, vx, vy, vz = state
@@ -334,13 +415,70 @@ def cpu_baseline(w, state, nsteps, pusher="boris", c_light=float("inf")):
                 c=c_light)
     st = O.State.from_arrays(x, vx, y, vy, vz, z)
     E, _ = O.initialise(s, st)
+    we = []
     t0 = time.perf_counter()
     for _ in range(nsteps):
         E, _, _ = O.step(s, st, E)
-    t1 = time.perf_counter()
-    return {"value": len(x) * nsteps / (t1 - t0), "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "full %s / %d-particle plasma, %d oracle steps (serial C particle loops + numpy FFT, "
-                      "FP64), %.1f s" % ("x".join(str(v) for v in _grid(w)), len(x), nsteps, t1 - t0)}
+        if record_we:
+            we.append(O.field_energy(s, E))
+    return time.perf_counter() - t0, we
+
+
+_FORK_JOB = None   # (workload, state, steps, pusher, c) handed to forked workers by inheritance
+
+
+def _oracle_worker(_):
+    w, state, nsteps, pusher, c_light = _FORK_JOB
+    sec, _ = _oracle_steps(w, state, nsteps, pusher, c_light)
+    return sec
+
+
+def cpu_baseline(w, state, nsteps, pusher="boris", c_light=float("inf"), record_we=False, all_cores=True):
+    """Serial FP64 oracle on the same plasma (host, one core), then the same
+    oracle in one process per host core, each advancing its own copy of the
+    plasma (the aggregate host throughput). With record_we, the oracle's
+    field energy after each step goes to "_we" (for field_energy_errors)."""
+    sec, we = _oracle_steps(w, state, nsteps, pusher, c_light, record_we=record_we)
+    n = len(state[0])
+    out = {"value": n * nsteps / sec, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": "full %s / %d-particle plasma, %d oracle steps (serial C particle loops + numpy FFT, "
+                     "FP64), %.1f s" % ("x".join(str(v) for v in _grid(w)), n, nsteps, sec)}
+    if all_cores:
+        import multiprocessing as mp
+        P = host_cores()
+        k = max(1, nsteps // 3)
+        global _FORK_JOB
+        _FORK_JOB = (w, state, k, pusher, c_light)
+        ctx = mp.get_context("fork")
+        t0 = time.perf_counter()
+        with ctx.Pool(P) as pool:
+            secs = pool.map(_oracle_worker, range(P), chunksize=1)
+        wall = time.perf_counter() - t0
+        _FORK_JOB = None
+        out["all_cores"] = {"value": P * n * k / max(secs), "unit": "particle-steps/s", "cores": P,
+                            "kind": "oracle, one process per core",
+                            "sample": "%d processes, each the full plasma for %d oracle steps (slowest %.1f s, "
+                                      "%.1f s wall with set-up)" % (P, k, max(secs), wall)}
+    if record_we:
+        out["_we"] = we
+    return out
+
+
+def field_energy_errors(gpu_we, we):
+    """Relative field-energy difference of each GPU path from the FP64 oracle,
+    both started from the same seeded state (the GPU's warm-up steps): after
+    the first step (the local error of one step) and the largest over the
+    steps both ran (the trajectories then separate at the rate the plasma's
+    noise grows)."""
+    fe = {}
+    for path, g in gpu_we.items():
+        m = min(len(g), len(we))
+        if m == 0:
+            continue
+        rel = [abs(g[i] - we[i]) / we[i] for i in range(m)]
+        fe[path] = {"first_step": rel[0], "max": max(rel), "steps": m}
+    return fe
 
 
 def _grid(w):
@@ -396,10 +534,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=36)
+    ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", default="mixed,fp64")
-    ap.add_argument("--workload", default="thermal_2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="magnetized_2d3v", choices=sorted(WORKLOADS))
+    ap.add_argument("--also", default=None,
+                    help="comma-separated extra single-plasma workloads measured the same way (both paths) and "
+                         "reported under their names; default thermal_2d with the default workload, none otherwise")
     ap.add_argument("--tile", default="auto", help="sort-bucket tile TXxTY (TXxTYxTZ in 3D), or auto (autotuner; the default tile in 3D)")
     ap.add_argument("--chunk", default="auto", help="batch work-item size, or auto (autotuner)")
     ap.add_argument("--pusher", default="boris", choices=("boris", "hc"),
@@ -418,11 +559,11 @@ def main():
         sys.exit(2)
     import torch
     from paper_2608_15249_amd import workloads as W
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     common = {"metric": "particle-steps/s (sort+deposit+gather+push), HBM GB/s; mixed vs FP64 path",
               "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
     if args.workload == "landau_batch":
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
         reps = W.landau_batch()
         chunk = args.chunk if args.chunk == "auto" else int(args.chunk)
         print("bench: landau_batch, %d replicas, %d warmup + %d timed steps" % (len(reps), args.warmup, args.steps),
@@ -444,6 +585,7 @@ def main():
     state = W.sample3(w) if w.dim == 3 else W.sample(w)
     tile = parse_tile(args.tile)
     if args.model == "em":
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
         if w.dim != 2 or w.vdim != 3:
             print("--model em needs a 2D3V workload (magnetized_2d3v)", file=sys.stderr)
             sys.exit(2)
@@ -484,6 +626,18 @@ def main():
         print("--pusher hc needs a 3V workload (magnetized_2d3v or thermal_3d)", file=sys.stderr)
         sys.exit(2)
     c_light = (8.0 if args.c_light is None else args.c_light) if args.pusher == "hc" else 0.0
+    # the oracle legs run first, on the host, before this process touches the
+    # GPU (the all-core leg forks one process per core)
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (%d oracle steps, then all host cores)" % args.cpu_steps, file=sys.stderr,
+              flush=True)
+        if args.walls:
+            cpu = cpu_baseline_walls(w, state, min(args.cpu_steps, 6))
+        else:
+            cpu = cpu_baseline(w, state, args.cpu_steps, args.pusher,
+                               c_light if args.pusher == "hc" else float("inf"), record_we=args.warmup > 0)
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
     res = {}
     for path in args.paths.split(","):
         print("bench: %s, %s path, %d warmup + %d timed steps" % (args.workload, path, args.warmup, args.steps),
@@ -506,6 +660,10 @@ def main():
         "particle_steps_s_by_phase": head["particle_steps_s_by_phase"],
         "tune_ms_per_step": head["tune_ms_per_step"],
     })
+    if head.get("exact_charge") is not None:
+        line["exact_charge"] = {"whole": head["exact_charge"][0], "frac": head["exact_charge"][1],
+                                "particles": head["n"],
+                                "note": "the last step's fixed-point node sums, totalled exactly on the device"}
     if "live_particles" in head:
         line["live_particles"] = head["live_particles"]
     if "fp64" in res and "mixed" in res:
@@ -515,13 +673,30 @@ def main():
                         "phase_ms_per_step": f["phase_ms_per_step"],
                         "particle_steps_s_by_phase": f["particle_steps_s_by_phase"]}
         line["mixed_over_fp64"] = head["value"] / f["value"]
-    if not args.no_cpu_baseline:
-        print("bench: cpu baseline (%d oracle steps)" % args.cpu_steps, file=sys.stderr, flush=True)
-        if args.walls:
-            line["cpu_baseline"] = cpu_baseline_walls(w, state, min(args.cpu_steps, 6))
-        else:
-            line["cpu_baseline"] = cpu_baseline(w, state, args.cpu_steps, args.pusher,
-                                                c_light if args.pusher == "hc" else float("inf"))
+    if cpu is not None:
+        we = cpu.pop("_we", None)
+        if we:
+            cpu["field_energy_err"] = field_energy_errors({p: r["warmup_WE"] for p, r in res.items()}, we)
+            line["field_energy_err"] = cpu["field_energy_err"]
+        line["cpu_baseline"] = cpu
+    del res
+    # the other workloads of the default run, measured the same way (both paths)
+    also = args.also if args.also is not None else ("thermal_2d" if args.workload == "magnetized_2d3v" and
+                                                      not args.walls and args.pusher == "boris" else "")
+    for name in [a for a in also.split(",") if a]:
+        w2 = getattr(W, name)()
+        st2 = W.sample3(w2) if w2.dim == 3 else W.sample(w2)
+        ex = {"config": {"workload": WORKLOADS[name], "grid": _grid(w2), "particles": w2.n_particles}}
+        for path in args.paths.split(","):
+            print("bench: %s, %s path, %d warmup + %d timed steps" % (name, path, args.warmup, args.steps),
+                  file=sys.stderr, flush=True)
+            r = run_path(path, w2, st2, args.steps, args.warmup, "auto", torch)
+            ex[path] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "tile": r["tile"],
+                        "hbm_gbs_step": r["hbm_gbs_step"], "roofline": with_copy(r["roofline"], copy_gbs),
+                        "phase_ms_per_step": r["phase_ms_per_step"],
+                        "particle_steps_s_by_phase": r["particle_steps_s_by_phase"]}
+        line[name] = ex
+        del st2
     print(json.dumps(line), flush=True)
 
 

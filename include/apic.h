@@ -178,14 +178,20 @@ double apic_q_macro(const apic_ctx *ctx);
  * another axis. */
 int apic_tile_size(const apic_ctx *ctx, int axis);
 
-/* Counting sort of the particles by bucket (a1): key = tile-major bucket of
- * each particle's cell; stable radix passes (tallies, exclusive scan,
- * scatter), the bucket table read off the sorted keys, a gather. Particles end up
+/* Counting sort of the particles by bucket: key = tile-major bucket of each
+ * particle's cell; stable radix passes (tallies, exclusive scan, scatter),
+ * the bucket table read off the sorted keys, a gather. Particles end up
  * ordered by ascending bucket, in place; bucket_start is written; perm is
- * written when non-NULL. The order inside a bucket is unspecified. */
+ * written when non-NULL. The order inside a bucket is unspecified. The paper
+ * leaves the particle data structures to the application ("Example setup and
+ * implementation"); this order is the library's choice, so that the deposit
+ * and the gather of one bucket touch one tile of the grid. */
 apic_status apic_sort_by_cell(apic_ctx *ctx, apic_particles *p, void *ws, void *stream);
 
-/* CIC charge deposit (a2) of the particles' current positions.
+/* Charge deposit of the particles' current positions: the paper's B_Scatter
+ * ("Core functionality", particle-grid coupling; module B01 of the two-stream
+ * example) with cloud-in-cell (bilinear; linear in 1D, trilinear in 3D)
+ * weights.
  * FP64 : rho [dev, double, G] is overwritten with
  *        rho_ion + (q_macro/dV) * sum_p W_j(x_p).
  * MIXED: rho [dev, int64, G] is overwritten with the fixed-point node sums
@@ -195,9 +201,11 @@ apic_status apic_sort_by_cell(apic_ctx *ctx, apic_particles *p, void *ws, void *
  * (LDS-tiled kernel); with NULL any order is accepted. */
 apic_status apic_deposit(apic_ctx *ctx, const apic_particles *p, void *rho, void *stream);
 
-/* Periodic Poisson solve and field (a3): -lap_h phi = rho with the 3-point
- * (1D) / 5-point (2D) finite-difference Laplacian, mean-free phi, and
- * E = -(centred difference of phi).
+/* Periodic Poisson solve and field: the paper's D_Poisson ("Core
+ * functionality"; modules D02, D05 and D06 of the two-stream example solve
+ * for phi and form E). -lap_h phi = rho with the 3-point (1D) / 5-point (2D)
+ * / 7-point (3D) finite-difference Laplacian, mean-free phi, and
+ * E = -(centred difference of phi), solved by FFT on the periodic grid.
  * rho  [dev]: double [G] (FP64) or int64 fixed-point sums [G] (MIXED; converted
  *             with rho_ion + q_macro * I * 2^(-S*dim) / dV).
  * E    [dev, double, dim*G] output.
@@ -206,7 +214,10 @@ apic_status apic_deposit(apic_ctx *ctx, const apic_particles *p, void *rho, void
 apic_status apic_field_solve(apic_ctx *ctx, const void *rho, double *E, float *E32, double *we,
                              void *ws, void *stream);
 
-/* Gather (a4) + Boris velocity advance (a5) [+ position update (a6)].
+/* Gather + velocity advance [+ position update]: the paper's C_Gather and
+ * A_Pusher ("Core functionality"; modules C01 and A01 of the two-stream
+ * example), then the position update with periodic boundaries that the
+ * example's application code performs ("Example setup and implementation").
  * E [dev]: double [dim*G] (FP64) or float [dim*G] (MIXED).
  * The velocity advances by dt * dt_scale (dt_scale = -0.5 gives the initial
  * backward half push, a7). move != 0 then advances positions by dt (not
@@ -215,7 +226,11 @@ apic_status apic_field_solve(apic_ctx *ctx, const void *rho, double *E, float *E
 apic_status apic_gather_push(apic_ctx *ctx, apic_particles *p, const void *E, double dt_scale,
                              int move, void *stream);
 
-/* nsteps full PIC cycles (a1-a8) from the leapfrog state (x^n, v^{n-1/2}),
+/* nsteps full PIC cycles in the order of the paper's two-stream driver
+ * ("Example setup and implementation": full push, move with periodic
+ * boundaries, then the field update of deposit and Poisson solve), with the
+ * energy diagnostics its "Results and validation" section tracks, from the
+ * leapfrog state (x^n, v^{n-1/2}),
  * bucket-ordered with a valid bucket_start, and the field E^n:
  *   gather E^n -> Boris -> move -> deposit rho^{n+1} -> counting sort ->
  *   Poisson -> E^{n+1}.
@@ -245,6 +260,19 @@ apic_status apic_gather_push(apic_ctx *ctx, apic_particles *p, const void *E, do
  * order. Workspace contents are not relied on across calls. */
 apic_status apic_step(apic_ctx *ctx, apic_particles *p, void *rho, double *E, float *E32, int nsteps,
                       double *diag, void *ws, void *stream);
+
+/* apic_step with a second, caller-owned particle buffer q (the same arrays
+ * as p, bucket_start included, none shared with p) in place of the
+ * workspace's: the steps alternate between p and q, and the call ends with
+ * the state in q when nsteps is odd (*in_q = 1 [host]) and in p when it is
+ * even (*in_q = 0), where apic_step copies an odd count's result back into p.
+ * Saves that copy, a read and a write of every particle array, for callers
+ * that step a few steps at a time (diagnostics between calls): the next
+ * call passes the two buffers the other way round. The buffer that does not
+ * hold the state is left with unspecified contents; q's content on entry is
+ * not read. perm and the outputs are as in apic_step (perm from p). */
+apic_status apic_step_pair(apic_ctx *ctx, apic_particles *p, apic_particles *q, void *rho, double *E, float *E32,
+                           int nsteps, double *diag, int *in_q, void *ws, void *stream);
 
 /* apic_step without a workspace argument, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, harnesses
@@ -281,17 +309,19 @@ apic_status apic_profile_read(apic_ctx *ctx, double ms[4], int *steps);
 apic_status apic_profile_phases(apic_ctx *ctx, int all);
 
 /* Convert a physical FP64 state to the context's particle representation (any
- * order): x, y [dev, double, n] positions (y NULL in 1D), vx, vy, vz [dev,
- * double, n] velocities (NULL beyond vdim). FP64 path: copies into p->x, p->y,
- * p->vx.. ; mixed path: p->cell = floor(x/dx) (mod nx; packed with iy in 2D),
- * p->ox = binary32(x/dx - floor(x/dx)), an offset that rounds to 1 moving to
- * the next cell with offset 0, velocities rounded to binary32. Positions must
- * lie in [0, L] (L is node 0); a coordinate outside raises APIC_EDOMAIN at the
- * next apic_sync_status. p->bucket_start and p->perm are not touched. */
-apic_status apic_import_state(apic_ctx *ctx, const double *x, const double *y, const double *vx, const double *vy,
-                              const double *vz, apic_particles *p, void *stream);
+ * order): x, y, z [dev, double, n] positions (y NULL in 1D, z NULL below 3D),
+ * vx, vy, vz [dev, double, n] velocities (NULL beyond vdim). FP64 path: copies
+ * into p->x, p->y, p->z, p->vx.. ; mixed path: p->cell = floor(x/dx) (mod nx;
+ * packed with iy in 2D, with iy and iz in 3D), p->ox = binary32(x/dx -
+ * floor(x/dx)), an offset that rounds to 1 moving to the next cell with offset
+ * 0, velocities rounded to binary32. Positions must lie in [0, L] (L is node
+ * 0); a coordinate outside raises APIC_EDOMAIN at the next apic_sync_status.
+ * Periodic contexts only (APIC_EUNSUPPORTED with walls). p->bucket_start and
+ * p->perm are not touched. */
+apic_status apic_import_state(apic_ctx *ctx, const double *x, const double *y, const double *z, const double *vx,
+                              const double *vy, const double *vz, apic_particles *p, void *stream);
 
-/* ---- adjoint (a10) ----------------------------------------------------------
+/* ---- adjoint ----------------------------------------------------------------
  * Gradient of the final field energy W = 1/2 sum_j |E_j^T|^2 dV of an
  * nsteps-step run with respect to every particle's initial position and
  * velocity (reverse-mode derivative of the discrete cycle; the paper has no
@@ -304,14 +334,16 @@ apic_status apic_import_state(apic_ctx *ctx, const double *x, const double *y, c
  * of lam_rho), sort (each step's permutation inverted). The derivative of the
  * CIC hat is its slope inside the particle's cell.
  *
- * With the Higuera-Cary advance (2D3V, state u = gamma v) the reverse of the
+ * With the Higuera-Cary advance (vdim = 3, state u = gamma v) the reverse of the
  * advance is the transpose of its Jacobian at the step's own velocity (the
  * advance is nonlinear in u through gamma), and the move's is
  * lam_u += dt (I - u u^T / (c^2 gamma^2)) lam_x / gamma; lam_vx, lam_vy and
  * lam_vz are then derivatives with respect to u^0.
  *
- * The adjoint entry points (and apic_import_state) cover 1D and 2D plasmas;
- * a 3D context returns APIC_EUNSUPPORTED.
+ * In 3D (trilinear weights, the 7-point solve) the same steps run with a
+ * third position component and E_z kicking v_z; lam_Ep is then scattered to
+ * the grid with global FP64 atomics rather than through per-tile LDS. The
+ * electromagnetic model and absorbing walls return APIC_EUNSUPPORTED.
  *
  * Step checkpointing: apic_adjoint_forward stores the state every `stride`
  * steps in the caller's checkpoint buffer; apic_step_adjoint recomputes one
@@ -338,18 +370,20 @@ apic_status apic_adjoint_forward(apic_ctx *ctx, const apic_particles *p0, int ns
 /* Reverse sweep over the checkpoints of the last apic_adjoint_forward with the
  * same nsteps and stride (ws contents between the two calls are not needed).
  * Writes seed * dW/d(state at t = 0) in the input order of p0, as FP64:
- * lam_x, lam_y [dev, n] (lam_y NULL in 1D) with respect to positions,
+ * lam_x, lam_y, lam_z [dev, n] (lam_y NULL in 1D, lam_z NULL below 3D) with
+ * respect to positions,
  * lam_vx, lam_vy, lam_vz [dev, n] (NULL beyond vdim) with respect to v^0.
  * grad_delta0 [dev, double, 1] (NULL = not computed): seed * dW/d delta0 for
  * the mode seeding of the paper's two-stream example ("Example setup and
  * implementation": every particle displaced by delta0 k/|k|^2 sin(k.x_u)),
  * i.e. sum_p lam_x[p] dx_ddelta0[p] + lam_y[p] dy_ddelta0[p], with
  * dx_ddelta0, dy_ddelta0 [dev, double, n] the derivative of each initial
- * position with respect to delta0 in the same order (dy NULL in 1D; the
+ * position with respect to delta0 in the same order (dy NULL in 1D; the mode
+ * has no z component, so a 3D seeding moves x and y only; the
  * caller knows its unperturbed positions x_u, the library does not); summed
  * in a fixed order on the device. */
 apic_status apic_step_adjoint(apic_ctx *ctx, const void *ckpt, int nsteps, int stride, double seed, double *lam_x,
-                              double *lam_y, double *lam_vx, double *lam_vy, double *lam_vz,
+                              double *lam_y, double *lam_z, double *lam_vx, double *lam_vy, double *lam_vz,
                               const double *dx_ddelta0, const double *dy_ddelta0, double *grad_delta0, void *ws,
                               void *stream);
 
@@ -439,8 +473,11 @@ apic_status apic_em_gather_push(apic_ctx *ctx, apic_particles *p, const double *
 apic_status apic_em_step(apic_ctx *ctx, apic_particles *p, double *F, double *J, int nsteps, double *diag,
                          void *ws, void *stream);
 
-/* ---- batched replicas (a9) ------------------------------------------------
- * Many independent 1D1V periodic electrostatic plasmas ("replicas") with
+/* ---- batched replicas -------------------------------------------------------
+ * The paper's modules serve any composition of small and large runs ("Core
+ * functionality": components assembled at different levels of complexity);
+ * this form fills the GPU with many small ones. Many independent 1D1V
+ * periodic electrostatic plasmas ("replicas") with
  * their own grid and particle counts, advanced together. Each replica is the
  * single-plasma mixed-precision cycle (binary32 push of cell + offset
  * positions, int64 fixed-point CIC deposit with S = 32, FP64 1D field solve)
@@ -503,17 +540,20 @@ const char *apic_batch_last_error(const apic_batch *b);
  * same shape returns the cached pick with *ms_per_step = -1 (may be NULL).
  * Returns APIC_EINVAL for bad arguments, APIC_EHIP if no candidate ran.
  *
- * apic_autotune_tiles: sort-bucket tile (tile_x, tile_y) for apic_create (1D
- * and 2D; a 3D descriptor returns APIC_EUNSUPPORTED and keeps the default), over
- *   powers of two 4x4 .. 32x32 (2D) or 8 .. 1024 nodes (1D) plus the default
- *   (0, 0). p: unsorted or sorted particles as for apic_sort_by_cell (n > 0);
- *   bucket_start and perm are ignored. Cache key: dim, vdim, nx, ny,
- *   precision and floor(log2(particles per cell)).
+ * apic_autotune_tiles: sort-bucket tile (tile_x, tile_y, and tile_z in 3D) for
+ *   apic_create, over powers of two 4x4 .. 32x32 (2D), 4x4x4 .. 16x16x8 (3D;
+ *   shapes whose tiles do not fit a workgroup's LDS are skipped) or 8 .. 1024
+ *   nodes (1D), plus the default (0, 0, 0). tile_z [host] may be NULL below
+ *   3D (it is written 0 there). p: unsorted or sorted particles as for
+ *   apic_sort_by_cell (n > 0); bucket_start and perm are ignored. Periodic
+ *   electrostatic plasmas (walls and the electromagnetic model return
+ *   APIC_EUNSUPPORTED). Cache key: dim, vdim, nx, ny, nz, precision,
+ *   floor(log2(particles per cell)) and the velocity advance.
  * apic_batch_autotune_chunk: work-item size (particles per item, 1024 ..
  *   65535) for apic_batch_create. st: the packed initial state (cell, ox, vx;
  *   E is ignored). Cache key: total particles and replica count. */
 apic_status apic_autotune_tiles(const apic_grid_desc *desc, const apic_particles *p, int nsteps, int *tile_x,
-                                int *tile_y, double *ms_per_step, void *stream);
+                                int *tile_y, int *tile_z, double *ms_per_step, void *stream);
 apic_status apic_batch_autotune_chunk(const apic_replica *reps, int nrep, double dt, double qm, double rho_ion,
                                       const apic_batch_state *st, int nsteps, int *chunk, double *ms_per_step,
                                       void *stream);

@@ -67,7 +67,7 @@ EXPORTS = ["apic_create", "apic_destroy", "apic_workspace_size", "apic_num_bucke
            "apic_batch_last_error", "apic_autotune_tiles", "apic_batch_autotune_chunk",
            "apic_import_state", "apic_adjoint_sizes", "apic_adjoint_forward", "apic_step_adjoint",
            "apic_em_init_fields", "apic_em_gather_push", "apic_em_step", "apic_charge_exact", "apic_q_macro",
-           "apic_step_static"]
+           "apic_step_static", "apic_step_pair"]
 
 _lib = None
 
@@ -109,16 +109,17 @@ def load_library(path: str = LIB_PATH):
         "apic_batch_step": ([vp, P(BatchStateC), cint, vp, vp, vp, vp, cint], cint),
         "apic_batch_sync_status": ([vp, vp], cint),
         "apic_batch_last_error": ([vp], ctypes.c_char_p),
-        "apic_import_state": ([vp, vp, vp, vp, vp, vp, P(ParticlesC), vp], cint),
+        "apic_import_state": ([vp, vp, vp, vp, vp, vp, vp, P(ParticlesC), vp], cint),
         "apic_adjoint_sizes": ([vp, cint, cint, P(ctypes.c_size_t), P(ctypes.c_size_t)], cint),
         "apic_adjoint_forward": ([vp, P(ParticlesC), cint, cint, vp, vp, vp, vp, vp], cint),
-        "apic_step_adjoint": ([vp, vp, cint, cint, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp], cint),
-        "apic_autotune_tiles": ([P(GridDesc), P(ParticlesC), cint, P(cint), P(cint), P(dbl), vp], cint),
+        "apic_step_adjoint": ([vp, vp, cint, cint, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp], cint),
+        "apic_autotune_tiles": ([P(GridDesc), P(ParticlesC), cint, P(cint), P(cint), P(cint), P(dbl), vp], cint),
         "apic_em_init_fields": ([vp, P(ParticlesC), vp, vp, vp], cint),
         "apic_em_gather_push": ([vp, P(ParticlesC), vp, dbl, cint, vp], cint),
         "apic_em_step": ([vp, P(ParticlesC), vp, vp, cint, vp, vp, vp], cint),
         "apic_charge_exact": ([vp, P(i64), P(i64), vp], cint),
         "apic_step_static": ([vp, P(ParticlesC), vp, vp, vp, cint, vp, vp], cint),
+        "apic_step_pair": ([vp, P(ParticlesC), P(ParticlesC), vp, vp, vp, cint, vp, P(cint), vp, vp], cint),
         "apic_batch_autotune_chunk": ([P(ReplicaC), cint, dbl, dbl, dbl, P(BatchStateC), cint, P(cint), P(dbl), vp],
                                       cint),
     }
@@ -272,24 +273,27 @@ class Context:
 
     def autotune_tiles(self, parts: "Particles", nsteps: int = 5):
         """Fastest sort-bucket tile for this plasma, timed on a copy of
-        `parts` (apic_autotune_tiles). Returns (tile_x, tile_y, ms_per_step);
+        `parts` (apic_autotune_tiles). Returns (tile, ms_per_step) with tile
+        (tile_x, tile_y) below 3D and (tile_x, tile_y, tile_z) in 3D;
         ms_per_step is -1 when the pick came from the process cache."""
         s = parts.struct()
-        tx, ty, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        tx, ty, tz, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         st = self.L.apic_autotune_tiles(ctypes.byref(self.desc), ctypes.byref(s), int(nsteps), ctypes.byref(tx),
-                                        ctypes.byref(ty), ctypes.byref(ms), _stream())
+                                        ctypes.byref(ty), ctypes.byref(tz), ctypes.byref(ms), _stream())
         if st != 0:
             raise ApicError(st, "apic_autotune_tiles found no runnable tile")
-        return int(tx.value), int(ty.value), float(ms.value)
+        tile = (int(tx.value), int(ty.value)) + ((int(tz.value),) if self.dim == 3 else ())
+        return tile, float(ms.value)
 
-    def import_state(self, parts: "Particles", x, y, vx, vy=None, vz=None):
+    def import_state(self, parts: "Particles", x, y, vx, vy=None, vz=None, z=None):
         """Physical FP64 device state -> this context's representation (apic_import_state)."""
         t = self.torch
-        for a, name, on in ((x, "x", True), (y, "y", self.dim >= 2), (vx, "vx", True), (vy, "vy", self.vdim >= 2),
-                            (vz, "vz", self.vdim >= 3)):
+        for a, name, on in ((x, "x", True), (y, "y", self.dim >= 2), (z, "z", self.dim == 3), (vx, "vx", True),
+                            (vy, "vy", self.vdim >= 2), (vz, "vz", self.vdim >= 3)):
             _need(a, t.float64, self.n, name, optional=not on)
         s = parts.struct()
         self._check(self.L.apic_import_state(self.h, ctypes.c_void_p(_ptr(x)), ctypes.c_void_p(_ptr(y)),
+                                             ctypes.c_void_p(_ptr(z)),
                                              ctypes.c_void_p(_ptr(vx)), ctypes.c_void_p(_ptr(vy)),
                                              ctypes.c_void_p(_ptr(vz)), ctypes.byref(s), _stream()))
 
@@ -312,20 +316,21 @@ class Context:
                                                 _stream()))
 
     def step_adjoint(self, ckpt, nsteps, stride, ws, lam_x, lam_y, lam_vx, lam_vy=None, lam_vz=None, seed=1.0,
-                     dx_ddelta0=None, dy_ddelta0=None, grad_delta0=None):
+                     dx_ddelta0=None, dy_ddelta0=None, grad_delta0=None, lam_z=None):
         t = self.torch
         ck, wb = self.adjoint_sizes(nsteps, stride)
         _need(ckpt, t.uint8, ck, "ckpt")
         _need(ws, t.uint8, wb, "ws")
-        for a, name, on in ((lam_x, "lam_x", True), (lam_y, "lam_y", self.dim == 2), (lam_vx, "lam_vx", True),
-                            (lam_vy, "lam_vy", self.vdim >= 2), (lam_vz, "lam_vz", self.vdim >= 3),
+        for a, name, on in ((lam_x, "lam_x", True), (lam_y, "lam_y", self.dim >= 2), (lam_z, "lam_z", self.dim == 3),
+                            (lam_vx, "lam_vx", True), (lam_vy, "lam_vy", self.vdim >= 2),
+                            (lam_vz, "lam_vz", self.vdim >= 3),
                             (dx_ddelta0, "dx_ddelta0", grad_delta0 is not None),
-                            (dy_ddelta0, "dy_ddelta0", grad_delta0 is not None and self.dim == 2)):
+                            (dy_ddelta0, "dy_ddelta0", grad_delta0 is not None and self.dim >= 2)):
             _need(a, t.float64, self.n, name, optional=not on)
         _need(grad_delta0, t.float64, 1, "grad_delta0", optional=True)
         self._check(self.L.apic_step_adjoint(self.h, ctypes.c_void_p(ckpt.data_ptr()), int(nsteps), int(stride),
                                              float(seed), ctypes.c_void_p(_ptr(lam_x)), ctypes.c_void_p(_ptr(lam_y)),
-                                             ctypes.c_void_p(_ptr(lam_vx)), ctypes.c_void_p(_ptr(lam_vy)),
+                                             ctypes.c_void_p(_ptr(lam_z)), ctypes.c_void_p(_ptr(lam_vx)), ctypes.c_void_p(_ptr(lam_vy)),
                                              ctypes.c_void_p(_ptr(lam_vz)), ctypes.c_void_p(_ptr(dx_ddelta0)),
                                              ctypes.c_void_p(_ptr(dy_ddelta0)), ctypes.c_void_p(_ptr(grad_delta0)),
                                              ctypes.c_void_p(ws.data_ptr()), _stream()))
@@ -368,6 +373,22 @@ class Context:
                                      ctypes.c_void_p(_ptr(E32)), int(nsteps), ctypes.c_void_p(_ptr(diag)),
                                      ctypes.c_void_p(self.ws.data_ptr()), _stream()))
 
+
+    def step_pair(self, parts: "Particles", other: "Particles", E, E32, nsteps, diag=None, rho=None, perm=None):
+        """nsteps cycles alternating between two particle buffers
+        (apic_step_pair): returns the buffer that holds the state afterwards
+        (``other`` for an odd count), with no copy back."""
+        self._check_step(E, E32, nsteps, diag, rho, perm)
+        if other is parts:
+            raise ApicError(-1, "step_pair needs two distinct particle buffers")
+        s = parts.struct(perm=perm)
+        q = other.struct()
+        in_q = ctypes.c_int(0)
+        self._check(self.L.apic_step_pair(self.h, ctypes.byref(s), ctypes.byref(q), ctypes.c_void_p(_ptr(rho)),
+                                          ctypes.c_void_p(E.data_ptr()), ctypes.c_void_p(_ptr(E32)), int(nsteps),
+                                          ctypes.c_void_p(_ptr(diag)), ctypes.byref(in_q),
+                                          ctypes.c_void_p(self.ws.data_ptr()), _stream()))
+        return other if in_q.value else parts
 
     def step_static(self, parts: "Particles", E, E32, nsteps, diag=None, rho=None, perm=None):
         """apic_step on the library's fixed device workspace (apic_step_static:

@@ -63,8 +63,8 @@ inline int nblocks(int64_t n, int cap = 8192) {
 // Positions of one time level (structure of arrays of the path's layout).
 struct PosP {
     const int32_t *cell;
-    const float *ox, *oy;
-    const double *x, *y;
+    const float *ox, *oy, *oz;
+    const double *x, *y, *z;
 };
 
 template <typename R>
@@ -90,7 +90,7 @@ struct AdjP {
     // final output (level 0): out[id0[i]] = lam of particle i
     int final_out;
     const int32_t *id0;
-    double *out_x, *out_y, *out_vx, *out_vy, *out_vz;
+    double *out_x, *out_y, *out_z, *out_vx, *out_vy, *out_vz;
     // coefficients
     R dt, cq;               // dt; Q/dV
     R a, t, s;              // Boris of a full step (t = tau = a bz for Higuera-Cary)
@@ -104,31 +104,46 @@ struct AdjP {
 };
 
 template <bool MIX, int DIM>
-__device__ __forceinline__ bool load_pos(const PosP &p, int64_t i, const Geo &g, int &ix, int &iy,
-                                         typename RealOf<MIX>::T &fx, typename RealOf<MIX>::T &fy) {
+__device__ __forceinline__ bool load_pos(const PosP &p, int64_t i, const Geo &g, int &ix, int &iy, int &iz,
+                                         typename RealOf<MIX>::T &fx, typename RealOf<MIX>::T &fy,
+                                         typename RealOf<MIX>::T &fz) {
     using R = typename RealOf<MIX>::T;
     bool ok = true;
+    iz = 0;
+    fz = R(0);
     if constexpr (MIX) {
         const int32_t c = p.cell[i];
-        ix = (DIM == 2) ? (c & 0xFFFF) : c;
-        iy = (DIM == 2) ? (c >> 16) : 0;
+        if constexpr (DIM == 3) {
+            ix = c & 0x3FF;
+            iy = (c >> 10) & 0x3FF;
+            iz = (c >> 20) & 0x3FF;
+            fz = p.oz[i];
+        } else {
+            ix = (DIM == 2) ? (c & 0xFFFF) : c;
+            iy = (DIM == 2) ? (c >> 16) : 0;
+        }
         fx = p.ox[i];
-        fy = (DIM == 2) ? p.oy[i] : 0.0f;
-        ok = ix >= 0 && ix < g.nx && iy >= 0 && iy < g.ny && fx >= 0.0f && fx < 1.0f && fy >= 0.0f && fy < 1.0f;
+        fy = (DIM >= 2) ? p.oy[i] : 0.0f;
+        ok = ix >= 0 && ix < g.nx && iy >= 0 && iy < g.ny && iz >= 0 && iz < g.nz && fx >= 0.0f && fx < 1.0f &&
+             fy >= 0.0f && fy < 1.0f && fz >= 0.0f && fz < 1.0f;
     } else {
         double f;
         ok = cell_f64(p.x[i], g.inv_dx, g.nx, ix, f);
         fx = (R)f;
         iy = 0;
         fy = R(0);
-        if constexpr (DIM == 2) {
+        if constexpr (DIM >= 2) {
             ok = cell_f64(p.y[i], g.inv_dy, g.ny, iy, f) && ok;
             fy = (R)f;
         }
+        if constexpr (DIM == 3) {
+            ok = cell_f64(p.z[i], g.inv_dz, g.nz, iz, f) && ok;
+            fz = (R)f;
+        }
     }
     if (!ok) {
-        ix = iy = 0;
-        fx = fy = R(0);
+        ix = iy = iz = 0;
+        fx = fy = fz = R(0);
     }
     return ok;
 }
@@ -151,15 +166,17 @@ __device__ __forceinline__ void boris_adj(R &gx, R &gy, R a, R t, R s, R &ex, R 
     }
 }
 
-// Higuera-Cary adjoint of one advance u1 = R(t) m + aE, m = u0 + aE (E_z = 0):
-// l (lam of u1) -> lam of u0 in place; returns lam_Ep (x, y) in ex, ey.
+// Higuera-Cary adjoint of one advance u1 = R(t) m + aE, m = u0 + aE:
+// l (lam of u1) -> lam of u0 in place; returns lam_Ep in ex, ey, ez (ez is
+// unused in 2D, where E_z = 0).
 //   R = [[C, S], [-S, C]] on (x, y), identity on z, C = (1-t^2)/(1+t^2),
 //   S = 2t/(1+t^2); t = tau / gamma+, gamma+^2 = (sigma + D)/2,
 //   sigma = 1 + |m|^2/c^2 - tau^2, D = sqrt(sigma^2 + 4 tau^2 (1 + mz^2/c^2));
 //   dt/dm = -t/(2 gamma+^2) d(gamma+^2)/dm,
 //   d(gamma+^2)/dm = (m (1 + sigma/D) + 2 tau^2 mz z / D) / c^2.
 template <typename R>
-__device__ __forceinline__ void hc_adj(R mx, R my, R mz, R a, R tau, R ic2, R &lx, R &ly, R &lz, R &ex, R &ey) {
+__device__ __forceinline__ void hc_adj(R mx, R my, R mz, R a, R tau, R ic2, R &lx, R &ly, R &lz, R &ex, R &ey,
+                                       R &ez) {
     const R g2 = R(1) + ((mx * mx + my * my) + mz * mz) * ic2;
     const R sig = g2 - tau * tau;
     const R us = mz * tau;
@@ -177,6 +194,7 @@ __device__ __forceinline__ void hc_adj(R mx, R my, R mz, R a, R tau, R ic2, R &l
     const R oz = lz + f * (k * mz + R(2) * tau * tau * mz / D);
     ex = a * (ox + lx);
     ey = a * (oy + ly);
+    ez = a * (oz + lz);
     lx = ox;
     ly = oy;
     lz = oz;
@@ -194,8 +212,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>:
     using R = typename RealOf<MIX>::T;
     const Geo &g = P.g;
     const int64_t n = P.n;
-    const int G = g.nx * g.ny;
-    const R idx = (R)g.inv_dx, idy = (R)g.inv_dy;
+    const int G = g.nx * g.ny * g.nz;
+    const R idx = (R)g.inv_dx, idy = (R)g.inv_dy, idz = (R)g.inv_dz;
     // lam_Ep scattered at x^{n-1}: into the block's LDS tile when the level's
     // bucket table is given and the node lies in the tile's window, else
     // straight to global memory
@@ -211,16 +229,171 @@ __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>:
             if (dx < 0) dx += g.nx;
             if (dy < 0) dy += g.ny;
             if (dx < tw && dy < th) {
-                atomicAdd(&sT[(comp * th + dy) * tw + dx], v);
+                // through an LDS-typed pointer: ds_add_f64 with no flat
+                // address-space test (the generic form of this add has
+                // crashed instruction selection for gfx950)
+                __hip_atomic_fetch_add((__attribute__((address_space(3))) double *)&sT[(comp * th + dy) * tw + dx], v,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 return;
             }
         }
         unsafeAtomicAdd(&P.lE_prev[comp * G + gy * g.nx + gx], v);
     };
+    // 3D: the cycle with trilinear weights, E_z and the z motion; lam_Ep is
+    // scattered with global atomics (no LDS tile)
+    auto body3 = [&](int64_t i) {
+        int ix, iy, iz;
+        R fx, fy, fz;
+        if (!load_pos<MIX, 3>(P.pos, i, g, ix, iy, iz, fx, fy, fz)) raise_err(P.err, ERR_DOMAIN);
+        R lx = R(0), ly = R(0), lz = R(0), lex = R(0), ley = R(0), lez = R(0), lvx = R(0), lvy = R(0), lvz = R(0);
+        if (!P.terminal) {
+            lx = P.lxp_in[i];
+            ly = P.lxp_in[n + i];
+            lz = P.lxp_in[2 * n + i];
+            lex = P.lep_in[i];
+            ley = P.lep_in[n + i];
+            lez = P.lep_in[2 * n + i];
+            lvx = P.lv_in[i];
+            lvy = P.lv_in[n + i];
+            lvz = P.lv_in[2 * n + i];
+        }
+        // deposit and gather adjoints at level n: the slope of the trilinear
+        // hat applied to g = E . lam_Ep + (Q/dV) lam_rho over the cell
+        {
+            const int xs[2] = {ix, ix + 1 >= g.nx ? 0 : ix + 1};
+            const int ys[2] = {iy, iy + 1 >= g.ny ? 0 : iy + 1};
+            const int zs[2] = {iz, iz + 1 >= g.nz ? 0 : iz + 1};
+            R gv[2][2][2];
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+                for (int b2 = 0; b2 < 2; ++b2)
+#pragma unroll
+                    for (int a2 = 0; a2 < 2; ++a2) {
+                        const int m = (zs[c2] * g.ny + ys[b2]) * g.nx + xs[a2];
+                        gv[c2][b2][a2] = (R)P.E[m] * lex + (R)P.E[G + m] * ley + (R)P.E[2 * G + m] * lez +
+                                         P.cq * (R)P.lrho[m];
+                    }
+            const R wx[2] = {R(1) - fx, fx}, wy[2] = {R(1) - fy, fy}, wz[2] = {R(1) - fz, fz};
+            R gx = R(0), gy = R(0), gz = R(0);
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 2; ++v) {
+                    gx += wy[u] * wz[v] * (gv[v][u][1] - gv[v][u][0]);
+                    gy += wx[u] * wz[v] * (gv[v][1][u] - gv[v][0][u]);
+                    gz += wx[u] * wy[v] * (gv[1][v][u] - gv[0][v][u]);
+                }
+            lx += gx * idx;
+            ly += gy * idy;
+            lz += gz * idz;
+        }
+        if (P.final_out) {
+            const int32_t o = P.id0[i];
+            if ((uint32_t)o >= (uint32_t)n) {
+                raise_err(P.err, ERR_ORDER);
+                return;
+            }
+            P.out_x[o] = (double)lx;
+            P.out_y[o] = (double)ly;
+            P.out_z[o] = (double)lz;
+            P.out_vx[o] = (double)lvx;
+            P.out_vy[o] = (double)lvy;
+            P.out_vz[o] = (double)lvz;
+            return;
+        }
+        if (!P.back) return;
+        const int32_t j = P.perm[i];
+        if ((uint32_t)j >= (uint32_t)n) {
+            raise_err(P.err, ERR_ORDER);
+            return;
+        }
+        int jx, jy, jz;
+        R qx, qy, qz;
+        if (!load_pos<MIX, 3>(P.prev, j, g, jx, jy, jz, qx, qy, qz)) raise_err(P.err, ERR_DOMAIN);
+        const int pxs[2] = {jx, jx + 1 >= g.nx ? 0 : jx + 1};
+        const int pys[2] = {jy, jy + 1 >= g.ny ? 0 : jy + 1};
+        const int pzs[2] = {jz, jz + 1 >= g.nz ? 0 : jz + 1};
+        const R vx2[2] = {R(1) - qx, qx}, vy2[2] = {R(1) - qy, qy}, vz2[2] = {R(1) - qz, qz};
+        R gx, gy, gz, ex, ey, ez;
+        if constexpr (HC) {
+            // re-run the advance from the level-(n-1) velocity in E_p^{n-1}
+            R epx = R(0), epy = R(0), epz = R(0);
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+                for (int b2 = 0; b2 < 2; ++b2)
+#pragma unroll
+                    for (int a2 = 0; a2 < 2; ++a2) {
+                        const int m = (pzs[c2] * g.ny + pys[b2]) * g.nx + pxs[a2];
+                        const R w = (vx2[a2] * vy2[b2]) * vz2[c2];
+                        epx += w * (R)P.Eprev[m];
+                        epy += w * (R)P.Eprev[G + m];
+                        epz += w * (R)P.Eprev[2 * G + m];
+                    }
+            const R u0x = P.vprev[j], u0y = P.vprev[n + j], u0z = P.vprev[2 * n + j];
+            R ux = u0x, uy = u0y, uz = u0z;
+            higuera_cary<R>(ux, uy, uz, epx, epy, epz, P.a, P.t, P.ic2);
+            // move x += (u / gamma) dt on all three axes: lam_u1 = lam_v + dt M(u1) lam_x
+            const R ig = R(1) / lorentz<R>(ux, uy, uz, P.ic2);
+            const R cf = P.ic2 * ((ux * lx + uy * ly) + uz * lz) * ig * ig;
+            gx = lvx + P.dt * ig * (lx - ux * cf);
+            gy = lvy + P.dt * ig * (ly - uy * cf);
+            gz = lvz + P.dt * ig * (lz - uz * cf);
+            hc_adj<R>(u0x + P.a * epx, u0y + P.a * epy, u0z + P.a * epz, P.a, P.t, P.ic2, gx, gy, gz, ex, ey, ez);
+            if (P.init) {
+                R hx = u0x, hy = u0y, hz = u0z;
+                higuera_cary<R>(hx, hy, hz, epx, epy, epz, -P.ah, -P.th, P.ic2);
+                R fx2, fy2, fz2;
+                hc_adj<R>(hx + P.ah * epx, hy + P.ah * epy, hz + P.ah * epz, P.ah, P.th, P.ic2, gx, gy, gz, fx2, fy2,
+                          fz2);
+                ex += fx2;
+                ey += fy2;
+                ez += fz2;
+            }
+        } else {
+            // move, then Boris: the rotation about z acts on (x, y); v_z takes
+            // the two half kicks a E_z, so lam_Ez = 2a lam_vz
+            gx = lvx + P.dt * lx;
+            gy = lvy + P.dt * ly;
+            gz = lvz + P.dt * lz;
+            boris_adj<R, 3>(gx, gy, P.a, P.t, P.s, ex, ey);
+            ez = R(2) * P.a * gz;
+            if (P.init) {
+                R hx, hy;
+                boris_adj<R, 3>(gx, gy, P.ah, P.th, P.sh, hx, hy);
+                ex += hx;
+                ey += hy;
+                ez += R(2) * P.ah * gz;
+            }
+        }
+        // gather adjoint at level n-1: W_j(x^{n-1}) lam_Ep into lam_E
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+            for (int b2 = 0; b2 < 2; ++b2)
+#pragma unroll
+                for (int a2 = 0; a2 < 2; ++a2) {
+                    const int m = (pzs[c2] * g.ny + pys[b2]) * g.nx + pxs[a2];
+                    const R w = (vx2[a2] * vy2[b2]) * vz2[c2];
+                    unsafeAtomicAdd(&P.lE_prev[m], (double)(w * ex));
+                    unsafeAtomicAdd(&P.lE_prev[G + m], (double)(w * ey));
+                    unsafeAtomicAdd(&P.lE_prev[2 * G + m], (double)(w * ez));
+                }
+        P.lxp_out[j] = lx;
+        P.lxp_out[n + j] = ly;
+        P.lxp_out[2 * n + j] = lz;
+        P.lep_out[j] = ex;
+        P.lep_out[n + j] = ey;
+        P.lep_out[2 * n + j] = ez;
+        P.lv_out[j] = gx;
+        P.lv_out[n + j] = gy;
+        P.lv_out[2 * n + j] = gz;
+    };
     auto body = [&](int64_t i) {
-        int ix, iy;
-        R fx, fy;
-        if (!load_pos<MIX, DIM>(P.pos, i, g, ix, iy, fx, fy)) raise_err(P.err, ERR_DOMAIN);
+        int ix, iy, iz_;
+        R fx, fy, fz_;
+        if (!load_pos<MIX, DIM>(P.pos, i, g, ix, iy, iz_, fx, fy, fz_)) raise_err(P.err, ERR_DOMAIN);
         R lx = R(0), ly = R(0), lex = R(0), ley = R(0), lvx = R(0), lvy = R(0), lvz = R(0);
         if (!P.terminal) {
             lx = P.lxp_in[i];
@@ -267,7 +440,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>:
         }
         if (!P.back) return;
         if constexpr (HC) {
-            static_assert(DIM == 2 && VDIM == 3, "the Higuera-Cary adjoint is 2D3V");
+            static_assert(VDIM == 3, "the Higuera-Cary adjoint needs three velocity components");
             // reverse of the step n-1 -> n: re-run the advance from the
             // level-(n-1) velocity, then the move and advance adjoints
             const int32_t j = P.perm[i];
@@ -275,9 +448,9 @@ __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>:
                 raise_err(P.err, ERR_ORDER);
                 return;
             }
-            int jx, jy;
-            R qx, qy;
-            if (!load_pos<MIX, DIM>(P.prev, j, g, jx, jy, qx, qy)) raise_err(P.err, ERR_DOMAIN);
+            int jx, jy, jz_;
+            R qx, qy, qz_;
+            if (!load_pos<MIX, DIM>(P.prev, j, g, jx, jy, jz_, qx, qy, qz_)) raise_err(P.err, ERR_DOMAIN);
             int jxp = jx + 1, jyp = jy + 1;
             if (jxp >= g.nx) jxp = 0;
             if (jyp >= g.ny) jyp = 0;
@@ -297,14 +470,14 @@ __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>:
             R gx = lvx + P.dt * ig * (lx - ux * cf);
             R gy = lvy + P.dt * ig * (ly - uy * cf);
             R gz = lvz - P.dt * ig * (uz * cf);
-            R ex, ey;
-            hc_adj<R>(u0x + P.a * epx, u0y + P.a * epy, u0z, P.a, P.t, P.ic2, gx, gy, gz, ex, ey);
+            R ex, ey, ez_unused;
+            hc_adj<R>(u0x + P.a * epx, u0y + P.a * epy, u0z, P.a, P.t, P.ic2, gx, gy, gz, ex, ey, ez_unused);
             if (P.init) {
                 // v^{-1/2} = advance(u^0, E_p^0, -dt/2); u^0 = advance(v^{-1/2}, E_p^0, +dt/2)
                 R hx = u0x, hy = u0y, hz = u0z;
                 higuera_cary<R>(hx, hy, hz, epx, epy, R(0), -P.ah, -P.th, P.ic2);
-                R fx, fy;
-                hc_adj<R>(hx + P.ah * epx, hy + P.ah * epy, hz, P.ah, P.th, P.ic2, gx, gy, gz, fx, fy);
+                R fx, fy, fz_unused;
+                hc_adj<R>(hx + P.ah * epx, hy + P.ah * epy, hz, P.ah, P.th, P.ic2, gx, gy, gz, fx, fy, fz_unused);
                 ex += fx;
                 ey += fy;
             }
@@ -342,9 +515,9 @@ __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>:
             raise_err(P.err, ERR_ORDER);
             return;
         }
-        int jx, jy;
-        R qx, qy;
-        if (!load_pos<MIX, DIM>(P.prev, j, g, jx, jy, qx, qy)) raise_err(P.err, ERR_DOMAIN);
+        int jx, jy, jz_;
+        R qx, qy, qz_;
+        if (!load_pos<MIX, DIM>(P.prev, j, g, jx, jy, jz_, qx, qy, qz_)) raise_err(P.err, ERR_DOMAIN);
         // gather adjoint at level n-1: scatter W_j(x^{n-1}) lam_Ep into lam_E
         int jxp = jx + 1;
         if (jxp >= g.nx) jxp = 0;
@@ -375,6 +548,11 @@ __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>:
         if constexpr (VDIM >= 2) P.lv_out[n + j] = gy;
         if constexpr (VDIM >= 3) P.lv_out[2 * n + j] = lvz;   // no E_z and no z motion
     };
+    if constexpr (DIM == 3) {
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+            body3(i);
+        return;
+    } else {
     if (!tiled) {
         for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
             body(i);
@@ -412,18 +590,22 @@ __global__ void __launch_bounds__(kBlock) k_adj_level(AdjP<typename RealOf<MIX>:
         }
         __syncthreads();
     }
+    }
 }
 
 // Physical FP64 state -> the path's representation (see apic_import_state).
 template <bool MIX, int DIM, int VDIM>
-__global__ void k_import(Geo g, int64_t n, double dx, double dy, const double *x, const double *y, const double *vx,
-                         const double *vy, const double *vz, Parts out, int *err) {
+__global__ void k_import(Geo g, int64_t n, double dx, double dy, double dz, const double *x, const double *y,
+                         const double *z, const double *vx, const double *vy, const double *vz, Parts out, int *err) {
     using R = typename RealOf<MIX>::T;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double xi = x[i];
-        const double yi = (DIM == 2) ? y[i] : 0.0;
+        const double yi = (DIM >= 2) ? y[i] : 0.0;
+        const double zi = (DIM == 3) ? z[i] : 0.0;
         // x = L (a wrap that rounded up) is the same node as x = 0
-        if (!(xi >= 0.0 && xi <= g.lx) || (DIM == 2 && !(yi >= 0.0 && yi <= g.ly))) raise_err(err, ERR_DOMAIN);
+        if (!(xi >= 0.0 && xi <= g.lx) || (DIM >= 2 && !(yi >= 0.0 && yi <= g.ly)) ||
+            (DIM == 3 && !(zi >= 0.0 && zi <= g.lz)))
+            raise_err(err, ERR_DOMAIN);
         if constexpr (MIX) {
             auto split = [](double v, double d, int nn, int &c, float &o) {
                 const double q = v / d;
@@ -437,16 +619,19 @@ __global__ void k_import(Geo g, int64_t n, double dx, double dy, const double *x
                 if (ci < 0) ci += nn;
                 c = (int)ci;
             };
-            int cx, cy = 0;
-            float ox, oy = 0.0f;
+            int cx, cy = 0, cz = 0;
+            float ox, oy = 0.0f, oz = 0.0f;
             split(isfinite(xi) ? xi : 0.0, dx, g.nx, cx, ox);
-            if constexpr (DIM == 2) split(isfinite(yi) ? yi : 0.0, dy, g.ny, cy, oy);
-            out.cell[i] = (DIM == 2) ? ((cy << 16) | cx) : cx;
+            if constexpr (DIM >= 2) split(isfinite(yi) ? yi : 0.0, dy, g.ny, cy, oy);
+            if constexpr (DIM == 3) split(isfinite(zi) ? zi : 0.0, dz, g.nz, cz, oz);
+            out.cell[i] = (DIM == 3) ? ((cz << 20) | (cy << 10) | cx) : (DIM == 2) ? ((cy << 16) | cx) : cx;
             out.ox[i] = ox;
-            if constexpr (DIM == 2) out.oy[i] = oy;
+            if constexpr (DIM >= 2) out.oy[i] = oy;
+            if constexpr (DIM == 3) out.oz[i] = oz;
         } else {
             out.x[i] = xi;
-            if constexpr (DIM == 2) out.y[i] = yi;
+            if constexpr (DIM >= 2) out.y[i] = yi;
+            if constexpr (DIM == 3) out.z[i] = zi;
         }
         ((R *)out.vx)[i] = (R)vx[i];
         if constexpr (VDIM >= 2) ((R *)out.vy)[i] = (R)vy[i];
@@ -507,19 +692,25 @@ __global__ void k_adj_fill(int64_t m, double *dst) {
         dst[i] = 0.0;
 }
 
-// lam_rho_hat = norm * (i kappa_x lam_Ex_hat + i kappa_y lam_Ey_hat) / K^2, 0 at k = 0
-__global__ void k_adj_spectral(Geo g, const double2 *lxh, const double2 *lyh, double2 *lrh, CtxDev c) {
+// lam_rho_hat = norm * (i kappa_x lam_Ex_hat + i kappa_y lam_Ey_hat
+// [+ i kappa_z lam_Ez_hat]) / K^2, 0 at k = 0; lzh NULL below 3D. lrh may be
+// lxh (each entry is read before it is written).
+__global__ void k_adj_spectral(Geo g, const double2 *lxh, const double2 *lyh, const double2 *lzh, double2 *lrh,
+                               CtxDev c) {
     const int hx = g.nx / 2 + 1;
-    const int64_t tot = (int64_t)hx * g.ny;
-    const double norm = 1.0 / ((double)g.nx * (double)g.ny);
+    const int64_t tot = (int64_t)hx * g.ny * g.nz;
+    const double norm = 1.0 / ((double)g.nx * (double)g.ny * (double)g.nz);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
-        const int kx = (int)(i % hx), ky = (int)(i / hx);
-        const double K2 = c.kx2[kx] + c.ky2[ky];
-        const double inv = (kx == 0 && ky == 0) ? 0.0 : norm / K2;
+        const int kx = (int)(i % hx);
+        const int64_t r = i / hx;
+        const int ky = (int)(r % g.ny), kz = (int)(r / g.ny);
+        const double K2 = c.kx2[kx] + c.ky2[ky] + c.kz2[kz];
+        const double inv = (i == 0) ? 0.0 : norm / K2;
         const double2 a = lxh[i], b = lyh[i];
-        const double kax = c.kapx[kx], kay = c.kapy[ky];
+        const double2 z = lzh ? lzh[i] : make_double2(0.0, 0.0);
+        const double kax = c.kapx[kx], kay = c.kapy[ky], kaz = c.kapz[kz];
         // i * kappa * (re + i im) = -kappa * im + i kappa * re
-        lrh[i] = make_double2(-(kax * a.y + kay * b.y) * inv, (kax * a.x + kay * b.x) * inv);
+        lrh[i] = make_double2(-((kax * a.y + kay * b.y) + kaz * z.y) * inv, ((kax * a.x + kay * b.x) + kaz * z.x) * inv);
     }
 }
 
@@ -567,7 +758,7 @@ namespace {
 // ---- layout of the checkpoint buffer and of the adjoint workspace ---------
 
 struct CkLayout {
-    size_t pos[3];      // mixed: cell, ox, oy; FP64: x, y (-1 = absent)
+    size_t pos[4];      // mixed: cell, ox, oy, oz; FP64: x, y, z (-1 = absent)
     size_t vel[3];
     size_t bstart, E, id;
     size_t bytes;       // one checkpoint
@@ -577,18 +768,16 @@ CkLayout ck_layout(const apic_ctx *c) {
     CkLayout L;
     const int64_t n = c->n;
     const size_t r = c->mixed ? 4 : 8;
-    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny * c->d.nz;
     size_t off = 0;
     auto take = [&](size_t b) { size_t o = off; off = align256(off + b); return o; };
     for (auto &v : L.pos) v = (size_t)-1;
     for (auto &v : L.vel) v = (size_t)-1;
     if (c->mixed) {
         L.pos[0] = take(4 * n);
-        L.pos[1] = take(4 * n);
-        if (c->d.dim == 2) L.pos[2] = take(4 * n);
+        for (int k = 0; k < c->d.dim; ++k) L.pos[1 + k] = take(4 * n);
     } else {
-        L.pos[0] = take(8 * n);
-        if (c->d.dim == 2) L.pos[1] = take(8 * n);
+        for (int k = 0; k < c->d.dim; ++k) L.pos[k] = take(8 * n);
     }
     for (int k = 0; k < c->d.vdim; ++k) L.vel[k] = take(r * n);
     L.bstart = take(4 * (c->g.nbuckets + 1));
@@ -600,7 +789,7 @@ CkLayout ck_layout(const apic_ctx *c) {
 
 struct AdjWs {
     size_t ctx;                 // the context workspace (sort, step, field solve)
-    size_t pw_pos[3], pw_vel[3], bstart, E, E32, rho;
+    size_t pw_pos[4], pw_vel[3], bstart, E, E32, rho;
     size_t id_a, id_b, inv, cross;
     size_t snap_pos;            // stride entries of positions
     size_t snap_pos_bytes;
@@ -614,7 +803,7 @@ struct AdjWs {
 
 size_t pos_bytes(const apic_ctx *c) {
     const int64_t n = c->n;
-    if (c->mixed) return align256(4 * n) * (c->d.dim == 2 ? 3 : 2);
+    if (c->mixed) return align256(4 * n) * (c->d.dim + 1);
     return align256(8 * n) * c->d.dim;
 }
 
@@ -622,7 +811,7 @@ AdjWs adj_layout(const apic_ctx *c, int stride) {
     AdjWs L;
     const int64_t n = c->n;
     const size_t r = c->mixed ? 4 : 8;
-    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny * c->d.nz;
     const int dim = c->d.dim, vdim = c->d.vdim;
     size_t off = 0;
     auto take = [&](size_t b) { size_t o = off; off = align256(off + b); return o; };
@@ -631,11 +820,9 @@ AdjWs adj_layout(const apic_ctx *c, int stride) {
     for (auto &v : L.pw_vel) v = (size_t)-1;
     if (c->mixed) {
         L.pw_pos[0] = take(4 * n);
-        L.pw_pos[1] = take(4 * n);
-        if (dim == 2) L.pw_pos[2] = take(4 * n);
+        for (int k = 0; k < dim; ++k) L.pw_pos[1 + k] = take(4 * n);
     } else {
-        L.pw_pos[0] = take(8 * n);
-        if (dim == 2) L.pw_pos[1] = take(8 * n);
+        for (int k = 0; k < dim; ++k) L.pw_pos[k] = take(8 * n);
     }
     for (int k = 0; k < vdim; ++k) L.pw_vel[k] = take(r * n);
     L.bstart = take(4 * (c->g.nbuckets + 1));
@@ -672,11 +859,13 @@ PosP pos_block(const apic_ctx *c, char *base) {
         const size_t a = align256(4 * n);
         p.cell = (const int32_t *)base;
         p.ox = (const float *)(base + a);
-        p.oy = c->d.dim == 2 ? (const float *)(base + 2 * a) : nullptr;
+        p.oy = c->d.dim >= 2 ? (const float *)(base + 2 * a) : nullptr;
+        p.oz = c->d.dim == 3 ? (const float *)(base + 3 * a) : nullptr;
     } else {
         const size_t a = align256(8 * n);
         p.x = (const double *)base;
-        p.y = c->d.dim == 2 ? (const double *)(base + a) : nullptr;
+        p.y = c->d.dim >= 2 ? (const double *)(base + a) : nullptr;
+        p.z = c->d.dim == 3 ? (const double *)(base + 2 * a) : nullptr;
     }
     return p;
 }
@@ -687,9 +876,11 @@ PosP pos_ck(const apic_ctx *c, const CkLayout &L, char *ck) {
         p.cell = wsp<const int32_t>(ck, L.pos[0]);
         p.ox = wsp<const float>(ck, L.pos[1]);
         p.oy = wsp<const float>(ck, L.pos[2]);
+        p.oz = wsp<const float>(ck, L.pos[3]);
     } else {
         p.x = wsp<const double>(ck, L.pos[0]);
         p.y = wsp<const double>(ck, L.pos[1]);
+        p.z = wsp<const double>(ck, L.pos[2]);
     }
     return p;
 }
@@ -701,9 +892,11 @@ apic_particles work_parts(const apic_ctx *c, const AdjWs &L, char *ws) {
         p.cell = wsp<int32_t>(ws, L.pw_pos[0]);
         p.ox = wsp<float>(ws, L.pw_pos[1]);
         p.oy = wsp<float>(ws, L.pw_pos[2]);
+        p.oz = wsp<float>(ws, L.pw_pos[3]);
     } else {
         p.x = wsp<double>(ws, L.pw_pos[0]);
         p.y = wsp<double>(ws, L.pw_pos[1]);
+        p.z = wsp<double>(ws, L.pw_pos[2]);
     }
     p.vx = wsp<void>(ws, L.pw_vel[0]);
     p.vy = wsp<void>(ws, L.pw_vel[1]);
@@ -720,11 +913,13 @@ apic_status save_pos(apic_ctx *c, const apic_particles &p, char *dst, hipStream_
         const size_t a = align256(4 * n);
         HIPCHK(c, launch_copy_bytes(dst, p.cell, 4 * n, s));
         HIPCHK(c, launch_copy_bytes(dst + a, p.ox, 4 * n, s));
-        if (c->d.dim == 2) HIPCHK(c, launch_copy_bytes(dst + 2 * a, p.oy, 4 * n, s));
+        if (c->d.dim >= 2) HIPCHK(c, launch_copy_bytes(dst + 2 * a, p.oy, 4 * n, s));
+        if (c->d.dim == 3) HIPCHK(c, launch_copy_bytes(dst + 3 * a, p.oz, 4 * n, s));
     } else {
         const size_t a = align256(8 * n);
         HIPCHK(c, launch_copy_bytes(dst, p.x, 8 * n, s));
-        if (c->d.dim == 2) HIPCHK(c, launch_copy_bytes(dst + a, p.y, 8 * n, s));
+        if (c->d.dim >= 2) HIPCHK(c, launch_copy_bytes(dst + a, p.y, 8 * n, s));
+        if (c->d.dim == 3) HIPCHK(c, launch_copy_bytes(dst + 2 * a, p.z, 8 * n, s));
     }
     return APIC_OK;
 }
@@ -734,7 +929,7 @@ apic_status ck_transfer(apic_ctx *c, const CkLayout &L, char *ck, apic_particles
                         int dir, hipStream_t s) {
     const int64_t n = c->n;
     const size_t r = c->mixed ? 4 : 8;
-    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny * c->d.nz;
     auto mv = [&](void *state, size_t off, size_t bytes) -> hipError_t {
         if (!state || off == (size_t)-1) return hipSuccess;
         return dir > 0 ? launch_copy_bytes(ck + off, state, (int64_t)bytes, s)
@@ -744,9 +939,11 @@ apic_status ck_transfer(apic_ctx *c, const CkLayout &L, char *ck, apic_particles
         HIPCHK(c, mv(p.cell, L.pos[0], 4 * n));
         HIPCHK(c, mv(p.ox, L.pos[1], 4 * n));
         HIPCHK(c, mv(p.oy, L.pos[2], 4 * n));
+        HIPCHK(c, mv(p.oz, L.pos[3], 4 * n));
     } else {
         HIPCHK(c, mv(p.x, L.pos[0], 8 * n));
         HIPCHK(c, mv(p.y, L.pos[1], 8 * n));
+        HIPCHK(c, mv(p.z, L.pos[2], 8 * n));
     }
     HIPCHK(c, mv(p.vx, L.vel[0], r * n));
     HIPCHK(c, mv(p.vy, L.vel[1], r * n));
@@ -761,24 +958,29 @@ int n_checkpoints(int nsteps, int stride) { return (nsteps + stride - 1) / strid
 
 // lam_rho = A^T lam_E (FP64)
 apic_status adj_solve(apic_ctx *c, double *lE, double *lrho, char *ws_ctx, hipStream_t s) {
-    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny * c->d.nz;
     if (c->d.dim == 1) {
         hipLaunchKernelGGL(k_adj_field1d, dim3(1), dim3(kBlock), (size_t)c->d.nx * sizeof(double), s, c->d.nx, lE,
                            c->d.lx / c->d.nx, lrho);
         HIPCHK(c, hipGetLastError());
         return APIC_OK;
     }
-    const size_t H = (size_t)(c->d.nx / 2 + 1) * c->d.ny;
+    // half spectra of the dim components (the context's one rho spectrum and
+    // its dim phi spectra hold them), combined in place into the first
+    const size_t H = (size_t)(c->d.nx / 2 + 1) * c->d.ny * c->d.nz;
     char *rhat = wsp<char>(ws_ctx, c->o_rhat);
     char *ehat = wsp<char>(ws_ctx, c->o_ehat);
     FFTCHK(c, hipfftSetStream(c->fwd, s));
     FFTCHK(c, hipfftExecD2Z(c->fwd, (hipfftDoubleReal *)lE, (hipfftDoubleComplex *)rhat));
     FFTCHK(c, hipfftExecD2Z(c->fwd, (hipfftDoubleReal *)(lE + G), (hipfftDoubleComplex *)ehat));
+    if (c->d.dim == 3)
+        FFTCHK(c, hipfftExecD2Z(c->fwd, (hipfftDoubleReal *)(lE + 2 * G), (hipfftDoubleComplex *)(ehat + 16 * H)));
     hipLaunchKernelGGL(k_adj_spectral, dim3(nblocks((int64_t)H, 1024)), dim3(kBlock), 0, s, c->g,
-                       (const double2 *)rhat, (const double2 *)ehat, (double2 *)(ehat + 16 * H), c->dev);
+                       (const double2 *)rhat, (const double2 *)ehat,
+                       c->d.dim == 3 ? (const double2 *)(ehat + 16 * H) : nullptr, (double2 *)rhat, c->dev);
     HIPCHK(c, hipGetLastError());
     FFTCHK(c, hipfftSetStream(c->inv, s));
-    FFTCHK(c, hipfftExecZ2D(c->inv, (hipfftDoubleComplex *)(ehat + 16 * H), (hipfftDoubleReal *)lrho));
+    FFTCHK(c, hipfftExecZ2D(c->inv, (hipfftDoubleComplex *)rhat, (hipfftDoubleReal *)lrho));
     return APIC_OK;
 }
 
@@ -821,6 +1023,7 @@ apic_status launch_level(apic_ctx *c, AdjP<R> &P, hipStream_t s) {
     // scatter into an LDS tile (tile + 2-cell halo per scattered component)
     dim3 grid(nblocks(c->n));
     size_t sh = 0;
+    if (c->d.dim == 3) P.bs = nullptr;   // 3D scatters lam_Ep with global atomics
     if (P.bs) {
         const int tw = (1 << c->g.tsx) + 5, th = c->d.dim == 2 ? (1 << c->g.tsy) + 5 : 1;
         sh = (size_t)c->d.dim * tw * th * sizeof(double);
@@ -831,7 +1034,19 @@ apic_status launch_level(apic_ctx *c, AdjP<R> &P, hipStream_t s) {
             grid = dim3(nblocks(c->n));
         }
     }
-    if (c->g.hc) {
+    if (c->d.dim == 3) {
+        if (c->mixed) {
+            if constexpr (std::is_same<R, float>::value) {
+                if (c->g.hc) hipLaunchKernelGGL((k_adj_level<true, 3, 3, true>), grid, dim3(kBlock), 0, s, P);
+                else hipLaunchKernelGGL((k_adj_level<true, 3, 3, false>), grid, dim3(kBlock), 0, s, P);
+            }
+        } else {
+            if constexpr (std::is_same<R, double>::value) {
+                if (c->g.hc) hipLaunchKernelGGL((k_adj_level<false, 3, 3, true>), grid, dim3(kBlock), 0, s, P);
+                else hipLaunchKernelGGL((k_adj_level<false, 3, 3, false>), grid, dim3(kBlock), 0, s, P);
+            }
+        }
+    } else if (c->g.hc) {
         if (c->mixed) {
             if constexpr (std::is_same<R, float>::value)
                 hipLaunchKernelGGL((k_adj_level<true, 2, 3, true>), grid, dim3(kBlock), sh, s, P);
@@ -850,7 +1065,6 @@ apic_status launch_level(apic_ctx *c, AdjP<R> &P, hipStream_t s) {
 }
 
 apic_status check_adj_args(apic_ctx *c, int nsteps, int stride) {
-    if (c->d.dim == 3) return fail(c, APIC_EUNSUPPORTED, "the adjoint covers 1D and 2D plasmas");
     if (c->g.em) return fail(c, APIC_EUNSUPPORTED, "the adjoint covers the electrostatic step");
     if (c->g.walls) return fail(c, APIC_EUNSUPPORTED, "the adjoint covers periodic plasmas (no absorbing walls)");
     if (nsteps < 0) return fail(c, APIC_EINVAL, "nsteps must be >= 0");
@@ -861,12 +1075,12 @@ apic_status check_adj_args(apic_ctx *c, int nsteps, int stride) {
 
 template <typename R>
 apic_status step_adjoint_impl(apic_ctx *c, char *ck, int nsteps, int stride, double seed, double *out_x,
-                              double *out_y, double *out_vx, double *out_vy, double *out_vz, char *ws,
+                              double *out_y, double *out_z, double *out_vx, double *out_vy, double *out_vz, char *ws,
                               hipStream_t s) {
     const CkLayout CL = ck_layout(c);
     const AdjWs L = adj_layout(c, stride);
     const int64_t n = c->n;
-    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny * c->d.nz;
     const int dim = c->d.dim;
     char *ws_ctx = ws + L.ctx;
     double *lE = wsp<double>(ws, L.lE);
@@ -967,6 +1181,7 @@ apic_status step_adjoint_impl(apic_ctx *c, char *ck, int nsteps, int stride, dou
     P.id0 = (const int32_t *)(ckp(0) + CL.id);
     P.out_x = out_x;
     P.out_y = out_y;
+    P.out_z = out_z;
     P.out_vx = out_vx;
     P.out_vy = out_vy;
     P.out_vz = out_vz;
@@ -977,28 +1192,29 @@ apic_status step_adjoint_impl(apic_ctx *c, char *ck, int nsteps, int stride, dou
 
 extern "C" {
 
-apic_status apic_import_state(apic_ctx *c, const double *x, const double *y, const double *vx, const double *vy,
-                              const double *vz, apic_particles *p, void *stream) {
+apic_status apic_import_state(apic_ctx *c, const double *x, const double *y, const double *z, const double *vx,
+                              const double *vy, const double *vz, apic_particles *p, void *stream) {
     if (!c) return APIC_EINVAL;
-    if (c->d.dim == 3) return fail(c, APIC_EUNSUPPORTED, "state import covers 1D and 2D plasmas");
     if (c->g.walls) return fail(c, APIC_EUNSUPPORTED, "state import covers periodic plasmas");
     apic_status st = check_parts(c, p, false);
     if (st != APIC_OK) return st;
-    if (!x || (c->d.dim == 2 && !y) || !vx || (c->d.vdim >= 2 && !vy) || (c->d.vdim >= 3 && !vz))
+    if (!x || (c->d.dim >= 2 && !y) || (c->d.dim == 3 && !z) || !vx || (c->d.vdim >= 2 && !vy) ||
+        (c->d.vdim >= 3 && !vz))
         return fail(c, APIC_EINVAL, "a state array is NULL");
     hipStream_t s = (hipStream_t)stream;
-    const double dx = c->d.lx / c->d.nx, dy = c->d.dim == 2 ? c->d.ly / c->d.ny : 1.0;
+    const double dx = c->d.lx / c->d.nx, dy = c->d.dim >= 2 ? c->d.ly / c->d.ny : 1.0;
+    const double dz = c->d.dim == 3 ? c->d.lz / c->d.nz : 1.0;
     const Parts out = parts_of(p);
-    APIC_DISPATCH_2D(c->g, c->mixed,
+    APIC_DISPATCH(c->g, c->mixed,
                   hipLaunchKernelGGL((k_import<MIX, DIM, VDIM>), dim3(nblocks(c->n)), dim3(kBlock), 0, s, c->g, c->n,
-                                     dx, dy, x, y, vx, vy, vz, out, c->dev.err));
+                                     dx, dy, dz, x, y, z, vx, vy, vz, out, c->dev.err));
     HIPCHK(c, hipGetLastError());
     return APIC_OK;
 }
 
 apic_status apic_adjoint_sizes(const apic_ctx *c, int nsteps, int stride, size_t *ckpt_bytes, size_t *ws_bytes) {
     if (!c || nsteps < 0 || stride < 1) return APIC_EINVAL;
-    if (c->d.dim == 3 || c->g.em || c->g.walls) return APIC_EUNSUPPORTED;
+    if (c->g.em || c->g.walls) return APIC_EUNSUPPORTED;
     const CkLayout CL = ck_layout(c);
     if (ckpt_bytes) *ckpt_bytes = CL.bytes * (size_t)(n_checkpoints(nsteps, stride) + 1);
     if (ws_bytes) *ws_bytes = adj_layout(c, stride).bytes;
@@ -1019,7 +1235,7 @@ apic_status apic_adjoint_forward(apic_ctx *c, const apic_particles *p0, int nste
     char *w = (char *)ws, *ck = (char *)ckpt;
     char *ws_ctx = w + L.ctx;
     const int64_t n = c->n;
-    const int64_t G = (int64_t)c->d.nx * c->d.ny;
+    const int64_t G = (int64_t)c->d.nx * c->d.ny * c->d.nz;
     const int dim = c->d.dim;
     double *E_w = wsp<double>(w, L.E);
     float *E32_w = wsp<float>(w, L.E32);
@@ -1065,27 +1281,29 @@ apic_status apic_adjoint_forward(apic_ctx *c, const apic_particles *p0, int nste
 }
 
 apic_status apic_step_adjoint(apic_ctx *c, const void *ckpt, int nsteps, int stride, double seed, double *lam_x,
-                              double *lam_y, double *lam_vx, double *lam_vy, double *lam_vz, const double *dx_ddelta0,
-                              const double *dy_ddelta0, double *grad_delta0, void *ws, void *stream) {
+                              double *lam_y, double *lam_z, double *lam_vx, double *lam_vy, double *lam_vz,
+                              const double *dx_ddelta0, const double *dy_ddelta0, double *grad_delta0, void *ws,
+                              void *stream) {
     if (!c) return APIC_EINVAL;
     apic_status st = check_adj_args(c, nsteps, stride);
     if (st != APIC_OK) return st;
     if (!ckpt || !ws) return fail(c, APIC_EINVAL, "checkpoint buffer and workspace are required");
-    if (!lam_x || (c->d.dim == 2 && !lam_y) || !lam_vx || (c->d.vdim >= 2 && !lam_vy) || (c->d.vdim >= 3 && !lam_vz))
+    if (!lam_x || (c->d.dim >= 2 && !lam_y) || (c->d.dim == 3 && !lam_z) || !lam_vx || (c->d.vdim >= 2 && !lam_vy) ||
+        (c->d.vdim >= 3 && !lam_vz))
         return fail(c, APIC_EINVAL, "a gradient output array is NULL");
     if (!std::isfinite(seed)) return fail(c, APIC_EINVAL, "seed is not finite");
-    if (grad_delta0 && (!dx_ddelta0 || (c->d.dim == 2 && !dy_ddelta0)))
+    if (grad_delta0 && (!dx_ddelta0 || (c->d.dim >= 2 && !dy_ddelta0)))
         return fail(c, APIC_EINVAL, "grad_delta0 needs the displacement direction of every particle (dx, dy in 2D)");
     hipStream_t s = (hipStream_t)stream;
     if (c->mixed)
-        st = step_adjoint_impl<float>(c, (char *)const_cast<void *>(ckpt), nsteps, stride, seed, lam_x, lam_y, lam_vx,
-                                      lam_vy, lam_vz, (char *)ws, s);
+        st = step_adjoint_impl<float>(c, (char *)const_cast<void *>(ckpt), nsteps, stride, seed, lam_x, lam_y, lam_z,
+                                      lam_vx, lam_vy, lam_vz, (char *)ws, s);
     else
         st = step_adjoint_impl<double>(c, (char *)const_cast<void *>(ckpt), nsteps, stride, seed, lam_x, lam_y,
-                                       lam_vx, lam_vy, lam_vz, (char *)ws, s);
+                                       lam_z, lam_vx, lam_vy, lam_vz, (char *)ws, s);
     if (st != APIC_OK || !grad_delta0) return st;
     hipLaunchKernelGGL(apic::k_adj_delta0, dim3(1), dim3(1024), 0, s, c->n, lam_x, dx_ddelta0,
-                       c->d.dim == 2 ? lam_y : nullptr, c->d.dim == 2 ? dy_ddelta0 : nullptr, grad_delta0);
+                       c->d.dim >= 2 ? lam_y : nullptr, c->d.dim >= 2 ? dy_ddelta0 : nullptr, grad_delta0);
     HIPCHK(c, hipGetLastError());
     return APIC_OK;
 }

@@ -646,15 +646,16 @@ apic_status apic_gather_push(apic_ctx *c, apic_particles *p, const void *E, doub
     return APIC_OK;
 }
 
-apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, float *E32, int nsteps, double *diag,
-                      void *ws, void *stream) {
-    if (!c) return APIC_EINVAL;
-    if (c->g.em) return fail(c, APIC_EUNSUPPORTED, "electromagnetic context: use apic_em_step");
-    apic_status st = check_parts(c, p, true);
-    if (st != APIC_OK) return st;
-    if (!E || !ws || nsteps < 0) return fail(c, APIC_EINVAL, "E, workspace and nsteps >= 0 are required");
-    if (nsteps == 0) return APIC_OK;
-    hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+namespace apic_host {
+
+// nsteps cycles alternating between the particle buffers A (p, holding the
+// state on entry) and B with its bucket table bsB; after an odd count the
+// state is in B, and copy_back moves it to p.
+apic_status step_run(apic_ctx *c, apic_particles *p, const Parts &B, int32_t *bsB, bool copy_back, void *rho,
+                     double *E, float *E32, int nsteps, double *diag, void *ws, hipStream_t s) {
+    apic_status st = APIC_OK;
     const int nb = c->g.nbuckets;
     const int64_t G = (int64_t)c->d.nx * c->d.ny * c->d.nz;
     int32_t *cnt = wsp<int32_t>(ws, c->o_cnt);
@@ -663,8 +664,8 @@ apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, floa
     int32_t *tot = wsp<int32_t>(ws, c->o_tot);
     int32_t *deep = wsp<int32_t>(ws, c->o_deep);
     void *acc = wsp<void>(ws, c->o_acc);
-    Parts A = parts_of(p), B = parts_ws(c, ws);
-    int32_t *bsA = p->bucket_start, *bsB = wsp<int32_t>(ws, c->o_bstart);
+    const Parts A = parts_of(p);
+    int32_t *bsA = p->bucket_start;
     const PushC pc = push_coeffs(c, 1.0, 1);
     HIPCHK(c, launch_fill_i32(farcnt, nb, 0, s));
     // the bucket totals: two buffers, alternating by step
@@ -708,12 +709,45 @@ apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, floa
         if (st != APIC_OK) return st;
         if (ev && c->prof_all) HIPCHK(c, hipEventRecord(ev[4], s));
     }
-    if (nsteps & 1) {
+    if ((nsteps & 1) && copy_back) {
         st = copy_parts(c, A, B, s);
         if (st != APIC_OK) return st;
         HIPCHK(c, launch_copy_bytes(bsA, bsB, 4 * (int64_t)(nb + 1), s));
     }
     return APIC_OK;
+}
+
+}  // namespace apic_host
+
+extern "C" {
+
+apic_status apic_step(apic_ctx *c, apic_particles *p, void *rho, double *E, float *E32, int nsteps, double *diag,
+                      void *ws, void *stream) {
+    if (!c) return APIC_EINVAL;
+    if (c->g.em) return fail(c, APIC_EUNSUPPORTED, "electromagnetic context: use apic_em_step");
+    apic_status st = check_parts(c, p, true);
+    if (st != APIC_OK) return st;
+    if (!E || !ws || nsteps < 0) return fail(c, APIC_EINVAL, "E, workspace and nsteps >= 0 are required");
+    if (nsteps == 0) return APIC_OK;
+    return step_run(c, p, parts_ws(c, ws), wsp<int32_t>(ws, c->o_bstart), true, rho, E, E32, nsteps, diag, ws,
+                    (hipStream_t)stream);
+}
+
+apic_status apic_step_pair(apic_ctx *c, apic_particles *p, apic_particles *q, void *rho, double *E, float *E32,
+                           int nsteps, double *diag, int *in_q, void *ws, void *stream) {
+    if (!c) return APIC_EINVAL;
+    if (c->g.em) return fail(c, APIC_EUNSUPPORTED, "electromagnetic context: use apic_em_step");
+    apic_status st = check_parts(c, p, true);
+    if (st != APIC_OK) return st;
+    st = check_parts(c, q, true);
+    if (st != APIC_OK) return st;
+    if (!E || !ws || !in_q || nsteps < 0)
+        return fail(c, APIC_EINVAL, "E, workspace, in_q and nsteps >= 0 are required");
+    if (c->n > 0 && (p->vx == q->vx || p->bucket_start == q->bucket_start))
+        return fail(c, APIC_EINVAL, "the two particle buffers must not share arrays");
+    *in_q = nsteps & 1;
+    if (nsteps == 0) return APIC_OK;
+    return step_run(c, p, parts_of(q), q->bucket_start, false, rho, E, E32, nsteps, diag, ws, (hipStream_t)stream);
 }
 
 apic_status apic_step_static(apic_ctx *c, apic_particles *p, void *rho, double *E, float *E32, int nsteps,

@@ -20,11 +20,12 @@
 
 namespace {
 
-// dim, vdim, nx, ny, precision, floor(log2(particles per cell))
-using TileKey = std::tuple<int, int, int, int, int, int>;
+// dim, vdim, nx, ny, nz, precision, floor(log2(particles per cell)), velocity advance
+using TileKey = std::tuple<int, int, int, int, int, int, int, int>;
+using Tile = std::tuple<int, int, int>;
 
 std::mutex g_mu;
-std::map<TileKey, std::pair<int, int>> g_tiles;
+std::map<TileKey, Tile> g_tiles;
 std::map<std::pair<int64_t, int>, int> g_chunks;  // (total particles, replicas) -> chunk
 
 struct DevBuf {
@@ -73,22 +74,23 @@ hipError_t copy_in(void *dst, const void *src, size_t bytes, hipStream_t s) {
 
 // One trial of a tile shape: copy the particles, sort, deposit, solve E^0,
 // two untimed steps, then nsteps timed steps. Returns ms per step or INFINITY.
-double trial_tiles(const apic_grid_desc &d, const apic_particles &src, int tx, int ty, int nsteps, hipStream_t s) {
+double trial_tiles(const apic_grid_desc &d, const apic_particles &src, const Tile &t, int nsteps, hipStream_t s) {
     apic_grid_desc dd = d;
-    dd.tile_x = tx;
-    dd.tile_y = ty;
+    dd.tile_x = std::get<0>(t);
+    dd.tile_y = std::get<1>(t);
+    dd.tile_z = std::get<2>(t);
     apic_ctx *c = nullptr;
     if (apic_create(&dd, src.n, &c) != APIC_OK) return INFINITY;
     const bool mixed = d.prec == APIC_MIXED;
     const size_t n = (size_t)src.n, r = mixed ? 4 : 8;
-    const size_t G = (size_t)d.nx * (d.dim == 2 ? d.ny : 1);
+    const size_t G = (size_t)d.nx * (d.dim >= 2 ? d.ny : 1) * (d.dim == 3 ? d.nz : 1);
     size_t wsb = 0;
     (void)apic_workspace_size(c, &wsb);
-    DevBuf ws(wsb), pa(r * n), pb(d.dim == 2 ? r * n : 0), cell(mixed ? 4 * n : 0), vx(r * n),
-        vy(d.vdim >= 2 ? r * n : 0), vz(d.vdim >= 3 ? r * n : 0), bs(4 * ((size_t)apic_num_buckets(c) + 1)),
-        rho(8 * G), E(8 * G * d.dim);
+    DevBuf ws(wsb), pa(r * n), pb(d.dim >= 2 ? r * n : 0), pc(d.dim == 3 ? r * n : 0), cell(mixed ? 4 * n : 0),
+        vx(r * n), vy(d.vdim >= 2 ? r * n : 0), vz(d.vdim >= 3 ? r * n : 0),
+        bs(4 * ((size_t)apic_num_buckets(c) + 1)), rho(8 * G), E(8 * G * d.dim);
     double out = INFINITY;
-    if (ws.ok && pa.ok && pb.ok && cell.ok && vx.ok && vy.ok && vz.ok && bs.ok && rho.ok && E.ok) {
+    if (ws.ok && pa.ok && pb.ok && pc.ok && cell.ok && vx.ok && vy.ok && vz.ok && bs.ok && rho.ok && E.ok) {
         apic_particles p{};
         p.n = src.n;
         hipError_t e = hipSuccess;
@@ -96,14 +98,18 @@ double trial_tiles(const apic_grid_desc &d, const apic_particles &src, int tx, i
             p.cell = (int32_t *)cell.p;
             p.ox = (float *)pa.p;
             p.oy = (float *)pb.p;
+            p.oz = (float *)pc.p;
             e = copy_in(p.cell, src.cell, 4 * n, s);
             if (e == hipSuccess) e = copy_in(p.ox, src.ox, 4 * n, s);
-            if (e == hipSuccess && d.dim == 2) e = copy_in(p.oy, src.oy, 4 * n, s);
+            if (e == hipSuccess && d.dim >= 2) e = copy_in(p.oy, src.oy, 4 * n, s);
+            if (e == hipSuccess && d.dim == 3) e = copy_in(p.oz, src.oz, 4 * n, s);
         } else {
             p.x = (double *)pa.p;
             p.y = (double *)pb.p;
+            p.z = (double *)pc.p;
             e = copy_in(p.x, src.x, 8 * n, s);
-            if (e == hipSuccess && d.dim == 2) e = copy_in(p.y, src.y, 8 * n, s);
+            if (e == hipSuccess && d.dim >= 2) e = copy_in(p.y, src.y, 8 * n, s);
+            if (e == hipSuccess && d.dim == 3) e = copy_in(p.z, src.z, 8 * n, s);
         }
         p.vx = vx.p;
         p.vy = d.vdim >= 2 ? vy.p : nullptr;
@@ -171,37 +177,51 @@ double trial_chunk(const apic_replica *reps, int nrep, double dt, double qm, dou
 extern "C" {
 
 apic_status apic_autotune_tiles(const apic_grid_desc *desc, const apic_particles *p, int nsteps, int *tile_x,
-                                int *tile_y, double *ms_per_step, void *stream) {
+                                int *tile_y, int *tile_z, double *ms_per_step, void *stream) {
     if (!desc || !p || !tile_x || !tile_y || nsteps <= 0 || p->n <= 0) return APIC_EINVAL;
     const apic_grid_desc &d = *desc;
-    if (d.dim == 3 || d.model == APIC_ELECTROMAGNETIC || d.walls_x) return APIC_EUNSUPPORTED;
-    if (d.prec == APIC_MIXED ? (!p->cell || !p->ox) : !p->x) return APIC_EINVAL;
-    const int ny = d.dim == 2 ? d.ny : 1;
-    const TileKey key{d.dim, d.vdim, d.nx, ny, (int)d.prec, floor_log2((double)p->n / ((double)d.nx * ny))};
+    if (d.dim == 3 && !tile_z) return APIC_EINVAL;
+    if (d.model == APIC_ELECTROMAGNETIC || d.walls_x) return APIC_EUNSUPPORTED;
+    if (d.prec == APIC_MIXED ? (!p->cell || !p->ox || (d.dim == 3 && !p->oz)) : (!p->x || (d.dim == 3 && !p->z)))
+        return APIC_EINVAL;
+    const int ny = d.dim >= 2 ? d.ny : 1, nz = d.dim == 3 ? d.nz : 1;
+    const TileKey key{d.dim, d.vdim, d.nx, ny, nz, (int)d.prec,
+                      floor_log2((double)p->n / ((double)d.nx * ny * nz)), d.pusher};
+    auto put = [&](const Tile &t) {
+        *tile_x = std::get<0>(t);
+        *tile_y = std::get<1>(t);
+        if (tile_z) *tile_z = std::get<2>(t);
+    };
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_tiles.find(key);
         if (it != g_tiles.end()) {
-            *tile_x = it->second.first;
-            *tile_y = it->second.second;
+            put(it->second);
             if (ms_per_step) *ms_per_step = -1.0;
             return APIC_OK;
         }
     }
-    std::vector<std::pair<int, int>> cand;
-    if (d.dim == 2) {
+    std::vector<Tile> cand;
+    if (d.dim == 3) {
+        // 4 to 16 cells along x, 4 to 8 along y and z (a candidate whose E
+        // tile and deposit region do not fit a workgroup's LDS is rejected by
+        // apic_create and skipped)
+        const int sizes[][3] = {{4, 4, 4}, {8, 4, 4}, {8, 8, 4}, {8, 8, 8}, {16, 8, 4}, {16, 8, 8}, {16, 16, 8}};
+        for (auto &t : sizes)
+            if (t[0] <= d.nx && t[1] <= d.ny && t[2] <= d.nz) cand.push_back({t[0], t[1], t[2]});
+    } else if (d.dim == 2) {
         const int sizes[][2] = {{4, 4}, {8, 4}, {8, 8}, {16, 8}, {16, 16}, {32, 16}, {32, 32}};
         for (auto &t : sizes)
-            if (t[0] <= d.nx && t[1] <= d.ny) cand.push_back({t[0], t[1]});
+            if (t[0] <= d.nx && t[1] <= d.ny) cand.push_back({t[0], t[1], 0});
     } else {
-        for (int t = 8; t <= 1024 && t <= d.nx; t *= 2) cand.push_back({t, 1});
+        for (int t = 8; t <= 1024 && t <= d.nx; t *= 2) cand.push_back({t, 1, 0});
     }
-    cand.push_back({0, 0});  // the library's default
+    cand.push_back({0, 0, 0});  // the library's default
     hipStream_t s = (hipStream_t)stream;
     double best = INFINITY;
-    std::pair<int, int> pick{0, 0};
+    Tile pick{0, 0, 0};
     for (auto &t : cand) {
-        const double ms = trial_tiles(d, *p, t.first, t.second, nsteps, s);
+        const double ms = trial_tiles(d, *p, t, nsteps, s);
         if (ms < best) {
             best = ms;
             pick = t;
@@ -212,8 +232,7 @@ apic_status apic_autotune_tiles(const apic_grid_desc *desc, const apic_particles
         std::lock_guard<std::mutex> lk(g_mu);
         g_tiles[key] = pick;
     }
-    *tile_x = pick.first;
-    *tile_y = pick.second;
+    put(pick);
     if (ms_per_step) *ms_per_step = best;
     return APIC_OK;
 }

@@ -2,11 +2,17 @@
 
 Usage:
   python -m paper_2608_15249_amd.rocprof_summary trace <results.db> [--cmd "..."] [--last N]
+  python -m paper_2608_15249_amd.rocprof_summary counters <pass1.db> [<pass2.db> ...] --kernel k_step_push \
+        --tag mixed --merge-into profiles/step_push_<workload>_counters.json --tile 32x32 [--cmd "..."]
   python -m paper_2608_15249_amd.rocprof_summary traffic <fetch.db> <write.db> \
         --kernel k_step --copy-bytes N [--cmd "..."] [--tag mixed] \
         [--merge-into profiles/step_push_<workload>_traffic.json --tile 8x8 --main k_step_push]
 
-`trace` prints per-kernel call counts and average/total durations. `traffic`
+`trace` prints per-kernel call counts and average/total durations.
+`counters` averages every counter of one or more PMC passes per dispatch of
+the named kernel (the timed launches of the run) and stores them, with the
+source hash and the tile, under the tag (the benchmark reads the atomic
+counts from there). `traffic`
 turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch, summed over the counter
 instances of a dispatch) into HBM bytes per dispatch of the named kernel,
 each scaled by the factor that makes the same counter read the known byte
@@ -84,6 +90,13 @@ def main():
     t.add_argument("--cmd", default="")
     t.add_argument("--last", type=int, default=0,
                    help="also average the last N dispatches of each kernel (the timed steps of a run)")
+    q = sub.add_parser("counters")
+    q.add_argument("dbs", nargs="+")
+    q.add_argument("--kernel", required=True)
+    q.add_argument("--tag", required=True)
+    q.add_argument("--merge-into", required=True)
+    q.add_argument("--tile", default="")
+    q.add_argument("--cmd", default="")
     f = sub.add_parser("traffic")
     f.add_argument("fetch_db")
     f.add_argument("write_db")
@@ -95,6 +108,36 @@ def main():
     f.add_argument("--tile", default="")
     f.add_argument("--main", default="", help="kernel (name prefix) whose bytes are the headline")
     a = ap.parse_args()
+    if a.cmd_name == "counters":
+        per = {}
+        name = None
+        for db in a.dbs:
+            con = sqlite3.connect(db)
+            cn_names = sorted({r[0] for r in con.execute("select distinct counter_name from pmc_events")})
+            for cn in cn_names:
+                vals = pmc_per_dispatch(db, cn)
+                ks = [k for k in vals if k.startswith(a.kernel)]
+                if not ks:
+                    continue
+                name = ks[0]
+                v = vals[ks[0]]
+                per[cn] = sum(v) / len(v)
+        sha = kernel_source_sha()
+        tile = [int(v) for v in a.tile.lower().split("x")] if a.tile else []
+        d = {}
+        if os.path.exists(a.merge_into):
+            with open(a.merge_into) as fh:
+                d = json.load(fh)
+            if d.get("kernel_src_sha") != sha or d.get("tile") != tile:
+                d = {}
+        d["kernel_src_sha"] = sha
+        d["tile"] = tile
+        d["note"] = "counter values per dispatch of the kernel, averaged over its dispatches in the profiled run"
+        d[a.tag] = {"kernel": name, "per_launch": per, "command": a.cmd}
+        with open(a.merge_into, "w") as fh:
+            json.dump(d, fh, indent=1)
+        print(json.dumps(d[a.tag], indent=1))
+        return
     if a.cmd_name == "trace":
         if a.cmd:
             print("command: %s" % a.cmd)

@@ -30,16 +30,15 @@ class Simulation:
                                bz=w.bz, precision=precision, frac_bits=frac_bits, tile=t, device=device,
                                nz=w.nz, lz=w.Lz, pusher=pusher, c_light=c_light, walls=walls)
         self.tune_ms = None
-        if tile == "auto" and (w.dim == 3 or walls):
-            # the tile autotuner covers periodic 1D and 2D plasmas; the others keep the default tile
-            tile = (0, 0, 0) if w.dim == 3 else (0, 0)
+        if tile == "auto" and walls:
+            # the tile autotuner covers periodic plasmas; between walls the default tile is kept
+            tile = (0, 0)
         if tile == "auto":
             # time the candidate tiles on this very state, then build the context with the pick
-            ctx = mk((0, 0))
+            ctx = mk((0, 0, 0) if w.dim == 3 else (0, 0))
             p = Particles(ctx)
             self._upload(p, ctx.mixed, state)
-            tx, ty, self.tune_ms = ctx.autotune_tiles(p)
-            tile = (tx, ty)
+            tile, self.tune_ms = ctx.autotune_tiles(p)
             del p, ctx
         self.ctx = mk(tuple(tile))
         self.tile = self.ctx.tile      # the tile the context uses (defaults resolved)

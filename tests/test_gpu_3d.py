@@ -352,6 +352,33 @@ def test_step_deterministic_3d(torch):
         assert np.array_equal(s1[k], s2[k]), k
 
 
+def test_autotuned_tile_3d_gives_the_same_plasma(torch):
+    """apic_autotune_tiles in 3D picks one of its candidate tiles (or the
+    default), caches the pick, and eight mixed steps with that tile give the
+    same field and, as a set, the same particles as a fixed 8 x 4 x 4 tile."""
+    from paper_2608_15249_amd.sim import Simulation
+    w = W.thermal_3d(seed=9, nx=24, ppc=16)
+    state = W.sample3(w)
+    a = Simulation(w, "mixed", state=state, tile="auto")
+    assert a.tune_ms > 0
+    assert len(a.tile) == 3 and all(t in (2, 4, 8, 16) for t in a.tile), a.tile
+    again = Simulation(w, "mixed", state=state, tile="auto")
+    assert again.tile == a.tile and again.tune_ms == -1.0
+    b = Simulation(w, "mixed", state=state, tile=(8, 4, 4))
+    for s in (a, b):
+        s.initialise()
+        s.run(8)
+        s.ctx.sync()
+    for ea, eb in zip(a.field(), b.field()):
+        assert np.array_equal(ea, eb)
+    sa, sb = a.state(), b.state()
+    keys = ("vz", "vy", "vx", "oz", "oy", "ox")
+    ka = np.lexsort(tuple(sa[k].view(np.uint32) for k in keys) + (sa["cell"],))
+    kb = np.lexsort(tuple(sb[k].view(np.uint32) for k in keys) + (sb["cell"],))
+    for f in ("cell", "ox", "oy", "oz", "vx", "vy", "vz"):
+        assert np.array_equal(sa[f][ka], sb[f][kb]), f
+
+
 def test_mixed_local_field_energy_error_3d(torch):
     """From identical states along an FP64 oracle trajectory, one mixed 3D step
     and one FP64 step give field energies within 1e-5 relative."""

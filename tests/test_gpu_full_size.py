@@ -1,10 +1,13 @@
 """Full-size parity checks in the launch configuration the benchmark times
 (the autotuned tile in 2D, the default tile otherwise), from the seeded host
 state: the GPU runs the field of the initial charge, the backward half push
-and one step; 4096 sampled particles are compared with the oracle applied to
-their initial state in the oracle's own field of the initial charge, and
-properties that hold at any size are checked on the whole plasma (every
-particle in the bucket the table says, the exact fixed-point charge).
+and one step. Every particle is compared with the oracle applied to its
+initial state in the oracle's own field of the initial charge (mixed path:
+bit for bit, and the whole int64 deposit of the step node by node against
+the oracle's quantised deposit of its own pushed plasma; FP64 path: every
+particle and every node of rho within rounding), and properties that hold at
+any size are checked on the whole plasma (every particle in the bucket the
+table says, the exact fixed-point charge).
 
 The oracle's field comes from its own quantised deposit (bit-identical to
 the GPU's by construction of the fixed-point scheme) and its numpy FFT solve;
@@ -47,15 +50,18 @@ def _exact_total(I):
     return (int((I >> 32).sum()) << 32) + int((I & 0xFFFFFFFF).sum())
 
 
-def _gpu_init_and_step(torch, sim, walls=False):
+def _gpu_init_and_step(torch, sim, walls=False, field_out=None):
     """Initial sort (perm0), field, half push, one step (perm1). Returns
-    (input index of each final slot, fixed-point sums of the step, live count)."""
+    (input index of each final slot, fixed-point sums of the step, live count);
+    field_out (a list) receives the GPU's E^0 when given."""
     c, p = sim.ctx, sim.p
     n = sim.n
     perm0 = torch.zeros(n, dtype=torch.int32, device="cuda")
     c.sort_by_cell(p, perm=perm0)
     c.deposit(p, sim.rho)
     c.field_solve(sim.rho, sim.E, sim.E32, sim.we0)
+    if field_out is not None:
+        field_out.append(sim.E.cpu().numpy().copy())
     c.gather_push(p, sim.E32 if sim.mixed else sim.E, dt_scale=-0.5, move=False)
     perm1 = torch.zeros(n, dtype=torch.int32, device="cuda")
     Iout = torch.zeros(c.G, dtype=torch.int64 if sim.mixed else torch.float64, device="cuda")
@@ -74,9 +80,22 @@ def _check_buckets(d, w, tile, nlive):
     assert np.array_equal(np.repeat(np.arange(len(bs) - 1), np.diff(bs)), key)
 
 
+def _stencil_nodes(ix, iy, nx, ny):
+    """Flat indices of the four CIC nodes of each cell (ix, iy)."""
+    ip, jp = (ix + 1) % nx, (iy + 1) % ny
+    return [iy * nx + ix, iy * nx + ip, jp * nx + ix, jp * nx + ip]
+
+
 @pytest.mark.parametrize("name,pusher", [("thermal_2d", "boris"), ("magnetized_2d3v", "boris"),
                                          ("magnetized_2d3v", "hc")])
-def test_full_size_mixed_2d_sampled(torch, name, pusher):
+def test_full_size_mixed_2d(torch, name, pusher):
+    """Every particle of the step bit for bit against the oracle's binary32
+    push of the whole plasma, and the step's int64 deposit node by node
+    against the oracle's quantised deposit of that pushed plasma. The oracle
+    solves its own field; where its binary32 rounding differs from the GPU's
+    (an FP64 value within rounding noise of a binary32 boundary, about one
+    chance in 1e8 per node), the particles that gather from such a node and
+    the nodes they deposit on are left out, and the test says how many."""
     from paper_2608_15249_amd.sim import Simulation
     w = getattr(W, name)()
     c_light = 8.0 if pusher == "hc" else 0.0
@@ -85,59 +104,82 @@ def test_full_size_mixed_2d_sampled(torch, name, pusher):
     n = len(x)
     sim = Simulation(w, "mixed", state=state, tile="auto" if pusher == "boris" else (16, 16), pusher=pusher,
                      c_light=c_light)
-    ids, I, nlive = _gpu_init_and_step(torch, sim)
+    Eg = []
+    ids, I, nlive = _gpu_init_and_step(torch, sim, field_out=Eg)
     d = sim.p.download()
     S = sim.ctx.frac_bits
     s = O.Setup(2, w.vdim, w.nx, w.Lx, n, w.dt, ny=w.ny, Ly=w.Ly, bz=w.bz)
     m = _mixed_cells(w, x, y)
     I0 = O.deposit_quantised(s, m["ix"], m["ox"], S, m["iy"], m["oy"])
     E32 = tuple(e.astype(np.float32) for e in O.solve_field(s, O.rho_from_quantised(s, I0, S)))
-    rng = np.random.default_rng(101)
-    idx = rng.choice(n, 4096, replace=False)
-    src = ids[idx]
-    m0 = {k: v[src] for k, v in m.items()}
-    m0["vx"], m0["vy"] = vx[src].astype(np.float32), vy[src].astype(np.float32)
+    G = w.nx * w.ny
+    off = np.zeros(G, bool)
+    for k in range(2):
+        off |= Eg[0][k * G:(k + 1) * G].astype(np.float32) != E32[k].ravel()
+    m0 = dict(m)
+    m0["vx"], m0["vy"] = vx.astype(np.float32), vy.astype(np.float32)
     if w.vdim == 3:
-        m0["vz"] = vz[src].astype(np.float32)
+        m0["vz"] = vz.astype(np.float32)
     kw = dict(dim=2, vdim=w.vdim, nx=w.nx, ny=w.ny, dx=w.dx, dy=w.dy, qm=-1.0, dt=w.dt, bz=w.bz, pusher=pusher,
               c=c_light if pusher == "hc" else float("inf"))
     half = OM.push(m0, E32, dt_scale=-0.5, move=False, **kw)
     ref = OM.push(half, E32, **kw)
-    ix, iy = W.unpack_cell(d["cell"][idx], 2)
-    got = {"ix": ix, "iy": iy, "ox": d["ox"][idx], "oy": d["oy"][idx], "vx": d["vx"][idx], "vy": d["vy"][idx]}
+    del half, m0
+    # particles that gather from a node whose binary32 field differs
+    bad = np.zeros(n, bool)
+    if off.any():
+        for nd in _stencil_nodes(m["ix"].astype(np.int64), m["iy"].astype(np.int64), w.nx, w.ny):
+            bad |= off[nd]
+    print("nodes with a differently rounded binary32 field: %d, particles left out: %d" % (off.sum(), bad.sum()))
+    assert bad.sum() <= 1e-4 * n
+    good = ~bad[ids]                       # in the GPU's order
+    ix, iy = W.unpack_cell(d["cell"], 2)
+    got = {"ix": ix, "iy": iy, "ox": d["ox"], "oy": d["oy"], "vx": d["vx"], "vy": d["vy"]}
     if w.vdim == 3:
-        got["vz"] = d["vz"][idx]
+        got["vz"] = d["vz"]
     for k in got:
-        assert np.array_equal(got[k], ref[k]), k
+        assert np.array_equal(got[k][good], ref[k][ids][good]), k
+    # the whole deposit, node by node
+    Iref = O.deposit_quantised(s, ref["ix"], ref["ox"], S, ref["iy"], ref["oy"]).ravel()
+    keep = np.ones(G, bool)
+    if bad.any():
+        for nd in _stencil_nodes(ref["ix"][bad].astype(np.int64), ref["iy"][bad].astype(np.int64), w.nx, w.ny):
+            keep[nd] = False
+    assert np.array_equal(I.ravel()[keep], Iref[keep])
     assert nlive == n
     _check_buckets(d, w, sim.ctx.tile, n)
     assert _exact_total(I) == n << (2 * S)
 
 
-def test_full_size_fp64_thermal_2d_sampled(torch):
+@pytest.mark.parametrize("name", ["thermal_2d", "magnetized_2d3v"])
+def test_full_size_fp64(torch, name):
+    """FP64 path at full size: every particle after the step against the
+    oracle's FP64 half push and step of the whole plasma in its own field,
+    and the step's charge density node by node (both within rounding: the
+    GPU sums its FP64 atomics in another order)."""
     from paper_2608_15249_amd.sim import Simulation
-    w = W.thermal_2d()
+    w = getattr(W, name)()
     state = W.sample(w)
-    x, y, vx, vy, _ = state
+    x, y, vx, vy, vz = state
     n = len(x)
     sim = Simulation(w, "fp64", state=state, tile="auto")
-    ids, _, nlive = _gpu_init_and_step(torch, sim)
+    ids, rho_g, nlive = _gpu_init_and_step(torch, sim)
     d = sim.p.download()
-    s = O.Setup(2, 2, w.nx, w.Lx, n, w.dt, ny=w.ny, Ly=w.Ly)
-    E0 = O.solve_field(s, O.deposit(s, O.State.from_arrays(x, vx, y, vy)))
-    rng = np.random.default_rng(102)
-    idx = rng.choice(n, 4096, replace=False)
-    src = ids[idx]
-    sub = dataclasses.replace(s, n_particles=len(src))
-    st = O.State.from_arrays(x[src], vx[src], y[src], vy[src])
-    O.boris(sub, st, O.gather(sub, st, E0), -0.5 * s.dt)
-    O.boris(sub, st, O.gather(sub, st, E0), s.dt)
-    O.move(sub, st)
-    for k, r in (("vx", st.vx), ("vy", st.vy)):
-        assert np.max(np.abs(d[k][idx] - r)) <= 1e-12, k
+    s = O.Setup(2, w.vdim, w.nx, w.Lx, n, w.dt, ny=w.ny, Ly=w.Ly, bz=w.bz)
+    st = O.State.from_arrays(x, vx, y, vy, vz)
+    E0 = O.solve_field(s, O.deposit(s, st))
+    O.boris(s, st, O.gather(s, st, E0), -0.5 * s.dt)
+    O.boris(s, st, O.gather(s, st, E0), s.dt)
+    O.move(s, st)
+    comps = (("vx", st.vx), ("vy", st.vy)) + ((("vz", st.vz),) if w.vdim == 3 else ())
+    for k, r in comps:
+        assert np.max(np.abs(d[k] - r[ids])) <= 1e-12, k
     for k, r, L in (("x", st.x, s.Lx), ("y", st.y, s.Ly)):
-        dd = np.abs(d[k][idx] - r)
+        dd = np.abs(d[k] - r[ids])
         assert np.max(np.minimum(dd, L - dd)) <= 1e-12 * L, k
+    rho_o = O.deposit(s, st)
+    assert np.max(np.abs(rho_g.reshape(rho_o.shape) - rho_o)) <= 1e-12 * np.max(np.abs(rho_o))
+    assert nlive == n
 
 
 def test_full_size_mixed_walls_sampled(torch):
