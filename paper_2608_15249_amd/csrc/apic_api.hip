@@ -226,6 +226,8 @@ PushC push_coeffs(const apic_ctx *c, double dt_scale, int move) {
     pc.dtdx = (float)(c->d.dt / dx);
     pc.dtdy = (float)(c->d.dt / dy);
     pc.dtdz = (float)(c->d.dt / dz);
+    pc.dtdx2 = pc.dtdx * pc.dtdx;
+    pc.dtdy2 = pc.dtdy * pc.dtdy;
     pc.move = move;
     pc.rot = c->d.bz != 0.0;
     pc.deep = 0.25f;

@@ -569,9 +569,22 @@ __device__ __forceinline__ void gather_global3(const ET *E, const Geo &g, int ix
 template <bool MIX> struct AccOf { using T = double; };
 template <> struct AccOf<true> { using T = unsigned long long; };
 
+// Accumulator adds with the address space stated: a device-memory atomic
+// (acc_add) and an LDS atomic (acc_add_lds, ds_add_u64 / ds_add_f64). Left
+// generic, the compiler may merge an LDS and a global add into one flat
+// atomic, which tests the address space per lane and holds the vector-memory
+// wait counter, so that the next wait for a particle load also waits for it.
 template <bool MIX>
 __device__ __forceinline__ void acc_add(typename AccOf<MIX>::T *a, typename AccOf<MIX>::T v) {
-    atomicAdd(a, v);
+    using T = typename AccOf<MIX>::T;
+    __hip_atomic_fetch_add((__attribute__((address_space(1))) T *)a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool MIX>
+__device__ __forceinline__ void acc_add_lds(typename AccOf<MIX>::T *a, typename AccOf<MIX>::T v) {
+    using T = typename AccOf<MIX>::T;
+    __hip_atomic_fetch_add((__attribute__((address_space(3))) T *)a, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // CIC weights of a particle at (fx, fy) as accumulator values. Fixed point:

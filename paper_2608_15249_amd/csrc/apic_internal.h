@@ -40,6 +40,7 @@ struct PushC {
     float af, tf, sf;
     double dt;            // position step (unscaled dt)
     float dtdx, dtdy, dtdz;  // dt/dx, dt/dy, dt/dz in binary32 (mixed path)
+    float dtdx2, dtdy2;      // their squares (the deep test of a rotating push)
     int move;
     int rot;              // bz != 0 (the push rotates v in the x-y plane)
     float deep;           // slack (cells) that makes a staying particle "deep"
@@ -103,8 +104,8 @@ constexpr int kMaxSpecBlocks = 4096;   // per-block partials of the field energi
 #endif
 constexpr int kSWaves = APIC_STEP_WAVES;
 constexpr int kSBlock = 64 * kSWaves;
-constexpr int kStepTab = kSWaves * 28; // per-bucket direction table entries, at most (waves x 28 directions in 3D)
-constexpr int kDeepTab = 2 * kSWaves;   // per-bucket deep-range entries (waves x (start, count))
+constexpr int kStepTab = 28;   // per-bucket direction table entries, at most (28 directions in 3D)
+constexpr int kDeepTab = 2;    // per-bucket deep-range entries (start, count)
 
 // ---- launchers (apic_kernels.hip) -----------------------------------------
 // All return hipSuccess or the launch error.

@@ -54,11 +54,11 @@ template <int DIM> struct Dir {
     static constexpr int kN = (DIM == 3) ? 28 : 10;      // direction codes (near + far)
     static constexpr int kFar = kN - 1;
     static constexpr int kStay = (DIM == 3) ? 13 : 4;    // the code of a particle that stays
-    static constexpr int kTab = kSWaves * kN;            // per-bucket table entries
+    static constexpr int kTab = kN;                      // per-bucket table entries (one per direction)
     static constexpr int kCodeBits = (DIM == 3) ? 5 : 4; // bits of a near code
 };
 static_assert(Dir<3>::kTab <= kStepTab && Dir<2>::kTab <= kStepTab, "direction table size");
-static_assert(kDeepTab == 2 * kSWaves, "deep table size");
+static_assert(kDeepTab == 2, "deep table size");
 
 // Tile coordinates of bucket b (tiles numbered x fastest, then y, then z).
 template <int DIM>
@@ -663,18 +663,18 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(Geo g, Parts p, const 
         if constexpr (DIM == 3) inl = inl && lz >= 0 && lz <= wz - 2;
         if (inl) {
             int a = (lz * wy + ly) * wx + lx;
-            acc_add<MIX>(&sA[a], w[0]);
-            acc_add<MIX>(&sA[a + 1], w[1]);
+            acc_add_lds<MIX>(&sA[a], w[0]);
+            acc_add_lds<MIX>(&sA[a + 1], w[1]);
             if constexpr (DIM >= 2) {
-                acc_add<MIX>(&sA[a + wx], w[2]);
-                acc_add<MIX>(&sA[a + wx + 1], w[3]);
+                acc_add_lds<MIX>(&sA[a + wx], w[2]);
+                acc_add_lds<MIX>(&sA[a + wx + 1], w[3]);
             }
             if constexpr (DIM == 3) {
                 const int wxy = wx * wy;
-                acc_add<MIX>(&sA[a + wxy], w[4]);
-                acc_add<MIX>(&sA[a + wxy + 1], w[5]);
-                acc_add<MIX>(&sA[a + wxy + wx], w[6]);
-                acc_add<MIX>(&sA[a + wxy + wx + 1], w[7]);
+                acc_add_lds<MIX>(&sA[a + wxy], w[4]);
+                acc_add_lds<MIX>(&sA[a + wxy + 1], w[5]);
+                acc_add_lds<MIX>(&sA[a + wxy + wx], w[6]);
+                acc_add_lds<MIX>(&sA[a + wxy + wx + 1], w[7]);
             }
         } else {
             raise_err(c.err, ERR_ORDER);
@@ -772,21 +772,14 @@ __global__ void __launch_bounds__(kBlock) k_gather_push_tiled(Geo g, Parts p, co
 
 // ---- fused step, pass 1: direction tallies ------------------------------------
 // Same arithmetic as k_step_push up to the new cell; keeps only the tallies
-// per (bucket, wave, direction) and counts far movers at their destination.
+// per (bucket, direction) and counts far movers at their destination.
 // U particles per thread are loaded before any is processed (more loads in
 // flight per wave).
 //
-// Deep ranges (see the push pass) are skipped when the tile's field cannot
+// The deep range (see the push pass) is skipped when the tile's field cannot
 // move a deep particle out of the tile: 2|a| max|E| dt/dx, with slack for
-// rounding, below pc.deep. Their particles are credited as stays to the waves
-// that own their indices; the remaining particles run the full computation and
-// are tallied with LDS atomics into their owning waves' entries.
-
-// Number of indices k in [lo, hi) owned by wave w (k mod kSBlock in [64w, 64w+64)).
-__device__ __forceinline__ int owned_by(int lo, int hi, int w) {
-    auto f = [w](int x) { return (x / kSBlock) * 64 + min(max((x % kSBlock) - 64 * w, 0), 64); };
-    return hi > lo ? f(hi) - f(lo) : 0;
-}
+// rounding, below pc.deep. Its particles are credited as stays; the remaining
+// particles run the full computation and are tallied with LDS atomics.
 // EM: the electromagnetic form (FP64 2D3V): E is the [6][G] Yee field.
 template <bool MIX, int DIM, int VDIM, int U, bool HC, bool EM>
 __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const int32_t *bstart, const double *E,
@@ -825,9 +818,7 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
         // tallies agree)
         const int sh = i0 & (MIX ? 31 : 15);
         const int send = span > 0 ? span + sh : 0;
-        int draw[2 * kSWaves];
-#pragma unroll
-        for (int r = 0; r < 2 * kSWaves; ++r) draw[r] = deep[b * kDeepTab + r];
+        const int draw0 = deep[b * kDeepTab], draw1 = deep[b * kDeepTab + 1];
         if constexpr (EM)
             load_f_tile<R>((R *)smem, E, g, x0, y0, fw, fh);
         else if constexpr (DIM == 3)
@@ -885,38 +876,16 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
         bool skip = kick * emx * pc.dtdx + 0.0009765625f <= pc.deep;
         if constexpr (DIM >= 2) skip = skip && kick * emy * pc.dtdy + 0.0009765625f <= pc.deep;
         if constexpr (DIM == 3) skip = skip && kick * emz * pc.dtdz + 0.0009765625f <= pc.deep;
-        // deep ranges of this bucket: increasing, disjoint, inside [0, span)
-        int da[kSWaves], dc[kSWaves], ndeep = 0;
-        {
-            int lo = 0;
-#pragma unroll
-            for (int r = 0; r < kSWaves; ++r) {
-                const int st = skip ? min(max(draw[2 * r], lo), span) : lo;
-                const int ct = skip ? min(max(draw[2 * r + 1], 0), span - st) : 0;
-                da[r] = st;
-                dc[r] = ct;
-                lo = st + ct;
-                ndeep += ct;
-            }
-        }
+        // the deep range of this bucket, inside [0, span)
+        const int da = skip ? min(max(draw0, 0), span) : 0;
+        const int ndeep = skip ? min(max(draw1, 0), span - da) : 0;
         if (ndeep > 0) {
-            if ((threadIdx.x & 63) == 0) {
-                int st = 0;
-#pragma unroll
-                for (int r = 0; r < kSWaves; ++r) st += owned_by(da[r] + sh, da[r] + dc[r] + sh, w);
-                atomicAdd(&sCnt[w * kDirs + kStay], st);
-            }
+            if (threadIdx.x == 0) atomicAdd(&sCnt[kStay], ndeep);
             // the shallow particles: indices of [0, span) outside the deep
-            // ranges, two register sets with each chunk's loads issued one
+            // range, two register sets with each chunk's loads issued one
             // chunk ahead of its use
             const int nsh = span - ndeep;
-            auto kmap = [&](int t) {
-                int k = t;
-#pragma unroll
-                for (int r = 0; r < kSWaves; ++r)
-                    if (k >= da[r]) k += dc[r];
-                return k;
-            };
+            auto kmap = [&](int t) { return t >= da ? t + ndeep : t; };
             auto sfetch = [&](Raw<MIX> &r1, int t) {
                 load_raw<MIX, DIM, VDIM>(p, i0 + kmap(min(t, nsh - 1)), r1);
                 __builtin_amdgcn_sched_barrier(0);
@@ -939,7 +908,7 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
                 if (g.walls && q.ix >= g.nxp) return;   // absorbed by a wall: leaves the order
                 const int code = dir_local<DIM>(tn, lx + sx, ly + sy, lz + sz);
                 if (code < kFar) {
-                    atomicAdd(&sCnt[(((k + sh) % kSBlock) >> 6) * kDirs + code], 1);
+                    atomicAdd(&sCnt[code], 1);
                 } else {
                     const int nbk = bucket_of<MIX, DIM>(g, q.ix, q.iy, q.iz);
                     atomicAdd(&farcnt[nbk], 1);
@@ -998,7 +967,7 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
                     const uint64_t bb = __ballot(near && ((code >> bit) & 1));
                     peers &= ((code >> bit) & 1) ? bb : ~bb;
                 }
-                if (near && (peers & lt) == 0) sCnt[w * kDirs + code] += (int)__popcll(peers);
+                if (near && (peers & lt) == 0) atomicAdd(&sCnt[code], (int)__popcll(peers));
                 if (code == kFar) {
                     atomicAdd(&farcnt[nbk], 1);
                     atomicAdd(&tot[nbk], 1);
@@ -1016,8 +985,7 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
         __syncthreads();
         if (threadIdx.x < kTab) cnt[b * kTab + threadIdx.x] = sCnt[threadIdx.x];
         if (threadIdx.x < kFar) {
-            int v = 0;
-            for (int w2 = 0; w2 < kSWaves; ++w2) v += sCnt[w2 * kDirs + threadIdx.x];
+            const int v = sCnt[threadIdx.x];
             if (v) atomicAdd(&tot[dir_target<DIM>(g, bx, by, bz, threadIdx.x)], v);
         }
         __syncthreads();
@@ -1027,30 +995,25 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
 }
 
 // ---- fused step: first slot of every tally inside its destination bucket -----
-// One wave per destination bucket nbk: its incoming tallies, in (direction,
-// source wave) order, are prefix-summed from the bucket's new start. Every
-// (source bucket, wave, near direction) entry has exactly one destination, so
-// each offs entry is written once.
+// One wave per destination bucket nbk: its incoming tallies, in direction
+// order, are prefix-summed from the bucket's new start. Every (source bucket,
+// near direction) entry has exactly one destination, so each offs entry is
+// written once.
 template <int DIM>
 __device__ __forceinline__ void dest_offsets_wave(const Geo &g, int nbk, int run, const int32_t *cnt, int32_t *offs) {
-    constexpr int kDirs = Dir<DIM>::kN, kFar = Dir<DIM>::kFar, kTab = Dir<DIM>::kTab;
-    constexpr int kIn = kFar * kSWaves;  // incoming entries per destination
+    constexpr int kFar = Dir<DIM>::kFar, kTab = Dir<DIM>::kTab;
+    static_assert(kFar <= 64, "one lane per incoming direction");
     const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int r = 0; r < (kIn + 63) / 64; ++r) {
-        const int e = r * 64 + lane;    // entry e = d * kSWaves + wave
-        const bool ok = e < kIn;
-        const int d = ok ? e / kSWaves : 0, wv = ok ? e % kSWaves : 0;
-        const int src = ok ? dir_source<DIM>(g, nbk, d) : 0;
-        const int v = ok ? cnt[src * kTab + wv * kDirs + d] : 0;
-        int inc = v;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(inc, o);
-            if (lane >= o) inc += y;
-        }
-        if (ok) offs[src * kTab + wv * kDirs + d] = run + inc - v;
-        run += __shfl(inc, 63);
+    const bool ok = lane < kFar;
+    const int d = ok ? lane : 0;
+    const int src = ok ? dir_source<DIM>(g, nbk, d) : 0;
+    const int v = ok ? cnt[src * kTab + d] : 0;
+    int inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
     }
+    if (ok) offs[src * kTab + d] = run + inc - v;
 }
 
 template <int DIM>
@@ -1112,11 +1075,18 @@ __global__ void __launch_bounds__(kSBlock) k_scan_offsets(Geo g, const int32_t *
 }
 
 // ---- fused step, pass 2: push, deposit, scatter into the next bucket order -----
+// Slots are handed out per workgroup: each direction of the bucket (its stay
+// range, and its range inside every neighbour bucket) is filled in the order
+// of the bucket's chunks, and within a chunk in wave order, then lane order.
+// After each chunk the waves publish their counts in LDS and, past one
+// barrier, every wave takes its offsets from the counts of the waves before
+// it. The bucket then writes to one advancing run per range instead of one
+// per (wave, range): far fewer concurrent write streams into HBM.
 // Staying particles are split by how far they sit from their tile's edges
 // after the move: a particle whose distance to every edge exceeds its own
 // displacement at the current velocity, |v| dt/dx, by at least pc.deep cells
-// is "deep" and takes its slot from the front of its wave's stay range; the
-// others fill that range from the back. The deep part of each range goes to
+// is "deep" and takes its slot from the front of the bucket's stay range; the
+// others fill that range from the back. The deep part of the range goes to
 // the deep table, so that the next count pass can credit those particles as
 // stays without reading them, as long as the field's share of the next move,
 // 2|a| max|E| dt/dx, stays below pc.deep.
@@ -1147,11 +1117,15 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sErr;
     __shared__ double sRed[kSWaves];
-    __shared__ int32_t sRun[kTab];
-    __shared__ int32_t sRunEnd[kTab];  // end of each (wave, direction) tally's slot range
-    __shared__ int32_t sEnd[kFar];   // end of each neighbour destination bucket (slot bound)
-    __shared__ int32_t sBack[kSWaves];    // next free slot, from the back, of each wave's stay range
-    __shared__ int32_t sFront0[kSWaves];  // first slot of each wave's stay range
+    __shared__ int32_t sRunEnd[kTab];  // end of each direction's slot range
+    __shared__ int32_t sEnd[kFar];     // end of each destination bucket (slot bound)
+    __shared__ int32_t sStay[2];       // the stay range [first, end)
+    __shared__ int32_t sCur[kSWaves][kTab];  // each wave's copy of the movers' next slots
+    // per-chunk counts, double-buffered by chunk parity: each wave's movers per
+    // direction (valid when its flag is set) and a packed word with its deep
+    // count, shallow count and mover flag
+    __shared__ int32_t sMv[2][kSWaves][kTab];
+    __shared__ int32_t sPk[2][kSWaves];
     const int ex_w = (1 << g.tsx) + 1, ey_w = (DIM >= 2) ? (1 << g.tsy) + 1 : 1;
     const int ez_w = (DIM == 3) ? (1 << g.tsz) + 1 : 1;
     const int wx = (1 << g.tsx) + 1 + 2 * g.halo;
@@ -1167,6 +1141,8 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
     R *sE = (R *)(smem + ((acc_bytes + 15) & ~(size_t)15));
     const int w = threadIdx.x >> 6;
     const uint64_t lt = lanemask_lt();
+    const int lane = (int)(threadIdx.x & 63);
+    int it = 0;   // chunks processed by this workgroup (the parity picks the count table)
     if (threadIdx.x == 0) sErr = 0;
     int first, end, stride;
     bucket_walk(g.nbuckets, first, end, stride);
@@ -1198,22 +1174,23 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
             const int na = EM ? 3 * jw * jh : wxy * wz;
             for (int t2 = threadIdx.x; t2 < na; t2 += blockDim.x) sA[t2] = (A)0;
         }
-        // first slot of each (wave, direction) tally of this bucket inside its
-        // destination bucket (from the offsets pass), and each destination's end
+        // first slot of each direction of this bucket inside its destination
+        // bucket (from the offsets pass), and each destination's end
         if (threadIdx.x < kTab) {
-            const int w2 = threadIdx.x / kDirs, d = threadIdx.x % kDirs;
+            const int d = threadIdx.x;
             int off = 0, ct = 0;
             if (d < kFar) {
-                off = offs[b * kTab + threadIdx.x];
-                ct = cnt[b * kTab + threadIdx.x];
-                if (w2 == 0) sEnd[d] = bstart_new[dir_target<DIM>(g, bx, by, bz, d) + 1];
+                off = offs[b * kTab + d];
+                ct = cnt[b * kTab + d];
+                sEnd[d] = bstart_new[dir_target<DIM>(g, bx, by, bz, d) + 1];
                 if (d == kStay) {
-                    sFront0[w2] = off;
-                    sBack[w2] = off + ct;
+                    sStay[0] = off;
+                    sStay[1] = off + ct;
                 }
             }
-            sRun[threadIdx.x] = off;
-            sRunEnd[threadIdx.x] = off + ct;
+#pragma unroll
+            for (int w2 = 0; w2 < kSWaves; ++w2) sCur[w2][d] = off;
+            sRunEnd[d] = off + ct;
         }
         if constexpr (EM)
             load_f_tile<R>(sE, E, g, x0, y0, fw, fh);
@@ -1222,10 +1199,11 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
         else
             load_e_tile<R, double, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
         __syncthreads();
-        // this wave's stay cursors (front: next deep slot, back: one past the
-        // next shallow slot) and the end of the bucket, uniform over the wave
-        int front = __builtin_amdgcn_readfirstlane(sRun[w * kDirs + kStay]);
-        int back = __builtin_amdgcn_readfirstlane(sBack[w]);
+        // the bucket's stay cursors (front: next deep slot, back: one past the
+        // next shallow slot), the same in every wave, and the end of the bucket
+        const int front0 = __builtin_amdgcn_readfirstlane(sStay[0]);
+        int front = front0;
+        int back = __builtin_amdgcn_readfirstlane(sStay[1]);
         const int stayEnd = __builtin_amdgcn_readfirstlane(sEnd[kStay]);
         // cells of this tile (the last tile of an axis may be cut by the grid edge)
         const float txe = (float)tn.txe;
@@ -1282,7 +1260,7 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
                     }
                     if (!good) atomicOr(&sErr, ERR_DOMAIN);
                     const double v2n = vsq<MIX, VDIM, HC>(q, pc);
-                    ke += 0.5 * (v2o + v2n);
+                    ke += v2o + v2n;   // halved once per bucket (exact: a power of two)
                     px += (double)q.vx;
                     code = dir_local<DIM>(tn, lx + sx, ly + sy, lz + sz);
                     // absorbed by a wall: no deposit, no slot
@@ -1299,17 +1277,23 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
                             const float uy = (float)(q.iy - y0) + (float)q.fy;
                             const float my = fminf(uy, tye - uy) - pc.deep;
                             const float vy = fabsf((float)q.vy);
+                            // with a rotation the speed can turn along either axis:
+                            // compared as squares, |v| dt/dx <= m <=> |v|^2 (dt/dx)^2
+                            // <= m^2 for m >= 0 (the rounding of either side,
+                            // a few ulps, is far inside the margin pc.deep keeps)
                             if constexpr (EM) {
                                 // a general B can turn the whole speed along either axis
                                 const float vz = (float)q.vz;
-                                const float vv = sqrtf(vx * vx + vy * vy + vz * vz);
-                                deep = mx >= vv * pc.dtdx && my >= vv * pc.dtdy;
+                                const float vv2 = vx * vx + vy * vy + vz * vz;
+                                deep = mx >= 0.0f && my >= 0.0f && mx * mx >= vv2 * pc.dtdx2 &&
+                                       my * my >= vv2 * pc.dtdy2;
                             } else if (!pc.rot) {
                                 deep = mx >= vx * pc.dtdx && my >= vy * pc.dtdy;
                             } else {
-                                // the rotation can turn the in-plane speed along either axis
-                                const float vv = sqrtf(vx * vx + vy * vy);
-                                deep = mx >= vv * pc.dtdx && my >= vv * pc.dtdy;
+                                // the rotation about z turns the in-plane speed
+                                const float vv2 = vx * vx + vy * vy;
+                                deep = mx >= 0.0f && my >= 0.0f && mx * mx >= vv2 * pc.dtdx2 &&
+                                       my * my >= vv2 * pc.dtdy2;
                             }
                             if constexpr (DIM == 3) {
                                 // vz only takes the kicks of Ez (the rotation is about z)
@@ -1348,17 +1332,17 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
                     if constexpr (DIM == 3) inl = inl && (unsigned)dlz <= (unsigned)(wz - 2);
                     if (inl) {
                         const int a0 = (dlz * wy + dly) * wx + dlx;
-                        acc_add<MIX>(&sA[a0], wgt[0]);
-                        acc_add<MIX>(&sA[a0 + 1], wgt[1]);
+                        acc_add_lds<MIX>(&sA[a0], wgt[0]);
+                        acc_add_lds<MIX>(&sA[a0 + 1], wgt[1]);
                         if constexpr (DIM >= 2) {
-                            acc_add<MIX>(&sA[a0 + wx], wgt[2]);
-                            acc_add<MIX>(&sA[a0 + wx + 1], wgt[3]);
+                            acc_add_lds<MIX>(&sA[a0 + wx], wgt[2]);
+                            acc_add_lds<MIX>(&sA[a0 + wx + 1], wgt[3]);
                         }
                         if constexpr (DIM == 3) {
-                            acc_add<MIX>(&sA[a0 + wxy], wgt[4]);
-                            acc_add<MIX>(&sA[a0 + wxy + 1], wgt[5]);
-                            acc_add<MIX>(&sA[a0 + wxy + wx], wgt[6]);
-                            acc_add<MIX>(&sA[a0 + wxy + wx + 1], wgt[7]);
+                            acc_add_lds<MIX>(&sA[a0 + wxy], wgt[4]);
+                            acc_add_lds<MIX>(&sA[a0 + wxy + 1], wgt[5]);
+                            acc_add_lds<MIX>(&sA[a0 + wxy + wx], wgt[6]);
+                            acc_add_lds<MIX>(&sA[a0 + wxy + wx + 1], wgt[7]);
                         }
                     } else if constexpr (DIM == 3) {
                         deposit_global3<MIX>(acc, g, q.ix, q.iy, q.iz, wgt);
@@ -1367,41 +1351,79 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
                     }
                     }
                 }
-                // slot: consecutive per (wave, direction) in the order the wave meets
-                // them; each group's range is checked once against its bucket's end
-                // (the start is its offset-table entry, computed from the same scan).
+                // slot: in chunk order, then wave order, then lane order, per
+                // direction; each group's range is checked against its bucket's
+                // end (the start is its offset-table entry, from the same scan)
                 int slot = -1;
-                // stays: deep ones from the front of the wave's stay range, the
-                // rest from its back (wave-private cursors held in registers)
+                // this wave's counts: deep and shallow stays, and movers to a
+                // neighbour bucket (lanes sharing a code found with one ballot
+                // per code bit; the group's lowest lane records its size)
                 const uint64_t gst = __ballot(code == kStay);
                 const uint64_t gd = __ballot(code == kStay && deep);
                 const uint64_t gs = gst & ~gd;
                 const int nd = (int)__popcll(gd), ns = (int)__popcll(gs);
-                const bool sfits = front >= 0 && front + nd <= back - ns && back <= stayEnd;
-                if (code == kStay)
-                    slot = !sfits ? -1 : deep ? front + (int)__popcll(gd & lt) : back - 1 - (int)__popcll(gs & lt);
-                front += nd;
-                back -= ns;
-                // movers to a neighbour bucket: the lanes sharing a code are found
-                // with one ballot per code bit; each lane reads its group's
-                // cursor, the group's lowest lane advances it
                 const bool mv = code >= 0 && code < kFar && code != kStay;
                 const uint64_t gmv = __ballot(mv);
+                const int par = it & 1;
+                ++it;
+                uint64_t peers = 0;
                 if (gmv) {
-                    uint64_t peers = gmv;
+                    peers = gmv;
 #pragma unroll
                     for (int bit = 0; bit < kCodeBits; ++bit) {
                         const uint64_t bb = __ballot(mv && ((code >> bit) & 1));
                         peers &= ((code >> bit) & 1) ? bb : ~bb;
                     }
+                    if (lane < kTab) sMv[par][w][lane] = 0;
+                    if (mv && (peers & lt) == 0) sMv[par][w][code] = (int)__popcll(peers);
+                }
+                if (lane == 0) sPk[par][w] = nd | (ns << 8) | ((gmv != 0) << 16);
+                __syncthreads();
+                // the counts of the waves before this one, and of the whole chunk
+                int pd = 0, ps = 0, td = 0, ts = 0, anymv = 0;
+#pragma unroll
+                for (int w2 = 0; w2 < kSWaves; ++w2) {
+                    const int pk = sPk[par][w2];
+                    const int a = pk & 0xFF, bb = (pk >> 8) & 0xFF;
+                    if (w2 < w) {
+                        pd += a;
+                        ps += bb;
+                    }
+                    td += a;
+                    ts += bb;
+                    anymv |= pk >> 16;
+                }
+                // stays: deep ones from the front of the bucket's stay range,
+                // the rest from its back
+                const bool sfits = front >= 0 && front + td <= back - ts && back <= stayEnd;
+                if (code == kStay)
+                    slot = !sfits ? -1
+                                  : deep ? front + pd + (int)__popcll(gd & lt)
+                                         : back - 1 - ps - (int)__popcll(gs & lt);
+                front += td;
+                back -= ts;
+                if (anymv) {
+                    // lane d of every wave: this wave's first slot in direction d,
+                    // and the wave's copy of the cursor moved past the chunk
+                    int offd = 0;
+                    if (lane < kTab) {
+                        int pre = 0, tot = 0;
+#pragma unroll
+                        for (int w2 = 0; w2 < kSWaves; ++w2) {
+                            const int c2 = (sPk[par][w2] >> 16) ? sMv[par][w2][lane] : 0;
+                            if (w2 < w) pre += c2;
+                            tot += c2;
+                        }
+                        offd = sCur[w][lane] + pre;
+                        sCur[w][lane] += tot;
+                    }
+                    const int basek = __shfl(offd, mv ? code : 0);
                     if (mv) {
-                        const int e = w * kDirs + code;
-                        const int basek = sRun[e];
                         const int r = (int)__popcll(peers & lt), cntk = (int)__popcll(peers);
-                        // inside this tally's own range (and so inside its bucket)
-                        const bool fits = basek >= 0 && basek + cntk <= sRunEnd[e] && sRunEnd[e] <= sEnd[code];
+                        // inside this direction's own range (and so inside its bucket)
+                        const bool fits =
+                            basek >= 0 && basek + cntk <= sRunEnd[code] && sRunEnd[code] <= sEnd[code];
                         slot = fits ? basek + r : -1;
-                        if (r == 0) sRun[e] = basek + cntk;
                     }
                 }
                 if (code == kFar) {
@@ -1439,33 +1461,30 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
             }
             commit();
         } else {
+            // the fetches are unconditional (indices clamped to the span: at
+            // most a chunk of harmless re-reads past the end), so that every
+            // path issues the same loads and a wait for one chunk's data
+            // never waits for the chunk fetched after it
             for (int base = 0; base < send; base += 2 * CH) {
-                if (base + CH < send) fetch(rb, base + CH);
+                fetch(rb, base + CH);
                 process(ra, base);
-                if (base + 2 * CH < send) fetch(ra, base + 2 * CH);
+                fetch(ra, base + 2 * CH);
                 if (base + CH < send) process(rb, base + CH);
             }
         }
-        if (__lane_id() == 0) {
-            sRun[w * kDirs + kStay] = front;
-            sBack[w] = back;
-        }
         __syncthreads();
-        // every tally's range filled exactly: a count that differs from the
-        // push's (a particle the count pass credited as staying that moved,
-        // or the reverse) leaves a slot empty or overflows a range
-        if (threadIdx.x < kTab) {
-            const int w2 = threadIdx.x / kDirs, d = threadIdx.x % kDirs;
-            if (d < kFar) {
-                const bool full = d == kStay ? sRun[threadIdx.x] == sBack[w2] : sRun[threadIdx.x] == sRunEnd[threadIdx.x];
-                if (!full) atomicOr(&sErr, ERR_ORDER);
-            }
+        // every range filled exactly: a count that differs from the push's (a
+        // particle the count pass credited as staying that moved, or the
+        // reverse) leaves a slot empty or overflows a range
+        if (threadIdx.x < kFar) {
+            const int d = threadIdx.x;
+            const bool full = d == kStay ? front == back : sCur[0][d] == sRunEnd[d];
+            if (!full) atomicOr(&sErr, ERR_ORDER);
         }
-        if (threadIdx.x < kSWaves) {
-            // deep range of each wave's stays, relative to this bucket's new start
-            const int t = threadIdx.x;
-            deep_out[b * kDeepTab + 2 * t] = sFront0[t] - bstart_new[b];
-            deep_out[b * kDeepTab + 2 * t + 1] = sRun[t * kDirs + kStay] - sFront0[t];
+        if (threadIdx.x == 0) {
+            // the deep range of the stays, relative to this bucket's new start
+            deep_out[b * kDeepTab] = front0 - bstart_new[b];
+            deep_out[b * kDeepTab + 1] = front - front0;
         }
         if constexpr (EM)
             flush_j((double *)acc, (const double *)sA, g, x0, y0, jw, jh);
@@ -1474,7 +1493,7 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
         else
             flush_region<MIX, DIM>(acc, sA, g, x0, y0, wx, wy, g.halo);
         if (part) {
-            double kt = block_sum(ke, sRed);
+            double kt = 0.5 * block_sum(ke, sRed);
             double pt = block_sum(px, sRed);
             if (threadIdx.x == 0) {
                 part[2 * b] = kt;
