@@ -534,7 +534,9 @@ const char *apic_batch_last_error(const apic_batch *b);
 /* ---- autotuning -------------------------------------------------------------
  * Setup calls (host, synchronous; they allocate scratch device memory and
  * contexts of their own and must not run under graph capture). Each times
- * nsteps steps per candidate on a private copy of the caller's particles
+ * every candidate on a private copy of the caller's particles (tiles: four
+ * warm-up steps, then the faster of two runs of nsteps steps, rounded up to
+ * even; batch chunks: nsteps steps)
  * (the caller's arrays are only read), returns the fastest candidate and
  * its ms per step, and caches the pick for the process: a later call for the
  * same shape returns the cached pick with *ms_per_step = -1 (may be NULL).

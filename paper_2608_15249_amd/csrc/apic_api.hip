@@ -466,7 +466,8 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     size_t bytes = align256(sizeof(int)) * 2 + align256(sizeof(double) * 2 * g.nbuckets) +
                    align256(sizeof(double) * kMaxSpecBlocks) + align256(sizeof(double)) +
                    align256(sizeof(double) * hx) * 2 + align256(sizeof(double) * g.ny) * 2 +
-                   align256(sizeof(double) * g.nz) * 2 + align256(tw_bytes) + align256(4 * sizeof(int64_t));
+                   align256(sizeof(double) * g.nz) * 2 + align256(tw_bytes) +
+                   align256(((size_t)kQSlots * kQStride + 2) * sizeof(int64_t));
     if (hipMalloc(&c->dev_block, bytes) != hipSuccess) { delete c; return APIC_ENOMEM; }
     if (hipMemset(c->dev_block, 0, bytes) != hipSuccess) { (void)hipFree(c->dev_block); delete c; return APIC_EHIP; }
     char *b = (char *)c->dev_block;
@@ -485,9 +486,9 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     c->dev.kapz = (double *)take(sizeof(double) * g.nz);
     c->dev.tw = c->fused_fft ? (double *)take(tw_bytes) : nullptr;
     {
-        int64_t *q = (int64_t *)take(4 * sizeof(int64_t));
+        int64_t *q = (int64_t *)take(((size_t)kQSlots * kQStride + 2) * sizeof(int64_t));
         c->dev.qacc = (unsigned long long *)q;
-        c->dev.qexact = q + 2;
+        c->dev.qexact = q + (size_t)kQSlots * kQStride;
     }
     // modified wavenumbers of the periodic FD operators:
     //   K^2_d = (2/d sin(k d / 2))^2 (3-point second difference),

@@ -118,25 +118,34 @@ __device__ QSum qsum_block(QSum q, int sd) {
     return t;
 }
 
-// The block total added to acc[0] (whole) and acc[1] (remainder) with one
-// integer atomic each (read by a later launch).
+// The block total added with one integer atomic each for the whole part and
+// the remainder, into one of kQSlots counter pairs (one 128-byte line each,
+// picked by the block index: hundreds of blocks adding to a single pair
+// serialise on it) read by a later launch. Integer sums: exact in any order.
 __device__ void qsum_flush(QSum q, int sd, unsigned long long *acc) {
     const QSum t = qsum_block(q, sd);
     if (threadIdx.x == 0) {
-        if (t.whole) atomicAdd(&acc[0], (unsigned long long)t.whole);
-        if (t.rem) atomicAdd(&acc[1], (unsigned long long)t.rem);
+        unsigned long long *a = acc + (size_t)(blockIdx.x % kQSlots) * kQStride;
+        if (t.whole) atomicAdd(&a[0], (unsigned long long)t.whole);
+        if (t.rem) atomicAdd(&a[1], (unsigned long long)t.rem);
     }
 }
 
-// The normalised total of acc, which is then cleared for the next solve
-// (one thread of a launch after every launch that added to acc).
-__device__ __forceinline__ QSum qsum_take(unsigned long long *acc, int sd) {
-    QSum t{(int64_t)acc[0], (uint64_t)acc[1]};
-    t.whole += (int64_t)(t.rem >> sd);
-    t.rem &= (1ull << sd) - 1;
-    acc[0] = 0ull;
-    acc[1] = 0ull;
-    return t;
+// The normalised total of every slot, which are then cleared for the next
+// solve (the whole workgroup of a launch after every launch that added to
+// them; valid in thread 0).
+__device__ QSum qsum_take(unsigned long long *acc, int sd) {
+    QSum t{0, 0};
+    for (int i = threadIdx.x; i < kQSlots; i += blockDim.x) {
+        unsigned long long *a = acc + (size_t)i * kQStride;
+        t.whole += (int64_t)a[0];
+        t.rem += a[1];
+        t.whole += (int64_t)(t.rem >> sd);
+        t.rem &= (1ull << sd) - 1;
+        a[0] = 0ull;
+        a[1] = 0ull;
+    }
+    return qsum_block(t, sd);
 }
 
 // Charge of an exact particle count whole + rem 2^-sd.
@@ -774,6 +783,15 @@ __device__ void finalize_block(const FinArgs &f, const CtxDev &c) {
     k = block_sum(k, sRed);
     p = block_sum(p, sRed);
     e = block_sum(e, sRed);
+    // fixed-point node sums: the exact integer total (whole workgroup)
+    QSum qt{0, 0};
+    if (f.nspec && f.sd) {
+        qt = qsum_take(c.qacc, f.sd);
+        if (threadIdx.x == 0) {
+            c.qexact[0] = qt.whole;
+            c.qexact[1] = (int64_t)qt.rem;
+        }
+    }
     if (threadIdx.x == 0) {
         double *d = f.diag ? step_slot(f.diag, c) : nullptr;
         if (f.npush && d) {
@@ -785,10 +803,7 @@ __device__ void finalize_block(const FinArgs &f, const CtxDev &c) {
             double q = f.dV * (*c.rho0 - f.G * f.rho_ion);
             if (f.sd) {
                 // fixed-point node sums: the exact integer total
-                const QSum t = qsum_take(c.qacc, f.sd);
-                c.qexact[0] = t.whole;
-                c.qexact[1] = (int64_t)t.rem;
-                q = qsum_charge(t, f.sd, f.q_macro);
+                q = qsum_charge(qt, f.sd, f.q_macro);
             }
             if (f.walls) {
                 // the physical half of the odd extension, wall nodes at half weight

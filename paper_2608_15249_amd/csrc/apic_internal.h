@@ -57,6 +57,10 @@ struct Parts {
     void *vx, *vy, *vz;
 };
 
+// Exact-charge counter slots (see CtxDev::qacc).
+constexpr int kQSlots = 64;
+constexpr int kQStride = 16;   // 64-bit words per slot (a 128-byte line)
+
 // Device scratch owned by the context.
 struct CtxDev {
     int *err;             // error bits
@@ -70,9 +74,10 @@ struct CtxDev {
     double *tw;           // fused 2D field solve: exp(-2 pi i k / nmax), k < nmax, interleaved (re, im)
     // exact charge of a fixed-point accumulation (mixed path): the launch that
     // converts the node sums adds (whole particles, remainder in units of
-    // 2^-(S dim) particle) to qacc with integer atomics; the diagnostics
-    // workgroup moves the normalised pair to qexact and clears qacc
-    unsigned long long *qacc;   // [2]
+    // 2^-(S dim) particle) to qacc with integer atomics, spread over counter
+    // slots; the diagnostics workgroup moves the normalised total to qexact
+    // and clears the slots
+    unsigned long long *qacc;   // [kQSlots * kQStride] (slot i: words 16 i, 16 i + 1)
     int64_t *qexact;            // [2]
 };
 
