@@ -14,10 +14,15 @@
 //      the centred difference), with the per-block Parseval partial of
 //      sum |E_hat|^2. Inverse FFT along y of phi_hat and kappa_y phi_hat; the
 //      x-spectrum Z of the complex field Ex + i Ey follows at columns kx and
-//      nx - kx from the Hermitian symmetry of the two real fields.
-//   3. k_fft_rows_inv: one workgroup per row. Inverse FFT along x of Z:
-//      Ex = Re, Ey = Im (and their binary32 rounding). The launch's last
-//      workgroup reduces the diagnostics.
+//      nx - kx from the Hermitian symmetry of the two real fields. Z is
+//      stored column by column ([nx][ny]), so that each workgroup writes its
+//      two columns as whole contiguous lines (stores that cover part of a
+//      line measured far slower than whole-line stores).
+//   3. k_fft_rows_inv: one workgroup per row. Inverse FFT along x of Z (a
+//      strided read of the column-major Z; the rows of one XCD are adjacent,
+//      so its L2 serves each fetched line to eight rows): Ex = Re, Ey = Im
+//      (and their binary32 rounding). The launch's last workgroup reduces
+//      the diagnostics.
 // The same mathematics as the general path (library real-to-complex
 // transforms, spectral division, real-space centred difference); the
 // gradient is taken in spectral form, -i sin(k d)/d, which is the transform
@@ -275,15 +280,15 @@ __global__ void __launch_bounds__(kBlock) k_fft_cols(Geo g, const double2 *H, do
             Q = fft_lds<+1>(S2, (P == S) ? F : S, lgny, 1, tw, lgmax);
         }
         const bool self = kx == 0 || 2 * kx == nx;
+        const int64_t c0 = (int64_t)kx * ny, c1 = (int64_t)(nx - kx) * ny;   // column-major Z
         for (int y = threadIdx.x; y < ny; y += blockDim.x) {
             const double2 p = P[y], q = Q[y];
-            const int64_t row = (int64_t)y * nx;
             if (self) {
                 // a self-conjugate column of two real fields: their real parts
-                Z[row + kx] = make_double2(kax * p.y, q.y);
+                Z[c0 + y] = make_double2(kax * p.y, q.y);
             } else {
-                Z[row + kx] = make_double2(kax * p.y + q.x, -kax * p.x + q.y);
-                Z[row + nx - kx] = make_double2(kax * p.y - q.x, kax * p.x + q.y);
+                Z[c0 + y] = make_double2(kax * p.y + q.x, -kax * p.x + q.y);
+                Z[c1 + y] = make_double2(kax * p.y - q.x, kax * p.x + q.y);
             }
         }
     }
@@ -304,8 +309,11 @@ __global__ void __launch_bounds__(kBlock) k_fft_rows_inv(Geo g, const double2 *Z
     const int nx = g.nx;
     const int64_t G = (int64_t)nx * g.ny;
     double2 *b0 = (double2 *)smem, *b1 = b0 + nx;
-    const int64_t row = (int64_t)blockIdx.x * nx;
-    for (int i = threadIdx.x; i < nx; i += blockDim.x) b0[i] = Z[row + i];
+    // rows of one XCD (workgroups b, b + 8, ...) adjacent
+    const int ny = g.ny;
+    const int y = ny >= 8 ? (int)(blockIdx.x % 8) * (ny / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+    const int64_t row = (int64_t)y * nx;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) b0[i] = Z[(int64_t)i * ny + y];
     __syncthreads();
     const double2 *U = fft_lds<+1>(b0, b1, lgnx, 1, tw, lgmax);
     for (int i = threadIdx.x; i < nx; i += blockDim.x) {
