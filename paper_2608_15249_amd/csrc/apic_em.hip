@@ -195,8 +195,9 @@ template <typename R>
 __device__ __forceinline__ R lerp_glob(const double *f, const Geo &g, int i, int j, R fx, R fy) {
     const int ip = wrap_up(i, g.nx), jp = wrap_up(j, g.ny);
     const int64_t r0 = (int64_t)j * g.nx, r1 = (int64_t)jp * g.nx;
-    return (R(1) - fx) * (R(1) - fy) * (R)f[r0 + i] + fx * (R(1) - fy) * (R)f[r0 + ip] +
-           (R(1) - fx) * fy * (R)f[r1 + i] + fx * fy * (R)f[r1 + ip];
+    const R f00 = (R)f[r0 + i], f10 = (R)f[r0 + ip], f01 = (R)f[r1 + i], f11 = (R)f[r1 + ip];
+    const R lo = fma(fx, f10 - f00, f00), hi = fma(fx, f11 - f01, f01);
+    return fma(fy, hi - lo, lo);
 }
 
 template <bool MIX, bool HC>
@@ -224,8 +225,8 @@ __global__ void __launch_bounds__(kBlock) k_em_gather_push(Geo g, Parts p, int64
             const R ic2 = MIX ? (R)pc.ic2f : (R)pc.ic2;
             hc3<R>(q.vx, q.vy, q.vz, e, b, a, ic2);
             if (pc.move) {
-                const R gm = lorentz<R>(q.vx, q.vy, q.vz, ic2);
-                ok = move_pt_v<MIX, 2>(q, g, pc, q.vx / gm, q.vy / gm, q.vz / gm, sx, sy, sz) && ok;
+                const R ig = recip<R>(lorentz<R>(q.vx, q.vy, q.vz, ic2));
+                ok = move_pt_v<MIX, 2>(q, g, pc, q.vx * ig, q.vy * ig, q.vz * ig, sx, sy, sz) && ok;
             }
         } else {
             boris3<R>(q.vx, q.vy, q.vz, e, b, a);

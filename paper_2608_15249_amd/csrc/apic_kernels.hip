@@ -209,13 +209,13 @@ __device__ __forceinline__ bool advance(Pt<MIX> &q, const Geo &g, const PushC &p
 // Electromagnetic form (2D3V): E and B gathered from the Yee field tile
 // (nodes from (x0-1, y0-1), width fw), Boris (or Higuera-Cary with the state
 // u = gamma v) in B, move. (lx, ly) and (fx0, fy0) return the old local cell
-// and fractions for the current deposit, gm the Lorentz factor the move
-// divided u by (1 for Boris).
+// and fractions for the current deposit, ig the factor 1 / gamma the move
+// multiplied u by (1 for Boris).
 template <bool MIX, bool HC>
 __device__ __forceinline__ bool advance_em(Pt<MIX> &q, const Geo &g, const PushC &pc,
                                            const typename Pt<MIX>::R *sF, int fw, int x0, int y0, int &lx, int &ly,
                                            int &sx, int &sy, typename Pt<MIX>::R &fx0, typename Pt<MIX>::R &fy0,
-                                           typename Pt<MIX>::R &gm) {
+                                           typename Pt<MIX>::R &ig) {
     using R = typename Pt<MIX>::R;
     const int tx = 1 << g.tsx, ty = 1 << g.tsy;
     lx = q.ix - x0;
@@ -235,11 +235,11 @@ __device__ __forceinline__ bool advance_em(Pt<MIX> &q, const Geo &g, const PushC
     if constexpr (HC) {
         const R ic2 = MIX ? (R)pc.ic2f : (R)pc.ic2;
         hc3<R>(q.vx, q.vy, q.vz, e, b, MIX ? (R)pc.af : (R)pc.a, ic2);
-        gm = lorentz<R>(q.vx, q.vy, q.vz, ic2);
-        return move_pt_v<MIX, 2>(q, g, pc, q.vx / gm, q.vy / gm, q.vz / gm, sx, sy, sz) && in;
+        ig = recip<R>(lorentz<R>(q.vx, q.vy, q.vz, ic2));
+        return move_pt_v<MIX, 2>(q, g, pc, q.vx * ig, q.vy * ig, q.vz * ig, sx, sy, sz) && in;
     } else {
         boris3<R>(q.vx, q.vy, q.vz, e, b, MIX ? (R)pc.af : (R)pc.a);
-        gm = R(1);
+        ig = R(1);
         return move_pt<MIX, 2>(q, g, pc, sx, sy, sz) && in;
     }
 }
@@ -897,8 +897,8 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
                 bool good = decode<MIX, DIM, VDIM>(r1, g, q);
                 int lx, ly, lz = 0, sx, sy, sz = 0;
                 if constexpr (EM) {
-                    R f0x, f0y, gm;
-                    good = advance_em<MIX, HC>(q, g, pc, (const R *)smem, fw, x0, y0, lx, ly, sx, sy, f0x, f0y, gm) &&
+                    R f0x, f0y, ig;
+                    good = advance_em<MIX, HC>(q, g, pc, (const R *)smem, fw, x0, y0, lx, ly, sx, sy, f0x, f0y, ig) &&
                            good;
                 } else {
                     good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx, sy,
@@ -946,9 +946,9 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
                     bool good = decode<MIX, DIM, VDIM>(r[j], g, q);
                     int lx, ly, lz = 0, sx, sy, sz = 0;
                     if constexpr (EM) {
-                        R f0x, f0y, gm;
+                        R f0x, f0y, ig;
                         good = advance_em<MIX, HC>(q, g, pc, (const R *)smem, fw, x0, y0, lx, ly, sx, sy, f0x, f0y,
-                                                   gm) && good;
+                                                   ig) && good;
                     } else {
                         good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx,
                                                            sy, sz) && good;
@@ -1251,9 +1251,9 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
                     bool good = decode<MIX, DIM, VDIM>(r[j], g, q);
                     const double v2o = vsq<MIX, VDIM, HC>(q, pc);
                     int lx, ly, lz = 0, sx, sy, sz = 0;
-                    R f0x = R(0), f0y = R(0), gm = R(1);
+                    R f0x = R(0), f0y = R(0), ig = R(1);
                     if constexpr (EM) {
-                        good = advance_em<MIX, HC>(q, g, pc, sE, fw, x0, y0, lx, ly, sx, sy, f0x, f0y, gm) && good;
+                        good = advance_em<MIX, HC>(q, g, pc, sE, fw, x0, y0, lx, ly, sx, sy, f0x, f0y, ig) && good;
                     } else {
                         good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx,
                                                            sy, sz) && good;
@@ -1307,8 +1307,8 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
                     } else if constexpr (EM) {
                         // current J^{n+1/2} of the move x^n -> x^{n+1} (Esirkepov); the
                         // mixed path's displacement is the binary32 product its move adds
-                        // (with Higuera-Cary the velocity is u / gamma, the quotient the move used)
-                        const R wvx = q.vx / gm, wvy = q.vy / gm, wvz = q.vz / gm;
+                        // (with Higuera-Cary the velocity is u / gamma, the product the move used)
+                        const R wvx = q.vx * ig, wvy = q.vy * ig, wvz = q.vz * ig;
                         R ddx, ddy;
                         if constexpr (MIX) {
                             ddx = wvx * pc.dtdx;
@@ -1317,8 +1317,8 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
                             ddx = (wvx * pc.dt) * g.inv_dx;
                             ddy = (wvy * pc.dt) * g.inv_dy;
                         }
-                        if (!esirkepov_lds<R>((double *)sA, jw, jw * jh, lx, ly, f0x, f0y, ddx, ddy, pc.jx, pc.jy,
-                                              pc.jz * (double)wvz))
+                        if (!esirkepov_lds<R>((double *)sA, jw, jw * jh, lx, ly, f0x, f0y, ddx, ddy,
+                                              (R)(pc.jz * (double)wvz)))
                             atomicOr(&sErr, ERR_DOMAIN);
                     } else {
                     // deposit rho^{n+1}: LDS tile + halo, global beyond it
@@ -1487,7 +1487,7 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
             deep_out[b * kDeepTab + 1] = front - front0;
         }
         if constexpr (EM)
-            flush_j((double *)acc, (const double *)sA, g, x0, y0, jw, jh);
+            flush_j((double *)acc, (const double *)sA, g, x0, y0, jw, jh, pc.jx, pc.jy);
         else if constexpr (DIM == 3)
             flush_region3<MIX>(acc, sA, g, x0, y0, z0, wx, wy, wz, g.halo);
         else
