@@ -115,6 +115,16 @@ struct TileNb {
 
 __device__ __forceinline__ int tile_width(int i, int t, int n) { return min(t, n - i * t); }
 
+// A wave-uniform 32-bit value moved into a vector register (when ON):
+// per-lane arithmetic reads it from there, leaving the scalar registers to
+// the state the chunk loop itself carries.
+template <bool ON, typename T>
+__device__ __forceinline__ T vreg(T x) {
+    static_assert(sizeof(T) == 4, "a 32-bit value");
+    if constexpr (ON) asm("" : "+v"(x));
+    return x;
+}
+
 template <int DIM>
 __device__ __forceinline__ TileNb tile_nb(const Geo &g, int bx, int by, int bz = 0) {
     TileNb t;
@@ -787,7 +797,7 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
                                                        const int32_t *deep, CtxDev c) {
     static_assert(!EM || (DIM == 2 && VDIM == 3), "the electromagnetic step is 2D3V");
     using R = typename Pt<MIX>::R;
-    constexpr int kDirs = Dir<DIM>::kN, kFar = Dir<DIM>::kFar, kStay = Dir<DIM>::kStay, kTab = Dir<DIM>::kTab;
+    constexpr int kFar = Dir<DIM>::kFar, kStay = Dir<DIM>::kStay, kTab = Dir<DIM>::kTab;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sErr;
     __shared__ int32_t sCnt[kTab];
@@ -892,7 +902,6 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
             };
             auto sprocess = [&](const Raw<MIX> &r1, int t) {
                 if (t >= nsh) return;
-                const int k = kmap(t);
                 Pt<MIX> q;
                 bool good = decode<MIX, DIM, VDIM>(r1, g, q);
                 int lx, ly, lz = 0, sx, sy, sz = 0;
@@ -1092,6 +1101,10 @@ __global__ void __launch_bounds__(kSBlock) k_scan_offsets(Geo g, const int32_t *
 // 2|a| max|E| dt/dx, stays below pc.deep.
 // EM: the electromagnetic form (FP64 2D3V): E is the [6][G] Yee field and
 // acc the [3][G] current J^{n+1/2} (Esirkepov), accumulated with atomics.
+// VR (mixed electrostatic push only): the tile's constants, and in 2D the
+// call's, held in vector registers (vreg). This build spills no scalar
+// registers inside the chunk loop but needs more vector registers; the
+// launch takes it where that costs no resident workgroup.
 // Waves per SIMD the push is compiled for (0: the compiler's choice). Each
 // push workgroup owns one bucket, so the resident waves per SIMD are at most
 // kSWaves * (buckets per CU) / 4 whatever the register count.
@@ -1104,7 +1117,7 @@ __global__ void __launch_bounds__(kSBlock) k_scan_offsets(Geo g, const int32_t *
 #define APIC_PUSH_BOUNDS __launch_bounds__(kSBlock)
 #endif
 
-template <bool MIX, int DIM, int VDIM, int U, bool HC, bool EM>
+template <bool MIX, int DIM, int VDIM, int U, bool HC, bool EM, bool VR = false>
 __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const int32_t *bstart,
                                                       const int32_t *bstart_new, const int32_t *cnt,
                                                       const int32_t *offs, int32_t *farcnt, const double *E, PushC pc,
@@ -1112,7 +1125,7 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
                                                       int32_t *deep_out, CtxDev c) {
     using R = typename Pt<MIX>::R;
     using A = typename AccOf<MIX>::T;
-    constexpr int kDirs = Dir<DIM>::kN, kFar = Dir<DIM>::kFar, kStay = Dir<DIM>::kStay, kTab = Dir<DIM>::kTab;
+    constexpr int kFar = Dir<DIM>::kFar, kStay = Dir<DIM>::kStay, kTab = Dir<DIM>::kTab;
     constexpr int kCodeBits = Dir<DIM>::kCodeBits;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sErr;
@@ -1139,18 +1152,53 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
     const size_t acc_bytes = EM ? (size_t)3 * jw * jh * sizeof(double) : (size_t)wxy * wz * sizeof(A);
     A *sA = (A *)smem;
     R *sE = (R *)(smem + ((acc_bytes + 15) & ~(size_t)15));
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const uint64_t lt = lanemask_lt();
     const int lane = (int)(threadIdx.x & 63);
     int it = 0;   // chunks processed by this workgroup (the parity picks the count table)
+    static_assert(!VR || (MIX && !HC && !EM), "the register-relieved build is the mixed electrostatic push");
+    constexpr bool kVt = VR, kVc = VR && DIM == 2;
+    // all ones for the waves before this one (their counts come first)
+    int before[kSWaves];
+#pragma unroll
+    for (int w2 = 0; w2 < kSWaves; ++w2) before[w2] = vreg<kVt>(w2 < w ? -1 : 0);
     if (threadIdx.x == 0) sErr = 0;
     int first, end, stride;
     bucket_walk(g.nbuckets, first, end, stride);
     for (int b = first; b < end; b += stride) {
         int bx, by, bz;
         tile_coords<DIM>(g, b, bx, by, bz);
-        const int x0 = bx << g.tsx, y0 = (DIM >= 2) ? (by << g.tsy) : 0, z0 = (DIM == 3) ? (bz << g.tsz) : 0;
-        const TileNb tn = tile_nb<DIM>(g, bx, by, bz);
+        const int x0s = bx << g.tsx, y0s = (DIM >= 2) ? (by << g.tsy) : 0, z0s = (DIM == 3) ? (bz << g.tsz) : 0;
+        TileNb tn = tile_nb<DIM>(g, bx, by, bz);
+        const int x0 = vreg<kVt>(x0s), y0 = vreg<kVt>(y0s), z0 = vreg<kVt>(z0s);
+        tn.txe = vreg<kVt>(tn.txe);
+        tn.lw = vreg<kVt>(tn.lw);
+        tn.rw = vreg<kVt>(tn.rw);
+        if constexpr (DIM >= 2) {
+            tn.tye = vreg<kVt>(tn.tye);
+            tn.dw = vreg<kVt>(tn.dw);
+            tn.uw = vreg<kVt>(tn.uw);
+        }
+        if constexpr (DIM == 3) {
+            tn.tze = vreg<kVt>(tn.tze);
+            tn.bw = vreg<kVt>(tn.bw);
+            tn.fw = vreg<kVt>(tn.fw);
+        }
+        PushC pv = pc;
+        pv.af = vreg<kVc>(pc.af);
+        pv.tf = vreg<kVc>(pc.tf);
+        pv.sf = vreg<kVc>(pc.sf);
+        pv.dtdx = vreg<kVc>(pc.dtdx);
+        pv.dtdy = vreg<kVc>(pc.dtdy);
+        pv.dtdz = vreg<kVc>(pc.dtdz);
+        pv.dtdx2 = vreg<kVc>(pc.dtdx2);
+        pv.dtdy2 = vreg<kVc>(pc.dtdy2);
+        pv.deep = vreg<kVc>(pc.deep);
+        Geo gv = g;
+        gv.nx = vreg<kVc>(g.nx);
+        gv.ny = vreg<kVc>(g.ny);
+        gv.nz = vreg<kVc>(g.nz);
+        gv.nxp = vreg<kVc>(g.nxp);
         // the bucket's range and (mixed path) its first chunk of particles,
         // loaded before the tables and the field tile so that the memory round
         // trips overlap; the FP64 pipeline issues its first chunk below
@@ -1248,58 +1296,58 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
                 bool deep = false;
                 Pt<MIX> q;
                 if (act) {
-                    bool good = decode<MIX, DIM, VDIM>(r[j], g, q);
-                    const double v2o = vsq<MIX, VDIM, HC>(q, pc);
+                    bool good = decode<MIX, DIM, VDIM>(r[j], gv, q);
+                    const double v2o = vsq<MIX, VDIM, HC>(q, pv);
                     int lx, ly, lz = 0, sx, sy, sz = 0;
                     R f0x = R(0), f0y = R(0), ig = R(1);
                     if constexpr (EM) {
-                        good = advance_em<MIX, HC>(q, g, pc, sE, fw, x0, y0, lx, ly, sx, sy, f0x, f0y, ig) && good;
+                        good = advance_em<MIX, HC>(q, gv, pv, sE, fw, x0, y0, lx, ly, sx, sy, f0x, f0y, ig) && good;
                     } else {
-                        good = advance<MIX, DIM, VDIM, HC>(q, g, pc, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx,
+                        good = advance<MIX, DIM, VDIM, HC>(q, gv, pv, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx,
                                                            sy, sz) && good;
                     }
                     if (!good) atomicOr(&sErr, ERR_DOMAIN);
-                    const double v2n = vsq<MIX, VDIM, HC>(q, pc);
+                    const double v2n = vsq<MIX, VDIM, HC>(q, pv);
                     ke += v2o + v2n;   // halved once per bucket (exact: a power of two)
                     px += (double)q.vx;
                     code = dir_local<DIM>(tn, lx + sx, ly + sy, lz + sz);
                     // absorbed by a wall: no deposit, no slot
-                    const bool dead = g.walls && q.ix >= g.nxp;
+                    const bool dead = g.walls && q.ix >= gv.nxp;
                     if (dead) code = -1;
-                    if (code == kFar) nbk = bucket_of<MIX, DIM>(g, q.ix, q.iy, q.iz);
+                    if (code == kFar) nbk = bucket_of<MIX, DIM>(gv, q.ix, q.iy, q.iz);
                     if (code == kStay) {
                         const float ux = (float)(q.ix - x0) + (float)q.fx;
-                        const float mx = fminf(ux, txe - ux) - pc.deep;
+                        const float mx = fminf(ux, txe - ux) - pv.deep;
                         const float vx = fabsf((float)q.vx);
                         if constexpr (DIM == 1) {
-                            deep = mx >= vx * pc.dtdx;
+                            deep = mx >= vx * pv.dtdx;
                         } else {
                             const float uy = (float)(q.iy - y0) + (float)q.fy;
-                            const float my = fminf(uy, tye - uy) - pc.deep;
+                            const float my = fminf(uy, tye - uy) - pv.deep;
                             const float vy = fabsf((float)q.vy);
                             // with a rotation the speed can turn along either axis:
                             // compared as squares, |v| dt/dx <= m <=> |v|^2 (dt/dx)^2
                             // <= m^2 for m >= 0 (the rounding of either side,
-                            // a few ulps, is far inside the margin pc.deep keeps)
+                            // a few ulps, is far inside the margin pv.deep keeps)
                             if constexpr (EM) {
                                 // a general B can turn the whole speed along either axis
                                 const float vz = (float)q.vz;
                                 const float vv2 = vx * vx + vy * vy + vz * vz;
-                                deep = mx >= 0.0f && my >= 0.0f && mx * mx >= vv2 * pc.dtdx2 &&
-                                       my * my >= vv2 * pc.dtdy2;
-                            } else if (!pc.rot) {
-                                deep = mx >= vx * pc.dtdx && my >= vy * pc.dtdy;
+                                deep = mx >= 0.0f && my >= 0.0f && mx * mx >= vv2 * pv.dtdx2 &&
+                                       my * my >= vv2 * pv.dtdy2;
+                            } else if (!pv.rot) {
+                                deep = mx >= vx * pv.dtdx && my >= vy * pv.dtdy;
                             } else {
                                 // the rotation about z turns the in-plane speed
                                 const float vv2 = vx * vx + vy * vy;
-                                deep = mx >= 0.0f && my >= 0.0f && mx * mx >= vv2 * pc.dtdx2 &&
-                                       my * my >= vv2 * pc.dtdy2;
+                                deep = mx >= 0.0f && my >= 0.0f && mx * mx >= vv2 * pv.dtdx2 &&
+                                       my * my >= vv2 * pv.dtdy2;
                             }
                             if constexpr (DIM == 3) {
                                 // vz only takes the kicks of Ez (the rotation is about z)
                                 const float uz = (float)(q.iz - z0) + (float)q.fz;
-                                const float mz = fminf(uz, tze - uz) - pc.deep;
-                                deep = deep && mz >= fabsf((float)q.vz) * pc.dtdz;
+                                const float mz = fminf(uz, tze - uz) - pv.deep;
+                                deep = deep && mz >= fabsf((float)q.vz) * pv.dtdz;
                             }
                         }
                     }
@@ -1311,8 +1359,8 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
                         const R wvx = q.vx * ig, wvy = q.vy * ig, wvz = q.vz * ig;
                         R ddx, ddy;
                         if constexpr (MIX) {
-                            ddx = wvx * pc.dtdx;
-                            ddy = wvy * pc.dtdy;
+                            ddx = wvx * pv.dtdx;
+                            ddy = wvy * pv.dtdy;
                         } else {
                             ddx = (wvx * pc.dt) * g.inv_dx;
                             ddy = (wvy * pc.dt) * g.inv_dy;
@@ -1323,7 +1371,7 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
                     } else {
                     // deposit rho^{n+1}: LDS tile + halo, global beyond it
                     A wgt[8];
-                    dep_weights<MIX, DIM>(q, g, wgt);
+                    dep_weights<MIX, DIM>(q, gv, wgt);
                     const int dlx = lx + sx + g.halo;
                     const int dly = (DIM >= 2) ? ly + sy + g.halo : 0;
                     const int dlz = (DIM == 3) ? lz + sz + g.halo : 0;
@@ -1377,22 +1425,23 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
                     if (lane < kTab) sMv[par][w][lane] = 0;
                     if (mv && (peers & lt) == 0) sMv[par][w][code] = (int)__popcll(peers);
                 }
-                if (lane == 0) sPk[par][w] = nd | (ns << 8) | ((gmv != 0) << 16);
+                // packed: deep count in bits 0-9, shallow count in bits 10-19, the
+                // mover flag from bit 20 (sums over the waves stay below 1024)
+                static_assert(kSBlock < 1024, "a chunk's counts fill ten bits");
+                if (lane == 0) sPk[par][w] = nd | (ns << 10) | ((gmv != 0) << 20);
                 __syncthreads();
-                // the counts of the waves before this one, and of the whole chunk
-                int pd = 0, ps = 0, td = 0, ts = 0, anymv = 0;
+                // the counts of the waves before this one, and of the whole chunk,
+                // summed as packed words
+                int pk[kSWaves], pre = 0, tot = 0;
 #pragma unroll
                 for (int w2 = 0; w2 < kSWaves; ++w2) {
-                    const int pk = sPk[par][w2];
-                    const int a = pk & 0xFF, bb = (pk >> 8) & 0xFF;
-                    if (w2 < w) {
-                        pd += a;
-                        ps += bb;
-                    }
-                    td += a;
-                    ts += bb;
-                    anymv |= pk >> 16;
+                    pk[w2] = sPk[par][w2];
+                    tot += pk[w2];
+                    pre += pk[w2] & before[w2];
                 }
+                const int pd = pre & 1023, ps = (pre >> 10) & 1023;
+                const int td = tot & 1023, ts = (tot >> 10) & 1023;
+                const int anymv = tot >> 20;
                 // stays: deep ones from the front of the bucket's stay range,
                 // the rest from its back
                 const bool sfits = front >= 0 && front + td <= back - ts && back <= stayEnd;
@@ -1407,15 +1456,15 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
                     // and the wave's copy of the cursor moved past the chunk
                     int offd = 0;
                     if (lane < kTab) {
-                        int pre = 0, tot = 0;
+                        int mpre = 0, mtot = 0;
 #pragma unroll
                         for (int w2 = 0; w2 < kSWaves; ++w2) {
-                            const int c2 = (sPk[par][w2] >> 16) ? sMv[par][w2][lane] : 0;
-                            if (w2 < w) pre += c2;
-                            tot += c2;
+                            const int c2 = (pk[w2] >> 20) ? sMv[par][w2][lane] : 0;
+                            mpre += c2 & before[w2];
+                            mtot += c2;
                         }
-                        offd = sCur[w][lane] + pre;
-                        sCur[w][lane] += tot;
+                        offd = sCur[w][lane] + mpre;
+                        sCur[w][lane] += mtot;
                     }
                     const int basek = __shfl(offd, mv ? code : 0);
                     if (mv) {
@@ -1826,10 +1875,7 @@ hipError_t launch_gather_push(const Geo &g, bool mixed, const Parts &p, int64_t 
     return hipGetLastError();
 }
 
-// Persistent grid: as many blocks as fit on the device at once (a multiple of
-// 8 for the XCD walk), never more than the bucket count needs.
-template <typename K>
-int persistent_grid(K kernel, size_t shmem, int nbuckets, int block = kBlock) {
+int cu_count() {
     static int cus = 0;
     if (!cus) {
         int dev = 0;
@@ -1837,6 +1883,27 @@ int persistent_grid(K kernel, size_t shmem, int nbuckets, int block = kBlock) {
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
     }
+    return cus;
+}
+
+// Workgroups of a bucket kernel resident on one CU during a launch over
+// nbuckets buckets: what its registers and LDS allow, at most the buckets'
+// share of a CU.
+template <typename K>
+int resident_per_cu(K kernel, size_t shmem, int nbuckets, int block) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, shmem) != hipSuccess || per_cu <= 0)
+        per_cu = 1;
+    const int cus = cu_count();
+    const int share = (nbuckets + cus - 1) / cus;
+    return per_cu < share ? per_cu : share;
+}
+
+// Persistent grid: as many blocks as fit on the device at once (a multiple of
+// 8 for the XCD walk), never more than the bucket count needs.
+template <typename K>
+int persistent_grid(K kernel, size_t shmem, int nbuckets, int block = kBlock) {
+    const int cus = cu_count();
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, shmem) != hipSuccess || per_cu <= 0)
         per_cu = 4;
@@ -1929,9 +1996,20 @@ hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Pa
     size_t sh = tile_acc_bytes(g, g.halo) + tile_e_bytes(g, mixed);
     APIC_DISPATCH(g, mixed, {
         auto kern = k_step_push<MIX, DIM, VDIM, U, HC, false>;
-        hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets, kSBlock)), dim3(kSBlock), sh, s, g, src, dst,
-                           bstart, bstart_new, cnt, offs, farcnt, E, pc, (typename AccOf<MIX>::T *)acc, perm, part,
-                           deep, c);
+        auto run = [&](auto k) {
+            hipLaunchKernelGGL(k, dim3(persistent_grid(k, sh, g.nbuckets, kSBlock)), dim3(kSBlock), sh, s, g, src,
+                               dst, bstart, bstart_new, cnt, offs, farcnt, E, pc, (typename AccOf<MIX>::T *)acc, perm,
+                               part, deep, c);
+        };
+        if constexpr (MIX && !HC) {
+            auto kvr = k_step_push<MIX, DIM, VDIM, U, HC, false, true>;
+            if (resident_per_cu(kvr, sh, g.nbuckets, kSBlock) >= resident_per_cu(kern, sh, g.nbuckets, kSBlock))
+                run(kvr);
+            else
+                run(kern);
+        } else {
+            run(kern);
+        }
     });
     return hipGetLastError();
 }
