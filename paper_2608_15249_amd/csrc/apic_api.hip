@@ -148,6 +148,7 @@ void layout(apic_ctx *c) {
     // alternating by step (the one-launch field update reads one, writes the other)
     c->o_jacc = c->d.model == APIC_ELECTROMAGNETIC ? take(2 * 24 * G) : (size_t)-1;
     c->o_f2 = c->d.model == APIC_ELECTROMAGNETIC ? take(48 * G) : (size_t)-1;
+    c->o_e32 = (c->mixed && dim >= 2 && c->d.model != APIC_ELECTROMAGNETIC) ? take(4 * dim * G) : (size_t)-1;
     c->o_rho = take(8 * G);
     if (dim >= 2) {
         const int64_t H = (int64_t)(c->d.nx / 2 + 1) * c->d.ny * c->d.nz;
@@ -677,6 +678,8 @@ apic_status step_run(apic_ctx *c, apic_particles *p, const Parts &B, int32_t *bs
     const Parts A = parts_of(p);
     int32_t *bsA = p->bucket_start;
     const PushC pc = push_coeffs(c, 1.0, 1);
+    // binary32 E between the steps of the mixed path (2D and 3D)
+    float *e32 = c->o_e32 != (size_t)-1 ? wsp<float>(ws, c->o_e32) : nullptr;
     HIPCHK(c, launch_fill_i32(farcnt, nb, 0, s));
     // the bucket totals: two buffers, alternating by step
     HIPCHK(c, launch_fill_i32(tot, 2 * (int64_t)nb, 0, s));
@@ -695,7 +698,8 @@ apic_status step_run(apic_ctx *c, apic_particles *p, const Parts &B, int32_t *bs
         if (c->prof_used < c->prof_max) ev = &c->ev[5 * (size_t)c->prof_used++];
         if (ev && c->prof_all) HIPCHK(c, hipEventRecord(ev[0], s));
         int32_t *tot_k = tot + (even ? 0 : nb), *tot_n = tot + (even ? nb : 0);
-        HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, E, pc, cnt, tot_k, farcnt, deep, c->dev, s));
+        HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, E, k > 0 ? e32 : nullptr, pc, cnt, tot_k, farcnt,
+                                    deep, c->dev, s));
         if (ev && c->prof_all) HIPCHK(c, hipEventRecord(ev[1], s));
         if (fused_scan_offsets(c->g)) {
             HIPCHK(c, launch_scan_offsets(c->g, tot_k, tot_n, bs_dst, c->n, max_per_bucket(c), 1, cnt, offs, c->dev,
@@ -705,8 +709,9 @@ apic_status step_run(apic_ctx *c, apic_particles *p, const Parts &B, int32_t *bs
             HIPCHK(c, launch_dest_offsets(c->g, cnt, bs_dst, offs, s));
         }
         if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
-        HIPCHK(c, launch_step_push(c->g, c->mixed, src, dst, bs_src, bs_dst, cnt, offs, farcnt, E, pc, acc,
-                                   p->perm, diag ? c->dev.part_push : nullptr, deep, c->dev, s));
+        HIPCHK(c, launch_step_push(c->g, c->mixed, src, dst, bs_src, bs_dst, cnt, offs, farcnt, E,
+                                   k > 0 ? e32 : nullptr, pc, acc, p->perm, diag ? c->dev.part_push : nullptr, deep,
+                                   c->dev, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[3], s));
         if (rho && last) {
             if (c->mixed)
@@ -714,8 +719,10 @@ apic_status step_run(apic_ctx *c, apic_particles *p, const Parts &B, int32_t *bs
             else
                 HIPCHK(c, launch_rho(c->g, false, acc, (double *)rho, acc_scale(c), c->d.rho_ion, 0, nullptr, s));
         }
-        st = field_from_acc(c, acc, false, E, last ? E32 : nullptr, diag, nullptr, nullptr, diag ? nb : 0, 1, ws, s,
-                            bs_dst + nb);
+        // mixed path: between steps only the binary32 field (the push reads no
+        // more); the FP64 E (and the caller's E32) after the last step
+        st = field_from_acc(c, acc, false, (last || !e32) ? E : nullptr, last ? E32 : e32, diag, nullptr, nullptr,
+                            diag ? nb : 0, 1, ws, s, bs_dst + nb);
         if (st != APIC_OK) return st;
         if (ev && c->prof_all) HIPCHK(c, hipEventRecord(ev[4], s));
     }

@@ -27,6 +27,7 @@ struct apic_ctx {
     size_t o_keys, o_bstart, o_acc, o_rho, o_rhat, o_ehat;
     size_t o_jacc;    // electromagnetic step: J [2][3][G] (two buffers)
     size_t o_f2;      // electromagnetic step: the second field buffer [6][G]
+    size_t o_e32;     // mixed electrostatic step in 2D and 3D: E between steps, binary32 [dim][G]
     size_t o_cnt, o_offs, o_farcnt, o_farcur, o_tot, o_deep;
     size_t o_keys2, o_idx, o_idx2, o_rcnt, o_roff, o_rpart;
     size_t ws_bytes;

@@ -524,6 +524,16 @@ __device__ void load_e_tile3(R *sE, const ET *E, const Geo &g, int x0, int y0, i
     }
 }
 
+// The E tile of a 1D, 2D or 3D step from a field of element type ET.
+template <typename R, typename ET, int DIM>
+__device__ __forceinline__ void load_tile_any(R *sE, const ET *E, const Geo &g, int x0, int y0, int z0, int wx,
+                                              int wy, int wz) {
+    if constexpr (DIM == 3)
+        load_e_tile3<R, ET>(sE, E, g, x0, y0, z0, wx, wy, wz);
+    else
+        load_e_tile<R, ET, DIM>(sE, E, g, x0, y0, wx, wy);
+}
+
 // 3D CIC interpolation: node weight (wx_a wy_b) wz_c; the eight terms are
 // added left to right with a (x) fastest, then b (y), then c (z). e(k) gives
 // the value of component comp at corner k = c*4 + b*2 + a.

@@ -393,7 +393,7 @@ apic_status apic_em_step(apic_ctx *c, apic_particles *p, double *F, double *J, i
         // F^n in F on even steps and in F2 on odd ones; J^{n+1/2} alternates likewise
         double *Fk = even ? F : F2, *Fk1 = even ? F2 : F;
         double *Jk = jacc + (even ? 0 : 3 * G), *Jk1 = jacc + (even ? 3 * G : 0);
-        HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, Fk, pc, cnt, tot_k, farcnt, deep, c->dev, s));
+        HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, Fk, nullptr, pc, cnt, tot_k, farcnt, deep, c->dev, s));
         if (ev && c->prof_all) HIPCHK(c, hipEventRecord(ev[1], s));
         if (fused_scan_offsets(c->g)) {
             HIPCHK(c, launch_scan_offsets(c->g, tot_k, tot_n, bs_dst, c->n, max_per_bucket(c), 1, cnt, offs, c->dev,
@@ -403,7 +403,7 @@ apic_status apic_em_step(apic_ctx *c, apic_particles *p, double *F, double *J, i
             HIPCHK(c, launch_dest_offsets(c->g, cnt, bs_dst, offs, s));
         }
         if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
-        HIPCHK(c, launch_step_push(c->g, c->mixed, src, dst, bs_src, bs_dst, cnt, offs, farcnt, Fk, pc, Jk, p->perm,
+        HIPCHK(c, launch_step_push(c->g, c->mixed, src, dst, bs_src, bs_dst, cnt, offs, farcnt, Fk, nullptr, pc, Jk, p->perm,
                                    diag ? c->dev.part_push : nullptr, deep, c->dev, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[3], s));
         HIPCHK(c, launch_fdtd_step(c->g, Fk, Fk1, Jk, Jk1, (J && last) ? J : nullptr, dt, c2, c->d.bz, c->dV, c->mass,

@@ -31,7 +31,8 @@
 // Transforms: Stockham passes between two LDS buffers (the output in natural
 // order, one barrier per pass), radix 8 in registers after one radix-2 or
 // radix-4 pass; twiddles exp(-2 pi i k / nmax) from a table in global memory
-// (16 KiB at most, cache resident).
+// (16 KiB at most, cache resident), one entry per butterfly and its powers
+// by complex products.
 #include "apic_device.h"
 
 namespace apic {
@@ -110,12 +111,15 @@ __device__ __forceinline__ void fft_pass(const double2 *a, double2 *b, int lgn, 
 #pragma unroll
         for (int q = 0; q < R; ++q) v[q] = a[base + j + q * nr];
         if (lgns > 0) {
+            // w^q from w = exp(SIGN 2 pi i k / (R ns)), one table entry: each a
+            // product of at most three factors (fewer scattered table reads)
+            double2 w[R];
+            w[1] = tw[k << tsh];
+            if (SIGN > 0) w[1].y = -w[1].y;
 #pragma unroll
-            for (int q = 1; q < R; ++q) {
-                double2 w = tw[(q * k) << tsh];
-                if (SIGN > 0) w.y = -w.y;
-                v[q] = cmul(v[q], w);
-            }
+            for (int q = 2; q < R; ++q) w[q] = cmul(w[q / 2], w[q - q / 2]);
+#pragma unroll
+            for (int q = 1; q < R; ++q) v[q] = cmul(v[q], w[q]);
         }
         if constexpr (LR == 1) dft2(v[0], v[1]);
         else if constexpr (LR == 2) dft4<SIGN>(v[0], v[1], v[2], v[3]);
@@ -318,8 +322,10 @@ __global__ void __launch_bounds__(kBlock) k_fft_rows_inv(Geo g, const double2 *Z
     const double2 *U = fft_lds<+1>(b0, b1, lgnx, 1, tw, lgmax);
     for (int i = threadIdx.x; i < nx; i += blockDim.x) {
         const double2 e = U[i];
-        E[row + i] = e.x;
-        E[G + row + i] = e.y;
+        if (E) {
+            E[row + i] = e.x;
+            E[G + row + i] = e.y;
+        }
         if (E32) {
             E32[row + i] = (float)e.x;
             E32[G + row + i] = (float)e.y;

@@ -149,8 +149,10 @@ hipError_t launch_gather_push(const Geo &g, bool mixed, const Parts &p, int64_t 
 // deep: per (bucket, wave) the [start, count) range, relative to the bucket,
 // of particles the previous push found deep inside their tile (written by
 // launch_step_push, all zero when unknown).
+// E32 (mixed path, may be NULL): the field already rounded to binary32, read
+// in place of E.
 hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int32_t *bstart,
-                             const double *E, const PushC &pc, int32_t *cnt, int32_t *tot,
+                             const double *E, const float *E32, const PushC &pc, int32_t *cnt, int32_t *tot,
                              int32_t *farcnt, const int32_t *deep, const CtxDev &c, hipStream_t s);
 hipError_t launch_scan_dir(const Geo &g, int32_t *tot, int32_t *start, int64_t n, int64_t max_per_bucket,
                            int step_mode, const CtxDev &c, hipStream_t s);
@@ -168,7 +170,8 @@ hipError_t launch_scan_offsets(const Geo &g, const int32_t *tot, int32_t *tot_ne
                                const CtxDev &c, hipStream_t s);
 hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Parts &dst,
                             const int32_t *bstart, const int32_t *bstart_new, const int32_t *cnt,
-                            const int32_t *offs, int32_t *farcnt, const double *E, const PushC &pc, void *acc,
+                            const int32_t *offs, int32_t *farcnt, const double *E, const float *E32,
+                            const PushC &pc, void *acc,
                             int32_t *perm, double *part, int32_t *deep, const CtxDev &c, hipStream_t s);
 
 // field: accumulation buffer -> rho (FP64): rho = add + scale * acc

@@ -791,9 +791,10 @@ __global__ void __launch_bounds__(kBlock) k_gather_push_tiled(Geo g, Parts p, co
 // rounding, below pc.deep. Its particles are credited as stays; the remaining
 // particles run the full computation and are tallied with LDS atomics.
 // EM: the electromagnetic form (FP64 2D3V): E is the [6][G] Yee field.
+// E32 (mixed path, may be NULL): E already rounded to binary32, read instead.
 template <bool MIX, int DIM, int VDIM, int U, bool HC, bool EM>
 __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const int32_t *bstart, const double *E,
-                                                       PushC pc, int32_t *cnt, int32_t *tot, int32_t *farcnt,
+                                                       const float *E32, PushC pc, int32_t *cnt, int32_t *tot, int32_t *farcnt,
                                                        const int32_t *deep, CtxDev c) {
     static_assert(!EM || (DIM == 2 && VDIM == 3), "the electromagnetic step is 2D3V");
     using R = typename Pt<MIX>::R;
@@ -831,10 +832,10 @@ __global__ void __launch_bounds__(kSBlock) k_step_count(Geo g, Parts p, const in
         const int draw0 = deep[b * kDeepTab], draw1 = deep[b * kDeepTab + 1];
         if constexpr (EM)
             load_f_tile<R>((R *)smem, E, g, x0, y0, fw, fh);
-        else if constexpr (DIM == 3)
-            load_e_tile3<R, double>(sE, E, g, x0, y0, z0, ex_w, ey_w, ez_w);
+        else if (MIX && E32)
+            load_tile_any<R, float, DIM>(sE, E32, g, x0, y0, z0, ex_w, ey_w, ez_w);
         else
-            load_e_tile<R, double, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
+            load_tile_any<R, double, DIM>(sE, E, g, x0, y0, z0, ex_w, ey_w, ez_w);
         __syncthreads();
         // field bound of the tile: per axis, or the in-plane |E| when the push
         // rotates v about z (on the node-centred grid the gathered E is a
@@ -1120,7 +1121,8 @@ __global__ void __launch_bounds__(kSBlock) k_scan_offsets(Geo g, const int32_t *
 template <bool MIX, int DIM, int VDIM, int U, bool HC, bool EM, bool VR = false>
 __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const int32_t *bstart,
                                                       const int32_t *bstart_new, const int32_t *cnt,
-                                                      const int32_t *offs, int32_t *farcnt, const double *E, PushC pc,
+                                                      const int32_t *offs, int32_t *farcnt, const double *E,
+                                                      const float *E32, PushC pc,
                                                       typename AccOf<MIX>::T *acc, int32_t *perm, double *part,
                                                       int32_t *deep_out, CtxDev c) {
     using R = typename Pt<MIX>::R;
@@ -1242,10 +1244,10 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
         }
         if constexpr (EM)
             load_f_tile<R>(sE, E, g, x0, y0, fw, fh);
-        else if constexpr (DIM == 3)
-            load_e_tile3<R, double>(sE, E, g, x0, y0, z0, ex_w, ey_w, ez_w);
+        else if (MIX && E32)
+            load_tile_any<R, float, DIM>(sE, E32, g, x0, y0, z0, ex_w, ey_w, ez_w);
         else
-            load_e_tile<R, double, DIM>(sE, E, g, x0, y0, ex_w, ey_w);
+            load_tile_any<R, double, DIM>(sE, E, g, x0, y0, z0, ex_w, ey_w, ez_w);
         __syncthreads();
         // the bucket's stay cursors (front: next deep slot, back: one past the
         // next shallow slot), the same in every wave, and the end of the bucket
@@ -1653,8 +1655,8 @@ __global__ void __launch_bounds__(kBlock) k_spectral(Geo g, const double2 *rh, d
 
 // E = -(centred difference of phi), periodic: E_d[j] = (phi[j - e_d] -
 // phi[j + e_d]) / (2 d_d), the real-space form of E_hat = -i sin(k d)/d
-// phi_hat. Writes E [dim][G] and, when E32 is not NULL, its binary32
-// rounding. h = 1 / (2 d) per axis.
+// phi_hat. Writes E [dim][G] when E is not NULL and, when E32 is not NULL,
+// its binary32 rounding. h = 1 / (2 d) per axis.
 // The last workgroup of the launch reduces the field diagnostics instead
 // (it reads only what earlier launches wrote).
 __global__ void __launch_bounds__(kBlock) k_grad(Geo g, const double *phi, double *E, float *E32, double hx,
@@ -1672,20 +1674,20 @@ __global__ void __launch_bounds__(kBlock) k_grad(Geo g, const double *phi, doubl
         const int iy = (int)(r % g.ny), iz = (int)(r / g.ny);
         const int64_t xm = (ix == 0) ? i + g.nx - 1 : i - 1, xp = (ix == g.nx - 1) ? i - (g.nx - 1) : i + 1;
         const double ex = (phi[xm] - phi[xp]) * hx;
-        E[i] = ex;
+        if (E) E[i] = ex;
         if (E32) E32[i] = (float)ex;
         if (g.dim >= 2) {
             const int64_t ym = (iy == 0) ? i + sxy - g.nx : i - g.nx;
             const int64_t yp = (iy == g.ny - 1) ? i - (sxy - g.nx) : i + g.nx;
             const double ey = (phi[ym] - phi[yp]) * hy;
-            E[G + i] = ey;
+            if (E) E[G + i] = ey;
             if (E32) E32[G + i] = (float)ey;
         }
         if (g.dim == 3) {
             const int64_t zm = (iz == 0) ? i + G - sxy : i - sxy;
             const int64_t zp = (iz == g.nz - 1) ? i - (G - sxy) : i + sxy;
             const double ez = (phi[zm] - phi[zp]) * hz;
-            E[2 * G + i] = ez;
+            if (E) E[2 * G + i] = ez;
             if (E32) E32[2 * G + i] = (float)ez;
         }
     }
@@ -1914,13 +1916,13 @@ int persistent_grid(K kernel, size_t shmem, int nbuckets, int block = kBlock) {
 }
 
 hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int32_t *bstart, const double *E,
-                             const PushC &pc, int32_t *cnt, int32_t *tot, int32_t *farcnt, const int32_t *deep,
-                             const CtxDev &c, hipStream_t s) {
+                             const float *E32, const PushC &pc, int32_t *cnt, int32_t *tot, int32_t *farcnt,
+                             const int32_t *deep, const CtxDev &c, hipStream_t s) {
     if (g.em) {
         const size_t sh = em_f_tile_bytes(g, mixed);
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets, kSBlock)), dim3(kSBlock), sh, s, g, p, bstart,
-                               E, pc, cnt, tot, farcnt, deep, c);
+                               E, nullptr, pc, cnt, tot, farcnt, deep, c);
         };
         if (mixed && g.hc) go(k_step_count<true, 2, 3, APIC_STEP_U, true, true>);
         else if (mixed) go(k_step_count<true, 2, 3, APIC_STEP_U, false, true>);
@@ -1932,7 +1934,7 @@ hipError_t launch_step_count(const Geo &g, bool mixed, const Parts &p, const int
     APIC_DISPATCH(g, mixed, {
         auto kern = k_step_count<MIX, DIM, VDIM, U, HC, false>;
         hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets, kSBlock)), dim3(kSBlock), sh, s, g, p, bstart, E,
-                           pc, cnt, tot, farcnt, deep, c);
+                           MIX ? E32 : nullptr, pc, cnt, tot, farcnt, deep, c);
     });
     return hipGetLastError();
 }
@@ -1977,13 +1979,13 @@ hipError_t launch_dest_offsets(const Geo &g, const int32_t *cnt, const int32_t *
 
 hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Parts &dst, const int32_t *bstart,
                             const int32_t *bstart_new, const int32_t *cnt, const int32_t *offs, int32_t *farcnt,
-                            const double *E, const PushC &pc, void *acc, int32_t *perm, double *part, int32_t *deep,
-                            const CtxDev &c, hipStream_t s) {
+                            const double *E, const float *E32, const PushC &pc, void *acc, int32_t *perm,
+                            double *part, int32_t *deep, const CtxDev &c, hipStream_t s) {
     if (g.em) {
         const size_t sh = em_j_tile_bytes(g) + em_f_tile_bytes(g, mixed);
         auto go = [&](auto kern, auto *accp) {
             hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, sh, g.nbuckets, kSBlock)), dim3(kSBlock), sh, s, g, src, dst,
-                               bstart, bstart_new, cnt, offs, farcnt, E, pc, accp, perm, part, deep, c);
+                               bstart, bstart_new, cnt, offs, farcnt, E, nullptr, pc, accp, perm, part, deep, c);
         };
         unsigned long long *am = (unsigned long long *)acc;
         double *ad = (double *)acc;
@@ -1998,8 +2000,8 @@ hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Pa
         auto kern = k_step_push<MIX, DIM, VDIM, U, HC, false>;
         auto run = [&](auto k) {
             hipLaunchKernelGGL(k, dim3(persistent_grid(k, sh, g.nbuckets, kSBlock)), dim3(kSBlock), sh, s, g, src,
-                               dst, bstart, bstart_new, cnt, offs, farcnt, E, pc, (typename AccOf<MIX>::T *)acc, perm,
-                               part, deep, c);
+                               dst, bstart, bstart_new, cnt, offs, farcnt, E, MIX ? E32 : nullptr, pc,
+                               (typename AccOf<MIX>::T *)acc, perm, part, deep, c);
         };
         if constexpr (MIX && !HC) {
             auto kvr = k_step_push<MIX, DIM, VDIM, U, HC, false, true>;
