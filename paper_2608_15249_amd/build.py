@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libapic.so")
-SOURCES = ["apic_api.hip", "apic_kernels.hip", "apic_batch.hip", "apic_adjoint.hip", "apic_em.hip", "apic_fft.hip", "apic_tune.cpp"]
+SOURCES = ["apic_api.hip", "apic_kernels.hip", "apic_batch.hip", "apic_adjoint.hip", "apic_em.hip", "apic_fft.hip", "apic_fft3.hip", "apic_tune.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

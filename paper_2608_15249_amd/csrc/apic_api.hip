@@ -12,6 +12,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 using namespace apic;
@@ -291,6 +292,15 @@ apic_status field_from_acc(apic_ctx *c, void *acc, bool acc_is_rho, double *E, f
                                      c->dev, s));
         return APIC_OK;
     }
+    if (c->fused_fft3) {
+        // phi into the rho buffer through the two spectra buffers, then E from phi
+        HIPCHK(c, launch_fused_field3(c->g, mixed_acc, acc, scale, add, clear, rhat, ehat, rho, c->dev.tw,
+                                      mixed_acc ? c->dev.qacc : nullptr, c->dev, s));
+        const FinArgs fin{diag ? npush : 0, fused_fft3_spec_blocks(c->g), c->mass, c->dV, G, c->d.rho_ion, diag,
+                          we, charge, c->g.walls, c->d.q_macro, nlive, mixed_acc ? c->g.S * c->d.dim : 0};
+        HIPCHK(c, launch_grad(c->g, rho, E, E32, fin, c->dev, s));
+        return APIC_OK;
+    }
     if (c->g.walls)
         HIPCHK(c, launch_rho_odd(c->g, mixed_acc, acc, rho, scale, add, clear, c->dev.qacc, s));
     else
@@ -468,9 +478,11 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     // the fused field solve (unless APIC_FIELD_FFT=library asks for the
     // library transforms, for comparison)
     const char *fft_env = std::getenv("APIC_FIELD_FFT");
-    c->fused_fft = fused_fft_supported(d.dim, g.nx, g.ny, g.nz) && !(fft_env && std::string(fft_env) == "library");
-    const int nmax = g.nx > g.ny ? g.nx : g.ny;
-    const size_t tw_bytes = c->fused_fft ? 2 * sizeof(double) * nmax : 0;   // nmax complex
+    const bool lib_fft = fft_env && std::string(fft_env) == "library";
+    c->fused_fft = fused_fft_supported(d.dim, g.nx, g.ny, g.nz) && !lib_fft;
+    c->fused_fft3 = fused_fft3_supported(d.dim, g.nx, g.ny, g.nz) && !lib_fft;
+    const int nmax = std::max(g.nx, std::max(g.ny, d.dim == 3 ? g.nz : 1));
+    const size_t tw_bytes = (c->fused_fft || c->fused_fft3) ? 2 * sizeof(double) * nmax : 0;   // nmax complex
     size_t bytes = align256(sizeof(int)) * 2 + align256(sizeof(double) * 2 * g.nbuckets) +
                    align256(sizeof(double) * kMaxSpecBlocks) + align256(sizeof(double)) +
                    align256(sizeof(double) * hx) * 2 + align256(sizeof(double) * g.ny) * 2 +
@@ -492,7 +504,7 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     c->dev.kapy = (double *)take(sizeof(double) * g.ny);
     c->dev.kz2 = (double *)take(sizeof(double) * g.nz);
     c->dev.kapz = (double *)take(sizeof(double) * g.nz);
-    c->dev.tw = c->fused_fft ? (double *)take(tw_bytes) : nullptr;
+    c->dev.tw = tw_bytes ? (double *)take(tw_bytes) : nullptr;
     {
         int64_t *q = (int64_t *)take(((size_t)kQSlots * kQStride + 2) * sizeof(int64_t));
         c->dev.qacc = (unsigned long long *)q;
@@ -527,7 +539,7 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
                   hipMemcpy(c->dev.kapy, kapy.data(), sizeof(double) * g.ny, hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->dev.kz2, kz2.data(), sizeof(double) * g.nz, hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->dev.kapz, kapz.data(), sizeof(double) * g.nz, hipMemcpyHostToDevice) == hipSuccess;
-    if (copied && c->fused_fft) {
+    if (copied && tw_bytes) {
         // exp(-2 pi i k / nmax), k < nmax; the angle 2 pi k / nmax is one rounding of pi times an exact ratio
         std::vector<double> tw(2 * nmax);
         for (int k = 0; k < nmax; ++k) {

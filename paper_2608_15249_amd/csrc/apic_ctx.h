@@ -21,6 +21,7 @@ struct apic_ctx {
     hipfftHandle fwd = 0, inv = 0;
     bool have_fft = false;
     bool fused_fft = false;   // 2D periodic field solve by the fused three-launch path
+    bool fused_fft3 = false;  // 3D periodic field solve by the fused transforms in LDS
     std::string err;
     // workspace layout (byte offsets)
     size_t o_x, o_y, o_z, o_cell, o_ox, o_oy, o_oz, o_vx, o_vy, o_vz;

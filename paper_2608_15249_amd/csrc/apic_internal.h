@@ -98,7 +98,7 @@ struct FinArgs {
     int sd;
 };
 
-constexpr int kMaxSpecBlocks = 4096;   // per-block partials of the field energies
+constexpr int kMaxSpecBlocks = 16384;  // per-block partials of the field energies
 // Waves per workgroup of the fused step passes (tally, offsets, push): one
 // workgroup per bucket, so this sets the waves a tile's particles share.
 // Measured at 512^2, 16.8M particles: 6 or 8 waves per bucket were slower
@@ -200,6 +200,19 @@ bool fused_fft_supported(int dim, int nx, int ny, int nz);
 hipError_t launch_fused_field(const Geo &g, bool mixed_acc, void *acc, double scale, double add, int clear,
                               void *H, void *Z, double *E, float *E32, const double *tw, const FinArgs &f,
                               const CtxDev &c, hipStream_t s);
+// Fused periodic 3D field solve (apic_fft3.hip): power-of-two nx, ny, nz in
+// [4, kFusedFft3Max]. acc -> rho (acc cleared when clear; with qacc, the
+// fixed-point node sums' exact total is added to it) -> phi (FP64 [G]) with
+// the field-energy partials of fused_fft3_spec_blocks(g) workgroups in
+// part_spec; E follows from phi by launch_grad. A: [nz][nx/2+1][ny] and B:
+// [nx/2+1][ny][nz] complex scratch. tw: the twiddle table of CtxDev for
+// nmax = max(nx, ny, nz).
+constexpr int kFusedFft3Max = 256;
+bool fused_fft3_supported(int dim, int nx, int ny, int nz);
+int fused_fft3_spec_blocks(const Geo &g);
+hipError_t launch_fused_field3(const Geo &g, bool mixed_acc, void *acc, double scale, double add, int clear,
+                               void *A, void *B, double *phi, const double *tw, unsigned long long *qacc,
+                               const CtxDev &c, hipStream_t s);
 hipError_t launch_finalize(int npush, int nspec, double mass, double dV, double G, double rho_ion,
                            double *diag, double *we, double *charge, const CtxDev &c, hipStream_t s);
 hipError_t launch_field1d(const Geo &g, bool mixed, void *acc, double scale, double add, double ion,

@@ -30,6 +30,8 @@
 //    density is exact and independent of summation order.
 //  * This file is compiled with -ffp-contract=off: the count pass and the push
 //    pass must produce identical bits for the same particle.
+#include <algorithm>
+
 #include "apic_device.h"
 #include "apic_em.h"
 
@@ -1632,22 +1634,28 @@ __global__ void __launch_bounds__(1024) k_finalize(FinArgs f, CtxDev c) { finali
 __global__ void __launch_bounds__(kBlock) k_spectral(Geo g, const double2 *rh, double2 *ph, CtxDev c) {
     __shared__ double sRed[kWaves];
     const int hx = g.nx / 2 + 1;
-    const int64_t tot = (int64_t)hx * g.ny * g.nz;
+    const int64_t rows = (int64_t)g.ny * g.nz;
     const double norm = 1.0 / ((double)g.nx * (double)g.ny * (double)g.nz);
     double part = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
-        const int kx = (int)(i % hx);
-        const int64_t r = i / hx;
+    // one (ky, kz) row of the half spectrum per wave at a time
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const int64_t nwv = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t r = wv; r < rows; r += nwv) {
         const int ky = (int)(r % g.ny), kz = (int)(r / g.ny);
-        double K2 = c.kx2[kx] + c.ky2[ky] + c.kz2[kz];
-        double2 rr = rh[i];
-        if (i == 0) *c.rho0 = rr.x;
-        double inv = (i == 0) ? 0.0 : 1.0 / K2;
-        double pr = rr.x * inv, pi = rr.y * inv;
-        double kax = c.kapx[kx], kay = c.kapy[ky], kaz = c.kapz[kz];
-        double wgt = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
-        part += wgt * (kax * kax + kay * kay + kaz * kaz) * (pr * pr + pi * pi);
-        ph[i] = make_double2(pr * norm, pi * norm);
+        const double ky2 = c.ky2[ky], kz2 = c.kz2[kz], kay = c.kapy[ky], kaz = c.kapz[kz];
+        for (int kx = lane; kx < hx; kx += 64) {
+            const int64_t i = r * hx + kx;
+            const double K2 = (c.kx2[kx] + ky2) + kz2;
+            const double2 rr = rh[i];
+            if (i == 0) *c.rho0 = rr.x;
+            const double inv = (i == 0) ? 0.0 : 1.0 / K2;
+            const double pr = rr.x * inv, pi = rr.y * inv;
+            const double kax = c.kapx[kx];
+            const double wgt = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
+            part += wgt * (kax * kax + kay * kay + kaz * kaz) * (pr * pr + pi * pi);
+            ph[i] = make_double2(pr * norm, pi * norm);
+        }
     }
     double bs = block_sum(part, sRed);
     if (threadIdx.x == 0) c.part_spec[blockIdx.x] = bs;
@@ -1667,28 +1675,34 @@ __global__ void __launch_bounds__(kBlock) k_grad(Geo g, const double *phi, doubl
     }
     const int64_t G = (int64_t)g.nx * g.ny * g.nz;
     const int64_t sxy = (int64_t)g.nx * g.ny;
-    const int64_t stride = (int64_t)(gridDim.x - 1) * blockDim.x;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G; i += stride) {
-        const int ix = (int)(i % g.nx);
-        const int64_t r = i / g.nx;
+    const int64_t rows = (int64_t)g.ny * g.nz;
+    // one (y, z) row per wave at a time: the neighbour rows' offsets once per row
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const int64_t nwv = (int64_t)(gridDim.x - 1) * (blockDim.x >> 6);
+    for (int64_t r = wv; r < rows; r += nwv) {
         const int iy = (int)(r % g.ny), iz = (int)(r / g.ny);
-        const int64_t xm = (ix == 0) ? i + g.nx - 1 : i - 1, xp = (ix == g.nx - 1) ? i - (g.nx - 1) : i + 1;
-        const double ex = (phi[xm] - phi[xp]) * hx;
-        if (E) E[i] = ex;
-        if (E32) E32[i] = (float)ex;
-        if (g.dim >= 2) {
-            const int64_t ym = (iy == 0) ? i + sxy - g.nx : i - g.nx;
-            const int64_t yp = (iy == g.ny - 1) ? i - (sxy - g.nx) : i + g.nx;
-            const double ey = (phi[ym] - phi[yp]) * hy;
-            if (E) E[G + i] = ey;
-            if (E32) E32[G + i] = (float)ey;
-        }
-        if (g.dim == 3) {
-            const int64_t zm = (iz == 0) ? i + G - sxy : i - sxy;
-            const int64_t zp = (iz == g.nz - 1) ? i - (G - sxy) : i + sxy;
-            const double ez = (phi[zm] - phi[zp]) * hz;
-            if (E) E[2 * G + i] = ez;
-            if (E32) E32[2 * G + i] = (float)ez;
+        const int64_t row = r * g.nx;
+        const int64_t ym = (iy == 0) ? row + sxy - g.nx : row - g.nx;
+        const int64_t yp = (iy == g.ny - 1) ? row - (sxy - g.nx) : row + g.nx;
+        const int64_t zm = (iz == 0) ? row + G - sxy : row - sxy;
+        const int64_t zp = (iz == g.nz - 1) ? row - (G - sxy) : row + sxy;
+        for (int ix = lane; ix < g.nx; ix += 64) {
+            const int64_t i = row + ix;
+            const int xm = (ix == 0) ? g.nx - 1 : ix - 1, xp = (ix == g.nx - 1) ? 0 : ix + 1;
+            const double ex = (phi[row + xm] - phi[row + xp]) * hx;
+            if (E) E[i] = ex;
+            if (E32) E32[i] = (float)ex;
+            if (g.dim >= 2) {
+                const double ey = (phi[ym + ix] - phi[yp + ix]) * hy;
+                if (E) E[G + i] = ey;
+                if (E32) E32[G + i] = (float)ey;
+            }
+            if (g.dim == 3) {
+                const double ez = (phi[zm + ix] - phi[zp + ix]) * hz;
+                if (E) E[2 * G + i] = ez;
+                if (E32) E32[2 * G + i] = (float)ez;
+            }
         }
     }
 }
@@ -2051,9 +2065,11 @@ hipError_t launch_spectral(const Geo &g, const void *rho_hat, void *phi_hat, con
 
 hipError_t launch_grad(const Geo &g, const double *phi, double *E, float *E32, const FinArgs &f,
                        const CtxDev &c, hipStream_t s) {
-    const int64_t G = (int64_t)g.nx * g.ny * g.nz;
     const double hx = 0.5 * g.inv_dx, hy = 0.5 * g.inv_dy, hz = 0.5 * g.inv_dz;
-    hipLaunchKernelGGL(k_grad, dim3(blocks_for(G, 8192) + 1), dim3(kBlock), 0, s, g, phi, E, E32, hx, hy, hz, f, c);
+    // a wave per (y, z) row, up to 8192 workgroups, then the diagnostics block
+    const int64_t rows = (int64_t)g.ny * g.nz;
+    const int nblk = (int)std::min<int64_t>(std::max<int64_t>((rows + kWaves - 1) / kWaves, 1), 8192);
+    hipLaunchKernelGGL(k_grad, dim3(nblk + 1), dim3(kBlock), 0, s, g, phi, E, E32, hx, hy, hz, f, c);
     return hipGetLastError();
 }
 
