@@ -36,6 +36,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# the timed run times the push pass with HIP events on one step in this many
+PROF_EVERY = 10
 
 # Algorithmic HBM bytes per particle and pass: the particle state is read
 # once (count pass) or read and written once (push pass); grid terms are
@@ -46,9 +48,9 @@ def state_bytes(precision, dim, vdim):
     return 4 + 4 * dim + 4 * vdim if precision == "mixed" else 8 * dim + 8 * vdim
 
 
-PHASE_NOTE = ("from a separate run of %d steps after the timed one, with HIP events between all phases (each "
+PHASE_NOTE = ("from a separate run of %%d steps after the timed one, with HIP events between all phases (each "
               "event drains the queue, so these sum to more than ms_per_step); the timed run records only the two "
-              "events around the push, whose duration gives roofline.achieved")
+              "events around the push, on one step in %d, whose average duration gives roofline.achieved" % PROF_EVERY)
 
 
 def phase_breakdown(ctx, run, steps):
@@ -174,9 +176,11 @@ def run_path(precision, w, state, steps, warmup, tile, torch, pusher="boris", c_
     n = sim.n
     n_start = int(sim.p.bucket_start[-1].item()) if walls else n
     diag = torch.zeros(steps * 4, dtype=torch.float64, device="cuda")
-    # the timed run records HIP events around the push pass only (each event
-    # makes the queue drain between kernels)
+    # the timed run records HIP events around the push pass only, on one step
+    # in PROF_EVERY (each event makes the queue drain between kernels, about
+    # 6 us a side at 1024^2)
     sim.ctx.profile_phases(False)
+    sim.ctx.profile_every(PROF_EVERY)
     sim.ctx.profile_enable(steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -186,6 +190,7 @@ def run_path(precision, w, state, steps, warmup, tile, torch, pusher="boris", c_
     sim.ctx.sync()
     ms_t, nprof_t = sim.ctx.profile_read()
     sim.ctx.profile_enable(0)
+    sim.ctx.profile_every(1)
     elapsed = t1 - t0
     sb = state_bytes(precision, w.dim, w.vdim)
     push_ms = ms_t[2] / max(nprof_t, 1)
@@ -261,6 +266,7 @@ def run_em(precision, w, state, steps, warmup, tile, c_light, torch):
     ctx.sync()
     diag = torch.zeros(steps * 4, dtype=torch.float64, device="cuda")
     ctx.profile_phases(False)
+    ctx.profile_every(PROF_EVERY)
     ctx.profile_enable(steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -270,6 +276,7 @@ def run_em(precision, w, state, steps, warmup, tile, c_light, torch):
     ctx.sync()
     ms_t, nprof_t = ctx.profile_read()
     ctx.profile_enable(0)
+    ctx.profile_every(1)
     elapsed = t1 - t0
     sb = state_bytes(precision, 2, 3)
     push_ms = ms_t[2] / max(nprof_t, 1)

@@ -308,6 +308,15 @@ apic_status apic_profile_read(apic_ctx *ctx, double ms[4], int *steps);
  * records only the push pass. Discards the steps profiled so far. */
 apic_status apic_profile_phases(apic_ctx *ctx, int all);
 
+/* Profile one step in every `every` (>= 1; 1, the default, profiles each
+ * step up to max_steps): the events are recorded on steps 0, every,
+ * 2 every, ... of the calls after this one (counted from the last
+ * apic_profile_enable, apic_profile_phases, apic_profile_every or
+ * apic_profile_read), so that a throughput run pays their cost on a sample
+ * of its steps only. Discards the steps profiled so far; APIC_EINVAL for
+ * every < 1. */
+apic_status apic_profile_every(apic_ctx *ctx, int every);
+
 /* Convert a physical FP64 state to the context's particle representation (any
  * order): x, y, z [dev, double, n] positions (y NULL in 1D, z NULL below 3D),
  * vx, vy, vz [dev, double, n] velocities (NULL beyond vdim). FP64 path: copies

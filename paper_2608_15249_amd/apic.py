@@ -62,6 +62,7 @@ class BatchStateC(ctypes.Structure):
 EXPORTS = ["apic_create", "apic_destroy", "apic_workspace_size", "apic_num_buckets", "apic_frac_bits", "apic_tile_size",
            "apic_sort_by_cell", "apic_deposit", "apic_field_solve", "apic_gather_push", "apic_step",
            "apic_sync_status", "apic_last_error", "apic_profile_enable", "apic_profile_read", "apic_profile_phases",
+           "apic_profile_every",
            "apic_batch_create", "apic_batch_destroy", "apic_batch_sizes", "apic_batch_offsets",
            "apic_batch_work_items", "apic_batch_init", "apic_batch_step", "apic_batch_sync_status",
            "apic_batch_last_error", "apic_autotune_tiles", "apic_batch_autotune_chunk",
@@ -99,6 +100,7 @@ def load_library(path: str = LIB_PATH):
         "apic_last_error": ([vp], ctypes.c_char_p),
         "apic_profile_enable": ([vp, cint], cint),
         "apic_profile_read": ([vp, P(ctypes.c_double), P(cint)], cint),
+        "apic_profile_every": ([vp, cint], cint),
         "apic_profile_phases": ([vp, cint], cint),
         "apic_batch_create": ([P(ReplicaC), cint, dbl, dbl, dbl, cint, P(vp)], cint),
         "apic_batch_destroy": ([vp], None),
@@ -234,6 +236,10 @@ class Context:
         """Events around every phase (True, the default) or only around the
         push pass (False: the cheaper form for throughput runs)."""
         self._check(self.L.apic_profile_phases(self.h, 1 if all_phases else 0))
+
+    def profile_every(self, every: int):
+        """Profile one step in every `every` (1: each step)."""
+        self._check(self.L.apic_profile_every(self.h, int(every)))
 
     def profile_read(self):
         """Summed milliseconds per phase (count, scan, push, field) and steps."""

@@ -707,7 +707,7 @@ apic_status step_run(apic_ctx *c, apic_particles *p, const Parts &B, int32_t *bs
         int32_t *bs_dst = even ? bsB : bsA;
         const bool last = k == nsteps - 1;
         hipEvent_t *ev = nullptr;
-        if (c->prof_used < c->prof_max) ev = &c->ev[5 * (size_t)c->prof_used++];
+        if (c->prof_used < c->prof_max && c->prof_step++ % c->prof_every == 0) ev = &c->ev[5 * (size_t)c->prof_used++];
         if (ev && c->prof_all) HIPCHK(c, hipEventRecord(ev[0], s));
         int32_t *tot_k = tot + (even ? 0 : nb), *tot_n = tot + (even ? nb : 0);
         HIPCHK(c, launch_step_count(c->g, c->mixed, src, bs_src, E, k > 0 ? e32 : nullptr, pc, cnt, tot_k, farcnt,
@@ -801,6 +801,7 @@ apic_status apic_profile_enable(apic_ctx *c, int max_steps) {
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
     c->prof_max = c->prof_used = 0;
+    c->prof_step = 0;
     if (max_steps == 0) return APIC_OK;
     c->ev.resize(5 * (size_t)max_steps);
     for (auto &e : c->ev) HIPCHK(c, hipEventCreate(&e));
@@ -812,6 +813,15 @@ apic_status apic_profile_phases(apic_ctx *c, int all) {
     if (!c) return APIC_EINVAL;
     c->prof_all = all != 0;
     c->prof_used = 0;
+    c->prof_step = 0;
+    return APIC_OK;
+}
+
+apic_status apic_profile_every(apic_ctx *c, int every) {
+    if (!c || every < 1) return APIC_EINVAL;
+    c->prof_every = every;
+    c->prof_used = 0;
+    c->prof_step = 0;
     return APIC_OK;
 }
 
@@ -819,6 +829,7 @@ apic_status apic_profile_read(apic_ctx *c, double ms[4], int *steps) {
     if (!c || !ms || !steps) return APIC_EINVAL;
     for (int k = 0; k < 4; ++k) ms[k] = 0.0;
     *steps = c->prof_used;
+    c->prof_step = 0;
     if (c->prof_used == 0) return APIC_OK;
     HIPCHK(c, hipEventSynchronize(c->ev[5 * (size_t)(c->prof_used - 1) + (c->prof_all ? 4 : 3)]));
     for (int st = 0; st < c->prof_used; ++st) {

@@ -37,6 +37,8 @@ struct apic_ctx {
     std::vector<hipEvent_t> ev;   // 5 events per profiled step
     int prof_max = 0, prof_used = 0;
     bool prof_all = true;          // events around every phase, or only around the push pass
+    int prof_every = 1;            // events on one step in prof_every
+    int64_t prof_step = 0;         // steps seen since profiling was armed
 };
 
 namespace apic_host {

@@ -387,7 +387,7 @@ apic_status apic_em_step(apic_ctx *c, apic_particles *p, double *F, double *J, i
         int32_t *bs_dst = even ? bsB : bsA;
         const bool last = k == nsteps - 1;
         hipEvent_t *ev = nullptr;
-        if (c->prof_used < c->prof_max) ev = &c->ev[5 * (size_t)c->prof_used++];
+        if (c->prof_used < c->prof_max && c->prof_step++ % c->prof_every == 0) ev = &c->ev[5 * (size_t)c->prof_used++];
         if (ev && c->prof_all) HIPCHK(c, hipEventRecord(ev[0], s));
         int32_t *tot_k = tot + (even ? 0 : nb), *tot_n = tot + (even ? nb : 0);
         // F^n in F on even steps and in F2 on odd ones; J^{n+1/2} alternates likewise

@@ -495,4 +495,20 @@ def test_profile_phases_modes(torch):
             assert all(m > 0 for m in ms)
         else:
             assert ms[0] == 0 and ms[1] == 0 and ms[3] == 0
+    # one step in three: steps 0, 3 and 6 of seven (then 0 of a second call)
+    c.profile_phases(False)
+    c.profile_every(3)
+    c.profile_enable(8)
+    c.step(p, E, E32, 7)
+    c.sync()
+    ms, steps = c.profile_read()
+    assert steps == 3 and ms[2] > 0
+    c.step(p, E, E32, 2)
+    c.sync()
+    assert c.profile_read()[1] == 1
+    c.profile_enable(0)
+    c.profile_every(1)
+    from paper_2608_15249_amd.apic import ApicError
+    with pytest.raises(ApicError):
+        c.profile_every(0)
     c.profile_phases(True)
