@@ -1108,20 +1108,14 @@ __global__ void __launch_bounds__(kSBlock) k_scan_offsets(Geo g, const int32_t *
 // call's, held in vector registers (vreg). This build spills no scalar
 // registers inside the chunk loop but needs more vector registers; the
 // launch takes it where that costs no resident workgroup.
-// Waves per SIMD the push is compiled for (0: the compiler's choice). Each
-// push workgroup owns one bucket, so the resident waves per SIMD are at most
-// kSWaves * (buckets per CU) / 4 whatever the register count.
-#ifndef APIC_PUSH_WAVES_PER_EU
-#define APIC_PUSH_WAVES_PER_EU 0
-#endif
-#if APIC_PUSH_WAVES_PER_EU > 0
-#define APIC_PUSH_BOUNDS __launch_bounds__(kSBlock, APIC_PUSH_WAVES_PER_EU)
-#else
-#define APIC_PUSH_BOUNDS __launch_bounds__(kSBlock)
-#endif
+// The mixed electromagnetic push (Boris), bound by its vector ALU work, holds
+// its tile constants in vector registers too and is compiled for five waves
+// per SIMD (96 vector registers), the most its LDS tile allows at 32 x 16.
+template <bool MIX, bool HC, bool EM>
+constexpr int push_waves() { return (MIX && EM && !HC) ? 5 : 1; }
 
 template <bool MIX, int DIM, int VDIM, int U, bool HC, bool EM, bool VR = false>
-__global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const int32_t *bstart,
+__global__ void __launch_bounds__(kSBlock, (push_waves<MIX, HC, EM>())) k_step_push(Geo g, Parts src, Parts dst, const int32_t *bstart,
                                                       const int32_t *bstart_new, const int32_t *cnt,
                                                       const int32_t *offs, int32_t *farcnt, const double *E,
                                                       const float *E32, PushC pc,
@@ -1161,11 +1155,11 @@ __global__ void APIC_PUSH_BOUNDS k_step_push(Geo g, Parts src, Parts dst, const 
     const int lane = (int)(threadIdx.x & 63);
     int it = 0;   // chunks processed by this workgroup (the parity picks the count table)
     static_assert(!VR || (MIX && !HC && !EM), "the register-relieved build is the mixed electrostatic push");
-    constexpr bool kVt = VR, kVc = VR && DIM == 2;
+    constexpr bool kVt = VR || (MIX && EM && !HC), kVc = VR && DIM == 2;
     // all ones for the waves before this one (their counts come first)
     int before[kSWaves];
 #pragma unroll
-    for (int w2 = 0; w2 < kSWaves; ++w2) before[w2] = vreg<kVt>(w2 < w ? -1 : 0);
+    for (int w2 = 0; w2 < kSWaves; ++w2) before[w2] = vreg<kVt || (MIX && EM)>(w2 < w ? -1 : 0);
     if (threadIdx.x == 0) sErr = 0;
     int first, end, stride;
     bucket_walk(g.nbuckets, first, end, stride);
