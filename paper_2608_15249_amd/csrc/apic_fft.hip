@@ -10,11 +10,13 @@
 //      node sums are also reduced exactly (integer sums) for the charge.
 //   2. k_fft_cols: one workgroup per column kx of H. FFT along y, then
 //      phi_hat = rho_hat / K^2 (K^2 the Laplacian's modified wavenumber,
-//      phi_hat(0) = 0) and E_hat_d = -i kappa_d phi_hat (kappa_d = sin(k d)/d,
-//      the centred difference), with the per-block Parseval partial of
-//      sum |E_hat|^2. Inverse FFT along y of phi_hat and kappa_y phi_hat; the
-//      x-spectrum Z of the complex field Ex + i Ey follows at columns kx and
-//      nx - kx from the Hermitian symmetry of the two real fields. Z is
+//      phi_hat(0) = 0), with the per-block Parseval partial of
+//      sum |E_hat|^2 (E_hat_d = -i kappa_d phi_hat, kappa_d = sin(k d)/d the
+//      symbol of the centred difference). One inverse FFT along y gives the
+//      x-spectrum of phi at kx; Ex~ = -i kappa_x of it, and Ey~ its centred
+//      difference along y. The x-spectrum Z of the complex field Ex + i Ey
+//      follows at columns kx and nx - kx from the Hermitian symmetry of the
+//      two real fields. Z is
 //      stored column by column ([nx][ny]), so that each workgroup writes its
 //      two columns as whole contiguous lines (stores that cover part of a
 //      line measured far slower than whole-line stores).
@@ -24,9 +26,10 @@
 //      (and their binary32 rounding). The launch's last workgroup reduces
 //      the diagnostics.
 // The same mathematics as the general path (library real-to-complex
-// transforms, spectral division, real-space centred difference); the
-// gradient is taken in spectral form, -i sin(k d)/d, which is the transform
-// of the centred difference exactly.
+// transforms, spectral division, real-space centred difference); the x
+// derivative is taken in spectral form, -i sin(kx dx)/dx, which is the
+// transform of the centred difference exactly, the y derivative as the
+// centred difference itself, applied to the x-spectrum of phi.
 //
 // Transforms: Stockham passes between two LDS buffers (the output in natural
 // order, one barrier per pass), radix 8 in registers after one radix-2 or
@@ -108,30 +111,26 @@ __global__ void __launch_bounds__(kBlock) k_fft_rows(Geo g, typename AccOf<MIX>:
     }
 }
 
-// LDS: two buffers of 2 ny complex when pair (the two inverse transforms
-// run together), else three of ny (one after the other). Block b handles
-// column (b % 8) * per + b / 8 (per = ceil(hx / 8)), so that neighbouring
-// columns share an XCD's L2; blocks past the last column only write their
-// zero partial.
+// LDS: two buffers of ny complex. Block b handles column (b % 8) * per + b / 8
+// (per = ceil(hx / 8)), so that neighbouring columns share an XCD's L2;
+// blocks past the last column only write their zero partial.
 __global__ void __launch_bounds__(kBlock) k_fft_cols(Geo g, const double2 *H, double2 *Z, const double2 *tw,
-                                                     int lgny, int lgmax, int per, int pair, CtxDev c) {
+                                                     int lgny, int lgmax, int per, CtxDev c) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double sRed[kWaves];
     const int nx = g.nx, ny = g.ny, hx = nx / 2 + 1;
-    double2 *A = (double2 *)smem, *B = A + (pair ? 2 * ny : ny), *C = B + ny;
+    double2 *A = (double2 *)smem, *B = A + ny;
     const int kx = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     double part = 0.0;
     if (kx < hx) {
         for (int y = threadIdx.x; y < ny; y += blockDim.x) A[y] = H[(int64_t)y * hx + kx];
         __syncthreads();
         double2 *R = fft_lds<-1>(A, B, lgny, 1, tw, lgmax);
-        double2 *S = pair ? ((R == A) ? B : A) : C;
-        double2 *S2 = pair ? S + ny : R;
+        double2 *S = (R == A) ? B : A;
         const double norm = 1.0 / ((double)nx * (double)ny);
         const double kx2 = c.kx2[kx], kax = c.kapx[kx];
         const double wgt = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
-        // phi_hat and kappa_y phi_hat (scaled by 1/G for the unnormalised
-        // inverses) into S and S2 (side by side, or over rho_hat in place)
+        // phi_hat (scaled by 1/G for the unnormalised inverse) into S
         for (int ky = threadIdx.x; ky < ny; ky += blockDim.x) {
             const double2 r = R[ky];
             if (kx == 0 && ky == 0) *c.rho0 = r.x;
@@ -140,29 +139,24 @@ __global__ void __launch_bounds__(kBlock) k_fft_cols(Geo g, const double2 *H, do
             const double kay = c.kapy[ky];
             part += wgt * (kax * kax + kay * kay) * (pr * pr + pi * pi);
             S[ky] = make_double2(pr * norm, pi * norm);
-            S2[ky] = make_double2(kay * pr * norm, kay * pi * norm);
         }
         __syncthreads();
-        // P = inverse_y(phi_hat), Q = inverse_y(kappa_y phi_hat); Ex~ = -i kappa_x P, Ey~ = -i Q
-        const double2 *P, *Q;
-        if (pair) {
-            P = fft_lds<+1>(S, R, lgny, 2, tw, lgmax);
-            Q = P + ny;
-        } else {
-            double2 *F = (R == A) ? B : A;
-            P = fft_lds<+1>(S, F, lgny, 1, tw, lgmax);
-            Q = fft_lds<+1>(S2, (P == S) ? F : S, lgny, 1, tw, lgmax);
-        }
+        // P = inverse_y(phi_hat), the x-spectrum of phi at this kx. Ex~ = -i kappa_x P;
+        // Ey~ = -(P(y+1) - P(y-1)) / (2 dy), the centred difference along y (whose
+        // symbol i sin(ky dy)/dy makes it the inverse of -i kappa_y phi_hat)
+        const double2 *P = fft_lds<+1>(S, R, lgny, 1, tw, lgmax);
+        const double hy = 0.5 * g.inv_dy;
         const bool self = kx == 0 || 2 * kx == nx;
         const int64_t c0 = (int64_t)kx * ny, c1 = (int64_t)(nx - kx) * ny;   // column-major Z
         for (int y = threadIdx.x; y < ny; y += blockDim.x) {
-            const double2 p = P[y], q = Q[y];
+            const double2 p = P[y], pm = P[(y - 1) & (ny - 1)], pp = P[(y + 1) & (ny - 1)];
+            const double dx_ = (pp.x - pm.x) * hy, dy_ = (pp.y - pm.y) * hy;   // centred difference of P
             if (self) {
                 // a self-conjugate column of two real fields: their real parts
-                Z[c0 + y] = make_double2(kax * p.y, q.y);
+                Z[c0 + y] = make_double2(kax * p.y, -dx_);
             } else {
-                Z[c0 + y] = make_double2(kax * p.y + q.x, -kax * p.x + q.y);
-                Z[c1 + y] = make_double2(kax * p.y - q.x, kax * p.x + q.y);
+                Z[c0 + y] = make_double2(kax * p.y + dy_, -kax * p.x - dx_);
+                Z[c1 + y] = make_double2(kax * p.y - dy_, kax * p.x - dx_);
             }
         }
     }
@@ -223,9 +217,7 @@ hipError_t launch_fused_field(const Geo &g, bool mixed_acc, void *acc, double sc
     const int lgmax = lgnx > lgny ? lgnx : lgny;
     const double2 *tw = (const double2 *)tw_table;
     const size_t sh_rows = 2 * (size_t)g.nx * sizeof(double2);
-    // the paired inverse needs 4 ny complex; keep within 64 KiB with the static reduction array
-    const int pair = 4 * (size_t)g.ny * sizeof(double2) + 256 <= 65536 ? 1 : 0;
-    const size_t sh_cols = (pair ? 4 : 3) * (size_t)g.ny * sizeof(double2);
+    const size_t sh_cols = 2 * (size_t)g.ny * sizeof(double2);
     const dim3 rows(g.ny / 2);
     if (mixed_acc) {
         auto *a = (unsigned long long *)acc;
@@ -248,7 +240,7 @@ hipError_t launch_fused_field(const Geo &g, bool mixed_acc, void *acc, double sc
     const int per = (hx + 7) / 8;
     const int ncol = 8 * per;
     hipLaunchKernelGGL(k_fft_cols, dim3(ncol), dim3(kBlock), sh_cols, s, g, (const double2 *)H, (double2 *)Z, tw,
-                       lgny, lgmax, per, pair, c);
+                       lgny, lgmax, per, c);
     FinArgs f = f0;
     f.nspec = ncol;
     hipLaunchKernelGGL(k_fft_rows_inv, dim3(g.ny + 1), dim3(kBlock), sh_rows, s, g, (const double2 *)Z, E, E32, tw,
