@@ -1156,6 +1156,10 @@ __global__ void __launch_bounds__(kSBlock, (push_waves<MIX, HC, EM>())) k_step_p
     int it = 0;   // chunks processed by this workgroup (the parity picks the count table)
     static_assert(!VR || (MIX && !HC && !EM), "the register-relieved build is the mixed electrostatic push");
     constexpr bool kVt = VR || (MIX && EM && !HC), kVc = VR && DIM == 2;
+    // the LDS tiles' strides as the per-particle code reads them (in vector
+    // registers in 2D; in 3D they would cost the VR build a wave per SIMD)
+    const int pwx = vreg<kVc>(wx), pwy = vreg<kVc>(wy), pwxy = vreg<kVc>(wxy);
+    const int pex = vreg<kVc>(ex_w), pey = vreg<kVc>(ey_w), pez = vreg<kVc>(ez_w);
     // all ones for the waves before this one (their counts come first)
     int before[kSWaves];
 #pragma unroll
@@ -1301,7 +1305,7 @@ __global__ void __launch_bounds__(kSBlock, (push_waves<MIX, HC, EM>())) k_step_p
                     if constexpr (EM) {
                         good = advance_em<MIX, HC>(q, gv, pv, sE, fw, x0, y0, lx, ly, sx, sy, f0x, f0y, ig) && good;
                     } else {
-                        good = advance<MIX, DIM, VDIM, HC>(q, gv, pv, sE, ex_w, ey_w, ez_w, x0, y0, z0, lx, ly, lz, sx,
+                        good = advance<MIX, DIM, VDIM, HC>(q, gv, pv, sE, pex, pey, pez, x0, y0, z0, lx, ly, lz, sx,
                                                            sy, sz) && good;
                     }
                     if (!good) atomicOr(&sErr, ERR_DOMAIN);
@@ -1373,22 +1377,22 @@ __global__ void __launch_bounds__(kSBlock, (push_waves<MIX, HC, EM>())) k_step_p
                     const int dlx = lx + sx + g.halo;
                     const int dly = (DIM >= 2) ? ly + sy + g.halo : 0;
                     const int dlz = (DIM == 3) ? lz + sz + g.halo : 0;
-                    bool inl = (unsigned)dlx <= (unsigned)(wx - 2);
-                    if constexpr (DIM >= 2) inl = inl && (unsigned)dly <= (unsigned)(wy - 2);
+                    bool inl = (unsigned)dlx <= (unsigned)(pwx - 2);
+                    if constexpr (DIM >= 2) inl = inl && (unsigned)dly <= (unsigned)(pwy - 2);
                     if constexpr (DIM == 3) inl = inl && (unsigned)dlz <= (unsigned)(wz - 2);
                     if (inl) {
-                        const int a0 = (dlz * wy + dly) * wx + dlx;
+                        const int a0 = (dlz * pwy + dly) * pwx + dlx;
                         acc_add_lds<MIX>(&sA[a0], wgt[0]);
                         acc_add_lds<MIX>(&sA[a0 + 1], wgt[1]);
                         if constexpr (DIM >= 2) {
-                            acc_add_lds<MIX>(&sA[a0 + wx], wgt[2]);
-                            acc_add_lds<MIX>(&sA[a0 + wx + 1], wgt[3]);
+                            acc_add_lds<MIX>(&sA[a0 + pwx], wgt[2]);
+                            acc_add_lds<MIX>(&sA[a0 + pwx + 1], wgt[3]);
                         }
                         if constexpr (DIM == 3) {
-                            acc_add_lds<MIX>(&sA[a0 + wxy], wgt[4]);
-                            acc_add_lds<MIX>(&sA[a0 + wxy + 1], wgt[5]);
-                            acc_add_lds<MIX>(&sA[a0 + wxy + wx], wgt[6]);
-                            acc_add_lds<MIX>(&sA[a0 + wxy + wx + 1], wgt[7]);
+                            acc_add_lds<MIX>(&sA[a0 + pwxy], wgt[4]);
+                            acc_add_lds<MIX>(&sA[a0 + pwxy + 1], wgt[5]);
+                            acc_add_lds<MIX>(&sA[a0 + pwxy + pwx], wgt[6]);
+                            acc_add_lds<MIX>(&sA[a0 + pwxy + pwx + 1], wgt[7]);
                         }
                     } else if constexpr (DIM == 3) {
                         deposit_global3<MIX>(acc, g, q.ix, q.iy, q.iz, wgt);
