@@ -393,6 +393,12 @@ apic_status apic_create(const apic_grid_desc *desc, int64_t n_particles, apic_ct
     // 2 lx); particles live in the first nx cells
     g.walls = d.walls_x;
     g.nxp = d.nx;
+    // the push build (APIC_PUSH_VR=0 or 1 forces the plain or the
+    // register-relieved one, for comparisons; otherwise by resident workgroups)
+    {
+        const char *vr_env = std::getenv("APIC_PUSH_VR");
+        g.push_vr = !vr_env ? 0 : (std::string(vr_env) == "1" ? 2 : (std::string(vr_env) == "0" ? 1 : 0));
+    }
     if (g.walls) {
         g.nx = 2 * d.nx;
         c->d.nx = g.nx;

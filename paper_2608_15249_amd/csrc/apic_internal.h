@@ -32,6 +32,7 @@ struct Geo {
     int nxp;              // physical cells along x (nx without walls)
     double lx, ly, lz;
     double inv_dx, inv_dy, inv_dz;
+    int push_vr;          // mixed electrostatic push build: 0 by resident workgroups, 1 plain, 2 VR
 };
 
 // Boris / move coefficients for one call (dt_eff = dt * dt_scale).

@@ -2017,7 +2017,9 @@ hipError_t launch_step_push(const Geo &g, bool mixed, const Parts &src, const Pa
         };
         if constexpr (MIX && !HC) {
             auto kvr = k_step_push<MIX, DIM, VDIM, U, HC, false, true>;
-            if (resident_per_cu(kvr, sh, g.nbuckets, kSBlock) >= resident_per_cu(kern, sh, g.nbuckets, kSBlock))
+            if (g.push_vr == 2 ||
+                (g.push_vr == 0 &&
+                 resident_per_cu(kvr, sh, g.nbuckets, kSBlock) >= resident_per_cu(kern, sh, g.nbuckets, kSBlock)))
                 run(kvr);
             else
                 run(kern);
