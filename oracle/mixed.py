@@ -23,7 +23,8 @@ multiply-add), in the order of the textbook formulas of the FP64 oracle:
            t = tau / gp; s = 1 / (1 + t t);
            p = s (mx + my t, my - mx t, mz + (mz t) t);
            u = (px + aEx + py t, py + aEy - px t, pz + aEz); the move uses
-           v = u / sqrt(1 + ((ux ux + uy uy) + uz uz) ic2)
+           v = u r with r = 1 / sqrt(1 + ((ux ux + uy uy) + uz uz) ic2)
+           (one binary32 division for r, then three products)
   move   : o' = o + v * fl32(dt/dx); k = floor(o'); o' = o' - k;
            if o' >= 1 then o' = o' - 1, k = k + 1; cell = (cell + k) mod n.
 The deposit of the result is oracle.deposit_quantised (exact integers).
@@ -153,7 +154,8 @@ def push(st: dict, E32, *, dim, vdim, nx, ny, dx, dy, qm, dt, bz, dt_scale=1.0, 
         wx, wy, wz = vx, vy, vz
         if pusher == "hc":
             g = np.sqrt(f32(1.0) + (vx * vx + vy * vy + vz * vz) * ic2).astype(f32)
-            wx, wy, wz = (vx / g).astype(f32), (vy / g).astype(f32), (vz / g).astype(f32)
+            r = (f32(1.0) / g).astype(f32)
+            wx, wy, wz = (vx * r).astype(f32), (vy * r).astype(f32), (vz * r).astype(f32)
         out["ix"], out["ox"] = mv(ix, fx, wx, dx, nx)
         if dim >= 2:
             out["iy"], out["oy"] = mv(iy, fy, wy, dy, ny)

@@ -323,8 +323,8 @@ __device__ __forceinline__ void higuera_cary(R &ux, R &uy, R &uz, R ex, R ey, R 
     uz = pz + a * ez;
 }
 
-// 1 / gamma of u = gamma v: 1 / sqrt(1 + |u|^2 / c^2), as a division of u by
-// gamma in the move.
+// gamma of u = gamma v: sqrt(1 + |u|^2 / c^2); the move divides u by it
+// (FP64) or multiplies u by its correctly rounded reciprocal (binary32).
 template <typename R>
 __device__ __forceinline__ R lorentz(R ux, R uy, R uz, R ic2) {
     return sqrt(R(1) + ((ux * ux + uy * uy) + uz * uz) * ic2);
@@ -422,7 +422,13 @@ __device__ __forceinline__ bool push_move(Pt<MIX> &p, const Geo &g, const PushC 
             return true;
         }
         const R gm = lorentz<R>(p.vx, p.vy, p.vz, ic2);
-        return move_pt_v<MIX, DIM>(p, g, pc, p.vx / gm, p.vy / gm, p.vz / gm, sx, sy, sz);
+        if constexpr (MIX) {
+            // binary32: one correctly rounded 1 / gamma, then three products
+            const R ig = R(1) / gm;
+            return move_pt_v<MIX, DIM>(p, g, pc, p.vx * ig, p.vy * ig, p.vz * ig, sx, sy, sz);
+        } else {
+            return move_pt_v<MIX, DIM>(p, g, pc, p.vx / gm, p.vy / gm, p.vz / gm, sx, sy, sz);
+        }
     } else {
         if constexpr (DIM == 3) boris_z<R>(p.vz, ez, a);
         boris<R, VDIM>(p.vx, p.vy, ex, ey, a, t, s);

@@ -170,10 +170,16 @@ __device__ __forceinline__ int dir_local(const TileNb &t, int lxn, int lyn, int 
 
 // Twice the kinetic energy per unit mass of a particle for the diagnostic:
 // |v|^2 (binary32 squares on the mixed path, FP64 on the FP64 path), or for
-// the Higuera-Cary state 2 (gamma - 1) c^2 = 2 |u|^2 / (gamma + 1) in FP64.
+// the Higuera-Cary state 2 (gamma - 1) c^2 = 2 |u|^2 / (gamma + 1): in FP64
+// on the FP64 path, on the mixed path in binary32 with the hardware square
+// root and reciprocal (each within 1 ulp; a diagnostic, summed in FP64).
 template <bool MIX, int VDIM, bool HC>
 __device__ __forceinline__ double vsq(const Pt<MIX> &q, const PushC &pc) {
-    if constexpr (HC) {
+    if constexpr (HC && MIX) {
+        const float u2 = (q.vx * q.vx + q.vy * q.vy) + q.vz * q.vz;
+        const float gp1 = __builtin_amdgcn_sqrtf(1.0f + u2 * pc.ic2f) + 1.0f;
+        return (double)(2.0f * u2 * __builtin_amdgcn_rcpf(gp1));
+    } else if constexpr (HC) {
         const double ux = q.vx, uy = q.vy, uz = q.vz;
         const double u2 = (ux * ux + uy * uy) + uz * uz;
         return 2.0 * u2 / (sqrt(1.0 + u2 * pc.ic2) + 1.0);
