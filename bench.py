@@ -561,7 +561,7 @@ def main():
                          "current; FP64 2D3V, magnetized_2d3v)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (N=%d requested)" % args.gpus,
+        print("bench.py measures one GPU: the library has no multi-GPU path (N=%d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch
