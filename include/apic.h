@@ -495,7 +495,9 @@ apic_status apic_em_step(apic_ctx *ctx, apic_particles *p, double *F, double *J,
  * items from a work counter, stage the replica's whole grid in LDS, and the
  * workgroup that finishes a replica's last chunk solves its field. Particles
  * keep their order (no sort: each replica's grid fits in LDS).
- * Every replica is a neutral electron plasma: q_macro = -rho_ion * lx / n. */
+ * Every replica is a neutral electron plasma: q_macro = -rho_ion * lx / n.
+ * A replica with n = 0 is the ion background alone: q_macro = 0, its field
+ * stays zero to rounding and its diagnostics are zero. */
 typedef struct {
     int nx;          /* grid nodes, 2..1024                                    */
     int64_t n;       /* particles                                              */

@@ -165,3 +165,29 @@ def test_batch_autotune_chunk_picks_a_candidate_and_keeps_results(torch):
         s.batch.sync()
     for f in ("E", "cell", "ox", "vx"):
         assert torch.equal(getattr(a.batch, f), getattr(b.batch, f)), f
+
+
+def test_batch_empty_replica(torch):
+    """A replica with no particles (q_macro = 0: the ion background alone)
+    between others: its field stays zero to rounding and its diagnostics are
+    zero, and every other replica gives the bits it gives without it."""
+    from paper_2608_15249_amd.sim import BatchSimulation
+    nsteps = 4
+    empty = W.Replica(48, 0, 0.03, 505)
+    with_empty = [REPS[0], REPS[1], empty, REPS[2]]
+    runs = []
+    for reps in (with_empty, [REPS[0], REPS[1], REPS[2]]):
+        bs = BatchSimulation(reps, chunk=2048)
+        bs.initialise()
+        dg = bs.run(nsteps)
+        bs.batch.sync()
+        runs.append((bs, dg.cpu().numpy().reshape(nsteps, len(reps), 4)))
+    (a, da), (b, db) = runs
+    assert np.max(np.abs(a.replica_field(2))) <= 1e-12
+    assert np.array_equal(da[:, 2, [0, 2, 3]], np.zeros((nsteps, 3)))
+    assert np.all(np.abs(da[:, 2, 1]) <= 1e-20)
+    for ra, rb in ((0, 0), (1, 1), (3, 2)):
+        assert np.array_equal(a.replica_field(ra), b.replica_field(rb)), ra
+        for x, y in zip(a.replica_state(ra), b.replica_state(rb)):
+            assert np.array_equal(x, y), ra
+        assert np.array_equal(da[:, ra], db[:, rb]), ra
