@@ -1111,7 +1111,7 @@ __global__ void __launch_bounds__(kSBlock) k_scan_offsets(Geo g, const int32_t *
 // EM: the electromagnetic form (FP64 2D3V): E is the [6][G] Yee field and
 // acc the [3][G] current J^{n+1/2} (Esirkepov), accumulated with atomics.
 // VR (mixed electrostatic push only): the tile's constants, and in 2D the
-// call's, held in vector registers (vreg). This build spills no scalar
+// call's, held in vector registers (vreg). This variant spills no scalar
 // registers inside the chunk loop but needs more vector registers; the
 // launch takes it where that costs no resident workgroup.
 // The mixed electromagnetic push (Boris), bound by its vector ALU work, holds

@@ -35,12 +35,39 @@ _CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 KERNEL_SOURCES = ("apic_kernels.hip", "apic_device.h", "apic_internal.h", "apic_em.h")
 
 
+def _code_only(text: str) -> str:
+    """C++ source without its comments, trailing blanks and empty lines
+    (string and character literals kept as written)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    lines = (ln.rstrip() for ln in "".join(out).split("\n"))
+    return "\n".join(ln for ln in lines if ln)
+
+
 def kernel_source_sha() -> str:
-    """Hash of the step kernels' sources (a counter run is valid for these only)."""
+    """Hash of the step kernels' code (a counter run is valid for this code
+    only; comments and blank space do not enter it)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(_CSRC, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(_CSRC, f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

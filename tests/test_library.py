@@ -62,3 +62,14 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_kernel_source_hash_ignores_comments_only():
+    """The hash a stored counter run is checked against changes with the
+    kernels' code, not with their comments or blank lines."""
+    from paper_2608_15249_amd.rocprof_summary import _code_only
+    a = 'int f(int x) {  // doubled\n    return 2 * x; /* "x" */\n}\nconst char *s = "a // b /* c";\nchar q = \'\\\'\';\n'
+    b = '// header\n\nint f(int x) {\n    return 2 * x;   \n}\n/* a\n   block */\nconst char *s = "a // b /* c";\nchar q = \'\\\'\';\n'
+    assert _code_only(a) == _code_only(b)
+    assert '"a // b /* c"' in _code_only(a)
+    assert _code_only(a) != _code_only(a.replace("2 * x", "3 * x"))
