@@ -41,6 +41,12 @@
 namespace apic {
 namespace {
 
+static_assert(kFusedFftMax <= 8 * kBlock, "one radix-8 butterfly per thread and pass");
+
+// Entries of one line per thread (a line of at most kFusedFftMax): the loads
+// of a line are all issued before the first is waited for.
+constexpr int kLinePer = kFusedFftMax / kBlock;
+
 // LDS: two buffers of nx complex.
 // qacc (fixed-point sums only, may be NULL): the exact total of the two rows'
 // node sums (the physical nodes 0..nxp between walls) is added to it.
@@ -53,10 +59,11 @@ __global__ void __launch_bounds__(kBlock) k_fft_rows(Geo g, typename AccOf<MIX>:
     double2 *b0 = (double2 *)smem, *b1 = b0 + nx;
     const int64_t r0 = (int64_t)(2 * blockIdx.x) * nx, r1 = r0 + nx;
     const int sd = g.S * g.dim;
+    const FftTw ft = fft_twiddles(lgnx, tw, lgmax);
     QSum q{0, 0};
-    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
-        double v0, v1;
-        if constexpr (WALLS) {
+    if constexpr (WALLS) {
+        for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+            double v0, v1;
             // odd extension of the physical rows [0, nxp]: zero on the walls
             const int nxp = g.nxp;
             if (i == 0 || i == nxp) {
@@ -67,18 +74,30 @@ __global__ void __launch_bounds__(kBlock) k_fft_rows(Geo g, typename AccOf<MIX>:
                 v0 = sg * acc_value<MIX>(acc, r0 + src, scale, add);
                 v1 = sg * acc_value<MIX>(acc, r1 + src, scale, add);
             }
-        } else {
-            const typename AccOf<MIX>::T a0 = acc[r0 + i], a1 = acc[r1 + i];
-            if constexpr (MIX) {
-                if (qacc) {
-                    qsum_add(q, (int64_t)a0, sd);
-                    qsum_add(q, (int64_t)a1, sd);
-                }
-            }
-            v0 = acc_to_rho<MIX>(a0, scale, add);
-            v1 = acc_to_rho<MIX>(a1, scale, add);
+            b0[i] = make_double2(v0, v1);
         }
-        b0[i] = make_double2(v0, v1);
+    }
+    if constexpr (!WALLS) {
+        typename AccOf<MIX>::T a0[kLinePer], a1[kLinePer];
+#pragma unroll
+        for (int r = 0; r < kLinePer; ++r) {
+            const int i = min((int)threadIdx.x + r * kBlock, nx - 1);   // in bounds, used only below nx
+            a0[r] = acc[r0 + i];
+            a1[r] = acc[r1 + i];
+        }
+#pragma unroll
+        for (int r = 0; r < kLinePer; ++r) {
+            const int i = threadIdx.x + r * kBlock;
+            if (i < nx) {
+                if constexpr (MIX) {
+                    if (qacc) {
+                        qsum_add(q, (int64_t)a0[r], sd);
+                        qsum_add(q, (int64_t)a1[r], sd);
+                    }
+                }
+                b0[i] = make_double2(acc_to_rho<MIX>(a0[r], scale, add), acc_to_rho<MIX>(a1[r], scale, add));
+            }
+        }
     }
     if constexpr (MIX) {
         if (qacc) {
@@ -100,7 +119,7 @@ __global__ void __launch_bounds__(kBlock) k_fft_rows(Geo g, typename AccOf<MIX>:
             acc[r1 + i] = (typename AccOf<MIX>::T)0;
         }
     }
-    const double2 *R = fft_lds<-1>(b0, b1, lgnx, 1, tw, lgmax);
+    const double2 *R = fft_lds_one<-1>(b0, b1, lgnx, tw, lgmax, ft);
     // split: rho_j0_hat(k) = (Z(k) + conj Z(-k)) / 2, rho_j1_hat(k) = (Z(k) - conj Z(-k)) / (2i)
     const int hx = nx / 2 + 1;
     const int64_t h0 = (int64_t)(2 * blockIdx.x) * hx, h1 = h0 + hx;
@@ -123,9 +142,22 @@ __global__ void __launch_bounds__(kBlock) k_fft_cols(Geo g, const double2 *H, do
     const int kx = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     double part = 0.0;
     if (kx < hx) {
-        for (int y = threadIdx.x; y < ny; y += blockDim.x) A[y] = H[(int64_t)y * hx + kx];
+        const FftTw ft = fft_twiddles(lgny, tw, lgmax);   // the same for the inverse
+        double2 h[kLinePer];
+#pragma unroll
+        for (int r = 0; r < kLinePer; ++r) {
+            const int y = min((int)threadIdx.x + r * kBlock, ny - 1);   // in bounds, used only below ny
+            h[r] = H[(int64_t)y * hx + kx];
+        }
+#pragma unroll
+        for (int r = 0; r < kLinePer; ++r) {
+            // entries past the line go to B, which the first pass overwrites
+            // (a store for every entry keeps the loads ahead of the first wait)
+            const int y = threadIdx.x + r * kBlock;
+            *(y < ny ? &A[y] : &B[threadIdx.x & (ny - 1)]) = h[r];
+        }
         __syncthreads();
-        double2 *R = fft_lds<-1>(A, B, lgny, 1, tw, lgmax);
+        double2 *R = fft_lds_one<-1>(A, B, lgny, tw, lgmax, ft);
         double2 *S = (R == A) ? B : A;
         const double norm = 1.0 / ((double)nx * (double)ny);
         const double kx2 = c.kx2[kx], kax = c.kapx[kx];
@@ -144,7 +176,7 @@ __global__ void __launch_bounds__(kBlock) k_fft_cols(Geo g, const double2 *H, do
         // P = inverse_y(phi_hat), the x-spectrum of phi at this kx. Ex~ = -i kappa_x P;
         // Ey~ = -(P(y+1) - P(y-1)) / (2 dy), the centred difference along y (whose
         // symbol i sin(ky dy)/dy makes it the inverse of -i kappa_y phi_hat)
-        const double2 *P = fft_lds<+1>(S, R, lgny, 1, tw, lgmax);
+        const double2 *P = fft_lds_one<+1>(S, R, lgny, tw, lgmax, ft);
         const double hy = 0.5 * g.inv_dy;
         const bool self = kx == 0 || 2 * kx == nx;
         const int64_t c0 = (int64_t)kx * ny, c1 = (int64_t)(nx - kx) * ny;   // column-major Z
@@ -181,9 +213,21 @@ __global__ void __launch_bounds__(kBlock) k_fft_rows_inv(Geo g, const double2 *Z
     const int ny = g.ny;
     const int y = ny >= 8 ? (int)(blockIdx.x % 8) * (ny / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
     const int64_t row = (int64_t)y * nx;
-    for (int i = threadIdx.x; i < nx; i += blockDim.x) b0[i] = Z[(int64_t)i * ny + y];
+    const FftTw ft = fft_twiddles(lgnx, tw, lgmax);
+    double2 z[kLinePer];
+#pragma unroll
+    for (int r = 0; r < kLinePer; ++r) {
+        const int i = min((int)threadIdx.x + r * kBlock, nx - 1);   // in bounds, used only below nx
+        z[r] = Z[(int64_t)i * ny + y];
+    }
+#pragma unroll
+    for (int r = 0; r < kLinePer; ++r) {
+        // entries past the line go to b1, which the first pass overwrites
+        const int i = threadIdx.x + r * kBlock;
+        *(i < nx ? &b0[i] : &b1[threadIdx.x & (nx - 1)]) = z[r];
+    }
     __syncthreads();
-    const double2 *U = fft_lds<+1>(b0, b1, lgnx, 1, tw, lgmax);
+    const double2 *U = fft_lds_one<+1>(b0, b1, lgnx, tw, lgmax, ft);
     for (int i = threadIdx.x; i < nx; i += blockDim.x) {
         const double2 e = U[i];
         if (E) {

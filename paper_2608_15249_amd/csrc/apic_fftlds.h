@@ -125,6 +125,80 @@ __device__ double2 *fft_lds(double2 *a, double2 *b, int lgn, int m, const double
     return a;
 }
 
+// One transform of n = 2^lgn <= 8 blockDim.x points: in each radix-8 pass a
+// thread has at most one butterfly, and its twiddle can be read before the
+// data. Entry q belongs to the pass with ns = 2^(lgn % 3 + 3 q) (when that is
+// below n and not 1).
+struct FftTw {
+    double2 w[3];
+};
+
+__device__ __forceinline__ FftTw fft_twiddles(int lgn, const double2 *tw, int lgmax) {
+    FftTw f;
+    const int j = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int lgns = lgn % 3 + 3 * q;
+        f.w[q] = make_double2(1.0, 0.0);
+        if (lgns > 0 && lgns < lgn && j < (1 << (lgn - 3))) f.w[q] = tw[(j & ((1 << lgns) - 1)) << (lgmax - lgns - 3)];
+    }
+    return f;
+}
+
+// fft_pass<SIGN, 3> for one transform with at most one butterfly per thread,
+// its twiddle w1 given.
+template <int SIGN>
+__device__ __forceinline__ void fft_pass8_one(const double2 *a, double2 *b, int lgn, int lgns, double2 w1) {
+    const int nr = 1 << (lgn - 3);
+    const int ns = 1 << lgns;
+    const int j = threadIdx.x;
+    if (j < nr) {
+        const int k = j & (ns - 1);
+        double2 v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = a[j + q * nr];
+        if (lgns > 0) {
+            double2 w[8];
+            w[1] = w1;
+            if (SIGN > 0) w[1].y = -w[1].y;
+#pragma unroll
+            for (int q = 2; q < 8; ++q) w[q] = cmul(w[q / 2], w[q - q / 2]);
+#pragma unroll
+            for (int q = 1; q < 8; ++q) v[q] = cmul(v[q], w[q]);
+        }
+        dft8<SIGN>(v);
+        const int d = ((j - k) << 3) + k;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) b[d + q * ns] = v[q];
+    }
+    __syncthreads();
+}
+
+// fft_lds for one transform of n <= 8 blockDim.x points with the twiddles of
+// fft_twiddles (the same arithmetic in the same order).
+template <int SIGN>
+__device__ double2 *fft_lds_one(double2 *a, double2 *b, int lgn, const double2 *tw, int lgmax, const FftTw &f) {
+    int lgns = lgn % 3;
+    if (lgns == 1) fft_pass<SIGN, 1>(a, b, lgn, 1, 0, tw, lgmax);
+    if (lgns == 2) fft_pass<SIGN, 2>(a, b, lgn, 1, 0, tw, lgmax);
+    if (lgns) {
+        double2 *t = a;
+        a = b;
+        b = t;
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (lgns < lgn) {
+            fft_pass8_one<SIGN>(a, b, lgn, lgns, f.w[q]);
+            double2 *t = a;
+            a = b;
+            b = t;
+            lgns += 3;
+        }
+    }
+    return a;
+}
+
 template <bool MIX>
 __device__ __forceinline__ double acc_to_rho(typename AccOf<MIX>::T v, double scale, double add) {
     double w;
