@@ -63,19 +63,31 @@ __global__ void __launch_bounds__(kBlock) k3_xfwd(Geo g, typename AccOf<MIX>::T 
     const int64_t base = ((int64_t)z * ny + y0) * nx;   // first of the Y rows
     const int sd = g.S * g.dim;
     QSum q{0, 0};
-    // row pair p: rows y0 + 2p (real part) and y0 + 2p + 1 (imaginary part)
-    for (int t = threadIdx.x; t < P * nx; t += blockDim.x) {
-        const int p = t / nx, i = t - p * nx;
-        const int64_t ia = base + (int64_t)(2 * p) * nx + i, ib = ia + nx;
-        const typename AccOf<MIX>::T a0 = acc[ia], a1 = acc[ib];
-        if constexpr (MIX) {
-            if (qacc) {
-                qsum_add(q, (int64_t)a0, sd);
-                qsum_add(q, (int64_t)a1, sd);
+    // row pair p: rows y0 + 2p (real part) and y0 + 2p + 1 (imaginary part);
+    // entries past the rows go to b1, which the first pass overwrites
+    using T = typename AccOf<MIX>::T;
+    struct Two {
+        T a, b;
+    };
+    const int cnt = P * nx;
+    fill_batched<Two, 4>(
+        cnt,
+        [&](int t) {
+            const int p = t / nx, i = t - p * nx;
+            const int64_t ia = base + (int64_t)(2 * p) * nx + i;
+            return Two{acc[ia], acc[ia + nx]};
+        },
+        [&](int t, const Two &v) {
+            const bool in = t < cnt;
+            if constexpr (MIX) {
+                if (qacc) {
+                    qsum_add(q, in ? (int64_t)v.a : 0, sd);
+                    qsum_add(q, in ? (int64_t)v.b : 0, sd);
+                }
             }
-        }
-        b0[t] = make_double2(acc_to_rho<MIX>(a0, scale, add), acc_to_rho<MIX>(a1, scale, add));
-    }
+            *(in ? &b0[t] : &b1[threadIdx.x & (cnt - 1)]) =
+                make_double2(acc_to_rho<MIX>(v.a, scale, add), acc_to_rho<MIX>(v.b, scale, add));
+        });
     if constexpr (MIX) {
         if (qacc) qsum_flush(q, sd, qacc);
     }
@@ -103,10 +115,14 @@ __global__ void __launch_bounds__(kBlock) k3_yfwd(Geo g, const double2 *A, doubl
     double2 *b0 = (double2 *)smem, *b1 = b0 + (size_t)ZB * ny;
     const int nzb = nz / ZB;
     const int kx = (int)blockIdx.x / nzb, z0 = ((int)blockIdx.x % nzb) * ZB;
-    for (int t = threadIdx.x; t < ZB * ny; t += blockDim.x) {
-        const int l = t / ny, y = t - l * ny;
-        b0[t] = A[((int64_t)(z0 + l) * hx + kx) * ny + y];
-    }
+    const int cnt = ZB * ny;
+    fill_batched<double2, 4>(
+        cnt,
+        [&](int t) {
+            const int l = t / ny, y = t - l * ny;
+            return A[((int64_t)(z0 + l) * hx + kx) * ny + y];
+        },
+        [&](int t, double2 v) { *(t < cnt ? &b0[t] : &b1[threadIdx.x & (cnt - 1)]) = v; });
     __syncthreads();
     const double2 *R = fft_lds<-1>(b0, b1, lgny, ZB, tw, lgmax);
     for (int t = threadIdx.x; t < ny * ZB; t += blockDim.x) {
@@ -125,7 +141,10 @@ __global__ void __launch_bounds__(kBlock) k3_zsolve(Geo g, double2 *B, const dou
     const int nyb = ny / KY;
     const int kx = (int)blockIdx.x / nyb, ky0 = ((int)blockIdx.x % nyb) * KY;
     double2 *line = B + ((int64_t)kx * ny + ky0) * nz;   // KY lines back to back
-    for (int t = threadIdx.x; t < KY * nz; t += blockDim.x) b0[t] = line[t];
+    const int cnt = KY * nz;
+    fill_batched<double2, 4>(
+        cnt, [&](int t) { return line[t]; },
+        [&](int t, double2 v) { *(t < cnt ? &b0[t] : &b1[threadIdx.x & (cnt - 1)]) = v; });
     __syncthreads();
     double2 *R = fft_lds<-1>(b0, b1, lgnz, KY, tw, lgmax);
     double2 *S = (R == b0) ? b1 : b0;
@@ -159,10 +178,17 @@ __global__ void __launch_bounds__(kBlock) k3_yinv(Geo g, const double2 *B, doubl
     double2 *b0 = (double2 *)smem, *b1 = b0 + (size_t)ZB * ny;
     const int nzb = nz / ZB;
     const int kx = (int)blockIdx.x / nzb, z0 = ((int)blockIdx.x % nzb) * ZB;
-    for (int t = threadIdx.x; t < ny * ZB; t += blockDim.x) {
-        const int ky = t / ZB, l = t - ky * ZB;
-        b0[l * ny + ky] = B[((int64_t)kx * ny + ky) * nz + z0 + l];
-    }
+    const int cnt = ny * ZB;
+    fill_batched<double2, 4>(
+        cnt,
+        [&](int t) {
+            const int ky = t / ZB, l = t - ky * ZB;
+            return B[((int64_t)kx * ny + ky) * nz + z0 + l];
+        },
+        [&](int t, double2 v) {
+            const int ky = t / ZB, l = t - ky * ZB;
+            *(t < cnt ? &b0[l * ny + ky] : &b1[threadIdx.x & (cnt - 1)]) = v;
+        });
     __syncthreads();
     const double2 *R = fft_lds<+1>(b0, b1, lgny, ZB, tw, lgmax);
     for (int t = threadIdx.x; t < ZB * ny; t += blockDim.x) {
@@ -180,10 +206,18 @@ __global__ void __launch_bounds__(kBlock) k3_xinv(Geo g, const double2 *A, doubl
     double2 *b0 = h + (size_t)Y * hx, *b1 = b0 + (size_t)P * nx;
     const int nyb = ny / Y;
     const int z = (int)blockIdx.x / nyb, y0 = ((int)blockIdx.x % nyb) * Y;
-    for (int t = threadIdx.x; t < hx * Y; t += blockDim.x) {
-        const int kx = t / Y, r = t - kx * Y;
-        h[r * hx + kx] = A[((int64_t)z * hx + kx) * ny + y0 + r];
-    }
+    // entries past the spectra go to b0, written only after the next barrier
+    const int cnt = hx * Y;
+    fill_batched<double2, 4>(
+        cnt,
+        [&](int t) {
+            const int kx = t / Y, r = t - kx * Y;
+            return A[((int64_t)z * hx + kx) * ny + y0 + r];
+        },
+        [&](int t, double2 v) {
+            const int kx = t / Y, r = t - kx * Y;
+            *(t < cnt ? &h[r * hx + kx] : &b0[threadIdx.x & (P * nx - 1)]) = v;
+        });
     __syncthreads();
     // Z_p(k) = Ha(k) + i Hb(k) over the full range, Ha(k) = conj Ha(nx - k)
     // above nx/2; at k = 0 and nx/2 the half spectra of real rows are real
