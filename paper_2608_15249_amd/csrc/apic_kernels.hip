@@ -1671,8 +1671,10 @@ __global__ void __launch_bounds__(kBlock) k_spectral(Geo g, const double2 *rh, d
 // its binary32 rounding. h = 1 / (2 d) per axis.
 // The last workgroup of the launch reduces the field diagnostics instead
 // (it reads only what earlier launches wrote).
-__global__ void __launch_bounds__(kBlock) k_grad(Geo g, const double *phi, double *E, float *E32, double hx,
-                                                 double hy, double hz, FinArgs f, CtxDev c) {
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_grad(Geo g, const double *__restrict__ phi, double *__restrict__ E,
+                                                 float *__restrict__ E32, double hx, double hy, double hz, FinArgs f,
+                                                 CtxDev c) {
     if (blockIdx.x == gridDim.x - 1) {
         finalize_block(f, c);
         return;
@@ -1684,6 +1686,8 @@ __global__ void __launch_bounds__(kBlock) k_grad(Geo g, const double *phi, doubl
     const int lane = (int)(threadIdx.x & 63);
     const int wv = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
     const int64_t nwv = (int64_t)(gridDim.x - 1) * (blockDim.x >> 6);
+    constexpr int U = 2;   // nodes per lane and round: their loads all issued before the first wait
+    constexpr int NV = 2 * DIM;
     for (int64_t r = wv; r < rows; r += nwv) {
         const int iy = (int)(r % g.ny), iz = (int)(r / g.ny);
         const int64_t row = r * g.nx;
@@ -1691,21 +1695,39 @@ __global__ void __launch_bounds__(kBlock) k_grad(Geo g, const double *phi, doubl
         const int64_t yp = (iy == g.ny - 1) ? row - (sxy - g.nx) : row + g.nx;
         const int64_t zm = (iz == 0) ? row + G - sxy : row - sxy;
         const int64_t zp = (iz == g.nz - 1) ? row - (G - sxy) : row + sxy;
-        for (int ix = lane; ix < g.nx; ix += 64) {
-            const int64_t i = row + ix;
-            const int xm = (ix == 0) ? g.nx - 1 : ix - 1, xp = (ix == g.nx - 1) ? 0 : ix + 1;
-            const double ex = (phi[row + xm] - phi[row + xp]) * hx;
-            if (E) E[i] = ex;
-            if (E32) E32[i] = (float)ex;
-            if (g.dim >= 2) {
-                const double ey = (phi[ym + ix] - phi[yp + ix]) * hy;
-                if (E) E[G + i] = ey;
-                if (E32) E32[G + i] = (float)ey;
+        for (int ix0 = 0; ix0 < g.nx; ix0 += U * 64) {
+            // nodes past the row repeat its last node: the same values to the same addresses
+            double v[U][NV];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int ix = min(ix0 + u * 64 + lane, g.nx - 1);
+                const int xm = (ix == 0) ? g.nx - 1 : ix - 1, xp = (ix == g.nx - 1) ? 0 : ix + 1;
+                v[u][0] = phi[row + xm];
+                v[u][1] = phi[row + xp];
+                v[u][2] = phi[ym + ix];
+                v[u][3] = phi[yp + ix];
+                if constexpr (DIM == 3) {
+                    v[u][4] = phi[zm + ix];
+                    v[u][5] = phi[zp + ix];
+                }
             }
-            if (g.dim == 3) {
-                const double ez = (phi[zm + ix] - phi[zp + ix]) * hz;
-                if (E) E[2 * G + i] = ez;
-                if (E32) E32[2 * G + i] = (float)ez;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = row + min(ix0 + u * 64 + lane, g.nx - 1);
+                const double ex = (v[u][0] - v[u][1]) * hx, ey = (v[u][2] - v[u][3]) * hy;
+                if (E) {
+                    E[i] = ex;
+                    E[G + i] = ey;
+                }
+                if (E32) {
+                    E32[i] = (float)ex;
+                    E32[G + i] = (float)ey;
+                }
+                if constexpr (DIM == 3) {
+                    const double ez = (v[u][4] - v[u][5]) * hz;
+                    if (E) E[2 * G + i] = ez;
+                    if (E32) E32[2 * G + i] = (float)ez;
+                }
             }
         }
     }
@@ -2075,7 +2097,10 @@ hipError_t launch_grad(const Geo &g, const double *phi, double *E, float *E32, c
     // a wave per (y, z) row, up to 8192 workgroups, then the diagnostics block
     const int64_t rows = (int64_t)g.ny * g.nz;
     const int nblk = (int)std::min<int64_t>(std::max<int64_t>((rows + kWaves - 1) / kWaves, 1), 8192);
-    hipLaunchKernelGGL(k_grad, dim3(nblk + 1), dim3(kBlock), 0, s, g, phi, E, E32, hx, hy, hz, f, c);
+    if (g.dim == 3)
+        hipLaunchKernelGGL(k_grad<3>, dim3(nblk + 1), dim3(kBlock), 0, s, g, phi, E, E32, hx, hy, hz, f, c);
+    else
+        hipLaunchKernelGGL(k_grad<2>, dim3(nblk + 1), dim3(kBlock), 0, s, g, phi, E, E32, hx, hy, hz, f, c);
     return hipGetLastError();
 }
 
