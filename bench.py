@@ -79,7 +79,7 @@ def load_traffic(precision, workload, tile):
     try:
         d = json.load(open(p))
         e = d.get(precision)
-        if not e or d.get("kernel_src_sha") != kernel_source_sha() or list(d.get("tile", [])) != list(tile):
+        if not e or d.get("kernel_src_sha") != kernel_source_sha() or list(e.get("tile", [])) != list(tile):
             return None
         return float(e["hbm_bytes_per_launch"])
     except Exception:
@@ -104,7 +104,7 @@ def load_counters(precision, workload, tile):
     try:
         d = json.load(open(p))
         e = d.get(precision)
-        if not e or d.get("kernel_src_sha") != kernel_source_sha() or list(d.get("tile", [])) != list(tile):
+        if not e or d.get("kernel_src_sha") != kernel_source_sha() or list(e.get("tile", [])) != list(tile):
             return None
         return e["per_launch"]
     except Exception:

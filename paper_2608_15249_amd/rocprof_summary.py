@@ -11,14 +11,13 @@ Usage:
 `trace` prints per-kernel call counts and average/total durations.
 `counters` averages every counter of one or more PMC passes per dispatch of
 the named kernel (the timed launches of the run) and stores them, with the
-source hash and the tile, under the tag (the benchmark reads the atomic
-counts from there). `traffic`
-turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch, summed over the counter
+bucket tile of the run, under the tag in a file keyed by the source hash
+(the benchmark reads the atomic counts from there). `traffic` turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch, summed over the counter
 instances of a dispatch) into HBM bytes per dispatch of the named kernel,
 each scaled by the factor that makes the same counter read the known byte
 count of the plain copy kernel (k_copy_bytes) of the same run. With
---merge-into the result is stored under its tag in a JSON file together with
-the hash of the step kernels' sources and the bucket tile, which is what the
+--merge-into the result is stored under its tag, with the bucket tile of the
+run, in a JSON file keyed by the hash of the step kernels' sources: what the
 benchmark checks before it reports the counted traffic.
 """
 from __future__ import annotations
@@ -155,12 +154,12 @@ def main():
         if os.path.exists(a.merge_into):
             with open(a.merge_into) as fh:
                 d = json.load(fh)
-            if d.get("kernel_src_sha") != sha or d.get("tile") != tile:
+            if d.get("kernel_src_sha") != sha:
                 d = {}
         d["kernel_src_sha"] = sha
-        d["tile"] = tile
-        d["note"] = "counter values per dispatch of the kernel, averaged over its dispatches in the profiled run"
-        d[a.tag] = {"kernel": name, "per_launch": per, "command": a.cmd}
+        d["note"] = ("counter values per dispatch of the kernel, averaged over its dispatches in the profiled run; "
+                     "each entry with the bucket tile of its run")
+        d[a.tag] = {"kernel": name, "tile": tile, "per_launch": per, "command": a.cmd}
         with open(a.merge_into, "w") as fh:
             json.dump(d, fh, indent=1)
         print(json.dumps(d[a.tag], indent=1))
@@ -203,15 +202,14 @@ def main():
         if os.path.exists(a.merge_into):
             with open(a.merge_into) as fh:
                 d = json.load(fh)
-            if d.get("kernel_src_sha") != sha or d.get("tile") != tile:
+            if d.get("kernel_src_sha") != sha:
                 d = {}
         d["kernel_src_sha"] = sha
-        d["tile"] = tile
         d["note"] = ("HBM bytes per launch of the step kernels; FETCH_SIZE and WRITE_SIZE (KiB per dispatch, "
                      "summed over counter instances) scaled so that the plain copy kernel k_copy_bytes of the "
-                     "same run reads/writes its known size")
+                     "same run reads/writes its known size; each entry with the bucket tile of its run")
         main_k = [k for k in res["kernels"] if k.startswith(a.main or a.kernel)]
-        d[a.tag] = {"kernel": main_k[0] if main_k else None,
+        d[a.tag] = {"kernel": main_k[0] if main_k else None, "tile": tile,
                     "hbm_bytes_per_launch": res["kernels"][main_k[0]]["hbm_bytes_per_launch"] if main_k else None,
                     "detail": res}
         with open(a.merge_into, "w") as fh:
