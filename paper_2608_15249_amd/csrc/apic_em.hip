@@ -13,6 +13,7 @@
 #include "apic.h"
 #include "apic_ctx.h"
 #include "apic_em.h"
+#include "apic_fill.h"
 
 #include <cmath>
 
@@ -64,6 +65,7 @@ __global__ void __launch_bounds__(kBlock) k_fdtd_step(Geo g, const double *F, do
     __shared__ double sE[3][kFTY + 3][kFTX + 3];   // E^n from node (x0 - 1, y0 - 1)
     __shared__ double sB[3][kFTY + 2][kFTX + 2];   // B^n, then B^{n+1/2}, from (x0 - 1, y0 - 1)
     __shared__ double sN[3][kFTY + 1][kFTX + 1];   // E^{n+1} from (x0, y0)
+    static_assert(3 * (kFTY + 1) * (kFTX + 1) >= kBlock, "sN takes the staging entries past sE and sB");
     const int nx = g.nx, ny = g.ny;
     const int64_t G = (int64_t)nx * ny;
     const double h = 0.5 * dt;
@@ -82,16 +84,23 @@ __global__ void __launch_bounds__(kBlock) k_fdtd_step(Geo g, const double *F, do
     double we = 0.0, wb = 0.0;
     for (int t = blockIdx.x; t < ntx * nty; t += gridDim.x) {
         const int x0 = (t % ntx) * kFTX, y0 = (t / ntx) * kFTY;
-        for (int k = threadIdx.x; k < 3 * (kFTY + 3) * (kFTX + 3); k += blockDim.x) {
-            const int c = k / ((kFTY + 3) * (kFTX + 3)), r = k % ((kFTY + 3) * (kFTX + 3));
-            const int ly = r / (kFTX + 3), lx = r % (kFTX + 3);
-            sE[c][ly][lx] = F[c * G + (int64_t)wrapy(y0 - 1 + ly) * nx + wrapx(x0 - 1 + lx)];
-        }
-        for (int k = threadIdx.x; k < 3 * (kFTY + 2) * (kFTX + 2); k += blockDim.x) {
-            const int c = k / ((kFTY + 2) * (kFTX + 2)), r = k % ((kFTY + 2) * (kFTX + 2));
-            const int ly = r / (kFTX + 2), lx = r % (kFTX + 2);
-            sB[c][ly][lx] = F[(3 + c) * G + (int64_t)wrapy(y0 - 1 + ly) * nx + wrapx(x0 - 1 + lx)];
-        }
+        // E^n and B^n staged in one round of loads (entries past both go to
+        // sN, which is written only after the next two barriers)
+        constexpr int nE = 3 * (kFTY + 3) * (kFTX + 3), nB = 3 * (kFTY + 2) * (kFTX + 2);
+        fill_batched<double, (nE + nB + kBlock - 1) / kBlock>(
+            nE + nB,
+            [&](int k) {
+                const bool e = k < nE;
+                const int kk = e ? k : k - nE;
+                const int ce = kk / ((kFTY + 3) * (kFTX + 3)), re = kk % ((kFTY + 3) * (kFTX + 3));
+                const int cb = kk / ((kFTY + 2) * (kFTX + 2)), rb = kk % ((kFTY + 2) * (kFTX + 2));
+                const int c = e ? ce : 3 + cb;
+                const int ly = e ? re / (kFTX + 3) : rb / (kFTX + 2), lx = e ? re % (kFTX + 3) : rb % (kFTX + 2);
+                return F[c * G + (int64_t)wrapy(y0 - 1 + ly) * nx + wrapx(x0 - 1 + lx)];
+            },
+            [&](int k, double v) {
+                *(k < nE ? &sE[0][0][0] + k : (k < nE + nB ? &sB[0][0][0] + (k - nE) : &sN[0][0][0] + threadIdx.x)) = v;
+            });
         __syncthreads();
         // B^{n+1/2} over the staged B nodes (forward differences of E^n)
         for (int k = threadIdx.x; k < (kFTY + 2) * (kFTX + 2); k += blockDim.x) {
